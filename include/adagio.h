@@ -1,0 +1,165 @@
+/* adagio.h -- C ABI of the MI355X (gfx950) ADAGIO hot path.
+ *
+ * ADAGIO (Blasiok & Tsourakakis, arXiv 1609.05388) maps each point w of a
+ * cloud T in R^d to (P w, S (w - P^T P w)), where P holds the top principal
+ * directions of the centred cloud and S is a +-1/sqrt(k) Johnson-Lindenstrauss
+ * matrix (Algorithm 1), and judges the map by its distortion: the largest,
+ * over all pairs, of | ||f(x) - f(y)|| / ||x - y|| - 1 | (eqs. 2 and 3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Arrays named X, Y, Pi, lambda, Vt are DEVICE pointers owned by the caller:
+ *   contiguous, row-major, FP32 unless stated.  X is n x d (one point per
+ *   row), Y is n x r, Pi is r x d.
+ * - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *   All device work is ordered on it.  Entry points that return host scalars
+ *   (fit, max_distortion, certify_map, pca) synchronise that stream before
+ *   returning; embed and project return without synchronising.
+ * - Host structs (adagio_cert_t, adagio_opts_t, adagio_stats_t) are owned by
+ *   the caller; opts may be NULL (defaults).
+ * - The library keeps a per-device workspace that grows on demand and is
+ *   reused across calls; adagio_release() frees it.  Calls are serialised by
+ *   an internal lock.
+ * - Return value: ADAGIO_OK (0) or a negative ADAGIO_E_* code.  On error the
+ *   output buffers are unspecified and adagio_last_error() describes the
+ *   failure (thread-local text).  Arguments are validated before any device
+ *   work, so invalid arguments never touch the GPU.
+ * - Results are deterministic: the same inputs, seed and device give bitwise
+ *   identical outputs.
+ */
+#ifndef ADAGIO_H
+#define ADAGIO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ADAGIO_OK 0
+#define ADAGIO_E_INVALID_ARG (-1)   /* n < 2, d < 1, r outside [1, d], eps outside (0, 1), NULL pointer */
+#define ADAGIO_E_NONFINITE (-2)     /* NaN or Inf in X (or Y) */
+#define ADAGIO_E_HIP (-3)           /* HIP runtime error; adagio_last_error() has its text */
+#define ADAGIO_E_OOM (-4)           /* device allocation failed */
+#define ADAGIO_E_UNSUPPORTED (-5)   /* device is not gfx950, or size beyond the supported range */
+#define ADAGIO_E_NO_CONVERGENCE (-6) /* eigensolver did not converge in its sweep limit */
+#define ADAGIO_E_CAPACITY (-7)      /* more certificate candidates than the hard cap */
+#define ADAGIO_E_NOT_CERTIFIED (-8) /* a certificate could not be completed */
+
+/* Screening precision of the all-pairs certificate (the FP64 rescore and the
+ * final value are exact in every mode). */
+#define ADAGIO_SCREEN_F32 0      /* FP32 MFMA Gram, rigorous per-pair bounds   */
+#define ADAGIO_SCREEN_BF16X3 1   /* BF16 hi/lo split, 3 BF16 MFMA products     */
+#define ADAGIO_SCREEN_FP8 2      /* FP8 e4m3 per-row scaled screen + rescoring */
+
+/* Target-dimension search. */
+#define ADAGIO_SEARCH_BISECT 0   /* bisection over r in (0, d]                 */
+#define ADAGIO_SEARCH_LEARNED 1  /* MLP prediction, certified, bisection fallback */
+
+/* Result of an all-pairs certificate (eq. 3 over unordered pairs i < j). */
+typedef struct adagio_cert {
+    double max_distortion; /* exact (FP64) maximum of eq. (2); 0 when no valid pair */
+    int64_t i, j;          /* argmax pair, i < j; smallest (i, j) among equal values; -1 if none */
+    int32_t side;          /* +1 expansion (||f(x)-f(y)|| > ||x-y||), -1 contraction, 0 none */
+    int32_t certified;     /* 1: every pair not re-evaluated in FP64 is proven <= max_distortion */
+    double runner_up;      /* largest FP64 distortion among the other re-evaluated pairs (-1 if none) */
+    int64_t i2, j2;        /* runner-up pair (-1 if none) */
+    double bound_rest;     /* proven upper bound on the distortion of every pair not re-evaluated */
+    int64_t n_rescored;    /* pairs re-evaluated exactly in FP64 */
+    int64_t n_pairs;       /* pairs covered: n (n - 1) / 2 */
+    int64_t n_flagged_tiles; /* pair tiles that needed a second, exact pass */
+} adagio_cert_t;
+
+/* Optional per-call timing and counters (filled when opts->stats != NULL). */
+typedef struct adagio_stats {
+    double t_total_ms;       /* host wall time of the call                        */
+    double t_pca_ms;         /* centring + covariance + eigensolve (device events) */
+    double t_search_ms;      /* the r search (device events)                      */
+    double t_screen_ms;      /* sum of all-pairs screen kernel times              */
+    double t_rescore_ms;     /* sum of candidate / rescore / emit stages          */
+    int32_t n_certificates;  /* certificates computed                             */
+    int32_t eig_sweeps;      /* Jacobi sweeps to convergence                      */
+    int32_t n_fallback;      /* learned search: 1 when bisection was needed       */
+    int32_t r_predicted;     /* learned search: the network's r (0 otherwise)     */
+    int64_t n_flagged_tiles; /* summed over certificates                          */
+    int64_t n_rescored;      /* summed over certificates                          */
+} adagio_stats_t;
+
+typedef struct adagio_opts {
+    int32_t screen;          /* ADAGIO_SCREEN_*; default F32                      */
+    int32_t search;          /* ADAGIO_SEARCH_*; default BISECT                   */
+    int32_t max_candidates;  /* initial candidate capacity per certificate; 0 = default */
+    int32_t reserved;
+    const float* predictor;  /* learned search: device pointer to the packed MLP parameters */
+    adagio_stats_t* stats;   /* optional host output                              */
+} adagio_opts_t;
+
+/* a1-a3.  Principal axes of the centred cloud (Sec. 2 PCA paragraph, eq. 4;
+ * Sec. 3 first paragraph: P holds the top singular directions).
+ * Computes mu = mean row (FP64), C = sum_i (x_i - mu)(x_i - mu)^T (FP64) and
+ * its eigenpairs by a parallel cyclic Jacobi method.
+ * Out: lambda (device, d doubles, decreasing), Vt (device, d x d doubles,
+ * row i = unit eigenvector of lambda[i]).  Synchronises `stream`. */
+int adagio_pca(const float* X, int64_t n, int64_t d, double* lambda, double* Vt, void* stream);
+
+/* a4-a5.  Algorithm 1's map at target dimension r from given principal axes:
+ * s = floor(r/2) rows P = Vt[0:s], k = ceil(r/2) rows S Q = S - (S P^T) P with
+ * S = B[0:k] / sqrt(k) (Lemma 1), the split of Sec. 4.1 "Implementation";
+ * r = d returns Vt (no reduction).  B is the fixed +-1 matrix whose entry
+ * (a, l) is the top bit of SplitMix64(seed) output number a * 2^32 + l + 1
+ * (+1 when the bit is 0).  Vt: device d x d FP64 (rows = axes, decreasing
+ * eigenvalue).  Pi_out: device r x d FP32.  Asynchronous. */
+int adagio_project_axes(const double* Vt, int64_t d, int32_t r, uint64_t seed, float* Pi_out, void* stream);
+
+/* a1-a5.  Algorithm 1 at a fixed target dimension r (the fixed-r runs of
+ * Sec. 4.2): PCA of X, then the map of adagio_project_axes.  Pi_out: device
+ * r x d FP32.  Synchronises `stream`. */
+int adagio_project(const float* X, int64_t n, int64_t d, int32_t r, uint64_t seed, float* Pi_out, void* stream);
+
+/* a6.  The embedding f(w) = Pi w of every point (Algorithm 1's output line),
+ * accumulated in FP64 and rounded once to FP32.  Y_out: device n x r FP32.
+ * Asynchronous. */
+int adagio_embed(const float* X, int64_t n, int64_t d, const float* Pi, int32_t r, float* Y_out, void* stream);
+
+/* a7-a8.  Certificate of eq. (3) for a cloud X and its images Y (any map):
+ * the exact maximum over unordered pairs i < j with x_i != x_j of eq. (2)
+ * | ||y_i - y_j|| / ||x_i - x_j|| - 1 |.  An MFMA screen bounds every pair;
+ * pairs whose bound reaches the best exact value are re-evaluated in FP64 by
+ * direct differences of the given rows.  opts->screen picks the screen
+ * precision.  cert_out: host.  Synchronises `stream`. */
+int adagio_max_distortion(const float* X, int64_t n, int64_t d, const float* Y, int32_t r,
+                          const adagio_opts_t* opts, adagio_cert_t* cert_out, void* stream);
+
+/* a6-a8.  Certificate of eq. (3) for the linear map Pi (r x d FP32, device)
+ * applied exactly: images are formed in FP64 from the FP32 entries of X and
+ * Pi, so the result is the distortion of Pi itself.  Synchronises `stream`. */
+int adagio_certify_map(const float* X, int64_t n, int64_t d, const float* Pi, int32_t r,
+                       const adagio_opts_t* opts, adagio_cert_t* cert_out, void* stream);
+
+/* a1-a9.  Fit: PCA once, then the smallest target dimension r whose map
+ * (adagio_project_axes at r) has certified distortion <= eps, found by
+ * bisection over r with lo = 0 and hi = d (Sec. 4.3 / Table 2 ask how many
+ * dimensions a distortion level needs; the search procedure is this
+ * library's).  eps is the absolute distortion target, in (0, 1).
+ * Pi_out: device buffer of capacity d x d FP32; receives Pi (r x d).
+ * r_out, s_out: host; cert_out: host, the certificate of the returned Pi.
+ * opts->search = ADAGIO_SEARCH_LEARNED starts from the network's prediction
+ * (opts->predictor) and falls back to bisection.  Synchronises `stream`. */
+int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed,
+               const adagio_opts_t* opts, float* Pi_out, int32_t* r_out, int32_t* s_out,
+               adagio_cert_t* cert_out, void* stream);
+
+/* Frees the cached device workspace of the current device. */
+int adagio_release(void);
+
+/* Static text of a status code. */
+const char* adagio_status_string(int status);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* adagio_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADAGIO_H */

@@ -1,0 +1,215 @@
+"""Python binding of libadagio.so (argument marshalling only).
+
+Every function takes and returns torch tensors on the current ROCm device and
+passes their device pointers and torch's current HIP stream to the C ABI of
+include/adagio.h.  No computation happens here: if the shared library is
+missing, ``load()`` raises instead of falling back to anything else.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libadagio.so")
+
+SCREEN = {"f32": 0, "bf16x3": 1, "fp8": 2}
+SEARCH = {"bisect": 0, "learned": 1}
+
+
+class AdagioError(RuntimeError):
+    def __init__(self, code, text):
+        super().__init__("adagio error %d: %s" % (code, text))
+        self.code = code
+
+
+class Cert(ctypes.Structure):
+    _fields_ = [("max_distortion", ctypes.c_double), ("i", ctypes.c_int64), ("j", ctypes.c_int64),
+                ("side", ctypes.c_int32), ("certified", ctypes.c_int32),
+                ("runner_up", ctypes.c_double), ("i2", ctypes.c_int64), ("j2", ctypes.c_int64),
+                ("bound_rest", ctypes.c_double), ("n_rescored", ctypes.c_int64),
+                ("n_pairs", ctypes.c_int64), ("n_flagged_tiles", ctypes.c_int64)]
+
+    def to_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("t_total_ms", ctypes.c_double), ("t_pca_ms", ctypes.c_double),
+                ("t_search_ms", ctypes.c_double), ("t_screen_ms", ctypes.c_double),
+                ("t_rescore_ms", ctypes.c_double), ("n_certificates", ctypes.c_int32),
+                ("eig_sweeps", ctypes.c_int32), ("n_fallback", ctypes.c_int32),
+                ("r_predicted", ctypes.c_int32), ("n_flagged_tiles", ctypes.c_int64),
+                ("n_rescored", ctypes.c_int64)]
+
+    def to_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("screen", ctypes.c_int32), ("search", ctypes.c_int32),
+                ("max_candidates", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("predictor", ctypes.c_void_p), ("stats", ctypes.POINTER(Stats))]
+
+
+_lib = None
+
+# name -> (restype, argtypes) of every exported entry point
+_P, _I64, _I32, _U64, _D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
+SIGNATURES = {
+    "adagio_pca": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _P]),
+    "adagio_project_axes": (ctypes.c_int, [_P, _I64, _I32, _U64, _P, _P]),
+    "adagio_project": (ctypes.c_int, [_P, _I64, _I64, _I32, _U64, _P, _P]),
+    "adagio_embed": (ctypes.c_int, [_P, _I64, _I64, _P, _I32, _P, _P]),
+    "adagio_max_distortion": (ctypes.c_int, [_P, _I64, _I64, _P, _I32, ctypes.POINTER(Opts),
+                                             ctypes.POINTER(Cert), _P]),
+    "adagio_certify_map": (ctypes.c_int, [_P, _I64, _I64, _P, _I32, ctypes.POINTER(Opts),
+                                          ctypes.POINTER(Cert), _P]),
+    "adagio_fit": (ctypes.c_int, [_P, _I64, _I64, _D, _U64, ctypes.POINTER(Opts), _P,
+                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(Cert), _P]),
+    "adagio_release": (ctypes.c_int, []),
+    "adagio_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "adagio_last_error": (ctypes.c_char_p, []),
+}
+
+
+def load(path=LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError("libadagio.so not built at %s; run __graft_entry__.build()" % path)
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        lib = load()
+        raise AdagioError(rc, "%s: %s" % (lib.adagio_status_string(rc).decode(),
+                                          lib.adagio_last_error().decode()))
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a torch tensor on the GPU" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s" % (name, dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _opts(screen="f32", search="bisect", max_candidates=0, predictor=None, stats=None):
+    o = Opts()
+    o.screen = SCREEN[screen]
+    o.search = SEARCH[search]
+    o.max_candidates = int(max_candidates)
+    o.predictor = ctypes.c_void_p(predictor.data_ptr()) if predictor is not None else None
+    o.stats = ctypes.pointer(stats) if stats is not None else None
+    return o
+
+
+def pca(X):
+    """(lambda, Vt): eigenvalues (decreasing) and eigenvectors (rows), FP64."""
+    lib = load()
+    n, d = X.shape
+    lam = torch.empty(d, dtype=torch.float64, device=X.device)
+    Vt = torch.empty((d, d), dtype=torch.float64, device=X.device)
+    _check(lib.adagio_pca(_dev(X, torch.float32, "X"), n, d, _dev(lam, torch.float64, "lam"),
+                          _dev(Vt, torch.float64, "Vt"), _stream()))
+    return lam, Vt
+
+
+def project_axes(Vt, r, seed):
+    lib = load()
+    d = Vt.shape[1]
+    Pi = torch.empty((r, d), dtype=torch.float32, device=Vt.device)
+    _check(lib.adagio_project_axes(_dev(Vt, torch.float64, "Vt"), d, int(r), int(seed),
+                                   _dev(Pi, torch.float32, "Pi"), _stream()))
+    return Pi
+
+
+def project(X, r, seed):
+    lib = load()
+    n, d = X.shape
+    Pi = torch.empty((r, d), dtype=torch.float32, device=X.device)
+    _check(lib.adagio_project(_dev(X, torch.float32, "X"), n, d, int(r), int(seed),
+                              _dev(Pi, torch.float32, "Pi"), _stream()))
+    return Pi
+
+
+def embed(X, Pi):
+    lib = load()
+    n, d = X.shape
+    r = Pi.shape[0]
+    if Pi.shape[1] != d:
+        raise ValueError("Pi must be r x d")
+    Y = torch.empty((n, r), dtype=torch.float32, device=X.device)
+    _check(lib.adagio_embed(_dev(X, torch.float32, "X"), n, d, _dev(Pi, torch.float32, "Pi"), r,
+                            _dev(Y, torch.float32, "Y"), _stream()))
+    return Y
+
+
+def max_distortion(X, Y, screen="f32", max_candidates=0, with_stats=False):
+    lib = load()
+    n, d = X.shape
+    if Y.shape[0] != n:
+        raise ValueError("Y must have one row per point")
+    st = Stats() if with_stats else None
+    o = _opts(screen, max_candidates=max_candidates, stats=st)
+    c = Cert()
+    _check(lib.adagio_max_distortion(_dev(X, torch.float32, "X"), n, d, _dev(Y, torch.float32, "Y"),
+                                     Y.shape[1], ctypes.byref(o), ctypes.byref(c), _stream()))
+    out = c.to_dict()
+    if st is not None:
+        out["stats"] = st.to_dict()
+    return out
+
+
+def certify_map(X, Pi, screen="f32", max_candidates=0, with_stats=False):
+    lib = load()
+    n, d = X.shape
+    if Pi.shape[1] != d:
+        raise ValueError("Pi must be r x d")
+    st = Stats() if with_stats else None
+    o = _opts(screen, max_candidates=max_candidates, stats=st)
+    c = Cert()
+    _check(lib.adagio_certify_map(_dev(X, torch.float32, "X"), n, d, _dev(Pi, torch.float32, "Pi"),
+                                  Pi.shape[0], ctypes.byref(o), ctypes.byref(c), _stream()))
+    out = c.to_dict()
+    if st is not None:
+        out["stats"] = st.to_dict()
+    return out
+
+
+def fit(X, eps, seed, screen="f32", search="bisect", predictor=None, max_candidates=0):
+    """Returns dict(Pi=(r x d tensor), r, s, k, cert, stats)."""
+    lib = load()
+    n, d = X.shape
+    Pi_buf = torch.empty((d, d), dtype=torch.float32, device=X.device)
+    st = Stats()
+    o = _opts(screen, search, max_candidates, predictor, st)
+    r = ctypes.c_int32()
+    s = ctypes.c_int32()
+    c = Cert()
+    _check(lib.adagio_fit(_dev(X, torch.float32, "X"), n, d, float(eps), int(seed), ctypes.byref(o),
+                          _dev(Pi_buf, torch.float32, "Pi"), ctypes.byref(r), ctypes.byref(s),
+                          ctypes.byref(c), _stream()))
+    rv = r.value
+    return {"Pi": Pi_buf[:rv], "r": rv, "s": s.value, "k": rv - s.value if rv < d else 0,
+            "cert": c.to_dict(), "stats": st.to_dict()}
+
+
+def release():
+    _check(load().adagio_release())

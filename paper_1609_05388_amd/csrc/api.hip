@@ -1,0 +1,636 @@
+// Host side of the C ABI declared in include/adagio.h.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/adagio.h"
+#include "common.h"
+#include "kernels.h"
+
+namespace adg {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+struct Fail {
+  int code;
+};
+
+static void set_err(const char* fmt, const char* a = "", long long b = 0) {
+  char buf[512];
+  snprintf(buf, sizeof(buf), fmt, a, b);
+  g_err = buf;
+}
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      set_err("%s (" #expr ", line %lld)", hipGetErrorString(e_), (long long)__LINE__); \
+      throw Fail{e_ == hipErrorOutOfMemory ? ADAGIO_E_OOM : ADAGIO_E_HIP};            \
+    }                                                                                 \
+  } while (0)
+
+#define ARGCHK(cond, msg)         \
+  do {                            \
+    if (!(cond)) {                \
+      set_err("%s", msg);         \
+      throw Fail{ADAGIO_E_INVALID_ARG}; \
+    }                             \
+  } while (0)
+
+// --------------------------------------------------------------- workspace
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+struct Workspace {
+  DevBuf mu, colpart, nonfinite, Xc, nx, tx, covpart, A0, A1, W, trace, rot, lam, Vt;
+  DevBuf S, T, Pi, Pi64, Y64, Yc, ny, ty, muY;
+  DevBuf recs, tparts, seeds, seedv, list, cand, vals, vparts, cd;
+  bool checked = false;
+};
+
+static std::mutex g_mu;
+static Workspace g_ws[64];
+
+template <typename T>
+static T* ensure(DevBuf& b, size_t count) {
+  size_t bytes = count * sizeof(T);
+  if (bytes == 0) bytes = 256;
+  if (b.cap < bytes) {
+    if (b.p) HIPCHK(hipFree(b.p));
+    b.p = nullptr;
+    b.cap = 0;
+    HIPCHK(hipMalloc(&b.p, bytes));
+    b.cap = bytes;
+  }
+  return static_cast<T*>(b.p);
+}
+
+static Workspace& workspace() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) {
+    set_err("device index %s%lld out of range", "", dev);
+    throw Fail{ADAGIO_E_UNSUPPORTED};
+  }
+  Workspace& ws = g_ws[dev];
+  if (!ws.checked) {
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+      set_err("device architecture %s is not gfx950%lld", prop.gcnArchName, 0);
+      throw Fail{ADAGIO_E_UNSUPPORTED};
+    }
+    ws.checked = true;
+  }
+  return ws;
+}
+
+// --------------------------------------------------------------- timing
+struct EvPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  void begin(hipStream_t st) {
+    if (!a) { HIPCHK(hipEventCreate(&a)); HIPCHK(hipEventCreate(&b)); }
+    HIPCHK(hipEventRecord(a, st));
+  }
+  void end(hipStream_t st) { HIPCHK(hipEventRecord(b, st)); }
+  double ms() {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, a, b));
+    return (double)t;
+  }
+  ~EvPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+// ------------------------------------------------------------ point state
+// Centred FP32 points and their bound terms, shared by every certificate of
+// one call.
+struct Points {
+  const float* X = nullptr;
+  int64_t n = 0, d = 0, n_pad = 0, ldx = 0;
+  double* mu = nullptr;
+  float* Xc = nullptr;
+  double* nx = nullptr;
+  float2* tx = nullptr;
+};
+
+static void mean_rows(Workspace& ws, const float* A, int64_t n, int64_t m, int64_t ld, double* mu, hipStream_t st) {
+  const int64_t rows_per_chunk = 512;
+  const int64_t nch = (n + rows_per_chunk - 1) / rows_per_chunk;
+  double* part = ensure<double>(ws.colpart, (size_t)(nch * m));
+  int* flag = ensure<int>(ws.nonfinite, 1);
+  HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), st));
+  HIPCHK(launch_mean<float>(A, n, m, ld, part, nch, rows_per_chunk, mu, flag, st));
+  int h = 0;
+  HIPCHK(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (h) {
+    set_err("input contains NaN or Inf%s%lld", "", 0);
+    throw Fail{ADAGIO_E_NONFINITE};
+  }
+}
+
+// Bound constant for an FP32 Gram screen over K (padded) terms: covers the
+// rounding of centring, of the row norms, of the MFMA dot product (gamma_K),
+// of the epilogue's add and fma, and an 8u margin for the reciprocal.
+static double screen_const(int64_t K) { return ((double)K + 32.0) * kU32 * 1.001; }
+
+static Points prep_points(Workspace& ws, const float* X, int64_t n, int64_t d, hipStream_t st) {
+  Points p;
+  p.X = X;
+  p.n = n;
+  p.d = d;
+  p.n_pad = round_up(n, kTile);
+  p.ldx = round_up(d, kChunk);
+  p.mu = ensure<double>(ws.mu, (size_t)d);
+  mean_rows(ws, X, n, d, d, p.mu, st);
+  p.Xc = ensure<float>(ws.Xc, (size_t)(p.n_pad * p.ldx));
+  p.nx = ensure<double>(ws.nx, (size_t)p.n_pad);
+  p.tx = ensure<float2>(ws.tx, (size_t)p.n_pad);
+  HIPCHK(launch_center<float>(X, n, d, d, p.mu, p.Xc, p.ldx, p.n_pad, p.nx, st));
+  HIPCHK(launch_row_terms(p.nx, screen_const(p.ldx), nullptr, 0.0, p.n_pad, p.tx, st));
+  return p;
+}
+
+// ---------------------------------------------------------------- PCA
+struct Axes {
+  double* lam = nullptr;
+  double* Vt = nullptr;  // d x d, rows = eigenvectors, decreasing eigenvalue
+  int sweeps = 0;
+};
+
+static Axes principal_axes(Workspace& ws, const Points& p, hipStream_t st, double* lam_out = nullptr,
+                           double* Vt_out = nullptr) {
+  const int64_t d = p.d;
+  const int m = (int)(d + (d & 1));
+  // covariance with split-K over points so that the grid fills the GPU
+  const int64_t NT = (d + 63) / 64;
+  const int64_t ntiles = NT * (NT + 1) / 2;
+  int nsplit = (int)((2048 + ntiles - 1) / ntiles);
+  const int64_t max_split = (p.n + 255) / 256;
+  if (nsplit > max_split) nsplit = (int)max_split;
+  if (nsplit < 1) nsplit = 1;
+  double* part = ensure<double>(ws.covpart, (size_t)(nsplit * d * d));
+  double* A = ensure<double>(ws.A0, (size_t)m * m);
+  double* B = ensure<double>(ws.A1, (size_t)m * m);
+  double* W = ensure<double>(ws.W, (size_t)m * m);
+  HIPCHK(launch_covariance(p.X, p.n, d, p.mu, part, nsplit, A, m, st));
+  HIPCHK(launch_eye(W, m, st));
+  double* tr = ensure<double>(ws.trace, 1);
+  HIPCHK(launch_trace(A, m, tr, st));
+  double trace = 0.0;
+  HIPCHK(hipMemcpyAsync(&trace, tr, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  // Rotations whose off-diagonal entry is below u64 * trace / m are skipped;
+  // the method has converged when a whole sweep skips every rotation.
+  const double thr = kU64 * trace / (double)m;
+  int* rot = ensure<int>(ws.rot, 1);
+  Axes ax;
+  const int max_sweeps = 60;
+  int sweep = 0;
+  bool converged = (m < 2);
+  for (; sweep < max_sweeps && !converged; ++sweep) {
+    HIPCHK(hipMemsetAsync(rot, 0, sizeof(int), st));
+    for (int t = 0; t < m - 1; ++t) {
+      HIPCHK(launch_jacobi_round(A, B, W, m, t, thr, rot, st));
+      std::swap(A, B);
+    }
+    int h = 0;
+    HIPCHK(hipMemcpyAsync(&h, rot, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    converged = (h == 0);
+  }
+  if (!converged) {
+    set_err("Jacobi eigensolver did not converge in %s%lld sweeps", "", max_sweeps);
+    throw Fail{ADAGIO_E_NO_CONVERGENCE};
+  }
+  ax.sweeps = sweep;
+  ax.lam = lam_out ? lam_out : ensure<double>(ws.lam, (size_t)d);
+  ax.Vt = Vt_out ? Vt_out : ensure<double>(ws.Vt, (size_t)(d * d));
+  HIPCHK(launch_eig_sort(A, W, m, (int)d, ax.lam, ax.Vt, st));
+  return ax;
+}
+
+// ------------------------------------------------------------------ map
+// Pi (r x d, FP32) of Algorithm 1 at target dimension r.
+static void build_map(Workspace& ws, const double* Vt, int64_t d, int64_t r, uint64_t seed, float* Pi,
+                      hipStream_t st) {
+  if (r == d) {
+    HIPCHK(launch_copy_rows(Vt, d, d, Pi, nullptr, st));
+    return;
+  }
+  const int64_t s = r / 2, k = r - r / 2;
+  HIPCHK(launch_copy_rows(Vt, s, d, Pi, nullptr, st));
+  double* S = ensure<double>(ws.S, (size_t)(k * d));
+  HIPCHK(launch_jl_signs(seed, k, d, S, st));
+  double* T = ensure<double>(ws.T, (size_t)(k * (s > 0 ? s : 1)));
+  if (s > 0) HIPCHK(launch_proj_T(S, k, d, Vt, s, T, st));
+  HIPCHK(launch_proj_SQ(S, T, k, s, Vt, d, Pi, nullptr, st));
+}
+
+// ----------------------------------------------------------- certificate
+struct Images {
+  int64_t r = 0, ldy = 0;
+  float* Yc = nullptr;
+  float2* ty = nullptr;
+  const float* Y32 = nullptr;   // rescore source (given images) ...
+  const double* Y64 = nullptr;  // ... or FP64 images of a map
+};
+
+// Images of the linear map Pi in FP64, centred: Y64 = (X - mu) Pi^T.
+static Images images_of_map(Workspace& ws, const Points& p, const float* Pi, int64_t r, hipStream_t st) {
+  Images im;
+  im.r = r;
+  im.ldy = round_up(r, kChunk);
+  double* Y64 = ensure<double>(ws.Y64, (size_t)(p.n * r));
+  HIPCHK(launch_embed_f64(p.X, p.n, p.d, p.mu, Pi, r, Y64, st));
+  im.Yc = ensure<float>(ws.Yc, (size_t)(p.n_pad * im.ldy));
+  double* ny = ensure<double>(ws.ny, (size_t)p.n_pad);
+  HIPCHK(launch_center<double>(Y64, p.n, r, r, nullptr, im.Yc, im.ldy, p.n_pad, ny, st));
+  im.ty = ensure<float2>(ws.ty, (size_t)p.n_pad);
+  // FP64 embedding error: |E_64^2 - E^2| <= 4.02 gamma_{d+1} ||Pi||_F^2 (N_i + N_j)
+  // with ||Pi||_F^2 <= s + d <= 2.1 d for Algorithm 1's maps.
+  const double dd = (double)p.d;
+  const double c_emb = 4.02 * 2.1 * dd * (dd + 1.0) * kU64 * 1.01;
+  HIPCHK(launch_row_terms(ny, screen_const(im.ldy), p.nx, c_emb, p.n_pad, im.ty, st));
+  im.Y64 = Y64;
+  return im;
+}
+
+// Given images (FP32), centred by their own mean.
+static Images images_given(Workspace& ws, const Points& p, const float* Y, int64_t r, hipStream_t st) {
+  Images im;
+  im.r = r;
+  im.ldy = round_up(r, kChunk);
+  double* muY = ensure<double>(ws.muY, (size_t)r);
+  mean_rows(ws, Y, p.n, r, r, muY, st);
+  im.Yc = ensure<float>(ws.Yc, (size_t)(p.n_pad * im.ldy));
+  double* ny = ensure<double>(ws.ny, (size_t)p.n_pad);
+  HIPCHK(launch_center<float>(Y, p.n, r, r, muY, im.Yc, im.ldy, p.n_pad, ny, st));
+  im.ty = ensure<float2>(ws.ty, (size_t)p.n_pad);
+  HIPCHK(launch_row_terms(ny, screen_const(im.ldy), nullptr, 0.0, p.n_pad, im.ty, st));
+  im.Y32 = Y;
+  return im;
+}
+
+struct CertTimes {
+  double screen_ms = 0.0, rest_ms = 0.0;
+  int64_t flagged = 0, rescored = 0;
+};
+
+static void rescore(const Points& p, const Images& im, const int2* pairs, const uint32_t* count_ptr,
+                    const int* count_i, uint32_t cap, PairVal* out, int grid, hipStream_t st) {
+  if (im.Y64) HIPCHK(launch_rescore<double>(p.X, p.d, im.Y64, im.r, pairs, count_ptr, count_i, cap, out, grid, st));
+  else HIPCHK(launch_rescore<float>(p.X, p.d, im.Y32, im.r, pairs, count_ptr, count_i, cap, out, grid, st));
+}
+
+static const uint32_t kDefaultCap = 1u << 20;
+static const uint32_t kHardCap = 1u << 26;
+
+static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& im, uint32_t cap0,
+                                 hipStream_t st, CertTimes* times) {
+  PairsView v;
+  v.X = p.Xc; v.ldx = (int)p.ldx;
+  v.Y = im.Yc; v.ldy = (int)im.ldy;
+  v.tx = p.tx; v.ty = im.ty;
+  v.n = (int)p.n;
+  v.NT = (int)(p.n_pad / kTile);
+  v.ntiles = (int64_t)v.NT * (v.NT + 1) / 2;
+
+  TileRec* recs = ensure<TileRec>(ws.recs, (size_t)v.ntiles);
+  const int nparts = 256;
+  TileRec* tparts = ensure<TileRec>(ws.tparts, nparts);
+  int2* seeds = ensure<int2>(ws.seeds, 2);
+  PairVal* seedv = ensure<PairVal>(ws.seedv, 2);
+  uint32_t* list = ensure<uint32_t>(ws.list, (size_t)v.ntiles);
+  CertDev* cd = ensure<CertDev>(ws.cd, 1);
+  const int vp = 64;
+  PairVal* vparts = ensure<PairVal>(ws.vparts, 2 * vp);
+
+  EvPair e_screen, e_rest;
+  e_screen.begin(st);
+  HIPCHK(launch_pairs_screen(v, recs, st));
+  e_screen.end(st);
+  e_rest.begin(st);
+  HIPCHK(launch_seeds(recs, v.ntiles, tparts, nparts, seeds, cd, st));
+  rescore(p, im, seeds, nullptr, &cd->n_seed, 2, seedv, 1, st);
+  HIPCHK(launch_thresholds(seedv, cd, st));
+  HIPCHK(launch_flag_tiles(recs, v.ntiles, cd, list, st));
+
+  uint32_t cap = cap0 ? cap0 : kDefaultCap;
+  CertDev h;
+  for (;;) {
+    int2* cand = ensure<int2>(ws.cand, cap);
+    PairVal* vals = ensure<PairVal>(ws.vals, cap);
+    HIPCHK(hipMemsetAsync(&cd->n_cand, 0, sizeof(uint32_t), st));
+    const int egrid = (int)std::min<int64_t>(v.ntiles, 2048);
+    HIPCHK(launch_pairs_emit(v, list, cd, cand, cap, &cd->n_cand, egrid, st));
+    rescore(p, im, cand, &cd->n_cand, nullptr, cap, vals, 1024, st);
+    HIPCHK(launch_top2(vals, &cd->n_cand, cap, vparts, vp, cd, st));
+    HIPCHK(hipMemcpyAsync(&h, cd, sizeof(CertDev), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (h.n_cand <= cap || cap >= kHardCap) break;
+    // More candidates than room: grow and redo the exact pass (the thresholds
+    // and flagged tiles are unchanged).
+    cap = h.n_cand > kHardCap ? kHardCap : h.n_cand;
+    // restore the seed-only best/second before re-merging
+    HIPCHK(launch_thresholds(seedv, cd, st));
+  }
+  e_rest.end(st);
+  HIPCHK(hipStreamSynchronize(st));
+
+  adagio_cert_t c;
+  memset(&c, 0, sizeof(c));
+  c.n_pairs = p.n * (p.n - 1) / 2;
+  c.n_flagged_tiles = h.n_flagged;
+  c.n_rescored = (int64_t)h.n_seed + (int64_t)std::min<uint32_t>(h.n_cand, cap);
+  const bool complete = h.n_cand <= cap;
+  if (h.best.i >= 0) {
+    c.max_distortion = h.best.v;
+    c.i = h.best.i;
+    c.j = h.best.j;
+    c.side = h.best.side;
+  } else {
+    c.max_distortion = 0.0;
+    c.i = c.j = -1;
+    c.side = 0;
+  }
+  if (h.second.i >= 0) {
+    c.runner_up = h.second.v;
+    c.i2 = h.second.i;
+    c.j2 = h.second.j;
+  } else {
+    c.runner_up = -1.0;
+    c.i2 = c.j2 = -1;
+  }
+  // Rigorous bound over every pair from the screen's global extremes.
+  const double qh = (double)h.qhi_all, ql = (double)h.qlo_all;
+  const double ub = std::max(std::sqrt(std::max(qh, 0.0)) - 1.0, 1.0 - std::sqrt(std::max(ql, 0.0)));
+  if (complete) {
+    c.certified = 1;
+    c.bound_rest = h.bound_rest;
+  } else {
+    c.certified = 0;
+    c.bound_rest = std::max(ub * (1.0 + 1e-12), c.max_distortion);
+  }
+  if (times) {
+    times->screen_ms += e_screen.ms();
+    times->rest_ms += e_rest.ms();
+    times->flagged += h.n_flagged;
+    times->rescored += c.n_rescored;
+  }
+  return c;
+}
+
+static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+template <typename F>
+static int guarded(F&& f) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_err.clear();
+  try {
+    f();
+    return ADAGIO_OK;
+  } catch (const Fail& e) {
+    return e.code;
+  } catch (...) {
+    g_err = "unexpected host exception";
+    return ADAGIO_E_HIP;
+  }
+}
+
+static void check_points(const float* X, int64_t n, int64_t d) {
+  ARGCHK(X != nullptr, "X is NULL");
+  ARGCHK(n >= 2, "need n >= 2 points");
+  ARGCHK(d >= 1, "need d >= 1");
+  if (n > (int64_t)0x7fffff00 || d > (int64_t)0x100000) {
+    set_err("n or d beyond the supported range%s%lld", "", 0);
+    throw Fail{ADAGIO_E_UNSUPPORTED};
+  }
+}
+
+}  // namespace adg
+
+using namespace adg;
+
+extern "C" {
+
+int adagio_pca(const float* X, int64_t n, int64_t d, double* lambda, double* Vt, void* stream) {
+  return guarded([&] {
+    check_points(X, n, d);
+    ARGCHK(lambda && Vt, "lambda or Vt is NULL");
+    hipStream_t st = as_stream(stream);
+    Workspace& ws = workspace();
+    Points p = prep_points(ws, X, n, d, st);
+    principal_axes(ws, p, st, lambda, Vt);
+    HIPCHK(hipStreamSynchronize(st));
+  });
+}
+
+int adagio_project_axes(const double* Vt, int64_t d, int32_t r, uint64_t seed, float* Pi_out, void* stream) {
+  return guarded([&] {
+    ARGCHK(Vt && Pi_out, "Vt or Pi_out is NULL");
+    ARGCHK(d >= 1, "need d >= 1");
+    ARGCHK(r >= 1 && r <= d, "r must be in [1, d]");
+    Workspace& ws = workspace();
+    build_map(ws, Vt, d, r, seed, Pi_out, as_stream(stream));
+  });
+}
+
+int adagio_project(const float* X, int64_t n, int64_t d, int32_t r, uint64_t seed, float* Pi_out, void* stream) {
+  return guarded([&] {
+    check_points(X, n, d);
+    ARGCHK(Pi_out, "Pi_out is NULL");
+    ARGCHK(r >= 1 && r <= d, "r must be in [1, d]");
+    hipStream_t st = as_stream(stream);
+    Workspace& ws = workspace();
+    Points p = prep_points(ws, X, n, d, st);
+    Axes ax = principal_axes(ws, p, st);
+    build_map(ws, ax.Vt, d, r, seed, Pi_out, st);
+    HIPCHK(hipStreamSynchronize(st));
+  });
+}
+
+int adagio_embed(const float* X, int64_t n, int64_t d, const float* Pi, int32_t r, float* Y_out, void* stream) {
+  return guarded([&] {
+    ARGCHK(X && Pi && Y_out, "NULL pointer");
+    ARGCHK(n >= 1 && d >= 1, "need n >= 1 and d >= 1");
+    ARGCHK(r >= 1, "need r >= 1");
+    (void)workspace();
+    HIPCHK(launch_embed_f32(X, n, d, Pi, r, Y_out, as_stream(stream)));
+  });
+}
+
+int adagio_max_distortion(const float* X, int64_t n, int64_t d, const float* Y, int32_t r, const adagio_opts_t* opts,
+                          adagio_cert_t* cert_out, void* stream) {
+  return guarded([&] {
+    check_points(X, n, d);
+    ARGCHK(Y && cert_out, "Y or cert_out is NULL");
+    ARGCHK(r >= 1, "need r >= 1");
+    ARGCHK(!opts || opts->screen == ADAGIO_SCREEN_F32, "only the FP32 screen is available here");
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = as_stream(stream);
+    Workspace& ws = workspace();
+    Points p = prep_points(ws, X, n, d, st);
+    Images im = images_given(ws, p, Y, r, st);
+    CertTimes tm;
+    *cert_out = certificate(ws, p, im, opts ? (uint32_t)std::max(0, opts->max_candidates) : 0u, st, &tm);
+    if (opts && opts->stats) {
+      adagio_stats_t* s = opts->stats;
+      memset(s, 0, sizeof(*s));
+      s->t_screen_ms = tm.screen_ms;
+      s->t_rescore_ms = tm.rest_ms;
+      s->n_certificates = 1;
+      s->n_flagged_tiles = tm.flagged;
+      s->n_rescored = tm.rescored;
+      s->t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+  });
+}
+
+int adagio_certify_map(const float* X, int64_t n, int64_t d, const float* Pi, int32_t r, const adagio_opts_t* opts,
+                       adagio_cert_t* cert_out, void* stream) {
+  return guarded([&] {
+    check_points(X, n, d);
+    ARGCHK(Pi && cert_out, "Pi or cert_out is NULL");
+    ARGCHK(r >= 1, "need r >= 1");
+    ARGCHK(!opts || opts->screen == ADAGIO_SCREEN_F32, "only the FP32 screen is available here");
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = as_stream(stream);
+    Workspace& ws = workspace();
+    Points p = prep_points(ws, X, n, d, st);
+    Images im = images_of_map(ws, p, Pi, r, st);
+    CertTimes tm;
+    *cert_out = certificate(ws, p, im, opts ? (uint32_t)std::max(0, opts->max_candidates) : 0u, st, &tm);
+    if (opts && opts->stats) {
+      adagio_stats_t* s = opts->stats;
+      memset(s, 0, sizeof(*s));
+      s->t_screen_ms = tm.screen_ms;
+      s->t_rescore_ms = tm.rest_ms;
+      s->n_certificates = 1;
+      s->n_flagged_tiles = tm.flagged;
+      s->n_rescored = tm.rescored;
+      s->t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+  });
+}
+
+int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, const adagio_opts_t* opts,
+               float* Pi_out, int32_t* r_out, int32_t* s_out, adagio_cert_t* cert_out, void* stream) {
+  return guarded([&] {
+    check_points(X, n, d);
+    ARGCHK(Pi_out && r_out && s_out && cert_out, "NULL output pointer");
+    ARGCHK(eps > 0.0 && eps < 1.0, "eps must be in (0, 1)");
+    ARGCHK(!opts || opts->screen == ADAGIO_SCREEN_F32, "only the FP32 screen is available here");
+    ARGCHK(!opts || opts->search == ADAGIO_SEARCH_BISECT, "only the bisection search is available here");
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = as_stream(stream);
+    Workspace& ws = workspace();
+    const uint32_t cap0 = opts ? (uint32_t)std::max(0, opts->max_candidates) : 0u;
+    EvPair e_pca, e_search;
+    e_pca.begin(st);
+    Points p = prep_points(ws, X, n, d, st);
+    Axes ax = principal_axes(ws, p, st);
+    e_pca.end(st);
+    e_search.begin(st);
+    float* Pi = ensure<float>(ws.Pi, (size_t)(d * d));
+    CertTimes tm;
+    int ncert = 0;
+    // Bisection over r: lo = 0 (empty map, distortion 1), hi = d (isometry).
+    int64_t lo = 0, hi = d;
+    bool have_hi = false;
+    adagio_cert_t cert_hi;
+    memset(&cert_hi, 0, sizeof(cert_hi));
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) / 2;
+      build_map(ws, ax.Vt, d, mid, seed, Pi, st);
+      Images im = images_of_map(ws, p, Pi, mid, st);
+      adagio_cert_t c = certificate(ws, p, im, cap0, st, &tm);
+      ++ncert;
+      // Pass when the exact maximum is <= eps, or (incomplete certificate)
+      // when the proven bound over all pairs is <= eps.
+      const bool pass = c.certified ? c.max_distortion <= eps : c.bound_rest <= eps;
+      if (pass) {
+        hi = mid;
+        have_hi = true;
+        cert_hi = c;
+        HIPCHK(hipMemcpyAsync(Pi_out, Pi, sizeof(float) * mid * d, hipMemcpyDeviceToDevice, st));
+      } else {
+        lo = mid;
+      }
+    }
+    if (!have_hi) {  // hi == d: the full eigenbasis
+      build_map(ws, ax.Vt, d, d, seed, Pi_out, st);
+      Images im = images_of_map(ws, p, Pi_out, d, st);
+      cert_hi = certificate(ws, p, im, cap0, st, &tm);
+      ++ncert;
+    }
+    e_search.end(st);
+    HIPCHK(hipStreamSynchronize(st));
+    *r_out = (int32_t)hi;
+    *s_out = (int32_t)(hi == d ? d : hi / 2);
+    *cert_out = cert_hi;
+    if (opts && opts->stats) {
+      adagio_stats_t* s = opts->stats;
+      memset(s, 0, sizeof(*s));
+      s->t_pca_ms = e_pca.ms();
+      s->t_search_ms = e_search.ms();
+      s->t_screen_ms = tm.screen_ms;
+      s->t_rescore_ms = tm.rest_ms;
+      s->n_certificates = ncert;
+      s->eig_sweeps = ax.sweeps;
+      s->n_flagged_tiles = tm.flagged;
+      s->n_rescored = tm.rescored;
+      s->t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+  });
+}
+
+int adagio_release(void) {
+  return guarded([&] {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return;
+    Workspace& ws = g_ws[dev];
+    DevBuf* bufs[] = {&ws.mu, &ws.colpart, &ws.nonfinite, &ws.Xc, &ws.nx, &ws.tx, &ws.covpart, &ws.A0, &ws.A1,
+                      &ws.W, &ws.trace, &ws.rot, &ws.lam, &ws.Vt, &ws.S, &ws.T, &ws.Pi, &ws.Pi64, &ws.Y64,
+                      &ws.Yc, &ws.ny, &ws.ty, &ws.muY, &ws.recs, &ws.tparts, &ws.seeds, &ws.seedv, &ws.list,
+                      &ws.cand, &ws.vals, &ws.vparts, &ws.cd};
+    for (DevBuf* b : bufs) {
+      if (b->p) HIPCHK(hipFree(b->p));
+      b->p = nullptr;
+      b->cap = 0;
+    }
+  });
+}
+
+const char* adagio_status_string(int status) {
+  switch (status) {
+    case ADAGIO_OK: return "ok";
+    case ADAGIO_E_INVALID_ARG: return "invalid argument";
+    case ADAGIO_E_NONFINITE: return "non-finite input";
+    case ADAGIO_E_HIP: return "HIP runtime error";
+    case ADAGIO_E_OOM: return "out of device memory";
+    case ADAGIO_E_UNSUPPORTED: return "unsupported device or size";
+    case ADAGIO_E_NO_CONVERGENCE: return "eigensolver did not converge";
+    case ADAGIO_E_CAPACITY: return "candidate capacity exceeded";
+    case ADAGIO_E_NOT_CERTIFIED: return "certificate incomplete";
+    default: return "unknown status";
+  }
+}
+
+const char* adagio_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,64 @@
+// Launchers of the gfx950 kernels (internal to the library).
+#pragma once
+#include "common.h"
+
+namespace adg {
+
+// k_prep.hip
+template <typename T>
+hipError_t launch_mean(const T* A, int64_t n, int64_t m, int64_t ld, double* partial, int64_t nchunks,
+                       int64_t rows_per_chunk, double* mu, int* nonfinite, hipStream_t st);
+template <typename T>
+hipError_t launch_center(const T* src, int64_t n, int64_t m, int64_t lds, const double* mu, float* dst,
+                         int64_t ldd, int64_t n_pad, double* norm2, hipStream_t st);
+hipError_t launch_row_terms(const double* norm2, double c_self, const double* norm2_other, double c_other,
+                            int64_t n_pad, float2* terms, hipStream_t st);
+
+// k_gemm64.hip
+hipError_t launch_covariance(const float* X, int64_t n, int64_t d, const double* mu, double* part, int nsplit,
+                             double* C, int64_t m_pad, hipStream_t st);
+hipError_t launch_embed_f64(const float* X, int64_t n, int64_t d, const double* mu, const float* Pi, int64_t r,
+                            double* Y, hipStream_t st);
+hipError_t launch_embed_f32(const float* X, int64_t n, int64_t d, const float* Pi, int64_t r, float* Y,
+                            hipStream_t st);
+hipError_t launch_proj_T(const double* S, int64_t k, int64_t d, const double* Vt, int64_t s, double* T,
+                         hipStream_t st);
+hipError_t launch_proj_SQ(const double* S, const double* T, int64_t k, int64_t s, const double* Vt, int64_t d,
+                          float* Pi, double* Pi64, hipStream_t st);
+
+// k_eig.hip
+hipError_t launch_eye(double* W, int m, hipStream_t st);
+hipError_t launch_trace(const double* A, int m, double* out, hipStream_t st);
+hipError_t launch_jacobi_round(const double* A, double* A2, double* W, int m, int t, double thr, int* rot_count,
+                               hipStream_t st);
+hipError_t launch_eig_sort(const double* A, const double* W, int m, int d, double* lam, double* Vt,
+                           hipStream_t st);
+
+// k_proj.hip
+hipError_t launch_jl_signs(uint64_t seed, int64_t k, int64_t d, double* S, hipStream_t st);
+hipError_t launch_copy_rows(const double* Vt, int64_t rows, int64_t d, float* Pi, double* Pi64, hipStream_t st);
+
+// k_pairs.hip
+struct PairsView {
+  const float* X; int ldx;      // centred points (n_pad x ldx)
+  const float* Y; int ldy;      // centred images (n_pad x ldy)
+  const float2* tx; const float2* ty;
+  int n; int NT; int64_t ntiles;
+};
+hipError_t launch_pairs_screen(const PairsView& v, TileRec* recs, hipStream_t st);
+hipError_t launch_pairs_emit(const PairsView& v, const uint32_t* list, const CertDev* cd, int2* cand, uint32_t cap,
+                             uint32_t* ncand, int grid, hipStream_t st);
+
+// k_cert.hip
+hipError_t launch_seeds(const TileRec* recs, int64_t ntiles, TileRec* part, int nparts, int2* seeds, CertDev* cd,
+                        hipStream_t st);
+template <typename TY>
+hipError_t launch_rescore(const float* X, int64_t d, const TY* Y, int64_t r, const int2* pairs,
+                          const uint32_t* count_ptr, const int* count_i, uint32_t cap, PairVal* out, int grid,
+                          hipStream_t st);
+hipError_t launch_thresholds(const PairVal* seedv, CertDev* cd, hipStream_t st);
+hipError_t launch_flag_tiles(const TileRec* recs, int64_t ntiles, CertDev* cd, uint32_t* list, hipStream_t st);
+hipError_t launch_top2(const PairVal* vals, const uint32_t* count_ptr, uint32_t cap, PairVal* part, int nparts,
+                       CertDev* cd, hipStream_t st);
+
+}  // namespace adg

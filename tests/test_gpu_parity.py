@@ -1,0 +1,215 @@
+"""GPU parity of the HIP path against the FP64 oracle.
+
+Every call goes through the C ABI (via its ctypes binding).  Inputs are the
+seeded generators' FP32 arrays; expected values come from ``oracle/`` only.
+Tolerances: 1e-5 absolute on the max distortion (FP32 path), argmax equal when
+the oracle's runner-up gap exceeds 1e-5; eigen-subspaces compared as
+projectors where the eigengap allows.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import certificate, embedding, pca as opca, search
+from paper_1609_05388_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def oracle_cert_of_map(X, Pi32):
+    Pi = np.asarray(Pi32, dtype=np.float64)
+    return certificate.certify(X, embedding.embed(X, Pi))
+
+
+def assert_cert_parity(got, want, tol=TOL):
+    assert got["certified"] == 1
+    assert abs(got["max_distortion"] - want["max"]) <= tol, (got, want)
+    if want["max"] - want["runner_up"] > tol:
+        assert (got["i"], got["j"]) == (want["i"], want["j"]), (got, want)
+        assert got["side"] == want["side"]
+
+
+# ---------------------------------------------------------------- a1 - a3
+@pytest.mark.parametrize("n,d", [(300, 48), (129, 7), (2000, 784), (65, 1)])
+def test_pca_matches_oracle(gpu_lib, n, d):
+    X = gen.low_rank_pixels(n=n, d=d, rank=min(6, d), seed=n + d)
+    lam, Vt = gpu_lib.pca(dev(X))
+    lam, Vt = lam.cpu().numpy(), Vt.cpu().numpy()
+    _, C, lam_o, Vt_o = opca.pca(X)
+    scale = max(lam_o[0], 1e-300)
+    assert np.abs(lam - lam_o).max() <= 1e-11 * scale * d
+    assert np.abs(Vt @ Vt.T - np.eye(d)).max() <= 1e-12 * d
+    resid = C @ Vt.T - Vt.T * lam
+    assert np.abs(resid).max() <= 1e-11 * scale * d
+    for s in sorted({1, 2, d // 4, d // 2, d - 1} - {0}):
+        if s < d and lam_o[s - 1] - lam_o[s] > 1e-6 * scale:
+            Pg = Vt[:s].T @ Vt[:s]
+            Po = Vt_o[:s].T @ Vt_o[:s]
+            gap = (lam_o[s - 1] - lam_o[s]) / scale
+            assert np.abs(Pg - Po).max() <= 1e-14 * d / gap + 1e-12, s
+
+
+# ------------------------------------------------------------------- a4-a5
+@pytest.mark.parametrize("d,r", [(40, 1), (40, 2), (40, 3), (40, 17), (40, 39), (40, 40), (784, 190), (784, 391)])
+def test_project_axes_matches_oracle(gpu_lib, d, r):
+    X = gen.low_rank_pixels(n=500, d=d, rank=8, seed=d + r)
+    _, _, lam_o, Vt_o = opca.pca(X)
+    Pi = gpu_lib.project_axes(dev(Vt_o), r, 5388).cpu().numpy()
+    want = embedding.adagio_map(Vt_o, r, 5388)
+    assert Pi.shape == want.shape
+    assert np.abs(Pi.astype(np.float64) - want).max() <= 4e-7 * max(1.0, np.abs(want).max())
+
+
+def test_jl_rows_are_the_published_signs(gpu_lib):
+    """With P empty (r = 1) Pi is the first row of S: the SplitMix64 signs."""
+    d = 96
+    Vt = np.eye(d)
+    Pi = gpu_lib.project_axes(dev(Vt), 1, 12345).cpu().numpy()
+    from oracle import jl_signs
+    assert np.array_equal(Pi[0], jl_signs.sign_matrix(12345, 1, d)[0].astype(np.float32))
+
+
+# ---------------------------------------------------------------------- a6
+@pytest.mark.parametrize("n,d,r", [(1000, 784, 190), (65, 7, 3), (3, 1, 1)])
+def test_embed_matches_oracle(gpu_lib, n, d, r):
+    X = gen.gaussian(n, d, seed=n)
+    Pi = gen.gaussian(r, d, seed=r + 7)
+    Y = gpu_lib.embed(dev(X), dev(Pi)).cpu().numpy()
+    want = embedding.embed(X, Pi.astype(np.float64))
+    assert np.abs(Y - want).max() <= 1e-6 * np.abs(want).max() + 1e-30
+
+
+# ------------------------------------------------------------------ a7 - a8
+def test_max_distortion_parity_c1(gpu_lib):
+    X = gen.low_rank_pixels()
+    _, _, _, Vt = opca.pca(X)
+    for r in (93, 190, 213, 364):
+        Y = embedding.embed(X, embedding.adagio_map(Vt, r, gen.JL_SEED)).astype(np.float32)
+        got = gpu_lib.max_distortion(dev(X), dev(Y))
+        want = certificate.certify(X, Y)
+        assert_cert_parity(got, want)
+        assert got["n_pairs"] == 2000 * 1999 // 2
+
+
+def test_certify_map_parity_c1(gpu_lib):
+    X = gen.low_rank_pixels()
+    _, _, _, Vt = opca.pca(X)
+    for r in (49, 190, 391, 784):
+        Pi32 = embedding.adagio_map(Vt, r, gen.JL_SEED).astype(np.float32)
+        got = gpu_lib.certify_map(dev(X), dev(Pi32))
+        want = oracle_cert_of_map(X, Pi32)
+        assert_cert_parity(got, want)
+
+
+@pytest.mark.parametrize("n", [2, 3, 63, 64, 65, 127, 128, 129, 257, 700])
+@pytest.mark.parametrize("d,r", [(1, 1), (7, 3), (64, 20), (100, 99)])
+def test_certificate_ragged_shapes(gpu_lib, n, d, r):
+    X = gen.gaussian(n, d, seed=1000 * n + d)
+    Pi = gen.gaussian(r, d, seed=r) / np.float32(np.sqrt(d))
+    Y = embedding.embed(X, Pi.astype(np.float64)).astype(np.float32)
+    got = gpu_lib.max_distortion(dev(X), dev(Y))
+    want = certificate.certify(X, Y)
+    assert_cert_parity(got, want)
+    gm = gpu_lib.certify_map(dev(X), dev(Pi))
+    assert_cert_parity(gm, oracle_cert_of_map(X, Pi))
+
+
+def test_certificate_duplicates_and_identical(gpu_lib):
+    X = gen.with_duplicates(gen.gaussian(300, 12, seed=4), 40)
+    Pi = gen.gaussian(5, 12, seed=3)
+    Y = embedding.embed(X, Pi.astype(np.float64)).astype(np.float32)
+    got = gpu_lib.max_distortion(dev(X), dev(Y))
+    assert_cert_parity(got, certificate.certify(X, Y))
+    same = np.tile(gen.gaussian(1, 9, seed=2), (50, 1))
+    g2 = gpu_lib.max_distortion(dev(same), dev(same[:, :4].copy()))
+    assert g2["max_distortion"] == 0.0 and g2["i"] == -1 and g2["certified"] == 1
+
+
+def test_certificate_offset_data(gpu_lib):
+    """Points far from the origin: centring keeps the screen exact enough."""
+    X = gen.gaussian(400, 30, seed=8, scale=0.01, offset=50.0)
+    Pi = gen.gaussian(10, 30, seed=9)
+    Y = embedding.embed(X, Pi.astype(np.float64)).astype(np.float32)
+    got = gpu_lib.max_distortion(dev(X), dev(Y))
+    assert_cert_parity(got, certificate.certify(X, Y))
+
+
+def test_nonfinite_rejected(gpu_lib):
+    X = gen.gaussian(50, 4, seed=1)
+    X[7, 2] = np.nan
+    with pytest.raises(gpu_lib.AdagioError) as e:
+        gpu_lib.max_distortion(dev(X), dev(X[:, :2].copy()))
+    assert e.value.code == -2
+
+
+# ---------------------------------------------------------------------- fit
+@pytest.mark.parametrize("eps", [0.05, 0.1, 0.2])
+def test_fit_parity_c1(gpu_lib, eps):
+    X = gen.low_rank_pixels()
+    got = gpu_lib.fit(dev(X), eps, gen.JL_SEED)
+    want = search.fit(X, eps, gen.JL_SEED)
+    Pi = got["Pi"].cpu().numpy()
+    # the GPU's map is certified exactly: oracle certificate of the same Pi
+    oc = oracle_cert_of_map(X, Pi)
+    assert_cert_parity(got["cert"], oc)
+    assert got["cert"]["max_distortion"] <= eps
+    # same r* unless a probe's distortion is within the tolerance of eps
+    near = [abs(v - eps) for _, v in want["probes"]]
+    if min(near) > TOL:
+        assert got["r"] == want["r"]
+        assert abs(got["cert"]["max_distortion"] - want["cert"]["max"]) <= TOL
+    # the principal part spans the oracle's subspace where the gap allows
+    s = got["s"]
+    lam = want["lam"]
+    if 0 < s < X.shape[1] and lam[s - 1] - lam[s] > 1e-6 * lam[0]:
+        Pg = Pi[:s].astype(np.float64)
+        Po = want["Vt"][:s]
+        assert np.abs(Pg.T @ Pg - Po.T @ Po).max() <= 1e-5
+
+
+def test_fit_deterministic(gpu_lib):
+    X = dev(gen.low_rank_pixels(n=700, d=200, rank=10, seed=3))
+    a = gpu_lib.fit(X, 0.1, 7)
+    b = gpu_lib.fit(X, 0.1, 7)
+    assert a["r"] == b["r"]
+    assert torch.equal(a["Pi"], b["Pi"])
+    assert a["cert"] == b["cert"]
+
+
+def test_fit_exact_rank_cloud(gpu_lib):
+    """Points on a q-dim subspace: r = 2q already isometric up to rounding."""
+    X = gen.exact_rank(500, 64, 5, seed=6)
+    got = gpu_lib.fit(dev(X), 0.05, 1)
+    assert got["r"] <= 10
+    assert got["cert"]["max_distortion"] <= 0.05
+
+
+# -------------------------------------------------------- full-size (C2)
+def test_c2_certificate_properties(gpu_lib):
+    """n = 60000: the oracle checks the reported pairs one by one and random
+    pairs stay below the certified maximum."""
+    X = gen.mnist_shaped()
+    Xd = dev(X)
+    lam, Vt = gpu_lib.pca(Xd)
+    Pi = gpu_lib.project_axes(Vt, 190, gen.JL_SEED)
+    got = gpu_lib.certify_map(Xd, Pi)
+    assert got["certified"] == 1
+    Pi64 = Pi.cpu().numpy().astype(np.float64)
+    Y = embedding.embed(X, Pi64)
+    v, _ = certificate.pair_distortions(X, Y, [got["i"]], [got["j"]])
+    assert abs(v[0] - got["max_distortion"]) <= 1e-12
+    if got["i2"] >= 0:
+        v2, _ = certificate.pair_distortions(X, Y, [got["i2"]], [got["j2"]])
+        assert abs(v2[0] - got["runner_up"]) <= 1e-12
+    rng = np.random.default_rng(0)
+    I = rng.integers(0, 60000, 200000)
+    J = rng.integers(0, 60000, 200000)
+    keep = I != J
+    vals, _ = certificate.pair_distortions(X, Y, np.minimum(I, J)[keep], np.maximum(I, J)[keep])
+    assert vals.max() <= got["max_distortion"] + 1e-12
