@@ -83,6 +83,11 @@ typedef struct adagio_stats {
     int32_t r_predicted;     /* learned search: the network's r (0 otherwise)     */
     int64_t n_flagged_tiles; /* summed over certificates                          */
     int64_t n_rescored;      /* summed over certificates                          */
+    int32_t n_probes;        /* certificates logged below, in call order (<= 48)  */
+    int32_t reserved;
+    int32_t probe_r[48];     /* target dimension of each certificate              */
+    double probe_delta[48];  /* its exact max distortion                          */
+    double probe_screen_ms[48]; /* its all-pairs screen kernel time (device events) */
 } adagio_stats_t;
 
 typedef struct adagio_opts {

@@ -40,10 +40,18 @@ class Stats(ctypes.Structure):
                 ("t_rescore_ms", ctypes.c_double), ("n_certificates", ctypes.c_int32),
                 ("eig_sweeps", ctypes.c_int32), ("n_fallback", ctypes.c_int32),
                 ("r_predicted", ctypes.c_int32), ("n_flagged_tiles", ctypes.c_int64),
-                ("n_rescored", ctypes.c_int64)]
+                ("n_rescored", ctypes.c_int64), ("n_probes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("probe_r", ctypes.c_int32 * 48),
+                ("probe_delta", ctypes.c_double * 48), ("probe_screen_ms", ctypes.c_double * 48)]
 
     def to_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            if name.startswith("probe_"):
+                v = list(v)[:self.n_probes]
+            out[name] = v
+        return out
 
 
 class Opts(ctypes.Structure):

@@ -288,7 +288,35 @@ static Images images_given(Workspace& ws, const Points& p, const float* Y, int64
 struct CertTimes {
   double screen_ms = 0.0, rest_ms = 0.0;
   int64_t flagged = 0, rescored = 0;
+  int nprobe = 0;
+  int32_t probe_r[48];
+  double probe_delta[48], probe_ms[48];
 };
+
+static void log_probe(CertTimes& tm, int64_t r, const adagio_cert_t& c, double screen_ms) {
+  if (tm.nprobe < 48) {
+    tm.probe_r[tm.nprobe] = (int32_t)r;
+    tm.probe_delta[tm.nprobe] = c.max_distortion;
+    tm.probe_ms[tm.nprobe] = screen_ms;
+    ++tm.nprobe;
+  }
+}
+
+static void fill_stats(adagio_stats_t* s, const CertTimes& tm, int ncert, double total_ms) {
+  memset(s, 0, sizeof(*s));
+  s->t_screen_ms = tm.screen_ms;
+  s->t_rescore_ms = tm.rest_ms;
+  s->n_certificates = ncert;
+  s->n_flagged_tiles = tm.flagged;
+  s->n_rescored = tm.rescored;
+  s->n_probes = tm.nprobe;
+  for (int k = 0; k < tm.nprobe; ++k) {
+    s->probe_r[k] = tm.probe_r[k];
+    s->probe_delta[k] = tm.probe_delta[k];
+    s->probe_screen_ms[k] = tm.probe_ms[k];
+  }
+  s->t_total_ms = total_ms;
+}
 
 static void rescore(const Points& p, const Images& im, const int2* pairs, const uint32_t* count_ptr,
                     const int* count_i, uint32_t cap, PairVal* out, int grid, hipStream_t st) {
@@ -386,10 +414,12 @@ static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& i
     c.bound_rest = std::max(ub * (1.0 + 1e-12), c.max_distortion);
   }
   if (times) {
-    times->screen_ms += e_screen.ms();
+    const double sm = e_screen.ms();
+    times->screen_ms += sm;
     times->rest_ms += e_rest.ms();
     times->flagged += h.n_flagged;
     times->rescored += c.n_rescored;
+    log_probe(*times, im.r, c, sm);
   }
   return c;
 }
@@ -487,16 +517,9 @@ int adagio_max_distortion(const float* X, int64_t n, int64_t d, const float* Y, 
     Images im = images_given(ws, p, Y, r, st);
     CertTimes tm;
     *cert_out = certificate(ws, p, im, opts ? (uint32_t)std::max(0, opts->max_candidates) : 0u, st, &tm);
-    if (opts && opts->stats) {
-      adagio_stats_t* s = opts->stats;
-      memset(s, 0, sizeof(*s));
-      s->t_screen_ms = tm.screen_ms;
-      s->t_rescore_ms = tm.rest_ms;
-      s->n_certificates = 1;
-      s->n_flagged_tiles = tm.flagged;
-      s->n_rescored = tm.rescored;
-      s->t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    }
+    if (opts && opts->stats)
+      fill_stats(opts->stats, tm, 1,
+                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
   });
 }
 
@@ -514,16 +537,9 @@ int adagio_certify_map(const float* X, int64_t n, int64_t d, const float* Pi, in
     Images im = images_of_map(ws, p, Pi, r, st);
     CertTimes tm;
     *cert_out = certificate(ws, p, im, opts ? (uint32_t)std::max(0, opts->max_candidates) : 0u, st, &tm);
-    if (opts && opts->stats) {
-      adagio_stats_t* s = opts->stats;
-      memset(s, 0, sizeof(*s));
-      s->t_screen_ms = tm.screen_ms;
-      s->t_rescore_ms = tm.rest_ms;
-      s->n_certificates = 1;
-      s->n_flagged_tiles = tm.flagged;
-      s->n_rescored = tm.rescored;
-      s->t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    }
+    if (opts && opts->stats)
+      fill_stats(opts->stats, tm, 1,
+                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
   });
 }
 
@@ -584,16 +600,11 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     *cert_out = cert_hi;
     if (opts && opts->stats) {
       adagio_stats_t* s = opts->stats;
-      memset(s, 0, sizeof(*s));
+      fill_stats(s, tm, ncert,
+                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
       s->t_pca_ms = e_pca.ms();
       s->t_search_ms = e_search.ms();
-      s->t_screen_ms = tm.screen_ms;
-      s->t_rescore_ms = tm.rest_ms;
-      s->n_certificates = ncert;
       s->eig_sweeps = ax.sweeps;
-      s->n_flagged_tiles = tm.flagged;
-      s->n_rescored = tm.rescored;
-      s->t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
   });
 }

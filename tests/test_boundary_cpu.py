@@ -58,7 +58,7 @@ def test_struct_layouts_match_header():
                 continue
             names = decl.split(None, 1)[1] if not decl.startswith("const") else decl.split(None, 2)[2]
             for nm in names.split(","):
-                fields.append(nm.strip().lstrip("*"))
+                fields.append(re.sub(r"\[.*\]", "", nm).strip().lstrip("*"))
         assert fields == [f for f, _ in py._fields_], cname
 
 
