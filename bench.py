@@ -18,6 +18,8 @@ Printed on one line (JSON):
               block of the same workload, in the same unit
 """
 import argparse
+import collections
+import csv
 import hashlib
 import json
 import os
@@ -50,6 +52,53 @@ def traffic_per_launch():
     if rec.get("kernel_source_sha256") != source_hash(PAIRS_KERNEL_SRC):
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+TRAFFIC_KERNEL = "adg::k_pairs_f32<0>"
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+COPY_BYTES = 1 << 30
+
+
+def per_kernel(path):
+    """Counter bytes (KiB x 1024) per dispatch, grouped by kernel name."""
+    agg = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        agg[r["Kernel_Name"]].append(float(r["Counter_Value"]) * 1024.0)
+    return agg
+
+
+def pick(agg, key):
+    vals = [v for k, vs in agg.items() if key in k for v in vs]
+    return sum(vals) / len(vals), len(vals)
+
+
+def summarize_traffic(d):
+    """HBM bytes per screen launch from two rocprofv3 --pmc runs (FETCH_SIZE,
+    WRITE_SIZE) of this script and of its 1 GiB copy calibration, each counter
+    scaled by the factor that maps its copy reading to 1 GiB."""
+    out = {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        copy_b, _ = pick(per_kernel(os.path.join(d, "copy_%s_counter_collection.csv" % c)), COPY_KERNEL)
+        kern_b, nl = pick(per_kernel(os.path.join(d, "fit_%s_counter_collection.csv" % c)), TRAFFIC_KERNEL)
+        factor = COPY_BYTES / copy_b
+        out[c] = {"copy_counter_bytes": copy_b, "factor": factor, "kernel_counter_bytes_per_launch": kern_b,
+                  "kernel_bytes_per_launch": kern_b * factor, "launches": nl}
+    src = os.path.join(ROOT, "paper_1609_05388_amd", "csrc", "k_pairs.hip")
+    rec = {
+        "kernel": TRAFFIC_KERNEL,
+        "kernel_source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+        "hbm_bytes_per_launch": out["FETCH_SIZE"]["kernel_bytes_per_launch"] + out["WRITE_SIZE"]["kernel_bytes_per_launch"],
+        "fetch": out["FETCH_SIZE"], "write": out["WRITE_SIZE"],
+        "commands": [
+            "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d <repo>/gpurun_out/pmc -o copy_FETCH_SIZE -- python3 <repo>/bench.py --calib-copy-mib 1024",
+            "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d <repo>/gpurun_out/pmc -o fit_FETCH_SIZE -- python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extra-eps",
+            "(the same two with WRITE_SIZE)",
+        ],
+        "note": "counter bytes are KiB x 1024 per dispatch, averaged over the screen launches of one fit "
+                "(10 launches, r from the bisection); each counter is scaled by the factor that maps its "
+                "reading for a plain 1 GiB copy to 1 GiB",
+    }
+    print(json.dumps(rec, indent=1))
 
 
 def cpu_baseline(X, Pi, target_s):
@@ -89,9 +138,16 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra-eps", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the precision-form fits")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this size (HBM counter calibration)")
+    ap.add_argument("--summarize-traffic", metavar="PMC_DIR",
+                    help="print the traffic summary of rocprofv3 --pmc runs in PMC_DIR and exit")
     args = ap.parse_args()
+
+    if args.summarize_traffic:
+        summarize_traffic(args.summarize_traffic)
+        return
 
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -155,6 +211,35 @@ def main():
                 "kernel": "k_pairs_f32<0> (all-pairs screen)", "launches": launches,
                 "avg_launch_ms": avg_ms, "flops_per_launch": flops / launches}
 
+    # precision form: BF16 split screen, same exact certificate
+    forms = {}
+    if not args.no_forms:
+        torch.cuda.synchronize()
+        bf = adagio.fit(Xd, args.eps, gen.JL_SEED, screen="bf16x3")  # warm-up of its buffers
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        bouts = [adagio.fit(Xd, args.eps, gen.JL_SEED, screen="bf16x3") for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        bf_s = (time.perf_counter() - tb) / args.steps
+        bl = bouts[-1]
+        bflops, bms, bn = 0.0, 0.0, 0
+        for o in bouts:
+            for r, t in zip(o["stats"]["probe_r"], o["stats"]["probe_screen_ms"]):
+                bflops += npairs * 2.0 * (d + r)
+                bms += t
+                bn += 1
+        forms["bf16x3"] = {
+            "fit_ms": bf_s * 1e3, "speedup_vs_plain": fit_s / bf_s, "r": bl["r"],
+            "max_distortion": bl["cert"]["max_distortion"], "certified": bl["cert"]["certified"],
+            "abs_err_vs_plain_fp64_certificate": abs(bl["cert"]["max_distortion"] - last["cert"]["max_distortion"]),
+            "same_map_as_plain": bool(bl["r"] == last["r"] and torch.equal(bl["Pi"], last["Pi"])),
+            "screen_avg_launch_ms": bms / bn,
+            "screen_useful_tflops": bflops / bn / (bms / bn * 1e-3) / 1e12,
+            "screen_bf16_mfma_tflops": 3.0 * bflops / bn / (bms / bn * 1e-3) / 1e12,
+            "screen_bf16_mfma_frac": 3.0 * bflops / bn / (bms / bn * 1e-3) / 1e12 / 2516.0,
+            "rescored_pairs": bl["stats"]["n_rescored"], "flagged_tiles": bl["stats"]["n_flagged_tiles"]}
+        log("bf16x3 fit %.1f ms (%.2fx), screen %.2f ms/launch" % (bf_s * 1e3, fit_s / bf_s, bms / bn))
+
     extra = {}
     if not args.no_extra_eps:
         for e in (0.05, 0.2):
@@ -199,6 +284,7 @@ def main():
                 "rescored_pairs": st["n_rescored"], "flagged_tiles": st["n_flagged_tiles"],
                 "probes": [[r, dl] for r, dl in zip(st["probe_r"], st["probe_delta"])]},
         "other_eps": extra,
+        "forms": forms,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "paper_context": "paper: <10 s for 60,000 x 784 MNIST on an i5-3317U laptop (abstract); not this workload",

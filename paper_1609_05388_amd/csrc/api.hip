@@ -55,6 +55,7 @@ struct Workspace {
   DevBuf mu, colpart, nonfinite, Xc, nx, tx, covpart, A0, A1, W, trace, rot, lam, Vt;
   DevBuf S, T, Pi, Pi64, Y64, Yc, ny, ty, muY;
   DevBuf recs, tparts, seeds, seedv, list, cand, vals, vparts, cd;
+  DevBuf Xb, txb, Yb, tyb;
   bool checked = false;
 };
 
@@ -124,6 +125,10 @@ struct Points {
   float* Xc = nullptr;
   double* nx = nullptr;
   float2* tx = nullptr;
+  int screen = ADAGIO_SCREEN_F32;
+  int64_t ldxb = 0;          // BF16 split (screen = BF16X3)
+  __bf16* Xb = nullptr;
+  float2* txb = nullptr;
 };
 
 static void mean_rows(Workspace& ws, const float* A, int64_t n, int64_t m, int64_t ld, double* mu, hipStream_t st) {
@@ -147,8 +152,15 @@ static void mean_rows(Workspace& ws, const float* A, int64_t n, int64_t m, int64
 // of the epilogue's add and fma, and an 8u margin for the reciprocal.
 static double screen_const(int64_t K) { return ((double)K + 32.0) * kU32 * 1.001; }
 
-static Points prep_points(Workspace& ws, const float* X, int64_t n, int64_t d, hipStream_t st) {
+// The same for the BF16 split Gram (x = hi + lo + e, three BF16 products):
+// dropped terms 3.01 * 2^-16 (= 770.6 u) and FP32 accumulation of 3K
+// products of total size 1.012 sum |x||y| (3.04 K u), in place of gamma_K.
+static double screen_const_bf16(int64_t K) { return (3.05 * (double)K + 771.0 + 32.0) * kU32 * 1.001; }
+static const int64_t kChunkBf16 = 32;
+static Points prep_points(Workspace& ws, const float* X, int64_t n, int64_t d, hipStream_t st,
+                          int screen = ADAGIO_SCREEN_F32) {
   Points p;
+  p.screen = screen;
   p.X = X;
   p.n = n;
   p.d = d;
@@ -161,6 +173,13 @@ static Points prep_points(Workspace& ws, const float* X, int64_t n, int64_t d, h
   p.tx = ensure<float2>(ws.tx, (size_t)p.n_pad);
   HIPCHK(launch_center<float>(X, n, d, d, p.mu, p.Xc, p.ldx, p.n_pad, p.nx, st));
   HIPCHK(launch_row_terms(p.nx, screen_const(p.ldx), nullptr, 0.0, p.n_pad, p.tx, st));
+  if (screen == ADAGIO_SCREEN_BF16X3) {
+    p.ldxb = round_up(d, kChunkBf16);
+    p.Xb = ensure<__bf16>(ws.Xb, (size_t)(p.n_pad * 2 * p.ldxb));
+    p.txb = ensure<float2>(ws.txb, (size_t)p.n_pad);
+    HIPCHK(launch_split_bf16(p.Xc, p.n_pad, d, p.ldx, p.ldxb, p.Xb, st));
+    HIPCHK(launch_row_terms(p.nx, screen_const_bf16(p.ldxb), nullptr, 0.0, p.n_pad, p.txb, st));
+  }
   return p;
 }
 
@@ -245,6 +264,9 @@ struct Images {
   int64_t r = 0, ldy = 0;
   float* Yc = nullptr;
   float2* ty = nullptr;
+  int64_t ldyb = 0;             // BF16 split (screen = BF16X3)
+  __bf16* Yb = nullptr;
+  float2* tyb = nullptr;
   const float* Y32 = nullptr;   // rescore source (given images) ...
   const double* Y64 = nullptr;  // ... or FP64 images of a map
 };
@@ -265,6 +287,13 @@ static Images images_of_map(Workspace& ws, const Points& p, const float* Pi, int
   const double dd = (double)p.d;
   const double c_emb = 4.02 * 2.1 * dd * (dd + 1.0) * kU64 * 1.01;
   HIPCHK(launch_row_terms(ny, screen_const(im.ldy), p.nx, c_emb, p.n_pad, im.ty, st));
+  if (p.screen == ADAGIO_SCREEN_BF16X3) {
+    im.ldyb = round_up(r, kChunkBf16);
+    im.Yb = ensure<__bf16>(ws.Yb, (size_t)(p.n_pad * 2 * im.ldyb));
+    im.tyb = ensure<float2>(ws.tyb, (size_t)p.n_pad);
+    HIPCHK(launch_split_bf16(im.Yc, p.n_pad, r, im.ldy, im.ldyb, im.Yb, st));
+    HIPCHK(launch_row_terms(ny, screen_const_bf16(im.ldyb), p.nx, c_emb, p.n_pad, im.tyb, st));
+  }
   im.Y64 = Y64;
   return im;
 }
@@ -281,6 +310,13 @@ static Images images_given(Workspace& ws, const Points& p, const float* Y, int64
   HIPCHK(launch_center<float>(Y, p.n, r, r, muY, im.Yc, im.ldy, p.n_pad, ny, st));
   im.ty = ensure<float2>(ws.ty, (size_t)p.n_pad);
   HIPCHK(launch_row_terms(ny, screen_const(im.ldy), nullptr, 0.0, p.n_pad, im.ty, st));
+  if (p.screen == ADAGIO_SCREEN_BF16X3) {
+    im.ldyb = round_up(r, kChunkBf16);
+    im.Yb = ensure<__bf16>(ws.Yb, (size_t)(p.n_pad * 2 * im.ldyb));
+    im.tyb = ensure<float2>(ws.tyb, (size_t)p.n_pad);
+    HIPCHK(launch_split_bf16(im.Yc, p.n_pad, r, im.ldy, im.ldyb, im.Yb, st));
+    HIPCHK(launch_row_terms(ny, screen_const_bf16(im.ldyb), nullptr, 0.0, p.n_pad, im.tyb, st));
+  }
   im.Y32 = Y;
   return im;
 }
@@ -349,7 +385,18 @@ static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& i
 
   EvPair e_screen, e_rest;
   e_screen.begin(st);
-  HIPCHK(launch_pairs_screen(v, recs, st));
+  if (p.screen == ADAGIO_SCREEN_BF16X3) {
+    // BF16 split screen; the emit pass below keeps the FP32 Gram (tighter
+    // bounds, fewer candidates, equally rigorous).
+    PairsViewB vb;
+    vb.Xb = p.Xb; vb.ldx = (int)p.ldxb;
+    vb.Yb = im.Yb; vb.ldy = (int)im.ldyb;
+    vb.tx = p.txb; vb.ty = im.tyb;
+    vb.n = v.n; vb.NT = v.NT; vb.ntiles = v.ntiles;
+    HIPCHK(launch_pairs_screen_bf16(vb, recs, st));
+  } else {
+    HIPCHK(launch_pairs_screen(v, recs, st));
+  }
   e_screen.end(st);
   e_rest.begin(st);
   HIPCHK(launch_seeds(recs, v.ntiles, tparts, nparts, seeds, cd, st));
@@ -509,11 +556,12 @@ int adagio_max_distortion(const float* X, int64_t n, int64_t d, const float* Y, 
     check_points(X, n, d);
     ARGCHK(Y && cert_out, "Y or cert_out is NULL");
     ARGCHK(r >= 1, "need r >= 1");
-    ARGCHK(!opts || opts->screen == ADAGIO_SCREEN_F32, "only the FP32 screen is available here");
+    const int screen = opts ? opts->screen : ADAGIO_SCREEN_F32;
+    ARGCHK(screen == ADAGIO_SCREEN_F32 || screen == ADAGIO_SCREEN_BF16X3, "unknown or unavailable screen precision");
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = as_stream(stream);
     Workspace& ws = workspace();
-    Points p = prep_points(ws, X, n, d, st);
+    Points p = prep_points(ws, X, n, d, st, screen);
     Images im = images_given(ws, p, Y, r, st);
     CertTimes tm;
     *cert_out = certificate(ws, p, im, opts ? (uint32_t)std::max(0, opts->max_candidates) : 0u, st, &tm);
@@ -529,11 +577,12 @@ int adagio_certify_map(const float* X, int64_t n, int64_t d, const float* Pi, in
     check_points(X, n, d);
     ARGCHK(Pi && cert_out, "Pi or cert_out is NULL");
     ARGCHK(r >= 1, "need r >= 1");
-    ARGCHK(!opts || opts->screen == ADAGIO_SCREEN_F32, "only the FP32 screen is available here");
+    const int screen = opts ? opts->screen : ADAGIO_SCREEN_F32;
+    ARGCHK(screen == ADAGIO_SCREEN_F32 || screen == ADAGIO_SCREEN_BF16X3, "unknown or unavailable screen precision");
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = as_stream(stream);
     Workspace& ws = workspace();
-    Points p = prep_points(ws, X, n, d, st);
+    Points p = prep_points(ws, X, n, d, st, screen);
     Images im = images_of_map(ws, p, Pi, r, st);
     CertTimes tm;
     *cert_out = certificate(ws, p, im, opts ? (uint32_t)std::max(0, opts->max_candidates) : 0u, st, &tm);
@@ -549,7 +598,8 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     check_points(X, n, d);
     ARGCHK(Pi_out && r_out && s_out && cert_out, "NULL output pointer");
     ARGCHK(eps > 0.0 && eps < 1.0, "eps must be in (0, 1)");
-    ARGCHK(!opts || opts->screen == ADAGIO_SCREEN_F32, "only the FP32 screen is available here");
+    const int screen = opts ? opts->screen : ADAGIO_SCREEN_F32;
+    ARGCHK(screen == ADAGIO_SCREEN_F32 || screen == ADAGIO_SCREEN_BF16X3, "unknown or unavailable screen precision");
     ARGCHK(!opts || opts->search == ADAGIO_SEARCH_BISECT, "only the bisection search is available here");
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = as_stream(stream);
@@ -557,7 +607,7 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     const uint32_t cap0 = opts ? (uint32_t)std::max(0, opts->max_candidates) : 0u;
     EvPair e_pca, e_search;
     e_pca.begin(st);
-    Points p = prep_points(ws, X, n, d, st);
+    Points p = prep_points(ws, X, n, d, st, screen);
     Axes ax = principal_axes(ws, p, st);
     e_pca.end(st);
     e_search.begin(st);
@@ -618,7 +668,7 @@ int adagio_release(void) {
     DevBuf* bufs[] = {&ws.mu, &ws.colpart, &ws.nonfinite, &ws.Xc, &ws.nx, &ws.tx, &ws.covpart, &ws.A0, &ws.A1,
                       &ws.W, &ws.trace, &ws.rot, &ws.lam, &ws.Vt, &ws.S, &ws.T, &ws.Pi, &ws.Pi64, &ws.Y64,
                       &ws.Yc, &ws.ny, &ws.ty, &ws.muY, &ws.recs, &ws.tparts, &ws.seeds, &ws.seedv, &ws.list,
-                      &ws.cand, &ws.vals, &ws.vparts, &ws.cd};
+                      &ws.cand, &ws.vals, &ws.vparts, &ws.cd, &ws.Xb, &ws.txb, &ws.Yb, &ws.tyb};
     for (DevBuf* b : bufs) {
       if (b->p) HIPCHK(hipFree(b->p));
       b->p = nullptr;

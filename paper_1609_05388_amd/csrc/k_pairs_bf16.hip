@@ -1,0 +1,232 @@
+// Step a10 (precision form): the all-pairs screen with BF16 split-precision
+// Grams.
+//
+// Every centred FP32 coordinate x is split as x = hi + lo + e with
+// hi = bf16(x), lo = bf16(x - hi) (x - hi is exact in FP32) and
+// |e| <= 2^-16 |x|.  A dot product is formed from three BF16 products,
+//   x.y ~= hi_x.hi_y + hi_x.lo_y + lo_x.hi_y,
+// on v_mfma_f32_32x32x16_bf16 with FP32 accumulation.  The dropped terms are
+// at most 3.01 * 2^-16 sum |x_k||y_k| and the FP32 accumulation of 3K
+// products at most gamma_3K * 1.012 sum |x_k||y_k|; the row terms carry these
+// in place of the FP32 Gram's gamma_K, so the epilogue's bounds stay rigorous
+// and the FP64 rescoring keeps the certificate exact.
+//
+// Operand layout in HBM: per row, per 32-column chunk, 32 hi values then 32
+// lo values (128 bytes), so one chunk of one row is one contiguous 128-byte
+// segment.  LDS rows are 144 bytes (128 + 16 padding: conflict-free
+// ds_read_b128 for 32 and 64 banks).  A 128 x 128 pair tile per workgroup of
+// four waves (64 x 64 each, 2 x 2 MFMA blocks), 32-column chunks double
+// buffered in LDS with the next chunk prefetched into registers.
+#include "common.h"
+#include "kernels.h"
+#include "pairs_common.h"
+
+namespace adg {
+
+constexpr int BK = 32;        // columns per chunk
+constexpr int BROW = 144;     // LDS bytes per row (64 hi + 64 lo bytes + 16 pad)
+
+// Split centred FP32 rows (n_pad x lds) into the chunk-interleaved BF16 hi/lo
+// layout (n_pad rows of ldb * 2 bf16, ldb = columns rounded up to 32).
+__global__ void k_split_bf16(const float* __restrict__ src, int64_t n_pad, int64_t m, int64_t lds,
+                             int64_t ldb, __bf16* __restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n_pad * ldb) return;
+  const int64_t row = e / ldb, col = e % ldb;
+  const float x = col < m ? src[row * lds + col] : 0.0f;
+  const __bf16 hi = (__bf16)x;
+  const __bf16 lo = (__bf16)(x - (float)hi);
+  const int64_t base = row * 2 * ldb + (col / BK) * (2 * BK) + (col % BK);
+  dst[base] = hi;
+  dst[base + BK] = lo;
+}
+
+struct PairsArgsB {
+  const __bf16* X; int ldx; int nchx;  // hi/lo points, row stride 2 * ldx bf16, ldx = 32 * nchx
+  const __bf16* Y; int ldy; int nchy;  // hi/lo images
+  PairsArgs p;                         // row terms, sizes, outputs (X/Y fields unused)
+};
+
+template <int MODE>
+__global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  unsigned char* As = lds_raw;                          // [2][128][BROW]
+  unsigned char* Bs = lds_raw + 2 * kTile * BROW;       // [2][128][BROW]
+  float4* termA = reinterpret_cast<float4*>(lds_raw + 4 * kTile * BROW);
+  float4* termB = termA + kTile;
+  float (*red_v)[4] = reinterpret_cast<float (*)[4]>(termB + kTile);
+  int (*red_i)[4] = reinterpret_cast<int (*)[4]>(reinterpret_cast<float*>(red_v) + 8);
+  int (*red_j)[4] = reinterpret_cast<int (*)[4]>(reinterpret_cast<int*>(red_i) + 8);
+  // Copy the argument struct into locals: a reference into the by-value kernel
+  // argument would make the compiler place a private copy in scratch memory.
+  const PairsArgs p = b.p;
+  const __bf16* const Xg = b.X;
+  const __bf16* const Yg = b.Y;
+  const int ldx = b.ldx, ldy = b.ldy, nchx = b.nchx, nchy = b.nchy;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int li = lane & 31, lh = lane >> 5;
+  const int total = nchx + nchy;
+
+  int I, J;
+  uint32_t u = blockIdx.x, u_end = 1;
+  float thr_hi = 0.f, thr_lo = 0.f;
+  if (MODE == 0) {
+    const uint32_t G = gridDim.x;
+    const int64_t slot = (int64_t)(blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+    if (slot >= p.nslots) return;
+    const TilePos tp = slot_tile(slot, p.NT, p.NS);
+    if (tp.I < 0) return;
+    I = (int)tp.I;
+    J = (int)tp.J;
+  } else {
+    u_end = p.cd->n_flagged;
+    thr_hi = p.cd->thr_hi;
+    thr_lo = p.cd->thr_lo;
+    if (u >= u_end) return;
+  }
+
+  for (;;) {
+    if (MODE == 1) {
+      const TilePos tp = tri_tile_p(p.list[u], p.NT);
+      I = (int)tp.I;
+      J = (int)tp.J;
+    }
+    const int row0 = I * kTile, col0 = J * kTile;
+    if (tid < kTile) {
+      const float2 a = p.tx[row0 + tid], c = p.ty[row0 + tid];
+      termA[tid] = make_float4(a.x, a.y, c.x, c.y);
+    } else {
+      const float2 a = p.tx[col0 + tid - kTile], c = p.ty[col0 + tid - kTile];
+      termB[tid - kTile] = make_float4(a.x, a.y, c.x, c.y);
+    }
+
+    f32x16 accX[2][2], accY[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        accX[x][y] = (f32x16){0};
+        accY[x][y] = (f32x16){0};
+      }
+
+    // staging: thread t loads 16-byte segment (t % 8) of rows t / 8 + 32 m
+    const int seg = tid & 7, lr = tid >> 3;
+    const size_t xstride = (size_t)2 * ldx, ystride = (size_t)2 * ldy;  // bf16 per row
+    const __bf16* xa = Xg + (size_t)(row0 + lr) * xstride + seg * 8;
+    const __bf16* xb = Xg + (size_t)(col0 + lr) * xstride + seg * 8;
+    const __bf16* ya = Yg + (size_t)(row0 + lr) * ystride + seg * 8;
+    const __bf16* yb = Yg + (size_t)(col0 + lr) * ystride + seg * 8;
+    u32x4 ga[4], gb[4];
+    auto fetch = [&](int c) __attribute__((always_inline)) {
+      if (c < nchx) {
+        const size_t off = (size_t)c * 2 * BK;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          ga[m] = *reinterpret_cast<const u32x4*>(xa + off + (size_t)32 * m * xstride);
+          gb[m] = *reinterpret_cast<const u32x4*>(xb + off + (size_t)32 * m * xstride);
+        }
+      } else {
+        const size_t off = (size_t)(c - nchx) * 2 * BK;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          ga[m] = *reinterpret_cast<const u32x4*>(ya + off + (size_t)32 * m * ystride);
+          gb[m] = *reinterpret_cast<const u32x4*>(yb + off + (size_t)32 * m * ystride);
+        }
+      }
+    };
+    auto stash = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        *reinterpret_cast<u32x4*>(As + (size_t)buf * kTile * BROW + (lr + 32 * m) * BROW + seg * 16) = ga[m];
+        *reinterpret_cast<u32x4*>(Bs + (size_t)buf * kTile * BROW + (lr + 32 * m) * BROW + seg * 16) = gb[m];
+      }
+    };
+    // k-step s of a chunk: lanes 0-31 take columns 16 s .. 16 s + 7, lanes
+    // 32-63 columns 16 s + 8 .. 16 s + 15 (8 bf16 = 16 bytes per lane).
+    auto mma = [&](f32x16 (&acc)[2][2], int buf) __attribute__((always_inline)) {
+      const unsigned char* A0 = As + (size_t)buf * kTile * BROW;
+      const unsigned char* B0 = Bs + (size_t)buf * kTile * BROW;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          const unsigned char* pa = A0 + (wr * 64 + x * 32 + li) * BROW + s * 32 + lh * 16;
+          const unsigned char* pb = B0 + (wc * 64 + x * 32 + li) * BROW + s * 32 + lh * 16;
+          ah[x] = *reinterpret_cast<const bf16x8*>(pa);
+          al[x] = *reinterpret_cast<const bf16x8*>(pa + 64);
+          bh[x] = *reinterpret_cast<const bf16x8*>(pb);
+          bl[x] = *reinterpret_cast<const bf16x8*>(pb + 64);
+        }
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[x], bh[y], acc[x][y], 0, 0, 0);
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[x], bl[y], acc[x][y], 0, 0, 0);
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[x], bh[y], acc[x][y], 0, 0, 0);
+      }
+    };
+
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int c = 0; c < nchx; ++c) {
+      const int buf = c & 1;
+      if (c + 1 < total) fetch(c + 1);
+      mma(accX, buf);
+      if (c + 1 < total) stash(buf ^ 1);
+      __syncthreads();
+    }
+    for (int c = nchx; c < total; ++c) {
+      const int buf = c & 1;
+      if (c + 1 < total) fetch(c + 1);
+      mma(accY, buf);
+      if (c + 1 < total) stash(buf ^ 1);
+      __syncthreads();
+    }
+
+    tile_epilogue<MODE>(accX, accY, termA, termB, I, J, p, thr_hi, thr_lo, red_v, red_i, red_j);
+    if (MODE == 0) return;
+    u += gridDim.x;
+    if (u >= u_end) return;
+    __syncthreads();
+  }
+}
+
+constexpr size_t kLdsBf16 = 4 * kTile * BROW + 2 * kTile * sizeof(float4) + 3 * 8 * sizeof(float);
+
+hipError_t launch_split_bf16(const float* src, int64_t n_pad, int64_t m, int64_t lds, int64_t ldb, __bf16* dst,
+                             hipStream_t st) {
+  k_split_bf16<<<(unsigned)((n_pad * ldb + 255) / 256), 256, 0, st>>>(src, n_pad, m, lds, ldb, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_pairs_screen_bf16(const PairsViewB& v, TileRec* recs, hipStream_t st) {
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pairs_bf16x3<0>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBf16);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const int NS = (v.NT + 7) / 8;
+  const int64_t nslots = (int64_t)NS * (NS + 1) / 2 * 64;
+  PairsArgsB a;
+  a.X = v.Xb; a.ldx = v.ldx; a.nchx = v.ldx / BK;
+  a.Y = v.Yb; a.ldy = v.ldy; a.nchy = v.ldy / BK;
+  a.p = PairsArgs{nullptr, 0, 0, nullptr, 0, 0, v.tx, v.ty, v.n, v.NT, v.ntiles, NS, nslots, recs,
+                  nullptr, nullptr, nullptr, 0u, nullptr};
+  const int64_t G = round_up(nslots, 8);
+  k_pairs_bf16x3<0><<<(unsigned)G, 256, kLdsBf16, st>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace adg

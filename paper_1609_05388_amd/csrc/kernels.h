@@ -49,6 +49,17 @@ hipError_t launch_pairs_screen(const PairsView& v, TileRec* recs, hipStream_t st
 hipError_t launch_pairs_emit(const PairsView& v, const uint32_t* list, const CertDev* cd, int2* cand, uint32_t cap,
                              uint32_t* ncand, int grid, hipStream_t st);
 
+// k_pairs_bf16.hip
+struct PairsViewB {
+  const __bf16* Xb; int ldx;    // hi/lo split points (n_pad rows of 2 * ldx bf16)
+  const __bf16* Yb; int ldy;    // hi/lo split images
+  const float2* tx; const float2* ty;
+  int n; int NT; int64_t ntiles;
+};
+hipError_t launch_split_bf16(const float* src, int64_t n_pad, int64_t m, int64_t lds, int64_t ldb, __bf16* dst,
+                             hipStream_t st);
+hipError_t launch_pairs_screen_bf16(const PairsViewB& v, TileRec* recs, hipStream_t st);
+
 // k_cert.hip
 hipError_t launch_seeds(const TileRec* recs, int64_t ntiles, TileRec* part, int nparts, int2* seeds, CertDev* cd,
                         hipStream_t st);
