@@ -55,7 +55,7 @@ struct Workspace {
   DevBuf mu, colpart, nonfinite, Xc, nx, tx, covpart, A0, A1, W, trace, rot, lam, Vt;
   DevBuf S, T, Pi, Pi64, Y64, Yc, ny, ty, muY;
   DevBuf recs, tparts, seeds, seedv, list, cand, vals, vparts, cd;
-  DevBuf Xb, txb, Yb, tyb;
+  DevBuf Xb, txb, Yb, tyb, bjU, bjS;
   bool checked = false;
 };
 
@@ -193,7 +193,10 @@ struct Axes {
 static Axes principal_axes(Workspace& ws, const Points& p, hipStream_t st, double* lam_out = nullptr,
                            double* Vt_out = nullptr) {
   const int64_t d = p.d;
-  const int m = (int)(d + (d & 1));
+  // block Jacobi works on m = d rounded up to a multiple of two index blocks
+  const int JB = bj_block();
+  const int m = (int)round_up(d, 2 * JB);
+  const int nb = m / JB;
   // covariance with split-K over points so that the grid fills the GPU
   const int64_t NT = (d + 63) / 64;
   const int64_t ntiles = NT * (NT + 1) / 2;
@@ -205,6 +208,8 @@ static Axes principal_axes(Workspace& ws, const Points& p, hipStream_t st, doubl
   double* A = ensure<double>(ws.A0, (size_t)m * m);
   double* B = ensure<double>(ws.A1, (size_t)m * m);
   double* W = ensure<double>(ws.W, (size_t)m * m);
+  double* Ub = ensure<double>(ws.bjU, (size_t)(nb / 2) * 4 * JB * JB);
+  double* Sb = ensure<double>(ws.bjS, (size_t)(nb / 2) * 4 * JB * JB);
   HIPCHK(launch_covariance(p.X, p.n, d, p.mu, part, nsplit, A, m, st));
   HIPCHK(launch_eye(W, m, st));
   double* tr = ensure<double>(ws.trace, 1);
@@ -212,18 +217,21 @@ static Axes principal_axes(Workspace& ws, const Points& p, hipStream_t st, doubl
   double trace = 0.0;
   HIPCHK(hipMemcpyAsync(&trace, tr, sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  // Rotations whose off-diagonal entry is below u64 * trace / m are skipped;
-  // the method has converged when a whole sweep skips every rotation.
-  const double thr = kU64 * trace / (double)m;
+  // Rotations whose off-diagonal entry is at most 4 u64 trace(C) are skipped
+  // (trace >= ||C||_F for PSD C; this sits above the rounding floor of the
+  // tile products); the method has converged when a whole sweep skips every
+  // rotation.  One inner sweep per block pair and round: the number of outer
+  // sweeps does not depend on solving the subproblems to convergence.
+  const double thr = 4.0 * kU64 * trace;
   int* rot = ensure<int>(ws.rot, 1);
   Axes ax;
-  const int max_sweeps = 60;
+  const int max_sweeps = 40, max_inner = 1;
   int sweep = 0;
-  bool converged = (m < 2);
+  bool converged = false;
   for (; sweep < max_sweeps && !converged; ++sweep) {
     HIPCHK(hipMemsetAsync(rot, 0, sizeof(int), st));
-    for (int t = 0; t < m - 1; ++t) {
-      HIPCHK(launch_jacobi_round(A, B, W, m, t, thr, rot, st));
+    for (int t = 0; t < nb - 1; ++t) {
+      HIPCHK(launch_bj_round(A, B, W, Ub, Sb, m, t, thr, max_inner, rot, st));
       std::swap(A, B);
     }
     int h = 0;
@@ -668,7 +676,7 @@ int adagio_release(void) {
     DevBuf* bufs[] = {&ws.mu, &ws.colpart, &ws.nonfinite, &ws.Xc, &ws.nx, &ws.tx, &ws.covpart, &ws.A0, &ws.A1,
                       &ws.W, &ws.trace, &ws.rot, &ws.lam, &ws.Vt, &ws.S, &ws.T, &ws.Pi, &ws.Pi64, &ws.Y64,
                       &ws.Yc, &ws.ny, &ws.ty, &ws.muY, &ws.recs, &ws.tparts, &ws.seeds, &ws.seedv, &ws.list,
-                      &ws.cand, &ws.vals, &ws.vparts, &ws.cd, &ws.Xb, &ws.txb, &ws.Yb, &ws.tyb};
+                      &ws.cand, &ws.vals, &ws.vparts, &ws.cd, &ws.Xb, &ws.txb, &ws.Yb, &ws.tyb, &ws.bjU, &ws.bjS};
     for (DevBuf* b : bufs) {
       if (b->p) HIPCHK(hipFree(b->p));
       b->p = nullptr;

@@ -29,10 +29,13 @@ hipError_t launch_proj_SQ(const double* S, const double* T, int64_t k, int64_t s
 // k_eig.hip
 hipError_t launch_eye(double* W, int m, hipStream_t st);
 hipError_t launch_trace(const double* A, int m, double* out, hipStream_t st);
-hipError_t launch_jacobi_round(const double* A, double* A2, double* W, int m, int t, double thr, int* rot_count,
-                               hipStream_t st);
 hipError_t launch_eig_sort(const double* A, const double* W, int m, int d, double* lam, double* Vt,
                            hipStream_t st);
+
+// k_eig_block.hip
+hipError_t launch_bj_round(const double* A, double* A2, double* W, double* Uall, double* Sall, int m, int t,
+                           double thr, int max_inner, int* rot_count, hipStream_t st);
+int bj_block();
 
 // k_proj.hip
 hipError_t launch_jl_signs(uint64_t seed, int64_t k, int64_t d, double* S, hipStream_t st);
