@@ -154,6 +154,41 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed,
                const adagio_opts_t* opts, float* Pi_out, int32_t* r_out, int32_t* s_out,
                adagio_cert_t* cert_out, void* stream);
 
+/* a11.  Learned form (a method extension, not in the paper): the 80 input
+ * features of the target-dimension predictor for cloud X and target eps.
+ * G = Omega Xc is a JL sketch of the centred cloud with kSketchRows = 128 rows
+ * of +-1/sqrt(128) signs (SplitMix64, seed ^ 0xD1B54A32D192ED03, counter
+ * a * 2^32 + i + 1 for row a and point i); its eigenvalues lam_i = sigma_i^2
+ * (decreasing) give f[i] = ln(sigma_i / ||sigma|| + 1e-6) / 4 for i < 64,
+ * f[64] = ln(n) / 10, f[65] = ln(d) / 10, f[66] = 5 eps, f[67..79] = 0.
+ * feat_out: device, 80 floats.  Synchronises `stream`. */
+int adagio_sketch_features(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, float* feat_out,
+                           void* stream);
+
+/* a11-a12.  Number of FP32 parameters of the predictor MLP: 67 inputs (padded
+ * to 80) -> 256 -> 256 -> 256 (ReLU) -> 1, laid out as W1[256][80], b1[256],
+ * W2[256][256], b2[256], W3[256][256], b3[256], w4[256], b4, 3 padding floats.
+ * The output is the predicted ln(r / d). */
+int64_t adagio_mlp_param_count(void);
+
+/* a11.  Forward pass for B feature rows (device, B x 80 FP32) with FP32 master
+ * parameters (device); products on BF16 MFMA with FP32 accumulation.  out:
+ * device, B floats.  Asynchronous. */
+int adagio_mlp_forward(const float* params, const float* feats, int32_t B, float* out, void* stream);
+
+/* a12.  Pinball loss at level tau (0 < tau < 1) of targets - outputs, mean over
+ * the batch, and its gradient w.r.t. all parameters (device, same layout as
+ * params).  loss: device, 1 float.  Asynchronous. */
+int adagio_mlp_grad(const float* params, const float* feats, const float* targets, int32_t B, float tau,
+                    float* grad, float* loss, void* stream);
+
+/* a12.  One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias corrected) on the
+ * FP32 master params with the gradient of adagio_mlp_grad; adam_m, adam_v are
+ * device state of the same layout (zero before step 1); step is 1-based.
+ * loss: device, 1 float (loss before the step).  Asynchronous. */
+int adagio_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t step, float lr, const float* feats,
+                          const float* targets, int32_t B, float tau, float* loss, void* stream);
+
 /* Frees the cached device workspace of the current device. */
 int adagio_release(void);
 

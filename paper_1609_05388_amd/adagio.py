@@ -76,6 +76,12 @@ SIGNATURES = {
     "adagio_fit": (ctypes.c_int, [_P, _I64, _I64, _D, _U64, ctypes.POINTER(Opts), _P,
                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(Cert), _P]),
+    "adagio_sketch_features": (ctypes.c_int, [_P, _I64, _I64, _D, _U64, _P, _P]),
+    "adagio_mlp_param_count": (ctypes.c_int64, []),
+    "adagio_mlp_forward": (ctypes.c_int, [_P, _P, _I32, _P, _P]),
+    "adagio_mlp_grad": (ctypes.c_int, [_P, _P, _P, _I32, ctypes.c_float, _P, _P, _P]),
+    "adagio_mlp_train_step": (ctypes.c_int, [_P, _P, _P, _I32, ctypes.c_float, _P, _P, _I32, ctypes.c_float,
+                                             _P, _P]),
     "adagio_release": (ctypes.c_int, []),
     "adagio_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "adagio_last_error": (ctypes.c_char_p, []),
@@ -217,6 +223,55 @@ def fit(X, eps, seed, screen="f32", search="bisect", predictor=None, max_candida
     rv = r.value
     return {"Pi": Pi_buf[:rv], "r": rv, "s": s.value, "k": rv - s.value if rv < d else 0,
             "cert": c.to_dict(), "stats": st.to_dict()}
+
+
+N_FEATURES = 80
+
+
+def sketch_features(X, eps, seed):
+    """80 predictor inputs (device FP32) of cloud X at target eps."""
+    lib = load()
+    n, d = X.shape
+    f = torch.empty(N_FEATURES, dtype=torch.float32, device=X.device)
+    _check(lib.adagio_sketch_features(_dev(X, torch.float32, "X"), n, d, float(eps), int(seed),
+                                      _dev(f, torch.float32, "feat"), _stream()))
+    return f
+
+
+def mlp_param_count():
+    return int(load().adagio_mlp_param_count())
+
+
+def mlp_forward(params, feats):
+    lib = load()
+    B = feats.shape[0]
+    out = torch.empty(B, dtype=torch.float32, device=feats.device)
+    _check(lib.adagio_mlp_forward(_dev(params, torch.float32, "params"), _dev(feats, torch.float32, "feats"), B,
+                                  _dev(out, torch.float32, "out"), _stream()))
+    return out
+
+
+def mlp_grad(params, feats, targets, tau):
+    lib = load()
+    B = feats.shape[0]
+    grad = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float32, device=params.device)
+    _check(lib.adagio_mlp_grad(_dev(params, torch.float32, "params"), _dev(feats, torch.float32, "feats"),
+                               _dev(targets, torch.float32, "targets"), B, float(tau),
+                               _dev(grad, torch.float32, "grad"), _dev(loss, torch.float32, "loss"), _stream()))
+    return grad, loss
+
+
+def mlp_train_step(params, adam_m, adam_v, step, lr, feats, targets, tau):
+    """One Adam step in place on params/adam_m/adam_v; returns the device loss."""
+    lib = load()
+    B = feats.shape[0]
+    loss = torch.empty(1, dtype=torch.float32, device=params.device)
+    _check(lib.adagio_mlp_train_step(_dev(params, torch.float32, "params"), _dev(adam_m, torch.float32, "m"),
+                                     _dev(adam_v, torch.float32, "v"), int(step), float(lr),
+                                     _dev(feats, torch.float32, "feats"), _dev(targets, torch.float32, "targets"),
+                                     B, float(tau), _dev(loss, torch.float32, "loss"), _stream()))
+    return loss
 
 
 def release():

@@ -56,6 +56,7 @@ struct Workspace {
   DevBuf S, T, Pi, Pi64, Y64, Yc, ny, ty, muY;
   DevBuf recs, tparts, seeds, seedv, list, cand, vals, vparts, cd;
   DevBuf Xb, txb, Yb, tyb, bjU, bjS;
+  DevBuf skpart, skG, skK, sklam, skV, skfeat, mlp_pb, mlp_X, mlp_f, mlp_hb, mlp_grad, mlp_loss;
   bool checked = false;
 };
 
@@ -190,41 +191,29 @@ struct Axes {
   int sweeps = 0;
 };
 
-static Axes principal_axes(Workspace& ws, const Points& p, hipStream_t st, double* lam_out = nullptr,
-                           double* Vt_out = nullptr) {
-  const int64_t d = p.d;
-  // block Jacobi works on m = d rounded up to a multiple of two index blocks
+// Eigenpairs of the symmetric m x m FP64 matrix in A (m a multiple of two
+// Jacobi blocks, zero outside the leading d x d); A is overwritten.  Writes
+// lam (d, decreasing) and Vt (d x d, rows = eigenvectors); returns sweeps.
+static int jacobi_eig(Workspace& ws, double* A, int m, int64_t d, double* lam, double* Vt, hipStream_t st) {
   const int JB = bj_block();
-  const int m = (int)round_up(d, 2 * JB);
   const int nb = m / JB;
-  // covariance with split-K over points so that the grid fills the GPU
-  const int64_t NT = (d + 63) / 64;
-  const int64_t ntiles = NT * (NT + 1) / 2;
-  int nsplit = (int)((2048 + ntiles - 1) / ntiles);
-  const int64_t max_split = (p.n + 255) / 256;
-  if (nsplit > max_split) nsplit = (int)max_split;
-  if (nsplit < 1) nsplit = 1;
-  double* part = ensure<double>(ws.covpart, (size_t)(nsplit * d * d));
-  double* A = ensure<double>(ws.A0, (size_t)m * m);
   double* B = ensure<double>(ws.A1, (size_t)m * m);
   double* W = ensure<double>(ws.W, (size_t)m * m);
   double* Ub = ensure<double>(ws.bjU, (size_t)(nb / 2) * 4 * JB * JB);
   double* Sb = ensure<double>(ws.bjS, (size_t)(nb / 2) * 4 * JB * JB);
-  HIPCHK(launch_covariance(p.X, p.n, d, p.mu, part, nsplit, A, m, st));
   HIPCHK(launch_eye(W, m, st));
   double* tr = ensure<double>(ws.trace, 1);
   HIPCHK(launch_trace(A, m, tr, st));
   double trace = 0.0;
   HIPCHK(hipMemcpyAsync(&trace, tr, sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  // Rotations whose off-diagonal entry is at most 4 u64 trace(C) are skipped
-  // (trace >= ||C||_F for PSD C; this sits above the rounding floor of the
+  // Rotations whose off-diagonal entry is at most 4 u64 trace(A) are skipped
+  // (trace >= ||A||_F for PSD A; this sits above the rounding floor of the
   // tile products); the method has converged when a whole sweep skips every
   // rotation.  One inner sweep per block pair and round: the number of outer
   // sweeps does not depend on solving the subproblems to convergence.
   const double thr = 4.0 * kU64 * trace;
   int* rot = ensure<int>(ws.rot, 1);
-  Axes ax;
   const int max_sweeps = 40, max_inner = 1;
   int sweep = 0;
   bool converged = false;
@@ -243,11 +232,93 @@ static Axes principal_axes(Workspace& ws, const Points& p, hipStream_t st, doubl
     set_err("Jacobi eigensolver did not converge in %s%lld sweeps", "", max_sweeps);
     throw Fail{ADAGIO_E_NO_CONVERGENCE};
   }
-  ax.sweeps = sweep;
+  HIPCHK(launch_eig_sort(A, W, m, (int)d, lam, Vt, st));
+  return sweep;
+}
+
+static Axes principal_axes(Workspace& ws, const Points& p, hipStream_t st, double* lam_out = nullptr,
+                           double* Vt_out = nullptr) {
+  const int64_t d = p.d;
+  // block Jacobi works on m = d rounded up to a multiple of two index blocks
+  const int m = (int)round_up(d, 2 * bj_block());
+  // covariance with split-K over points so that the grid fills the GPU
+  const int64_t NT = (d + 63) / 64;
+  const int64_t ntiles = NT * (NT + 1) / 2;
+  int nsplit = (int)((2048 + ntiles - 1) / ntiles);
+  const int64_t max_split = (p.n + 255) / 256;
+  if (nsplit > max_split) nsplit = (int)max_split;
+  if (nsplit < 1) nsplit = 1;
+  double* part = ensure<double>(ws.covpart, (size_t)(nsplit * d * d));
+  double* A = ensure<double>(ws.A0, (size_t)m * m);
+  HIPCHK(launch_covariance(p.X, p.n, d, p.mu, part, nsplit, A, m, st));
+  Axes ax;
   ax.lam = lam_out ? lam_out : ensure<double>(ws.lam, (size_t)d);
   ax.Vt = Vt_out ? Vt_out : ensure<double>(ws.Vt, (size_t)(d * d));
-  HIPCHK(launch_eig_sort(A, W, m, (int)d, ax.lam, ax.Vt, st));
+  ax.sweeps = jacobi_eig(ws, A, m, d, ax.lam, ax.Vt, st);
   return ax;
+}
+
+// ------------------------------------------------------------ learned form
+static const int kSketchRows = 128;
+static const uint64_t kSketchStream = 0xD1B54A32D192ED03ull;
+
+// Features of the learned search (80 floats, device): spectrum of the JL
+// sketch G = Omega Xc (kSketchRows x d, Omega = +-1/sqrt(m) signs from the
+// sketch stream of `seed`), log n, log d, eps.
+static void sketch_features(Workspace& ws, const Points& p, double eps, uint64_t seed, float* feat, hipStream_t st) {
+  const int m = kSketchRows;
+  int nsplit = (int)std::min<int64_t>(64, (p.n + 1023) / 1024);
+  if (nsplit < 1) nsplit = 1;
+  double* part = ensure<double>(ws.skpart, (size_t)nsplit * m * p.d);
+  double* G = ensure<double>(ws.skG, (size_t)m * p.d);
+  HIPCHK(launch_sketch(p.X, p.n, p.d, p.mu, m, seed ^ kSketchStream, part, nsplit, G, st));
+  const int mp = (int)round_up(m, 2 * bj_block());
+  double* K = ensure<double>(ws.skK, (size_t)mp * mp);
+  HIPCHK(launch_gram_rows(G, m, p.d, K, mp, st));
+  // The m x m eigenproblem reuses the Jacobi buffers (A0 is not needed here).
+  double* lam = ensure<double>(ws.sklam, (size_t)m);
+  double* V = ensure<double>(ws.skV, (size_t)m * m);
+  jacobi_eig(ws, K, mp, m, lam, V, st);
+  HIPCHK(launch_sketch_features(lam, m, p.n, p.d, eps, feat, st));
+}
+
+struct MlpBufs {
+  __bf16* pb;
+  __bf16* X;
+  MlpActs a;
+  float* out;
+};
+
+static MlpBufs mlp_bufs(Workspace& ws, const MlpLayout& L, int B) {
+  MlpBufs b;
+  b.pb = ensure<__bf16>(ws.mlp_pb, (size_t)L.total);
+  b.X = ensure<__bf16>(ws.mlp_X, (size_t)B * L.in_pad);
+  const size_t BH = (size_t)B * L.hidden;
+  float* f = ensure<float>(ws.mlp_f, 5 * BH + 2 * (size_t)B);
+  b.a.A1 = f;
+  b.a.A2 = f + BH;
+  b.a.A3 = f + 2 * BH;
+  b.a.dZ = f + 3 * BH;
+  b.a.dZ2 = f + 4 * BH;
+  b.a.g = f + 5 * BH;
+  b.out = f + 5 * BH + B;
+  __bf16* hb = ensure<__bf16>(ws.mlp_hb, 2 * BH);
+  b.a.A1b = hb;
+  b.a.A2b = hb + BH;
+  return b;
+}
+
+// Predicted log(r / d) for one feature row (host float).
+static float mlp_predict(Workspace& ws, const float* params, const float* feat, hipStream_t st) {
+  const MlpLayout L = mlp_layout();
+  MlpBufs b = mlp_bufs(ws, L, 1);
+  HIPCHK(mlp_to_bf16(params, b.pb, L.total, st));
+  HIPCHK(mlp_to_bf16(feat, b.X, L.in_pad, st));
+  HIPCHK(mlp_forward(L, params, b.pb, b.X, 1, b.a, b.out, st));
+  float h = 0.0f;
+  HIPCHK(hipMemcpyAsync(&h, b.out, sizeof(float), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return h;
 }
 
 // ------------------------------------------------------------------ map
@@ -414,7 +485,15 @@ static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& i
 
   uint32_t cap = cap0 ? cap0 : kDefaultCap;
   CertDev h;
-  for (;;) {
+  // When the bounds cannot separate pairs (a near-isometry: every pair's
+  // bound reaches the best exact value), the flagged tiles can hold more
+  // candidates than the hard cap and the exact pass would only overflow;
+  // report the proven bound instead.
+  HIPCHK(hipMemcpyAsync(&h, cd, sizeof(CertDev), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const bool skip_exact = (int64_t)h.n_flagged * kTile * kTile > (int64_t)kHardCap;
+  if (skip_exact) h.n_cand = 0xffffffffu;
+  for (; !skip_exact;) {
     int2* cand = ensure<int2>(ws.cand, cap);
     PairVal* vals = ensure<PairVal>(ws.vals, cap);
     HIPCHK(hipMemsetAsync(&cd->n_cand, 0, sizeof(uint32_t), st));
@@ -438,8 +517,8 @@ static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& i
   memset(&c, 0, sizeof(c));
   c.n_pairs = p.n * (p.n - 1) / 2;
   c.n_flagged_tiles = h.n_flagged;
-  c.n_rescored = (int64_t)h.n_seed + (int64_t)std::min<uint32_t>(h.n_cand, cap);
-  const bool complete = h.n_cand <= cap;
+  c.n_rescored = (int64_t)h.n_seed + (skip_exact ? 0 : (int64_t)std::min<uint32_t>(h.n_cand, cap));
+  const bool complete = !skip_exact && h.n_cand <= cap;
   if (h.best.i >= 0) {
     c.max_distortion = h.best.v;
     c.i = h.best.i;
@@ -608,7 +687,9 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     ARGCHK(eps > 0.0 && eps < 1.0, "eps must be in (0, 1)");
     const int screen = opts ? opts->screen : ADAGIO_SCREEN_F32;
     ARGCHK(screen == ADAGIO_SCREEN_F32 || screen == ADAGIO_SCREEN_BF16X3, "unknown or unavailable screen precision");
-    ARGCHK(!opts || opts->search == ADAGIO_SEARCH_BISECT, "only the bisection search is available here");
+    const int search = opts ? opts->search : ADAGIO_SEARCH_BISECT;
+    ARGCHK(search == ADAGIO_SEARCH_BISECT || search == ADAGIO_SEARCH_LEARNED, "unknown search");
+    ARGCHK(search != ADAGIO_SEARCH_LEARNED || opts->predictor, "learned search needs opts->predictor");
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = as_stream(stream);
     Workspace& ws = workspace();
@@ -622,27 +703,48 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     float* Pi = ensure<float>(ws.Pi, (size_t)(d * d));
     CertTimes tm;
     int ncert = 0;
-    // Bisection over r: lo = 0 (empty map, distortion 1), hi = d (isometry).
     int64_t lo = 0, hi = d;
     bool have_hi = false;
     adagio_cert_t cert_hi;
     memset(&cert_hi, 0, sizeof(cert_hi));
-    while (hi - lo > 1) {
-      const int64_t mid = (lo + hi) / 2;
-      build_map(ws, ax.Vt, d, mid, seed, Pi, st);
-      Images im = images_of_map(ws, p, Pi, mid, st);
+    // One probe: certify the map at r; on a pass keep it as the current answer.
+    // Pass when the exact maximum is <= eps, or (incomplete certificate) when
+    // the proven bound over all pairs is <= eps.
+    auto probe = [&](int64_t r) {
+      build_map(ws, ax.Vt, d, r, seed, Pi, st);
+      Images im = images_of_map(ws, p, Pi, r, st);
       adagio_cert_t c = certificate(ws, p, im, cap0, st, &tm);
       ++ncert;
-      // Pass when the exact maximum is <= eps, or (incomplete certificate)
-      // when the proven bound over all pairs is <= eps.
       const bool pass = c.certified ? c.max_distortion <= eps : c.bound_rest <= eps;
       if (pass) {
-        hi = mid;
         have_hi = true;
         cert_hi = c;
-        HIPCHK(hipMemcpyAsync(Pi_out, Pi, sizeof(float) * mid * d, hipMemcpyDeviceToDevice, st));
-      } else {
-        lo = mid;
+        HIPCHK(hipMemcpyAsync(Pi_out, Pi, sizeof(float) * r * d, hipMemcpyDeviceToDevice, st));
+      }
+      return pass;
+    };
+    int32_t r_pred = 0, fallback = 0;
+    if (search == ADAGIO_SEARCH_LEARNED) {
+      // The network's r is certified like any probe; if it fails, bisection
+      // continues on (r_pred, d].
+      float* feat = ensure<float>(ws.skfeat, 80);
+      sketch_features(ws, p, eps, seed, feat, st);
+      const double y = (double)mlp_predict(ws, opts->predictor, feat, st);
+      int64_t rp = (int64_t)std::ceil((double)d * std::exp(std::min(y, 0.0)));
+      if (rp < 1) rp = 1;
+      if (rp > d) rp = d;
+      r_pred = (int32_t)rp;
+      if (rp < d) {
+        if (probe(rp)) hi = rp;
+        else { lo = rp; fallback = 1; }
+      }
+    }
+    // Bisection over r: lo = 0 (empty map, distortion 1), hi = d (isometry).
+    if (search == ADAGIO_SEARCH_BISECT || fallback) {
+      while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) / 2;
+        if (probe(mid)) hi = mid;
+        else lo = mid;
       }
     }
     if (!have_hi) {  // hi == d: the full eigenbasis
@@ -663,7 +765,78 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
       s->t_pca_ms = e_pca.ms();
       s->t_search_ms = e_search.ms();
       s->eig_sweeps = ax.sweeps;
+      s->r_predicted = r_pred;
+      s->n_fallback = fallback;
     }
+  });
+}
+
+int adagio_sketch_features(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, float* feat_out,
+                           void* stream) {
+  return guarded([&] {
+    check_points(X, n, d);
+    ARGCHK(feat_out, "feat_out is NULL");
+    ARGCHK(eps > 0.0 && eps < 1.0, "eps must be in (0, 1)");
+    hipStream_t st = as_stream(stream);
+    Workspace& ws = workspace();
+    Points p = prep_points(ws, X, n, d, st);
+    sketch_features(ws, p, eps, seed, feat_out, st);
+    HIPCHK(hipStreamSynchronize(st));
+  });
+}
+
+int64_t adagio_mlp_param_count(void) { return mlp_layout().total; }
+
+int adagio_mlp_forward(const float* params, const float* feats, int32_t B, float* out, void* stream) {
+  return guarded([&] {
+    ARGCHK(params && feats && out, "NULL pointer");
+    ARGCHK(B >= 1 && B <= (1 << 20), "batch must be in [1, 2^20]");
+    hipStream_t st = as_stream(stream);
+    Workspace& ws = workspace();
+    const MlpLayout L = mlp_layout();
+    MlpBufs b = mlp_bufs(ws, L, B);
+    HIPCHK(mlp_to_bf16(params, b.pb, L.total, st));
+    HIPCHK(mlp_to_bf16(feats, b.X, (int64_t)B * L.in_pad, st));
+    HIPCHK(mlp_forward(L, params, b.pb, b.X, B, b.a, out, st));
+  });
+}
+
+int adagio_mlp_grad(const float* params, const float* feats, const float* targets, int32_t B, float tau, float* grad,
+                    float* loss, void* stream) {
+  return guarded([&] {
+    ARGCHK(params && feats && targets && grad && loss, "NULL pointer");
+    ARGCHK(B >= 1 && B <= (1 << 20), "batch must be in [1, 2^20]");
+    ARGCHK(tau > 0.0f && tau < 1.0f, "tau must be in (0, 1)");
+    hipStream_t st = as_stream(stream);
+    Workspace& ws = workspace();
+    const MlpLayout L = mlp_layout();
+    MlpBufs b = mlp_bufs(ws, L, B);
+    HIPCHK(mlp_to_bf16(params, b.pb, L.total, st));
+    HIPCHK(mlp_to_bf16(feats, b.X, (int64_t)B * L.in_pad, st));
+    HIPCHK(hipMemsetAsync(grad, 0, sizeof(float) * L.total, st));
+    HIPCHK(mlp_forward(L, params, b.pb, b.X, B, b.a, b.out, st));
+    HIPCHK(mlp_backward(L, b.pb, b.X, targets, B, tau, b.a, b.out, grad, loss, st));
+  });
+}
+
+int adagio_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t step, float lr, const float* feats,
+                          const float* targets, int32_t B, float tau, float* loss, void* stream) {
+  return guarded([&] {
+    ARGCHK(params && adam_m && adam_v && feats && targets && loss, "NULL pointer");
+    ARGCHK(B >= 1 && B <= (1 << 20), "batch must be in [1, 2^20]");
+    ARGCHK(step >= 1, "step is 1-based");
+    ARGCHK(tau > 0.0f && tau < 1.0f, "tau must be in (0, 1)");
+    hipStream_t st = as_stream(stream);
+    Workspace& ws = workspace();
+    const MlpLayout L = mlp_layout();
+    MlpBufs b = mlp_bufs(ws, L, B);
+    float* grad = ensure<float>(ws.mlp_grad, (size_t)L.total);
+    HIPCHK(mlp_to_bf16(params, b.pb, L.total, st));
+    HIPCHK(mlp_to_bf16(feats, b.X, (int64_t)B * L.in_pad, st));
+    HIPCHK(hipMemsetAsync(grad, 0, sizeof(float) * L.total, st));
+    HIPCHK(mlp_forward(L, params, b.pb, b.X, B, b.a, b.out, st));
+    HIPCHK(mlp_backward(L, b.pb, b.X, targets, B, tau, b.a, b.out, grad, loss, st));
+    HIPCHK(mlp_adam(params, b.pb, grad, adam_m, adam_v, L.total, lr, step, st));
   });
 }
 
@@ -676,7 +849,9 @@ int adagio_release(void) {
     DevBuf* bufs[] = {&ws.mu, &ws.colpart, &ws.nonfinite, &ws.Xc, &ws.nx, &ws.tx, &ws.covpart, &ws.A0, &ws.A1,
                       &ws.W, &ws.trace, &ws.rot, &ws.lam, &ws.Vt, &ws.S, &ws.T, &ws.Pi, &ws.Pi64, &ws.Y64,
                       &ws.Yc, &ws.ny, &ws.ty, &ws.muY, &ws.recs, &ws.tparts, &ws.seeds, &ws.seedv, &ws.list,
-                      &ws.cand, &ws.vals, &ws.vparts, &ws.cd, &ws.Xb, &ws.txb, &ws.Yb, &ws.tyb, &ws.bjU, &ws.bjS};
+                      &ws.cand, &ws.vals, &ws.vparts, &ws.cd, &ws.Xb, &ws.txb, &ws.Yb, &ws.tyb, &ws.bjU, &ws.bjS,
+                      &ws.skpart, &ws.skG, &ws.skK, &ws.sklam, &ws.skV, &ws.skfeat, &ws.mlp_pb, &ws.mlp_X,
+                      &ws.mlp_f, &ws.mlp_hb, &ws.mlp_grad, &ws.mlp_loss};
     for (DevBuf* b : bufs) {
       if (b->p) HIPCHK(hipFree(b->p));
       b->p = nullptr;

@@ -61,6 +61,18 @@ struct RowsF64N {         // B(k, n) = M[k][n]
   }
 };
 
+struct SketchSigns {       // A(a, i) = +-1/sqrt(m): top bit of SplitMix64 output (a << 32 | i) + 1
+  uint64_t seed; int64_t m, n; double scale;
+  __device__ double operator()(int64_t a, int64_t i) const {
+    if (a >= m || i >= n) return 0.0;
+    uint64_t z = seed + ((((uint64_t)a << 32) | (uint64_t)i) + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (z >> 63) ? -scale : scale;
+  }
+};
+
 // ------------------------------------------------------------------ outputs
 struct StoreF64 {         // C[m][n] (+ split offset)
   double* C; int64_t M, N, ld, split_stride;
@@ -262,6 +274,64 @@ hipError_t launch_proj_SQ(const double* S, const double* T, int64_t k, int64_t s
   RowsF64N B{Vt, s, d, d};
   StoreSQ Sq{Pi, Pi64, S, k, d, s};
   k_gemm64<RowsF64, RowsF64N, StoreSQ, true, false, false><<<(unsigned)(tm * tn), 256, 0, st>>>(A, B, Sq, k, d, s, round_up(s > 0 ? s : 1, GK), tn);
+  return hipGetLastError();
+}
+
+// Sum of split partials: out[e] = sum_s part[s * count + e].
+__global__ void k_sum_splits(const double* __restrict__ part, int nsplit, int64_t count, double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= count) return;
+  double s = 0.0;
+  for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * count + e];
+  out[e] = s;
+}
+
+hipError_t launch_sketch(const float* X, int64_t n, int64_t d, const double* mu, int m, uint64_t sseed, double* part,
+                         int nsplit, double* G, hipStream_t st) {
+  const int64_t tm = (m + GT - 1) / GT, tn = (d + GT - 1) / GT;
+  SketchSigns A{sseed, m, n, 1.0 / sqrt((double)m)};
+  CentredColsB B{X, mu, n, d};
+  StoreF64 S{part, m, d, d, (int64_t)m * d};
+  const int64_t kps = round_up((n + nsplit - 1) / nsplit, GK);
+  dim3 g((unsigned)(tm * tn), (unsigned)nsplit);
+  k_gemm64<SketchSigns, CentredColsB, StoreF64, true, false, false><<<g, 256, 0, st>>>(A, B, S, m, d, n, kps, tn);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_sum_splits<<<(unsigned)((m * d + 255) / 256), 256, 0, st>>>(part, nsplit, (int64_t)m * d, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_rows(const double* G, int m, int64_t d, double* K, int mp, hipStream_t st) {
+  const int64_t tm = (mp + GT - 1) / GT;
+  RowsF64 A{G, m, d, d};
+  RowsF64T B{G, m, d, d};
+  StoreF64 S{K, mp, mp, mp, 0};
+  k_gemm64<RowsF64, RowsF64T, StoreF64, true, true, false><<<(unsigned)(tm * tm), 256, 0, st>>>(A, B, S, mp, mp, d, round_up(d, GK), tm);
+  return hipGetLastError();
+}
+
+// Features of the learned search, from the sketch spectrum (decreasing lam):
+//   f[i] = ln(sigma_i / ||sigma||_2 + 1e-6) / 4 for i < 64 (sigma = sqrt(lam)),
+//   f[64] = ln(n) / 10, f[65] = ln(d) / 10, f[66] = 5 eps, f[67..79] = 0.
+__global__ void k_sketch_features(const double* __restrict__ lam, int m, int64_t n, int64_t d, double eps,
+                                  float* __restrict__ f) {
+  if (threadIdx.x != 0) return;
+  double tot = 0.0;
+  for (int i = 0; i < m; ++i) tot += lam[i] > 0.0 ? lam[i] : 0.0;
+  const double norm = sqrt(tot) > 0.0 ? sqrt(tot) : 1.0;
+  for (int i = 0; i < 64; ++i) {
+    const double sg = i < m && lam[i] > 0.0 ? sqrt(lam[i]) : 0.0;
+    f[i] = (float)(log(sg / norm + 1e-6) / 4.0);
+  }
+  f[64] = (float)(log((double)n) / 10.0);
+  f[65] = (float)(log((double)d) / 10.0);
+  f[66] = (float)(5.0 * eps);
+  for (int i = 67; i < 80; ++i) f[i] = 0.0f;
+}
+
+hipError_t launch_sketch_features(const double* lam, int m, int64_t n, int64_t d, double eps, float* feat,
+                                  hipStream_t st) {
+  k_sketch_features<<<1, 64, 0, st>>>(lam, m, n, d, eps, feat);
   return hipGetLastError();
 }
 

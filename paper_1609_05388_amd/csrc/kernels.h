@@ -75,4 +75,33 @@ hipError_t launch_flag_tiles(const TileRec* recs, int64_t ntiles, CertDev* cd, u
 hipError_t launch_top2(const PairVal* vals, const uint32_t* count_ptr, uint32_t cap, PairVal* part, int nparts,
                        CertDev* cd, hipStream_t st);
 
+// k_gemm64.hip (sketch)
+// G = Omega Xc (m x d, FP64) with Omega[a][i] = +-1/sqrt(m) from SplitMix64
+// output (a << 32 | i) + 1 of seed `sseed`; split over points, partials summed.
+hipError_t launch_sketch(const float* X, int64_t n, int64_t d, const double* mu, int m, uint64_t sseed, double* part,
+                         int nsplit, double* G, hipStream_t st);
+// K = G G^T (m x m, FP64) into an mp x mp zero-padded matrix.
+hipError_t launch_gram_rows(const double* G, int m, int64_t d, double* K, int mp, hipStream_t st);
+// Features from the sorted sketch eigenvalues lam (m values, decreasing).
+hipError_t launch_sketch_features(const double* lam, int m, int64_t n, int64_t d, double eps, float* feat,
+                                  hipStream_t st);
+
+// k_mlp.hip
+struct MlpLayout {
+  int in, in_pad, hidden;
+  int64_t W1, b1, W2, b2, W3, b3, w4, b4, total;
+};
+struct MlpActs {
+  float *A1, *A2, *A3, *dZ, *dZ2, *g;
+  __bf16 *A1b, *A2b;
+};
+MlpLayout mlp_layout();
+hipError_t mlp_forward(const MlpLayout& L, const float* p, const __bf16* pb, const __bf16* X, int B, MlpActs& a,
+                       float* out, hipStream_t st);
+hipError_t mlp_backward(const MlpLayout& L, const __bf16* pb, const __bf16* X, const float* y, int B, float tau,
+                        MlpActs& a, const float* out, float* grad, float* loss, hipStream_t st);
+hipError_t mlp_adam(float* p, __bf16* pb, const float* g, float* m, float* v, int64_t count, float lr, int step,
+                    hipStream_t st);
+hipError_t mlp_to_bf16(const float* src, __bf16* dst, int64_t count, hipStream_t st);
+
 }  // namespace adg
