@@ -30,6 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_FP8_MFMA_TFLOPS = 5000.0
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 PAIRS_KERNEL_SRC = os.path.join(ROOT, "paper_1609_05388_amd", "csrc", "k_pairs.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pairs_f32_mnist60k_traffic.json")
 
@@ -126,6 +128,50 @@ def cpu_baseline(X, Pi, target_s):
             "sample": "eq.(3) certificate by FP64 direct differences (oracle/certificate.c, OpenMP) over "
                       "rows [0,%d) x all j>i of the same cloud at the fitted r (%d pairs, %.1f s)"
                       % (m2, c["n_pairs"], dt)}
+
+
+def timed_fits(adagio, torch, Xd, eps, seed, steps, **kw):
+    adagio.fit(Xd, eps, seed, **kw)             # buffers and first-call set-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [adagio.fit(Xd, eps, seed, **kw) for _ in range(steps)]
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, outs
+
+
+def fp8_form(adagio, gen, torch, Xd, eps, steps, plain_s, plain, npairs, d):
+    """Fit whose bisection decides on FP8 screens, then certifies its result
+    with the BF16 split screen."""
+    fs, outs = timed_fits(adagio, torch, Xd, eps, gen.JL_SEED, steps, screen="fp8")
+    o = outs[-1]
+    st = o["stats"]
+    scr = [(r, t) for r, t in zip(st["probe_r"], st["probe_screen_ms"])][:st["n_screened"]]
+    fl = sum(npairs * 2.0 * (d + r) for r, _ in scr)
+    ms = sum(t for _, t in scr)
+    return {"fit_ms": fs * 1e3, "speedup_vs_plain": plain_s / fs, "r": o["r"],
+            "max_distortion": o["cert"]["max_distortion"], "certified": o["cert"]["certified"],
+            "abs_err_vs_plain_fp64_certificate": abs(o["cert"]["max_distortion"] - plain["cert"]["max_distortion"]),
+            "same_map_as_plain": bool(o["r"] == plain["r"] and torch.equal(o["Pi"], plain["Pi"])),
+            "screens": st["n_screened"], "certificates": st["n_certificates"] - st["n_screened"],
+            "screen_probes": [[r, dl] for r, dl in zip(st["probe_r"], st["probe_delta"])][:st["n_screened"]],
+            "screen_avg_launch_ms": ms / max(1, len(scr)),
+            "screen_fp8_mfma_tflops": fl / max(ms, 1e-9) / 1e9,
+            "screen_fp8_mfma_frac": fl / max(ms, 1e-9) / 1e9 / PEAK_FP8_MFMA_TFLOPS}
+
+
+def learned_form(adagio, gen, torch, Xd, eps, steps, plain_s, plain):
+    """Fit from the trained predictor's r (certified, bisection fallback)."""
+    import numpy as np
+    from paper_1609_05388_amd import learned
+    if not os.path.exists(learned.PREDICTOR):
+        return None
+    P = learned.load_predictor(learned.PREDICTOR)
+    fs, outs = timed_fits(adagio, torch, Xd, eps, gen.JL_SEED, steps, search="learned", predictor=P)
+    o = outs[-1]
+    return {"fit_ms": fs * 1e3, "speedup_vs_plain": plain_s / fs, "r": o["r"], "r_plain": plain["r"],
+            "r_predicted": o["stats"]["r_predicted"], "fallback": o["stats"]["n_fallback"],
+            "certificates": o["stats"]["n_certificates"], "max_distortion": o["cert"]["max_distortion"],
+            "certified": o["cert"]["certified"]}
 
 
 def main():
@@ -236,9 +282,15 @@ def main():
             "screen_avg_launch_ms": bms / bn,
             "screen_useful_tflops": bflops / bn / (bms / bn * 1e-3) / 1e12,
             "screen_bf16_mfma_tflops": 3.0 * bflops / bn / (bms / bn * 1e-3) / 1e12,
-            "screen_bf16_mfma_frac": 3.0 * bflops / bn / (bms / bn * 1e-3) / 1e12 / 2516.0,
+            "screen_bf16_mfma_frac": 3.0 * bflops / bn / (bms / bn * 1e-3) / 1e12 / PEAK_BF16_MFMA_TFLOPS,
             "rescored_pairs": bl["stats"]["n_rescored"], "flagged_tiles": bl["stats"]["n_flagged_tiles"]}
         log("bf16x3 fit %.1f ms (%.2fx), screen %.2f ms/launch" % (bf_s * 1e3, fit_s / bf_s, bms / bn))
+        forms["fp8"] = fp8_form(adagio, gen, torch, Xd, args.eps, args.steps, fit_s, last, npairs, d)
+        log("fp8 fit %.1f ms (%.2fx)" % (forms["fp8"]["fit_ms"], forms["fp8"]["speedup_vs_plain"]))
+        lf = learned_form(adagio, gen, torch, Xd, args.eps, args.steps, fit_s, last)
+        if lf:
+            forms["learned"] = lf
+            log("learned fit %.1f ms (%.2fx)" % (lf["fit_ms"], lf["speedup_vs_plain"]))
 
     extra = {}
     if not args.no_extra_eps:

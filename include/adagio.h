@@ -50,7 +50,12 @@ extern "C" {
  * final value are exact in every mode). */
 #define ADAGIO_SCREEN_F32 0      /* FP32 MFMA Gram, rigorous per-pair bounds   */
 #define ADAGIO_SCREEN_BF16X3 1   /* BF16 hi/lo split, 3 BF16 MFMA products     */
-#define ADAGIO_SCREEN_FP8 2      /* FP8 e4m3 per-row scaled screen + rescoring */
+#define ADAGIO_SCREEN_FP8 2      /* FP8 e4m3 per-row scaled screen: its 1024
+                                    tiles of largest estimated distortion are
+                                    re-screened with FP32 bounds and rescored;
+                                    proves nothing about the other tiles
+                                    (certified = 0, bound_rest = +inf); fits
+                                    certify their result with BF16X3 */
 
 /* Target-dimension search. */
 #define ADAGIO_SEARCH_BISECT 0   /* bisection over r in (0, d]                 */
@@ -84,7 +89,7 @@ typedef struct adagio_stats {
     int64_t n_flagged_tiles; /* summed over certificates                          */
     int64_t n_rescored;      /* summed over certificates                          */
     int32_t n_probes;        /* certificates logged below, in call order (<= 48)  */
-    int32_t reserved;
+    int32_t n_screened;      /* how many of the certificates were FP8 screens     */
     int32_t probe_r[48];     /* target dimension of each certificate              */
     double probe_delta[48];  /* its exact max distortion                          */
     double probe_screen_ms[48]; /* its all-pairs screen kernel time (device events) */
@@ -93,7 +98,7 @@ typedef struct adagio_stats {
 typedef struct adagio_opts {
     int32_t screen;          /* ADAGIO_SCREEN_*; default F32                      */
     int32_t search;          /* ADAGIO_SEARCH_*; default BISECT                   */
-    int32_t max_candidates;  /* initial candidate capacity per certificate; 0 = default */
+    int32_t max_candidates;  /* initial candidate capacity per certificate; 0 = default (2^20) */
     int32_t reserved;
     const float* predictor;  /* learned search: device pointer to the packed MLP parameters */
     adagio_stats_t* stats;   /* optional host output                              */
@@ -131,7 +136,10 @@ int adagio_embed(const float* X, int64_t n, int64_t d, const float* Pi, int32_t 
  * | ||y_i - y_j|| / ||x_i - x_j|| - 1 |.  An MFMA screen bounds every pair;
  * pairs whose bound reaches the best exact value are re-evaluated in FP64 by
  * direct differences of the given rows.  opts->screen picks the screen
- * precision.  cert_out: host.  Synchronises `stream`. */
+ * precision; with ADAGIO_SCREEN_FP8 the result is the exact maximum over the
+ * pairs of the screen's selected tiles only (a lower bound of eq. (3),
+ * certified = 0).
+ * cert_out: host.  Synchronises `stream`. */
 int adagio_max_distortion(const float* X, int64_t n, int64_t d, const float* Y, int32_t r,
                           const adagio_opts_t* opts, adagio_cert_t* cert_out, void* stream);
 
@@ -149,10 +157,23 @@ int adagio_certify_map(const float* X, int64_t n, int64_t d, const float* Pi, in
  * Pi_out: device buffer of capacity d x d FP32; receives Pi (r x d).
  * r_out, s_out: host; cert_out: host, the certificate of the returned Pi.
  * opts->search = ADAGIO_SEARCH_LEARNED starts from the network's prediction
- * (opts->predictor) and falls back to bisection.  Synchronises `stream`. */
+ * (opts->predictor) and falls back to bisection.  With ADAGIO_SCREEN_FP8 the
+ * bisection decides on FP8 screens, then the result is certified with the
+ * BF16 split screen; if that fails, certified bisection continues above it,
+ * so the returned certificate is always a certificate.  Synchronises
+ * `stream`. */
 int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed,
                const adagio_opts_t* opts, float* Pi_out, int32_t* r_out, int32_t* s_out,
                adagio_cert_t* cert_out, void* stream);
+
+/* a10.  The FP8 screen's operand encoding: every row a_i of A (device, n x m
+ * FP32, row-major) is scaled by s_i = max_l |a_il| / 448 (s_i = 1 for a zero
+ * row) and rounded to nearest even into OCP FP8 e4m3 (bias 7, no infinities,
+ * 448 the largest finite value): Q_out[i][l] = e4m3(a_il / s_i) (device, n x m
+ * bytes), scale_out[i] = s_i (device, n floats), norm2_out[i] = s_i^2 |q_i|^2
+ * accumulated in FP64 (device, n doubles).  Asynchronous. */
+int adagio_quantize_fp8(const float* A, int64_t n, int64_t m, uint8_t* Q_out, float* scale_out, double* norm2_out,
+                        void* stream);
 
 /* a11.  Learned form (a method extension, not in the paper): the 80 input
  * features of the target-dimension predictor for cloud X and target eps.

@@ -41,7 +41,7 @@ class Stats(ctypes.Structure):
                 ("eig_sweeps", ctypes.c_int32), ("n_fallback", ctypes.c_int32),
                 ("r_predicted", ctypes.c_int32), ("n_flagged_tiles", ctypes.c_int64),
                 ("n_rescored", ctypes.c_int64), ("n_probes", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("probe_r", ctypes.c_int32 * 48),
+                ("n_screened", ctypes.c_int32), ("probe_r", ctypes.c_int32 * 48),
                 ("probe_delta", ctypes.c_double * 48), ("probe_screen_ms", ctypes.c_double * 48)]
 
     def to_dict(self):
@@ -77,6 +77,7 @@ SIGNATURES = {
                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(Cert), _P]),
     "adagio_sketch_features": (ctypes.c_int, [_P, _I64, _I64, _D, _U64, _P, _P]),
+    "adagio_quantize_fp8": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _P, _P]),
     "adagio_mlp_param_count": (ctypes.c_int64, []),
     "adagio_mlp_forward": (ctypes.c_int, [_P, _P, _I32, _P, _P]),
     "adagio_mlp_grad": (ctypes.c_int, [_P, _P, _P, _I32, ctypes.c_float, _P, _P, _P]),
@@ -226,6 +227,20 @@ def fit(X, eps, seed, screen="f32", search="bisect", predictor=None, max_candida
 
 
 N_FEATURES = 80
+
+
+def quantize_fp8(A):
+    """(Q, scale, norm2): per-row scaled OCP e4m3 bytes (uint8, n x m), the row
+    scales (FP32) and s_i^2 |q_i|^2 (FP64) of the FP32 rows of A."""
+    lib = load()
+    n, m = A.shape
+    Q = torch.empty((n, m), dtype=torch.uint8, device=A.device)
+    scale = torch.empty(n, dtype=torch.float32, device=A.device)
+    norm2 = torch.empty(n, dtype=torch.float64, device=A.device)
+    _check(lib.adagio_quantize_fp8(_dev(A, torch.float32, "A"), n, m, _dev(Q, torch.uint8, "Q"),
+                                   _dev(scale, torch.float32, "scale"), _dev(norm2, torch.float64, "norm2"),
+                                   _stream()))
+    return Q, scale, norm2
 
 
 def sketch_features(X, eps, seed):

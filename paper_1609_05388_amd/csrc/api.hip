@@ -56,6 +56,7 @@ struct Workspace {
   DevBuf S, T, Pi, Pi64, Y64, Yc, ny, ty, muY;
   DevBuf recs, tparts, seeds, seedv, list, cand, vals, vparts, cd;
   DevBuf Xb, txb, Yb, tyb, bjU, bjS;
+  DevBuf Xq, sx, nxq, Yq, sy, nyq, q8terms, hist, kthr;
   DevBuf skpart, skG, skK, sklam, skV, skfeat, mlp_pb, mlp_X, mlp_f, mlp_hb, mlp_grad, mlp_loss;
   bool checked = false;
 };
@@ -127,9 +128,13 @@ struct Points {
   double* nx = nullptr;
   float2* tx = nullptr;
   int screen = ADAGIO_SCREEN_F32;
-  int64_t ldxb = 0;          // BF16 split (screen = BF16X3)
+  int64_t ldxb = 0;          // BF16 split (screen = BF16X3 or FP8)
   __bf16* Xb = nullptr;
   float2* txb = nullptr;
+  int64_t ldxq = 0;          // per-row scaled e4m3 copy (screen = FP8)
+  unsigned char* Xq = nullptr;
+  float* sx = nullptr;
+  double* nxq = nullptr;
 };
 
 static void mean_rows(Workspace& ws, const float* A, int64_t n, int64_t m, int64_t ld, double* mu, hipStream_t st) {
@@ -174,12 +179,21 @@ static Points prep_points(Workspace& ws, const float* X, int64_t n, int64_t d, h
   p.tx = ensure<float2>(ws.tx, (size_t)p.n_pad);
   HIPCHK(launch_center<float>(X, n, d, d, p.mu, p.Xc, p.ldx, p.n_pad, p.nx, st));
   HIPCHK(launch_row_terms(p.nx, screen_const(p.ldx), nullptr, 0.0, p.n_pad, p.tx, st));
-  if (screen == ADAGIO_SCREEN_BF16X3) {
+  // The FP8 screen ranks pairs only; its fits end with a BF16 split
+  // certificate, so both copies are made.
+  if (screen == ADAGIO_SCREEN_BF16X3 || screen == ADAGIO_SCREEN_FP8) {
     p.ldxb = round_up(d, kChunkBf16);
     p.Xb = ensure<__bf16>(ws.Xb, (size_t)(p.n_pad * 2 * p.ldxb));
     p.txb = ensure<float2>(ws.txb, (size_t)p.n_pad);
     HIPCHK(launch_split_bf16(p.Xc, p.n_pad, d, p.ldx, p.ldxb, p.Xb, st));
     HIPCHK(launch_row_terms(p.nx, screen_const_bf16(p.ldxb), nullptr, 0.0, p.n_pad, p.txb, st));
+  }
+  if (screen == ADAGIO_SCREEN_FP8) {
+    p.ldxq = round_up(d, fp8_chunk());
+    p.Xq = ensure<unsigned char>(ws.Xq, (size_t)(p.n_pad * p.ldxq));
+    p.sx = ensure<float>(ws.sx, (size_t)p.n_pad);
+    p.nxq = ensure<double>(ws.nxq, (size_t)p.n_pad);
+    HIPCHK(launch_quant_fp8(p.Xc, p.n_pad, d, p.ldx, p.ldxq, p.Xq, p.sx, p.nxq, st));
   }
   return p;
 }
@@ -275,10 +289,9 @@ static void sketch_features(Workspace& ws, const Points& p, double eps, uint64_t
   const int mp = (int)round_up(m, 2 * bj_block());
   double* K = ensure<double>(ws.skK, (size_t)mp * mp);
   HIPCHK(launch_gram_rows(G, m, p.d, K, mp, st));
-  // The m x m eigenproblem reuses the Jacobi buffers (A0 is not needed here).
+  // eigenvalues only (the features need no eigenvectors)
   double* lam = ensure<double>(ws.sklam, (size_t)m);
-  double* V = ensure<double>(ws.skV, (size_t)m * m);
-  jacobi_eig(ws, K, mp, m, lam, V, st);
+  HIPCHK(launch_sym_eigvals(K, m, mp, lam, st));
   HIPCHK(launch_sketch_features(lam, m, p.n, p.d, eps, feat, st));
 }
 
@@ -346,9 +359,34 @@ struct Images {
   int64_t ldyb = 0;             // BF16 split (screen = BF16X3)
   __bf16* Yb = nullptr;
   float2* tyb = nullptr;
+  int64_t ldyq = 0;             // per-row scaled e4m3 copy (screen = FP8)
+  unsigned char* Yq = nullptr;
+  float4* q8 = nullptr;         // per row (N_x, N_y, s_x, s_y) of the FP8 screen
   const float* Y32 = nullptr;   // rescore source (given images) ...
   const double* Y64 = nullptr;  // ... or FP64 images of a map
 };
+
+// The screen's reduced-precision copies of the centred images Yc (row norms
+// ny); nx_emb / c_emb: the FP64 embedding error term of images of a map.
+static void image_copies(Workspace& ws, const Points& p, Images& im, const double* ny, const double* nx_emb,
+                         double c_emb, hipStream_t st) {
+  if (p.screen == ADAGIO_SCREEN_BF16X3 || p.screen == ADAGIO_SCREEN_FP8) {
+    im.ldyb = round_up(im.r, kChunkBf16);
+    im.Yb = ensure<__bf16>(ws.Yb, (size_t)(p.n_pad * 2 * im.ldyb));
+    im.tyb = ensure<float2>(ws.tyb, (size_t)p.n_pad);
+    HIPCHK(launch_split_bf16(im.Yc, p.n_pad, im.r, im.ldy, im.ldyb, im.Yb, st));
+    HIPCHK(launch_row_terms(ny, screen_const_bf16(im.ldyb), nx_emb, c_emb, p.n_pad, im.tyb, st));
+  }
+  if (p.screen == ADAGIO_SCREEN_FP8) {
+    im.ldyq = round_up(im.r, fp8_chunk());
+    im.Yq = ensure<unsigned char>(ws.Yq, (size_t)(p.n_pad * im.ldyq));
+    float* sy = ensure<float>(ws.sy, (size_t)p.n_pad);
+    double* nyq = ensure<double>(ws.nyq, (size_t)p.n_pad);
+    HIPCHK(launch_quant_fp8(im.Yc, p.n_pad, im.r, im.ldy, im.ldyq, im.Yq, sy, nyq, st));
+    im.q8 = ensure<float4>(ws.q8terms, (size_t)p.n_pad);
+    HIPCHK(launch_fp8_terms(p.nxq, nyq, p.sx, sy, p.n_pad, im.q8, st));
+  }
+}
 
 // Images of the linear map Pi in FP64, centred: Y64 = (X - mu) Pi^T.
 static Images images_of_map(Workspace& ws, const Points& p, const float* Pi, int64_t r, hipStream_t st) {
@@ -366,13 +404,7 @@ static Images images_of_map(Workspace& ws, const Points& p, const float* Pi, int
   const double dd = (double)p.d;
   const double c_emb = 4.02 * 2.1 * dd * (dd + 1.0) * kU64 * 1.01;
   HIPCHK(launch_row_terms(ny, screen_const(im.ldy), p.nx, c_emb, p.n_pad, im.ty, st));
-  if (p.screen == ADAGIO_SCREEN_BF16X3) {
-    im.ldyb = round_up(r, kChunkBf16);
-    im.Yb = ensure<__bf16>(ws.Yb, (size_t)(p.n_pad * 2 * im.ldyb));
-    im.tyb = ensure<float2>(ws.tyb, (size_t)p.n_pad);
-    HIPCHK(launch_split_bf16(im.Yc, p.n_pad, r, im.ldy, im.ldyb, im.Yb, st));
-    HIPCHK(launch_row_terms(ny, screen_const_bf16(im.ldyb), p.nx, c_emb, p.n_pad, im.tyb, st));
-  }
+  image_copies(ws, p, im, ny, p.nx, c_emb, st);
   im.Y64 = Y64;
   return im;
 }
@@ -389,13 +421,7 @@ static Images images_given(Workspace& ws, const Points& p, const float* Y, int64
   HIPCHK(launch_center<float>(Y, p.n, r, r, muY, im.Yc, im.ldy, p.n_pad, ny, st));
   im.ty = ensure<float2>(ws.ty, (size_t)p.n_pad);
   HIPCHK(launch_row_terms(ny, screen_const(im.ldy), nullptr, 0.0, p.n_pad, im.ty, st));
-  if (p.screen == ADAGIO_SCREEN_BF16X3) {
-    im.ldyb = round_up(r, kChunkBf16);
-    im.Yb = ensure<__bf16>(ws.Yb, (size_t)(p.n_pad * 2 * im.ldyb));
-    im.tyb = ensure<float2>(ws.tyb, (size_t)p.n_pad);
-    HIPCHK(launch_split_bf16(im.Yc, p.n_pad, r, im.ldy, im.ldyb, im.Yb, st));
-    HIPCHK(launch_row_terms(ny, screen_const_bf16(im.ldyb), nullptr, 0.0, p.n_pad, im.tyb, st));
-  }
+  image_copies(ws, p, im, ny, nullptr, 0.0, st);
   im.Y32 = Y;
   return im;
 }
@@ -403,6 +429,7 @@ static Images images_given(Workspace& ws, const Points& p, const float* Y, int64
 struct CertTimes {
   double screen_ms = 0.0, rest_ms = 0.0;
   int64_t flagged = 0, rescored = 0;
+  int screened = 0;   // FP8 screens among the calls
   int nprobe = 0;
   int32_t probe_r[48];
   double probe_delta[48], probe_ms[48];
@@ -425,6 +452,7 @@ static void fill_stats(adagio_stats_t* s, const CertTimes& tm, int ncert, double
   s->n_flagged_tiles = tm.flagged;
   s->n_rescored = tm.rescored;
   s->n_probes = tm.nprobe;
+  s->n_screened = tm.screened;
   for (int k = 0; k < tm.nprobe; ++k) {
     s->probe_r[k] = tm.probe_r[k];
     s->probe_delta[k] = tm.probe_delta[k];
@@ -441,9 +469,15 @@ static void rescore(const Points& p, const Images& im, const int2* pairs, const 
 
 static const uint32_t kDefaultCap = 1u << 20;
 static const uint32_t kHardCap = 1u << 26;
+// FP8 screen: tiles re-screened with the FP32 bounds (at most 4x that many
+// when key buckets tie).
+static const uint32_t kFp8Tiles = 1024;
 
+// The certificate of eq. (3) for points p and images im.  With the FP8 screen
+// the same steps run on the FP8 estimates' top tiles only, and the result is
+// the exact maximum over those tiles (certified = 0, no bound on the rest).
 static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& im, uint32_t cap0,
-                                 hipStream_t st, CertTimes* times) {
+                                 hipStream_t st, CertTimes* times, int screen) {
   PairsView v;
   v.X = p.Xc; v.ldx = (int)p.ldx;
   v.Y = im.Yc; v.ldy = (int)im.ldy;
@@ -464,7 +498,7 @@ static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& i
 
   EvPair e_screen, e_rest;
   e_screen.begin(st);
-  if (p.screen == ADAGIO_SCREEN_BF16X3) {
+  if (screen == ADAGIO_SCREEN_BF16X3) {
     // BF16 split screen; the emit pass below keeps the FP32 Gram (tighter
     // bounds, fewer candidates, equally rigorous).
     PairsViewB vb;
@@ -473,6 +507,8 @@ static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& i
     vb.tx = p.txb; vb.ty = im.tyb;
     vb.n = v.n; vb.NT = v.NT; vb.ntiles = v.ntiles;
     HIPCHK(launch_pairs_screen_bf16(vb, recs, st));
+  } else if (screen == ADAGIO_SCREEN_FP8) {
+    HIPCHK(launch_pairs_screen_fp8(p.Xq, (int)p.ldxq, im.Yq, (int)im.ldyq, im.q8, v.n, v.NT, recs, st));
   } else {
     HIPCHK(launch_pairs_screen(v, recs, st));
   }
@@ -481,7 +517,14 @@ static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& i
   HIPCHK(launch_seeds(recs, v.ntiles, tparts, nparts, seeds, cd, st));
   rescore(p, im, seeds, nullptr, &cd->n_seed, 2, seedv, 1, st);
   HIPCHK(launch_thresholds(seedv, cd, st));
-  HIPCHK(launch_flag_tiles(recs, v.ntiles, cd, list, st));
+  if (screen == ADAGIO_SCREEN_FP8) {
+    uint32_t* hist = ensure<uint32_t>(ws.hist, 65536);
+    uint32_t* kthr = ensure<uint32_t>(ws.kthr, 1);
+    HIPCHK(hipMemsetAsync(hist, 0, 65536 * sizeof(uint32_t), st));
+    HIPCHK(launch_topk_tiles(recs, v.ntiles, kFp8Tiles, 4 * kFp8Tiles, hist, kthr, list, &cd->n_flagged, st));
+  } else {
+    HIPCHK(launch_flag_tiles(recs, v.ntiles, cd, list, st));
+  }
 
   uint32_t cap = cap0 ? cap0 : kDefaultCap;
   CertDev h;
@@ -540,7 +583,10 @@ static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& i
   // Rigorous bound over every pair from the screen's global extremes.
   const double qh = (double)h.qhi_all, ql = (double)h.qlo_all;
   const double ub = std::max(std::sqrt(std::max(qh, 0.0)) - 1.0, 1.0 - std::sqrt(std::max(ql, 0.0)));
-  if (complete) {
+  if (screen == ADAGIO_SCREEN_FP8) {
+    c.certified = 0;
+    c.bound_rest = INFINITY;
+  } else if (complete) {
     c.certified = 1;
     c.bound_rest = h.bound_rest;
   } else {
@@ -553,6 +599,7 @@ static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& i
     times->rest_ms += e_rest.ms();
     times->flagged += h.n_flagged;
     times->rescored += c.n_rescored;
+    if (screen == ADAGIO_SCREEN_FP8) ++times->screened;
     log_probe(*times, im.r, c, sm);
   }
   return c;
@@ -644,14 +691,15 @@ int adagio_max_distortion(const float* X, int64_t n, int64_t d, const float* Y, 
     ARGCHK(Y && cert_out, "Y or cert_out is NULL");
     ARGCHK(r >= 1, "need r >= 1");
     const int screen = opts ? opts->screen : ADAGIO_SCREEN_F32;
-    ARGCHK(screen == ADAGIO_SCREEN_F32 || screen == ADAGIO_SCREEN_BF16X3, "unknown or unavailable screen precision");
+    ARGCHK(screen == ADAGIO_SCREEN_F32 || screen == ADAGIO_SCREEN_BF16X3 || screen == ADAGIO_SCREEN_FP8,
+           "unknown screen precision");
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = as_stream(stream);
     Workspace& ws = workspace();
     Points p = prep_points(ws, X, n, d, st, screen);
     Images im = images_given(ws, p, Y, r, st);
     CertTimes tm;
-    *cert_out = certificate(ws, p, im, opts ? (uint32_t)std::max(0, opts->max_candidates) : 0u, st, &tm);
+    *cert_out = certificate(ws, p, im, opts ? (uint32_t)std::max(0, opts->max_candidates) : 0u, st, &tm, screen);
     if (opts && opts->stats)
       fill_stats(opts->stats, tm, 1,
                  std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
@@ -665,14 +713,15 @@ int adagio_certify_map(const float* X, int64_t n, int64_t d, const float* Pi, in
     ARGCHK(Pi && cert_out, "Pi or cert_out is NULL");
     ARGCHK(r >= 1, "need r >= 1");
     const int screen = opts ? opts->screen : ADAGIO_SCREEN_F32;
-    ARGCHK(screen == ADAGIO_SCREEN_F32 || screen == ADAGIO_SCREEN_BF16X3, "unknown or unavailable screen precision");
+    ARGCHK(screen == ADAGIO_SCREEN_F32 || screen == ADAGIO_SCREEN_BF16X3 || screen == ADAGIO_SCREEN_FP8,
+           "unknown screen precision");
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = as_stream(stream);
     Workspace& ws = workspace();
     Points p = prep_points(ws, X, n, d, st, screen);
     Images im = images_of_map(ws, p, Pi, r, st);
     CertTimes tm;
-    *cert_out = certificate(ws, p, im, opts ? (uint32_t)std::max(0, opts->max_candidates) : 0u, st, &tm);
+    *cert_out = certificate(ws, p, im, opts ? (uint32_t)std::max(0, opts->max_candidates) : 0u, st, &tm, screen);
     if (opts && opts->stats)
       fill_stats(opts->stats, tm, 1,
                  std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
@@ -686,7 +735,8 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     ARGCHK(Pi_out && r_out && s_out && cert_out, "NULL output pointer");
     ARGCHK(eps > 0.0 && eps < 1.0, "eps must be in (0, 1)");
     const int screen = opts ? opts->screen : ADAGIO_SCREEN_F32;
-    ARGCHK(screen == ADAGIO_SCREEN_F32 || screen == ADAGIO_SCREEN_BF16X3, "unknown or unavailable screen precision");
+    ARGCHK(screen == ADAGIO_SCREEN_F32 || screen == ADAGIO_SCREEN_BF16X3 || screen == ADAGIO_SCREEN_FP8,
+           "unknown screen precision");
     const int search = opts ? opts->search : ADAGIO_SEARCH_BISECT;
     ARGCHK(search == ADAGIO_SEARCH_BISECT || search == ADAGIO_SEARCH_LEARNED, "unknown search");
     ARGCHK(search != ADAGIO_SEARCH_LEARNED || opts->predictor, "learned search needs opts->predictor");
@@ -707,14 +757,21 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     bool have_hi = false;
     adagio_cert_t cert_hi;
     memset(&cert_hi, 0, sizeof(cert_hi));
-    // One probe: certify the map at r; on a pass keep it as the current answer.
-    // Pass when the exact maximum is <= eps, or (incomplete certificate) when
-    // the proven bound over all pairs is <= eps.
-    auto probe = [&](int64_t r) {
+    // The rigorous screen: the FP8 screen only ranks pairs, so an FP8 fit
+    // makes its decisions with screened probes and then certifies with the
+    // BF16 split screen.
+    const int rig = screen == ADAGIO_SCREEN_FP8 ? ADAGIO_SCREEN_BF16X3 : screen;
+    // One probe: the map at r under screen `scr`.  A certificate passes when
+    // its exact maximum is <= eps, or (incomplete) when its proven bound over
+    // all pairs is <= eps, and becomes the current answer.  A screened probe
+    // passes when its re-evaluated maximum is <= eps; it fails only on a pair
+    // that exceeds eps, but may pass a map that a certificate rejects.
+    auto probe = [&](int64_t r, int scr) {
       build_map(ws, ax.Vt, d, r, seed, Pi, st);
       Images im = images_of_map(ws, p, Pi, r, st);
-      adagio_cert_t c = certificate(ws, p, im, cap0, st, &tm);
+      adagio_cert_t c = certificate(ws, p, im, cap0, st, &tm, scr);
       ++ncert;
+      if (scr == ADAGIO_SCREEN_FP8) return c.max_distortion <= eps;
       const bool pass = c.certified ? c.max_distortion <= eps : c.bound_rest <= eps;
       if (pass) {
         have_hi = true;
@@ -722,6 +779,13 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
         HIPCHK(hipMemcpyAsync(Pi_out, Pi, sizeof(float) * r * d, hipMemcpyDeviceToDevice, st));
       }
       return pass;
+    };
+    auto bisect = [&](int scr) {
+      while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) / 2;
+        if (probe(mid, scr)) hi = mid;
+        else lo = mid;
+      }
     };
     int32_t r_pred = 0, fallback = 0;
     if (search == ADAGIO_SEARCH_LEARNED) {
@@ -735,22 +799,27 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
       if (rp > d) rp = d;
       r_pred = (int32_t)rp;
       if (rp < d) {
-        if (probe(rp)) hi = rp;
+        if (probe(rp, rig)) hi = rp;
         else { lo = rp; fallback = 1; }
       }
-    }
-    // Bisection over r: lo = 0 (empty map, distortion 1), hi = d (isometry).
-    if (search == ADAGIO_SEARCH_BISECT || fallback) {
-      while (hi - lo > 1) {
-        const int64_t mid = (lo + hi) / 2;
-        if (probe(mid)) hi = mid;
-        else lo = mid;
+      if (fallback) bisect(rig);
+    } else if (screen == ADAGIO_SCREEN_FP8) {
+      // Bisection over r on screened probes, then the certificate of the
+      // result; if it fails, certified bisection continues on (r, d].
+      bisect(ADAGIO_SCREEN_FP8);
+      if (hi < d && !probe(hi, rig)) {
+        lo = hi;
+        hi = d;
+        bisect(rig);
       }
+    } else {
+      // Bisection over r: lo = 0 (empty map, distortion 1), hi = d (isometry).
+      bisect(rig);
     }
     if (!have_hi) {  // hi == d: the full eigenbasis
       build_map(ws, ax.Vt, d, d, seed, Pi_out, st);
       Images im = images_of_map(ws, p, Pi_out, d, st);
-      cert_hi = certificate(ws, p, im, cap0, st, &tm);
+      cert_hi = certificate(ws, p, im, cap0, st, &tm, rig);
       ++ncert;
     }
     e_search.end(st);
@@ -768,6 +837,16 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
       s->r_predicted = r_pred;
       s->n_fallback = fallback;
     }
+  });
+}
+
+int adagio_quantize_fp8(const float* A, int64_t n, int64_t m, uint8_t* Q_out, float* scale_out, double* norm2_out,
+                        void* stream) {
+  return guarded([&] {
+    ARGCHK(A && Q_out && scale_out && norm2_out, "NULL pointer");
+    ARGCHK(n >= 1 && m >= 1, "need n >= 1 and m >= 1");
+    (void)workspace();
+    HIPCHK(launch_quant_fp8(A, n, m, m, m, Q_out, scale_out, norm2_out, as_stream(stream)));
   });
 }
 
@@ -850,6 +929,7 @@ int adagio_release(void) {
                       &ws.W, &ws.trace, &ws.rot, &ws.lam, &ws.Vt, &ws.S, &ws.T, &ws.Pi, &ws.Pi64, &ws.Y64,
                       &ws.Yc, &ws.ny, &ws.ty, &ws.muY, &ws.recs, &ws.tparts, &ws.seeds, &ws.seedv, &ws.list,
                       &ws.cand, &ws.vals, &ws.vparts, &ws.cd, &ws.Xb, &ws.txb, &ws.Yb, &ws.tyb, &ws.bjU, &ws.bjS,
+                      &ws.Xq, &ws.sx, &ws.nxq, &ws.Yq, &ws.sy, &ws.nyq, &ws.q8terms, &ws.hist, &ws.kthr,
                       &ws.skpart, &ws.skG, &ws.skK, &ws.sklam, &ws.skV, &ws.skfeat, &ws.mlp_pb, &ws.mlp_X,
                       &ws.mlp_f, &ws.mlp_hb, &ws.mlp_grad, &ws.mlp_loss};
     for (DevBuf* b : bufs) {

@@ -1,0 +1,384 @@
+// Step a10 (precision form, large scale): an FP8 all-pairs screen.
+//
+// Every centred row a_i is scaled by s_i = max_l |a_il| / 448 and quantised
+// to OCP FP8 e4m3 (round to nearest even; 448 is the largest finite value):
+// q_i = e4m3(a_i / s_i).  The Gram q_i . q_j runs on
+// v_mfma_scale_f32_32x32x64_f8f6f4 (scale bytes 127 = 2^0) with FP32
+// accumulation, and the epilogue forms the central estimates
+//   D~^2 = N_i + N_j - 2 s_i s_j q_i.q_j,   N_i = s_i^2 |q_i|^2 (FP64, rounded),
+// and the same for the images, q~ = E~^2 / D~^2.  With a 2^-4 unit roundoff
+// these are estimates, not bounds: the screen ranks tiles.  Every tile keeps
+// its largest and smallest q~ (the tile record); the tiles whose estimated
+// distortion max(sqrt(q~hi) - 1, 1 - sqrt(q~lo)) is among the K largest are
+// selected by a histogram of the keys' top 16 bits.  The certificate code then
+// re-screens the selected tiles with the FP32 Gram and its rigorous bounds and
+// re-evaluates in FP64 every pair there that can reach the best exact value:
+// the result is the exact maximum over the selected tiles, a screened value.
+//
+// Operand layout in HBM: per row, chunks of 64 e4m3 bytes (one MFMA k-step);
+// LDS rows of 144 bytes hold two k-steps (128 bytes) plus 16 bytes padding.
+#include "common.h"
+#include "kernels.h"
+#include "pairs_common.h"
+
+namespace adg {
+
+constexpr int FK = 128;     // columns per chunk (two k-steps of 64)
+constexpr int FROW = 144;   // LDS bytes per row
+
+// OCP FP8 e4m3 (bias 7, no infinities, 448 the largest finite): round to
+// nearest even of |x| <= 448, returned as its bit pattern.
+__device__ inline unsigned char e4m3_rne(float x) {
+  const unsigned s = x < 0.0f ? 0x80u : 0u;
+  float a = fabsf(x);
+  if (!(a > 0.0f)) return (unsigned char)s;
+  if (a >= 448.0f) return (unsigned char)(s | 0x7Eu);
+  int e;
+  frexpf(a, &e);             // a = f * 2^e, f in [0.5, 1): unit exponent e - 1
+  int ue = e - 1;
+  if (ue < -6) ue = -6;      // subnormal spacing 2^-9
+  const float ulp = ldexpf(1.0f, ue - 3);
+  const float m = rintf(a / ulp);   // integer mantissa incl. leading bit (8..16 normal)
+  float v = m * ulp;
+  if (v > 448.0f) v = 448.0f;
+  // encode v
+  int ve;
+  frexpf(v, &ve);
+  int vu = ve - 1;
+  unsigned bits;
+  if (v == 0.0f) bits = 0u;
+  else if (vu < -6) bits = (unsigned)(v / ldexpf(1.0f, -9));          // subnormal: m * 2^-9, m < 8
+  else bits = ((unsigned)(vu + 7) << 3) | ((unsigned)(v / ldexpf(1.0f, vu) * 8.0f) & 7u);
+  return (unsigned char)(s | bits);
+}
+
+__device__ inline float e4m3_value(unsigned char b) {
+  const float sg = (b & 0x80u) ? -1.0f : 1.0f;
+  const int ex = (b >> 3) & 15, mt = b & 7;
+  if (ex == 0) return sg * ldexpf((float)mt, -9);
+  return sg * ldexpf(1.0f + mt / 8.0f, ex - 7);
+}
+
+// One wave per row: scale, quantise into the chunked layout (ldq bytes per
+// row, ldq a multiple of 128, zero padding), and the row's N = s^2 |q|^2.
+__global__ void k_quant_fp8(const float* __restrict__ src, int64_t n_pad, int64_t m, int64_t lds, int64_t ldq,
+                            unsigned char* __restrict__ q, float* __restrict__ scale, double* __restrict__ norm2) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n_pad) return;
+  const float* a = src + row * lds;
+  float mx = 0.0f;
+  for (int64_t l = lane; l < m; l += 64) mx = fmaxf(mx, fabsf(a[l]));
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+  const float s = mx > 0.0f ? mx / 448.0f : 1.0f;
+  double acc = 0.0;
+  for (int64_t l = lane; l < ldq; l += 64) {
+    unsigned char b = 0;
+    if (l < m) b = e4m3_rne(a[l] / s);
+    q[row * ldq + l] = b;
+    const double v = (double)e4m3_value(b);
+    acc += v * v;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane == 0) {
+    scale[row] = s;
+    norm2[row] = acc * ((double)s * (double)s);   // s^2 is exact in FP64
+  }
+}
+
+// Per-row epilogue terms (N_x, N_y, s_x, s_y).
+__global__ void k_fp8_terms(const double* __restrict__ nx, const double* __restrict__ ny,
+                            const float* __restrict__ sx, const float* __restrict__ sy, int64_t n_pad,
+                            float4* __restrict__ t) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n_pad) t[i] = make_float4((float)nx[i], (float)ny[i], sx[i], sy[i]);
+}
+
+struct PairsArgsF {
+  const unsigned char* X; int ldx; int nchx;   // e4m3 points, ldx bytes per row, nchx = ldx / FK
+  const unsigned char* Y; int ldy; int nchy;
+  const float4* terms;
+  int n; int NT; int NS; int64_t nslots;
+  TileRec* recs;
+};
+
+__global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  unsigned char* As = lds_raw;
+  unsigned char* Bs = lds_raw + 2 * kTile * FROW;
+  float4* termA = reinterpret_cast<float4*>(lds_raw + 4 * kTile * FROW);
+  float4* termB = termA + kTile;
+  float* red_v = reinterpret_cast<float*>(termB + kTile);   // [2][4]
+  int* red_i = reinterpret_cast<int*>(red_v + 8);           // [2][4]
+  int* red_j = red_i + 8;                                   // [2][4]
+  const unsigned char* const Xg = b.X;
+  const unsigned char* const Yg = b.Y;
+  const int ldx = b.ldx, ldy = b.ldy, nchx = b.nchx, nchy = b.nchy, n = b.n, NT = b.NT;
+  const int total = nchx + nchy;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int li = lane & 31, lh = lane >> 5;
+
+  const uint32_t G = gridDim.x;
+  const int64_t slot = (int64_t)(blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  if (slot >= b.nslots) return;
+  const TilePos tp = slot_tile(slot, NT, b.NS);
+  if (tp.I < 0) return;
+  const int I = (int)tp.I, J = (int)tp.J;
+  const int row0 = I * kTile, col0 = J * kTile;
+  if (tid < kTile) termA[tid] = b.terms[row0 + tid];
+  else termB[tid - kTile] = b.terms[col0 + tid - kTile];
+
+  f32x16 accX[2][2], accY[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      accX[x][y] = (f32x16){0};
+      accY[x][y] = (f32x16){0};
+    }
+  const int seg = tid & 7, lr = tid >> 3;
+  const unsigned char* xa = Xg + (size_t)(row0 + lr) * ldx + seg * 16;
+  const unsigned char* xb = Xg + (size_t)(col0 + lr) * ldx + seg * 16;
+  const unsigned char* ya = Yg + (size_t)(row0 + lr) * ldy + seg * 16;
+  const unsigned char* yb = Yg + (size_t)(col0 + lr) * ldy + seg * 16;
+  u32x4 ga[4], gb[4];
+  auto fetch = [&](int c) __attribute__((always_inline)) {
+    if (c < nchx) {
+      const size_t off = (size_t)c * FK;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        ga[m] = *reinterpret_cast<const u32x4*>(xa + off + (size_t)32 * m * ldx);
+        gb[m] = *reinterpret_cast<const u32x4*>(xb + off + (size_t)32 * m * ldx);
+      }
+    } else {
+      const size_t off = (size_t)(c - nchx) * FK;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        ga[m] = *reinterpret_cast<const u32x4*>(ya + off + (size_t)32 * m * ldy);
+        gb[m] = *reinterpret_cast<const u32x4*>(yb + off + (size_t)32 * m * ldy);
+      }
+    }
+  };
+  auto stash = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      *reinterpret_cast<u32x4*>(As + (size_t)buf * kTile * FROW + (lr + 32 * m) * FROW + seg * 16) = ga[m];
+      *reinterpret_cast<u32x4*>(Bs + (size_t)buf * kTile * FROW + (lr + 32 * m) * FROW + seg * 16) = gb[m];
+    }
+  };
+  // k-step s: lanes 0-31 take bytes 64 s .. 64 s + 31 of their row, lanes
+  // 32-63 bytes 64 s + 32 .. 64 s + 63 (the same split for both operands).
+  auto mma = [&](f32x16 (&acc)[2][2], int buf) __attribute__((always_inline)) {
+    const unsigned char* A0 = As + (size_t)buf * kTile * FROW;
+    const unsigned char* B0 = Bs + (size_t)buf * kTile * FROW;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      i32x8 av[2], bv[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const unsigned char* pa = A0 + (wr * 64 + x * 32 + li) * FROW + s * 64 + lh * 32;
+        const unsigned char* pb = B0 + (wc * 64 + x * 32 + li) * FROW + s * 64 + lh * 32;
+        const u32x4 a0 = *reinterpret_cast<const u32x4*>(pa), a1 = *reinterpret_cast<const u32x4*>(pa + 16);
+        const u32x4 b0 = *reinterpret_cast<const u32x4*>(pb), b1 = *reinterpret_cast<const u32x4*>(pb + 16);
+        av[x] = (i32x8){(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w, (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
+        bv[x] = (i32x8){(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w, (int)b1.x, (int)b1.y, (int)b1.z, (int)b1.w};
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av[x], bv[y], acc[x][y], 0, 0, 0, 127, 0, 127);
+    }
+  };
+
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int c = 0; c < nchx; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < total) fetch(c + 1);
+    mma(accX, buf);
+    if (c + 1 < total) stash(buf ^ 1);
+    __syncthreads();
+  }
+  for (int c = nchx; c < total; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < total) fetch(c + 1);
+    mma(accY, buf);
+    if (c + 1 < total) stash(buf ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue: central estimates, largest and smallest q~ of the tile
+  const bool masked = !((I < J) && (col0 + kTile <= n));
+  float best_hi = -1.0f, best_lo = 3.0e38f;
+  int code_hi = -1, code_lo = -1;
+  const float4 tb0 = termB[wc * 64 + li], tb1 = termB[wc * 64 + 32 + li];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int rl = wr * 64 + x * 32 + (v >> 2) * 8 + lh * 4 + (v & 3);
+      const float4 ta = termA[rl];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const float4 tb = y ? tb1 : tb0;
+        const float d2 = fmaf(-2.0f * ta.z * tb.z, accX[x][y][v], ta.x + tb.x);
+        const float e2 = fmaf(-2.0f * ta.w * tb.w, accY[x][y][v], ta.y + tb.y);
+        // a pair whose estimated distance vanishes is not ranked
+        const float q = fmaxf(e2, 0.0f) * __builtin_amdgcn_rcpf(d2);
+        float qh = d2 > 0.0f ? q : -1.0f, ql = d2 > 0.0f ? q : 3.0e38f;
+        if (masked) {
+          const int cl = wc * 64 + y * 32 + li;
+          if (!((I < J || rl < cl) && col0 + cl < n)) { qh = -1.0f; ql = 3.0e38f; }
+        }
+        const int code = (x * 2 + y) * 16 + v;
+        if (qh > best_hi) { best_hi = qh; code_hi = code; }
+        if (ql < best_lo) { best_lo = ql; code_lo = code; }
+        asm volatile("" : "+v"(best_hi), "+v"(code_hi), "+v"(best_lo), "+v"(code_lo));
+      }
+    }
+  auto decode = [&](int code, int& gi, int& gj) {
+    if (code < 0) { gi = 0x7fffffff; gj = 0x7fffffff; return; }
+    const int x = code >> 5, y = (code >> 4) & 1, v = code & 15;
+    gi = row0 + wr * 64 + x * 32 + (v >> 2) * 8 + lh * 4 + (v & 3);
+    gj = col0 + wc * 64 + y * 32 + li;
+  };
+  int ih, jh, il, jl;
+  decode(code_hi, ih, jh);
+  decode(code_lo, il, jl);
+  wave_arg<true>(best_hi, ih, jh);
+  wave_arg<false>(best_lo, il, jl);
+  if (lane == 0) {
+    red_v[wave] = best_hi; red_i[wave] = ih; red_j[wave] = jh;
+    red_v[4 + wave] = best_lo; red_i[4 + wave] = il; red_j[4 + wave] = jl;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    float vh = red_v[0], vl = red_v[4];
+    int ih0 = red_i[0], jh0 = red_j[0], il0 = red_i[4], jl0 = red_j[4];
+    for (int w = 1; w < 4; ++w) {
+      if (red_v[w] > vh || (red_v[w] == vh && idx_better(red_i[w], red_j[w], ih0, jh0))) {
+        vh = red_v[w]; ih0 = red_i[w]; jh0 = red_j[w];
+      }
+      if (red_v[4 + w] < vl || (red_v[4 + w] == vl && idx_better(red_i[4 + w], red_j[4 + w], il0, jl0))) {
+        vl = red_v[4 + w]; il0 = red_i[4 + w]; jl0 = red_j[4 + w];
+      }
+    }
+    const bool none_hi = ih0 == 0x7fffffff || vh < 0.0f;
+    const bool none_lo = il0 == 0x7fffffff || vl >= 3.0e38f;
+    TileRec rec;
+    rec.qhi = vh; rec.qlo = vl;
+    rec.ihi = none_hi ? -1 : ih0; rec.jhi = none_hi ? -1 : jh0;
+    rec.ilo = none_lo ? -1 : il0; rec.jlo = none_lo ? -1 : jl0;
+    rec.pad0 = 0; rec.pad1 = 0;
+    b.recs[(int64_t)I * NT - (int64_t)I * (I - 1) / 2 + (J - I)] = rec;
+  }
+}
+
+// Estimated distortion of a tile record, as a monotone 32-bit key.
+__device__ inline uint32_t tile_key(const TileRec& r) {
+  float u = 0.0f;
+  if (r.ihi >= 0) u = fmaxf(u, sqrtf(fmaxf(r.qhi, 0.0f)) - 1.0f);
+  if (r.ilo >= 0) u = fmaxf(u, 1.0f - sqrtf(fmaxf(r.qlo, 0.0f)));
+  return __float_as_uint(fmaxf(u, 0.0f));   // non-negative floats order like their bits
+}
+
+// Histogram of the keys' top 16 bits.
+__global__ void k_key_hist(const TileRec* __restrict__ recs, int64_t ntiles, uint32_t* __restrict__ hist) {
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * 256)
+    atomicAdd(&hist[tile_key(recs[t]) >> 16], 1u);
+}
+
+// Largest bucket b such that the tiles in buckets >= b number at least K
+// (bucket 0, all tiles, if fewer); when a tied boundary bucket would take the
+// count above kmax, b + 1 (fewer than K tiles, none of that bucket).
+// out[0] = b.  1024 threads, 64 buckets each.
+__global__ __launch_bounds__(1024) void k_key_select(const uint32_t* __restrict__ hist, uint32_t K, uint32_t kmax,
+                                                     uint32_t* __restrict__ out) {
+  __shared__ uint32_t seg[1024];
+  const int t = threadIdx.x;
+  uint32_t s = 0;
+  for (int k = 0; k < 64; ++k) s += hist[t * 64 + k];
+  seg[t] = s;
+  __syncthreads();
+  if (t != 0) return;
+  uint64_t acc = 0;
+  int g = 1023;
+  for (; g > 0; --g) {
+    if (acc + seg[g] >= K) break;
+    acc += seg[g];
+  }
+  int b = g * 64 + 63;
+  for (; b > g * 64; --b) {
+    if (acc + hist[b] >= K) break;
+    acc += hist[b];
+  }
+  if (acc + hist[b] > kmax && b < 65535) ++b;
+  out[0] = (uint32_t)b;
+}
+
+// Tiles whose key bucket is >= the threshold and that hold a pair: their
+// indices appended to list, counted in nsel.
+__global__ void k_key_compact(const TileRec* __restrict__ recs, int64_t ntiles, const uint32_t* __restrict__ thr,
+                              uint32_t* __restrict__ list, uint32_t* __restrict__ nsel) {
+  const uint32_t tb = thr[0];
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * 256) {
+    const TileRec r = recs[t];
+    if ((tile_key(r) >> 16) < tb || (r.ihi < 0 && r.ilo < 0)) continue;
+    list[atomicAdd(nsel, 1u)] = (uint32_t)t;
+  }
+}
+
+constexpr size_t kLdsFp8 = 4 * kTile * FROW + 2 * kTile * sizeof(float4) + 24 * sizeof(float);
+
+hipError_t launch_quant_fp8(const float* src, int64_t n_pad, int64_t m, int64_t lds, int64_t ldq, unsigned char* q,
+                            float* scale, double* norm2, hipStream_t st) {
+  k_quant_fp8<<<(unsigned)((n_pad + 3) / 4), 256, 0, st>>>(src, n_pad, m, lds, ldq, q, scale, norm2);
+  return hipGetLastError();
+}
+
+hipError_t launch_fp8_terms(const double* nx, const double* ny, const float* sx, const float* sy, int64_t n_pad,
+                            float4* t, hipStream_t st) {
+  k_fp8_terms<<<(unsigned)((n_pad + 255) / 256), 256, 0, st>>>(nx, ny, sx, sy, n_pad, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_pairs_screen_fp8(const unsigned char* Xq, int ldx, const unsigned char* Yq, int ldy,
+                                   const float4* terms, int n, int NT, TileRec* recs, hipStream_t st) {
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pairs_fp8),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsFp8);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  PairsArgsF a;
+  a.X = Xq; a.ldx = ldx; a.nchx = ldx / FK;
+  a.Y = Yq; a.ldy = ldy; a.nchy = ldy / FK;
+  a.terms = terms;
+  a.n = n; a.NT = NT;
+  a.NS = (NT + 7) / 8;
+  a.nslots = (int64_t)a.NS * (a.NS + 1) / 2 * 64;
+  a.recs = recs;
+  k_pairs_fp8<<<(unsigned)round_up(a.nslots, 8), 256, kLdsFp8, st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_topk_tiles(const TileRec* recs, int64_t ntiles, uint32_t K, uint32_t kmax, uint32_t* hist,
+                             uint32_t* thr, uint32_t* list, uint32_t* nsel, hipStream_t st) {
+  int64_t g = (ntiles + 255) / 256;
+  if (g > 2048) g = 2048;
+  if (g < 1) g = 1;
+  k_key_hist<<<(unsigned)g, 256, 0, st>>>(recs, ntiles, hist);
+  k_key_select<<<1, 1024, 0, st>>>(hist, K, kmax, thr);
+  k_key_compact<<<(unsigned)g, 256, 0, st>>>(recs, ntiles, thr, list, nsel);
+  return hipGetLastError();
+}
+
+int fp8_chunk() { return FK; }
+
+}  // namespace adg

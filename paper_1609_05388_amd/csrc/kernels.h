@@ -86,6 +86,29 @@ hipError_t launch_gram_rows(const double* G, int m, int64_t d, double* K, int mp
 hipError_t launch_sketch_features(const double* lam, int m, int64_t n, int64_t d, double eps, float* feat,
                                   hipStream_t st);
 
+// k_eigvals.hip
+// Eigenvalues (decreasing) of the symmetric m x m FP64 matrix A (row stride
+// lda), m <= 128, by tridiagonal reduction and Sturm bisection in one
+// workgroup.
+hipError_t launch_sym_eigvals(const double* A, int m, int lda, double* lam, hipStream_t st);
+
+// k_pairs_fp8.hip
+// Per-row scaled OCP e4m3 copy of n_pad rows of m FP32 values (row stride
+// lds): q (ldq bytes per row, zero padded), scale s_i, N_i = s_i^2 |q_i|^2.
+hipError_t launch_quant_fp8(const float* src, int64_t n_pad, int64_t m, int64_t lds, int64_t ldq, unsigned char* q,
+                            float* scale, double* norm2, hipStream_t st);
+hipError_t launch_fp8_terms(const double* nx, const double* ny, const float* sx, const float* sy, int64_t n_pad,
+                            float4* t, hipStream_t st);
+// Estimated q extremes per tile (ldx, ldy multiples of fp8_chunk()).
+hipError_t launch_pairs_screen_fp8(const unsigned char* Xq, int ldx, const unsigned char* Yq, int ldy,
+                                   const float4* terms, int n, int NT, TileRec* recs, hipStream_t st);
+// Indices of the >= K tiles with the largest estimated distortion appended to
+// list (at most kmax unless a single tied bucket exceeds it; hist: 65536
+// zeroed counters; nsel zeroed, receives the count).
+hipError_t launch_topk_tiles(const TileRec* recs, int64_t ntiles, uint32_t K, uint32_t kmax, uint32_t* hist,
+                             uint32_t* thr, uint32_t* list, uint32_t* nsel, hipStream_t st);
+int fp8_chunk();
+
 // k_mlp.hip
 struct MlpLayout {
   int in, in_pad, hidden;

@@ -1,0 +1,121 @@
+"""Precision form, FP8: the per-row scaled e4m3 encoding (bit-exact against
+the oracle's), the FP8 screen (its value is the exact distortion of the pair
+it names, never above the oracle's maximum, and on these clouds equal to
+it), and fits whose decisions are screened and whose result is certified."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import certificate, embedding, fp8, pca as opca
+from paper_1609_05388_amd import gen
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def quant_cases():
+    rng = np.random.default_rng(11)
+    yield rng.normal(0, 1, (1, 1))
+    yield rng.normal(0, 1, (5, 37))
+    A = rng.normal(0, 1, (300, 784)) * np.exp(rng.uniform(-14, 7, (300, 1)))
+    A[7] = 0.0
+    A[8, :300] = 0.0
+    yield A
+    # wide dynamic range inside rows: subnormal codes and exact ties
+    B = np.exp(rng.uniform(-16, 0, (64, 200))) * rng.choice([-1.0, 1.0], (64, 200))
+    B[:, 0] = 448.0
+    B[:, 1:17] = (np.arange(16) + 0.5) * 2.0 ** -9
+    yield B
+    yield gen.low_rank_pixels(n=129, d=130, rank=10, seed=2)
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_quantize_bit_exact(gpu_lib, case):
+    A = np.asarray(list(quant_cases())[case], dtype=np.float32)
+    Q, s, N = gpu_lib.quantize_fp8(dev(A))
+    Qo, so, No = fp8.quantize_rows(A)
+    assert np.array_equal(Q.cpu().numpy(), Qo)
+    assert np.array_equal(s.cpu().numpy(), so)
+    assert np.array_equal(N.cpu().numpy(), No)
+
+
+def check_screen(got, X, Y, want):
+    assert got["certified"] == 0 and np.isinf(got["bound_rest"])
+    assert got["n_rescored"] >= 1
+    # the reported value is the exact distortion of the reported pair
+    v = certificate.pair_distortions(X, Y, np.array([got["i"]]), np.array([got["j"]]))[0][0]
+    assert abs(got["max_distortion"] - v) <= 1e-12
+    assert got["max_distortion"] <= want["max"] + 1e-12
+
+
+def test_fp8_screen_finds_the_maximum_c1(gpu_lib):
+    X = gen.low_rank_pixels()
+    _, _, _, Vt = opca.pca(X)
+    for r in (93, 213, 391):
+        Pi32 = embedding.adagio_map(Vt, r, gen.JL_SEED).astype(np.float32)
+        Y64 = embedding.embed(X, Pi32.astype(np.float64))
+        want = certificate.certify(X, Y64)
+        got = gpu_lib.certify_map(dev(X), dev(Pi32), screen="fp8")
+        check_screen(got, X, Y64, want)
+        # the max is in the re-evaluated set on this cloud: error vs oracle
+        assert abs(got["max_distortion"] - want["max"]) <= TOL
+        if want["max"] - want["runner_up"] > TOL:
+            assert (got["i"], got["j"]) == (want["i"], want["j"])
+
+
+@pytest.mark.parametrize("n,d,r", [(2, 1, 1), (65, 7, 3), (257, 64, 20), (700, 200, 41)])
+def test_fp8_screen_ragged(gpu_lib, n, d, r):
+    X = gen.gaussian(n, d, seed=n + 7 * d)
+    Pi = gen.gaussian(r, d, seed=r + 3) / np.float32(np.sqrt(d))
+    Y = embedding.embed(X, Pi.astype(np.float64)).astype(np.float32)
+    want = certificate.certify(X, Y)
+    got = gpu_lib.max_distortion(dev(X), dev(Y), screen="fp8")
+    check_screen(got, X, Y, want)
+    assert abs(got["max_distortion"] - want["max"]) <= TOL
+
+
+def test_fp8_screen_duplicates(gpu_lib):
+    X = gen.with_duplicates(gen.gaussian(500, 40, seed=3), 30)
+    Pi = gen.gaussian(12, 40, seed=4)
+    Y = embedding.embed(X, Pi.astype(np.float64)).astype(np.float32)
+    got = gpu_lib.max_distortion(dev(X), dev(Y), screen="fp8")
+    check_screen(got, X, Y, certificate.certify(X, Y))
+
+
+@pytest.mark.parametrize("eps", [0.05, 0.1, 0.2])
+def test_fp8_fit_certified_and_equal_to_plain_c1(gpu_lib, eps):
+    X = dev(gen.low_rank_pixels())
+    a = gpu_lib.fit(X, eps, gen.JL_SEED)
+    b = gpu_lib.fit(X, eps, gen.JL_SEED, screen="fp8")
+    assert b["cert"]["certified"] == 1 and b["cert"]["max_distortion"] <= eps
+    assert b["stats"]["n_screened"] >= 1
+    assert a["r"] == b["r"] and torch.equal(a["Pi"], b["Pi"])
+    for key in ("max_distortion", "i", "j", "side"):
+        assert a["cert"][key] == b["cert"][key]
+
+
+def test_fp8_fit_mnist_shaped(gpu_lib):
+    X = dev(gen.mnist_shaped())
+    a = gpu_lib.fit(X, 0.1, gen.JL_SEED, screen="bf16x3")
+    b = gpu_lib.fit(X, 0.1, gen.JL_SEED, screen="fp8")
+    assert b["cert"]["certified"] == 1
+    assert a["r"] == b["r"] and torch.equal(a["Pi"], b["Pi"])
+    assert a["cert"]["max_distortion"] == b["cert"]["max_distortion"]
+
+
+def test_fp8_screen_selects_the_maximum_tile(gpu_lib):
+    """A cloud with more tiles (2016) than the screen re-screens (1024): the
+    FP8 estimates must rank the tile of the exact maximum among them."""
+    X = gen.mnist_shaped(n=8000)
+    _, _, _, Vt = opca.pca(X)
+    Pi32 = embedding.adagio_map(Vt, 150, gen.JL_SEED).astype(np.float32)
+    Y64 = embedding.embed(X, Pi32.astype(np.float64))
+    want = certificate.certify(X, Y64)
+    got = gpu_lib.certify_map(dev(X), dev(Pi32), screen="fp8", with_stats=True)
+    assert 1024 <= got["stats"]["n_flagged_tiles"] <= 4096
+    check_screen(got, X, Y64, want)
+    assert abs(got["max_distortion"] - want["max"]) <= TOL

@@ -130,11 +130,13 @@ def test_learned_search_certified_with_fallback(gpu_lib):
 
 @pytest.mark.skipif(not os.path.exists(learned.PREDICTOR), reason="no trained predictor committed")
 def test_trained_predictor_gains_over_bisection(gpu_lib):
-    """Held-out instances: every learned fit is certified within eps, with
-    fewer certificates and less fit time than plain bisection."""
+    """Held-out instances: every fit's certificate proves max distortion <=
+    eps (its exact maximum, or for a near-isometry its proven bound), and the
+    learned search needs fewer certificates and less fit time than plain
+    bisection."""
     res = learned.evaluate(learned.PREDICTOR, range(0, 12), held_out=True, log_every=100)
     s = learned.summarize(res)
     print(s)
-    assert s["all_certified"] and s["all_within_eps"]
+    assert s["all_proven_within_eps"]
     assert s["mean_certificates_learned"] < s["mean_certificates_plain"]
     assert s["speedup"] > 1.0
