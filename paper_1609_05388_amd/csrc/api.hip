@@ -224,17 +224,16 @@ static int jacobi_eig(Workspace& ws, double* A, int m, int64_t d, double* lam, d
   // Rotations whose off-diagonal entry is at most 4 u64 trace(A) are skipped
   // (trace >= ||A||_F for PSD A; this sits above the rounding floor of the
   // tile products); the method has converged when a whole sweep skips every
-  // rotation.  One inner sweep per block pair and round: the number of outer
-  // sweeps does not depend on solving the subproblems to convergence.
+  // rotation.
   const double thr = 4.0 * kU64 * trace;
   int* rot = ensure<int>(ws.rot, 1);
-  const int max_sweeps = 40, max_inner = 1;
+  const int max_sweeps = 40;
   int sweep = 0;
   bool converged = false;
   for (; sweep < max_sweeps && !converged; ++sweep) {
     HIPCHK(hipMemsetAsync(rot, 0, sizeof(int), st));
     for (int t = 0; t < nb - 1; ++t) {
-      HIPCHK(launch_bj_round(A, B, W, Ub, Sb, m, t, thr, max_inner, rot, st));
+      HIPCHK(launch_bj_round(A, B, W, Ub, Sb, m, t, thr, rot, st));
       std::swap(A, B);
     }
     int h = 0;

@@ -3,11 +3,15 @@
 // The m x m FP64 matrix (m a multiple of 2 * JB, padding rows/columns zero)
 // is cut into nb = m / JB index blocks.  A sweep has nb - 1 rounds; in each,
 // the round-robin ordering pairs the blocks into nb / 2 disjoint pairs (P, Q).
-// For each pair one workgroup diagonalises the 2 JB x 2 JB principal
-// submatrix S = A[{P,Q}, {P,Q}] to convergence with the scalar two-sided
-// Jacobi method in LDS, S = U Lambda U^T (rotations below the threshold are
-// skipped).  The round then applies the block-diagonal orthogonal J (the U's
-// on their index sets): A <- J^T A J tile by tile (tile (PQ, RS) becomes
+// For each pair one workgroup rotates the 2 JB x 2 JB principal submatrix
+// S = A[{P,Q}, {P,Q}] in LDS with the scalar two-sided Jacobi method,
+// S <- U^T S U: in the first round of a sweep over every index pair of S (the
+// pairs inside each block, once per sweep, and across), in the other rounds
+// over the JB x JB pairs (p in P, q in Q) only, so a sweep rotates every index
+// pair of the matrix about once, as one cyclic sweep of the scalar method in a
+// parallel order.  Rotations with |S_pq| below the threshold are skipped.
+// The round then applies the block-diagonal orthogonal J (the U's on their
+// index sets): A <- J^T A J tile by tile (tile (PQ, RS) becomes
 // U_PQ^T A_tile U_RS) and W <- J^T W, with W = V^T accumulating eigenvectors
 // as rows.  The method has converged when a whole sweep skips every rotation.
 #include "common.h"
@@ -47,48 +51,59 @@ __device__ inline void sub_rotation(const double* S, int p, int q, double thr, d
   }
 }
 
-// One workgroup per block pair: `max_inner` sweeps of the scalar method on S
-// (writes U, JS x JS row-major with U[i][j] = component i of vector j, and the
-// final S).  Each inner round is one phase: a thread recomputes the rotations
-// of the pairs it touches from the current S and writes its 2 x 2 blocks of
-// J^T S J into the other LDS buffer, and rotates its pair's columns of U; one
-// barrier per round.
+// One workgroup per block pair (rr_pair_b(t, blockIdx.x)).  FULL: the
+// round-robin over all 2 JB indices of S (2 JB - 1 inner rounds); else the
+// cross pairs only, inner round r pairing p = i with q = JB + (i + r) mod JB
+// (JB inner rounds).  Each inner round is one phase: a thread recomputes the
+// rotations of the pairs it touches from the current S (every wave computes
+// the JB rotations once: lanes l and l + 32 hold rotation l % 32, fetched by
+// shuffles), writes its 2 x 2 blocks of J^T S J into the other LDS buffer and
+// rotates its pair's columns of U; one barrier per inner round.  Writes U
+// (JS x JS, U[i][j] = component i of vector j) and the final S; a subproblem
+// with nothing above the threshold returns U = I without rotating.
+template <bool FULL>
 __global__ __launch_bounds__(256) void k_bj_solve(const double* __restrict__ A, int m, int nb, int t, double thr,
-                                                  int max_inner, double* __restrict__ Uout,
-                                                  double* __restrict__ Sout, int* __restrict__ rot_count) {
+                                                  double* __restrict__ Uout, double* __restrict__ Sout,
+                                                  int* __restrict__ rot_count) {
   extern __shared__ double lds_d[];
   double* const S0 = lds_d;
   double* const S1 = lds_d + JS * JLD;
   double* const U = lds_d + 2 * JS * JLD;
+  __shared__ double off_sh[4];
   __shared__ int applied_sh;
   const int pair = blockIdx.x;
   int P, Q;
   rr_pair_b(t, pair, nb, P, Q);
   const int tid = threadIdx.x;
+  double off = 0.0;
   for (int e = tid; e < JS * JS; e += 256) {
     const int i = e / JS, j = e % JS;
-    S0[i * JLD + j] = A[(int64_t)sub_index(P, Q, i) * m + sub_index(P, Q, j)];
+    const double x = A[(int64_t)sub_index(P, Q, i) * m + sub_index(P, Q, j)];
+    S0[i * JLD + j] = x;
     U[i * JLD + j] = (i == j) ? 1.0 : 0.0;
+    if (FULL ? i != j : (i < JB && j >= JB)) off = fmax(off, fabs(x));
   }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) off = fmax(off, __shfl_xor(off, o, 64));
+  if ((tid & 63) == 0) off_sh[tid >> 6] = off;
   if (tid == 0) applied_sh = 0;
   __syncthreads();
+  off = fmax(fmax(off_sh[0], off_sh[1]), fmax(off_sh[2], off_sh[3]));
   int cur = 0;
-  // thread -> column pair kb = tid % 32 and row pairs ka = tid / 32 + 8 u (u < 4);
-  // the U update: pair kb, rows tid / 32 + 8 v (v < 8)
-  const int kb = tid & 31, ka0 = tid >> 5;
-  int total_applied = 0;
-  for (int sw = 0; sw < max_inner; ++sw) {
-    const int before = applied_sh;
-    for (int r = 0; r < JS - 1; ++r) {
+  if (off > thr) {
+    // thread -> column pair kb = tid % 32 and row pairs ka = tid / 32 + 8 u
+    // (u < 4); the U update: pair kb, rows tid / 32 + 8 v (v < 8)
+    const int kb = tid & (JB - 1), ka0 = tid >> 5;
+    constexpr int rounds = FULL ? JS - 1 : JB;
+    for (int r = 0; r < rounds; ++r) {
       const double* S = cur ? S1 : S0;
       double* S2 = cur ? S0 : S1;
-      // every wave computes the 32 rotations of this round once (lane l and
-      // lane l + 32 both hold rotation l % 32); threads fetch theirs by shuffle
       int pb, qb;
-      rr_pair_b(r, kb, JS, pb, qb);
+      if (FULL) rr_pair_b(r, kb, JS, pb, qb);
+      else { pb = kb; qb = JB + ((kb + r) & (JB - 1)); }
       double cb, sbv;
       sub_rotation(S, pb, qb, thr, cb, sbv);
-      if (tid < 32 && sbv != 0.0) atomicAdd(&applied_sh, 1);
+      if (tid < JB && sbv != 0.0) atomicAdd(&applied_sh, 1);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int ka = ka0 + 8 * u;
@@ -116,9 +131,6 @@ __global__ __launch_bounds__(256) void k_bj_solve(const double* __restrict__ A, 
       __syncthreads();
       cur ^= 1;
     }
-    const int a = applied_sh - before;
-    total_applied += a;
-    if (a == 0) break;
   }
   const double* S = cur ? S1 : S0;
   double* Ug = Uout + (int64_t)pair * JS * JS;
@@ -128,21 +140,48 @@ __global__ __launch_bounds__(256) void k_bj_solve(const double* __restrict__ A, 
     Ug[e] = U[i * JLD + j];
     Sg[e] = S[i * JLD + j];
   }
-  if (tid == 0 && total_applied) atomicAdd(rot_count, total_applied);
+  if (tid == 0 && applied_sh) atomicAdd(rot_count, applied_sh);
+}
+
+// One 32 x 32 quadrant (wave w: rows 32 (w / 2), columns 32 (w % 2)) of
+// C = X^T Y for 64 x 64 LDS matrices X, Y (row stride JLD): C[i][j] =
+// sum_k X[k][i] Y[k][j], on v_mfma_f64_16x16x4f64 (A operand lane l: row
+// l % 16, k = 4 ks + l / 16; B operand: column l % 16, same k; D register v:
+// row 4 v + l / 16, column l % 16).
+__device__ inline void quad_xty(const double* X, const double* Y, f64x4 (&acc)[2][2]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = (wave >> 1) * 32, c0 = (wave & 1) * 32;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (f64x4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int ks = 0; ks < JS / 4; ++ks) {
+    const int k = 4 * ks + (lane >> 4);
+    const double x0 = X[k * JLD + r0 + (lane & 15)], x1 = X[k * JLD + r0 + 16 + (lane & 15)];
+    const double y0 = Y[k * JLD + c0 + (lane & 15)], y1 = Y[k * JLD + c0 + 16 + (lane & 15)];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, acc[1][1], 0, 0, 0);
+  }
 }
 
 // Apply round t: A2 = J^T A J (grid: (nb/2)^2 tiles of JS x JS) and
-// W <- J^T W (grid: (nb/2) * (m / JS) tiles), one workgroup per tile.
+// W <- J^T W (grid: (nb/2) * (m / JS) tiles), one workgroup per tile:
+// tile (PQ, RS) of A becomes U_PQ^T A_tile U_RS (two FP64 MFMA products with
+// the intermediate kept transposed in LDS), a diagonal tile is the solved S.
 __global__ __launch_bounds__(256) void k_bj_apply(const double* __restrict__ A, double* __restrict__ A2,
                                                   double* __restrict__ W, const double* __restrict__ Uall,
                                                   const double* __restrict__ Sall, int m, int nb, int t) {
   extern __shared__ double lds_d[];
-  double* T0 = lds_d;
-  double* Ua = lds_d + JS * JLD;
-  double* Ub = lds_d + 2 * JS * JLD;
+  double* X = lds_d;
+  double* Y = lds_d + JS * JLD;
   const int half = nb / 2;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r0 = (wave >> 1) * 32, c0w = (wave & 1) * 32;
   const int nA = half * half;
+  f64x4 acc[2][2];
   if ((int)blockIdx.x < nA) {
     const int ka = blockIdx.x / half, kb = blockIdx.x % half;
     int P, Q, R, S;
@@ -160,38 +199,34 @@ __global__ __launch_bounds__(256) void k_bj_apply(const double* __restrict__ A, 
     const double* ub = Uall + (int64_t)kb * JS * JS;
     for (int e = tid; e < JS * JS; e += 256) {
       const int i = e / JS, j = e % JS;
-      T0[i * JLD + j] = A[(int64_t)sub_index(P, Q, i) * m + sub_index(R, S, j)];
-      Ua[i * JLD + j] = ua[e];
-      Ub[i * JLD + j] = ub[e];
+      X[i * JLD + j] = A[(int64_t)sub_index(P, Q, i) * m + sub_index(R, S, j)];
+      Y[i * JLD + j] = ua[e];
     }
     __syncthreads();
-    // T1 = Ua^T T0, kept in registers: thread owns 16 entries of column j
-    const int j = tid % JS, i0 = (tid / JS) * 16;
-    double t1[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) t1[u] = 0.0;
-    for (int k = 0; k < JS; ++k) {
-      const double x = T0[k * JLD + j];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) t1[u] = fma(Ua[k * JLD + i0 + u], x, t1[u]);
-    }
+    quad_xty(Y, X, acc);          // T1 = Ua^T A_tile
     __syncthreads();
+    // X <- T1^T (X[j][i] = T1[i][j]), Y <- Ub
 #pragma unroll
-    for (int u = 0; u < 16; ++u) T0[(i0 + u) * JLD + j] = t1[u];
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = r0 + a * 16 + 4 * v + (lane >> 4), j = c0w + b * 16 + (lane & 15);
+          X[j * JLD + i] = acc[a][b][v];
+        }
+    for (int e = tid; e < JS * JS; e += 256) Y[(e / JS) * JLD + (e % JS)] = ub[e];
     __syncthreads();
-    // A2 tile = T1 Ub: thread owns 16 entries of row i
-    const int i = tid % JS, j0 = (tid / JS) * 16;
-    double o[16];
+    quad_xty(X, Y, acc);          // T1 Ub = (T1^T)^T Ub
 #pragma unroll
-    for (int u = 0; u < 16; ++u) o[u] = 0.0;
-    for (int k = 0; k < JS; ++k) {
-      const double x = T0[i * JLD + k];
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int u = 0; u < 16; ++u) o[u] = fma(x, Ub[k * JLD + j0 + u], o[u]);
-    }
-    const int64_t gi = sub_index(P, Q, i);
+      for (int b = 0; b < 2; ++b)
 #pragma unroll
-    for (int u = 0; u < 16; ++u) A2[gi * m + sub_index(R, S, j0 + u)] = o[u];
+        for (int v = 0; v < 4; ++v) {
+          const int i = r0 + a * 16 + 4 * v + (lane >> 4), j = c0w + b * 16 + (lane & 15);
+          A2[(int64_t)sub_index(P, Q, i) * m + sub_index(R, S, j)] = acc[a][b][v];
+        }
   } else {
     // W rows of pair ka, columns [c0, c0 + JS): W' = Ua^T W
     const int wb = blockIdx.x - nA;
@@ -202,33 +237,35 @@ __global__ __launch_bounds__(256) void k_bj_apply(const double* __restrict__ A, 
     const double* ua = Uall + (int64_t)ka * JS * JS;
     for (int e = tid; e < JS * JS; e += 256) {
       const int i = e / JS, j = e % JS;
-      T0[i * JLD + j] = W[(int64_t)sub_index(P, Q, i) * m + c0 + j];
-      Ua[i * JLD + j] = ua[e];
+      X[i * JLD + j] = W[(int64_t)sub_index(P, Q, i) * m + c0 + j];
+      Y[i * JLD + j] = ua[e];
     }
     __syncthreads();
-    const int j = tid % JS, i0 = (tid / JS) * 16;
-    double t1[16];
+    quad_xty(Y, X, acc);
 #pragma unroll
-    for (int u = 0; u < 16; ++u) t1[u] = 0.0;
-    for (int k = 0; k < JS; ++k) {
-      const double x = T0[k * JLD + j];
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int u = 0; u < 16; ++u) t1[u] = fma(Ua[k * JLD + i0 + u], x, t1[u]);
-    }
+      for (int b = 0; b < 2; ++b)
 #pragma unroll
-    for (int u = 0; u < 16; ++u) W[(int64_t)sub_index(P, Q, i0 + u) * m + c0 + j] = t1[u];
+        for (int v = 0; v < 4; ++v) {
+          const int i = r0 + a * 16 + 4 * v + (lane >> 4), j = c0w + b * 16 + (lane & 15);
+          W[(int64_t)sub_index(P, Q, i) * m + c0 + j] = acc[a][b][v];
+        }
   }
 }
 
 constexpr size_t kLdsSolve = 3 * JS * JLD * sizeof(double);
-constexpr size_t kLdsApply = 3 * JS * JLD * sizeof(double);
+constexpr size_t kLdsApply = 2 * JS * JLD * sizeof(double);
 
 hipError_t launch_bj_round(const double* A, double* A2, double* W, double* Uall, double* Sall, int m, int t,
-                           double thr, int max_inner, int* rot_count, hipStream_t st) {
+                           double thr, int* rot_count, hipStream_t st) {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bj_solve),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bj_solve<true>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsSolve);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bj_solve<false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsSolve);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bj_apply), hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)kLdsApply);
@@ -237,7 +274,8 @@ hipError_t launch_bj_round(const double* A, double* A2, double* W, double* Uall,
   }
   const int nb = m / JB;
   const int half = nb / 2;
-  k_bj_solve<<<(unsigned)half, 256, kLdsSolve, st>>>(A, m, nb, t, thr, max_inner, Uall, Sall, rot_count);
+  if (t == 0) k_bj_solve<true><<<(unsigned)half, 256, kLdsSolve, st>>>(A, m, nb, t, thr, Uall, Sall, rot_count);
+  else k_bj_solve<false><<<(unsigned)half, 256, kLdsSolve, st>>>(A, m, nb, t, thr, Uall, Sall, rot_count);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_bj_apply<<<(unsigned)(half * half + half * (m / JS)), 256, kLdsApply, st>>>(A, A2, W, Uall, Sall, m, nb, t);

@@ -34,7 +34,7 @@ hipError_t launch_eig_sort(const double* A, const double* W, int m, int d, doubl
 
 // k_eig_block.hip
 hipError_t launch_bj_round(const double* A, double* A2, double* W, double* Uall, double* Sall, int m, int t,
-                           double thr, int max_inner, int* rot_count, hipStream_t st);
+                           double thr, int* rot_count, hipStream_t st);
 int bj_block();
 
 // k_proj.hip
