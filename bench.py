@@ -33,7 +33,7 @@ PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_FP8_MFMA_TFLOPS = 5000.0
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 PAIRS_KERNEL_SRC = os.path.join(ROOT, "paper_1609_05388_amd", "csrc", "k_pairs.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pairs_f32_mnist60k_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pairs_f32_mnist60k_traffic.txt")
 
 
 def log(*a):
@@ -93,7 +93,8 @@ def summarize_traffic(d):
         "fetch": out["FETCH_SIZE"], "write": out["WRITE_SIZE"],
         "commands": [
             "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d <repo>/gpurun_out/pmc -o copy_FETCH_SIZE -- python3 <repo>/bench.py --calib-copy-mib 1024",
-            "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d <repo>/gpurun_out/pmc -o fit_FETCH_SIZE -- python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extra-eps",
+            "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d <repo>/gpurun_out/pmc -o fit_FETCH_SIZE -- python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extra-eps --no-forms --no-large",
+            "python3 <repo>/bench.py --summarize-traffic <repo>/gpurun_out/pmc",
             "(the same two with WRITE_SIZE)",
         ],
         "note": "counter bytes are KiB x 1024 per dispatch, averaged over the screen launches of one fit "
