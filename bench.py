@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_FP8_MFMA_TFLOPS = 5000.0
 PEAK_BF16_MFMA_TFLOPS = 2500.0
-PAIRS_KERNEL_SRC = os.path.join(ROOT, "paper_1609_05388_amd", "csrc", "k_pairs.hip")
+PAIRS_KERNEL_SRC = [os.path.join(ROOT, "paper_1609_05388_amd", "csrc", f) for f in ("k_pairs.hip", "pairs_common.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pairs_f32_mnist60k_traffic.txt")
 
 
@@ -40,20 +40,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def source_hash(path):
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+def source_hash():
+    """Hash of the screen kernel's sources (the traffic figures go stale when they change)."""
+    h = hashlib.sha256()
+    for path in PAIRS_KERNEL_SRC:
+        h.update(open(path, "rb").read())
+    return h.hexdigest()
 
 
-def traffic_per_launch():
-    """HBM bytes per screen launch from the committed rocprofv3 counter runs,
-    or None when absent or taken on a different kernel source."""
+def traffic_per_launch(kind):
+    """HBM bytes per screen launch of one kind ("full": the first certificate
+    of a fit, point Gram computed and stored; "cached": the others) from the
+    committed rocprofv3 counter runs, or None when absent or taken on other
+    kernel sources."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256") != source_hash(PAIRS_KERNEL_SRC):
+    if rec.get("kernel_source_sha256") != source_hash():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec.get("hbm_bytes_per_launch", {}).get(kind)
 
 
 TRAFFIC_KERNEL = "adg::k_pairs_f32<0>"
@@ -62,44 +68,50 @@ COPY_BYTES = 1 << 30
 
 
 def per_kernel(path):
-    """Counter bytes (KiB x 1024) per dispatch, grouped by kernel name."""
+    """Counter bytes (KiB x 1024) per dispatch in dispatch order, by kernel name."""
     agg = collections.defaultdict(list)
-    for r in csv.DictReader(open(path)):
+    rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Dispatch_Id"]))
+    for r in rows:
         agg[r["Kernel_Name"]].append(float(r["Counter_Value"]) * 1024.0)
     return agg
 
 
 def pick(agg, key):
-    vals = [v for k, vs in agg.items() if key in k for v in vs]
-    return sum(vals) / len(vals), len(vals)
+    return [v for k, vs in agg.items() if key in k for v in vs]
 
 
 def summarize_traffic(d):
     """HBM bytes per screen launch from two rocprofv3 --pmc runs (FETCH_SIZE,
-    WRITE_SIZE) of this script and of its 1 GiB copy calibration, each counter
-    scaled by the factor that maps its copy reading to 1 GiB."""
+    WRITE_SIZE) of one plain fit and of the 1 GiB copy calibration, each
+    counter scaled by the factor that maps its copy reading to 1 GiB.  The
+    fit's first screen launch computes and stores the point Gram ("full"),
+    the others load it ("cached")."""
     out = {}
     for c in ("FETCH_SIZE", "WRITE_SIZE"):
-        copy_b, _ = pick(per_kernel(os.path.join(d, "copy_%s_counter_collection.csv" % c)), COPY_KERNEL)
-        kern_b, nl = pick(per_kernel(os.path.join(d, "fit_%s_counter_collection.csv" % c)), TRAFFIC_KERNEL)
-        factor = COPY_BYTES / copy_b
-        out[c] = {"copy_counter_bytes": copy_b, "factor": factor, "kernel_counter_bytes_per_launch": kern_b,
-                  "kernel_bytes_per_launch": kern_b * factor, "launches": nl}
-    src = os.path.join(ROOT, "paper_1609_05388_amd", "csrc", "k_pairs.hip")
+        copy = pick(per_kernel(os.path.join(d, "copy_%s_counter_collection.csv" % c)), COPY_KERNEL)
+        kern = pick(per_kernel(os.path.join(d, "fit_%s_counter_collection.csv" % c)), TRAFFIC_KERNEL)
+        factor = COPY_BYTES / (sum(copy) / len(copy))
+        out[c] = {"copy_counter_bytes": sum(copy) / len(copy), "factor": factor,
+                  "full_launch_bytes": kern[0] * factor,
+                  "cached_launch_bytes": (sum(kern[1:]) / len(kern[1:]) * factor) if len(kern) > 1 else None,
+                  "launches": len(kern)}
+    hb = {"full": out["FETCH_SIZE"]["full_launch_bytes"] + out["WRITE_SIZE"]["full_launch_bytes"]}
+    if out["FETCH_SIZE"]["cached_launch_bytes"] is not None:
+        hb["cached"] = out["FETCH_SIZE"]["cached_launch_bytes"] + out["WRITE_SIZE"]["cached_launch_bytes"]
     rec = {
         "kernel": TRAFFIC_KERNEL,
-        "kernel_source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
-        "hbm_bytes_per_launch": out["FETCH_SIZE"]["kernel_bytes_per_launch"] + out["WRITE_SIZE"]["kernel_bytes_per_launch"],
+        "kernel_source_sha256": source_hash(),
+        "hbm_bytes_per_launch": hb,
         "fetch": out["FETCH_SIZE"], "write": out["WRITE_SIZE"],
         "commands": [
             "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d <repo>/gpurun_out/pmc -o copy_FETCH_SIZE -- python3 <repo>/bench.py --calib-copy-mib 1024",
             "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d <repo>/gpurun_out/pmc -o fit_FETCH_SIZE -- python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extra-eps --no-forms --no-large",
-            "python3 <repo>/bench.py --summarize-traffic <repo>/gpurun_out/pmc",
             "(the same two with WRITE_SIZE)",
+            "python3 <repo>/bench.py --summarize-traffic <repo>/gpurun_out/pmc",
         ],
-        "note": "counter bytes are KiB x 1024 per dispatch, averaged over the screen launches of one fit "
-                "(10 launches, r from the bisection); each counter is scaled by the factor that maps its "
-                "reading for a plain 1 GiB copy to 1 GiB",
+        "note": "counter bytes are KiB x 1024 per dispatch; one fit: its first screen launch (point Gram "
+                "computed and stored) and the mean of the others (point Gram loaded); each counter is scaled "
+                "by the factor that maps its reading for a plain 1 GiB copy to 1 GiB",
     }
     print(json.dumps(rec, indent=1))
 
@@ -131,6 +143,12 @@ def cpu_baseline(X, Pi, target_s):
                       % (m2, c["n_pairs"], dt)}
 
 
+def screen_flops(npairs, d, r, gram):
+    """Algorithmic flops of one screen launch: both Grams (2(d + r) per pair),
+    or the image Gram only (2r) when the point Gram came from the cache."""
+    return npairs * 2.0 * (r if gram == 2 else d + r)
+
+
 def timed_fits(adagio, torch, Xd, eps, seed, steps, **kw):
     adagio.fit(Xd, eps, seed, **kw)             # buffers and first-call set-up
     torch.cuda.synchronize()
@@ -146,9 +164,9 @@ def fp8_form(adagio, gen, torch, Xd, eps, steps, plain_s, plain, npairs, d):
     fs, outs = timed_fits(adagio, torch, Xd, eps, gen.JL_SEED, steps, screen="fp8")
     o = outs[-1]
     st = o["stats"]
-    scr = [(r, t) for r, t in zip(st["probe_r"], st["probe_screen_ms"])][:st["n_screened"]]
-    fl = sum(npairs * 2.0 * (d + r) for r, _ in scr)
-    ms = sum(t for _, t in scr)
+    scr = list(zip(st["probe_r"], st["probe_screen_ms"], st["probe_gram"]))[:st["n_screened"]]
+    fl = sum(screen_flops(npairs, d, r, g) for r, _, g in scr)
+    ms = sum(t for _, t, _ in scr)
     return {"fit_ms": fs * 1e3, "speedup_vs_plain": plain_s / fs, "r": o["r"],
             "max_distortion": o["cert"]["max_distortion"], "certified": o["cert"]["certified"],
             "abs_err_vs_plain_fp64_certificate": abs(o["cert"]["max_distortion"] - plain["cert"]["max_distortion"]),
@@ -193,14 +211,14 @@ def large_form(adagio, gen, torch, eps):
     st = o["stats"]
     n, d = Xd.shape
     npairs = n * (n - 1) // 2
-    scr = list(zip(st["probe_r"], st["probe_delta"], st["probe_screen_ms"]))
+    scr = list(zip(st["probe_r"], st["probe_delta"], st["probe_screen_ms"], st["probe_gram"]))
     fp8 = scr[:st["n_screened"]]
     rig = scr[st["n_screened"]:]
-    fl = sum(npairs * 2.0 * (d + r) for r, _, _ in fp8)
-    ms = sum(t for _, _, t in fp8)
-    bfl = sum(npairs * 2.0 * (d + r) for r, _, _ in rig)
-    bms = sum(t for _, _, t in rig)
-    same_r = [dl for r, dl, _ in fp8 if r == o["r"]]
+    fl = sum(screen_flops(npairs, d, r, g) for r, _, _, g in fp8)
+    ms = sum(t for _, _, t, _ in fp8)
+    bfl = sum(screen_flops(npairs, d, r, g) for r, _, _, g in rig)
+    bms = sum(t for _, _, t, _ in rig)
+    same_r = [dl for r, dl, _, _ in fp8 if r == o["r"]]
     plain = adagio.certify_map(Xd, o["Pi"].contiguous(), screen="f32", with_stats=True)
     pst = plain.pop("stats")
     del Xd
@@ -221,7 +239,7 @@ def large_form(adagio, gen, torch, eps):
                                          "screen_tflops": npairs * 2.0 * (d + o["r"]) / pst["t_screen_ms"] / 1e9,
                                          "max_distortion": plain["max_distortion"],
                                          "certified": plain["certified"]},
-        "probes": [[r, dl] for r, dl, _ in scr],
+        "probes": [[r, dl] for r, dl, _, _ in scr],
     }
 
 
@@ -293,21 +311,29 @@ def main():
         % (fit_s * 1e3, last["r"], ncert, last["cert"]["max_distortion"], st["t_pca_ms"], st["t_search_ms"],
            st["t_screen_ms"]))
 
-    # roofline of the screen kernel over every launch of the timed steps
-    flops, ms, launches = 0.0, 0.0, 0
+    # roofline of the screen kernel over the launches of the timed steps.  The
+    # first certificate of a fit computes (and caches) the point Gram: 2(d + r)
+    # flops per pair; the others load it and compute the image Gram: 2r.
+    kinds = {"full": [0.0, 0.0, 0], "cached": [0.0, 0.0, 0]}
     for o in outs:
         s = o["stats"]
-        for r, t in zip(s["probe_r"], s["probe_screen_ms"]):
-            flops += npairs * 2.0 * (d + r)
-            ms += t
-            launches += 1
-    avg_ms = ms / launches
-    achieved = flops / launches / (avg_ms * 1e-3) / 1e12
-    traffic = traffic_per_launch()
-    roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_MFMA_TFLOPS, "traffic": traffic,
-                "kernel": "k_pairs_f32<0> (all-pairs screen)", "launches": launches,
-                "avg_launch_ms": avg_ms, "flops_per_launch": flops / launches}
+        for r, t, g in zip(s["probe_r"], s["probe_screen_ms"], s["probe_gram"]):
+            k = "cached" if g == 2 else "full"
+            kinds[k][0] += npairs * 2.0 * ((d + r) if k == "full" else r)
+            kinds[k][1] += t
+            kinds[k][2] += 1
+    launch_kinds = {}
+    for k, (fl, ms, nl) in kinds.items():
+        if nl:
+            launch_kinds[k] = {"launches": nl, "avg_launch_ms": ms / nl, "flops_per_launch": fl / nl,
+                               "tflops": fl / ms / 1e9, "frac": fl / ms / 1e9 / PEAK_FP32_MFMA_TFLOPS}
+    dom = max(launch_kinds, key=lambda k: kinds[k][1])
+    traffic = traffic_per_launch(dom)
+    roofline = {"bound": "mfma", "achieved": launch_kinds[dom]["tflops"], "peak": PEAK_FP32_MFMA_TFLOPS,
+                "unit": "TFLOP/s", "frac": launch_kinds[dom]["frac"], "traffic": traffic,
+                "kernel": "k_pairs_f32<0> (all-pairs screen), %s launches" % dom,
+                "launches": launch_kinds[dom]["launches"], "avg_launch_ms": launch_kinds[dom]["avg_launch_ms"],
+                "flops_per_launch": launch_kinds[dom]["flops_per_launch"], "launch_kinds": launch_kinds}
 
     # precision form: BF16 split screen, same exact certificate
     forms = {}
@@ -322,8 +348,8 @@ def main():
         bl = bouts[-1]
         bflops, bms, bn = 0.0, 0.0, 0
         for o in bouts:
-            for r, t in zip(o["stats"]["probe_r"], o["stats"]["probe_screen_ms"]):
-                bflops += npairs * 2.0 * (d + r)
+            for r, t, g in zip(o["stats"]["probe_r"], o["stats"]["probe_screen_ms"], o["stats"]["probe_gram"]):
+                bflops += screen_flops(npairs, d, r, g)
                 bms += t
                 bn += 1
         forms["bf16x3"] = {
@@ -332,9 +358,9 @@ def main():
             "abs_err_vs_plain_fp64_certificate": abs(bl["cert"]["max_distortion"] - last["cert"]["max_distortion"]),
             "same_map_as_plain": bool(bl["r"] == last["r"] and torch.equal(bl["Pi"], last["Pi"])),
             "screen_avg_launch_ms": bms / bn,
-            "screen_useful_tflops": bflops / bn / (bms / bn * 1e-3) / 1e12,
-            "screen_bf16_mfma_tflops": 3.0 * bflops / bn / (bms / bn * 1e-3) / 1e12,
-            "screen_bf16_mfma_frac": 3.0 * bflops / bn / (bms / bn * 1e-3) / 1e12 / PEAK_BF16_MFMA_TFLOPS,
+            "screen_useful_tflops": bflops / bms / 1e9,
+            "screen_bf16_mfma_tflops": 3.0 * bflops / bms / 1e9,
+            "screen_bf16_mfma_frac": 3.0 * bflops / bms / 1e9 / PEAK_BF16_MFMA_TFLOPS,
             "rescored_pairs": bl["stats"]["n_rescored"], "flagged_tiles": bl["stats"]["n_flagged_tiles"]}
         log("bf16x3 fit %.1f ms (%.2fx), screen %.2f ms/launch" % (bf_s * 1e3, fit_s / bf_s, bms / bn))
         forms["fp8"] = fp8_form(adagio, gen, torch, Xd, args.eps, args.steps, fit_s, last, npairs, d)

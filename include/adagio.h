@@ -93,6 +93,8 @@ typedef struct adagio_stats {
     int32_t probe_r[48];     /* target dimension of each certificate              */
     double probe_delta[48];  /* its exact max distortion                          */
     double probe_screen_ms[48]; /* its all-pairs screen kernel time (device events) */
+    int32_t probe_gram[48];  /* its point Gram: 0 computed, 1 computed and stored in the
+                                fit's point-Gram cache, 2 loaded from it (image Gram only) */
 } adagio_stats_t;
 
 typedef struct adagio_opts {
@@ -160,8 +162,13 @@ int adagio_certify_map(const float* X, int64_t n, int64_t d, const float* Pi, in
  * (opts->predictor) and falls back to bisection.  With ADAGIO_SCREEN_FP8 the
  * bisection decides on FP8 screens, then the result is certified with the
  * BF16 split screen; if that fails, certified bisection continues above it,
- * so the returned certificate is always a certificate.  Synchronises
- * `stream`. */
+ * so the returned certificate is always a certificate.  The certificates of
+ * the search share a point-Gram cache: the points do not change within a
+ * fit, so the first certificate keeps each 128 x 128 tile's point Gram
+ * (64 KB per tile: 7.2 GB at n = 60000) in device memory and the others read
+ * it back and compute only the image Gram; the cache is used when it fits in
+ * half of the free device memory, and the certificate is the same either
+ * way.  Synchronises `stream`. */
 int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed,
                const adagio_opts_t* opts, float* Pi_out, int32_t* r_out, int32_t* s_out,
                adagio_cert_t* cert_out, void* stream);

@@ -56,7 +56,7 @@ struct Workspace {
   DevBuf S, T, Pi, Pi64, Y64, Yc, ny, ty, muY;
   DevBuf recs, tparts, seeds, seedv, list, cand, vals, vparts, cd;
   DevBuf Xb, txb, Yb, tyb, bjU, bjS;
-  DevBuf Xq, sx, nxq, Yq, sy, nyq, q8terms, hist, kthr;
+  DevBuf Xq, sx, nxq, Yq, sy, nyq, q8terms, hist, kthr, gcache;
   DevBuf skpart, skG, skK, sklam, skV, skfeat, mlp_pb, mlp_X, mlp_f, mlp_hb, mlp_grad, mlp_loss;
   bool checked = false;
 };
@@ -360,7 +360,7 @@ struct Images {
   float2* tyb = nullptr;
   int64_t ldyq = 0;             // per-row scaled e4m3 copy (screen = FP8)
   unsigned char* Yq = nullptr;
-  float4* q8 = nullptr;         // per row (N_x, N_y, s_x, s_y) of the FP8 screen
+  float4* q8 = nullptr;         // per row (N_x, N_y, -2 s_x, -2 s_y) of the FP8 screen
   const float* Y32 = nullptr;   // rescore source (given images) ...
   const double* Y64 = nullptr;  // ... or FP64 images of a map
 };
@@ -432,13 +432,15 @@ struct CertTimes {
   int nprobe = 0;
   int32_t probe_r[48];
   double probe_delta[48], probe_ms[48];
+  int32_t probe_gram[48];
 };
 
-static void log_probe(CertTimes& tm, int64_t r, const adagio_cert_t& c, double screen_ms) {
+static void log_probe(CertTimes& tm, int64_t r, const adagio_cert_t& c, double screen_ms, int gmode) {
   if (tm.nprobe < 48) {
     tm.probe_r[tm.nprobe] = (int32_t)r;
     tm.probe_delta[tm.nprobe] = c.max_distortion;
     tm.probe_ms[tm.nprobe] = screen_ms;
+    tm.probe_gram[tm.nprobe] = gmode;
     ++tm.nprobe;
   }
 }
@@ -456,6 +458,7 @@ static void fill_stats(adagio_stats_t* s, const CertTimes& tm, int ncert, double
     s->probe_r[k] = tm.probe_r[k];
     s->probe_delta[k] = tm.probe_delta[k];
     s->probe_screen_ms[k] = tm.probe_ms[k];
+    s->probe_gram[k] = tm.probe_gram[k];
   }
   s->t_total_ms = total_ms;
 }
@@ -475,8 +478,24 @@ static const uint32_t kFp8Tiles = 1024;
 // The certificate of eq. (3) for points p and images im.  With the FP8 screen
 // the same steps run on the FP8 estimates' top tiles only, and the result is
 // the exact maximum over those tiles (certified = 0, no bound on the rest).
+// Point-Gram cache for the certificates of one fit (64 KB per tile of pairs):
+// the points do not change across a fit's certificates, so the first one
+// stores every tile's point Gram and the others read it back instead of
+// recomputing it.  Null (no caching) when it would take more than half of the
+// free device memory.
+static float* gram_cache(Workspace& ws, const Points& p) {
+  const int64_t NT = p.n_pad / kTile;
+  const size_t bytes = (size_t)(NT * (NT + 1) / 2) * (size_t)kGcacheFloatsPerTile * sizeof(float);
+  if (ws.gcache.cap >= bytes) return static_cast<float*>(ws.gcache.p);
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) return nullptr;
+  if (bytes > (fr + ws.gcache.cap) / 2) return nullptr;
+  return ensure<float>(ws.gcache, bytes / sizeof(float));
+}
+
 static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& im, uint32_t cap0,
-                                 hipStream_t st, CertTimes* times, int screen) {
+                                 hipStream_t st, CertTimes* times, int screen, float* gcache = nullptr,
+                                 int gmode = 0) {
   PairsView v;
   v.X = p.Xc; v.ldx = (int)p.ldx;
   v.Y = im.Yc; v.ldy = (int)im.ldy;
@@ -505,11 +524,12 @@ static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& i
     vb.Yb = im.Yb; vb.ldy = (int)im.ldyb;
     vb.tx = p.txb; vb.ty = im.tyb;
     vb.n = v.n; vb.NT = v.NT; vb.ntiles = v.ntiles;
-    HIPCHK(launch_pairs_screen_bf16(vb, recs, st));
+    HIPCHK(launch_pairs_screen_bf16(vb, recs, gcache, gmode, st));
   } else if (screen == ADAGIO_SCREEN_FP8) {
-    HIPCHK(launch_pairs_screen_fp8(p.Xq, (int)p.ldxq, im.Yq, (int)im.ldyq, im.q8, v.n, v.NT, recs, st));
+    HIPCHK(launch_pairs_screen_fp8(p.Xq, (int)p.ldxq, im.Yq, (int)im.ldyq, im.q8, v.n, v.NT, recs, gcache, gmode,
+                                   st));
   } else {
-    HIPCHK(launch_pairs_screen(v, recs, st));
+    HIPCHK(launch_pairs_screen(v, recs, gcache, gmode, st));
   }
   e_screen.end(st);
   e_rest.begin(st);
@@ -599,7 +619,7 @@ static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& i
     times->flagged += h.n_flagged;
     times->rescored += c.n_rescored;
     if (screen == ADAGIO_SCREEN_FP8) ++times->screened;
-    log_probe(*times, im.r, c, sm);
+    log_probe(*times, im.r, c, sm, gcache ? gmode : 0);
   }
   return c;
 }
@@ -765,10 +785,19 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     // all pairs is <= eps, and becomes the current answer.  A screened probe
     // passes when its re-evaluated maximum is <= eps; it fails only on a pair
     // that exceeds eps, but may pass a map that a certificate rejects.
+    // The probes of the search's own screen share the point-Gram cache.
+    float* gcache = nullptr;
+    bool gready = false;
     auto probe = [&](int64_t r, int scr) {
       build_map(ws, ax.Vt, d, r, seed, Pi, st);
       Images im = images_of_map(ws, p, Pi, r, st);
-      adagio_cert_t c = certificate(ws, p, im, cap0, st, &tm, scr);
+      int gmode = 0;
+      if (scr == screen) {
+        if (!gready) gcache = gram_cache(ws, p);
+        gmode = gcache ? (gready ? 2 : 1) : 0;
+      }
+      adagio_cert_t c = certificate(ws, p, im, cap0, st, &tm, scr, gcache, gmode);
+      if (gmode == 1) gready = true;
       ++ncert;
       if (scr == ADAGIO_SCREEN_FP8) return c.max_distortion <= eps;
       const bool pass = c.certified ? c.max_distortion <= eps : c.bound_rest <= eps;
@@ -928,7 +957,7 @@ int adagio_release(void) {
                       &ws.W, &ws.trace, &ws.rot, &ws.lam, &ws.Vt, &ws.S, &ws.T, &ws.Pi, &ws.Pi64, &ws.Y64,
                       &ws.Yc, &ws.ny, &ws.ty, &ws.muY, &ws.recs, &ws.tparts, &ws.seeds, &ws.seedv, &ws.list,
                       &ws.cand, &ws.vals, &ws.vparts, &ws.cd, &ws.Xb, &ws.txb, &ws.Yb, &ws.tyb, &ws.bjU, &ws.bjS,
-                      &ws.Xq, &ws.sx, &ws.nxq, &ws.Yq, &ws.sy, &ws.nyq, &ws.q8terms, &ws.hist, &ws.kthr,
+                      &ws.Xq, &ws.sx, &ws.nxq, &ws.Yq, &ws.sy, &ws.nyq, &ws.q8terms, &ws.hist, &ws.kthr, &ws.gcache,
                       &ws.skpart, &ws.skG, &ws.skK, &ws.sklam, &ws.skV, &ws.skfeat, &ws.mlp_pb, &ws.mlp_X,
                       &ws.mlp_f, &ws.mlp_hb, &ws.mlp_grad, &ws.mlp_loss};
     for (DevBuf* b : bufs) {

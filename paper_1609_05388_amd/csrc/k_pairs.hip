@@ -146,10 +146,14 @@ __global__ __launch_bounds__(256, 2) void k_pairs_f32(PairsArgs p) {
 
     // Two loops with fixed accumulators (one selected per chunk would make
     // the compiler copy the other set); the prefetch runs across the seam.
-    fetch(0);
-    stash(0);
+    // With a loaded point Gram the pipeline starts at the first image chunk.
+    const bool gload = MODE == 0 && p.gmode == 2;
+    const int64_t tix = (int64_t)I * p.NT - (int64_t)I * (I - 1) / 2 + (J - I);
+    const int c0 = gload ? p.nchx : 0;
+    fetch(c0);
+    stash(c0 & 1);
     __syncthreads();
-    for (int c = 0; c < p.nchx; ++c) {
+    for (int c = c0; c < p.nchx; ++c) {
       const int buf = c & 1;
       if (c + 1 < total) fetch(c + 1);
       mma(accX, buf);
@@ -159,10 +163,15 @@ __global__ __launch_bounds__(256, 2) void k_pairs_f32(PairsArgs p) {
     for (int c = p.nchx; c < total; ++c) {
       const int buf = c & 1;
       if (c + 1 < total) fetch(c + 1);
+      // the cached point Gram, issued after the last prefetch so that the
+      // chunk loads before it complete first; it lands during the last MFMAs
+      if (gload && c == (total - 2 > p.nchx ? total - 2 : p.nchx)) gcache_load(p.gcache, tix, accX);
       mma(accY, buf);
       if (c + 1 < total) stash(buf ^ 1);
       __syncthreads();
     }
+    // stored after the image loop: earlier stores would hold up its chunk loads
+    if (MODE == 0 && p.gmode == 1) gcache_store(p.gcache, tix, accX);
 
     tile_epilogue<MODE>(accX, accY, termA, termB, I, J, p, thr_hi, thr_lo, red_v, red_i, red_j);
     if (MODE == 0) return;
@@ -172,11 +181,11 @@ __global__ __launch_bounds__(256, 2) void k_pairs_f32(PairsArgs p) {
   }
 }
 
-hipError_t launch_pairs_screen(const PairsView& v, TileRec* recs, hipStream_t st) {
+hipError_t launch_pairs_screen(const PairsView& v, TileRec* recs, float* gcache, int gmode, hipStream_t st) {
   const int NS = (v.NT + 7) / 8;
   const int64_t nslots = (int64_t)NS * (NS + 1) / 2 * 64;
   PairsArgs a{v.X, v.ldx, v.ldx / PK, v.Y, v.ldy, v.ldy / PK, v.tx, v.ty, v.n, v.NT, v.ntiles,
-              NS, nslots, recs, nullptr, nullptr, nullptr, 0u, nullptr};
+              NS, nslots, recs, nullptr, nullptr, nullptr, 0u, nullptr, gcache, gcache ? gmode : 0};
   const int64_t G = round_up(nslots, 8);
   k_pairs_f32<0><<<(unsigned)G, 256, 0, st>>>(a);
   return hipGetLastError();
@@ -185,7 +194,7 @@ hipError_t launch_pairs_screen(const PairsView& v, TileRec* recs, hipStream_t st
 hipError_t launch_pairs_emit(const PairsView& v, const uint32_t* list, const CertDev* cd, int2* cand,
                              uint32_t cap, uint32_t* ncand, int grid, hipStream_t st) {
   PairsArgs a{v.X, v.ldx, v.ldx / PK, v.Y, v.ldy, v.ldy / PK, v.tx, v.ty, v.n, v.NT, v.ntiles,
-              0, 0, nullptr, list, cd, cand, cap, ncand};
+              0, 0, nullptr, list, cd, cand, cap, ncand, nullptr, 0};
   k_pairs_f32<1><<<(unsigned)grid, 256, 0, st>>>(a);
   return hipGetLastError();
 }

@@ -175,10 +175,14 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
       }
     };
 
-    fetch(0);
-    stash(0);
+    // with a loaded point Gram the pipeline starts at the first image chunk
+    const bool gload = MODE == 0 && p.gmode == 2;
+    const int64_t tix = (int64_t)I * p.NT - (int64_t)I * (I - 1) / 2 + (J - I);
+    const int c0 = gload ? nchx : 0;
+    fetch(c0);
+    stash(c0 & 1);
     __syncthreads();
-    for (int c = 0; c < nchx; ++c) {
+    for (int c = c0; c < nchx; ++c) {
       const int buf = c & 1;
       if (c + 1 < total) fetch(c + 1);
       mma(accX, buf);
@@ -188,10 +192,15 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
     for (int c = nchx; c < total; ++c) {
       const int buf = c & 1;
       if (c + 1 < total) fetch(c + 1);
+      // the cached point Gram, issued after the last prefetch so that the
+      // chunk loads before it complete first; it lands during the last MFMAs
+      if (gload && c == (total - 2 > nchx ? total - 2 : nchx)) gcache_load(p.gcache, tix, accX);
       mma(accY, buf);
       if (c + 1 < total) stash(buf ^ 1);
       __syncthreads();
     }
+    // stored after the image loop: earlier stores would hold up its chunk loads
+    if (MODE == 0 && p.gmode == 1) gcache_store(p.gcache, tix, accX);
 
     tile_epilogue<MODE>(accX, accY, termA, termB, I, J, p, thr_hi, thr_lo, red_v, red_i, red_j);
     if (MODE == 0) return;
@@ -209,7 +218,7 @@ hipError_t launch_split_bf16(const float* src, int64_t n_pad, int64_t m, int64_t
   return hipGetLastError();
 }
 
-hipError_t launch_pairs_screen_bf16(const PairsViewB& v, TileRec* recs, hipStream_t st) {
+hipError_t launch_pairs_screen_bf16(const PairsViewB& v, TileRec* recs, float* gcache, int gmode, hipStream_t st) {
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pairs_bf16x3<0>),
@@ -223,7 +232,7 @@ hipError_t launch_pairs_screen_bf16(const PairsViewB& v, TileRec* recs, hipStrea
   a.X = v.Xb; a.ldx = v.ldx; a.nchx = v.ldx / BK;
   a.Y = v.Yb; a.ldy = v.ldy; a.nchy = v.ldy / BK;
   a.p = PairsArgs{nullptr, 0, 0, nullptr, 0, 0, v.tx, v.ty, v.n, v.NT, v.ntiles, NS, nslots, recs,
-                  nullptr, nullptr, nullptr, 0u, nullptr};
+                  nullptr, nullptr, nullptr, 0u, nullptr, gcache, gcache ? gmode : 0};
   const int64_t G = round_up(nslots, 8);
   k_pairs_bf16x3<0><<<(unsigned)G, 256, kLdsBf16, st>>>(a);
   return hipGetLastError();

@@ -88,20 +88,21 @@ __global__ void k_quant_fp8(const float* __restrict__ src, int64_t n_pad, int64_
   }
 }
 
-// Per-row epilogue terms (N_x, N_y, s_x, s_y).
+// Per-row epilogue terms (N_x, N_y, -2 s_x, -2 s_y).
 __global__ void k_fp8_terms(const double* __restrict__ nx, const double* __restrict__ ny,
                             const float* __restrict__ sx, const float* __restrict__ sy, int64_t n_pad,
                             float4* __restrict__ t) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n_pad) t[i] = make_float4((float)nx[i], (float)ny[i], sx[i], sy[i]);
+  if (i < n_pad) t[i] = make_float4((float)nx[i], (float)ny[i], -2.0f * sx[i], -2.0f * sy[i]);
 }
 
 struct PairsArgsF {
   const unsigned char* X; int ldx; int nchx;   // e4m3 points, ldx bytes per row, nchx = ldx / FK
   const unsigned char* Y; int ldy; int nchy;
-  const float4* terms;
+  const float4* terms;                         // (N_x, N_y, -2 s_x, -2 s_y) per row
   int n; int NT; int NS; int64_t nslots;
   TileRec* recs;
+  float* gcache; int gmode;                    // point-Gram cache: 0 off, 1 store, 2 load
 };
 
 __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
@@ -194,16 +195,23 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
     }
   };
 
-  fetch(0);
-  stash(0);
+  // with a loaded point Gram the pipeline starts at the first image chunk
+  const bool gload = b.gmode == 2;
+  const int64_t tix = (int64_t)I * NT - (int64_t)I * (I - 1) / 2 + (J - I);
+  const int c0 = gload ? nchx : 0;
+  fetch(c0);
+  stash(c0 & 1);
   __syncthreads();
-  for (int c = 0; c < nchx; ++c) {
+  for (int c = c0; c < nchx; ++c) {
     const int buf = c & 1;
     if (c + 1 < total) fetch(c + 1);
     mma(accX, buf);
     if (c + 1 < total) stash(buf ^ 1);
     __syncthreads();
   }
+  // the cached point Gram (loaded before the image loop: placing the loads
+  // inside it costs this kernel register spills)
+  if (gload) gcache_load(b.gcache, tix, accX);
   for (int c = nchx; c < total; ++c) {
     const int buf = c & 1;
     if (c + 1 < total) fetch(c + 1);
@@ -211,12 +219,17 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
     if (c + 1 < total) stash(buf ^ 1);
     __syncthreads();
   }
+  // stored after the image loop: earlier stores would hold up its chunk loads
+  if (b.gmode == 1) gcache_store(b.gcache, tix, accX);
 
   // epilogue: central estimates, largest and smallest q~ of the tile
   const bool masked = !((I < J) && (col0 + kTile <= n));
   float best_hi = -1.0f, best_lo = 3.0e38f;
   int code_hi = -1, code_lo = -1;
-  const float4 tb0 = termB[wc * 64 + li], tb1 = termB[wc * 64 + 32 + li];
+  // column terms with s in place of -2 s (the row term carries the -2)
+  float4 tb0 = termB[wc * 64 + li], tb1 = termB[wc * 64 + 32 + li];
+  tb0.z *= -0.5f; tb0.w *= -0.5f;
+  tb1.z *= -0.5f; tb1.w *= -0.5f;
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -226,8 +239,8 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
 #pragma unroll
       for (int y = 0; y < 2; ++y) {
         const float4 tb = y ? tb1 : tb0;
-        const float d2 = fmaf(-2.0f * ta.z * tb.z, accX[x][y][v], ta.x + tb.x);
-        const float e2 = fmaf(-2.0f * ta.w * tb.w, accY[x][y][v], ta.y + tb.y);
+        const float d2 = fmaf(ta.z * tb.z, accX[x][y][v], ta.x + tb.x);   // -2 s_i s_j g + N_i + N_j
+        const float e2 = fmaf(ta.w * tb.w, accY[x][y][v], ta.y + tb.y);
         // a pair whose estimated distance vanishes is not ranked
         const float q = fmaxf(e2, 0.0f) * __builtin_amdgcn_rcpf(d2);
         float qh = d2 > 0.0f ? q : -1.0f, ql = d2 > 0.0f ? q : 3.0e38f;
@@ -348,7 +361,8 @@ hipError_t launch_fp8_terms(const double* nx, const double* ny, const float* sx,
 }
 
 hipError_t launch_pairs_screen_fp8(const unsigned char* Xq, int ldx, const unsigned char* Yq, int ldy,
-                                   const float4* terms, int n, int NT, TileRec* recs, hipStream_t st) {
+                                   const float4* terms, int n, int NT, TileRec* recs, float* gcache, int gmode,
+                                   hipStream_t st) {
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pairs_fp8),
@@ -364,6 +378,8 @@ hipError_t launch_pairs_screen_fp8(const unsigned char* Xq, int ldx, const unsig
   a.NS = (NT + 7) / 8;
   a.nslots = (int64_t)a.NS * (a.NS + 1) / 2 * 64;
   a.recs = recs;
+  a.gcache = gcache;
+  a.gmode = gcache ? gmode : 0;
   k_pairs_fp8<<<(unsigned)round_up(a.nslots, 8), 256, kLdsFp8, st>>>(a);
   return hipGetLastError();
 }

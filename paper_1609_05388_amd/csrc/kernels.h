@@ -48,7 +48,9 @@ struct PairsView {
   const float2* tx; const float2* ty;
   int n; int NT; int64_t ntiles;
 };
-hipError_t launch_pairs_screen(const PairsView& v, TileRec* recs, hipStream_t st);
+// gcache: point-Gram cache (16384 floats per tile) or null; gmode 1 stores
+// the tiles' point Grams there, 2 loads them instead of recomputing.
+hipError_t launch_pairs_screen(const PairsView& v, TileRec* recs, float* gcache, int gmode, hipStream_t st);
 hipError_t launch_pairs_emit(const PairsView& v, const uint32_t* list, const CertDev* cd, int2* cand, uint32_t cap,
                              uint32_t* ncand, int grid, hipStream_t st);
 
@@ -61,7 +63,7 @@ struct PairsViewB {
 };
 hipError_t launch_split_bf16(const float* src, int64_t n_pad, int64_t m, int64_t lds, int64_t ldb, __bf16* dst,
                              hipStream_t st);
-hipError_t launch_pairs_screen_bf16(const PairsViewB& v, TileRec* recs, hipStream_t st);
+hipError_t launch_pairs_screen_bf16(const PairsViewB& v, TileRec* recs, float* gcache, int gmode, hipStream_t st);
 
 // k_cert.hip
 hipError_t launch_seeds(const TileRec* recs, int64_t ntiles, TileRec* part, int nparts, int2* seeds, CertDev* cd,
@@ -99,9 +101,11 @@ hipError_t launch_quant_fp8(const float* src, int64_t n_pad, int64_t m, int64_t 
                             float* scale, double* norm2, hipStream_t st);
 hipError_t launch_fp8_terms(const double* nx, const double* ny, const float* sx, const float* sy, int64_t n_pad,
                             float4* t, hipStream_t st);
-// Estimated q extremes per tile (ldx, ldy multiples of fp8_chunk()).
+// Estimated q extremes per tile (ldx, ldy multiples of fp8_chunk()); gcache /
+// gmode as for launch_pairs_screen.
 hipError_t launch_pairs_screen_fp8(const unsigned char* Xq, int ldx, const unsigned char* Yq, int ldy,
-                                   const float4* terms, int n, int NT, TileRec* recs, hipStream_t st);
+                                   const float4* terms, int n, int NT, TileRec* recs, float* gcache, int gmode,
+                                   hipStream_t st);
 // Indices of the >= K tiles with the largest estimated distortion appended to
 // list (at most kmax unless a single tied bucket exceeds it; hist: 65536
 // zeroed counters; nsel zeroed, receives the count).

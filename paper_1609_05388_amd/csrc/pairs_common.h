@@ -48,6 +48,31 @@ __device__ inline void wave_arg(float& v, int& i, int& j) {
   }
 }
 
+// Point-Gram cache of a screen: the 16384 FP32 values of a 128 x 128 tile's
+// point Gram (the accX accumulators of its 256 threads) stored as 16 float4
+// per thread, element k4 of thread tid at float4 index k4 * 256 + tid of the
+// tile's 64 KB block, so every store and load of a wave is one contiguous
+// 1 KB segment.  The points do not change across the certificates of one
+// fit, so the first certificate stores the Grams and the others load them.
+__device__ inline void gcache_store(float* cache, int64_t tile, const f32x16 (&acc)[2][2]) {
+  float4* g = reinterpret_cast<float4*>(cache) + tile * 4096 + threadIdx.x;
+#pragma unroll
+  for (int k4 = 0; k4 < 16; ++k4) {
+    const f32x16& a = acc[k4 >> 3][(k4 >> 2) & 1];
+    const int v = (k4 & 3) * 4;
+    g[k4 * 256] = make_float4(a[v], a[v + 1], a[v + 2], a[v + 3]);
+  }
+}
+__device__ inline void gcache_load(const float* cache, int64_t tile, f32x16 (&acc)[2][2]) {
+  const float4* g = reinterpret_cast<const float4*>(cache) + tile * 4096 + threadIdx.x;
+#pragma unroll
+  for (int k4 = 0; k4 < 16; ++k4) {
+    const float4 t = g[k4 * 256];
+    f32x16& a = acc[k4 >> 3][(k4 >> 2) & 1];
+    const int v = (k4 & 3) * 4;
+    a[v] = t.x; a[v + 1] = t.y; a[v + 2] = t.z; a[v + 3] = t.w;
+  }
+}
 struct PairsArgs {
   const float* X; int ldx; int nchx;   // centred points, n_pad x ldx, ldx = 16 * nchx
   const float* Y; int ldy; int nchy;   // centred images, n_pad x ldy
@@ -58,6 +83,7 @@ struct PairsArgs {
   const uint32_t* list;                // MODE 1: flagged tiles
   const CertDev* cd;                   //         thresholds and count
   int2* cand; uint32_t cap; uint32_t* ncand;
+  float* gcache; int gmode;            // MODE 0: point Gram per tile, 0 off, 1 store, 2 load
 };
 
 // Bounds on q for one pair from its two Gram entries and row terms.  Branch
