@@ -383,6 +383,21 @@ def main():
                              "max_distortion": o["cert"]["max_distortion"],
                              "certificates": o["stats"]["n_certificates"]}
 
+    # Table 2 analogue: the smallest certified r of each map family per eps
+    tradeoff = {}
+    if not args.no_extra_eps:
+        for fam in ("adagio", "pca", "jl"):
+            tradeoff[fam] = {}
+            for e in (0.05, 0.1, 0.2):
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                o = adagio.fit(Xd, e, gen.JL_SEED, family=fam)
+                torch.cuda.synchronize()
+                tradeoff[fam][str(e)] = {"r": o["r"], "fit_ms": (time.perf_counter() - ta) * 1e3,
+                                         "max_distortion": o["cert"]["max_distortion"],
+                                         "certified": o["cert"]["certified"]}
+        log("tradeoff r: " + ", ".join("%s %s" % (f, [v["r"] for v in tradeoff[f].values()]) for f in tradeoff))
+
     large = None
     if not args.no_large:
         log("precision form at n=200000, d=4096")
@@ -420,6 +435,7 @@ def main():
                 "rescored_pairs": st["n_rescored"], "flagged_tiles": st["n_flagged_tiles"],
                 "probes": [[r, dl] for r, dl in zip(st["probe_r"], st["probe_delta"])]},
         "other_eps": extra,
+        "tradeoff_min_r": tradeoff,
         "forms": forms,
         "large_precision_form": large,
         "roofline": roofline,

@@ -57,6 +57,11 @@ extern "C" {
                                     (certified = 0, bound_rest = +inf); fits
                                     certify their result with BF16X3 */
 
+/* Map family of a fit (Sec. 4.3 / Table 2 compare the three). */
+#define ADAGIO_MAP_ADAGIO 0      /* Algorithm 1: [P ; S Q], floor(r/2) + ceil(r/2) rows */
+#define ADAGIO_MAP_PCA 1         /* the top r principal directions alone          */
+#define ADAGIO_MAP_JL 2          /* Lemma 1's r x d +-1/sqrt(r) matrix alone (no PCA) */
+
 /* Target-dimension search. */
 #define ADAGIO_SEARCH_BISECT 0   /* bisection over r in (0, d]                 */
 #define ADAGIO_SEARCH_LEARNED 1  /* MLP prediction, certified, bisection fallback */
@@ -101,7 +106,7 @@ typedef struct adagio_opts {
     int32_t screen;          /* ADAGIO_SCREEN_*; default F32                      */
     int32_t search;          /* ADAGIO_SEARCH_*; default BISECT                   */
     int32_t max_candidates;  /* initial candidate capacity per certificate; 0 = default (2^20) */
-    int32_t reserved;
+    int32_t family;          /* ADAGIO_MAP_*; default ADAGIO (fit only)           */
     const float* predictor;  /* learned search: device pointer to the packed MLP parameters */
     adagio_stats_t* stats;   /* optional host output                              */
 } adagio_opts_t;
@@ -168,7 +173,10 @@ int adagio_certify_map(const float* X, int64_t n, int64_t d, const float* Pi, in
  * (64 KB per tile: 7.2 GB at n = 60000) in device memory and the others read
  * it back and compute only the image Gram; the cache is used when it fits in
  * half of the free device memory, and the certificate is the same either
- * way.  Synchronises `stream`. */
+ * way.  opts->family = ADAGIO_MAP_PCA or ADAGIO_MAP_JL runs the same search
+ * over the PCA-only or JL-only maps of Table 2 (at r = d: V^T, resp. the
+ * identity); the learned search is for Algorithm 1's maps only.
+ * Synchronises `stream`. */
 int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed,
                const adagio_opts_t* opts, float* Pi_out, int32_t* r_out, int32_t* s_out,
                adagio_cert_t* cert_out, void* stream);

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libadagio.so")
 
 SCREEN = {"f32": 0, "bf16x3": 1, "fp8": 2}
 SEARCH = {"bisect": 0, "learned": 1}
+FAMILY = {"adagio": 0, "pca": 1, "jl": 2}
 
 
 class AdagioError(RuntimeError):
@@ -57,7 +58,7 @@ class Stats(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("screen", ctypes.c_int32), ("search", ctypes.c_int32),
-                ("max_candidates", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_candidates", ctypes.c_int32), ("family", ctypes.c_int32),
                 ("predictor", ctypes.c_void_p), ("stats", ctypes.POINTER(Stats))]
 
 
@@ -126,10 +127,11 @@ def _dev(t, dtype, name):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _opts(screen="f32", search="bisect", max_candidates=0, predictor=None, stats=None):
+def _opts(screen="f32", search="bisect", max_candidates=0, predictor=None, stats=None, family="adagio"):
     o = Opts()
     o.screen = SCREEN[screen]
     o.search = SEARCH[search]
+    o.family = FAMILY[family]
     o.max_candidates = int(max_candidates)
     o.predictor = ctypes.c_void_p(predictor.data_ptr()) if predictor is not None else None
     o.stats = ctypes.pointer(stats) if stats is not None else None
@@ -209,13 +211,14 @@ def certify_map(X, Pi, screen="f32", max_candidates=0, with_stats=False):
     return out
 
 
-def fit(X, eps, seed, screen="f32", search="bisect", predictor=None, max_candidates=0):
-    """Returns dict(Pi=(r x d tensor), r, s, k, cert, stats)."""
+def fit(X, eps, seed, screen="f32", search="bisect", predictor=None, max_candidates=0, family="adagio"):
+    """Returns dict(Pi=(r x d tensor), r, s, k, cert, stats).  family: "adagio"
+    (Algorithm 1), "pca" or "jl" (Table 2's single-component maps)."""
     lib = load()
     n, d = X.shape
     Pi_buf = torch.empty((d, d), dtype=torch.float32, device=X.device)
     st = Stats()
-    o = _opts(screen, search, max_candidates, predictor, st)
+    o = _opts(screen, search, max_candidates, predictor, st, family)
     r = ctypes.c_int32()
     s = ctypes.c_int32()
     c = Cert()

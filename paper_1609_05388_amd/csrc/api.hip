@@ -350,6 +350,23 @@ static void build_map(Workspace& ws, const double* Vt, int64_t d, int64_t r, uin
   HIPCHK(launch_proj_SQ(S, T, k, s, Vt, d, Pi, nullptr, st));
 }
 
+// Pi (r x d, FP32) of a map family at target dimension r: Algorithm 1, the
+// top r principal directions alone, or Lemma 1's JL matrix alone (r = d: the
+// identity, no reduction).
+static void build_family_map(Workspace& ws, int family, const double* Vt, int64_t d, int64_t r, uint64_t seed,
+                             float* Pi, hipStream_t st) {
+  if (family == ADAGIO_MAP_PCA) {
+    HIPCHK(launch_copy_rows(Vt, r, d, Pi, nullptr, st));
+  } else if (family == ADAGIO_MAP_JL) {
+    double* S = ensure<double>(ws.S, (size_t)(r * d));
+    if (r == d) HIPCHK(launch_eye(S, (int)d, st));
+    else HIPCHK(launch_jl_signs(seed, r, d, S, st));
+    HIPCHK(launch_copy_rows(S, r, d, Pi, nullptr, st));
+  } else {
+    build_map(ws, Vt, d, r, seed, Pi, st);
+  }
+}
+
 // ----------------------------------------------------------- certificate
 struct Images {
   int64_t r = 0, ldy = 0;
@@ -759,6 +776,10 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     const int search = opts ? opts->search : ADAGIO_SEARCH_BISECT;
     ARGCHK(search == ADAGIO_SEARCH_BISECT || search == ADAGIO_SEARCH_LEARNED, "unknown search");
     ARGCHK(search != ADAGIO_SEARCH_LEARNED || opts->predictor, "learned search needs opts->predictor");
+    const int family = opts ? opts->family : ADAGIO_MAP_ADAGIO;
+    ARGCHK(family == ADAGIO_MAP_ADAGIO || family == ADAGIO_MAP_PCA || family == ADAGIO_MAP_JL, "unknown map family");
+    ARGCHK(family == ADAGIO_MAP_ADAGIO || search == ADAGIO_SEARCH_BISECT,
+           "the learned search is for Algorithm 1's maps only");
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = as_stream(stream);
     Workspace& ws = workspace();
@@ -766,7 +787,8 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     EvPair e_pca, e_search;
     e_pca.begin(st);
     Points p = prep_points(ws, X, n, d, st, screen);
-    Axes ax = principal_axes(ws, p, st);
+    Axes ax;                         // the JL-only family needs no PCA
+    if (family != ADAGIO_MAP_JL) ax = principal_axes(ws, p, st);
     e_pca.end(st);
     e_search.begin(st);
     float* Pi = ensure<float>(ws.Pi, (size_t)(d * d));
@@ -789,7 +811,7 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     float* gcache = nullptr;
     bool gready = false;
     auto probe = [&](int64_t r, int scr) {
-      build_map(ws, ax.Vt, d, r, seed, Pi, st);
+      build_family_map(ws, family, ax.Vt, d, r, seed, Pi, st);
       Images im = images_of_map(ws, p, Pi, r, st);
       int gmode = 0;
       if (scr == screen) {
@@ -844,8 +866,8 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
       // Bisection over r: lo = 0 (empty map, distortion 1), hi = d (isometry).
       bisect(rig);
     }
-    if (!have_hi) {  // hi == d: the full eigenbasis
-      build_map(ws, ax.Vt, d, d, seed, Pi_out, st);
+    if (!have_hi) {  // hi == d: no reduction (the full eigenbasis, or the identity)
+      build_family_map(ws, family, ax.Vt, d, d, seed, Pi_out, st);
       Images im = images_of_map(ws, p, Pi_out, d, st);
       cert_hi = certificate(ws, p, im, cap0, st, &tm, rig);
       ++ncert;
@@ -853,7 +875,9 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     e_search.end(st);
     HIPCHK(hipStreamSynchronize(st));
     *r_out = (int32_t)hi;
-    *s_out = (int32_t)(hi == d ? d : hi / 2);
+    *s_out = family == ADAGIO_MAP_PCA ? (int32_t)hi
+             : family == ADAGIO_MAP_JL ? 0
+             : (int32_t)(hi == d ? d : hi / 2);
     *cert_out = cert_hi;
     if (opts && opts->stats) {
       adagio_stats_t* s = opts->stats;
