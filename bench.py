@@ -179,18 +179,24 @@ def fp8_form(adagio, gen, torch, Xd, eps, steps, plain_s, plain, npairs, d):
 
 
 def learned_form(adagio, gen, torch, Xd, eps, steps, plain_s, plain):
-    """Fit from the trained predictor's r (certified, bisection fallback)."""
-    import numpy as np
+    """Fit from the trained predictor's r (certified, bisection fallback),
+    with exact PCA and with the randomized PCA for the predicted s."""
     from paper_1609_05388_amd import learned
     if not os.path.exists(learned.PREDICTOR):
         return None
     P = learned.load_predictor(learned.PREDICTOR)
     fs, outs = timed_fits(adagio, torch, Xd, eps, gen.JL_SEED, steps, search="learned", predictor=P)
     o = outs[-1]
+    rs, routs = timed_fits(adagio, torch, Xd, eps, gen.JL_SEED, steps, search="learned", predictor=P,
+                           pca="randomized", pca_iters=2)
+    ro = routs[-1]
     return {"fit_ms": fs * 1e3, "speedup_vs_plain": plain_s / fs, "r": o["r"], "r_plain": plain["r"],
             "r_predicted": o["stats"]["r_predicted"], "fallback": o["stats"]["n_fallback"],
             "certificates": o["stats"]["n_certificates"], "max_distortion": o["cert"]["max_distortion"],
-            "certified": o["cert"]["certified"]}
+            "certified": o["cert"]["certified"],
+            "with_randomized_pca": {"fit_ms": rs * 1e3, "speedup_vs_plain": plain_s / rs, "r": ro["r"],
+                                    "max_distortion": ro["cert"]["max_distortion"],
+                                    "certified": ro["cert"]["certified"]}}
 
 
 def large_form(adagio, gen, torch, eps):
@@ -221,6 +227,12 @@ def large_form(adagio, gen, torch, eps):
     same_r = [dl for r, dl, _, _ in fp8 if r == o["r"]]
     plain = adagio.certify_map(Xd, o["Pi"].contiguous(), screen="f32", with_stats=True)
     pst = plain.pop("stats")
+    torch.cuda.synchronize()
+    tr = time.perf_counter()
+    ro = adagio.fit(Xd, eps, gen.JL_SEED, screen="fp8", pca="randomized", pca_iters=2)
+    torch.cuda.synchronize()
+    rand = {"fit_ms": (time.perf_counter() - tr) * 1e3, "r": ro["r"], "max_distortion": ro["cert"]["max_distortion"],
+            "certified": ro["cert"]["certified"], "power_iterations": 2, "oversampling": 10}
     del Xd
     torch.cuda.empty_cache()
     return {
@@ -240,6 +252,7 @@ def large_form(adagio, gen, torch, eps):
                                          "max_distortion": plain["max_distortion"],
                                          "certified": plain["certified"]},
         "probes": [[r, dl] for r, dl, _, _ in scr],
+        "with_randomized_pca": rand,
     }
 
 
@@ -365,6 +378,13 @@ def main():
         log("bf16x3 fit %.1f ms (%.2fx), screen %.2f ms/launch" % (bf_s * 1e3, fit_s / bf_s, bms / bn))
         forms["fp8"] = fp8_form(adagio, gen, torch, Xd, args.eps, args.steps, fit_s, last, npairs, d)
         log("fp8 fit %.1f ms (%.2fx)" % (forms["fp8"]["fit_ms"], forms["fp8"]["speedup_vs_plain"]))
+        rs, routs = timed_fits(adagio, torch, Xd, args.eps, gen.JL_SEED, args.steps, pca="randomized", pca_iters=2)
+        ro = routs[-1]
+        forms["randomized_pca"] = {"fit_ms": rs * 1e3, "speedup_vs_plain": fit_s / rs, "r": ro["r"],
+                                   "r_exact_pca": last["r"], "max_distortion": ro["cert"]["max_distortion"],
+                                   "certified": ro["cert"]["certified"], "power_iterations": 2,
+                                   "oversampling": 10}
+        log("randomized-PCA fit %.1f ms (%.2fx), r=%d" % (rs * 1e3, fit_s / rs, ro["r"]))
         lf = learned_form(adagio, gen, torch, Xd, args.eps, args.steps, fit_s, last)
         if lf:
             forms["learned"] = lf

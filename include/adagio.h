@@ -62,6 +62,11 @@ extern "C" {
 #define ADAGIO_MAP_PCA 1         /* the top r principal directions alone          */
 #define ADAGIO_MAP_JL 2          /* Lemma 1's r x d +-1/sqrt(r) matrix alone (no PCA) */
 
+/* Principal directions of a fit. */
+#define ADAGIO_PCA_EXACT 0       /* FP64 covariance + block Jacobi: every eigenpair */
+#define ADAGIO_PCA_RANDOMIZED 1  /* Sec. 4.5's randomized PCA: top s + 10 directions
+                                    by randomized subspace iteration              */
+
 /* Target-dimension search. */
 #define ADAGIO_SEARCH_BISECT 0   /* bisection over r in (0, d]                 */
 #define ADAGIO_SEARCH_LEARNED 1  /* MLP prediction, certified, bisection fallback */
@@ -109,6 +114,8 @@ typedef struct adagio_opts {
     int32_t family;          /* ADAGIO_MAP_*; default ADAGIO (fit only)           */
     const float* predictor;  /* learned search: device pointer to the packed MLP parameters */
     adagio_stats_t* stats;   /* optional host output                              */
+    int32_t pca;             /* ADAGIO_PCA_*; default EXACT (fit only)            */
+    int32_t pca_iters;       /* randomized PCA: power iterations q (>= 0)         */
 } adagio_opts_t;
 
 /* a1-a3.  Principal axes of the centred cloud (Sec. 2 PCA paragraph, eq. 4;
@@ -118,6 +125,20 @@ typedef struct adagio_opts {
  * Out: lambda (device, d doubles, decreasing), Vt (device, d x d doubles,
  * row i = unit eigenvector of lambda[i]).  Synchronises `stream`. */
 int adagio_pca(const float* X, int64_t n, int64_t d, double* lambda, double* Vt, void* stream);
+
+/* Randomized PCA, the paper's Adagio-Randomized-PCA variant (Sec. 4.1
+ * "Implementation", Sec. 4.5; the randomized range finder of Halko,
+ * Martinsson and Tropp): C = sum_i (x_i - mu)(x_i - mu)^T in FP64; a block of
+ * ell sign vectors Omega (entry (a, l) from SplitMix64 output a * 2^32 + l + 1
+ * of seed ^ 0x94D049BB133111EB, the same counter scheme as the JL signs);
+ * Y = C Omega, then q more products Y = C Q, each time with Q an orthonormal
+ * basis of the block (kept as rows; Lambda^-1/2 V^T Y^T from the eigenpairs
+ * of the block's Gram, twice); finally the eigenpairs (W, lambda) of Q^T C Q
+ * give the ell approximate principal directions (Q W)^T.  ell in [1, d],
+ * power_iters = q >= 0.  Out: lambda (device, ell doubles, decreasing), Vt
+ * (device, ell x d doubles, rows = unit directions).  Synchronises `stream`. */
+int adagio_pca_randomized(const float* X, int64_t n, int64_t d, int32_t ell, int32_t power_iters, uint64_t seed,
+                          double* lambda, double* Vt, void* stream);
 
 /* a4-a5.  Algorithm 1's map at target dimension r from given principal axes:
  * s = floor(r/2) rows P = Vt[0:s], k = ceil(r/2) rows S Q = S - (S P^T) P with
@@ -176,7 +197,10 @@ int adagio_certify_map(const float* X, int64_t n, int64_t d, const float* Pi, in
  * way.  opts->family = ADAGIO_MAP_PCA or ADAGIO_MAP_JL runs the same search
  * over the PCA-only or JL-only maps of Table 2 (at r = d: V^T, resp. the
  * identity); the learned search is for Algorithm 1's maps only.
- * Synchronises `stream`. */
+ * opts->pca = ADAGIO_PCA_RANDOMIZED takes the principal directions from
+ * adagio_pca_randomized with ell = s + 10 for the largest s the search has
+ * needed so far (recomputed when a probe needs more; ell = d gives the exact
+ * eigenbasis) and q = opts->pca_iters.  Synchronises `stream`. */
 int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed,
                const adagio_opts_t* opts, float* Pi_out, int32_t* r_out, int32_t* s_out,
                adagio_cert_t* cert_out, void* stream);

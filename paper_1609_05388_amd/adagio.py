@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libadagio.so")
 SCREEN = {"f32": 0, "bf16x3": 1, "fp8": 2}
 SEARCH = {"bisect": 0, "learned": 1}
 FAMILY = {"adagio": 0, "pca": 1, "jl": 2}
+PCA = {"exact": 0, "randomized": 1}
 
 
 class AdagioError(RuntimeError):
@@ -59,7 +60,8 @@ class Stats(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("screen", ctypes.c_int32), ("search", ctypes.c_int32),
                 ("max_candidates", ctypes.c_int32), ("family", ctypes.c_int32),
-                ("predictor", ctypes.c_void_p), ("stats", ctypes.POINTER(Stats))]
+                ("predictor", ctypes.c_void_p), ("stats", ctypes.POINTER(Stats)),
+                ("pca", ctypes.c_int32), ("pca_iters", ctypes.c_int32)]
 
 
 _lib = None
@@ -68,6 +70,7 @@ _lib = None
 _P, _I64, _I32, _U64, _D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
 SIGNATURES = {
     "adagio_pca": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _P]),
+    "adagio_pca_randomized": (ctypes.c_int, [_P, _I64, _I64, _I32, _I32, _U64, _P, _P, _P]),
     "adagio_project_axes": (ctypes.c_int, [_P, _I64, _I32, _U64, _P, _P]),
     "adagio_project": (ctypes.c_int, [_P, _I64, _I64, _I32, _U64, _P, _P]),
     "adagio_embed": (ctypes.c_int, [_P, _I64, _I64, _P, _I32, _P, _P]),
@@ -127,11 +130,14 @@ def _dev(t, dtype, name):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _opts(screen="f32", search="bisect", max_candidates=0, predictor=None, stats=None, family="adagio"):
+def _opts(screen="f32", search="bisect", max_candidates=0, predictor=None, stats=None, family="adagio",
+          pca="exact", pca_iters=2):
     o = Opts()
     o.screen = SCREEN[screen]
     o.search = SEARCH[search]
     o.family = FAMILY[family]
+    o.pca = PCA[pca]
+    o.pca_iters = int(pca_iters)
     o.max_candidates = int(max_candidates)
     o.predictor = ctypes.c_void_p(predictor.data_ptr()) if predictor is not None else None
     o.stats = ctypes.pointer(stats) if stats is not None else None
@@ -146,6 +152,17 @@ def pca(X):
     Vt = torch.empty((d, d), dtype=torch.float64, device=X.device)
     _check(lib.adagio_pca(_dev(X, torch.float32, "X"), n, d, _dev(lam, torch.float64, "lam"),
                           _dev(Vt, torch.float64, "Vt"), _stream()))
+    return lam, Vt
+
+
+def pca_randomized(X, ell, power_iters, seed):
+    """(lambda, Vt): ell approximate principal values and directions (rows), FP64."""
+    lib = load()
+    n, d = X.shape
+    lam = torch.empty(ell, dtype=torch.float64, device=X.device)
+    Vt = torch.empty((ell, d), dtype=torch.float64, device=X.device)
+    _check(lib.adagio_pca_randomized(_dev(X, torch.float32, "X"), n, d, int(ell), int(power_iters), int(seed),
+                                     _dev(lam, torch.float64, "lambda"), _dev(Vt, torch.float64, "Vt"), _stream()))
     return lam, Vt
 
 
@@ -211,14 +228,16 @@ def certify_map(X, Pi, screen="f32", max_candidates=0, with_stats=False):
     return out
 
 
-def fit(X, eps, seed, screen="f32", search="bisect", predictor=None, max_candidates=0, family="adagio"):
+def fit(X, eps, seed, screen="f32", search="bisect", predictor=None, max_candidates=0, family="adagio",
+        pca="exact", pca_iters=2):
     """Returns dict(Pi=(r x d tensor), r, s, k, cert, stats).  family: "adagio"
-    (Algorithm 1), "pca" or "jl" (Table 2's single-component maps)."""
+    (Algorithm 1), "pca" or "jl" (Table 2's single-component maps); pca:
+    "exact" or "randomized" (Sec. 4.5's variant, pca_iters power iterations)."""
     lib = load()
     n, d = X.shape
     Pi_buf = torch.empty((d, d), dtype=torch.float32, device=X.device)
     st = Stats()
-    o = _opts(screen, search, max_candidates, predictor, st, family)
+    o = _opts(screen, search, max_candidates, predictor, st, family, pca, pca_iters)
     r = ctypes.c_int32()
     s = ctypes.c_int32()
     c = Cert()

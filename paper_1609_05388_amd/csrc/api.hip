@@ -57,6 +57,7 @@ struct Workspace {
   DevBuf recs, tparts, seeds, seedv, list, cand, vals, vparts, cd;
   DevBuf Xb, txb, Yb, tyb, bjU, bjS;
   DevBuf Xq, sx, nxq, Yq, sy, nyq, q8terms, hist, kthr, gcache;
+  DevBuf rpQ, rpY, rpG, rpV, rpLam;
   DevBuf skpart, skG, skK, sklam, skV, skfeat, mlp_pb, mlp_X, mlp_f, mlp_hb, mlp_grad, mlp_loss;
   bool checked = false;
 };
@@ -249,12 +250,11 @@ static int jacobi_eig(Workspace& ws, double* A, int m, int64_t d, double* lam, d
   return sweep;
 }
 
-static Axes principal_axes(Workspace& ws, const Points& p, hipStream_t st, double* lam_out = nullptr,
-                           double* Vt_out = nullptr) {
+// C = sum_i (x_i - mu)(x_i - mu)^T into ws.A0 (m x m, zero padding; m = d
+// rounded up to a multiple of two Jacobi blocks).
+static double* covariance(Workspace& ws, const Points& p, int m, hipStream_t st) {
   const int64_t d = p.d;
-  // block Jacobi works on m = d rounded up to a multiple of two index blocks
-  const int m = (int)round_up(d, 2 * bj_block());
-  // covariance with split-K over points so that the grid fills the GPU
+  // split-K over points so that the grid fills the GPU
   const int64_t NT = (d + 63) / 64;
   const int64_t ntiles = NT * (NT + 1) / 2;
   int nsplit = (int)((2048 + ntiles - 1) / ntiles);
@@ -264,6 +264,54 @@ static Axes principal_axes(Workspace& ws, const Points& p, hipStream_t st, doubl
   double* part = ensure<double>(ws.covpart, (size_t)(nsplit * d * d));
   double* A = ensure<double>(ws.A0, (size_t)m * m);
   HIPCHK(launch_covariance(p.X, p.n, d, p.mu, part, nsplit, A, m, st));
+  return A;
+}
+
+// Randomized PCA (the paper's Sec. 4.5 variant, after Halko, Martinsson &
+// Tropp's randomized subspace iteration): a block of ell sign vectors Omega
+// (counter signs of the stream seed ^ kRpcaStream), Y = C Omega, then q times
+// Y = C Q with Q an orthonormal basis of the previous block, and the
+// Rayleigh-Ritz step on the last basis: the eigenpairs of Q^T C Q give ell
+// approximate principal directions (rows of Vt_out, decreasing value) and
+// values.  Bases are kept as rows (Q^T, ell x d); an orthonormal basis of a
+// block Y^T is Lambda^-1/2 V^T Y^T with Y^T Y = V Lambda V^T from the Jacobi
+// solver, applied twice (directions below 1e-24 of the largest are dropped).
+static const uint64_t kRpcaStream = 0x94D049BB133111EBull;
+static void randomized_axes(Workspace& ws, const double* C, int m, int64_t d, int64_t ell, int q, uint64_t seed,
+                            double* lam_out, double* Vt_out, hipStream_t st) {
+  const int mg = (int)round_up(ell, 2 * bj_block());
+  double* Qt = ensure<double>(ws.rpQ, (size_t)(ell * d));
+  double* Yt = ensure<double>(ws.rpY, (size_t)(ell * d));
+  double* G = ensure<double>(ws.rpG, (size_t)mg * mg);
+  double* V = ensure<double>(ws.rpV, (size_t)(ell * ell));
+  double* lam = ensure<double>(ws.rpLam, (size_t)ell);
+  auto orthonormal_rows = [&](double* src, double* dst) {   // dst = orth basis of the rows of src
+    HIPCHK(launch_gram_rows(src, (int)ell, d, G, mg, st));
+    jacobi_eig(ws, G, mg, ell, lam, V, st);
+    HIPCHK(launch_gemm_nn(V, ell, ell, ell, src, d, d, dst, d, st));
+    HIPCHK(launch_scale_rows_isqrt(dst, ell, d, lam, 1e-24, st));
+  };
+  HIPCHK(launch_jl_signs(seed ^ kRpcaStream, ell, d, Qt, st));            // Omega^T
+  for (int it = 0; it <= q; ++it) {
+    HIPCHK(launch_gemm_nt(Qt, ell, d, d, C, d, m, Yt, d, st));             // Y^T = Q^T C (C symmetric)
+    orthonormal_rows(Yt, Qt);
+    orthonormal_rows(Qt, Yt);
+    std::swap(Qt, Yt);
+  }
+  // Rayleigh-Ritz: B = Q^T C Q, its eigenvectors rotate the basis
+  HIPCHK(launch_gemm_nt(Qt, ell, d, d, C, d, m, Yt, d, st));               // Z^T = Q^T C
+  HIPCHK(hipMemsetAsync(G, 0, sizeof(double) * (size_t)mg * mg, st));
+  HIPCHK(launch_gemm_nt(Yt, ell, d, d, Qt, ell, d, G, mg, st));           // B = Z^T Q
+  jacobi_eig(ws, G, mg, ell, lam_out, V, st);
+  HIPCHK(launch_gemm_nn(V, ell, ell, ell, Qt, d, d, Vt_out, d, st));
+}
+
+static Axes principal_axes(Workspace& ws, const Points& p, hipStream_t st, double* lam_out = nullptr,
+                           double* Vt_out = nullptr) {
+  const int64_t d = p.d;
+  // block Jacobi works on m = d rounded up to a multiple of two index blocks
+  const int m = (int)round_up(d, 2 * bj_block());
+  double* A = covariance(ws, p, m, st);
   Axes ax;
   ax.lam = lam_out ? lam_out : ensure<double>(ws.lam, (size_t)d);
   ax.Vt = Vt_out ? Vt_out : ensure<double>(ws.Vt, (size_t)(d * d));
@@ -686,6 +734,23 @@ int adagio_pca(const float* X, int64_t n, int64_t d, double* lambda, double* Vt,
   });
 }
 
+int adagio_pca_randomized(const float* X, int64_t n, int64_t d, int32_t ell, int32_t power_iters, uint64_t seed,
+                          double* lambda, double* Vt, void* stream) {
+  return guarded([&] {
+    check_points(X, n, d);
+    ARGCHK(lambda && Vt, "lambda or Vt is NULL");
+    ARGCHK(ell >= 1 && ell <= d, "ell must be in [1, d]");
+    ARGCHK(power_iters >= 0 && power_iters <= 64, "power_iters must be in [0, 64]");
+    hipStream_t st = as_stream(stream);
+    Workspace& ws = workspace();
+    Points p = prep_points(ws, X, n, d, st);
+    const int m = (int)round_up(d, 2 * bj_block());
+    const double* C = covariance(ws, p, m, st);
+    randomized_axes(ws, C, m, d, ell, power_iters, seed, lambda, Vt, st);
+    HIPCHK(hipStreamSynchronize(st));
+  });
+}
+
 int adagio_project_axes(const double* Vt, int64_t d, int32_t r, uint64_t seed, float* Pi_out, void* stream) {
   return guarded([&] {
     ARGCHK(Vt && Pi_out, "Vt or Pi_out is NULL");
@@ -776,6 +841,10 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     const int search = opts ? opts->search : ADAGIO_SEARCH_BISECT;
     ARGCHK(search == ADAGIO_SEARCH_BISECT || search == ADAGIO_SEARCH_LEARNED, "unknown search");
     ARGCHK(search != ADAGIO_SEARCH_LEARNED || opts->predictor, "learned search needs opts->predictor");
+    const int pca = opts ? opts->pca : ADAGIO_PCA_EXACT;
+    const int pca_iters = opts ? opts->pca_iters : 0;
+    ARGCHK(pca == ADAGIO_PCA_EXACT || pca == ADAGIO_PCA_RANDOMIZED, "unknown PCA mode");
+    ARGCHK(pca_iters >= 0 && pca_iters <= 64, "pca_iters must be in [0, 64]");
     const int family = opts ? opts->family : ADAGIO_MAP_ADAGIO;
     ARGCHK(family == ADAGIO_MAP_ADAGIO || family == ADAGIO_MAP_PCA || family == ADAGIO_MAP_JL, "unknown map family");
     ARGCHK(family == ADAGIO_MAP_ADAGIO || search == ADAGIO_SEARCH_BISECT,
@@ -788,8 +857,27 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     e_pca.begin(st);
     Points p = prep_points(ws, X, n, d, st, screen);
     Axes ax;                         // the JL-only family needs no PCA
-    if (family != ADAGIO_MAP_JL) ax = principal_axes(ws, p, st);
+    const bool randomized = pca == ADAGIO_PCA_RANDOMIZED && family != ADAGIO_MAP_JL;
+    const int mc = (int)round_up(d, 2 * bj_block());
+    const double* Cov = nullptr;
+    if (randomized) {
+      Cov = covariance(ws, p, mc, st);
+      ax.lam = ensure<double>(ws.lam, (size_t)d);
+      ax.Vt = ensure<double>(ws.Vt, (size_t)(d * d));
+    } else if (family != ADAGIO_MAP_JL) {
+      ax = principal_axes(ws, p, st);
+    }
     e_pca.end(st);
+    // Randomized PCA: directions for the largest s needed so far plus 10.
+    const int64_t kOversample = 10;
+    int64_t ell_cur = 0;
+    auto need_axes = [&](int64_t r) {
+      if (!randomized) return;
+      const int64_t sn = family == ADAGIO_MAP_PCA ? r : (r == d ? d : r / 2);
+      if (sn == 0 || ell_cur == d || sn + kOversample <= ell_cur) return;
+      ell_cur = std::min<int64_t>(d, sn + kOversample);
+      randomized_axes(ws, Cov, mc, d, ell_cur, pca_iters, seed, ax.lam, ax.Vt, st);
+    };
     e_search.begin(st);
     float* Pi = ensure<float>(ws.Pi, (size_t)(d * d));
     CertTimes tm;
@@ -811,6 +899,7 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     float* gcache = nullptr;
     bool gready = false;
     auto probe = [&](int64_t r, int scr) {
+      need_axes(r);
       build_family_map(ws, family, ax.Vt, d, r, seed, Pi, st);
       Images im = images_of_map(ws, p, Pi, r, st);
       int gmode = 0;
@@ -867,6 +956,7 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
       bisect(rig);
     }
     if (!have_hi) {  // hi == d: no reduction (the full eigenbasis, or the identity)
+      need_axes(d);
       build_family_map(ws, family, ax.Vt, d, d, seed, Pi_out, st);
       Images im = images_of_map(ws, p, Pi_out, d, st);
       cert_hi = certificate(ws, p, im, cap0, st, &tm, rig);
@@ -981,7 +1071,8 @@ int adagio_release(void) {
                       &ws.W, &ws.trace, &ws.rot, &ws.lam, &ws.Vt, &ws.S, &ws.T, &ws.Pi, &ws.Pi64, &ws.Y64,
                       &ws.Yc, &ws.ny, &ws.ty, &ws.muY, &ws.recs, &ws.tparts, &ws.seeds, &ws.seedv, &ws.list,
                       &ws.cand, &ws.vals, &ws.vparts, &ws.cd, &ws.Xb, &ws.txb, &ws.Yb, &ws.tyb, &ws.bjU, &ws.bjS,
-                      &ws.Xq, &ws.sx, &ws.nxq, &ws.Yq, &ws.sy, &ws.nyq, &ws.q8terms, &ws.hist, &ws.kthr, &ws.gcache,
+                      &ws.Xq, &ws.sx, &ws.nxq, &ws.Yq, &ws.sy, &ws.nyq, &ws.q8terms, &ws.hist, &ws.kthr, &ws.gcache, &ws.rpQ, &ws.rpY,
+                      &ws.rpG, &ws.rpV, &ws.rpLam,
                       &ws.skpart, &ws.skG, &ws.skK, &ws.sklam, &ws.skV, &ws.skfeat, &ws.mlp_pb, &ws.mlp_X,
                       &ws.mlp_f, &ws.mlp_hb, &ws.mlp_grad, &ws.mlp_loss};
     for (DevBuf* b : bufs) {

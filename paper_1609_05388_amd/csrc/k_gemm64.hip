@@ -286,6 +286,45 @@ __global__ void k_sum_splits(const double* __restrict__ part, int nsplit, int64_
   out[e] = s;
 }
 
+// C (M x N, row stride ldc) = A B^T with A (M x K, row stride lda) and B
+// (N x K, row stride ldb), FP64.
+hipError_t launch_gemm_nt(const double* A, int64_t M, int64_t K, int64_t lda, const double* B, int64_t N,
+                          int64_t ldb, double* C, int64_t ldc, hipStream_t st) {
+  const int64_t tm = (M + GT - 1) / GT, tn = (N + GT - 1) / GT;
+  RowsF64 a{A, M, K, lda};
+  RowsF64T b{B, N, K, ldb};
+  StoreF64 c{C, M, N, ldc, 0};
+  k_gemm64<RowsF64, RowsF64T, StoreF64, true, true, false><<<(unsigned)(tm * tn), 256, 0, st>>>(a, b, c, M, N, K, round_up(K, GK), tn);
+  return hipGetLastError();
+}
+
+// C (M x N, row stride ldc) = A B with A (M x K, row stride lda) and B
+// (K x N, row stride ldb), FP64.
+hipError_t launch_gemm_nn(const double* A, int64_t M, int64_t K, int64_t lda, const double* B, int64_t N,
+                          int64_t ldb, double* C, int64_t ldc, hipStream_t st) {
+  const int64_t tm = (M + GT - 1) / GT, tn = (N + GT - 1) / GT;
+  RowsF64 a{A, M, K, lda};
+  RowsF64N b{B, K, N, ldb};
+  StoreF64 c{C, M, N, ldc, 0};
+  k_gemm64<RowsF64, RowsF64N, StoreF64, true, false, false><<<(unsigned)(tm * tn), 256, 0, st>>>(a, b, c, M, N, K, round_up(K, GK), tn);
+  return hipGetLastError();
+}
+
+// Row i of Q (rows x cols) times lam_i^(-1/2), or 0 where lam_i <= rel lam_0
+// (lam decreasing: directions the block does not span).
+__global__ void k_scale_rows_isqrt(double* __restrict__ Q, int64_t rows, int64_t cols, const double* __restrict__ lam,
+                                   double rel) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= rows * cols) return;
+  const double l = lam[e / cols];
+  Q[e] = l > rel * lam[0] ? Q[e] / sqrt(l) : 0.0;
+}
+hipError_t launch_scale_rows_isqrt(double* Q, int64_t rows, int64_t cols, const double* lam, double rel,
+                                   hipStream_t st) {
+  k_scale_rows_isqrt<<<(unsigned)((rows * cols + 255) / 256), 256, 0, st>>>(Q, rows, cols, lam, rel);
+  return hipGetLastError();
+}
+
 hipError_t launch_sketch(const float* X, int64_t n, int64_t d, const double* mu, int m, uint64_t sseed, double* part,
                          int nsplit, double* G, hipStream_t st) {
   const int64_t tm = (m + GT - 1) / GT, tn = (d + GT - 1) / GT;

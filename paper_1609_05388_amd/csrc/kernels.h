@@ -77,6 +77,15 @@ hipError_t launch_flag_tiles(const TileRec* recs, int64_t ntiles, CertDev* cd, u
 hipError_t launch_top2(const PairVal* vals, const uint32_t* count_ptr, uint32_t cap, PairVal* part, int nparts,
                        CertDev* cd, hipStream_t st);
 
+// k_gemm64.hip (general FP64 products of the randomized PCA)
+hipError_t launch_gemm_nt(const double* A, int64_t M, int64_t K, int64_t lda, const double* B, int64_t N,
+                          int64_t ldb, double* C, int64_t ldc, hipStream_t st);
+hipError_t launch_gemm_nn(const double* A, int64_t M, int64_t K, int64_t lda, const double* B, int64_t N,
+                          int64_t ldb, double* C, int64_t ldc, hipStream_t st);
+// Q row i times lam_i^(-1/2), zero where lam_i <= rel lam_0 (lam decreasing).
+hipError_t launch_scale_rows_isqrt(double* Q, int64_t rows, int64_t cols, const double* lam, double rel,
+                                   hipStream_t st);
+
 // k_gemm64.hip (sketch)
 // G = Omega Xc (m x d, FP64) with Omega[a][i] = +-1/sqrt(m) from SplitMix64
 // output (a << 32 | i) + 1 of seed `sseed`; split over points, partials summed.
