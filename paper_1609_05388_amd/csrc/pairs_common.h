@@ -1,6 +1,8 @@
 // Pieces shared by the all-pairs screen kernels (FP32 and BF16x3 Grams):
 // tile enumeration, the per-pair bounds of the epilogue, arg-reductions.
 #pragma once
+#include <type_traits>
+
 #include "common.h"
 
 namespace adg {
@@ -126,37 +128,44 @@ __device__ inline void tile_epilogue(const f32x16 (&accX)[2][2], const f32x16 (&
   float best_hi = -1.0f, best_lo = 3.0e38f;
   int code_hi = -1, code_lo = -1;
   const float4 tb0 = termB[wc * 64 + li], tb1 = termB[wc * 64 + 32 + li];
+  // The pass over the thread's 64 pairs, compiled once with the edge mask and
+  // once without (the mask is uniform per tile: no per-pair branch).
+  auto scan = [&](auto maskc) __attribute__((always_inline)) {
+    constexpr bool M = decltype(maskc)::value;
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int rl = wr * 64 + x * 32 + (v >> 2) * 8 + lh * 4 + (v & 3);
-      const float4 ta = termA[rl];
+      for (int v = 0; v < 16; ++v) {
+        const int rl = wr * 64 + x * 32 + (v >> 2) * 8 + lh * 4 + (v & 3);
+        const float4 ta = termA[rl];
 #pragma unroll
-      for (int y = 0; y < 2; ++y) {
-        float qhi, qlo;
-        pair_bounds(accX[x][y][v], accY[x][y][v], ta, y ? tb1 : tb0, qhi, qlo);
-        if (masked) {
-          const int cl = wc * 64 + y * 32 + li;
-          const bool valid = (I < J || rl < cl) && col0 + cl < p.n;
-          if (!valid) { qhi = -1.0f; qlo = 3.0e38f; }
-        }
-        if (MODE == 0) {
-          const int code = (x * 2 + y) * 16 + v;
-          if (qhi > best_hi) { best_hi = qhi; code_hi = code; }
-          if (qlo < best_lo) { best_lo = qlo; code_lo = code; }
-          // Pin the running arg-extremes here: otherwise the compiler first
-          // evaluates all 64 pairs (128 live values) and spills.
-          asm volatile("" : "+v"(best_hi), "+v"(code_hi), "+v"(best_lo), "+v"(code_lo));
-        } else {
-          if (qhi >= thr_hi || qlo <= thr_lo) {
-            const uint32_t pos = atomicAdd(p.ncand, 1u);
+        for (int y = 0; y < 2; ++y) {
+          float qhi, qlo;
+          pair_bounds(accX[x][y][v], accY[x][y][v], ta, y ? tb1 : tb0, qhi, qlo);
+          if (M) {
             const int cl = wc * 64 + y * 32 + li;
-            if (pos < p.cap) p.cand[pos] = make_int2(row0 + rl, col0 + cl);
+            const bool valid = (I < J || rl < cl) && col0 + cl < p.n;
+            if (!valid) { qhi = -1.0f; qlo = 3.0e38f; }
+          }
+          if (MODE == 0) {
+            const int code = (x * 2 + y) * 16 + v;
+            if (qhi > best_hi) { best_hi = qhi; code_hi = code; }
+            if (qlo < best_lo) { best_lo = qlo; code_lo = code; }
+            // Pin the running arg-extremes here: otherwise the compiler first
+            // evaluates all 64 pairs (128 live values) and spills.
+            asm volatile("" : "+v"(best_hi), "+v"(code_hi), "+v"(best_lo), "+v"(code_lo));
+          } else {
+            if (qhi >= thr_hi || qlo <= thr_lo) {
+              const uint32_t pos = atomicAdd(p.ncand, 1u);
+              const int cl = wc * 64 + y * 32 + li;
+              if (pos < p.cap) p.cand[pos] = make_int2(row0 + rl, col0 + cl);
+            }
           }
         }
       }
-    }
+  };
+  if (masked) scan(std::integral_constant<bool, true>{});
+  else scan(std::integral_constant<bool, false>{});
 
   if (MODE == 0) {
     auto decode = [&](int code, int& gi, int& gj) {
