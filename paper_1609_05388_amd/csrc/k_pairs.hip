@@ -27,6 +27,8 @@
 // b mod 8, so slot = (b mod 8) * (G / 8) + b / 8 gives every XCD a contiguous
 // run of super-tiles: the ~64 workgroups resident on an XCD work on one
 // super-tile and share its 8 row panels and 8 column panels in that XCD's L2.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 #include "pairs_common.h"
@@ -38,8 +40,11 @@ constexpr int PK = kChunk;  // 16
 constexpr int PLD = 20;     // LDS row stride in floats (conflict-free b128 reads)
 
 
-template <int MODE>
-__global__ __launch_bounds__(256, 2) void k_pairs_f32(PairsArgs p) {
+// LOADED (MODE 0 only): the point Gram comes from the cache; the kernel runs
+// the image chunks only and loads the point-Gram accumulators after them, so
+// far fewer registers are live in its loop and three workgroups fit a CU.
+template <int MODE, bool LOADED>
+__global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_f32(PairsArgs p) {
   __shared__ __attribute__((aligned(16))) float As[2][PT * PLD];
   __shared__ __attribute__((aligned(16))) float Bs[2][PT * PLD];
   __shared__ float4 termA[PT], termB[PT];
@@ -147,31 +152,32 @@ __global__ __launch_bounds__(256, 2) void k_pairs_f32(PairsArgs p) {
     // Two loops with fixed accumulators (one selected per chunk would make
     // the compiler copy the other set); the prefetch runs across the seam.
     // With a loaded point Gram the pipeline starts at the first image chunk.
-    const bool gload = MODE == 0 && p.gmode == 2;
     const int64_t tix = (int64_t)I * p.NT - (int64_t)I * (I - 1) / 2 + (J - I);
-    const int c0 = gload ? p.nchx : 0;
+    const int c0 = LOADED ? p.nchx : 0;
     fetch(c0);
     stash(c0 & 1);
     __syncthreads();
-    for (int c = c0; c < p.nchx; ++c) {
-      const int buf = c & 1;
-      if (c + 1 < total) fetch(c + 1);
-      mma(accX, buf);
-      if (c + 1 < total) stash(buf ^ 1);
-      __syncthreads();
+    if (!LOADED) {
+      for (int c = 0; c < p.nchx; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < total) fetch(c + 1);
+        mma(accX, buf);
+        if (c + 1 < total) stash(buf ^ 1);
+        __syncthreads();
+      }
     }
     for (int c = p.nchx; c < total; ++c) {
       const int buf = c & 1;
       if (c + 1 < total) fetch(c + 1);
-      // the cached point Gram, issued after the last prefetch so that the
-      // chunk loads before it complete first; it lands during the last MFMAs
-      if (gload && c == (total - 2 > p.nchx ? total - 2 : p.nchx)) gcache_load(p.gcache, tix, accX);
       mma(accY, buf);
       if (c + 1 < total) stash(buf ^ 1);
       __syncthreads();
     }
-    // stored after the image loop: earlier stores would hold up its chunk loads
-    if (MODE == 0 && p.gmode == 1) gcache_store(p.gcache, tix, accX);
+    // the cached point Gram after the loop, where its accumulators become
+    // live; stores after the image loop too (earlier they would hold up its
+    // chunk loads, which the vector-memory counter completes in issue order)
+    if (LOADED) gcache_load(p.gcache, tix, accX);
+    if (!LOADED && MODE == 0 && p.gmode == 1) gcache_store(p.gcache, tix, accX);
 
     tile_epilogue<MODE>(accX, accY, termA, termB, I, J, p, thr_hi, thr_lo, red_v, red_i, red_j);
     if (MODE == 0) return;
@@ -187,7 +193,8 @@ hipError_t launch_pairs_screen(const PairsView& v, TileRec* recs, float* gcache,
   PairsArgs a{v.X, v.ldx, v.ldx / PK, v.Y, v.ldy, v.ldy / PK, v.tx, v.ty, v.n, v.NT, v.ntiles,
               NS, nslots, recs, nullptr, nullptr, nullptr, 0u, nullptr, gcache, gcache ? gmode : 0};
   const int64_t G = round_up(nslots, 8);
-  k_pairs_f32<0><<<(unsigned)G, 256, 0, st>>>(a);
+  if (a.gmode == 2) k_pairs_f32<0, true><<<(unsigned)G, 256, 0, st>>>(a);
+  else k_pairs_f32<0, false><<<(unsigned)G, 256, 0, st>>>(a);
   return hipGetLastError();
 }
 
@@ -195,7 +202,7 @@ hipError_t launch_pairs_emit(const PairsView& v, const uint32_t* list, const Cer
                              uint32_t cap, uint32_t* ncand, int grid, hipStream_t st) {
   PairsArgs a{v.X, v.ldx, v.ldx / PK, v.Y, v.ldy, v.ldy / PK, v.tx, v.ty, v.n, v.NT, v.ntiles,
               0, 0, nullptr, list, cd, cand, cap, ncand, nullptr, 0};
-  k_pairs_f32<1><<<(unsigned)grid, 256, 0, st>>>(a);
+  k_pairs_f32<1, false><<<(unsigned)grid, 256, 0, st>>>(a);
   return hipGetLastError();
 }
 
