@@ -22,6 +22,11 @@ What it computes, each step following the paper (Blasiok & Tsourakakis,
                      Table 2), by bisection over r.
 * ``mlp``         -- FP64 forward/backward of the learned dimension predictor
                      (a method extension; not in the paper).
+* ``sketch``      -- the predictor's input features (a method extension).
+* ``fp8``         -- the e4m3 operand encoding of the FP8 screen (OCP FP8).
+* ``rpca``        -- the randomized PCA of Sec. 4.5's Adagio-Randomized-PCA.
+* ``knn``         -- exact k-nearest-neighbour queries and the majority vote
+                     of Sec. 5's applications.
 
 Readings of the paper where it is silent or garbled are listed in each
 module header.

@@ -106,3 +106,60 @@ def instance_params(index, held_out=False):
     rank = int(min(rng.integers(10, 201), d))
     eps = float(rng.uniform(0.05, 0.3))
     return {"seed": seed, "n": n, "d": d, "alpha": alpha, "rank": rank, "eps": eps}
+
+
+def sift_shaped(buildings=201, photos=4, per_photo=500, per_query=100, proto=300, clutter=3000,
+                latent=32, own=0.5, noise=0.04, seed=DATA_SEED):
+    """SIFT-shaped descriptors of a building-retrieval workload (the image
+    retrieval experiment of Sec. 5's nearest-neighbour queries): ``buildings``
+    objects, ``photos`` database photos of ``per_photo`` descriptors each and
+    one query photo of ``per_query`` descriptors per object, all in R^128.
+
+    A descriptor is a prototype seen with noise.  Prototypes are
+    sift(relu(A z)) with z ~ N(0, 1)^latent and A a 128 x latent Gaussian
+    matrix whose column j is scaled by (j + 1)^-0.7, so that most variance
+    sits in a few dozen directions as for real SIFT; sift(v) is SIFT's own
+    normalisation: unit length, entries clipped at 0.2, unit length again.
+    Each object owns ``proto`` prototypes; a pool of ``clutter`` prototypes
+    is shared by all objects.  A photo draws a fraction ``own`` of its
+    descriptors from its object's prototypes and the rest from the pool (both
+    uniformly), and each descriptor is round(512 sift(relu(p + noise e))),
+    e ~ N(0, 1)^128, as integers in FP32.
+
+    Returns (D, d_label, Q, q_image): the database (buildings * photos *
+    per_photo x 128, object by object, photo by photo), the object of each
+    database row, the queries (buildings * per_query x 128, object by
+    object) and the object of each query row.
+    Draw order: A, object prototypes, pool, then per object: database photos
+    (choices, pool choices, noise) and the query photo (same)."""
+    rng = np.random.default_rng(seed)
+    m = 128
+    A = rng.standard_normal((m, latent)) * (np.arange(1, latent + 1, dtype=np.float64) ** -0.7)
+
+    def sift(v):
+        v = v / np.maximum(np.linalg.norm(v, axis=-1, keepdims=True), 1e-12)
+        v = np.minimum(v, 0.2)
+        return v / np.maximum(np.linalg.norm(v, axis=-1, keepdims=True), 1e-12)
+
+    def protos(cnt):
+        return sift(np.maximum(rng.standard_normal((cnt, latent)) @ A.T, 0.0))
+
+    P = protos(buildings * proto).reshape(buildings, proto, m)
+    pool = protos(clutter)
+
+    def photo(b, cnt):
+        n_own = int(round(own * cnt))
+        src = np.concatenate([P[b][rng.integers(0, proto, n_own)], pool[rng.integers(0, clutter, cnt - n_own)]])
+        e = rng.standard_normal((cnt, m))
+        return np.round(512.0 * sift(np.maximum(src + noise * e, 0.0)))
+
+    D, Q = [], []
+    for b in range(buildings):
+        for _ in range(photos):
+            D.append(photo(b, per_photo))
+        Q.append(photo(b, per_query))
+    D = np.concatenate(D).astype(np.float32)
+    Q = np.concatenate(Q).astype(np.float32)
+    d_label = np.repeat(np.arange(buildings, dtype=np.int32), photos * per_photo)
+    q_image = np.repeat(np.arange(buildings, dtype=np.int32), per_query)
+    return D, d_label, Q, q_image
