@@ -249,6 +249,49 @@ int adagio_mlp_grad(const float* params, const float* feats, const float* target
 int adagio_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t step, float lr, const float* feats,
                           const float* targets, int32_t B, float tau, float* loss, void* stream);
 
+/* Timings and counts of one adagio_knn call. */
+typedef struct adagio_knn_stats {
+    double t_total_ms;       /* host wall time of the call                          */
+    double t_prep_ms;        /* padded copies and row norms (device events)         */
+    double t_screen_ms;      /* the FP32 MFMA screen (device events)                */
+    double t_finish_ms;      /* candidate merge, FP64 rescoring, checks (events)    */
+    double t_fallback_ms;    /* FP64 brute force of listed queries (events)         */
+    int32_t splits;          /* database splits of the screen                       */
+    int32_t n_fallback;      /* queries answered by the FP64 brute force            */
+    int64_t reserved[4];
+} adagio_knn_stats_t;
+
+/* f4.  Exact k-nearest-neighbour queries, the operation of Sec. 5's
+ * applications: the 10-NN query of each descriptor of a query photo in the
+ * image-retrieval experiment (Q = query descriptors, D = the database) and the
+ * k = 30 nearest-neighbour graph of the classification experiment (Q = D,
+ * exclude_self = 1), on original or embedded points.
+ * Q: device nq x m FP32, D: device nd x m FP32, both dense row-major.  For
+ * every query i the k database rows with the smallest squared distance
+ * sum_l (q_l - x_l)^2, each difference, square and sum in FP64 in coordinate
+ * order, equal distances ordered by the smaller row index; with
+ * exclude_self = 1 query i skips database row i (nq <= nd).  1 <= k <= 32 and
+ * k <= nd - exclude_self.  idx_out: device nq x k int32, dist_out: device
+ * nq x k FP64, both ordered by (distance, index).  The answer is exact: an
+ * FP32 MFMA screen keeps 32 candidates per query, and a query for which the
+ * screen's error bound cannot prove that no other row enters the k best is
+ * answered by FP64 brute force (stats_out->n_fallback counts them).
+ * stats_out: host, may be NULL.  NaN or Inf inputs return ADAGIO_E_NONFINITE.
+ * Synchronises `stream`. */
+int adagio_knn(const float* Q, int64_t nq, const float* D, int64_t nd, int64_t m, int32_t k, int32_t exclude_self,
+               int32_t* idx_out, double* dist_out, adagio_knn_stats_t* stats_out, void* stream);
+
+/* f4.  Majority vote of the image-retrieval experiment (Sec. 5): queries come
+ * in groups of `group` consecutive rows (one query photo; the last group may
+ * be shorter); every neighbour in nn_idx (device nq x k int32, database row
+ * indices) adds a vote to its label d_label[row] (device nd int32, in
+ * [0, n_labels), n_labels <= 8192); label_out[g] (device, ceil(nq / group)
+ * int32) is the label with most votes in group g, the smallest label among
+ * ties (the paper draws at random among tied labels).  An index or label out
+ * of range returns ADAGIO_E_INVALID_ARG.  Synchronises `stream`. */
+int adagio_knn_vote(const int32_t* nn_idx, int64_t nq, int32_t k, const int32_t* d_label, int64_t nd,
+                    int32_t n_labels, int32_t group, int32_t* label_out, void* stream);
+
 /* Frees the cached device workspace of the current device. */
 int adagio_release(void);
 

@@ -57,6 +57,16 @@ class Stats(ctypes.Structure):
         return out
 
 
+class KnnStats(ctypes.Structure):
+    _fields_ = [("t_total_ms", ctypes.c_double), ("t_prep_ms", ctypes.c_double),
+                ("t_screen_ms", ctypes.c_double), ("t_finish_ms", ctypes.c_double),
+                ("t_fallback_ms", ctypes.c_double), ("splits", ctypes.c_int32),
+                ("n_fallback", ctypes.c_int32), ("reserved", ctypes.c_int64 * 4)]
+
+    def to_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
 class Opts(ctypes.Structure):
     _fields_ = [("screen", ctypes.c_int32), ("search", ctypes.c_int32),
                 ("max_candidates", ctypes.c_int32), ("family", ctypes.c_int32),
@@ -88,6 +98,8 @@ SIGNATURES = {
     "adagio_mlp_grad": (ctypes.c_int, [_P, _P, _P, _I32, ctypes.c_float, _P, _P, _P]),
     "adagio_mlp_train_step": (ctypes.c_int, [_P, _P, _P, _I32, ctypes.c_float, _P, _P, _I32, ctypes.c_float,
                                              _P, _P]),
+    "adagio_knn": (ctypes.c_int, [_P, _I64, _P, _I64, _I64, _I32, _I32, _P, _P, ctypes.POINTER(KnnStats), _P]),
+    "adagio_knn_vote": (ctypes.c_int, [_P, _I64, _I32, _P, _I64, _I32, _I32, _P, _P]),
     "adagio_release": (ctypes.c_int, []),
     "adagio_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "adagio_last_error": (ctypes.c_char_p, []),
@@ -310,6 +322,35 @@ def mlp_train_step(params, adam_m, adam_v, step, lr, feats, targets, tau):
                                      _dev(feats, torch.float32, "feats"), _dev(targets, torch.float32, "targets"),
                                      B, float(tau), _dev(loss, torch.float32, "loss"), _stream()))
     return loss
+
+
+def knn(Q, D, k, exclude_self=False):
+    """(idx, dist, stats): the k nearest rows of D (device nd x m FP32) to each
+    row of Q (device nq x m FP32), int32 indices and FP64 squared distances,
+    ordered by (distance, index)."""
+    lib = load()
+    nq, m = Q.shape
+    nd, m2 = D.shape
+    if m != m2:
+        raise ValueError("Q and D need the same number of columns")
+    idx = torch.empty((nq, k), dtype=torch.int32, device=Q.device)
+    dist = torch.empty((nq, k), dtype=torch.float64, device=Q.device)
+    st = KnnStats()
+    _check(lib.adagio_knn(_dev(Q, torch.float32, "Q"), nq, _dev(D, torch.float32, "D"), nd, m, int(k),
+                          int(bool(exclude_self)), _dev(idx, torch.int32, "idx"), _dev(dist, torch.float64, "dist"),
+                          ctypes.byref(st), _stream()))
+    return idx, dist, st.to_dict()
+
+
+def knn_vote(nn_idx, d_label, n_labels, group):
+    """Majority label per group of ``group`` consecutive queries (int32)."""
+    lib = load()
+    nq, k = nn_idx.shape
+    out = torch.empty((nq + group - 1) // group, dtype=torch.int32, device=nn_idx.device)
+    _check(lib.adagio_knn_vote(_dev(nn_idx, torch.int32, "nn_idx"), nq, k, _dev(d_label, torch.int32, "d_label"),
+                               d_label.shape[0], int(n_labels), int(group), _dev(out, torch.int32, "out"),
+                               _stream()))
+    return out
 
 
 def release():

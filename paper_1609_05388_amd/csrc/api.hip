@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/adagio.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -59,6 +60,7 @@ struct Workspace {
   DevBuf Xq, sx, nxq, Yq, sy, nyq, q8terms, hist, kthr, gcache;
   DevBuf rpQ, rpY, rpG, rpV, rpLam;
   DevBuf skpart, skG, skK, sklam, skV, skfeat, mlp_pb, mlp_X, mlp_f, mlp_hb, mlp_grad, mlp_loss;
+  DevBuf knQ, knD, knNq64, knNd64, knNq32, knNd32, knMax, knKeys, knFb, knCnt;
   bool checked = false;
 };
 
@@ -1061,6 +1063,111 @@ int adagio_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t s
   });
 }
 
+int adagio_knn(const float* Q, int64_t nq, const float* D, int64_t nd, int64_t m, int32_t k, int32_t exclude_self,
+               int32_t* idx_out, double* dist_out, adagio_knn_stats_t* stats_out, void* stream) {
+  return guarded([&] {
+    auto t0 = std::chrono::steady_clock::now();
+    ARGCHK(Q && D && idx_out && dist_out, "NULL pointer");
+    ARGCHK(nq >= 1 && nd >= 1 && m >= 1, "need nq, nd, m >= 1");
+    ARGCHK(nd <= ((int64_t)1 << 31) - 2 && nq <= ((int64_t)1 << 31) - 2, "nq and nd must be below 2^31 - 1");
+    ARGCHK(m <= ((int64_t)1 << 20), "m must be at most 2^20");
+    ARGCHK(k >= 1 && k <= kKnnKeep, "k must be in [1, 32]");
+    ARGCHK(exclude_self == 0 || exclude_self == 1, "exclude_self must be 0 or 1");
+    ARGCHK(!exclude_self || nq <= nd, "exclude_self needs nq <= nd (query i is database row i)");
+    ARGCHK(k <= nd - exclude_self, "k exceeds the number of database rows");
+    hipStream_t st = as_stream(stream);
+    Workspace& ws = workspace();
+    const int64_t K = round_up(m, kChunk);
+    const int64_t nq_pad = round_up(nq, kTile), nd_pad = round_up(nd, kTile);
+    KnnView v;
+    float* Qp = ensure<float>(ws.knQ, (size_t)(nq_pad * K));
+    float* Dp = ensure<float>(ws.knD, (size_t)(nd_pad * K));
+    double* nq64 = ensure<double>(ws.knNq64, (size_t)nq_pad);
+    double* nd64 = ensure<double>(ws.knNd64, (size_t)nd_pad);
+    float* nq32 = ensure<float>(ws.knNq32, (size_t)nq_pad);
+    float* nd32 = ensure<float>(ws.knNd32, (size_t)nd_pad);
+    double* ndmax = ensure<double>(ws.knMax, 1);
+    int* cnt = ensure<int>(ws.knCnt, 2);   // [0] non-finite flag, [1] listed queries
+    int* fb = ensure<int>(ws.knFb, (size_t)nq);
+    EvPair e_prep, e_screen, e_finish, e_fb;
+    e_prep.begin(st);
+    HIPCHK(hipMemsetAsync(cnt, 0, 2 * sizeof(int), st));
+    HIPCHK(launch_knn_prep(Q, nq, m, nq_pad, K, Qp, nq64, nq32, cnt, st));
+    HIPCHK(launch_knn_prep(D, nd, m, nd_pad, K, Dp, nd64, nd32, cnt, st));
+    HIPCHK(launch_knn_max(nd64, nd, ndmax, st));
+    e_prep.end(st);
+    int flags[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(flags, cnt, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (flags[0]) {
+      set_err("input contains NaN or Inf%s%lld", "", 0);
+      throw Fail{ADAGIO_E_NONFINITE};
+    }
+    v.Qp = Qp; v.Dp = Dp; v.K = K; v.m = m; v.nq32 = nq32; v.nd32 = nd32; v.nq = nq; v.nd = nd;
+    v.QB = (int)(nq_pad / kTile);
+    v.NTd = (int)(nd_pad / kTile);
+    v.excl = exclude_self;
+    // Splits of the database: enough workgroups to fill the chip several
+    // times over, at most kKnnMaxSplits, every split non-empty.
+    int S = (int)std::min<int64_t>({(int64_t)kKnnMaxSplits, (int64_t)v.NTd, std::max<int64_t>(1, (4096 + v.QB - 1) / v.QB)});
+    v.tps = (v.NTd + S - 1) / S;
+    v.S = (v.NTd + v.tps - 1) / v.tps;
+    uint64_t* keys = ensure<uint64_t>(ws.knKeys, (size_t)nq_pad * v.S * kKnnKeep);
+    e_screen.begin(st);
+    HIPCHK(launch_knn_screen(v, keys, st));
+    e_screen.end(st);
+    // |est - d| <= c_K (N_q + N_x): the screen constant of an FP32 Gram of K terms;
+    // the FP64 sums of m squares are within (m + 4) u64 (relative) of d.
+    const double cK = ((double)K + 32.0) * kU32 * 1.001;
+    const double g64 = ((double)m + 4.0) * kU64 * 1.01;
+    e_finish.begin(st);
+    HIPCHK(launch_knn_finish(v, keys, Q, D, nq64, ndmax, cK, g64, k, idx_out, dist_out, cnt + 1, fb, st));
+    e_finish.end(st);
+    HIPCHK(hipMemcpyAsync(flags + 1, cnt + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const int nfb = flags[1];
+    double t_fb = 0.0;
+    if (nfb > 0) {
+      e_fb.begin(st);
+      HIPCHK(launch_knn_fallback(Q, D, m, nd, k, exclude_self, fb, nfb, idx_out, dist_out, st));
+      e_fb.end(st);
+      HIPCHK(hipStreamSynchronize(st));
+      t_fb = e_fb.ms();
+    }
+    if (stats_out) {
+      adagio_knn_stats_t o;
+      memset(&o, 0, sizeof(o));
+      o.splits = v.S;
+      o.n_fallback = nfb;
+      o.t_prep_ms = e_prep.ms();
+      o.t_screen_ms = e_screen.ms();
+      o.t_finish_ms = e_finish.ms();
+      o.t_fallback_ms = t_fb;
+      o.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      *stats_out = o;
+    }
+  });
+}
+
+int adagio_knn_vote(const int32_t* nn_idx, int64_t nq, int32_t k, const int32_t* d_label, int64_t nd,
+                    int32_t n_labels, int32_t group, int32_t* label_out, void* stream) {
+  return guarded([&] {
+    ARGCHK(nn_idx && d_label && label_out, "NULL pointer");
+    ARGCHK(nq >= 1 && nd >= 1 && k >= 1, "need nq, nd, k >= 1");
+    ARGCHK(n_labels >= 1 && n_labels <= 8192, "n_labels must be in [1, 8192]");
+    ARGCHK(group >= 1, "group must be >= 1");
+    hipStream_t st = as_stream(stream);
+    Workspace& ws = workspace();
+    int* bad = ensure<int>(ws.knCnt, 2);
+    HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), st));
+    HIPCHK(launch_knn_vote(nn_idx, nq, k, d_label, nd, n_labels, group, label_out, bad, st));
+    int h = 0;
+    HIPCHK(hipMemcpyAsync(&h, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    ARGCHK(!h, "a neighbour index or label is out of range");
+  });
+}
+
 int adagio_release(void) {
   return guarded([&] {
     int dev = 0;
@@ -1074,7 +1181,8 @@ int adagio_release(void) {
                       &ws.Xq, &ws.sx, &ws.nxq, &ws.Yq, &ws.sy, &ws.nyq, &ws.q8terms, &ws.hist, &ws.kthr, &ws.gcache, &ws.rpQ, &ws.rpY,
                       &ws.rpG, &ws.rpV, &ws.rpLam,
                       &ws.skpart, &ws.skG, &ws.skK, &ws.sklam, &ws.skV, &ws.skfeat, &ws.mlp_pb, &ws.mlp_X,
-                      &ws.mlp_f, &ws.mlp_hb, &ws.mlp_grad, &ws.mlp_loss};
+                      &ws.mlp_f, &ws.mlp_hb, &ws.mlp_grad, &ws.mlp_loss, &ws.knQ, &ws.knD, &ws.knNq64,
+                      &ws.knNd64, &ws.knNq32, &ws.knNd32, &ws.knMax, &ws.knKeys, &ws.knFb, &ws.knCnt};
     for (DevBuf* b : bufs) {
       if (b->p) HIPCHK(hipFree(b->p));
       b->p = nullptr;

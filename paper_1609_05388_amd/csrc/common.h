@@ -26,6 +26,11 @@ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // FP32 values of a tile's point Gram in the screens' point-Gram cache.
 constexpr int64_t kGcacheFloatsPerTile = (int64_t)kTile * kTile;
 
+// kNN screen: candidates kept per query and database split, and the most
+// splits one query's keys may span.
+constexpr int kKnnKeep = 32;
+constexpr int kKnnMaxSplits = 32;
+
 // One tile record of the screen: the largest upper bound on the squared
 // distance ratio q = E^2 / D^2 in the tile with its pair, and the smallest
 // lower bound with its pair.  Pairs are global point indices, i < j.

@@ -1,0 +1,531 @@
+// Exact k-nearest-neighbour queries, the operation behind Sec. 5's
+// applications: the 10-NN query of every descriptor of a query photo in the
+// image-retrieval experiment and the 30-NN graph of the classification
+// experiment.  For every query q the answer is the k database rows x with the
+// smallest FP64 squared distance ||q - x||^2, summed coordinate by
+// coordinate, equal distances ordered by the smaller database index.
+//
+// Stage 1, k_knn_screen: tiles of 128 database rows x 128 queries on
+//   v_mfma_f32_32x32x2f32 give est = N_q + N_x - 2 q.x (FP32 norms of the FP64
+//   squared norms).  A workgroup scans one split of the database for one block
+//   of 128 queries and keeps, per query, the KP = 32 smallest estimates as
+//   64-bit keys (order-preserving bits of est, then the database index).
+//   Candidates below the query's current 32nd key go to an LDS queue; the
+//   queue is merged into the sorted list when any query's queue holds more
+//   than 32 entries, so a sub-step (32 candidates per query) never overflows.
+// Stage 2, k_knn_finish (one wave per query): the KP smallest keys over all
+//   splits, their exact FP64 distances, the k best by (distance, index), and a
+//   check that no row outside the KP can enter the answer:
+//     |est - d| <= c_K (N_q + N_x) <= c_K (N_q + max_x N_x) =: beta
+//   for every estimate (FP32 rounding of the norms, gamma_K of the MFMA dot
+//   product, the add and the fma), so every row not kept has
+//   d >= est_KP - beta; the FP64 sums themselves are within (m + 4) u64 of d.
+//   A query whose k-th distance is not strictly below that bound is listed.
+// Stage 3, k_knn_fallback: listed queries by FP64 brute force over the whole
+//   database (same distance arithmetic, same order), one workgroup each.
+//
+// Layout: queries and database rows are copied to row-padded FP32 panels of
+// width K = m rounded up to 16 (zero columns and rows); keys of the screen are
+// [query][split][KP].  Workgroup b runs on XCD b mod 8; slot =
+// (b mod 8) * (G / 8) + b / 8 and slot = split * QB + query block, so the
+// workgroups resident on one XCD scan the same database split and share its
+// tiles in that XCD's L2.
+#include "common.h"
+#include "kernels.h"
+
+namespace adg {
+
+constexpr int KN_T = 128;     // rows per tile side
+constexpr int KN_C = 16;      // chunk width
+constexpr int KN_LD = 20;     // LDS operand row stride (floats)
+constexpr int KN_QC = 64;     // queue capacity per query
+constexpr int KN_LST = kKnnKeep + 1;  // padded list row (u64)
+constexpr int KN_QST = KN_QC + 1;     // padded queue row (u64)
+constexpr uint64_t kKnnEmpty = (0xFF800000ull << 32) | 0xFFFFFFFFull;  // key of (+inf, no row)
+
+struct KnnLds {
+  float As[2][KN_T * KN_LD];  // database chunk
+  float Bs[2][KN_T * KN_LD];  // query chunk
+  float nq[KN_T], nd[KN_T];
+  float tau[KN_T];
+  int cnt[KN_T];
+  int flag, pad0, pad1, pad2;
+  uint64_t L[KN_T * KN_LST];
+  uint64_t Qu[KN_T * KN_QST];
+};
+
+__device__ inline uint64_t knn_key(float e, uint32_t row) {
+  uint32_t b = __float_as_uint(e);
+  b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+  return ((uint64_t)b << 32) | row;
+}
+__device__ inline float knn_key_est(uint64_t k) {
+  uint32_t b = (uint32_t)(k >> 32);
+  b = (b & 0x80000000u) ? (b & 0x7fffffffu) : ~b;
+  return __uint_as_float(b);
+}
+
+// Padded FP32 copy of rows [0, n) (zero rows up to n_pad), FP64 and FP32
+// squared norms; one wave per row.
+__global__ __launch_bounds__(256) void k_knn_prep(const float* __restrict__ src, int64_t n, int64_t m,
+                                                  int64_t n_pad, int64_t K, float* __restrict__ dst,
+                                                  double* __restrict__ n64, float* __restrict__ n32,
+                                                  int* __restrict__ nonfinite) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n_pad) return;
+  double s = 0.0;
+  for (int64_t l = lane; l < K; l += 64) {
+    const float v = (row < n && l < m) ? src[row * m + l] : 0.0f;
+    dst[row * K + l] = v;
+    s += (double)v * (double)v;
+  }
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) {
+    n64[row] = s;
+    n32[row] = (float)s;
+    if (!isfinite(s)) atomicOr(nonfinite, 1);
+  }
+}
+
+// Largest FP64 norm, one workgroup.
+__global__ __launch_bounds__(1024) void k_knn_max(const double* __restrict__ v, int64_t n, double* __restrict__ out) {
+  __shared__ double part[16];
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) m = fmax(m, v[i]);
+  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 16; ++w) m = fmax(m, part[w]);
+    *out = fmax(m, part[0]);
+  }
+}
+
+struct KnnScreenArgs {
+  const float* D; const float* Q; int K; int nch;
+  const float* nd32; const float* nq32;
+  int64_t nd; int QB; int S; int tps; int NTd; int excl;
+  uint64_t* keys;   // [nq_pad][S][KP]
+};
+
+__global__ __launch_bounds__(256, 1) void k_knn_screen(KnnScreenArgs p) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char knn_lds_raw[];
+  KnnLds& sm = *reinterpret_cast<KnnLds*>(knn_lds_raw);
+
+  const uint32_t G = gridDim.x;
+  const int64_t slot = (int64_t)(blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  if (slot >= (int64_t)p.QB * p.S) return;
+  const int s = (int)(slot / p.QB), qb = (int)(slot % p.QB);
+  const int t0 = s * p.tps, t1 = min(p.NTd, t0 + p.tps);
+  const int q0 = qb * KN_T;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int li = lane & 31, lh = lane >> 5;
+
+  if (tid < KN_T) {
+    sm.nq[tid] = p.nq32[q0 + tid];
+    sm.tau[tid] = __uint_as_float(0x7f800000u);
+    sm.cnt[tid] = 0;
+  }
+  if (tid == 0) sm.flag = 0;
+  for (int e = tid; e < KN_T * KN_LST; e += 256) sm.L[e] = kKnnEmpty;
+
+  const int lr = tid >> 2, lc = (tid & 3) * 4;
+  const float* qa = p.Q + (size_t)(q0 + lr) * p.K + lc;
+  const size_t q64 = (size_t)64 * p.K, d64 = (size_t)64 * p.K;
+  float4 ga0, ga1, gb0, gb1;
+  // chunk g of the scan: tile t0 + g / nch, columns (g mod nch) * 16
+  auto fetch = [&](int g) __attribute__((always_inline)) {
+    const int t = t0 + g / p.nch, cb = (g % p.nch) * KN_C;
+    const float* da = p.D + (size_t)(t * KN_T + lr) * p.K + lc + cb;
+    ga0 = *reinterpret_cast<const float4*>(da);
+    ga1 = *reinterpret_cast<const float4*>(da + d64);
+    gb0 = *reinterpret_cast<const float4*>(qa + cb);
+    gb1 = *reinterpret_cast<const float4*>(qa + q64 + cb);
+  };
+  auto stash = [&](int buf) __attribute__((always_inline)) {
+    *reinterpret_cast<float4*>(&sm.As[buf][lr * KN_LD + lc]) = ga0;
+    *reinterpret_cast<float4*>(&sm.As[buf][(lr + 64) * KN_LD + lc]) = ga1;
+    *reinterpret_cast<float4*>(&sm.Bs[buf][lr * KN_LD + lc]) = gb0;
+    *reinterpret_cast<float4*>(&sm.Bs[buf][(lr + 64) * KN_LD + lc]) = gb1;
+  };
+
+  const int gend = (t1 - t0) * p.nch;
+  fetch(0);
+  stash(0);
+  // the lane's two query columns
+  const int qc0 = wc * 64 + li, qc1 = wc * 64 + 32 + li;
+  __syncthreads();
+  const float nq0 = sm.nq[qc0], nq1 = sm.nq[qc1];
+  float tau0 = sm.tau[qc0], tau1 = sm.tau[qc1];
+
+  for (int t = t0; t < t1; ++t) {
+    const int row0 = t * KN_T;
+    if (tid < KN_T) sm.nd[tid] = p.nd32[row0 + tid];
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) acc[x][y] = (f32x16){0};
+    const int gb = (t - t0) * p.nch;
+    for (int c = 0; c < p.nch; ++c) {
+      const int g = gb + c, buf = g & 1;
+      if (g + 1 < gend) fetch(g + 1);
+      // MFMA step kk sums chunk columns kk (lanes 0-31) and 8 + kk (lanes
+      // 32-63), the same permutation for both operands.
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        float4 a4[2], b4[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          a4[x] = *reinterpret_cast<const float4*>(&sm.As[buf][(wr * 64 + x * 32 + li) * KN_LD + lh * 8 + half * 4]);
+          b4[x] = *reinterpret_cast<const float4*>(&sm.Bs[buf][(wc * 64 + x * 32 + li) * KN_LD + lh * 8 + half * 4]);
+        }
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+          for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+              acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[x][kk], b4[y][kk], acc[x][y], 0, 0, 0);
+      }
+      if (g + 1 < gend) stash(buf ^ 1);
+      __syncthreads();
+    }
+
+    // Edge tiles: rows past the database end, and with exclude-self the tile
+    // whose rows are this block's queries (row0 == q0).
+    const bool masked = (row0 + KN_T > p.nd) || (p.excl && row0 == q0);
+    // D layout: lane l, register v -> row (v / 4) * 8 + (l / 32) * 4 + v % 4,
+    // column l % 32.  Sub-step s takes registers 4s .. 4s + 3 of both row
+    // blocks: 8 candidates per lane and query, 32 per query.
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int stamp = (t - t0) * 4 + st + 1;
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv) {
+          const int v = st * 4 + vv;
+          const int rl = wr * 64 + x * 32 + st * 8 + lh * 4 + vv;
+          const float ndr = sm.nd[rl];
+#pragma unroll
+          for (int y = 0; y < 2; ++y) {
+            float est = fmaf(-2.0f, acc[x][y][v], (y ? nq1 : nq0) + ndr);
+            if (masked) {
+              const int64_t rg = row0 + rl;
+              const int qg = q0 + (y ? qc1 : qc0);
+              if (rg >= p.nd || (p.excl && rg == qg)) est = __uint_as_float(0x7f800000u);
+            }
+            if (est < (y ? tau1 : tau0)) {
+              const int qc = y ? qc1 : qc0;
+              const int pos = atomicAdd(&sm.cnt[qc], 1);
+              sm.Qu[qc * KN_QST + pos] = knn_key(est, (uint32_t)(row0 + rl));
+              if (pos >= KN_QC - 32) sm.flag = stamp;
+            }
+          }
+        }
+      __syncthreads();
+      // The flag holds the stamp of the last sub-step that asked for a merge.
+      // Stamps increase, so a thread that is still reading it after others
+      // went on to the next sub-step (possible only when no merge is due)
+      // sees a later stamp, not its own: every thread takes the same branch.
+      if (sm.flag == stamp) {
+        if (tid < KN_T) {
+          const int c = sm.cnt[tid];
+          sm.cnt[tid] = 0;
+          uint64_t* Lq = &sm.L[tid * KN_LST];
+          const uint64_t* Qq = &sm.Qu[tid * KN_QST];
+          uint64_t last = Lq[kKnnKeep - 1];
+          for (int i = 0; i < c; ++i) {
+            const uint64_t kv = Qq[i];
+            if (kv >= last) continue;
+            int pp = 0;
+#pragma unroll
+            for (int step = kKnnKeep / 2; step > 0; step >>= 1)
+              if (Lq[pp + step - 1] < kv) pp += step;
+            for (int j = kKnnKeep - 1; j > pp; --j) Lq[j] = Lq[j - 1];
+            Lq[pp] = kv;
+            last = Lq[kKnnKeep - 1];
+          }
+          sm.tau[tid] = knn_key_est(last);
+        }
+        __syncthreads();
+        tau0 = sm.tau[qc0];
+        tau1 = sm.tau[qc1];
+      }
+    }
+  }
+
+  // Queued entries that never triggered a merge.
+  if (tid < KN_T) {
+    const int c = sm.cnt[tid];
+    uint64_t* Lq = &sm.L[tid * KN_LST];
+    const uint64_t* Qq = &sm.Qu[tid * KN_QST];
+    uint64_t last = Lq[kKnnKeep - 1];
+    for (int i = 0; i < c; ++i) {
+      const uint64_t kv = Qq[i];
+      if (kv >= last) continue;
+      int pp = 0;
+#pragma unroll
+      for (int step = kKnnKeep / 2; step > 0; step >>= 1)
+        if (Lq[pp + step - 1] < kv) pp += step;
+      for (int j = kKnnKeep - 1; j > pp; --j) Lq[j] = Lq[j - 1];
+      Lq[pp] = kv;
+      last = Lq[kKnnKeep - 1];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < KN_T * kKnnKeep; e += 256) {
+    const int q = e / kKnnKeep, i = e % kKnnKeep;
+    p.keys[((size_t)(q0 + q) * p.S + s) * kKnnKeep + i] = sm.L[q * KN_LST + i];
+  }
+}
+
+// FP64 squared distance of two FP32 rows, difference, square and sum in
+// coordinate order, one rounding each (no contraction).
+__device__ inline double knn_dist64(const float* __restrict__ a, const float* __restrict__ b, int64_t m) {
+#pragma clang fp contract(off)
+  double s = 0.0;
+  for (int64_t l = 0; l < m; ++l) {
+    const double df = (double)a[l] - (double)b[l];
+    const double sq = df * df;
+    s = s + sq;
+  }
+  return s;
+}
+
+__device__ inline bool knn_less(double da, int ia, double db, int ib) {
+  return da < db || (da == db && ia < ib);
+}
+
+struct KnnFinishArgs {
+  const uint64_t* keys; int S;
+  const float* Q; const float* D; int64_t m;
+  int64_t nq; int k;
+  const double* nq64; const double* ndmax;
+  double cK;     // screen bound constant c_K
+  double g64;    // relative bound of the FP64 sums
+  int32_t* idx; double* dist;
+  int* nfb; int* fb;
+};
+
+__global__ __launch_bounds__(256) void k_knn_finish(KnnFinishArgs p) {
+  const int lane = threadIdx.x & 63;
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= p.nq) return;
+  // the KP smallest of the S * KP keys: lane-local pools, KP wave minima
+  constexpr int PER = kKnnMaxSplits * kKnnKeep / 64;
+  uint64_t kv[PER];
+  const int tot = p.S * kKnnKeep;
+  const uint64_t* src = p.keys + (size_t)q * tot;
+#pragma unroll
+  for (int t = 0; t < PER; ++t) {
+    const int e = lane + 64 * t;
+    kv[t] = e < tot ? src[e] : ~0ull;
+  }
+  uint64_t mine = ~0ull;
+  for (int r = 0; r < kKnnKeep; ++r) {
+    uint64_t lm = kv[0];
+#pragma unroll
+    for (int t = 1; t < PER; ++t) lm = kv[t] < lm ? kv[t] : lm;
+    uint64_t wm = lm;
+    for (int o = 32; o >= 1; o >>= 1) {
+      const uint64_t w2 = __shfl_xor(wm, o, 64);
+      wm = w2 < wm ? w2 : wm;
+    }
+    if (lane == r) mine = wm;
+    if (lm == wm) {
+      // remove one copy (real keys are unique; empty keys may repeat)
+      bool done = false;
+#pragma unroll
+      for (int t = 0; t < PER; ++t)
+        if (!done && kv[t] == wm) { kv[t] = ~0ull; done = true; }
+    }
+  }
+  const uint64_t klast = __shfl(mine, kKnnKeep - 1, 64);
+  const bool valid = lane < kKnnKeep && mine != ~0ull && (uint32_t)mine != 0xFFFFFFFFu;
+  const int row = valid ? (int)(uint32_t)mine : 0x7fffffff;
+  const double d = valid ? knn_dist64(p.Q + q * p.m, p.D + (int64_t)row * p.m, p.m) : __longlong_as_double(0x7ff0000000000000ll);
+  int rank = 0;
+  for (int j = 0; j < kKnnKeep; ++j) {
+    const double dj = __shfl(d, j, 64);
+    const int ij = __shfl(row, j, 64);
+    rank += knn_less(dj, ij, d, row) ? 1 : 0;
+  }
+  if (lane < kKnnKeep && rank < p.k) {
+    p.idx[q * p.k + rank] = row;
+    p.dist[q * p.k + rank] = d;
+  }
+  // k-th distance: the largest of the k smallest
+  double dk = (lane < kKnnKeep && rank < p.k) ? d : -1.0;
+  for (int o = 32; o >= 1; o >>= 1) dk = fmax(dk, __shfl_xor(dk, o, 64));
+  if (lane == 0) {
+    const float e_last = knn_key_est(klast);
+    bool ok = true;
+    if ((uint32_t)klast != 0xFFFFFFFFu && klast != ~0ull) {
+      const double beta = p.cK * (p.nq64[q] + *p.ndmax);
+      const double lower = ((double)e_last - beta) * (1.0 - p.g64);
+      ok = lower > dk;
+    }
+    if (!ok) {
+      const int at = atomicAdd(p.nfb, 1);
+      p.fb[at] = (int)q;
+    }
+  }
+}
+
+// FP64 brute force for listed queries: each thread keeps the k best of its
+// rows (sorted by (distance, index)) in LDS, then k rounds of a block-wide
+// minimum over the threads' list heads.
+struct KnnFallbackArgs {
+  const float* Q; const float* D; int64_t m; int64_t nd; int k; int excl;
+  const int* fb; int32_t* idx; double* dist;
+};
+
+__global__ __launch_bounds__(256) void k_knn_fallback(KnnFallbackArgs p) {
+  __shared__ double ld[kKnnKeep][256];
+  __shared__ int li[kKnnKeep][256];
+  __shared__ double rv[4];
+  __shared__ int ri[4], rt[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t q = p.fb[blockIdx.x];
+  const float* qrow = p.Q + q * p.m;
+  int cnt = 0;
+  double worst = __longlong_as_double(0x7ff0000000000000ll);
+  for (int64_t j = tid; j < p.nd; j += 256) {
+    if (p.excl && j == q) continue;
+    const double d = knn_dist64(qrow, p.D + j * p.m, p.m);
+    if (cnt == p.k && !(d < worst)) continue;   // later rows lose ties
+    int pos = cnt < p.k ? cnt : p.k - 1;
+    while (pos > 0 && d < ld[pos - 1][tid]) {
+      ld[pos][tid] = ld[pos - 1][tid];
+      li[pos][tid] = li[pos - 1][tid];
+      --pos;
+    }
+    ld[pos][tid] = d;
+    li[pos][tid] = (int)j;
+    if (cnt < p.k) ++cnt;
+    worst = cnt == p.k ? ld[p.k - 1][tid] : worst;
+  }
+  int head = 0;
+  for (int r = 0; r < p.k; ++r) {
+    double v = head < cnt ? ld[head][tid] : __longlong_as_double(0x7ff0000000000000ll);
+    int vi = head < cnt ? li[head][tid] : 0x7fffffff;
+    int vt = tid;
+    for (int o = 32; o >= 1; o >>= 1) {
+      const double v2 = __shfl_xor(v, o, 64);
+      const int i2 = __shfl_xor(vi, o, 64), t2 = __shfl_xor(vt, o, 64);
+      if (knn_less(v2, i2, v, vi)) { v = v2; vi = i2; vt = t2; }
+    }
+    if (lane == 0) { rv[wave] = v; ri[wave] = vi; rt[wave] = vt; }
+    __syncthreads();
+    double bv = rv[0];
+    int bi = ri[0], bt = rt[0];
+    for (int w = 1; w < 4; ++w)
+      if (knn_less(rv[w], ri[w], bv, bi)) { bv = rv[w]; bi = ri[w]; bt = rt[w]; }
+    if (tid == bt) ++head;
+    if (tid == 0) {
+      p.idx[q * p.k + r] = bi;
+      p.dist[q * p.k + r] = bv;
+    }
+    __syncthreads();
+  }
+}
+
+// Majority vote per group of consecutive queries (one workgroup per group):
+// each neighbour adds a vote to its database label; the answer is the label
+// with most votes, the smallest label among ties.  Indices or labels out of
+// range set *bad and are not counted.
+__global__ __launch_bounds__(256) void k_knn_vote(const int32_t* __restrict__ nn, int64_t nq, int k,
+                                                  const int32_t* __restrict__ label, int64_t nd, int n_labels,
+                                                  int group, int32_t* __restrict__ out, int* __restrict__ bad) {
+  extern __shared__ int hist[];
+  __shared__ int bc[4], bl[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < n_labels; i += 256) hist[i] = 0;
+  __syncthreads();
+  const int64_t a = (int64_t)blockIdx.x * group, b = min(nq, a + group);
+  for (int64_t e = a * k + tid; e < b * k; e += 256) {
+    const int32_t j = nn[e];
+    if (j < 0 || j >= nd) { atomicOr(bad, 1); continue; }
+    const int32_t lab = label[j];
+    if (lab < 0 || lab >= n_labels) { atomicOr(bad, 1); continue; }
+    atomicAdd(&hist[lab], 1);
+  }
+  __syncthreads();
+  int c = -1, l = 0x7fffffff;
+  for (int i = tid; i < n_labels; i += 256)
+    if (hist[i] > c) { c = hist[i]; l = i; }   // i increases: first maximum kept
+  for (int o = 32; o >= 1; o >>= 1) {
+    const int c2 = __shfl_xor(c, o, 64), l2 = __shfl_xor(l, o, 64);
+    if (c2 > c || (c2 == c && l2 < l)) { c = c2; l = l2; }
+  }
+  if (lane == 0) { bc[wave] = c; bl[wave] = l; }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < 4; ++w)
+      if (bc[w] > c || (bc[w] == c && bl[w] < l)) { c = bc[w]; l = bl[w]; }
+    out[blockIdx.x] = l;
+  }
+}
+
+// ------------------------------------------------------------ launchers
+hipError_t launch_knn_prep(const float* src, int64_t n, int64_t m, int64_t n_pad, int64_t K, float* dst,
+                           double* n64, float* n32, int* nonfinite, hipStream_t st) {
+  k_knn_prep<<<(unsigned)((n_pad + 3) / 4), 256, 0, st>>>(src, n, m, n_pad, K, dst, n64, n32, nonfinite);
+  return hipGetLastError();
+}
+
+hipError_t launch_knn_max(const double* v, int64_t n, double* out, hipStream_t st) {
+  k_knn_max<<<1, 1024, 0, st>>>(v, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_knn_screen(const KnnView& v, uint64_t* keys, hipStream_t st) {
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_knn_screen),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(KnnLds));
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  KnnScreenArgs a;
+  a.D = v.Dp; a.Q = v.Qp; a.K = (int)v.K; a.nch = (int)(v.K / KN_C);
+  a.nd32 = v.nd32; a.nq32 = v.nq32;
+  a.nd = v.nd; a.QB = v.QB; a.S = v.S; a.tps = v.tps; a.NTd = v.NTd; a.excl = v.excl;
+  a.keys = keys;
+  const int64_t G = round_up((int64_t)v.QB * v.S, 8);
+  k_knn_screen<<<(unsigned)G, 256, sizeof(KnnLds), st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_knn_finish(const KnnView& v, const uint64_t* keys, const float* Q, const float* D,
+                             const double* nq64, const double* ndmax, double cK, double g64, int k,
+                             int32_t* idx, double* dist, int* nfb, int* fb, hipStream_t st) {
+  KnnFinishArgs a;
+  a.keys = keys; a.S = v.S; a.Q = Q; a.D = D; a.m = v.m; a.nq = v.nq; a.k = k;
+  a.nq64 = nq64; a.ndmax = ndmax; a.cK = cK; a.g64 = g64;
+  a.idx = idx; a.dist = dist; a.nfb = nfb; a.fb = fb;
+  k_knn_finish<<<(unsigned)((v.nq + 3) / 4), 256, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_knn_fallback(const float* Q, const float* D, int64_t m, int64_t nd, int k, int excl, const int* fb,
+                               int nfb, int32_t* idx, double* dist, hipStream_t st) {
+  KnnFallbackArgs a{Q, D, m, nd, k, excl, fb, idx, dist};
+  k_knn_fallback<<<(unsigned)nfb, 256, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_knn_vote(const int32_t* nn, int64_t nq, int k, const int32_t* label, int64_t nd, int n_labels,
+                           int group, int32_t* out, int* bad, hipStream_t st) {
+  const int64_t groups = (nq + group - 1) / group;
+  k_knn_vote<<<(unsigned)groups, 256, (size_t)n_labels * sizeof(int), st>>>(nn, nq, k, label, nd, n_labels, group,
+                                                                              out, bad);
+  return hipGetLastError();
+}
+
+}  // namespace adg

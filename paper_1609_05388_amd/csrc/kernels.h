@@ -140,4 +140,24 @@ hipError_t mlp_adam(float* p, __bf16* pb, const float* g, float* m, float* v, in
                     hipStream_t st);
 hipError_t mlp_to_bf16(const float* src, __bf16* dst, int64_t count, hipStream_t st);
 
+// k_knn.hip
+struct KnnView {
+  const float* Qp; const float* Dp;  // padded panels, row stride K
+  int64_t K, m;                      // padded and true widths
+  const float* nq32; const float* nd32;
+  int64_t nq, nd;
+  int QB, S, tps, NTd, excl;
+};
+hipError_t launch_knn_prep(const float* src, int64_t n, int64_t m, int64_t n_pad, int64_t K, float* dst,
+                           double* n64, float* n32, int* nonfinite, hipStream_t st);
+hipError_t launch_knn_max(const double* v, int64_t n, double* out, hipStream_t st);
+hipError_t launch_knn_screen(const KnnView& v, uint64_t* keys, hipStream_t st);
+hipError_t launch_knn_finish(const KnnView& v, const uint64_t* keys, const float* Q, const float* D,
+                             const double* nq64, const double* ndmax, double cK, double g64, int k,
+                             int32_t* idx, double* dist, int* nfb, int* fb, hipStream_t st);
+hipError_t launch_knn_fallback(const float* Q, const float* D, int64_t m, int64_t nd, int k, int excl, const int* fb,
+                               int nfb, int32_t* idx, double* dist, hipStream_t st);
+hipError_t launch_knn_vote(const int32_t* nn, int64_t nq, int k, const int32_t* label, int64_t nd, int n_labels,
+                           int group, int32_t* out, int* bad, hipStream_t st);
+
 }  // namespace adg

@@ -49,7 +49,7 @@ def test_struct_layouts_match_header():
     from paper_1609_05388_amd import adagio
     text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
     for cname, py in (("adagio_cert", adagio.Cert), ("adagio_stats", adagio.Stats),
-                      ("adagio_opts", adagio.Opts)):
+                      ("adagio_opts", adagio.Opts), ("adagio_knn_stats", adagio.KnnStats)):
         body = re.search(r"typedef struct %s \{(.*?)\}" % cname, text, flags=re.S).group(1)
         fields = []
         for decl in body.split(";"):
@@ -67,7 +67,7 @@ def test_struct_offsets_match_c_compiler(tmp_path):
     from paper_1609_05388_amd import adagio
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "adagio.h"', "int main(void) {"]
     for ctype, py in (("adagio_cert_t", adagio.Cert), ("adagio_stats_t", adagio.Stats),
-                      ("adagio_opts_t", adagio.Opts)):
+                      ("adagio_opts_t", adagio.Opts), ("adagio_knn_stats_t", adagio.KnnStats)):
         lines.append('printf("%%zu\\n", sizeof(%s));' % ctype)
         for f, _ in py._fields_:
             lines.append('printf("%%zu\\n", offsetof(%s, %s));' % (ctype, f))
@@ -79,7 +79,7 @@ def test_struct_offsets_match_c_compiler(tmp_path):
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = []
-    for py in (adagio.Cert, adagio.Stats, adagio.Opts):
+    for py in (adagio.Cert, adagio.Stats, adagio.Opts, adagio.KnnStats):
         want.append(ctypes.sizeof(py))
         want.extend(getattr(py, f).offset for f, _ in py._fields_)
     assert got == want
@@ -115,3 +115,11 @@ def test_invalid_arguments_rejected_without_gpu(lib):
     o = adagio.Opts()
     o.screen = 7
     assert lib.adagio_certify_map(fake, 10, 8, fake, 3, ctypes.byref(o), ctypes.byref(c), None) == -1
+    # kNN: k out of range, exclude_self with more queries than rows, NULL output
+    ks = adagio.KnnStats()
+    assert lib.adagio_knn(fake, 10, fake, 10, 4, 0, 0, fake, fake, ctypes.byref(ks), None) == -1
+    assert lib.adagio_knn(fake, 10, fake, 10, 4, 33, 0, fake, fake, ctypes.byref(ks), None) == -1
+    assert lib.adagio_knn(fake, 11, fake, 10, 4, 3, 1, fake, fake, ctypes.byref(ks), None) == -1
+    assert lib.adagio_knn(fake, 10, fake, 10, 4, 3, 0, None, fake, ctypes.byref(ks), None) == -1
+    assert lib.adagio_knn_vote(fake, 10, 3, fake, 10, 0, 5, fake, None) == -1
+    assert lib.adagio_knn_vote(fake, 10, 3, fake, 10, 4, 0, fake, None) == -1
