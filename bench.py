@@ -264,6 +264,7 @@ def knn_form(adagio, gen, torch, rs=(128, 64, 32, 24, 20, 16, 12, 8, 4)):
     the embedding of database and queries, exact 10-NN of every query, the
     majority vote per query photo and its accuracy; also the 30-NN graph of
     50,000 database rows.  The screen's roofline is taken at r = 128."""
+    import numpy as np
     D, dl, Q, qi = gen.sift_shaped()
     nb = int(qi.max()) + 1
     per_q = len(Q) // nb
