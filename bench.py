@@ -62,7 +62,9 @@ def traffic_per_launch(kind):
     return rec.get("hbm_bytes_per_launch", {}).get(kind)
 
 
-TRAFFIC_KERNEL = "adg::k_pairs_f32<0>"
+TRAFFIC_KERNEL = "adg::k_pairs_f32<0"
+FULL_KERNEL = "adg::k_pairs_f32<0, false>"     # point Gram computed (and stored)
+CACHED_KERNEL = "adg::k_pairs_f32<0, true>"    # point Gram loaded
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 COPY_BYTES = 1 << 30
 
@@ -89,12 +91,13 @@ def summarize_traffic(d):
     out = {}
     for c in ("FETCH_SIZE", "WRITE_SIZE"):
         copy = pick(per_kernel(os.path.join(d, "copy_%s_counter_collection.csv" % c)), COPY_KERNEL)
-        kern = pick(per_kernel(os.path.join(d, "fit_%s_counter_collection.csv" % c)), TRAFFIC_KERNEL)
+        agg = per_kernel(os.path.join(d, "fit_%s_counter_collection.csv" % c))
+        full, cached = pick(agg, FULL_KERNEL), pick(agg, CACHED_KERNEL)
         factor = COPY_BYTES / (sum(copy) / len(copy))
         out[c] = {"copy_counter_bytes": sum(copy) / len(copy), "factor": factor,
-                  "full_launch_bytes": kern[0] * factor,
-                  "cached_launch_bytes": (sum(kern[1:]) / len(kern[1:]) * factor) if len(kern) > 1 else None,
-                  "launches": len(kern)}
+                  "full_launch_bytes": sum(full) / len(full) * factor,
+                  "cached_launch_bytes": (sum(cached) / len(cached) * factor) if cached else None,
+                  "launches": len(full) + len(cached)}
     hb = {"full": out["FETCH_SIZE"]["full_launch_bytes"] + out["WRITE_SIZE"]["full_launch_bytes"]}
     if out["FETCH_SIZE"]["cached_launch_bytes"] is not None:
         hb["cached"] = out["FETCH_SIZE"]["cached_launch_bytes"] + out["WRITE_SIZE"]["cached_launch_bytes"]
@@ -109,9 +112,9 @@ def summarize_traffic(d):
             "(the same two with WRITE_SIZE)",
             "python3 <repo>/bench.py --summarize-traffic <repo>/gpurun_out/pmc",
         ],
-        "note": "counter bytes are KiB x 1024 per dispatch; one fit: its first screen launch (point Gram "
-                "computed and stored) and the mean of the others (point Gram loaded); each counter is scaled "
-                "by the factor that maps its reading for a plain 1 GiB copy to 1 GiB",
+        "note": "counter bytes are KiB x 1024 per dispatch; one fit: the mean of its k_pairs_f32<0, false> "
+                "launches (point Gram computed and stored) and of its k_pairs_f32<0, true> launches (point Gram "
+                "loaded); each counter is scaled by the factor that maps its reading for a plain 1 GiB copy to 1 GiB",
     }
     print(json.dumps(rec, indent=1))
 
@@ -260,8 +263,9 @@ def knn_form(adagio, gen, torch, rs=(128, 64, 32, 24, 20, 16, 12, 8, 4)):
     """Sec. 5's image retrieval on the SIFT-shaped workload (201 objects, a
     402,000 x 128 database of 4 photos x 500 descriptors each, 20,100 query
     descriptors of one photo per object): at each target dimension r the
-    ADAGIO map of the database (PCA of the database, r = 128 = no reduction),
-    the embedding of database and queries, exact 10-NN of every query, the
+    ADAGIO map of the database and, beside it, the PCA-only map (both from
+    the PCA of the database; r = 128 = no reduction), the embedding of
+    database and queries, exact 10-NN of every query, the
     majority vote per query photo and its accuracy; also the 30-NN graph of
     50,000 database rows.  The screen's roofline is taken at r = 128."""
     import numpy as np
@@ -274,11 +278,11 @@ def knn_form(adagio, gen, torch, rs=(128, 64, 32, 24, 20, 16, 12, 8, 4)):
     adagio.knn(Qd, Dd, 10)                       # warm-up of the workspace
     rows = []
     roof = None
-    for r in rs:
-        if r >= D.shape[1]:
+    for r, fam in [(r, f) for r in rs for f in (("none",) if r >= D.shape[1] else ("adagio", "pca"))]:
+        if fam == "none":
             YD, YQ = Dd, Qd
         else:
-            Pi = adagio.project_axes(Vt, r, gen.JL_SEED)
+            Pi = adagio.project_family(Vt, r, fam, gen.JL_SEED)
             YD, YQ = adagio.embed(Dd, Pi), adagio.embed(Qd, Pi)
         torch.cuda.synchronize()
         best = None
@@ -292,11 +296,11 @@ def knn_form(adagio, gen, torch, rs=(128, 64, 32, 24, 20, 16, 12, 8, 4)):
         pred = adagio.knn_vote(idx, dld, nb, per_q).cpu().numpy()
         acc = float((pred == np.arange(nb)).mean())
         t, st = best
-        rows.append({"r": r, "knn_ms": t, "screen_ms": st["t_screen_ms"], "finish_ms": st["t_finish_ms"],
+        rows.append({"r": r, "map": fam, "knn_ms": t, "screen_ms": st["t_screen_ms"], "finish_ms": st["t_finish_ms"],
                      "fallback_ms": st["t_fallback_ms"], "n_fallback": st["n_fallback"], "accuracy": acc,
                      "correct": int((pred == np.arange(nb)).sum()), "splits": st["splits"]})
-        log("knn r=%d: %.2f ms (screen %.2f), accuracy %.3f, fallbacks %d" % (r, t, st["t_screen_ms"], acc,
-                                                                              st["n_fallback"]))
+        log("knn r=%d %s: %.2f ms (screen %.2f), accuracy %.3f, fallbacks %d" % (r, fam, t, st["t_screen_ms"], acc,
+                                                                                 st["n_fallback"]))
         if r == rs[0]:
             fl = 2.0 * D.shape[1] * len(Q) * len(D)
             roof = {"kernel": "k_knn_screen", "m": D.shape[1], "flops_per_launch": fl,
@@ -408,7 +412,7 @@ def main():
     traffic = traffic_per_launch(dom)
     roofline = {"bound": "mfma", "achieved": launch_kinds[dom]["tflops"], "peak": PEAK_FP32_MFMA_TFLOPS,
                 "unit": "TFLOP/s", "frac": launch_kinds[dom]["frac"], "traffic": traffic,
-                "kernel": "k_pairs_f32<0> (all-pairs screen), %s launches" % dom,
+                "kernel": "k_pairs_f32<0, %s> (all-pairs screen), %s launches" % ("true" if dom == "cached" else "false", dom),
                 "launches": launch_kinds[dom]["launches"], "avg_launch_ms": launch_kinds[dom]["avg_launch_ms"],
                 "flops_per_launch": launch_kinds[dom]["flops_per_launch"], "launch_kinds": launch_kinds}
 

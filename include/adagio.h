@@ -149,6 +149,14 @@ int adagio_pca_randomized(const float* X, int64_t n, int64_t d, int32_t ell, int
  * eigenvalue).  Pi_out: device r x d FP32.  Asynchronous. */
 int adagio_project_axes(const double* Vt, int64_t d, int32_t r, uint64_t seed, float* Pi_out, void* stream);
 
+/* f3.  The map of one family at a fixed r from the same sorted axes (the
+ * rows compared in Table 2): ADAGIO_MAP_ADAGIO is adagio_project_axes's map,
+ * ADAGIO_MAP_PCA the top r rows of Vt, ADAGIO_MAP_JL the r x d +-1/sqrt(r)
+ * sign matrix of Lemma 1 (the identity at r = d).  Vt: device d x d FP64;
+ * Pi_out: device r x d FP32.  Asynchronous. */
+int adagio_project_family(const double* Vt, int64_t d, int32_t r, int32_t family, uint64_t seed, float* Pi_out,
+                          void* stream);
+
 /* a1-a5.  Algorithm 1 at a fixed target dimension r (the fixed-r runs of
  * Sec. 4.2): PCA of X, then the map of adagio_project_axes.  Pi_out: device
  * r x d FP32.  Synchronises `stream`. */

@@ -83,6 +83,7 @@ SIGNATURES = {
     "adagio_pca_randomized": (ctypes.c_int, [_P, _I64, _I64, _I32, _I32, _U64, _P, _P, _P]),
     "adagio_project_axes": (ctypes.c_int, [_P, _I64, _I32, _U64, _P, _P]),
     "adagio_project": (ctypes.c_int, [_P, _I64, _I64, _I32, _U64, _P, _P]),
+    "adagio_project_family": (ctypes.c_int, [_P, _I64, _I32, _I32, _U64, _P, _P]),
     "adagio_embed": (ctypes.c_int, [_P, _I64, _I64, _P, _I32, _P, _P]),
     "adagio_max_distortion": (ctypes.c_int, [_P, _I64, _I64, _P, _I32, ctypes.POINTER(Opts),
                                              ctypes.POINTER(Cert), _P]),
@@ -184,6 +185,16 @@ def project_axes(Vt, r, seed):
     Pi = torch.empty((r, d), dtype=torch.float32, device=Vt.device)
     _check(lib.adagio_project_axes(_dev(Vt, torch.float64, "Vt"), d, int(r), int(seed),
                                    _dev(Pi, torch.float32, "Pi"), _stream()))
+    return Pi
+
+
+def project_family(Vt, r, family, seed):
+    """r x d FP32 map of a family ("adagio", "pca", "jl") from sorted axes Vt."""
+    lib = load()
+    d = Vt.shape[1]
+    Pi = torch.empty((r, d), dtype=torch.float32, device=Vt.device)
+    _check(lib.adagio_project_family(_dev(Vt, torch.float64, "Vt"), d, int(r), FAMILY[family], int(seed),
+                                     _dev(Pi, torch.float32, "Pi"), _stream()))
     return Pi
 
 

@@ -60,7 +60,7 @@ struct Workspace {
   DevBuf Xq, sx, nxq, Yq, sy, nyq, q8terms, hist, kthr, gcache;
   DevBuf rpQ, rpY, rpG, rpV, rpLam;
   DevBuf skpart, skG, skK, sklam, skV, skfeat, mlp_pb, mlp_X, mlp_f, mlp_hb, mlp_grad, mlp_loss;
-  DevBuf knQ, knD, knNq64, knNd64, knNq32, knNd32, knMax, knKeys, knFb, knCnt;
+  DevBuf knQ, knD, knNq64, knNd64, knNq32, knNd32, knMax, knKeys, knFb, knCnt, knTau;
   bool checked = false;
 };
 
@@ -763,6 +763,18 @@ int adagio_project_axes(const double* Vt, int64_t d, int32_t r, uint64_t seed, f
   });
 }
 
+int adagio_project_family(const double* Vt, int64_t d, int32_t r, int32_t family, uint64_t seed, float* Pi_out,
+                          void* stream) {
+  return guarded([&] {
+    ARGCHK(Vt && Pi_out, "Vt or Pi_out is NULL");
+    ARGCHK(d >= 1, "need d >= 1");
+    ARGCHK(r >= 1 && r <= d, "r must be in [1, d]");
+    ARGCHK(family == ADAGIO_MAP_ADAGIO || family == ADAGIO_MAP_PCA || family == ADAGIO_MAP_JL, "unknown map family");
+    Workspace& ws = workspace();
+    build_family_map(ws, family, Vt, d, r, seed, Pi_out, as_stream(stream));
+  });
+}
+
 int adagio_project(const float* X, int64_t n, int64_t d, int32_t r, uint64_t seed, float* Pi_out, void* stream) {
   return guarded([&] {
     check_points(X, n, d);
@@ -1113,15 +1125,18 @@ int adagio_knn(const float* Q, int64_t nq, const float* D, int64_t nd, int64_t m
     v.tps = (v.NTd + S - 1) / S;
     v.S = (v.NTd + v.tps - 1) / v.tps;
     uint64_t* keys = ensure<uint64_t>(ws.knKeys, (size_t)nq_pad * v.S * kKnnKeep);
+    // shared per-query thresholds, order-preserving bits of +inf to start
+    unsigned* tau_g = ensure<unsigned>(ws.knTau, (size_t)nq_pad);
     e_screen.begin(st);
-    HIPCHK(launch_knn_screen(v, keys, st));
+    HIPCHK(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(tau_g), 0xFF800000, (size_t)nq_pad, st));
+    HIPCHK(launch_knn_screen(v, keys, tau_g, st));
     e_screen.end(st);
     // |est - d| <= c_K (N_q + N_x): the screen constant of an FP32 Gram of K terms;
     // the FP64 sums of m squares are within (m + 4) u64 (relative) of d.
     const double cK = ((double)K + 32.0) * kU32 * 1.001;
     const double g64 = ((double)m + 4.0) * kU64 * 1.01;
     e_finish.begin(st);
-    HIPCHK(launch_knn_finish(v, keys, Q, D, nq64, ndmax, cK, g64, k, idx_out, dist_out, cnt + 1, fb, st));
+    HIPCHK(launch_knn_finish(v, keys, Q, D, nq64, ndmax, tau_g, cK, g64, k, idx_out, dist_out, cnt + 1, fb, st));
     e_finish.end(st);
     HIPCHK(hipMemcpyAsync(flags + 1, cnt + 1, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1182,7 +1197,7 @@ int adagio_release(void) {
                       &ws.rpG, &ws.rpV, &ws.rpLam,
                       &ws.skpart, &ws.skG, &ws.skK, &ws.sklam, &ws.skV, &ws.skfeat, &ws.mlp_pb, &ws.mlp_X,
                       &ws.mlp_f, &ws.mlp_hb, &ws.mlp_grad, &ws.mlp_loss, &ws.knQ, &ws.knD, &ws.knNq64,
-                      &ws.knNd64, &ws.knNq32, &ws.knNd32, &ws.knMax, &ws.knKeys, &ws.knFb, &ws.knCnt};
+                      &ws.knNd64, &ws.knNq32, &ws.knNd32, &ws.knMax, &ws.knKeys, &ws.knFb, &ws.knCnt, &ws.knTau};
     for (DevBuf* b : bufs) {
       if (b->p) HIPCHK(hipFree(b->p));
       b->p = nullptr;

@@ -107,7 +107,16 @@ struct KnnScreenArgs {
   const float* nd32; const float* nq32;
   int64_t nd; int QB; int S; int tps; int NTd; int excl;
   uint64_t* keys;   // [nq_pad][S][KP]
+  unsigned* tau_g;  // [nq_pad] order-preserving bits of the shared threshold
 };
+
+__device__ inline unsigned knn_ord(float e) {
+  const unsigned b = __float_as_uint(e);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ inline float knn_unord(unsigned b) {
+  return __uint_as_float((b & 0x80000000u) ? (b & 0x7fffffffu) : ~b);
+}
 
 __global__ __launch_bounds__(256, 1) void k_knn_screen(KnnScreenArgs p) {
   extern __shared__ __attribute__((aligned(16))) unsigned char knn_lds_raw[];
@@ -163,7 +172,14 @@ __global__ __launch_bounds__(256, 1) void k_knn_screen(KnnScreenArgs p) {
 
   for (int t = t0; t < t1; ++t) {
     const int row0 = t * KN_T;
-    if (tid < KN_T) sm.nd[tid] = p.nd32[row0 + tid];
+    if (tid < KN_T) {
+      sm.nd[tid] = p.nd32[row0 + tid];
+      // Any split's 32nd smallest estimate bounds the query's global 32nd
+      // smallest from above, so the smallest one published so far is a valid
+      // filter here too (a stale value is merely a looser one).
+      const unsigned g = __hip_atomic_load(&p.tau_g[q0 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      sm.tau[tid] = fminf(sm.tau[tid], knn_unord(g));
+    }
     f32x16 acc[2][2];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
@@ -191,9 +207,13 @@ __global__ __launch_bounds__(256, 1) void k_knn_screen(KnnScreenArgs p) {
             for (int y = 0; y < 2; ++y)
               acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[x][kk], b4[y][kk], acc[x][y], 0, 0, 0);
       }
-      if (g + 1 < gend) stash(buf ^ 1);
+      // the next tile's first chunk is stashed after this tile's epilogue,
+      // so its loads complete behind the epilogue
+      if (g + 1 < gend && c + 1 < p.nch) stash(buf ^ 1);
       __syncthreads();
     }
+    tau0 = sm.tau[qc0];
+    tau1 = sm.tau[qc1];
 
     // Edge tiles: rows past the database end, and with exclude-self the tile
     // whose rows are this block's queries (row0 == q0).
@@ -250,12 +270,19 @@ __global__ __launch_bounds__(256, 1) void k_knn_screen(KnnScreenArgs p) {
             Lq[pp] = kv;
             last = Lq[kKnnKeep - 1];
           }
-          sm.tau[tid] = knn_key_est(last);
+          const unsigned lb = (unsigned)(last >> 32);   // +inf bits while the list is not full
+          const unsigned old = atomicMin(&p.tau_g[q0 + tid], lb);
+          sm.tau[tid] = knn_unord(min(old, lb));
         }
         __syncthreads();
         tau0 = sm.tau[qc0];
         tau1 = sm.tau[qc1];
       }
+    }
+    const int gn = (t + 1 - t0) * p.nch;
+    if (gn < gend) {
+      stash(gn & 1);
+      __syncthreads();
     }
   }
 
@@ -276,6 +303,7 @@ __global__ __launch_bounds__(256, 1) void k_knn_screen(KnnScreenArgs p) {
       Lq[pp] = kv;
       last = Lq[kKnnKeep - 1];
     }
+    atomicMin(&p.tau_g[q0 + tid], (unsigned)(last >> 32));
   }
   __syncthreads();
   for (int e = tid; e < KN_T * kKnnKeep; e += 256) {
@@ -306,6 +334,7 @@ struct KnnFinishArgs {
   const float* Q; const float* D; int64_t m;
   int64_t nq; int k;
   const double* nq64; const double* ndmax;
+  const unsigned* tau_g;  // shared thresholds of the screen
   double cK;     // screen bound constant c_K
   double g64;    // relative bound of the FP64 sums
   int32_t* idx; double* dist;
@@ -363,9 +392,12 @@ __global__ __launch_bounds__(256) void k_knn_finish(KnnFinishArgs p) {
   double dk = (lane < kKnnKeep && rank < p.k) ? d : -1.0;
   for (int o = 32; o >= 1; o >>= 1) dk = fmax(dk, __shfl_xor(dk, o, 64));
   if (lane == 0) {
-    const float e_last = knn_key_est(klast);
+    // Every row outside the kept keys has an estimate of at least the 32nd
+    // kept one or the shared threshold (rows filtered or evicted in a split).
+    const bool full = (uint32_t)klast != 0xFFFFFFFFu && klast != ~0ull;
+    const float e_last = fminf(full ? knn_key_est(klast) : __uint_as_float(0x7f800000u), knn_unord(p.tau_g[q]));
     bool ok = true;
-    if ((uint32_t)klast != 0xFFFFFFFFu && klast != ~0ull) {
+    if (e_last < __uint_as_float(0x7f800000u)) {
       const double beta = p.cK * (p.nq64[q] + *p.ndmax);
       const double lower = ((double)e_last - beta) * (1.0 - p.g64);
       ok = lower > dk;
@@ -484,7 +516,7 @@ hipError_t launch_knn_max(const double* v, int64_t n, double* out, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_knn_screen(const KnnView& v, uint64_t* keys, hipStream_t st) {
+hipError_t launch_knn_screen(const KnnView& v, uint64_t* keys, unsigned* tau_g, hipStream_t st) {
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_knn_screen),
@@ -497,17 +529,18 @@ hipError_t launch_knn_screen(const KnnView& v, uint64_t* keys, hipStream_t st) {
   a.nd32 = v.nd32; a.nq32 = v.nq32;
   a.nd = v.nd; a.QB = v.QB; a.S = v.S; a.tps = v.tps; a.NTd = v.NTd; a.excl = v.excl;
   a.keys = keys;
+  a.tau_g = tau_g;
   const int64_t G = round_up((int64_t)v.QB * v.S, 8);
   k_knn_screen<<<(unsigned)G, 256, sizeof(KnnLds), st>>>(a);
   return hipGetLastError();
 }
 
 hipError_t launch_knn_finish(const KnnView& v, const uint64_t* keys, const float* Q, const float* D,
-                             const double* nq64, const double* ndmax, double cK, double g64, int k,
-                             int32_t* idx, double* dist, int* nfb, int* fb, hipStream_t st) {
+                             const double* nq64, const double* ndmax, const unsigned* tau_g, double cK, double g64,
+                             int k, int32_t* idx, double* dist, int* nfb, int* fb, hipStream_t st) {
   KnnFinishArgs a;
   a.keys = keys; a.S = v.S; a.Q = Q; a.D = D; a.m = v.m; a.nq = v.nq; a.k = k;
-  a.nq64 = nq64; a.ndmax = ndmax; a.cK = cK; a.g64 = g64;
+  a.nq64 = nq64; a.ndmax = ndmax; a.tau_g = tau_g; a.cK = cK; a.g64 = g64;
   a.idx = idx; a.dist = dist; a.nfb = nfb; a.fb = fb;
   k_knn_finish<<<(unsigned)((v.nq + 3) / 4), 256, 0, st>>>(a);
   return hipGetLastError();

@@ -151,10 +151,10 @@ struct KnnView {
 hipError_t launch_knn_prep(const float* src, int64_t n, int64_t m, int64_t n_pad, int64_t K, float* dst,
                            double* n64, float* n32, int* nonfinite, hipStream_t st);
 hipError_t launch_knn_max(const double* v, int64_t n, double* out, hipStream_t st);
-hipError_t launch_knn_screen(const KnnView& v, uint64_t* keys, hipStream_t st);
+hipError_t launch_knn_screen(const KnnView& v, uint64_t* keys, unsigned* tau_g, hipStream_t st);
 hipError_t launch_knn_finish(const KnnView& v, const uint64_t* keys, const float* Q, const float* D,
-                             const double* nq64, const double* ndmax, double cK, double g64, int k,
-                             int32_t* idx, double* dist, int* nfb, int* fb, hipStream_t st);
+                             const double* nq64, const double* ndmax, const unsigned* tau_g, double cK, double g64,
+                             int k, int32_t* idx, double* dist, int* nfb, int* fb, hipStream_t st);
 hipError_t launch_knn_fallback(const float* Q, const float* D, int64_t m, int64_t nd, int k, int excl, const int* fb,
                                int nfb, int32_t* idx, double* dist, hipStream_t st);
 hipError_t launch_knn_vote(const int32_t* nn, int64_t nq, int k, const int32_t* label, int64_t nd, int n_labels,

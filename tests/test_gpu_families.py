@@ -54,3 +54,19 @@ def test_family_maps_are_the_oracle_maps(gpu_lib, c1):
     Vo = Vt[:p["r"]]
     cos = np.linalg.svd(P @ Vo.T, compute_uv=False)
     assert cos.min() > 1 - 1e-6
+
+
+@pytest.mark.parametrize("r", [1, 37, 96])
+def test_project_family_maps(gpu_lib, c1, r):
+    """Fixed-r maps of the three families from the library's own axes: the
+    Algorithm 1 map equals adagio_project_axes's bit for bit, the PCA map is
+    Vt's top r rows, the JL map the oracle's sign matrix."""
+    X, (lam, Vt) = c1
+    _, Vg = gpu_lib.pca(dev(X))
+    a = gpu_lib.project_family(Vg, r, "adagio", gen.JL_SEED)
+    assert torch.equal(a, gpu_lib.project_axes(Vg, r, gen.JL_SEED))
+    p = gpu_lib.project_family(Vg, r, "pca", gen.JL_SEED).cpu().numpy()
+    assert np.array_equal(p, Vg[:r].cpu().numpy().astype(np.float32))
+    j = gpu_lib.project_family(Vg, r, "jl", gen.JL_SEED).cpu().numpy()
+    want = embedding.jl_map(X.shape[1], r, gen.JL_SEED).astype(np.float32) if r < X.shape[1] else np.eye(r, dtype=np.float32)
+    assert np.array_equal(j, want)
