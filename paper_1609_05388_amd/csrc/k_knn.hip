@@ -30,6 +30,8 @@
 // (b mod 8) * (G / 8) + b / 8 and slot = split * QB + query block, so the
 // workgroups resident on one XCD scan the same database split and share its
 // tiles in that XCD's L2.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -170,16 +172,22 @@ __global__ __launch_bounds__(256, 1) void k_knn_screen(KnnScreenArgs p) {
   const float nq0 = sm.nq[qc0], nq1 = sm.nq[qc1];
   float tau0 = sm.tau[qc0], tau1 = sm.tau[qc1];
 
+  // Row norms of the next tile and the shared threshold are loaded with the
+  // next tile's first chunk and written to LDS after this tile's epilogue.
+  // Any split's 32nd smallest estimate bounds the query's global 32nd
+  // smallest from above, so the smallest one published so far is a valid
+  // filter here too (a stale value is merely a looser one).
+  float nd_next = 0.0f;
+  unsigned tg_next = 0xFF800000u;
+  if (tid < KN_T) {
+    sm.nd[tid] = p.nd32[t0 * KN_T + tid];
+    tg_next = __hip_atomic_load(&p.tau_g[q0 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    sm.tau[tid] = fminf(sm.tau[tid], knn_unord(tg_next));
+  }
+  __syncthreads();
+
   for (int t = t0; t < t1; ++t) {
     const int row0 = t * KN_T;
-    if (tid < KN_T) {
-      sm.nd[tid] = p.nd32[row0 + tid];
-      // Any split's 32nd smallest estimate bounds the query's global 32nd
-      // smallest from above, so the smallest one published so far is a valid
-      // filter here too (a stale value is merely a looser one).
-      const unsigned g = __hip_atomic_load(&p.tau_g[q0 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      sm.tau[tid] = fminf(sm.tau[tid], knn_unord(g));
-    }
     f32x16 acc[2][2];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
@@ -188,7 +196,13 @@ __global__ __launch_bounds__(256, 1) void k_knn_screen(KnnScreenArgs p) {
     const int gb = (t - t0) * p.nch;
     for (int c = 0; c < p.nch; ++c) {
       const int g = gb + c, buf = g & 1;
-      if (g + 1 < gend) fetch(g + 1);
+      if (g + 1 < gend) {
+        fetch(g + 1);
+        if (c + 1 == p.nch && tid < KN_T) {
+          nd_next = p.nd32[row0 + KN_T + tid];
+          tg_next = __hip_atomic_load(&p.tau_g[q0 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
       // MFMA step kk sums chunk columns kk (lanes 0-31) and 8 + kk (lanes
       // 32-63), the same permutation for both operands.
 #pragma unroll
@@ -224,29 +238,57 @@ __global__ __launch_bounds__(256, 1) void k_knn_screen(KnnScreenArgs p) {
 #pragma unroll
     for (int st = 0; st < 4; ++st) {
       const int stamp = (t - t0) * 4 + st + 1;
+      // All 16 estimates of the sub-step first (straight-line code), then
+      // the appends only in waves where some candidate passes its filter:
+      // after the first tiles most sub-steps pass none.
+      float est[2][4][2];
+      bool any = false;
+      auto eval = [&](auto maskc) __attribute__((always_inline)) {
+        constexpr bool M = decltype(maskc)::value;
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+        for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int vv = 0; vv < 4; ++vv) {
-          const int v = st * 4 + vv;
-          const int rl = wr * 64 + x * 32 + st * 8 + lh * 4 + vv;
-          const float ndr = sm.nd[rl];
+          for (int vv = 0; vv < 4; ++vv) {
+            const int rl = wr * 64 + x * 32 + st * 8 + lh * 4 + vv;
+            const float ndr = sm.nd[rl];
 #pragma unroll
-          for (int y = 0; y < 2; ++y) {
-            float est = fmaf(-2.0f, acc[x][y][v], (y ? nq1 : nq0) + ndr);
-            if (masked) {
-              const int64_t rg = row0 + rl;
-              const int qg = q0 + (y ? qc1 : qc0);
-              if (rg >= p.nd || (p.excl && rg == qg)) est = __uint_as_float(0x7f800000u);
-            }
-            if (est < (y ? tau1 : tau0)) {
-              const int qc = y ? qc1 : qc0;
-              const int pos = atomicAdd(&sm.cnt[qc], 1);
-              sm.Qu[qc * KN_QST + pos] = knn_key(est, (uint32_t)(row0 + rl));
-              if (pos >= KN_QC - 32) sm.flag = stamp;
+            for (int y = 0; y < 2; ++y) {
+              float e = fmaf(-2.0f, acc[x][y][st * 4 + vv], (y ? nq1 : nq0) + ndr);
+              if (M) {
+                const int64_t rg = row0 + rl;
+                const int qg = q0 + (y ? qc1 : qc0);
+                if (rg >= p.nd || (p.excl && rg == qg)) e = __uint_as_float(0x7f800000u);
+              }
+              est[x][vv][y] = e;
+              any |= e < (y ? tau1 : tau0);
             }
           }
-        }
+      };
+      if (masked) eval(std::integral_constant<bool, true>{});
+      else eval(std::integral_constant<bool, false>{});
+      if (__builtin_amdgcn_ballot_w64(any)) {
+        // One LDS atomic per lane and query reserves all of the lane's slots;
+        // the writes then need no round trip.
+        int n0 = 0, n1 = 0;
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int vv = 0; vv < 4; ++vv) {
+            n0 += est[x][vv][0] < tau0 ? 1 : 0;
+            n1 += est[x][vv][1] < tau1 ? 1 : 0;
+          }
+        int i0 = n0 ? atomicAdd(&sm.cnt[qc0], n0) : 0;
+        int i1 = n1 ? atomicAdd(&sm.cnt[qc1], n1) : 0;
+        if (i0 + n0 > KN_QC - 32 || i1 + n1 > KN_QC - 32) sm.flag = stamp;
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int vv = 0; vv < 4; ++vv) {
+            const uint32_t row = (uint32_t)(row0 + wr * 64 + x * 32 + st * 8 + lh * 4 + vv);
+            if (est[x][vv][0] < tau0) sm.Qu[qc0 * KN_QST + i0++] = knn_key(est[x][vv][0], row);
+            if (est[x][vv][1] < tau1) sm.Qu[qc1 * KN_QST + i1++] = knn_key(est[x][vv][1], row);
+          }
+      }
       __syncthreads();
       // The flag holds the stamp of the last sub-step that asked for a merge.
       // Stamps increase, so a thread that is still reading it after others
@@ -282,6 +324,10 @@ __global__ __launch_bounds__(256, 1) void k_knn_screen(KnnScreenArgs p) {
     const int gn = (t + 1 - t0) * p.nch;
     if (gn < gend) {
       stash(gn & 1);
+      if (tid < KN_T) {
+        sm.nd[tid] = nd_next;
+        sm.tau[tid] = fminf(sm.tau[tid], knn_unord(tg_next));
+      }
       __syncthreads();
     }
   }
