@@ -1116,7 +1116,7 @@ int adagio_knn(const float* Q, int64_t nq, const float* D, int64_t nd, int64_t m
       throw Fail{ADAGIO_E_NONFINITE};
     }
     v.Qp = Qp; v.Dp = Dp; v.K = K; v.m = m; v.nq32 = nq32; v.nd32 = nd32; v.nq = nq; v.nd = nd;
-    v.QB = (int)(nq_pad / kTile);
+    v.QB = (int)(nq_pad / kKnnQueries);
     v.NTd = (int)(nd_pad / kTile);
     v.excl = exclude_self;
     // Splits of the database: enough workgroups to fill the chip several

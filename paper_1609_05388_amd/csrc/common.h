@@ -30,6 +30,7 @@ constexpr int64_t kGcacheFloatsPerTile = (int64_t)kTile * kTile;
 // splits one query's keys may span.
 constexpr int kKnnKeep = 32;
 constexpr int kKnnMaxSplits = 32;
+constexpr int kKnnQueries = 64;   // queries per screen workgroup
 
 // One tile record of the screen: the largest upper bound on the squared
 // distance ratio q = E^2 / D^2 in the tile with its pair, and the smallest

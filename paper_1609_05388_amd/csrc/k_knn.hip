@@ -5,11 +5,12 @@
 // smallest FP64 squared distance ||q - x||^2, summed coordinate by
 // coordinate, equal distances ordered by the smaller database index.
 //
-// Stage 1, k_knn_screen: tiles of 128 database rows x 128 queries on
+// Stage 1, k_knn_screen: tiles of 128 database rows x 64 queries on
 //   v_mfma_f32_32x32x2f32 give est = N_q + N_x - 2 q.x (FP32 norms of the FP64
 //   squared norms).  A workgroup scans one split of the database for one block
-//   of 128 queries and keeps, per query, the KP = 32 smallest estimates as
-//   64-bit keys (order-preserving bits of est, then the database index).
+//   of 64 queries and keeps, per query, the KP = 32 smallest estimates as
+//   64-bit keys (order-preserving bits of est, then the database index); two
+//   workgroups share a CU, so one's MFMAs overlap the other's selection.
 //   Candidates below the query's current 32nd key go to an LDS queue; the
 //   queue is merged into the sorted list when any query's queue holds more
 //   than 32 entries, so a sub-step (32 candidates per query) never overflows.
@@ -37,23 +38,24 @@
 
 namespace adg {
 
-constexpr int KN_T = 128;     // rows per tile side
+constexpr int KN_T = 128;     // database rows per tile
+constexpr int KN_Q = kKnnQueries;  // queries per block
 constexpr int KN_C = 16;      // chunk width
 constexpr int KN_LD = 20;     // LDS operand row stride (floats)
 constexpr int KN_QC = 64;     // queue capacity per query
 constexpr int KN_LST = kKnnKeep + 1;  // padded list row (u64)
-constexpr int KN_QST = KN_QC + 1;     // padded queue row (u64)
 constexpr uint64_t kKnnEmpty = (0xFF800000ull << 32) | 0xFFFFFFFFull;  // key of (+inf, no row)
 
+// 81,680 bytes: two workgroups share a CU's 160 KB.
 struct KnnLds {
   float As[2][KN_T * KN_LD];  // database chunk
-  float Bs[2][KN_T * KN_LD];  // query chunk
-  float nq[KN_T], nd[KN_T];
-  float tau[KN_T];
-  int cnt[KN_T];
+  float Bs[2][KN_Q * KN_LD];  // query chunk
+  float nd[KN_T];
+  float nq[KN_Q], tau[KN_Q];
+  int cnt[KN_Q];
   int flag, pad0, pad1, pad2;
-  uint64_t L[KN_T * KN_LST];
-  uint64_t Qu[KN_T * KN_QST];
+  uint64_t L[KN_Q * KN_LST];
+  uint64_t Qu[KN_Q * KN_QC];
 };
 
 __device__ inline uint64_t knn_key(float e, uint32_t row) {
@@ -120,7 +122,32 @@ __device__ inline float knn_unord(unsigned b) {
   return __uint_as_float((b & 0x80000000u) ? (b & 0x7fffffffu) : ~b);
 }
 
-__global__ __launch_bounds__(256, 1) void k_knn_screen(KnnScreenArgs p) {
+// Insert the queued keys of query q into its sorted list; returns the
+// list's last (32nd) key.
+__device__ inline uint64_t knn_merge_one(KnnLds& sm, int q) {
+  const int c = sm.cnt[q];
+  sm.cnt[q] = 0;
+  uint64_t* Lq = &sm.L[q * KN_LST];
+  const uint64_t* Qq = &sm.Qu[q * KN_QC];
+  uint64_t last = Lq[kKnnKeep - 1];
+  for (int i = 0; i < c; ++i) {
+    const uint64_t kv = Qq[i];
+    if (kv >= last) continue;
+    int pp = 0;
+#pragma unroll
+    for (int step = kKnnKeep / 2; step > 0; step >>= 1)
+      if (Lq[pp + step - 1] < kv) pp += step;
+    for (int j = kKnnKeep - 1; j > pp; --j) Lq[j] = Lq[j - 1];
+    Lq[pp] = kv;
+    last = Lq[kKnnKeep - 1];
+  }
+  return last;
+}
+
+// One workgroup: one block of 64 queries against one split of the database,
+// tiles of 128 rows x 64 queries; wave w computes rows 32w .. 32w + 31 of the
+// tile against all 64 queries (two 32 x 32 MFMA blocks).
+__global__ __launch_bounds__(256, 2) void k_knn_screen(KnnScreenArgs p) {
   extern __shared__ __attribute__((aligned(16))) unsigned char knn_lds_raw[];
   KnnLds& sm = *reinterpret_cast<KnnLds*>(knn_lds_raw);
 
@@ -129,24 +156,25 @@ __global__ __launch_bounds__(256, 1) void k_knn_screen(KnnScreenArgs p) {
   if (slot >= (int64_t)p.QB * p.S) return;
   const int s = (int)(slot / p.QB), qb = (int)(slot % p.QB);
   const int t0 = s * p.tps, t1 = min(p.NTd, t0 + p.tps);
-  const int q0 = qb * KN_T;
+  const int q0 = qb * KN_Q;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
   const int li = lane & 31, lh = lane >> 5;
 
-  if (tid < KN_T) {
+  if (tid < KN_Q) {
     sm.nq[tid] = p.nq32[q0 + tid];
     sm.tau[tid] = __uint_as_float(0x7f800000u);
     sm.cnt[tid] = 0;
   }
   if (tid == 0) sm.flag = 0;
-  for (int e = tid; e < KN_T * KN_LST; e += 256) sm.L[e] = kKnnEmpty;
+  for (int e = tid; e < KN_Q * KN_LST; e += 256) sm.L[e] = kKnnEmpty;
 
+  // loads: database rows lr and lr + 64, query row lr (threads < 256 cover
+  // 64 rows x 16 columns as float4)
   const int lr = tid >> 2, lc = (tid & 3) * 4;
   const float* qa = p.Q + (size_t)(q0 + lr) * p.K + lc;
-  const size_t q64 = (size_t)64 * p.K, d64 = (size_t)64 * p.K;
-  float4 ga0, ga1, gb0, gb1;
+  const size_t d64 = (size_t)64 * p.K;
+  float4 ga0, ga1, gb0;
   // chunk g of the scan: tile t0 + g / nch, columns (g mod nch) * 16
   auto fetch = [&](int g) __attribute__((always_inline)) {
     const int t = t0 + g / p.nch, cb = (g % p.nch) * KN_C;
@@ -154,23 +182,21 @@ __global__ __launch_bounds__(256, 1) void k_knn_screen(KnnScreenArgs p) {
     ga0 = *reinterpret_cast<const float4*>(da);
     ga1 = *reinterpret_cast<const float4*>(da + d64);
     gb0 = *reinterpret_cast<const float4*>(qa + cb);
-    gb1 = *reinterpret_cast<const float4*>(qa + q64 + cb);
   };
   auto stash = [&](int buf) __attribute__((always_inline)) {
     *reinterpret_cast<float4*>(&sm.As[buf][lr * KN_LD + lc]) = ga0;
     *reinterpret_cast<float4*>(&sm.As[buf][(lr + 64) * KN_LD + lc]) = ga1;
     *reinterpret_cast<float4*>(&sm.Bs[buf][lr * KN_LD + lc]) = gb0;
-    *reinterpret_cast<float4*>(&sm.Bs[buf][(lr + 64) * KN_LD + lc]) = gb1;
   };
 
   const int gend = (t1 - t0) * p.nch;
   fetch(0);
   stash(0);
   // the lane's two query columns
-  const int qc0 = wc * 64 + li, qc1 = wc * 64 + 32 + li;
+  const int qc0 = li, qc1 = 32 + li;
   __syncthreads();
   const float nq0 = sm.nq[qc0], nq1 = sm.nq[qc1];
-  float tau0 = sm.tau[qc0], tau1 = sm.tau[qc1];
+  float tau0, tau1;
 
   // Row norms of the next tile and the shared threshold are loaded with the
   // next tile's first chunk and written to LDS after this tile's epilogue.
@@ -179,8 +205,8 @@ __global__ __launch_bounds__(256, 1) void k_knn_screen(KnnScreenArgs p) {
   // filter here too (a stale value is merely a looser one).
   float nd_next = 0.0f;
   unsigned tg_next = 0xFF800000u;
-  if (tid < KN_T) {
-    sm.nd[tid] = p.nd32[t0 * KN_T + tid];
+  if (tid < KN_T) sm.nd[tid] = p.nd32[t0 * KN_T + tid];
+  if (tid < KN_Q) {
     tg_next = __hip_atomic_load(&p.tau_g[q0 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     sm.tau[tid] = fminf(sm.tau[tid], knn_unord(tg_next));
   }
@@ -188,38 +214,34 @@ __global__ __launch_bounds__(256, 1) void k_knn_screen(KnnScreenArgs p) {
 
   for (int t = t0; t < t1; ++t) {
     const int row0 = t * KN_T;
-    f32x16 acc[2][2];
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y) acc[x][y] = (f32x16){0};
+    f32x16 acc[2];
+    acc[0] = (f32x16){0};
+    acc[1] = (f32x16){0};
     const int gb = (t - t0) * p.nch;
     for (int c = 0; c < p.nch; ++c) {
       const int g = gb + c, buf = g & 1;
       if (g + 1 < gend) {
         fetch(g + 1);
-        if (c + 1 == p.nch && tid < KN_T) {
-          nd_next = p.nd32[row0 + KN_T + tid];
-          tg_next = __hip_atomic_load(&p.tau_g[q0 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (c + 1 == p.nch) {
+          if (tid < KN_T) nd_next = p.nd32[row0 + KN_T + tid];
+          if (tid < KN_Q)
+            tg_next = __hip_atomic_load(&p.tau_g[q0 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
       // MFMA step kk sums chunk columns kk (lanes 0-31) and 8 + kk (lanes
       // 32-63), the same permutation for both operands.
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
-        float4 a4[2], b4[2];
+        const float4 a4 = *reinterpret_cast<const float4*>(&sm.As[buf][(wave * 32 + li) * KN_LD + lh * 8 + half * 4]);
+        float4 b4[2];
 #pragma unroll
-        for (int x = 0; x < 2; ++x) {
-          a4[x] = *reinterpret_cast<const float4*>(&sm.As[buf][(wr * 64 + x * 32 + li) * KN_LD + lh * 8 + half * 4]);
-          b4[x] = *reinterpret_cast<const float4*>(&sm.Bs[buf][(wc * 64 + x * 32 + li) * KN_LD + lh * 8 + half * 4]);
-        }
+        for (int y = 0; y < 2; ++y)
+          b4[y] = *reinterpret_cast<const float4*>(&sm.Bs[buf][(y * 32 + li) * KN_LD + lh * 8 + half * 4]);
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-          for (int x = 0; x < 2; ++x)
-#pragma unroll
-            for (int y = 0; y < 2; ++y)
-              acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[x][kk], b4[y][kk], acc[x][y], 0, 0, 0);
+          for (int y = 0; y < 2; ++y)
+            acc[y] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[kk], b4[y][kk], acc[y], 0, 0, 0);
       }
       // the next tile's first chunk is stashed after this tile's epilogue,
       // so its loads complete behind the epilogue
@@ -230,39 +252,37 @@ __global__ __launch_bounds__(256, 1) void k_knn_screen(KnnScreenArgs p) {
     tau1 = sm.tau[qc1];
 
     // Edge tiles: rows past the database end, and with exclude-self the tile
-    // whose rows are this block's queries (row0 == q0).
-    const bool masked = (row0 + KN_T > p.nd) || (p.excl && row0 == q0);
+    // that holds this block's queries as rows.
+    const bool masked = (row0 + KN_T > p.nd) || (p.excl && q0 >= row0 && q0 < row0 + KN_T);
     // D layout: lane l, register v -> row (v / 4) * 8 + (l / 32) * 4 + v % 4,
-    // column l % 32.  Sub-step s takes registers 4s .. 4s + 3 of both row
-    // blocks: 8 candidates per lane and query, 32 per query.
+    // column l % 32.  Sub-step s takes registers 4s .. 4s + 3: 4 candidates
+    // per lane and query, 32 per query over the 4 waves.
 #pragma unroll
     for (int st = 0; st < 4; ++st) {
       const int stamp = (t - t0) * 4 + st + 1;
-      // All 16 estimates of the sub-step first (straight-line code), then
-      // the appends only in waves where some candidate passes its filter:
-      // after the first tiles most sub-steps pass none.
-      float est[2][4][2];
+      // All estimates of the sub-step first (straight-line code), then the
+      // appends only in waves where some candidate passes its filter: after
+      // the first tiles most sub-steps pass none.
+      float est[4][2];
       bool any = false;
       auto eval = [&](auto maskc) __attribute__((always_inline)) {
         constexpr bool M = decltype(maskc)::value;
 #pragma unroll
-        for (int x = 0; x < 2; ++x)
+        for (int vv = 0; vv < 4; ++vv) {
+          const int rl = wave * 32 + st * 8 + lh * 4 + vv;
+          const float ndr = sm.nd[rl];
 #pragma unroll
-          for (int vv = 0; vv < 4; ++vv) {
-            const int rl = wr * 64 + x * 32 + st * 8 + lh * 4 + vv;
-            const float ndr = sm.nd[rl];
-#pragma unroll
-            for (int y = 0; y < 2; ++y) {
-              float e = fmaf(-2.0f, acc[x][y][st * 4 + vv], (y ? nq1 : nq0) + ndr);
-              if (M) {
-                const int64_t rg = row0 + rl;
-                const int qg = q0 + (y ? qc1 : qc0);
-                if (rg >= p.nd || (p.excl && rg == qg)) e = __uint_as_float(0x7f800000u);
-              }
-              est[x][vv][y] = e;
-              any |= e < (y ? tau1 : tau0);
+          for (int y = 0; y < 2; ++y) {
+            float e = fmaf(-2.0f, acc[y][st * 4 + vv], (y ? nq1 : nq0) + ndr);
+            if (M) {
+              const int64_t rg = row0 + rl;
+              const int qg = q0 + (y ? qc1 : qc0);
+              if (rg >= p.nd || (p.excl && rg == qg)) e = __uint_as_float(0x7f800000u);
             }
+            est[vv][y] = e;
+            any |= e < (y ? tau1 : tau0);
           }
+        }
       };
       if (masked) eval(std::integral_constant<bool, true>{});
       else eval(std::integral_constant<bool, false>{});
@@ -271,23 +291,19 @@ __global__ __launch_bounds__(256, 1) void k_knn_screen(KnnScreenArgs p) {
         // the writes then need no round trip.
         int n0 = 0, n1 = 0;
 #pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int vv = 0; vv < 4; ++vv) {
-            n0 += est[x][vv][0] < tau0 ? 1 : 0;
-            n1 += est[x][vv][1] < tau1 ? 1 : 0;
-          }
+        for (int vv = 0; vv < 4; ++vv) {
+          n0 += est[vv][0] < tau0 ? 1 : 0;
+          n1 += est[vv][1] < tau1 ? 1 : 0;
+        }
         int i0 = n0 ? atomicAdd(&sm.cnt[qc0], n0) : 0;
         int i1 = n1 ? atomicAdd(&sm.cnt[qc1], n1) : 0;
         if (i0 + n0 > KN_QC - 32 || i1 + n1 > KN_QC - 32) sm.flag = stamp;
 #pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int vv = 0; vv < 4; ++vv) {
-            const uint32_t row = (uint32_t)(row0 + wr * 64 + x * 32 + st * 8 + lh * 4 + vv);
-            if (est[x][vv][0] < tau0) sm.Qu[qc0 * KN_QST + i0++] = knn_key(est[x][vv][0], row);
-            if (est[x][vv][1] < tau1) sm.Qu[qc1 * KN_QST + i1++] = knn_key(est[x][vv][1], row);
-          }
+        for (int vv = 0; vv < 4; ++vv) {
+          const uint32_t row = (uint32_t)(row0 + wave * 32 + st * 8 + lh * 4 + vv);
+          if (est[vv][0] < tau0) sm.Qu[qc0 * KN_QC + i0++] = knn_key(est[vv][0], row);
+          if (est[vv][1] < tau1) sm.Qu[qc1 * KN_QC + i1++] = knn_key(est[vv][1], row);
+        }
       }
       __syncthreads();
       // The flag holds the stamp of the last sub-step that asked for a merge.
@@ -295,23 +311,8 @@ __global__ __launch_bounds__(256, 1) void k_knn_screen(KnnScreenArgs p) {
       // went on to the next sub-step (possible only when no merge is due)
       // sees a later stamp, not its own: every thread takes the same branch.
       if (sm.flag == stamp) {
-        if (tid < KN_T) {
-          const int c = sm.cnt[tid];
-          sm.cnt[tid] = 0;
-          uint64_t* Lq = &sm.L[tid * KN_LST];
-          const uint64_t* Qq = &sm.Qu[tid * KN_QST];
-          uint64_t last = Lq[kKnnKeep - 1];
-          for (int i = 0; i < c; ++i) {
-            const uint64_t kv = Qq[i];
-            if (kv >= last) continue;
-            int pp = 0;
-#pragma unroll
-            for (int step = kKnnKeep / 2; step > 0; step >>= 1)
-              if (Lq[pp + step - 1] < kv) pp += step;
-            for (int j = kKnnKeep - 1; j > pp; --j) Lq[j] = Lq[j - 1];
-            Lq[pp] = kv;
-            last = Lq[kKnnKeep - 1];
-          }
+        if (tid < KN_Q) {
+          const uint64_t last = knn_merge_one(sm, tid);
           const unsigned lb = (unsigned)(last >> 32);   // +inf bits while the list is not full
           const unsigned old = atomicMin(&p.tau_g[q0 + tid], lb);
           sm.tau[tid] = knn_unord(min(old, lb));
@@ -324,35 +325,19 @@ __global__ __launch_bounds__(256, 1) void k_knn_screen(KnnScreenArgs p) {
     const int gn = (t + 1 - t0) * p.nch;
     if (gn < gend) {
       stash(gn & 1);
-      if (tid < KN_T) {
-        sm.nd[tid] = nd_next;
-        sm.tau[tid] = fminf(sm.tau[tid], knn_unord(tg_next));
-      }
+      if (tid < KN_T) sm.nd[tid] = nd_next;
+      if (tid < KN_Q) sm.tau[tid] = fminf(sm.tau[tid], knn_unord(tg_next));
       __syncthreads();
     }
   }
 
   // Queued entries that never triggered a merge.
-  if (tid < KN_T) {
-    const int c = sm.cnt[tid];
-    uint64_t* Lq = &sm.L[tid * KN_LST];
-    const uint64_t* Qq = &sm.Qu[tid * KN_QST];
-    uint64_t last = Lq[kKnnKeep - 1];
-    for (int i = 0; i < c; ++i) {
-      const uint64_t kv = Qq[i];
-      if (kv >= last) continue;
-      int pp = 0;
-#pragma unroll
-      for (int step = kKnnKeep / 2; step > 0; step >>= 1)
-        if (Lq[pp + step - 1] < kv) pp += step;
-      for (int j = kKnnKeep - 1; j > pp; --j) Lq[j] = Lq[j - 1];
-      Lq[pp] = kv;
-      last = Lq[kKnnKeep - 1];
-    }
+  if (tid < KN_Q) {
+    const uint64_t last = knn_merge_one(sm, tid);
     atomicMin(&p.tau_g[q0 + tid], (unsigned)(last >> 32));
   }
   __syncthreads();
-  for (int e = tid; e < KN_T * kKnnKeep; e += 256) {
+  for (int e = tid; e < KN_Q * kKnnKeep; e += 256) {
     const int q = e / kKnnKeep, i = e % kKnnKeep;
     p.keys[((size_t)(q0 + q) * p.S + s) * kKnnKeep + i] = sm.L[q * KN_LST + i];
   }
