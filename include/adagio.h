@@ -13,8 +13,11 @@
  *   row), Y is n x r, Pi is r x d.
  * - `stream` is a hipStream_t passed as void*; NULL means the null stream.
  *   All device work is ordered on it.  Entry points that return host scalars
- *   (fit, max_distortion, certify_map, pca) synchronise that stream before
- *   returning; embed and project return without synchronising.
+ *   or check device results (fit, max_distortion, certify_map, pca,
+ *   pca_randomized, project, knn, knn_vote) synchronise that stream before
+ *   returning; embed, project_axes, project_family and the MLP calls return
+ *   without synchronising (later calls that share the workspace must use the
+ *   same stream).
  * - Host structs (adagio_cert_t, adagio_opts_t, adagio_stats_t) are owned by
  *   the caller; opts may be NULL (defaults).
  * - The library keeps a per-device workspace that grows on demand and is
@@ -25,7 +28,8 @@
  *   failure (thread-local text).  Arguments are validated before any device
  *   work, so invalid arguments never touch the GPU.
  * - Results are deterministic: the same inputs, seed and device give bitwise
- *   identical outputs.
+ *   identical outputs (timing fields aside; adagio_knn's n_fallback may also
+ *   vary between runs, its answers do not).
  */
 #ifndef ADAGIO_H
 #define ADAGIO_H

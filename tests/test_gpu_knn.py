@@ -60,6 +60,17 @@ def test_knn_graph_excludes_self(gpu_lib):
     check(gpu_lib, X, X, 30, exclude_self=True)
 
 
+@pytest.mark.parametrize("nq,nd,m,k", [
+    (100, 300, 9, 7),          # query block ends inside the first database tile
+    (33, 33, 5, 32),           # k = nd - 1: every other row is an answer
+    (200, 1000, 130, 12),      # width past one 128-column chunk, queries span blocks
+])
+def test_knn_exclude_self_ragged(gpu_lib, nq, nd, m, k):
+    rng = np.random.default_rng(nd + m)
+    D = rng.standard_normal((nd, m)).astype(np.float32)
+    check(gpu_lib, D[:nq].copy(), D, k, exclude_self=True)
+
+
 def test_knn_sift_integer_ties(gpu_lib):
     """Integer SIFT-shaped descriptors: FP32 estimates are exact, distances
     tie often; the answer still matches (distance, index) order exactly."""
