@@ -61,6 +61,7 @@ struct Workspace {
   DevBuf rpQ, rpY, rpG, rpV, rpLam;
   DevBuf skpart, skG, skK, sklam, skV, skfeat, mlp_pb, mlp_X, mlp_f, mlp_hb, mlp_grad, mlp_loss;
   DevBuf knQ, knD, knNq64, knNd64, knNq32, knNd32, knMax, knKeys, knFb, knCnt, knTau;
+  DevBuf cidx, lam1, Vt1, Asub;
   bool checked = false;
 };
 
@@ -317,7 +318,27 @@ static Axes principal_axes(Workspace& ws, const Points& p, hipStream_t st, doubl
   Axes ax;
   ax.lam = lam_out ? lam_out : ensure<double>(ws.lam, (size_t)d);
   ax.Vt = Vt_out ? Vt_out : ensure<double>(ws.Vt, (size_t)(d * d));
-  ax.sweeps = jacobi_eig(ws, A, m, d, ax.lam, ax.Vt, st);
+  // Exactly constant coordinates (C_ii = 0) split off a zero block of C: the
+  // eigensolver runs on the block of the others only.
+  int* idx = ensure<int>(ws.cidx, (size_t)d + 1);
+  HIPCHK(launch_const_coords(A, m, (int)d, idx, idx + d, st));
+  int d1 = 0;
+  HIPCHK(hipMemcpyAsync(&d1, idx + d, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (d1 == d) {
+    ax.sweeps = jacobi_eig(ws, A, m, d, ax.lam, ax.Vt, st);
+    return ax;
+  }
+  double* lam1 = ensure<double>(ws.lam1, (size_t)std::max(d1, 1));
+  double* Vt1 = ensure<double>(ws.Vt1, (size_t)std::max(d1, 1) * std::max(d1, 1));
+  ax.sweeps = 0;
+  if (d1 > 0) {
+    const int m1 = (int)round_up(d1, 2 * bj_block());
+    double* A1 = ensure<double>(ws.Asub, (size_t)m1 * m1);
+    HIPCHK(launch_gather_sym(A, m, idx, d1, A1, m1, st));
+    ax.sweeps = jacobi_eig(ws, A1, m1, d1, lam1, Vt1, st);
+  }
+  HIPCHK(launch_scatter_axes(lam1, Vt1, idx, d1, (int)d, ax.lam, ax.Vt, st));
   return ax;
 }
 
@@ -1197,7 +1218,8 @@ int adagio_release(void) {
                       &ws.rpG, &ws.rpV, &ws.rpLam,
                       &ws.skpart, &ws.skG, &ws.skK, &ws.sklam, &ws.skV, &ws.skfeat, &ws.mlp_pb, &ws.mlp_X,
                       &ws.mlp_f, &ws.mlp_hb, &ws.mlp_grad, &ws.mlp_loss, &ws.knQ, &ws.knD, &ws.knNq64,
-                      &ws.knNd64, &ws.knNq32, &ws.knNd32, &ws.knMax, &ws.knKeys, &ws.knFb, &ws.knCnt, &ws.knTau};
+                      &ws.knNd64, &ws.knNq32, &ws.knNd32, &ws.knMax, &ws.knKeys, &ws.knFb, &ws.knCnt, &ws.knTau, &ws.cidx,
+                      &ws.lam1, &ws.Vt1, &ws.Asub};
     for (DevBuf* b : bufs) {
       if (b->p) HIPCHK(hipFree(b->p));
       b->p = nullptr;

@@ -31,6 +31,10 @@ hipError_t launch_eye(double* W, int m, hipStream_t st);
 hipError_t launch_trace(const double* A, int m, double* out, hipStream_t st);
 hipError_t launch_eig_sort(const double* A, const double* W, int m, int d, double* lam, double* Vt,
                            hipStream_t st);
+hipError_t launch_const_coords(const double* A, int m, int d, int* idx, int* d1, hipStream_t st);
+hipError_t launch_gather_sym(const double* A, int m, const int* idx, int d1, double* A1, int m1, hipStream_t st);
+hipError_t launch_scatter_axes(const double* lam1, const double* Vt1, const int* idx, int d1, int d, double* lam,
+                               double* Vt, hipStream_t st);
 
 // k_eig_block.hip
 hipError_t launch_bj_round(const double* A, double* A2, double* W, double* Uall, double* Sall, int m, int t,

@@ -55,6 +55,40 @@ def test_pca_matches_oracle(gpu_lib, n, d):
             assert np.abs(Pg - Po).max() <= 1e-14 * d / gap + 1e-12, s
 
 
+def test_pca_constant_coordinates(gpu_lib):
+    """549 always-zero pixels plus one constant non-zero pixel: C has an exact
+    zero block, which the library splits off before the eigensolve; the
+    eigenpairs still match the oracle's full FP64 eigendecomposition."""
+    X = gen.mnist_shaped(n=3000)
+    X[:, np.flatnonzero(X.std(axis=0) > 0)[0]] = np.float32(0.25)
+    d = X.shape[1]
+    lam, Vt = gpu_lib.pca(dev(X))
+    lam, Vt = lam.cpu().numpy(), Vt.cpu().numpy()
+    _, C, lam_o, Vt_o = opca.pca(X)
+    const = np.flatnonzero(np.diag(C) == 0)
+    assert len(const) >= 550
+    scale = lam_o[0]
+    assert np.abs(lam - lam_o).max() <= 1e-11 * scale * d
+    assert np.all(lam[d - len(const):] == 0)
+    assert np.abs(Vt @ Vt.T - np.eye(d)).max() <= 1e-12 * d
+    assert np.abs(C @ Vt.T - Vt.T * lam).max() <= 1e-11 * scale * d
+    for s in (1, 10, 50, 100):
+        if lam_o[s - 1] - lam_o[s] > 1e-6 * scale:
+            gap = (lam_o[s - 1] - lam_o[s]) / scale
+            assert np.abs(Vt[:s].T @ Vt[:s] - Vt_o[:s].T @ Vt_o[:s]).max() <= 1e-14 * d / gap + 1e-12, s
+
+
+def test_fit_parity_constant_coordinates(gpu_lib):
+    X = gen.mnist_shaped(n=2500)
+    got = gpu_lib.fit(dev(X), 0.1, gen.JL_SEED)
+    want = search.fit(X, 0.1, gen.JL_SEED)
+    assert_cert_parity(got["cert"], oracle_cert_of_map(X, got["Pi"].cpu().numpy()))
+    near = [abs(v - 0.1) for _, v in want["probes"]]
+    if min(near) > TOL:
+        assert got["r"] == want["r"]
+        assert abs(got["cert"]["max_distortion"] - want["cert"]["max"]) <= TOL
+
+
 # ------------------------------------------------------------------- a4-a5
 @pytest.mark.parametrize("d,r", [(40, 1), (40, 2), (40, 3), (40, 17), (40, 39), (40, 40), (784, 190), (784, 391)])
 def test_project_axes_matches_oracle(gpu_lib, d, r):
