@@ -12,8 +12,9 @@ Printed on one line (JSON):
   ms_per_step the fit time (the paper's headline quantity: time to an
               embedding whose max distortion is certified <= eps)
   roofline    the all-pairs screen kernel (FP32 MFMA): algorithmic flops
-              n(n-1)/2 * 2 (d + r) per launch over its average launch time
-              from HIP events on the library's stream
+              n(n-1)/2 * 2 (d' + r) per launch (d' = non-constant
+              coordinates; 2r when the point Gram is cached) over its
+              average launch time from HIP events on the library's stream
   cpu_baseline the FP64 oracle's certificate on this host, on a bounded row
               block of the same workload, in the same unit
 """
@@ -146,9 +147,17 @@ def cpu_baseline(X, Pi, target_s):
                       % (m2, c["n_pairs"], dt)}
 
 
+def nonconstant_columns(X):
+    """Coordinates that are not constant over the cloud: the point Gram's
+    algorithmic width (a constant coordinate centres to exact zeros and adds
+    nothing to any distance; the library's screens leave it out)."""
+    return int((X.max(axis=0) != X.min(axis=0)).sum())
+
+
 def screen_flops(npairs, d, r, gram):
-    """Algorithmic flops of one screen launch: both Grams (2(d + r) per pair),
-    or the image Gram only (2r) when the point Gram came from the cache."""
+    """Algorithmic flops of one screen launch: both Grams (2(d + r) per pair,
+    d = non-constant coordinates), or the image Gram only (2r) when the point
+    Gram came from the cache."""
     return npairs * 2.0 * (r if gram == 2 else d + r)
 
 
@@ -210,6 +219,7 @@ def large_form(adagio, gen, torch, eps):
     t0 = time.perf_counter()
     X = gen.power_law(200000, 4096, 512, 1.0, noise=0.01)
     gen_s = time.perf_counter() - t0
+    dx = nonconstant_columns(X)
     Xd = torch.from_numpy(X).cuda()
     del X
     torch.cuda.synchronize()
@@ -223,9 +233,9 @@ def large_form(adagio, gen, torch, eps):
     scr = list(zip(st["probe_r"], st["probe_delta"], st["probe_screen_ms"], st["probe_gram"]))
     fp8 = scr[:st["n_screened"]]
     rig = scr[st["n_screened"]:]
-    fl = sum(screen_flops(npairs, d, r, g) for r, _, _, g in fp8)
+    fl = sum(screen_flops(npairs, dx, r, g) for r, _, _, g in fp8)
     ms = sum(t for _, _, t, _ in fp8)
-    bfl = sum(screen_flops(npairs, d, r, g) for r, _, _, g in rig)
+    bfl = sum(screen_flops(npairs, dx, r, g) for r, _, _, g in rig)
     bms = sum(t for _, _, t, _ in rig)
     same_r = [dl for r, dl, _, _ in fp8 if r == o["r"]]
     plain = adagio.certify_map(Xd, o["Pi"].contiguous(), screen="f32", with_stats=True)
@@ -251,7 +261,7 @@ def large_form(adagio, gen, torch, eps):
         "bf16x3_screen_useful_tflops": bfl / max(bms, 1e-9) / 1e9,
         "fp8_error_vs_certificate_at_r": (abs(same_r[-1] - o["cert"]["max_distortion"]) if same_r else None),
         "fp32_certificate_of_same_map": {"ms": pst["t_total_ms"], "screen_ms": pst["t_screen_ms"],
-                                         "screen_tflops": npairs * 2.0 * (d + o["r"]) / pst["t_screen_ms"] / 1e9,
+                                         "screen_tflops": npairs * 2.0 * (dx + o["r"]) / pst["t_screen_ms"] / 1e9,
                                          "max_distortion": plain["max_distortion"],
                                          "certified": plain["certified"]},
         "probes": [[r, dl] for r, dl, _, _ in scr],
@@ -368,6 +378,7 @@ def main():
     log("generating MNIST-shaped cloud n=%d" % args.n)
     X = gen.mnist_shaped(n=args.n)
     n, d = X.shape
+    dx = nonconstant_columns(X)
     Xd = torch.from_numpy(X).cuda()
     torch.cuda.synchronize()
 
@@ -393,14 +404,15 @@ def main():
            st["t_screen_ms"]))
 
     # roofline of the screen kernel over the launches of the timed steps.  The
-    # first certificate of a fit computes (and caches) the point Gram: 2(d + r)
-    # flops per pair; the others load it and compute the image Gram: 2r.
+    # first certificate of a fit computes (and caches) the point Gram: 2(d' + r)
+    # flops per pair (d' non-constant coordinates); the others load it and
+    # compute the image Gram: 2r.
     kinds = {"full": [0.0, 0.0, 0], "cached": [0.0, 0.0, 0]}
     for o in outs:
         s = o["stats"]
         for r, t, g in zip(s["probe_r"], s["probe_screen_ms"], s["probe_gram"]):
             k = "cached" if g == 2 else "full"
-            kinds[k][0] += npairs * 2.0 * ((d + r) if k == "full" else r)
+            kinds[k][0] += npairs * 2.0 * ((dx + r) if k == "full" else r)
             kinds[k][1] += t
             kinds[k][2] += 1
     launch_kinds = {}
@@ -430,7 +442,7 @@ def main():
         bflops, bms, bn = 0.0, 0.0, 0
         for o in bouts:
             for r, t, g in zip(o["stats"]["probe_r"], o["stats"]["probe_screen_ms"], o["stats"]["probe_gram"]):
-                bflops += screen_flops(npairs, d, r, g)
+                bflops += screen_flops(npairs, dx, r, g)
                 bms += t
                 bn += 1
         forms["bf16x3"] = {
@@ -444,7 +456,7 @@ def main():
             "screen_bf16_mfma_frac": 3.0 * bflops / bms / 1e9 / PEAK_BF16_MFMA_TFLOPS,
             "rescored_pairs": bl["stats"]["n_rescored"], "flagged_tiles": bl["stats"]["n_flagged_tiles"]}
         log("bf16x3 fit %.1f ms (%.2fx), screen %.2f ms/launch" % (bf_s * 1e3, fit_s / bf_s, bms / bn))
-        forms["fp8"] = fp8_form(adagio, gen, torch, Xd, args.eps, args.steps, fit_s, last, npairs, d)
+        forms["fp8"] = fp8_form(adagio, gen, torch, Xd, args.eps, args.steps, fit_s, last, npairs, dx)
         log("fp8 fit %.1f ms (%.2fx)" % (forms["fp8"]["fit_ms"], forms["fp8"]["speedup_vs_plain"]))
         rs, routs = timed_fits(adagio, torch, Xd, args.eps, gen.JL_SEED, args.steps, pca="randomized", pca_iters=2)
         ro = routs[-1]
@@ -518,7 +530,7 @@ def main():
         "config": {"workload": "MNIST-shaped synthetic cloud (rank-50 mixture of 10 classes, 70%% fixed "
                                "zero mask), n=%d, d=%d, eps=%g, plain FP32 screen, bisection search"
                                % (n, d, args.eps),
-                   "n": n, "d": d, "eps": args.eps, "seed": gen.JL_SEED, "data_seed": gen.DATA_SEED,
+                   "n": n, "d": d, "d_nonconstant": dx, "eps": args.eps, "seed": gen.JL_SEED, "data_seed": gen.DATA_SEED,
                    "parallelism": "single GPU"},
         "fit": {"r": last["r"], "s": last["s"], "k": last["k"], "certificates": ncert,
                 "max_distortion": last["cert"]["max_distortion"], "certified": last["cert"]["certified"],

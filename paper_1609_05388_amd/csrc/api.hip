@@ -61,7 +61,7 @@ struct Workspace {
   DevBuf rpQ, rpY, rpG, rpV, rpLam;
   DevBuf skpart, skG, skK, sklam, skV, skfeat, mlp_pb, mlp_X, mlp_f, mlp_hb, mlp_grad, mlp_loss;
   DevBuf knQ, knD, knNq64, knNd64, knNq32, knNd32, knMax, knKeys, knFb, knCnt, knTau;
-  DevBuf cidx, lam1, Vt1, Asub;
+  DevBuf cidx, lam1, Vt1, Asub, colmap, colminmax, colkeep;
   bool checked = false;
 };
 
@@ -127,6 +127,7 @@ struct EvPair {
 struct Points {
   const float* X = nullptr;
   int64_t n = 0, d = 0, n_pad = 0, ldx = 0;
+  int64_t dx = 0;            // columns of the screens' copies (non-constant columns of X)
   double* mu = nullptr;
   float* Xc = nullptr;
   double* nx = nullptr;
@@ -141,20 +142,32 @@ struct Points {
   double* nxq = nullptr;
 };
 
-static void mean_rows(Workspace& ws, const float* A, int64_t n, int64_t m, int64_t ld, double* mu, hipStream_t st) {
+// Column means (FP64) of the n x m rows of A.  With colmap, also the columns
+// that hold more than one value: colmap[0, k) lists them ascending and k is
+// returned (m without colmap); the others have exactly zero centred entries.
+static int64_t mean_rows(Workspace& ws, const float* A, int64_t n, int64_t m, int64_t ld, double* mu, hipStream_t st,
+                         int* colmap = nullptr) {
   const int64_t rows_per_chunk = 512;
   const int64_t nch = (n + rows_per_chunk - 1) / rows_per_chunk;
   double* part = ensure<double>(ws.colpart, (size_t)(nch * m));
-  int* flag = ensure<int>(ws.nonfinite, 1);
-  HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), st));
-  HIPCHK(launch_mean<float>(A, n, m, ld, part, nch, rows_per_chunk, mu, flag, st));
-  int h = 0;
-  HIPCHK(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  int* flag = ensure<int>(ws.nonfinite, 2);   // [0] non-finite, [1] kept columns
+  HIPCHK(hipMemsetAsync(flag, 0, 2 * sizeof(int), st));
+  if (colmap) {
+    double* pmm = ensure<double>(ws.colminmax, (size_t)(2 * nch * m));
+    int* keep = ensure<int>(ws.colkeep, (size_t)m);
+    HIPCHK(launch_mean<float>(A, n, m, ld, part, nch, rows_per_chunk, mu, flag, st, pmm, pmm + nch * m, keep));
+    HIPCHK(launch_compact_keep(keep, (int)m, colmap, flag + 1, st));
+  } else {
+    HIPCHK(launch_mean<float>(A, n, m, ld, part, nch, rows_per_chunk, mu, flag, st));
+  }
+  int h[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(h, flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  if (h) {
+  if (h[0]) {
     set_err("input contains NaN or Inf%s%lld", "", 0);
     throw Fail{ADAGIO_E_NONFINITE};
   }
+  return colmap ? (int64_t)h[1] : m;
 }
 
 // Bound constant for an FP32 Gram screen over K (padded) terms: covers the
@@ -175,29 +188,33 @@ static Points prep_points(Workspace& ws, const float* X, int64_t n, int64_t d, h
   p.n = n;
   p.d = d;
   p.n_pad = round_up(n, kTile);
-  p.ldx = round_up(d, kChunk);
   p.mu = ensure<double>(ws.mu, (size_t)d);
-  mean_rows(ws, X, n, d, d, p.mu, st);
+  // Columns that hold one value only centre to exact zeros and add nothing
+  // to any distance or Gram entry: the screens' copies leave them out.
+  int* colmap = ensure<int>(ws.colmap, (size_t)d);
+  p.dx = mean_rows(ws, X, n, d, d, p.mu, st, colmap);
+  const int64_t dxc = std::max<int64_t>(p.dx, 1);
+  p.ldx = round_up(dxc, kChunk);
   p.Xc = ensure<float>(ws.Xc, (size_t)(p.n_pad * p.ldx));
   p.nx = ensure<double>(ws.nx, (size_t)p.n_pad);
   p.tx = ensure<float2>(ws.tx, (size_t)p.n_pad);
-  HIPCHK(launch_center<float>(X, n, d, d, p.mu, p.Xc, p.ldx, p.n_pad, p.nx, st));
+  HIPCHK(launch_center<float>(X, n, p.dx, d, p.mu, p.Xc, p.ldx, p.n_pad, p.nx, st, colmap));
   HIPCHK(launch_row_terms(p.nx, screen_const(p.ldx), nullptr, 0.0, p.n_pad, p.tx, st));
   // The FP8 screen ranks pairs only; its fits end with a BF16 split
   // certificate, so both copies are made.
   if (screen == ADAGIO_SCREEN_BF16X3 || screen == ADAGIO_SCREEN_FP8) {
-    p.ldxb = round_up(d, kChunkBf16);
+    p.ldxb = round_up(dxc, kChunkBf16);
     p.Xb = ensure<__bf16>(ws.Xb, (size_t)(p.n_pad * 2 * p.ldxb));
     p.txb = ensure<float2>(ws.txb, (size_t)p.n_pad);
-    HIPCHK(launch_split_bf16(p.Xc, p.n_pad, d, p.ldx, p.ldxb, p.Xb, st));
+    HIPCHK(launch_split_bf16(p.Xc, p.n_pad, p.dx, p.ldx, p.ldxb, p.Xb, st));
     HIPCHK(launch_row_terms(p.nx, screen_const_bf16(p.ldxb), nullptr, 0.0, p.n_pad, p.txb, st));
   }
   if (screen == ADAGIO_SCREEN_FP8) {
-    p.ldxq = round_up(d, fp8_chunk());
+    p.ldxq = round_up(dxc, fp8_chunk());
     p.Xq = ensure<unsigned char>(ws.Xq, (size_t)(p.n_pad * p.ldxq));
     p.sx = ensure<float>(ws.sx, (size_t)p.n_pad);
     p.nxq = ensure<double>(ws.nxq, (size_t)p.n_pad);
-    HIPCHK(launch_quant_fp8(p.Xc, p.n_pad, d, p.ldx, p.ldxq, p.Xq, p.sx, p.nxq, st));
+    HIPCHK(launch_quant_fp8(p.Xc, p.n_pad, p.dx, p.ldx, p.ldxq, p.Xq, p.sx, p.nxq, st));
   }
   return p;
 }
@@ -1219,7 +1236,8 @@ int adagio_release(void) {
                       &ws.skpart, &ws.skG, &ws.skK, &ws.sklam, &ws.skV, &ws.skfeat, &ws.mlp_pb, &ws.mlp_X,
                       &ws.mlp_f, &ws.mlp_hb, &ws.mlp_grad, &ws.mlp_loss, &ws.knQ, &ws.knD, &ws.knNq64,
                       &ws.knNd64, &ws.knNq32, &ws.knNd32, &ws.knMax, &ws.knKeys, &ws.knFb, &ws.knCnt, &ws.knTau, &ws.cidx,
-                      &ws.lam1, &ws.Vt1, &ws.Asub};
+                      &ws.lam1, &ws.Vt1, &ws.Asub, &ws.colmap,
+                      &ws.colminmax, &ws.colkeep};
     for (DevBuf* b : bufs) {
       if (b->p) HIPCHK(hipFree(b->p));
       b->p = nullptr;

@@ -5,12 +5,17 @@
 namespace adg {
 
 // k_prep.hip
+// pmin/pmax (nchunks x m) and keep (m) may be null; with them keep[c] = 0
+// marks a column holding one value only.
 template <typename T>
 hipError_t launch_mean(const T* A, int64_t n, int64_t m, int64_t ld, double* partial, int64_t nchunks,
-                       int64_t rows_per_chunk, double* mu, int* nonfinite, hipStream_t st);
+                       int64_t rows_per_chunk, double* mu, int* nonfinite, hipStream_t st,
+                       double* pmin = nullptr, double* pmax = nullptr, int* keep = nullptr);
+hipError_t launch_compact_keep(const int* keep, int m, int* idx, int* k_out, hipStream_t st);
+// colmap (m entries, may be null): source column of each destination column.
 template <typename T>
 hipError_t launch_center(const T* src, int64_t n, int64_t m, int64_t lds, const double* mu, float* dst,
-                         int64_t ldd, int64_t n_pad, double* norm2, hipStream_t st);
+                         int64_t ldd, int64_t n_pad, double* norm2, hipStream_t st, const int* colmap = nullptr);
 hipError_t launch_row_terms(const double* norm2, double c_self, const double* norm2_other, double c_other,
                             int64_t n_pad, float2* terms, hipStream_t st);
 
