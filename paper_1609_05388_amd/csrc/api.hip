@@ -128,6 +128,7 @@ struct Points {
   const float* X = nullptr;
   int64_t n = 0, d = 0, n_pad = 0, ldx = 0;
   int64_t dx = 0;            // columns of the screens' copies (non-constant columns of X)
+  const int* colmap = nullptr;  // those columns, ascending (device)
   double* mu = nullptr;
   float* Xc = nullptr;
   double* nx = nullptr;
@@ -193,6 +194,7 @@ static Points prep_points(Workspace& ws, const float* X, int64_t n, int64_t d, h
   // to any distance or Gram entry: the screens' copies leave them out.
   int* colmap = ensure<int>(ws.colmap, (size_t)d);
   p.dx = mean_rows(ws, X, n, d, d, p.mu, st, colmap);
+  p.colmap = colmap;
   const int64_t dxc = std::max<int64_t>(p.dx, 1);
   p.ldx = round_up(dxc, kChunk);
   p.Xc = ensure<float>(ws.Xc, (size_t)(p.n_pad * p.ldx));
@@ -498,7 +500,7 @@ static Images images_of_map(Workspace& ws, const Points& p, const float* Pi, int
   im.r = r;
   im.ldy = round_up(r, kChunk);
   double* Y64 = ensure<double>(ws.Y64, (size_t)(p.n * r));
-  HIPCHK(launch_embed_f64(p.X, p.n, p.d, p.mu, Pi, r, Y64, st));
+  HIPCHK(launch_embed_f64(p.X, p.n, p.d, p.mu, Pi, r, Y64, st, p.dx < p.d ? p.colmap : nullptr, p.dx));
   im.Yc = ensure<float>(ws.Yc, (size_t)(p.n_pad * im.ldy));
   double* ny = ensure<double>(ws.ny, (size_t)p.n_pad);
   HIPCHK(launch_center<double>(Y64, p.n, r, r, nullptr, im.Yc, im.ldy, p.n_pad, ny, st));

@@ -5,6 +5,8 @@
 // One generic 64 x 64-tile kernel on v_mfma_f64_16x16x4f64: four waves, each
 // a 32 x 32 block of 2 x 2 MFMA tiles, K staged through LDS in chunks of 16
 // with the next chunk prefetched into registers.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -40,6 +42,20 @@ struct RowsF32T {         // B(k, n) = P[n][k] for an FP32 rows x cols matrix
   const float* P; int64_t rows, cols;
   __device__ double operator()(int64_t k, int64_t n) const {
     return (n < rows && k < cols) ? (double)P[n * cols + k] : 0.0;
+  }
+};
+struct CentredRowsMap {   // A(m, k) = X[m][c] - mu[c], c = cmap[k], k < kc (only the mapped columns)
+  const float* X; const double* mu; int64_t n, d; const int* cmap; int64_t kc;
+  __device__ double operator()(int64_t m, int64_t k) const {
+    if (m >= n || k >= kc) return 0.0;
+    const int64_t c = cmap[k];
+    return (double)X[m * d + c] - mu[c];
+  }
+};
+struct RowsF32TMap {      // B(k, n) = P[n][cmap[k]], k < kc
+  const float* P; int64_t rows, cols; const int* cmap; int64_t kc;
+  __device__ double operator()(int64_t k, int64_t n) const {
+    return (n < rows && k < kc) ? (double)P[n * cols + cmap[k]] : 0.0;
   }
 };
 struct RowsF64 {          // A(m, k) = M[m][k]
@@ -235,12 +251,20 @@ hipError_t launch_covariance(const float* X, int64_t n, int64_t d, const double*
 
 // Y64[i][c] = sum_l (X[i][l] - mu[l]) Pi[c][l]   (n x r, FP64, ld = r)
 hipError_t launch_embed_f64(const float* X, int64_t n, int64_t d, const double* mu, const float* Pi,
-                            int64_t r, double* Y, hipStream_t st) {
+                            int64_t r, double* Y, hipStream_t st, const int* cmap, int64_t kc) {
   const int64_t tm = (n + GT - 1) / GT, tn = (r + GT - 1) / GT;
-  CentredRows A{X, mu, n, d};
-  RowsF32T B{Pi, r, d};
   StoreF64 S{Y, n, r, r, 0};
-  k_gemm64<CentredRows, RowsF32T, StoreF64, true, true, false><<<(unsigned)(tm * tn), 256, 0, st>>>(A, B, S, n, r, d, round_up(d, GK), tn);
+  if (cmap) {
+    // constant coordinates centre to exact zeros: the sum runs over the others
+    CentredRowsMap A{X, mu, n, d, cmap, kc};
+    RowsF32TMap B{Pi, r, d, cmap, kc};
+    k_gemm64<CentredRowsMap, RowsF32TMap, StoreF64, true, true, false><<<(unsigned)(tm * tn), 256, 0, st>>>(
+        A, B, S, n, r, kc, round_up(std::max<int64_t>(kc, 1), GK), tn);
+  } else {
+    CentredRows A{X, mu, n, d};
+    RowsF32T B{Pi, r, d};
+    k_gemm64<CentredRows, RowsF32T, StoreF64, true, true, false><<<(unsigned)(tm * tn), 256, 0, st>>>(A, B, S, n, r, d, round_up(d, GK), tn);
+  }
   return hipGetLastError();
 }
 

@@ -22,8 +22,9 @@ hipError_t launch_row_terms(const double* norm2, double c_self, const double* no
 // k_gemm64.hip
 hipError_t launch_covariance(const float* X, int64_t n, int64_t d, const double* mu, double* part, int nsplit,
                              double* C, int64_t m_pad, hipStream_t st);
+// cmap (kc entries, may be null): only these columns of X and Pi enter the sum.
 hipError_t launch_embed_f64(const float* X, int64_t n, int64_t d, const double* mu, const float* Pi, int64_t r,
-                            double* Y, hipStream_t st);
+                            double* Y, hipStream_t st, const int* cmap = nullptr, int64_t kc = 0);
 hipError_t launch_embed_f32(const float* X, int64_t n, int64_t d, const float* Pi, int64_t r, float* Y,
                             hipStream_t st);
 hipError_t launch_proj_T(const double* S, int64_t k, int64_t d, const double* Vt, int64_t s, double* T,

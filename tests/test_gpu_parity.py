@@ -89,6 +89,27 @@ def test_fit_parity_constant_coordinates(gpu_lib):
         assert abs(got["cert"]["max_distortion"] - want["cert"]["max"]) <= TOL
 
 
+@pytest.mark.parametrize("varying", [0, 1, 3])
+def test_nearly_constant_clouds(gpu_lib, varying):
+    """Clouds where only `varying` coordinates are not constant (0: all points
+    identical): the screens' copies keep only those coordinates, the PCA
+    splits off the others; the fit is certified and agrees with the oracle."""
+    rng = np.random.default_rng(70 + varying)
+    X = np.full((300, 40), np.float32(0.5), dtype=np.float32)
+    X[:, 7] = np.float32(-1.25)
+    cols = [3, 19, 31][:varying]
+    X[:, cols] = rng.standard_normal((300, varying)).astype(np.float32)
+    lam, Vt = gpu_lib.pca(dev(X))
+    lam, Vt = lam.cpu().numpy(), Vt.cpu().numpy()
+    assert np.all(lam[varying:] == 0)
+    assert np.abs(Vt @ Vt.T - np.eye(40)).max() <= 1e-12 * 40
+    got = gpu_lib.fit(dev(X), 0.1, gen.JL_SEED)
+    c = got["cert"]
+    assert c["certified"] == 1 and c["max_distortion"] <= 0.1
+    want = oracle_cert_of_map(X, got["Pi"].cpu().numpy())
+    assert abs(c["max_distortion"] - want["max"]) <= TOL
+
+
 # ------------------------------------------------------------------- a4-a5
 @pytest.mark.parametrize("d,r", [(40, 1), (40, 2), (40, 3), (40, 17), (40, 39), (40, 40), (784, 190), (784, 391)])
 def test_project_axes_matches_oracle(gpu_lib, d, r):
