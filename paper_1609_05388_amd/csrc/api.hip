@@ -61,7 +61,7 @@ struct Workspace {
   DevBuf rpQ, rpY, rpG, rpV, rpLam;
   DevBuf skpart, skG, skK, sklam, skV, skfeat, mlp_pb, mlp_X, mlp_f, mlp_hb, mlp_grad, mlp_loss;
   DevBuf knQ, knD, knNq64, knNd64, knNq32, knNd32, knMax, knKeys, knFb, knCnt, knTau;
-  DevBuf cidx, lam1, Vt1, Asub, colmap, colminmax, colkeep;
+  DevBuf lam1, Vt1, colmap, colminmax, colkeep;
   bool checked = false;
 };
 
@@ -273,9 +273,10 @@ static int jacobi_eig(Workspace& ws, double* A, int m, int64_t d, double* lam, d
 }
 
 // C = sum_i (x_i - mu)(x_i - mu)^T into ws.A0 (m x m, zero padding; m = d
-// rounded up to a multiple of two Jacobi blocks).
-static double* covariance(Workspace& ws, const Points& p, int m, hipStream_t st) {
-  const int64_t d = p.d;
+// rounded up to a multiple of two Jacobi blocks); with `compact`, the
+// covariance of the non-constant coordinates p.colmap[0, p.dx) only.
+static double* covariance(Workspace& ws, const Points& p, int m, hipStream_t st, bool compact = false) {
+  const int64_t d = compact ? p.dx : p.d;
   // split-K over points so that the grid fills the GPU
   const int64_t NT = (d + 63) / 64;
   const int64_t ntiles = NT * (NT + 1) / 2;
@@ -285,7 +286,8 @@ static double* covariance(Workspace& ws, const Points& p, int m, hipStream_t st)
   if (nsplit < 1) nsplit = 1;
   double* part = ensure<double>(ws.covpart, (size_t)(nsplit * d * d));
   double* A = ensure<double>(ws.A0, (size_t)m * m);
-  HIPCHK(launch_covariance(p.X, p.n, d, p.mu, part, nsplit, A, m, st));
+  if (compact) HIPCHK(launch_covariance(p.X, p.n, p.d, p.mu, part, nsplit, A, m, st, p.colmap, p.dx));
+  else HIPCHK(launch_covariance(p.X, p.n, d, p.mu, part, nsplit, A, m, st));
   return A;
 }
 
@@ -332,32 +334,29 @@ static Axes principal_axes(Workspace& ws, const Points& p, hipStream_t st, doubl
                            double* Vt_out = nullptr) {
   const int64_t d = p.d;
   // block Jacobi works on m = d rounded up to a multiple of two index blocks
-  const int m = (int)round_up(d, 2 * bj_block());
-  double* A = covariance(ws, p, m, st);
   Axes ax;
   ax.lam = lam_out ? lam_out : ensure<double>(ws.lam, (size_t)d);
   ax.Vt = Vt_out ? Vt_out : ensure<double>(ws.Vt, (size_t)(d * d));
-  // Exactly constant coordinates (C_ii = 0) split off a zero block of C: the
-  // eigensolver runs on the block of the others only.
-  int* idx = ensure<int>(ws.cidx, (size_t)d + 1);
-  HIPCHK(launch_const_coords(A, m, (int)d, idx, idx + d, st));
-  int d1 = 0;
-  HIPCHK(hipMemcpyAsync(&d1, idx + d, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  if (d1 == d) {
+  if (p.dx == d || !p.colmap) {
+    const int m = (int)round_up(d, 2 * bj_block());
+    double* A = covariance(ws, p, m, st);
     ax.sweeps = jacobi_eig(ws, A, m, d, ax.lam, ax.Vt, st);
     return ax;
   }
-  double* lam1 = ensure<double>(ws.lam1, (size_t)std::max(d1, 1));
-  double* Vt1 = ensure<double>(ws.Vt1, (size_t)std::max(d1, 1) * std::max(d1, 1));
+  // Coordinates that hold one value over the cloud (listed after the others
+  // in p.colmap) split off an exactly zero block of C: the eigensolver runs
+  // on the covariance of the others only.
+  const int64_t d1 = p.dx;
+  double* lam1 = ensure<double>(ws.lam1, (size_t)std::max<int64_t>(d1, 1));
+  double* Vt1 = ensure<double>(ws.Vt1, (size_t)std::max<int64_t>(d1, 1) * std::max<int64_t>(d1, 1));
   ax.sweeps = 0;
   if (d1 > 0) {
     const int m1 = (int)round_up(d1, 2 * bj_block());
-    double* A1 = ensure<double>(ws.Asub, (size_t)m1 * m1);
-    HIPCHK(launch_gather_sym(A, m, idx, d1, A1, m1, st));
+    double* A1 = covariance(ws, p, m1, st, true);
     ax.sweeps = jacobi_eig(ws, A1, m1, d1, lam1, Vt1, st);
   }
-  HIPCHK(launch_scatter_axes(lam1, Vt1, idx, d1, (int)d, ax.lam, ax.Vt, st));
+  const int* idx = p.colmap;
+  HIPCHK(launch_scatter_axes(lam1, Vt1, idx, (int)d1, (int)d, ax.lam, ax.Vt, st));
   return ax;
 }
 
@@ -1237,8 +1236,8 @@ int adagio_release(void) {
                       &ws.rpG, &ws.rpV, &ws.rpLam,
                       &ws.skpart, &ws.skG, &ws.skK, &ws.sklam, &ws.skV, &ws.skfeat, &ws.mlp_pb, &ws.mlp_X,
                       &ws.mlp_f, &ws.mlp_hb, &ws.mlp_grad, &ws.mlp_loss, &ws.knQ, &ws.knD, &ws.knNq64,
-                      &ws.knNd64, &ws.knNq32, &ws.knNd32, &ws.knMax, &ws.knKeys, &ws.knFb, &ws.knCnt, &ws.knTau, &ws.cidx,
-                      &ws.lam1, &ws.Vt1, &ws.Asub, &ws.colmap,
+                      &ws.knNd64, &ws.knNq32, &ws.knNd32, &ws.knMax, &ws.knKeys, &ws.knFb, &ws.knCnt, &ws.knTau,
+                      &ws.lam1, &ws.Vt1, &ws.colmap,
                       &ws.colminmax, &ws.colkeep};
     for (DevBuf* b : bufs) {
       if (b->p) HIPCHK(hipFree(b->p));

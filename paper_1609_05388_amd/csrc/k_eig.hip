@@ -58,64 +58,14 @@ __global__ void k_eig_sort(const double* __restrict__ A, const double* __restric
   for (int l = threadIdx.x; l < d; l += 256) Vt[(int64_t)rk * d + l] = W[(int64_t)a * m + l];
 }
 
-// Constant coordinates.  A coordinate whose centred values are all exactly
-// zero has C_ii = 0, and then its whole row and column of C are zero (every
-// term of C_ij carries the factor x_i - mu_i = 0): C is block diagonal with
-// a zero block, so the eigenpairs of C are those of the block of the other
-// coordinates, embedded, plus eigenvalue 0 with the unit vectors of the
-// constant coordinates.  One workgroup lists the coordinates with C_ii != 0
-// (ascending) in idx[0, d1) and the others in idx[d1, d); *d1_out = d1.
-__global__ __launch_bounds__(1024) void k_const_coords(const double* __restrict__ A, int m, int d,
-                                                       int* __restrict__ idx, int* __restrict__ d1_out) {
-  __shared__ int wsum[2][16];
-  __shared__ int base[2];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid == 0) { base[0] = 0; base[1] = 0; }
-  __syncthreads();
-  // first pass: count the non-constant coordinates
-  int nz = 0;
-  for (int i = tid; i < d; i += 1024) nz += A[(int64_t)i * m + i] != 0.0 ? 1 : 0;
-  for (int o = 32; o >= 1; o >>= 1) nz += __shfl_xor(nz, o, 64);
-  if (lane == 0) wsum[0][wave] = nz;
-  __syncthreads();
-  int d1 = 0;
-  for (int w = 0; w < 16; ++w) d1 += wsum[0][w];
-  __syncthreads();
-  // second pass: stable compaction, 1024 coordinates at a time
-  for (int c0 = 0; c0 < d; c0 += 1024) {
-    const int i = c0 + tid;
-    const bool in = i < d;
-    const bool keep = in && A[(int64_t)i * m + i] != 0.0;
-    const uint64_t bk = __builtin_amdgcn_ballot_w64(keep);
-    const uint64_t bz = __builtin_amdgcn_ballot_w64(in && !keep);
-    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    if (lane == 0) { wsum[0][wave] = __popcll(bk); wsum[1][wave] = __popcll(bz); }
-    __syncthreads();
-    int ok = base[0], oz = base[1];
-    for (int w = 0; w < wave; ++w) { ok += wsum[0][w]; oz += wsum[1][w]; }
-    if (keep) idx[ok + __popcll(bk & below)] = i;
-    else if (in) idx[d1 + oz + __popcll(bz & below)] = i;
-    __syncthreads();
-    if (tid == 0) {
-      for (int w = 0; w < 16; ++w) { base[0] += wsum[0][w]; base[1] += wsum[1][w]; }
-    }
-    __syncthreads();
-  }
-  if (tid == 0) *d1_out = d1;
-}
-
-// A1 = the d1 x d1 block of A on the coordinates idx[0, d1), zero padding to
-// m1 x m1.
-__global__ void k_gather_sym(const double* __restrict__ A, int m, const int* __restrict__ idx, int d1,
-                             double* __restrict__ A1, int m1) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)m1 * m1) return;
-  const int i = (int)(e / m1), j = (int)(e % m1);
-  A1[e] = (i < d1 && j < d1) ? A[(int64_t)idx[i] * m + idx[j]] : 0.0;
-}
-
+// Constant coordinates: a coordinate whose centred values are all exactly
+// zero has an all-zero row and column of C (every term of C_ij carries the
+// factor x_i - mu_i = 0), so C is block diagonal with a zero block and its
+// eigenpairs are those of the block of the other coordinates, embedded, plus
+// eigenvalue 0 with the unit vectors of the constant coordinates.
 // Eigenpairs of C from those of its non-constant block (lam1 decreasing,
-// Vt1 rows, d1 of each) and eigenvalue 0 for each constant coordinate:
+// Vt1 rows, d1 of each; idx[0, d1) its coordinates, idx[d1, d) the constant
+// ones) and eigenvalue 0 for each constant coordinate:
 // element a < d1 is (lam1[a], Vt1[a] scattered to the coordinates idx[0, d1)),
 // element a >= d1 is (0, unit vector of coordinate idx[a]); sorted by
 // decreasing value, ties by a.  One workgroup per element.
@@ -150,14 +100,6 @@ __global__ void k_scatter_axes(const double* __restrict__ lam1, const double* __
 }
 
 // ---------------------------------------------------------------- launchers
-hipError_t launch_const_coords(const double* A, int m, int d, int* idx, int* d1, hipStream_t st) {
-  k_const_coords<<<1, 1024, 0, st>>>(A, m, d, idx, d1);
-  return hipGetLastError();
-}
-hipError_t launch_gather_sym(const double* A, int m, const int* idx, int d1, double* A1, int m1, hipStream_t st) {
-  k_gather_sym<<<(unsigned)(((int64_t)m1 * m1 + 255) / 256), 256, 0, st>>>(A, m, idx, d1, A1, m1);
-  return hipGetLastError();
-}
 hipError_t launch_scatter_axes(const double* lam1, const double* Vt1, const int* idx, int d1, int d, double* lam,
                                double* Vt, hipStream_t st) {
   k_scatter_axes<<<(unsigned)d, 256, 0, st>>>(lam1, Vt1, idx, d1, d, lam, Vt);

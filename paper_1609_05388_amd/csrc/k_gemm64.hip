@@ -30,6 +30,22 @@ struct CentredColsB {     // B(k, n) = X[k][n] - mu[n]  (k = point, n = feature)
     return (c < d && k < n) ? (double)X[k * d + c] - mu[c] : 0.0;
   }
 };
+struct CentredColsMap {   // A(m, k) = X[k][c] - mu[c], c = cmap[m], m < kc (mapped features only)
+  const float* X; const double* mu; int64_t n, d; const int* cmap; int64_t kc;
+  __device__ double operator()(int64_t m, int64_t k) const {
+    if (m >= kc || k >= n) return 0.0;
+    const int64_t c = cmap[m];
+    return (double)X[k * d + c] - mu[c];
+  }
+};
+struct CentredColsBMap {  // B(k, c') = X[k][cmap[c']] - mu[cmap[c']], c' < kc
+  const float* X; const double* mu; int64_t n, d; const int* cmap; int64_t kc;
+  __device__ double operator()(int64_t k, int64_t c2) const {
+    if (c2 >= kc || k >= n) return 0.0;
+    const int64_t c = cmap[c2];
+    return (double)X[k * d + c] - mu[c];
+  }
+};
 struct CentredRows {      // A(m, k) = X[m][k] - mu[k]  (m = point, k = feature); mu may be NULL
   const float* X; const double* mu; int64_t n, d;
   __device__ double operator()(int64_t m, int64_t k) const {
@@ -234,18 +250,25 @@ __global__ void k_cov_reduce(const double* __restrict__ part, int nsplit, int64_
 
 // ---------------------------------------------------------------- launchers
 hipError_t launch_covariance(const float* X, int64_t n, int64_t d, const double* mu, double* part,
-                             int nsplit, double* C, int64_t m_pad, hipStream_t st) {
-  const int64_t NT = (d + GT - 1) / GT;
+                             int nsplit, double* C, int64_t m_pad, hipStream_t st, const int* cmap, int64_t kc) {
+  const int64_t D = cmap ? kc : d;   // features in the result
+  const int64_t NT = (D + GT - 1) / GT;
   const int64_t ntiles = NT * (NT + 1) / 2;
   int64_t kps = round_up((n + nsplit - 1) / nsplit, GK);
-  CentredCols A{X, mu, n, d};
-  CentredColsB B{X, mu, n, d};
-  StoreF64 S{part, d, d, d, d * d};
+  StoreF64 S{part, D, D, D, D * D};
   dim3 g((unsigned)ntiles, (unsigned)nsplit);
-  k_gemm64<CentredCols, CentredColsB, StoreF64, false, false, true><<<g, 256, 0, st>>>(A, B, S, d, d, n, kps, NT);
+  if (cmap) {
+    CentredColsMap A{X, mu, n, d, cmap, kc};
+    CentredColsBMap B{X, mu, n, d, cmap, kc};
+    k_gemm64<CentredColsMap, CentredColsBMap, StoreF64, false, false, true><<<g, 256, 0, st>>>(A, B, S, D, D, n, kps, NT);
+  } else {
+    CentredCols A{X, mu, n, d};
+    CentredColsB B{X, mu, n, d};
+    k_gemm64<CentredCols, CentredColsB, StoreF64, false, false, true><<<g, 256, 0, st>>>(A, B, S, D, D, n, kps, NT);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_cov_reduce<<<(unsigned)((m_pad * m_pad + 255) / 256), 256, 0, st>>>(part, nsplit, d, m_pad, C);
+  k_cov_reduce<<<(unsigned)((m_pad * m_pad + 255) / 256), 256, 0, st>>>(part, nsplit, D, m_pad, C);
   return hipGetLastError();
 }
 

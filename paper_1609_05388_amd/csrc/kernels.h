@@ -20,8 +20,9 @@ hipError_t launch_row_terms(const double* norm2, double c_self, const double* no
                             int64_t n_pad, float2* terms, hipStream_t st);
 
 // k_gemm64.hip
+// cmap (kc entries, may be null): the covariance of these features only (kc x kc).
 hipError_t launch_covariance(const float* X, int64_t n, int64_t d, const double* mu, double* part, int nsplit,
-                             double* C, int64_t m_pad, hipStream_t st);
+                             double* C, int64_t m_pad, hipStream_t st, const int* cmap = nullptr, int64_t kc = 0);
 // cmap (kc entries, may be null): only these columns of X and Pi enter the sum.
 hipError_t launch_embed_f64(const float* X, int64_t n, int64_t d, const double* mu, const float* Pi, int64_t r,
                             double* Y, hipStream_t st, const int* cmap = nullptr, int64_t kc = 0);
@@ -37,8 +38,6 @@ hipError_t launch_eye(double* W, int m, hipStream_t st);
 hipError_t launch_trace(const double* A, int m, double* out, hipStream_t st);
 hipError_t launch_eig_sort(const double* A, const double* W, int m, int d, double* lam, double* Vt,
                            hipStream_t st);
-hipError_t launch_const_coords(const double* A, int m, int d, int* idx, int* d1, hipStream_t st);
-hipError_t launch_gather_sym(const double* A, int m, const int* idx, int d1, double* A1, int m1, hipStream_t st);
 hipError_t launch_scatter_axes(const double* lam1, const double* Vt1, const int* idx, int d1, int d, double* lam,
                                double* Vt, hipStream_t st);
 
