@@ -108,10 +108,10 @@ def summarize_traffic(d):
         "hbm_bytes_per_launch": hb,
         "fetch": out["FETCH_SIZE"], "write": out["WRITE_SIZE"],
         "commands": [
-            "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d <repo>/gpurun_out/pmc -o copy_FETCH_SIZE -- python3 <repo>/bench.py --calib-copy-mib 1024",
-            "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d <repo>/gpurun_out/pmc -o fit_FETCH_SIZE -- python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extra-eps --no-forms --no-large",
+            "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pmc -o copy_FETCH_SIZE -- python3 <repo>/bench.py --calib-copy-mib 1024",
+            "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pmc -o fit_FETCH_SIZE -- python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extra-eps --no-forms --no-large --no-knn",
             "(the same two with WRITE_SIZE)",
-            "python3 <repo>/bench.py --summarize-traffic <repo>/gpurun_out/pmc",
+            "python3 <repo>/bench.py --summarize-traffic <out>/pmc",
         ],
         "note": "counter bytes are KiB x 1024 per dispatch; one fit: the mean of its k_pairs_f32<0, false> "
                 "launches (point Gram computed and stored) and of its k_pairs_f32<0, true> launches (point Gram "
