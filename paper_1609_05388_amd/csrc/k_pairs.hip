@@ -37,7 +37,13 @@ namespace adg {
 
 constexpr int PT = kTile;   // 128
 constexpr int PK = kChunk;  // 16
-constexpr int PLD = 20;     // LDS row stride in floats (conflict-free b128 reads)
+constexpr int PLD = 16;     // LDS row stride in floats (no padding; see lds_at)
+
+// LDS position of float4 number q (0..3) of row `row` in a chunk buffer: the
+// float4s of a row are XOR-swizzled with bits 2-3 of the row, so that both
+// the staging writes (4 rows x 4 float4s per 16 lanes) and the MFMA operand
+// reads (16 rows x 1 float4 per 16 lanes) hit 16 distinct 4-bank groups.
+__device__ inline int lds_at(int row, int q) { return row * PLD + ((q ^ (row >> 2)) & 3) * 4; }
 
 
 // LOADED (MODE 0 only): the point Gram comes from the cache; the kernel runs
@@ -123,10 +129,10 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_f32(PairsArgs p) 
       }
     };
     auto stash = [&](int buf) __attribute__((always_inline)) {
-      *reinterpret_cast<float4*>(&As[buf][lr * PLD + lc]) = ga0;
-      *reinterpret_cast<float4*>(&As[buf][(lr + 64) * PLD + lc]) = ga1;
-      *reinterpret_cast<float4*>(&Bs[buf][lr * PLD + lc]) = gb0;
-      *reinterpret_cast<float4*>(&Bs[buf][(lr + 64) * PLD + lc]) = gb1;
+      *reinterpret_cast<float4*>(&As[buf][lds_at(lr, lc >> 2)]) = ga0;
+      *reinterpret_cast<float4*>(&As[buf][lds_at(lr + 64, lc >> 2)]) = ga1;
+      *reinterpret_cast<float4*>(&Bs[buf][lds_at(lr, lc >> 2)]) = gb0;
+      *reinterpret_cast<float4*>(&Bs[buf][lds_at(lr + 64, lc >> 2)]) = gb1;
     };
     // MFMA step kk sums columns kk (lanes 0-31) and 8 + kk (lanes 32-63) of
     // the chunk; the same permutation is used for both operands.
@@ -136,8 +142,8 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_f32(PairsArgs p) 
         float4 a4[2], b4[2];
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
-          a4[x] = *reinterpret_cast<const float4*>(&As[buf][(wr * 64 + x * 32 + li) * PLD + lh * 8 + half * 4]);
-          b4[x] = *reinterpret_cast<const float4*>(&Bs[buf][(wc * 64 + x * 32 + li) * PLD + lh * 8 + half * 4]);
+          a4[x] = *reinterpret_cast<const float4*>(&As[buf][lds_at(wr * 64 + x * 32 + li, lh * 2 + half)]);
+          b4[x] = *reinterpret_cast<const float4*>(&Bs[buf][lds_at(wc * 64 + x * 32 + li, lh * 2 + half)]);
         }
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk)
