@@ -41,12 +41,18 @@ namespace adg {
 constexpr int KN_T = 128;     // database rows per tile
 constexpr int KN_Q = kKnnQueries;  // queries per block
 constexpr int KN_C = 16;      // chunk width
-constexpr int KN_LD = 20;     // LDS operand row stride (floats)
+constexpr int KN_LD = 16;     // LDS operand row stride (floats, unpadded; see kn_at)
 constexpr int KN_QC = 64;     // queue capacity per query
 constexpr int KN_LST = kKnnKeep + 1;  // padded list row (u64)
 constexpr uint64_t kKnnEmpty = (0xFF800000ull << 32) | 0xFFFFFFFFull;  // key of (+inf, no row)
 
-// 81,680 bytes: two workgroups share a CU's 160 KB.
+// LDS position of float4 number q (0..3) of row `row` in a chunk buffer: the
+// float4s of a row are XOR-swizzled with bits 2-3 of the row, so that the
+// staging writes (4 rows x 4 float4s per 16 lanes) and the MFMA operand reads
+// (16 rows x 1 float4 per 16 lanes) both hit 16 distinct 4-bank groups.
+__device__ inline int kn_at(int row, int q) { return row * KN_LD + ((q ^ (row >> 2)) & 3) * 4; }
+
+// 75,536 bytes: two workgroups share a CU's 160 KB.
 struct KnnLds {
   float As[2][KN_T * KN_LD];  // database chunk
   float Bs[2][KN_Q * KN_LD];  // query chunk
@@ -184,9 +190,9 @@ __global__ __launch_bounds__(256, 2) void k_knn_screen(KnnScreenArgs p) {
     gb0 = *reinterpret_cast<const float4*>(qa + cb);
   };
   auto stash = [&](int buf) __attribute__((always_inline)) {
-    *reinterpret_cast<float4*>(&sm.As[buf][lr * KN_LD + lc]) = ga0;
-    *reinterpret_cast<float4*>(&sm.As[buf][(lr + 64) * KN_LD + lc]) = ga1;
-    *reinterpret_cast<float4*>(&sm.Bs[buf][lr * KN_LD + lc]) = gb0;
+    *reinterpret_cast<float4*>(&sm.As[buf][kn_at(lr, lc >> 2)]) = ga0;
+    *reinterpret_cast<float4*>(&sm.As[buf][kn_at(lr + 64, lc >> 2)]) = ga1;
+    *reinterpret_cast<float4*>(&sm.Bs[buf][kn_at(lr, lc >> 2)]) = gb0;
   };
 
   const int gend = (t1 - t0) * p.nch;
@@ -232,11 +238,11 @@ __global__ __launch_bounds__(256, 2) void k_knn_screen(KnnScreenArgs p) {
       // 32-63), the same permutation for both operands.
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
-        const float4 a4 = *reinterpret_cast<const float4*>(&sm.As[buf][(wave * 32 + li) * KN_LD + lh * 8 + half * 4]);
+        const float4 a4 = *reinterpret_cast<const float4*>(&sm.As[buf][kn_at(wave * 32 + li, lh * 2 + half)]);
         float4 b4[2];
 #pragma unroll
         for (int y = 0; y < 2; ++y)
-          b4[y] = *reinterpret_cast<const float4*>(&sm.Bs[buf][(y * 32 + li) * KN_LD + lh * 8 + half * 4]);
+          b4[y] = *reinterpret_cast<const float4*>(&sm.Bs[buf][kn_at(y * 32 + li, lh * 2 + half)]);
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
