@@ -11,9 +11,12 @@
 //   of 64 queries and keeps, per query, the KP = 32 smallest estimates as
 //   64-bit keys (order-preserving bits of est, then the database index); two
 //   workgroups share a CU, so one's MFMAs overlap the other's selection.
-//   Candidates below the query's current 32nd key go to an LDS queue; the
-//   queue is merged into the sorted list when any query's queue holds more
-//   than 32 entries, so a sub-step (32 candidates per query) never overflows.
+//   Candidates below the query's current 32nd key go to an LDS queue of 64
+//   slots: each lane reserves its slots for the whole tile with one atomic
+//   per query, and the queues are merged into the sorted lists when one
+//   passes 32 entries.  A tile whose candidates would not fit (the first
+//   tiles of a scan) is taken in four sub-steps of at most 32 candidates per
+//   query with a merge check after each.
 // Stage 2, k_knn_finish (one wave per query): the KP smallest keys over all
 //   splits, their exact FP64 distances, the k best by (distance, index), and a
 //   check that no row outside the KP can enter the answer:
@@ -52,14 +55,15 @@ constexpr uint64_t kKnnEmpty = (0xFF800000ull << 32) | 0xFFFFFFFFull;  // key of
 // (16 rows x 1 float4 per 16 lanes) both hit 16 distinct 4-bank groups.
 __device__ inline int kn_at(int row, int q) { return row * KN_LD + ((q ^ (row >> 2)) & 3) * 4; }
 
-// 75,536 bytes: two workgroups share a CU's 160 KB.
+// 76,048 bytes: two workgroups share a CU's 160 KB.
 struct KnnLds {
   float As[2][KN_T * KN_LD];  // database chunk
   float Bs[2][KN_Q * KN_LD];  // query chunk
   float nd[KN_T];
   float nq[KN_Q], tau[KN_Q];
   int cnt[KN_Q];
-  int flag, pad0, pad1, pad2;
+  int res[2][KN_Q];           // slots reserved by the current / previous tile
+  int flag, flag2, pad0, pad1;
   uint64_t L[KN_Q * KN_LST];
   uint64_t Qu[KN_Q * KN_QC];
 };
@@ -171,8 +175,10 @@ __global__ __launch_bounds__(256, 2) void k_knn_screen(KnnScreenArgs p) {
     sm.nq[tid] = p.nq32[q0 + tid];
     sm.tau[tid] = __uint_as_float(0x7f800000u);
     sm.cnt[tid] = 0;
+    sm.res[0][tid] = 0;
+    sm.res[1][tid] = 0;
   }
-  if (tid == 0) sm.flag = 0;
+  if (tid == 0) { sm.flag = 0; sm.flag2 = 0; }
   for (int e = tid; e < KN_Q * KN_LST; e += 256) sm.L[e] = kKnnEmpty;
 
   // loads: database rows lr and lr + 64, query row lr (threads < 256 cover
@@ -220,6 +226,12 @@ __global__ __launch_bounds__(256, 2) void k_knn_screen(KnnScreenArgs p) {
 
   for (int t = t0; t < t1; ++t) {
     const int row0 = t * KN_T;
+    // the previous tile's reserved slots become committed queue entries
+    // (its writes are complete: a barrier separates them from here)
+    if (t > t0 && tid < KN_Q) {
+      sm.cnt[tid] += sm.res[(t - 1) & 1][tid];
+      sm.res[(t - 1) & 1][tid] = 0;
+    }
     f32x16 acc[2];
     acc[0] = (f32x16){0};
     acc[1] = (f32x16){0};
@@ -261,71 +273,126 @@ __global__ __launch_bounds__(256, 2) void k_knn_screen(KnnScreenArgs p) {
     // that holds this block's queries as rows.
     const bool masked = (row0 + KN_T > p.nd) || (p.excl && q0 >= row0 && q0 < row0 + KN_T);
     // D layout: lane l, register v -> row (v / 4) * 8 + (l / 32) * 4 + v % 4,
-    // column l % 32.  Sub-step s takes registers 4s .. 4s + 3: 4 candidates
-    // per lane and query, 32 per query over the 4 waves.
+    // column l % 32: 16 candidates per lane and query, 128 per query over the
+    // 4 waves.  All 32 estimates of the lane first (straight-line code).
+    float est[16][2];
+    auto eval = [&](auto maskc) __attribute__((always_inline)) {
+      constexpr bool M = decltype(maskc)::value;
 #pragma unroll
-    for (int st = 0; st < 4; ++st) {
-      const int stamp = (t - t0) * 4 + st + 1;
-      // All estimates of the sub-step first (straight-line code), then the
-      // appends only in waves where some candidate passes its filter: after
-      // the first tiles most sub-steps pass none.
-      float est[4][2];
-      bool any = false;
-      auto eval = [&](auto maskc) __attribute__((always_inline)) {
-        constexpr bool M = decltype(maskc)::value;
+      for (int v = 0; v < 16; ++v) {
+        const int rl = wave * 32 + (v >> 2) * 8 + lh * 4 + (v & 3);
+        const float ndr = sm.nd[rl];
 #pragma unroll
-        for (int vv = 0; vv < 4; ++vv) {
-          const int rl = wave * 32 + st * 8 + lh * 4 + vv;
-          const float ndr = sm.nd[rl];
-#pragma unroll
-          for (int y = 0; y < 2; ++y) {
-            float e = fmaf(-2.0f, acc[y][st * 4 + vv], (y ? nq1 : nq0) + ndr);
-            if (M) {
-              const int64_t rg = row0 + rl;
-              const int qg = q0 + (y ? qc1 : qc0);
-              if (rg >= p.nd || (p.excl && rg == qg)) e = __uint_as_float(0x7f800000u);
-            }
-            est[vv][y] = e;
-            any |= e < (y ? tau1 : tau0);
+        for (int y = 0; y < 2; ++y) {
+          float e = fmaf(-2.0f, acc[y][v], (y ? nq1 : nq0) + ndr);
+          if (M) {
+            const int64_t rg = row0 + rl;
+            const int qg = q0 + (y ? qc1 : qc0);
+            if (rg >= p.nd || (p.excl && rg == qg)) e = __uint_as_float(0x7f800000u);
           }
-        }
-      };
-      if (masked) eval(std::integral_constant<bool, true>{});
-      else eval(std::integral_constant<bool, false>{});
-      if (__builtin_amdgcn_ballot_w64(any)) {
-        // One LDS atomic per lane and query reserves all of the lane's slots;
-        // the writes then need no round trip.
-        int n0 = 0, n1 = 0;
-#pragma unroll
-        for (int vv = 0; vv < 4; ++vv) {
-          n0 += est[vv][0] < tau0 ? 1 : 0;
-          n1 += est[vv][1] < tau1 ? 1 : 0;
-        }
-        int i0 = n0 ? atomicAdd(&sm.cnt[qc0], n0) : 0;
-        int i1 = n1 ? atomicAdd(&sm.cnt[qc1], n1) : 0;
-        if (i0 + n0 > KN_QC - 32 || i1 + n1 > KN_QC - 32) sm.flag = stamp;
-#pragma unroll
-        for (int vv = 0; vv < 4; ++vv) {
-          const uint32_t row = (uint32_t)(row0 + wave * 32 + st * 8 + lh * 4 + vv);
-          if (est[vv][0] < tau0) sm.Qu[qc0 * KN_QC + i0++] = knn_key(est[vv][0], row);
-          if (est[vv][1] < tau1) sm.Qu[qc1 * KN_QC + i1++] = knn_key(est[vv][1], row);
+          est[v][y] = e;
         }
       }
-      __syncthreads();
-      // The flag holds the stamp of the last sub-step that asked for a merge.
-      // Stamps increase, so a thread that is still reading it after others
-      // went on to the next sub-step (possible only when no merge is due)
-      // sees a later stamp, not its own: every thread takes the same branch.
-      if (sm.flag == stamp) {
+    };
+    if (masked) eval(std::integral_constant<bool, true>{});
+    else eval(std::integral_constant<bool, false>{});
+    auto row_of = [&](int v) { return (uint32_t)(row0 + wave * 32 + (v >> 2) * 8 + lh * 4 + (v & 3)); };
+
+    // One reservation per lane and query for the whole tile.  A tile fits
+    // when every query's committed entries plus its reservations stay within
+    // the queue; stamps increase, so every thread reads the flags alike (a
+    // thread can only move on to set later stamps after a barrier that the
+    // others reach after reading them).
+    const int stampT = (t - t0) * 8 + 1;
+    const int rb = t & 1;
+    int n0 = 0, n1 = 0;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      n0 += est[v][0] < tau0 ? 1 : 0;
+      n1 += est[v][1] < tau1 ? 1 : 0;
+    }
+    int b0 = 0, b1 = 0;
+    const int c0 = sm.cnt[qc0], c1 = sm.cnt[qc1];
+    if (n0) b0 = atomicAdd(&sm.res[rb][qc0], n0);
+    if (n1) b1 = atomicAdd(&sm.res[rb][qc1], n1);
+    const int e0 = c0 + b0 + n0, e1 = c1 + b1 + n1;
+    if ((n0 && e0 > KN_QC) || (n1 && e1 > KN_QC)) sm.flag = stampT;
+    else if ((n0 && e0 > KN_QC - 32) || (n1 && e1 > KN_QC - 32)) sm.flag2 = stampT;
+    __syncthreads();
+    if (sm.flag != stampT) {
+      // fits: write the reserved entries
+      if (n0 | n1) {
+        int i0 = c0 + b0, i1 = c1 + b1;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          if (est[v][0] < tau0) sm.Qu[qc0 * KN_QC + i0++] = knn_key(est[v][0], row_of(v));
+          if (est[v][1] < tau1) sm.Qu[qc1 * KN_QC + i1++] = knn_key(est[v][1], row_of(v));
+        }
+      }
+      if (sm.flag2 == stampT) {
+        // more than half full somewhere: merge every queue
+        __syncthreads();
         if (tid < KN_Q) {
+          sm.cnt[tid] += sm.res[rb][tid];
+          sm.res[rb][tid] = 0;
           const uint64_t last = knn_merge_one(sm, tid);
-          const unsigned lb = (unsigned)(last >> 32);   // +inf bits while the list is not full
+          const unsigned lb = (unsigned)(last >> 32);
           const unsigned old = atomicMin(&p.tau_g[q0 + tid], lb);
           sm.tau[tid] = knn_unord(min(old, lb));
         }
         __syncthreads();
         tau0 = sm.tau[qc0];
         tau1 = sm.tau[qc1];
+      }
+    } else {
+      // Some query would overflow: drop the reservations, merge the
+      // committed entries, then take the tile in four sub-steps of at most 32
+      // candidates per query, each followed by a merge check.
+      if (tid < KN_Q) {
+        sm.res[rb][tid] = 0;
+        const uint64_t last = knn_merge_one(sm, tid);
+        const unsigned lb = (unsigned)(last >> 32);
+        const unsigned old = atomicMin(&p.tau_g[q0 + tid], lb);
+        sm.tau[tid] = knn_unord(min(old, lb));
+      }
+      __syncthreads();
+      tau0 = sm.tau[qc0];
+      tau1 = sm.tau[qc1];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int stamp = stampT + 1 + st;
+        bool any = false;
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv) any |= est[st * 4 + vv][0] < tau0 || est[st * 4 + vv][1] < tau1;
+        if (__builtin_amdgcn_ballot_w64(any)) {
+          int m0 = 0, m1 = 0;
+#pragma unroll
+          for (int vv = 0; vv < 4; ++vv) {
+            m0 += est[st * 4 + vv][0] < tau0 ? 1 : 0;
+            m1 += est[st * 4 + vv][1] < tau1 ? 1 : 0;
+          }
+          int i0 = m0 ? atomicAdd(&sm.cnt[qc0], m0) : 0;
+          int i1 = m1 ? atomicAdd(&sm.cnt[qc1], m1) : 0;
+          if (i0 + m0 > KN_QC - 32 || i1 + m1 > KN_QC - 32) sm.flag = stamp;
+#pragma unroll
+          for (int vv = 0; vv < 4; ++vv) {
+            const int v = st * 4 + vv;
+            if (est[v][0] < tau0) sm.Qu[qc0 * KN_QC + i0++] = knn_key(est[v][0], row_of(v));
+            if (est[v][1] < tau1) sm.Qu[qc1 * KN_QC + i1++] = knn_key(est[v][1], row_of(v));
+          }
+        }
+        __syncthreads();
+        if (sm.flag == stamp) {
+          if (tid < KN_Q) {
+            const uint64_t last = knn_merge_one(sm, tid);
+            const unsigned lb = (unsigned)(last >> 32);
+            const unsigned old = atomicMin(&p.tau_g[q0 + tid], lb);
+            sm.tau[tid] = knn_unord(min(old, lb));
+          }
+          __syncthreads();
+          tau0 = sm.tau[qc0];
+          tau1 = sm.tau[qc1];
+        }
       }
     }
     const int gn = (t + 1 - t0) * p.nch;
@@ -337,8 +404,12 @@ __global__ __launch_bounds__(256, 2) void k_knn_screen(KnnScreenArgs p) {
     }
   }
 
-  // Queued entries that never triggered a merge.
+  // Queued entries that never triggered a merge (the last tile's writes
+  // complete at the barrier).
+  __syncthreads();
   if (tid < KN_Q) {
+    sm.cnt[tid] += sm.res[(t1 - 1) & 1][tid];
+    sm.res[(t1 - 1) & 1][tid] = 0;
     const uint64_t last = knn_merge_one(sm, tid);
     atomicMin(&p.tau_g[q0 + tid], (unsigned)(last >> 32));
   }
