@@ -10,6 +10,8 @@
 #include <string>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "../../include/adagio.h"
 #include "common.h"
 #include "kernels.h"
@@ -61,7 +63,8 @@ struct Workspace {
   DevBuf rpQ, rpY, rpG, rpV, rpLam;
   DevBuf skpart, skG, skK, sklam, skV, skfeat, mlp_pb, mlp_X, mlp_f, mlp_hb, mlp_grad, mlp_loss;
   DevBuf knQ, knD, knNq64, knNd64, knNq32, knNd32, knMax, knKeys, knFb, knCnt, knTau;
-  DevBuf lam1, Vt1, colmap, colminmax, colkeep;
+  DevBuf lam1, Vt1, colmap, colminmax, colkeep, xc64, pi64c, covL;
+  rocblas_handle blas = nullptr;  // plain FP64 GEMMs (covariance, embeddings)
   bool checked = false;
 };
 
@@ -102,6 +105,32 @@ static Workspace& workspace() {
   return ws;
 }
 
+// rocBLAS handle of the workspace's device on stream st: deterministic
+// (no atomics), host scalars.
+static rocblas_handle blas_on(Workspace& ws, hipStream_t st) {
+  auto chk = [](rocblas_status e, const char* what) {
+    if (e != rocblas_status_success) {
+      set_err("rocBLAS %s failed (status %lld)", what, (long long)e);
+      throw Fail{ADAGIO_E_HIP};
+    }
+  };
+  if (!ws.blas) {
+    chk(rocblas_create_handle(&ws.blas), "create_handle");
+    chk(rocblas_set_atomics_mode(ws.blas, rocblas_atomics_not_allowed), "set_atomics_mode");
+    chk(rocblas_set_pointer_mode(ws.blas, rocblas_pointer_mode_host), "set_pointer_mode");
+  }
+  chk(rocblas_set_stream(ws.blas, st), "set_stream");
+  return ws.blas;
+}
+#define BLASCHK(expr)                                                            \
+  do {                                                                           \
+    rocblas_status b_ = (expr);                                                  \
+    if (b_ != rocblas_status_success) {                                          \
+      set_err("rocBLAS call failed (" #expr ", status %lld)", "", (long long)b_); \
+      throw Fail{ADAGIO_E_HIP};                                                  \
+    }                                                                            \
+  } while (0)
+
 // --------------------------------------------------------------- timing
 struct EvPair {
   hipEvent_t a = nullptr, b = nullptr;
@@ -129,6 +158,7 @@ struct Points {
   int64_t n = 0, d = 0, n_pad = 0, ldx = 0;
   int64_t dx = 0;            // columns of the screens' copies (non-constant columns of X)
   const int* colmap = nullptr;  // those columns, ascending (device)
+  mutable double* xc64 = nullptr;  // FP64 centred copy of those columns (n x dx), on first use
   double* mu = nullptr;
   float* Xc = nullptr;
   double* nx = nullptr;
@@ -272,11 +302,11 @@ static int jacobi_eig(Workspace& ws, double* A, int m, int64_t d, double* lam, d
   return sweep;
 }
 
-// C = sum_i (x_i - mu)(x_i - mu)^T into ws.A0 (m x m, zero padding; m = d
-// rounded up to a multiple of two Jacobi blocks); with `compact`, the
-// covariance of the non-constant coordinates p.colmap[0, p.dx) only.
-static double* covariance(Workspace& ws, const Points& p, int m, hipStream_t st, bool compact = false) {
-  const int64_t d = compact ? p.dx : p.d;
+// C = sum_i (x_i - mu)(x_i - mu)^T over all d coordinates into ws.A0 (m x m,
+// zero padding; m = d rounded up to a multiple of two Jacobi blocks), by the
+// library's own FP64 MFMA kernel (the randomized PCA's input).
+static double* covariance(Workspace& ws, const Points& p, int m, hipStream_t st) {
+  const int64_t d = p.d;
   // split-K over points so that the grid fills the GPU
   const int64_t NT = (d + 63) / 64;
   const int64_t ntiles = NT * (NT + 1) / 2;
@@ -286,9 +316,56 @@ static double* covariance(Workspace& ws, const Points& p, int m, hipStream_t st,
   if (nsplit < 1) nsplit = 1;
   double* part = ensure<double>(ws.covpart, (size_t)(nsplit * d * d));
   double* A = ensure<double>(ws.A0, (size_t)m * m);
-  if (compact) HIPCHK(launch_covariance(p.X, p.n, p.d, p.mu, part, nsplit, A, m, st, p.colmap, p.dx));
-  else HIPCHK(launch_covariance(p.X, p.n, d, p.mu, part, nsplit, A, m, st));
+  HIPCHK(launch_covariance(p.X, p.n, d, p.mu, part, nsplit, A, m, st));
   return A;
+}
+
+// FP64 centred copy of the non-constant columns (n x dx, row-major), made
+// on first use in a call.
+static const double* centred64(Workspace& ws, const Points& p, hipStream_t st) {
+  if (!p.xc64) {
+    p.xc64 = ensure<double>(ws.xc64, (size_t)(p.n * std::max<int64_t>(p.dx, 1)));
+    if (p.dx > 0) HIPCHK(launch_center64(p.X, p.n, p.d, p.mu, p.colmap, p.dx, p.xc64, st));
+  }
+  return p.xc64;
+}
+
+// The covariance of the non-constant coordinates, C = Xc^T Xc over the FP64
+// centred rows (a plain product: rocBLAS), in full into ws.A0 (m_pad x m_pad,
+// zero padding).
+static double* covariance64(Workspace& ws, const Points& p, int m_pad, hipStream_t st) {
+  const int64_t D = p.dx;
+  double* A = ensure<double>(ws.A0, (size_t)m_pad * m_pad);
+  double* L = ensure<double>(ws.covL, (size_t)std::max<int64_t>(D * D, 1));
+  const double* xc = centred64(ws, p, st);
+  const double one = 1.0, zero = 0.0;
+  // row-major n x D = column-major D x n (ld D): C = A A^T as a GEMM (the
+  // library's SYRK is far slower for a small D and long k); the lower
+  // triangle is then mirrored, so C is exactly symmetric
+  BLASCHK(rocblas_dgemm(blas_on(ws, st), rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)D,
+                        (rocblas_int)D, (rocblas_int)p.n, &one, xc, (rocblas_int)D, xc, (rocblas_int)D, &zero, L,
+                        (rocblas_int)D));
+  HIPCHK(launch_sym_full(L, D, A, m_pad, st));
+  return A;
+}
+
+// Y64 = (X - mu) Pi^T in FP64 over the non-constant columns (constant ones
+// centre to exact zeros), a plain GEMM (rocBLAS) of the FP64 centred rows and
+// the FP64 values of the FP32 map.  Y64: n x r row-major.
+static void embed64(Workspace& ws, const Points& p, const float* Pi, int64_t r, double* Y64, hipStream_t st) {
+  if (p.dx == 0) {
+    HIPCHK(hipMemsetAsync(Y64, 0, sizeof(double) * (size_t)(p.n * r), st));
+    return;
+  }
+  const double* xc = centred64(ws, p, st);
+  double* P64 = ensure<double>(ws.pi64c, (size_t)(r * p.dx));
+  HIPCHK(launch_cols64(Pi, r, p.d, p.colmap, p.dx, P64, st));
+  const double one = 1.0, zero = 0.0;
+  // column-major: Y^T (r x n, ld r) = op(P64) (r x dx) * Xc^T (dx x n, ld dx),
+  // P64 stored as column-major dx x r (ld dx), transposed
+  BLASCHK(rocblas_dgemm(blas_on(ws, st), rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)r,
+                        (rocblas_int)p.n, (rocblas_int)p.dx, &one, P64, (rocblas_int)p.dx, xc, (rocblas_int)p.dx,
+                        &zero, Y64, (rocblas_int)r));
 }
 
 // Randomized PCA (the paper's Sec. 4.5 variant, after Halko, Martinsson &
@@ -337,9 +414,9 @@ static Axes principal_axes(Workspace& ws, const Points& p, hipStream_t st, doubl
   Axes ax;
   ax.lam = lam_out ? lam_out : ensure<double>(ws.lam, (size_t)d);
   ax.Vt = Vt_out ? Vt_out : ensure<double>(ws.Vt, (size_t)(d * d));
-  if (p.dx == d || !p.colmap) {
+  if (p.dx == d) {
     const int m = (int)round_up(d, 2 * bj_block());
-    double* A = covariance(ws, p, m, st);
+    double* A = covariance64(ws, p, m, st);
     ax.sweeps = jacobi_eig(ws, A, m, d, ax.lam, ax.Vt, st);
     return ax;
   }
@@ -352,7 +429,7 @@ static Axes principal_axes(Workspace& ws, const Points& p, hipStream_t st, doubl
   ax.sweeps = 0;
   if (d1 > 0) {
     const int m1 = (int)round_up(d1, 2 * bj_block());
-    double* A1 = covariance(ws, p, m1, st, true);
+    double* A1 = covariance64(ws, p, m1, st);
     ax.sweeps = jacobi_eig(ws, A1, m1, d1, lam1, Vt1, st);
   }
   const int* idx = p.colmap;
@@ -499,7 +576,7 @@ static Images images_of_map(Workspace& ws, const Points& p, const float* Pi, int
   im.r = r;
   im.ldy = round_up(r, kChunk);
   double* Y64 = ensure<double>(ws.Y64, (size_t)(p.n * r));
-  HIPCHK(launch_embed_f64(p.X, p.n, p.d, p.mu, Pi, r, Y64, st, p.dx < p.d ? p.colmap : nullptr, p.dx));
+  embed64(ws, p, Pi, r, Y64, st);
   im.Yc = ensure<float>(ws.Yc, (size_t)(p.n_pad * im.ldy));
   double* ny = ensure<double>(ws.ny, (size_t)p.n_pad);
   HIPCHK(launch_center<double>(Y64, p.n, r, r, nullptr, im.Yc, im.ldy, p.n_pad, ny, st));
@@ -1237,12 +1314,16 @@ int adagio_release(void) {
                       &ws.skpart, &ws.skG, &ws.skK, &ws.sklam, &ws.skV, &ws.skfeat, &ws.mlp_pb, &ws.mlp_X,
                       &ws.mlp_f, &ws.mlp_hb, &ws.mlp_grad, &ws.mlp_loss, &ws.knQ, &ws.knD, &ws.knNq64,
                       &ws.knNd64, &ws.knNq32, &ws.knNd32, &ws.knMax, &ws.knKeys, &ws.knFb, &ws.knCnt, &ws.knTau,
-                      &ws.lam1, &ws.Vt1, &ws.colmap,
+                      &ws.lam1, &ws.Vt1, &ws.colmap, &ws.xc64, &ws.pi64c, &ws.covL,
                       &ws.colminmax, &ws.colkeep};
     for (DevBuf* b : bufs) {
       if (b->p) HIPCHK(hipFree(b->p));
       b->p = nullptr;
       b->cap = 0;
+    }
+    if (ws.blas) {
+      (void)rocblas_destroy_handle(ws.blas);
+      ws.blas = nullptr;
     }
   });
 }

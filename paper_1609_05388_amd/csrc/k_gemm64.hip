@@ -30,22 +30,6 @@ struct CentredColsB {     // B(k, n) = X[k][n] - mu[n]  (k = point, n = feature)
     return (c < d && k < n) ? (double)X[k * d + c] - mu[c] : 0.0;
   }
 };
-struct CentredColsMap {   // A(m, k) = X[k][c] - mu[c], c = cmap[m], m < kc (mapped features only)
-  const float* X; const double* mu; int64_t n, d; const int* cmap; int64_t kc;
-  __device__ double operator()(int64_t m, int64_t k) const {
-    if (m >= kc || k >= n) return 0.0;
-    const int64_t c = cmap[m];
-    return (double)X[k * d + c] - mu[c];
-  }
-};
-struct CentredColsBMap {  // B(k, c') = X[k][cmap[c']] - mu[cmap[c']], c' < kc
-  const float* X; const double* mu; int64_t n, d; const int* cmap; int64_t kc;
-  __device__ double operator()(int64_t k, int64_t c2) const {
-    if (c2 >= kc || k >= n) return 0.0;
-    const int64_t c = cmap[c2];
-    return (double)X[k * d + c] - mu[c];
-  }
-};
 struct CentredRows {      // A(m, k) = X[m][k] - mu[k]  (m = point, k = feature); mu may be NULL
   const float* X; const double* mu; int64_t n, d;
   __device__ double operator()(int64_t m, int64_t k) const {
@@ -58,20 +42,6 @@ struct RowsF32T {         // B(k, n) = P[n][k] for an FP32 rows x cols matrix
   const float* P; int64_t rows, cols;
   __device__ double operator()(int64_t k, int64_t n) const {
     return (n < rows && k < cols) ? (double)P[n * cols + k] : 0.0;
-  }
-};
-struct CentredRowsMap {   // A(m, k) = X[m][c] - mu[c], c = cmap[k], k < kc (only the mapped columns)
-  const float* X; const double* mu; int64_t n, d; const int* cmap; int64_t kc;
-  __device__ double operator()(int64_t m, int64_t k) const {
-    if (m >= n || k >= kc) return 0.0;
-    const int64_t c = cmap[k];
-    return (double)X[m * d + c] - mu[c];
-  }
-};
-struct RowsF32TMap {      // B(k, n) = P[n][cmap[k]], k < kc
-  const float* P; int64_t rows, cols; const int* cmap; int64_t kc;
-  __device__ double operator()(int64_t k, int64_t n) const {
-    return (n < rows && k < kc) ? (double)P[n * cols + cmap[k]] : 0.0;
   }
 };
 struct RowsF64 {          // A(m, k) = M[m][k]
@@ -250,44 +220,18 @@ __global__ void k_cov_reduce(const double* __restrict__ part, int nsplit, int64_
 
 // ---------------------------------------------------------------- launchers
 hipError_t launch_covariance(const float* X, int64_t n, int64_t d, const double* mu, double* part,
-                             int nsplit, double* C, int64_t m_pad, hipStream_t st, const int* cmap, int64_t kc) {
-  const int64_t D = cmap ? kc : d;   // features in the result
-  const int64_t NT = (D + GT - 1) / GT;
+                             int nsplit, double* C, int64_t m_pad, hipStream_t st) {
+  const int64_t NT = (d + GT - 1) / GT;
   const int64_t ntiles = NT * (NT + 1) / 2;
   int64_t kps = round_up((n + nsplit - 1) / nsplit, GK);
-  StoreF64 S{part, D, D, D, D * D};
+  CentredCols A{X, mu, n, d};
+  CentredColsB B{X, mu, n, d};
+  StoreF64 S{part, d, d, d, d * d};
   dim3 g((unsigned)ntiles, (unsigned)nsplit);
-  if (cmap) {
-    CentredColsMap A{X, mu, n, d, cmap, kc};
-    CentredColsBMap B{X, mu, n, d, cmap, kc};
-    k_gemm64<CentredColsMap, CentredColsBMap, StoreF64, false, false, true><<<g, 256, 0, st>>>(A, B, S, D, D, n, kps, NT);
-  } else {
-    CentredCols A{X, mu, n, d};
-    CentredColsB B{X, mu, n, d};
-    k_gemm64<CentredCols, CentredColsB, StoreF64, false, false, true><<<g, 256, 0, st>>>(A, B, S, D, D, n, kps, NT);
-  }
+  k_gemm64<CentredCols, CentredColsB, StoreF64, false, false, true><<<g, 256, 0, st>>>(A, B, S, d, d, n, kps, NT);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_cov_reduce<<<(unsigned)((m_pad * m_pad + 255) / 256), 256, 0, st>>>(part, nsplit, D, m_pad, C);
-  return hipGetLastError();
-}
-
-// Y64[i][c] = sum_l (X[i][l] - mu[l]) Pi[c][l]   (n x r, FP64, ld = r)
-hipError_t launch_embed_f64(const float* X, int64_t n, int64_t d, const double* mu, const float* Pi,
-                            int64_t r, double* Y, hipStream_t st, const int* cmap, int64_t kc) {
-  const int64_t tm = (n + GT - 1) / GT, tn = (r + GT - 1) / GT;
-  StoreF64 S{Y, n, r, r, 0};
-  if (cmap) {
-    // constant coordinates centre to exact zeros: the sum runs over the others
-    CentredRowsMap A{X, mu, n, d, cmap, kc};
-    RowsF32TMap B{Pi, r, d, cmap, kc};
-    k_gemm64<CentredRowsMap, RowsF32TMap, StoreF64, true, true, false><<<(unsigned)(tm * tn), 256, 0, st>>>(
-        A, B, S, n, r, kc, round_up(std::max<int64_t>(kc, 1), GK), tn);
-  } else {
-    CentredRows A{X, mu, n, d};
-    RowsF32T B{Pi, r, d};
-    k_gemm64<CentredRows, RowsF32T, StoreF64, true, true, false><<<(unsigned)(tm * tn), 256, 0, st>>>(A, B, S, n, r, d, round_up(d, GK), tn);
-  }
+  k_cov_reduce<<<(unsigned)((m_pad * m_pad + 255) / 256), 256, 0, st>>>(part, nsplit, d, m_pad, C);
   return hipGetLastError();
 }
 

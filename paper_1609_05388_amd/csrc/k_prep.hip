@@ -155,7 +155,52 @@ __global__ void k_row_terms(const double* __restrict__ norm2, double c_self,
   terms[i] = make_float2(f32_down(N - slack), f32_up(N + slack));
 }
 
+// FP64 centred copy of the listed columns: dst[i][c] = src[i][k] - mu[k],
+// k = colmap[c] (FP64 difference of the FP32 value), n x m row-major.
+__global__ void k_center64(const float* __restrict__ src, int64_t n, int64_t lds, const double* __restrict__ mu,
+                           const int* __restrict__ colmap, int64_t m, double* __restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * m) return;
+  const int64_t i = e / m, c = e % m;
+  const int64_t k = colmap[c];
+  dst[e] = (double)src[i * lds + k] - mu[k];
+}
+
+// FP64 copy of the listed columns of an FP32 r x d map (exact): r x m.
+__global__ void k_cols64(const float* __restrict__ P, int64_t r, int64_t d, const int* __restrict__ colmap, int64_t m,
+                         double* __restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= r * m) return;
+  const int64_t j = e / m, c = e % m;
+  dst[e] = (double)P[j * d + colmap[c]];
+}
+
+// The m x m symmetric matrix whose lower triangle is stored column-major in
+// L (ld = m), written in full into A (ld = m_pad, zero outside m x m).
+__global__ void k_sym_full(const double* __restrict__ L, int64_t m, double* __restrict__ A, int64_t m_pad) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= m_pad * m_pad) return;
+  const int64_t i = e / m_pad, j = e % m_pad;
+  double v = 0.0;
+  if (i < m && j < m) v = i >= j ? L[j * m + i] : L[i * m + j];
+  A[e] = v;
+}
+
 // ---------------------------------------------------------------- launchers
+hipError_t launch_center64(const float* src, int64_t n, int64_t lds, const double* mu, const int* colmap, int64_t m,
+                           double* dst, hipStream_t st) {
+  k_center64<<<(unsigned)((n * m + 255) / 256), 256, 0, st>>>(src, n, lds, mu, colmap, m, dst);
+  return hipGetLastError();
+}
+hipError_t launch_cols64(const float* P, int64_t r, int64_t d, const int* colmap, int64_t m, double* dst,
+                         hipStream_t st) {
+  k_cols64<<<(unsigned)((r * m + 255) / 256), 256, 0, st>>>(P, r, d, colmap, m, dst);
+  return hipGetLastError();
+}
+hipError_t launch_sym_full(const double* L, int64_t m, double* A, int64_t m_pad, hipStream_t st) {
+  k_sym_full<<<(unsigned)((m_pad * m_pad + 255) / 256), 256, 0, st>>>(L, m, A, m_pad);
+  return hipGetLastError();
+}
 template <typename T>
 hipError_t launch_mean(const T* A, int64_t n, int64_t m, int64_t ld, double* partial,
                        int64_t nchunks, int64_t rows_per_chunk, double* mu, int* nonfinite,

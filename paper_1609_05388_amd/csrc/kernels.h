@@ -12,6 +12,14 @@ hipError_t launch_mean(const T* A, int64_t n, int64_t m, int64_t ld, double* par
                        int64_t rows_per_chunk, double* mu, int* nonfinite, hipStream_t st,
                        double* pmin = nullptr, double* pmax = nullptr, int* keep = nullptr);
 hipError_t launch_compact_keep(const int* keep, int m, int* idx, int* k_out, hipStream_t st);
+// FP64 centred copy of the columns colmap[0, m) (n x m); FP64 copy of the
+// columns colmap[0, m) of an FP32 r x d matrix (r x m); full symmetric
+// m_pad x m_pad matrix from a column-major lower triangle (m x m).
+hipError_t launch_center64(const float* src, int64_t n, int64_t lds, const double* mu, const int* colmap, int64_t m,
+                           double* dst, hipStream_t st);
+hipError_t launch_cols64(const float* P, int64_t r, int64_t d, const int* colmap, int64_t m, double* dst,
+                         hipStream_t st);
+hipError_t launch_sym_full(const double* L, int64_t m, double* A, int64_t m_pad, hipStream_t st);
 // colmap (m entries, may be null): source column of each destination column.
 template <typename T>
 hipError_t launch_center(const T* src, int64_t n, int64_t m, int64_t lds, const double* mu, float* dst,
@@ -20,12 +28,8 @@ hipError_t launch_row_terms(const double* norm2, double c_self, const double* no
                             int64_t n_pad, float2* terms, hipStream_t st);
 
 // k_gemm64.hip
-// cmap (kc entries, may be null): the covariance of these features only (kc x kc).
 hipError_t launch_covariance(const float* X, int64_t n, int64_t d, const double* mu, double* part, int nsplit,
-                             double* C, int64_t m_pad, hipStream_t st, const int* cmap = nullptr, int64_t kc = 0);
-// cmap (kc entries, may be null): only these columns of X and Pi enter the sum.
-hipError_t launch_embed_f64(const float* X, int64_t n, int64_t d, const double* mu, const float* Pi, int64_t r,
-                            double* Y, hipStream_t st, const int* cmap = nullptr, int64_t kc = 0);
+                             double* C, int64_t m_pad, hipStream_t st);
 hipError_t launch_embed_f32(const float* X, int64_t n, int64_t d, const float* Pi, int64_t r, float* Y,
                             hipStream_t st);
 hipError_t launch_proj_T(const double* S, int64_t k, int64_t d, const double* Vt, int64_t s, double* T,
