@@ -63,7 +63,7 @@ struct Workspace {
   DevBuf rpQ, rpY, rpG, rpV, rpLam;
   DevBuf skpart, skG, skK, sklam, skV, skfeat, mlp_pb, mlp_X, mlp_f, mlp_hb, mlp_grad, mlp_loss;
   DevBuf knQ, knD, knNq64, knNd64, knNq32, knNd32, knMax, knKeys, knFb, knCnt, knTau;
-  DevBuf lam1, Vt1, colmap, colminmax, colkeep, xc64, pi64c, covL;
+  DevBuf lam1, Vt1, colmap, colminmax, colkeep, xc64, pi64c;
   rocblas_handle blas = nullptr;  // plain FP64 GEMMs (covariance, embeddings)
   bool checked = false;
 };
@@ -322,30 +322,42 @@ static double* covariance(Workspace& ws, const Points& p, int m, hipStream_t st)
 
 // FP64 centred copy of the non-constant columns (n x dx, row-major), made
 // on first use in a call.
+// Rows are zero-padded to a multiple of 4096 (zero rows add nothing to the
+// products; the covariance splits the rows into equal blocks).
+static int64_t rows64(const Points& p) { return round_up(p.n, 4096); }
 static const double* centred64(Workspace& ws, const Points& p, hipStream_t st) {
   if (!p.xc64) {
-    p.xc64 = ensure<double>(ws.xc64, (size_t)(p.n * std::max<int64_t>(p.dx, 1)));
+    const int64_t D = std::max<int64_t>(p.dx, 1), np = rows64(p);
+    p.xc64 = ensure<double>(ws.xc64, (size_t)(np * D));
     if (p.dx > 0) HIPCHK(launch_center64(p.X, p.n, p.d, p.mu, p.colmap, p.dx, p.xc64, st));
+    if (np > p.n) HIPCHK(hipMemsetAsync(p.xc64 + p.n * D, 0, sizeof(double) * (size_t)((np - p.n) * D), st));
   }
   return p.xc64;
 }
 
 // The covariance of the non-constant coordinates, C = Xc^T Xc over the FP64
-// centred rows (a plain product: rocBLAS), in full into ws.A0 (m_pad x m_pad,
+// centred rows (plain products: rocBLAS), in full into ws.A0 (m_pad x m_pad,
 // zero padding).
 static double* covariance64(Workspace& ws, const Points& p, int m_pad, hipStream_t st) {
   const int64_t D = p.dx;
   double* A = ensure<double>(ws.A0, (size_t)m_pad * m_pad);
-  double* L = ensure<double>(ws.covL, (size_t)std::max<int64_t>(D * D, 1));
   const double* xc = centred64(ws, p, st);
+  // Split-K over row blocks so that a small D still fills the GPU: each block
+  // of kc rows gives a partial A_b A_b^T (one batched library GEMM; row-major
+  // rows x D is column-major D x rows), and k_cov_reduce adds the partials in
+  // block order and mirrors one triangle, so C is exactly symmetric.
+  const int64_t np = rows64(p);
+  const int64_t tiles = ((D + 127) / 128) * ((D + 127) / 128);
+  int64_t nsplit = std::max<int64_t>(1, std::min<int64_t>(np / 4096 * 8, (512 + tiles - 1) / tiles));
+  while (np % nsplit) --nsplit;
+  const int64_t kc = np / nsplit;
+  double* part = ensure<double>(ws.covpart, (size_t)(nsplit * D * D));
   const double one = 1.0, zero = 0.0;
-  // row-major n x D = column-major D x n (ld D): C = A A^T as a GEMM (the
-  // library's SYRK is far slower for a small D and long k); the lower
-  // triangle is then mirrored, so C is exactly symmetric
-  BLASCHK(rocblas_dgemm(blas_on(ws, st), rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)D,
-                        (rocblas_int)D, (rocblas_int)p.n, &one, xc, (rocblas_int)D, xc, (rocblas_int)D, &zero, L,
-                        (rocblas_int)D));
-  HIPCHK(launch_sym_full(L, D, A, m_pad, st));
+  BLASCHK(rocblas_dgemm_strided_batched(blas_on(ws, st), rocblas_operation_none, rocblas_operation_transpose,
+                                        (rocblas_int)D, (rocblas_int)D, (rocblas_int)kc, &one, xc, (rocblas_int)D,
+                                        (rocblas_stride)(kc * D), xc, (rocblas_int)D, (rocblas_stride)(kc * D), &zero,
+                                        part, (rocblas_int)D, (rocblas_stride)(D * D), (rocblas_int)nsplit));
+  HIPCHK(launch_cov_reduce(part, (int)nsplit, D, m_pad, A, st));
   return A;
 }
 
@@ -1314,7 +1326,7 @@ int adagio_release(void) {
                       &ws.skpart, &ws.skG, &ws.skK, &ws.sklam, &ws.skV, &ws.skfeat, &ws.mlp_pb, &ws.mlp_X,
                       &ws.mlp_f, &ws.mlp_hb, &ws.mlp_grad, &ws.mlp_loss, &ws.knQ, &ws.knD, &ws.knNq64,
                       &ws.knNd64, &ws.knNq32, &ws.knNd32, &ws.knMax, &ws.knKeys, &ws.knFb, &ws.knCnt, &ws.knTau,
-                      &ws.lam1, &ws.Vt1, &ws.colmap, &ws.xc64, &ws.pi64c, &ws.covL,
+                      &ws.lam1, &ws.Vt1, &ws.colmap, &ws.xc64, &ws.pi64c,
                       &ws.colminmax, &ws.colkeep};
     for (DevBuf* b : bufs) {
       if (b->p) HIPCHK(hipFree(b->p));

@@ -219,6 +219,11 @@ __global__ void k_cov_reduce(const double* __restrict__ part, int nsplit, int64_
 }
 
 // ---------------------------------------------------------------- launchers
+hipError_t launch_cov_reduce(const double* part, int nsplit, int64_t d, int64_t m_pad, double* C, hipStream_t st) {
+  k_cov_reduce<<<(unsigned)((m_pad * m_pad + 255) / 256), 256, 0, st>>>(part, nsplit, d, m_pad, C);
+  return hipGetLastError();
+}
+
 hipError_t launch_covariance(const float* X, int64_t n, int64_t d, const double* mu, double* part,
                              int nsplit, double* C, int64_t m_pad, hipStream_t st) {
   const int64_t NT = (d + GT - 1) / GT;

@@ -175,17 +175,6 @@ __global__ void k_cols64(const float* __restrict__ P, int64_t r, int64_t d, cons
   dst[e] = (double)P[j * d + colmap[c]];
 }
 
-// The m x m symmetric matrix whose lower triangle is stored column-major in
-// L (ld = m), written in full into A (ld = m_pad, zero outside m x m).
-__global__ void k_sym_full(const double* __restrict__ L, int64_t m, double* __restrict__ A, int64_t m_pad) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= m_pad * m_pad) return;
-  const int64_t i = e / m_pad, j = e % m_pad;
-  double v = 0.0;
-  if (i < m && j < m) v = i >= j ? L[j * m + i] : L[i * m + j];
-  A[e] = v;
-}
-
 // ---------------------------------------------------------------- launchers
 hipError_t launch_center64(const float* src, int64_t n, int64_t lds, const double* mu, const int* colmap, int64_t m,
                            double* dst, hipStream_t st) {
@@ -195,10 +184,6 @@ hipError_t launch_center64(const float* src, int64_t n, int64_t lds, const doubl
 hipError_t launch_cols64(const float* P, int64_t r, int64_t d, const int* colmap, int64_t m, double* dst,
                          hipStream_t st) {
   k_cols64<<<(unsigned)((r * m + 255) / 256), 256, 0, st>>>(P, r, d, colmap, m, dst);
-  return hipGetLastError();
-}
-hipError_t launch_sym_full(const double* L, int64_t m, double* A, int64_t m_pad, hipStream_t st) {
-  k_sym_full<<<(unsigned)((m_pad * m_pad + 255) / 256), 256, 0, st>>>(L, m, A, m_pad);
   return hipGetLastError();
 }
 template <typename T>

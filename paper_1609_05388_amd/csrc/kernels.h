@@ -13,13 +13,11 @@ hipError_t launch_mean(const T* A, int64_t n, int64_t m, int64_t ld, double* par
                        double* pmin = nullptr, double* pmax = nullptr, int* keep = nullptr);
 hipError_t launch_compact_keep(const int* keep, int m, int* idx, int* k_out, hipStream_t st);
 // FP64 centred copy of the columns colmap[0, m) (n x m); FP64 copy of the
-// columns colmap[0, m) of an FP32 r x d matrix (r x m); full symmetric
-// m_pad x m_pad matrix from a column-major lower triangle (m x m).
+// columns colmap[0, m) of an FP32 r x d matrix (r x m).
 hipError_t launch_center64(const float* src, int64_t n, int64_t lds, const double* mu, const int* colmap, int64_t m,
                            double* dst, hipStream_t st);
 hipError_t launch_cols64(const float* P, int64_t r, int64_t d, const int* colmap, int64_t m, double* dst,
                          hipStream_t st);
-hipError_t launch_sym_full(const double* L, int64_t m, double* A, int64_t m_pad, hipStream_t st);
 // colmap (m entries, may be null): source column of each destination column.
 template <typename T>
 hipError_t launch_center(const T* src, int64_t n, int64_t m, int64_t lds, const double* mu, float* dst,
@@ -30,6 +28,9 @@ hipError_t launch_row_terms(const double* norm2, double c_self, const double* no
 // k_gemm64.hip
 hipError_t launch_covariance(const float* X, int64_t n, int64_t d, const double* mu, double* part, int nsplit,
                              double* C, int64_t m_pad, hipStream_t st);
+// C (m_pad x m_pad, zero padding) = the sum of nsplit d x d partial products
+// in split order, element (i, j) taken from partial entry [min][max].
+hipError_t launch_cov_reduce(const double* part, int nsplit, int64_t d, int64_t m_pad, double* C, hipStream_t st);
 hipError_t launch_embed_f32(const float* X, int64_t n, int64_t d, const float* Pi, int64_t r, float* Y,
                             hipStream_t st);
 hipError_t launch_proj_T(const double* S, int64_t k, int64_t d, const double* Vt, int64_t s, double* T,
