@@ -8,7 +8,9 @@ eps = 0.1, the input already resident in HBM.
 
 Printed on one line (JSON):
   value       certified pair evaluations per second over the whole fit
-              (n(n-1)/2 pairs per certificate x certificates / fit time)
+              (n(n-1)/2 pairs per certificate x certificates / fit time;
+              probes refuted by a witness pair evaluate a few thousand pairs
+              and are not counted)
   ms_per_step the fit time (the paper's headline quantity: time to an
               embedding whose max distortion is certified <= eps)
   roofline    the all-pairs screen kernel (FP32 MFMA): algorithmic flops
@@ -161,6 +163,21 @@ def screen_flops(npairs, d, r, gram):
     return npairs * 2.0 * (r if gram == 2 else d + r)
 
 
+def split_probes(st):
+    """A fit's logged probes as (screened, rigorous, refuted) lists of
+    (r, delta, screen_ms, gram): the first n_screened probes that ran a
+    screen were FP8 screens; gram 3 marks a probe refuted by a witness pair."""
+    fp8, rig, ref = [], [], []
+    for p in zip(st["probe_r"], st["probe_delta"], st["probe_screen_ms"], st["probe_gram"]):
+        if p[3] == 3:
+            ref.append(p)
+        elif len(fp8) < st["n_screened"]:
+            fp8.append(p)
+        else:
+            rig.append(p)
+    return fp8, rig, ref
+
+
 def timed_fits(adagio, torch, Xd, eps, seed, steps, **kw):
     adagio.fit(Xd, eps, seed, **kw)             # buffers and first-call set-up
     torch.cuda.synchronize()
@@ -176,15 +193,16 @@ def fp8_form(adagio, gen, torch, Xd, eps, steps, plain_s, plain, npairs, d):
     fs, outs = timed_fits(adagio, torch, Xd, eps, gen.JL_SEED, steps, screen="fp8")
     o = outs[-1]
     st = o["stats"]
-    scr = list(zip(st["probe_r"], st["probe_screen_ms"], st["probe_gram"]))[:st["n_screened"]]
-    fl = sum(screen_flops(npairs, d, r, g) for r, _, g in scr)
-    ms = sum(t for _, t, _ in scr)
+    scr, _, ref = split_probes(st)
+    fl = sum(screen_flops(npairs, d, r, g) for r, _, _, g in scr)
+    ms = sum(t for _, _, t, _ in scr)
     return {"fit_ms": fs * 1e3, "speedup_vs_plain": plain_s / fs, "r": o["r"],
             "max_distortion": o["cert"]["max_distortion"], "certified": o["cert"]["certified"],
             "abs_err_vs_plain_fp64_certificate": abs(o["cert"]["max_distortion"] - plain["cert"]["max_distortion"]),
             "same_map_as_plain": bool(o["r"] == plain["r"] and torch.equal(o["Pi"], plain["Pi"])),
             "screens": st["n_screened"], "certificates": st["n_certificates"] - st["n_screened"],
-            "screen_probes": [[r, dl] for r, dl in zip(st["probe_r"], st["probe_delta"])][:st["n_screened"]],
+            "refuted_probes": st["n_refuted"],
+            "screen_probes": [[r, dl] for r, dl, _, _ in scr],
             "screen_avg_launch_ms": ms / max(1, len(scr)),
             "screen_fp8_mfma_tflops": fl / max(ms, 1e-9) / 1e9,
             "screen_fp8_mfma_frac": fl / max(ms, 1e-9) / 1e9 / PEAK_FP8_MFMA_TFLOPS}
@@ -231,8 +249,7 @@ def large_form(adagio, gen, torch, eps):
     n, d = Xd.shape
     npairs = n * (n - 1) // 2
     scr = list(zip(st["probe_r"], st["probe_delta"], st["probe_screen_ms"], st["probe_gram"]))
-    fp8 = scr[:st["n_screened"]]
-    rig = scr[st["n_screened"]:]
+    fp8, rig, ref = split_probes(st)
     fl = sum(screen_flops(npairs, dx, r, g) for r, _, _, g in fp8)
     ms = sum(t for _, _, t, _ in fp8)
     bfl = sum(screen_flops(npairs, dx, r, g) for r, _, _, g in rig)
@@ -253,7 +270,7 @@ def large_form(adagio, gen, torch, eps):
         "generate_s": gen_s, "fit_ms": fit_ms, "t_pca_ms": st["t_pca_ms"], "eig_sweeps": st["eig_sweeps"],
         "r": o["r"], "max_distortion": o["cert"]["max_distortion"], "certified": o["cert"]["certified"],
         "argmax": [o["cert"]["i"], o["cert"]["j"]],
-        "fp8_screens": len(fp8), "bf16x3_certificates": len(rig),
+        "fp8_screens": len(fp8), "bf16x3_certificates": len(rig), "refuted_probes": len(ref),
         "fp8_screen_avg_ms": ms / max(1, len(fp8)),
         "fp8_screen_tflops": fl / max(ms, 1e-9) / 1e9,
         "fp8_screen_frac_of_fp8_peak": fl / max(ms, 1e-9) / 1e9 / PEAK_FP8_MFMA_TFLOPS,
@@ -264,7 +281,7 @@ def large_form(adagio, gen, torch, eps):
                                          "screen_tflops": npairs * 2.0 * (dx + o["r"]) / pst["t_screen_ms"] / 1e9,
                                          "max_distortion": plain["max_distortion"],
                                          "certified": plain["certified"]},
-        "probes": [[r, dl] for r, dl, _, _ in scr],
+        "probes": [[r, dl, "refuted" if g == 3 else "screened"] for r, dl, _, g in scr],
         "with_randomized_pca": rand,
     }
 
@@ -399,9 +416,18 @@ def main():
     npairs = n * (n - 1) // 2
     ncert = st["n_certificates"]
     value = npairs * ncert / fit_s
-    log("fit %.1f ms/step: r=%d, %d certificates, delta=%.6f, pca %.1f ms, search %.1f ms, screen %.1f ms"
-        % (fit_s * 1e3, last["r"], ncert, last["cert"]["max_distortion"], st["t_pca_ms"], st["t_search_ms"],
-           st["t_screen_ms"]))
+    log("fit %.1f ms/step: r=%d, %d certificates, %d probes refuted, delta=%.6f, pca %.1f ms, search %.1f ms, "
+        "screen %.1f ms" % (fit_s * 1e3, last["r"], ncert, st["n_refuted"], last["cert"]["max_distortion"],
+                            st["t_pca_ms"], st["t_search_ms"], st["t_screen_ms"]))
+
+    # the same fit certifying every probe in full (no witness pool)
+    nw_s, nw_outs = timed_fits(adagio, torch, Xd, args.eps, gen.JL_SEED, args.steps, witness=False)
+    nw = nw_outs[-1]
+    without_witness = {"fit_ms": nw_s * 1e3, "certificates": nw["stats"]["n_certificates"],
+                       "same_result": bool(nw["r"] == last["r"] and torch.equal(nw["Pi"], last["Pi"])
+                                           and nw["cert"] == last["cert"]),
+                       "value": npairs * nw["stats"]["n_certificates"] / nw_s}
+    log("without witnesses: fit %.1f ms, %d certificates" % (nw_s * 1e3, without_witness["certificates"]))
 
     # roofline of the screen kernel over the launches of the timed steps.  The
     # first certificate of a fit computes (and caches) the point Gram: 2(d' + r)
@@ -411,6 +437,8 @@ def main():
     for o in outs:
         s = o["stats"]
         for r, t, g in zip(s["probe_r"], s["probe_screen_ms"], s["probe_gram"]):
+            if g == 3:          # refuted by a witness pair: no screen
+                continue
             k = "cached" if g == 2 else "full"
             kinds[k][0] += npairs * 2.0 * ((dx + r) if k == "full" else r)
             kinds[k][1] += t
@@ -442,6 +470,8 @@ def main():
         bflops, bms, bn = 0.0, 0.0, 0
         for o in bouts:
             for r, t, g in zip(o["stats"]["probe_r"], o["stats"]["probe_screen_ms"], o["stats"]["probe_gram"]):
+                if g == 3:
+                    continue
                 bflops += screen_flops(npairs, dx, r, g)
                 bms += t
                 bn += 1
@@ -556,7 +586,10 @@ def main():
                 "t_search_ms": st["t_search_ms"], "t_screen_ms": st["t_screen_ms"],
                 "t_rescore_ms": st["t_rescore_ms"], "eig_sweeps": st["eig_sweeps"],
                 "rescored_pairs": st["n_rescored"], "flagged_tiles": st["n_flagged_tiles"],
-                "probes": [[r, dl] for r, dl in zip(st["probe_r"], st["probe_delta"])]},
+                "refuted_probes": st["n_refuted"], "cloud_pairs_certified_per_s": npairs / fit_s,
+                "probes": [[r, dl, "refuted" if g == 3 else "certified"]
+                           for r, dl, g in zip(st["probe_r"], st["probe_delta"], st["probe_gram"])],
+                "without_witness_pool": without_witness},
         "other_eps": extra,
         "mnist_like_67_constant_coordinates": border67,
         "tradeoff_min_r": tradeoff,

@@ -108,7 +108,12 @@ typedef struct adagio_stats {
     double probe_delta[48];  /* its exact max distortion                          */
     double probe_screen_ms[48]; /* its all-pairs screen kernel time (device events) */
     int32_t probe_gram[48];  /* its point Gram: 0 computed, 1 computed and stored in the
-                                fit's point-Gram cache, 2 loaded from it (image Gram only) */
+                                fit's point-Gram cache, 2 loaded from it (image Gram only),
+                                3 none: the probe was refuted by a witness pair (no screen;
+                                probe_delta is that pair's exact distortion, a lower bound
+                                on the probe's maximum) */
+    int32_t n_refuted;       /* fit: probes refuted by a witness pair (not counted in
+                                n_certificates)                                   */
 } adagio_stats_t;
 
 typedef struct adagio_opts {
@@ -120,6 +125,8 @@ typedef struct adagio_opts {
     adagio_stats_t* stats;   /* optional host output                              */
     int32_t pca;             /* ADAGIO_PCA_*; default EXACT (fit only)            */
     int32_t pca_iters;       /* randomized PCA: power iterations q (>= 0)         */
+    int32_t no_witness;      /* fit: 1 = certify every probe in full (no refutation by
+                                witness pairs); default 0                         */
 } adagio_opts_t;
 
 /* a1-a3.  Principal axes of the centred cloud (Sec. 2 PCA paragraph, eq. 4;
@@ -212,7 +219,18 @@ int adagio_certify_map(const float* X, int64_t n, int64_t d, const float* Pi, in
  * opts->pca = ADAGIO_PCA_RANDOMIZED takes the principal directions from
  * adagio_pca_randomized with ell = s + 10 for the largest s the search has
  * needed so far (recomputed when a probe needs more; ell = d gives the exact
- * eigenbasis) and q = opts->pca_iters.  Synchronises `stream`. */
+ * eigenbasis) and q = opts->pca_iters.
+ * Refutation by witness pairs: a single pair whose exact eq. (2) value
+ * exceeds eps shows that the maximum of eq. (3) exceeds eps, so a probe can
+ * fail without an all-pairs screen.  After each certificate of a search, the
+ * record pairs (the pair of largest and of smallest ratio bound) of its 256
+ * tiles of largest bound join a pool of at most 16384 pairs; every later probe
+ * first re-evaluates the pool in FP64 (the certificate's own re-evaluation,
+ * on the probe's FP64 images) and fails when a pair exceeds eps + 1e-9 (a
+ * margin far above the re-evaluation's rounding error, so that a refuted
+ * probe is one its certificate would fail too).  Passing probes are certified in full as before, so r, Pi
+ * and the certificate do not depend on the pool; opts->no_witness = 1 turns
+ * it off.  Synchronises `stream`. */
 int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed,
                const adagio_opts_t* opts, float* Pi_out, int32_t* r_out, int32_t* s_out,
                adagio_cert_t* cert_out, void* stream);

@@ -45,7 +45,7 @@ class Stats(ctypes.Structure):
                 ("n_rescored", ctypes.c_int64), ("n_probes", ctypes.c_int32),
                 ("n_screened", ctypes.c_int32), ("probe_r", ctypes.c_int32 * 48),
                 ("probe_delta", ctypes.c_double * 48), ("probe_screen_ms", ctypes.c_double * 48),
-                ("probe_gram", ctypes.c_int32 * 48)]
+                ("probe_gram", ctypes.c_int32 * 48), ("n_refuted", ctypes.c_int32)]
 
     def to_dict(self):
         out = {}
@@ -71,7 +71,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("screen", ctypes.c_int32), ("search", ctypes.c_int32),
                 ("max_candidates", ctypes.c_int32), ("family", ctypes.c_int32),
                 ("predictor", ctypes.c_void_p), ("stats", ctypes.POINTER(Stats)),
-                ("pca", ctypes.c_int32), ("pca_iters", ctypes.c_int32)]
+                ("pca", ctypes.c_int32), ("pca_iters", ctypes.c_int32), ("no_witness", ctypes.c_int32)]
 
 
 _lib = None
@@ -144,8 +144,9 @@ def _dev(t, dtype, name):
 
 
 def _opts(screen="f32", search="bisect", max_candidates=0, predictor=None, stats=None, family="adagio",
-          pca="exact", pca_iters=2):
+          pca="exact", pca_iters=2, witness=True):
     o = Opts()
+    o.no_witness = 0 if witness else 1
     o.screen = SCREEN[screen]
     o.search = SEARCH[search]
     o.family = FAMILY[family]
@@ -252,15 +253,16 @@ def certify_map(X, Pi, screen="f32", max_candidates=0, with_stats=False):
 
 
 def fit(X, eps, seed, screen="f32", search="bisect", predictor=None, max_candidates=0, family="adagio",
-        pca="exact", pca_iters=2):
+        pca="exact", pca_iters=2, witness=True):
     """Returns dict(Pi=(r x d tensor), r, s, k, cert, stats).  family: "adagio"
     (Algorithm 1), "pca" or "jl" (Table 2's single-component maps); pca:
-    "exact" or "randomized" (Sec. 4.5's variant, pca_iters power iterations)."""
+    "exact" or "randomized" (Sec. 4.5's variant, pca_iters power iterations);
+    witness=False certifies every probe in full."""
     lib = load()
     n, d = X.shape
     Pi_buf = torch.empty((d, d), dtype=torch.float32, device=X.device)
     st = Stats()
-    o = _opts(screen, search, max_candidates, predictor, st, family, pca, pca_iters)
+    o = _opts(screen, search, max_candidates, predictor, st, family, pca, pca_iters, witness)
     r = ctypes.c_int32()
     s = ctypes.c_int32()
     c = Cert()

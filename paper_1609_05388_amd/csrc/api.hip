@@ -64,6 +64,7 @@ struct Workspace {
   DevBuf skpart, skG, skK, sklam, skV, skfeat, mlp_pb, mlp_X, mlp_f, mlp_hb, mlp_grad, mlp_loss;
   DevBuf knQ, knD, knNq64, knNd64, knNq32, knNd32, knMax, knKeys, knFb, knCnt, knTau;
   DevBuf lam1, Vt1, colmap, colminmax, colkeep, xc64, pi64c;
+  DevBuf pool, pooln, wvals, wparts, wcd;
   rocblas_handle blas = nullptr;  // plain FP64 GEMMs (covariance, embeddings)
   bool checked = false;
 };
@@ -582,13 +583,18 @@ static void image_copies(Workspace& ws, const Points& p, Images& im, const doubl
   }
 }
 
-// Images of the linear map Pi in FP64, centred: Y64 = (X - mu) Pi^T.
-static Images images_of_map(Workspace& ws, const Points& p, const float* Pi, int64_t r, hipStream_t st) {
+// FP64 images of the linear map Pi, centred: Y64 = (X - mu) Pi^T (n x r).
+static double* map_images64(Workspace& ws, const Points& p, const float* Pi, int64_t r, hipStream_t st) {
+  double* Y64 = ensure<double>(ws.Y64, (size_t)(p.n * r));
+  embed64(ws, p, Pi, r, Y64, st);
+  return Y64;
+}
+
+// The screens' inputs from the FP64 images of a map.
+static Images images_from64(Workspace& ws, const Points& p, double* Y64, int64_t r, hipStream_t st) {
   Images im;
   im.r = r;
   im.ldy = round_up(r, kChunk);
-  double* Y64 = ensure<double>(ws.Y64, (size_t)(p.n * r));
-  embed64(ws, p, Pi, r, Y64, st);
   im.Yc = ensure<float>(ws.Yc, (size_t)(p.n_pad * im.ldy));
   double* ny = ensure<double>(ws.ny, (size_t)p.n_pad);
   HIPCHK(launch_center<double>(Y64, p.n, r, r, nullptr, im.Yc, im.ldy, p.n_pad, ny, st));
@@ -601,6 +607,10 @@ static Images images_of_map(Workspace& ws, const Points& p, const float* Pi, int
   image_copies(ws, p, im, ny, p.nx, c_emb, st);
   im.Y64 = Y64;
   return im;
+}
+
+static Images images_of_map(Workspace& ws, const Points& p, const float* Pi, int64_t r, hipStream_t st) {
+  return images_from64(ws, p, map_images64(ws, p, Pi, r, st), r, st);
 }
 
 // Given images (FP32), centred by their own mean.
@@ -625,6 +635,7 @@ struct CertTimes {
   int64_t flagged = 0, rescored = 0;
   int screened = 0;   // FP8 screens among the calls
   int nprobe = 0;
+  int refuted = 0;    // probes refuted by a witness pair
   int32_t probe_r[48];
   double probe_delta[48], probe_ms[48];
   int32_t probe_gram[48];
@@ -636,6 +647,17 @@ static void log_probe(CertTimes& tm, int64_t r, const adagio_cert_t& c, double s
     tm.probe_delta[tm.nprobe] = c.max_distortion;
     tm.probe_ms[tm.nprobe] = screen_ms;
     tm.probe_gram[tm.nprobe] = gmode;
+    ++tm.nprobe;
+  }
+}
+
+static void log_refuted(CertTimes& tm, int64_t r, double w) {
+  ++tm.refuted;
+  if (tm.nprobe < 48) {
+    tm.probe_r[tm.nprobe] = (int32_t)r;
+    tm.probe_delta[tm.nprobe] = w;
+    tm.probe_ms[tm.nprobe] = 0.0;
+    tm.probe_gram[tm.nprobe] = 3;
     ++tm.nprobe;
   }
 }
@@ -655,6 +677,7 @@ static void fill_stats(adagio_stats_t* s, const CertTimes& tm, int ncert, double
     s->probe_screen_ms[k] = tm.probe_ms[k];
     s->probe_gram[k] = tm.probe_gram[k];
   }
+  s->n_refuted = tm.refuted;
   s->t_total_ms = total_ms;
 }
 
@@ -817,6 +840,53 @@ static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& i
     log_probe(*times, im.r, c, sm, gcache ? gmode : 0);
   }
   return c;
+}
+
+// Witness pool of a fit's search (eq. (3) is a maximum: one pair above eps
+// fails a map).  Each certificate adds the record pairs of its kPoolTiles
+// tiles of largest bound; a probe re-evaluates the pool exactly before its
+// screen.
+static const uint32_t kPoolCap = 16384;
+static const uint32_t kPoolTiles = 256;
+static const double kWitnessMargin = 1e-9;
+
+static void pool_reset(Workspace& ws, hipStream_t st) {
+  uint32_t* pn = ensure<uint32_t>(ws.pooln, 2);
+  HIPCHK(hipMemsetAsync(pn, 0, 2 * sizeof(uint32_t), st));
+}
+
+// After a certificate of points p: its tile records are still in ws.recs.
+static void pool_add(Workspace& ws, const Points& p, hipStream_t st) {
+  const int64_t NT = p.n_pad / kTile;
+  const int64_t ntiles = NT * (NT + 1) / 2;
+  int2* pool = ensure<int2>(ws.pool, kPoolCap);
+  uint32_t* pn = static_cast<uint32_t*>(ws.pooln.p);          // [0] pool size, [1] selected tiles
+  uint32_t* hist = ensure<uint32_t>(ws.hist, 65536);
+  uint32_t* kthr = ensure<uint32_t>(ws.kthr, 1);
+  uint32_t* list = ensure<uint32_t>(ws.list, (size_t)ntiles);
+  const TileRec* recs = static_cast<const TileRec*>(ws.recs.p);
+  HIPCHK(hipMemsetAsync(hist, 0, 65536 * sizeof(uint32_t), st));
+  HIPCHK(hipMemsetAsync(pn + 1, 0, sizeof(uint32_t), st));
+  HIPCHK(launch_topk_tiles(recs, ntiles, kPoolTiles, 4 * kPoolTiles, hist, kthr, list, pn + 1, st));
+  HIPCHK(launch_pool_gather(recs, list, pn + 1, 4 * kPoolTiles, pool, pn, kPoolCap, st));
+}
+
+// The largest exact distortion over the pool for the FP64 images Y64 of a
+// probe's map (i < 0: empty pool or only coincident pairs).
+static PairVal pool_witness(Workspace& ws, const Points& p, const double* Y64, int64_t r, hipStream_t st) {
+  const int2* pool = static_cast<const int2*>(ws.pool.p);
+  const uint32_t* pn = static_cast<const uint32_t*>(ws.pooln.p);
+  PairVal* vals = ensure<PairVal>(ws.wvals, kPoolCap);
+  const int vp = 32;
+  PairVal* parts = ensure<PairVal>(ws.wparts, 2 * vp);
+  CertDev* wcd = ensure<CertDev>(ws.wcd, 1);
+  HIPCHK(launch_rescore<double>(p.X, p.d, Y64, r, pool, pn, nullptr, kPoolCap, vals, 256, st));
+  HIPCHK(launch_best_reset(wcd, st));
+  HIPCHK(launch_top2(vals, pn, kPoolCap, parts, vp, wcd, st));
+  PairVal w;
+  HIPCHK(hipMemcpyAsync(&w, &wcd->best, sizeof(PairVal), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return w;
 }
 
 static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -991,6 +1061,8 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     ARGCHK(family == ADAGIO_MAP_ADAGIO || family == ADAGIO_MAP_PCA || family == ADAGIO_MAP_JL, "unknown map family");
     ARGCHK(family == ADAGIO_MAP_ADAGIO || search == ADAGIO_SEARCH_BISECT,
            "the learned search is for Algorithm 1's maps only");
+    const int no_witness = opts ? opts->no_witness : 0;
+    ARGCHK(no_witness == 0 || no_witness == 1, "no_witness must be 0 or 1");
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = as_stream(stream);
     Workspace& ws = workspace();
@@ -1040,10 +1112,22 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     // The probes of the search's own screen share the point-Gram cache.
     float* gcache = nullptr;
     bool gready = false;
+    // Witness pool: probes after the first certificate are first checked
+    // against the worst pairs of the earlier certificates.
+    bool pool_live = false;
+    if (!no_witness) pool_reset(ws, st);
     auto probe = [&](int64_t r, int scr) {
       need_axes(r);
       build_family_map(ws, family, ax.Vt, d, r, seed, Pi, st);
-      Images im = images_of_map(ws, p, Pi, r, st);
+      double* Y64 = map_images64(ws, p, Pi, r, st);
+      if (pool_live) {
+        const PairVal w = pool_witness(ws, p, Y64, r, st);
+        if (w.i >= 0 && w.v > eps + kWitnessMargin) {
+          log_refuted(tm, r, w.v);
+          return false;
+        }
+      }
+      Images im = images_from64(ws, p, Y64, r, st);
       int gmode = 0;
       if (scr == screen) {
         if (!gready) gcache = gram_cache(ws, p);
@@ -1052,6 +1136,10 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
       adagio_cert_t c = certificate(ws, p, im, cap0, st, &tm, scr, gcache, gmode);
       if (gmode == 1) gready = true;
       ++ncert;
+      if (!no_witness) {
+        pool_add(ws, p, st);
+        pool_live = true;
+      }
       if (scr == ADAGIO_SCREEN_FP8) return c.max_distortion <= eps;
       const bool pass = c.certified ? c.max_distortion <= eps : c.bound_rest <= eps;
       if (pass) {
@@ -1327,7 +1415,7 @@ int adagio_release(void) {
                       &ws.mlp_f, &ws.mlp_hb, &ws.mlp_grad, &ws.mlp_loss, &ws.knQ, &ws.knD, &ws.knNq64,
                       &ws.knNd64, &ws.knNq32, &ws.knNd32, &ws.knMax, &ws.knKeys, &ws.knFb, &ws.knCnt, &ws.knTau,
                       &ws.lam1, &ws.Vt1, &ws.colmap, &ws.xc64, &ws.pi64c,
-                      &ws.colminmax, &ws.colkeep};
+                      &ws.colminmax, &ws.colkeep, &ws.pool, &ws.pooln, &ws.wvals, &ws.wparts, &ws.wcd};
     for (DevBuf* b : bufs) {
       if (b->p) HIPCHK(hipFree(b->p));
       b->p = nullptr;

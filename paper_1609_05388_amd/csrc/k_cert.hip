@@ -218,6 +218,35 @@ __global__ void k_top2_final(const PairVal* __restrict__ part, int nparts, CertD
   cd->second = b2;
 }
 
+// Witness pool of a search: the record pairs (largest and smallest ratio
+// bound) of selected tiles, appended at pool_n (slots past cap are dropped;
+// pool_n keeps counting and readers clamp it to cap).
+__global__ __launch_bounds__(256) void k_pool_gather(const TileRec* __restrict__ recs,
+                                                     const uint32_t* __restrict__ list,
+                                                     const uint32_t* __restrict__ nsel, uint32_t kmax,
+                                                     int2* __restrict__ pool, uint32_t* __restrict__ pool_n,
+                                                     uint32_t cap) {
+  uint32_t m = *nsel;
+  if (m > kmax) m = kmax;
+  for (uint32_t t = blockIdx.x * 256 + threadIdx.x; t < m; t += gridDim.x * 256) {
+    const TileRec r = recs[list[t]];
+    if (r.ihi >= 0) {
+      const uint32_t pos = atomicAdd(pool_n, 1u);
+      if (pos < cap) pool[pos] = make_int2(r.ihi, r.jhi);
+    }
+    if (r.ilo >= 0 && !(r.ilo == r.ihi && r.jlo == r.jhi)) {
+      const uint32_t pos = atomicAdd(pool_n, 1u);
+      if (pos < cap) pool[pos] = make_int2(r.ilo, r.jlo);
+    }
+  }
+}
+
+__global__ void k_best_reset(CertDev* __restrict__ cd) {
+  if (threadIdx.x != 0) return;
+  cd->best = pv_none();
+  cd->second = pv_none();
+}
+
 // ---------------------------------------------------------------- launchers
 hipError_t launch_seeds(const TileRec* recs, int64_t ntiles, TileRec* part, int nparts, int2* seeds, CertDev* cd,
                         hipStream_t st) {
@@ -255,6 +284,17 @@ hipError_t launch_top2(const PairVal* vals, const uint32_t* count_ptr, uint32_t 
                        CertDev* cd, hipStream_t st) {
   k_top2_partial<<<(unsigned)nparts, 256, 0, st>>>(vals, count_ptr, cap, part);
   k_top2_final<<<1, 64, 0, st>>>(part, nparts, cd);
+  return hipGetLastError();
+}
+
+hipError_t launch_pool_gather(const TileRec* recs, const uint32_t* list, const uint32_t* nsel, uint32_t kmax,
+                              int2* pool, uint32_t* pool_n, uint32_t cap, hipStream_t st) {
+  k_pool_gather<<<(unsigned)((kmax + 255) / 256), 256, 0, st>>>(recs, list, nsel, kmax, pool, pool_n, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_best_reset(CertDev* cd, hipStream_t st) {
+  k_best_reset<<<1, 64, 0, st>>>(cd);
   return hipGetLastError();
 }
 

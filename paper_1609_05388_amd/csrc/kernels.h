@@ -90,6 +90,12 @@ hipError_t launch_thresholds(const PairVal* seedv, CertDev* cd, hipStream_t st);
 hipError_t launch_flag_tiles(const TileRec* recs, int64_t ntiles, CertDev* cd, uint32_t* list, hipStream_t st);
 hipError_t launch_top2(const PairVal* vals, const uint32_t* count_ptr, uint32_t cap, PairVal* part, int nparts,
                        CertDev* cd, hipStream_t st);
+// Appends the record pairs of the first min(*nsel, kmax) tiles of list to a
+// witness pool (pool_n counts, slots past cap are dropped).
+hipError_t launch_pool_gather(const TileRec* recs, const uint32_t* list, const uint32_t* nsel, uint32_t kmax,
+                              int2* pool, uint32_t* pool_n, uint32_t cap, hipStream_t st);
+// cd->best = cd->second = no pair.
+hipError_t launch_best_reset(CertDev* cd, hipStream_t st);
 
 // k_gemm64.hip (general FP64 products of the randomized PCA)
 hipError_t launch_gemm_nt(const double* A, int64_t M, int64_t K, int64_t lda, const double* B, int64_t N,
