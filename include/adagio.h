@@ -225,8 +225,8 @@ int adagio_certify_map(const float* X, int64_t n, int64_t d, const float* Pi, in
  * fail without an all-pairs screen.  After each certificate of a search, the
  * record pairs (the pair of largest and of smallest ratio bound) of its 256
  * tiles of largest bound join a pool of at most 16384 pairs; every later probe
- * first re-evaluates the pool in FP64 (the certificate's own re-evaluation,
- * on the probe's FP64 images) and fails when a pair exceeds eps + 1e-9 (a
+ * first evaluates the pool in FP64 by direct differences Pi (x_i - x_j), before
+ * it embeds the cloud, and fails when a pair exceeds eps + 1e-9 (a
  * margin far above the re-evaluation's rounding error, so that a refuted
  * probe is one its certificate would fail too).  Passing probes are certified in full as before, so r, Pi
  * and the certificate do not depend on the pool; opts->no_witness = 1 turns

@@ -64,7 +64,7 @@ struct Workspace {
   DevBuf skpart, skG, skK, sklam, skV, skfeat, mlp_pb, mlp_X, mlp_f, mlp_hb, mlp_grad, mlp_loss;
   DevBuf knQ, knD, knNq64, knNd64, knNq32, knNd32, knMax, knKeys, knFb, knCnt, knTau;
   DevBuf lam1, Vt1, colmap, colminmax, colkeep, xc64, pi64c;
-  DevBuf pool, pooln, wvals, wparts, wcd;
+  DevBuf pool, pooln, wvals, wparts, wcd, wV, wW;
   rocblas_handle blas = nullptr;  // plain FP64 GEMMs (covariance, embeddings)
   bool checked = false;
 };
@@ -583,18 +583,13 @@ static void image_copies(Workspace& ws, const Points& p, Images& im, const doubl
   }
 }
 
-// FP64 images of the linear map Pi, centred: Y64 = (X - mu) Pi^T (n x r).
-static double* map_images64(Workspace& ws, const Points& p, const float* Pi, int64_t r, hipStream_t st) {
-  double* Y64 = ensure<double>(ws.Y64, (size_t)(p.n * r));
-  embed64(ws, p, Pi, r, Y64, st);
-  return Y64;
-}
-
-// The screens' inputs from the FP64 images of a map.
-static Images images_from64(Workspace& ws, const Points& p, double* Y64, int64_t r, hipStream_t st) {
+// Images of the linear map Pi in FP64, centred: Y64 = (X - mu) Pi^T.
+static Images images_of_map(Workspace& ws, const Points& p, const float* Pi, int64_t r, hipStream_t st) {
   Images im;
   im.r = r;
   im.ldy = round_up(r, kChunk);
+  double* Y64 = ensure<double>(ws.Y64, (size_t)(p.n * r));
+  embed64(ws, p, Pi, r, Y64, st);
   im.Yc = ensure<float>(ws.Yc, (size_t)(p.n_pad * im.ldy));
   double* ny = ensure<double>(ws.ny, (size_t)p.n_pad);
   HIPCHK(launch_center<double>(Y64, p.n, r, r, nullptr, im.Yc, im.ldy, p.n_pad, ny, st));
@@ -607,10 +602,6 @@ static Images images_from64(Workspace& ws, const Points& p, double* Y64, int64_t
   image_copies(ws, p, im, ny, p.nx, c_emb, st);
   im.Y64 = Y64;
   return im;
-}
-
-static Images images_of_map(Workspace& ws, const Points& p, const float* Pi, int64_t r, hipStream_t st) {
-  return images_from64(ws, p, map_images64(ws, p, Pi, r, st), r, st);
 }
 
 // Given images (FP32), centred by their own mean.
@@ -844,8 +835,8 @@ static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& i
 
 // Witness pool of a fit's search (eq. (3) is a maximum: one pair above eps
 // fails a map).  Each certificate adds the record pairs of its kPoolTiles
-// tiles of largest bound; a probe re-evaluates the pool exactly before its
-// screen.
+// tiles of largest bound; a probe evaluates the pool exactly, by direct
+// differences, before it embeds the cloud and screens it.
 static const uint32_t kPoolCap = 16384;
 static const uint32_t kPoolTiles = 256;
 static const double kWitnessMargin = 1e-9;
@@ -855,8 +846,10 @@ static void pool_reset(Workspace& ws, hipStream_t st) {
   HIPCHK(hipMemsetAsync(pn, 0, 2 * sizeof(uint32_t), st));
 }
 
-// After a certificate of points p: its tile records are still in ws.recs.
-static void pool_add(Workspace& ws, const Points& p, hipStream_t st) {
+// After a certificate of points p (its tile records are still in ws.recs):
+// appends the pairs and recomputes their difference rows.  Returns the pool
+// size.
+static uint32_t pool_add(Workspace& ws, const Points& p, hipStream_t st) {
   const int64_t NT = p.n_pad / kTile;
   const int64_t ntiles = NT * (NT + 1) / 2;
   int2* pool = ensure<int2>(ws.pool, kPoolCap);
@@ -869,21 +862,43 @@ static void pool_add(Workspace& ws, const Points& p, hipStream_t st) {
   HIPCHK(hipMemsetAsync(pn + 1, 0, sizeof(uint32_t), st));
   HIPCHK(launch_topk_tiles(recs, ntiles, kPoolTiles, 4 * kPoolTiles, hist, kthr, list, pn + 1, st));
   HIPCHK(launch_pool_gather(recs, list, pn + 1, 4 * kPoolTiles, pool, pn, kPoolCap, st));
+  uint32_t cnt = 0;
+  HIPCHK(hipMemcpyAsync(&cnt, pn, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  cnt = std::min(cnt, kPoolCap);
+  if (cnt > 0 && p.dx > 0) {
+    double* V = ensure<double>(ws.wV, (size_t)cnt * (size_t)p.dx);
+    HIPCHK(launch_pair_diffs(p.X, p.d, p.colmap, p.dx, pool, cnt, V, st));
+  }
+  return cnt;
 }
 
-// The largest exact distortion over the pool for the FP64 images Y64 of a
-// probe's map (i < 0: empty pool or only coincident pairs).
-static PairVal pool_witness(Workspace& ws, const Points& p, const double* Y64, int64_t r, hipStream_t st) {
+// The largest eq. (2) value over the pool's npool pairs under the map Pi
+// (r x d FP32), by direct differences: W = V Pi^T in FP64 (a plain library
+// GEMM over the non-constant coordinates).  i < 0: no pair with x_i != x_j.
+static PairVal pool_witness(Workspace& ws, const Points& p, const float* Pi, int64_t r, uint32_t npool,
+                            hipStream_t st) {
+  PairVal w;
+  w.v = -1.0; w.i = w.j = -1; w.side = 0; w.pad = 0;
+  if (npool == 0 || p.dx == 0) return w;
   const int2* pool = static_cast<const int2*>(ws.pool.p);
   const uint32_t* pn = static_cast<const uint32_t*>(ws.pooln.p);
+  const double* V = static_cast<const double*>(ws.wV.p);
+  double* W = ensure<double>(ws.wW, (size_t)npool * (size_t)r);
+  double* P64 = ensure<double>(ws.pi64c, (size_t)(r * p.dx));
   PairVal* vals = ensure<PairVal>(ws.wvals, kPoolCap);
   const int vp = 32;
   PairVal* parts = ensure<PairVal>(ws.wparts, 2 * vp);
   CertDev* wcd = ensure<CertDev>(ws.wcd, 1);
-  HIPCHK(launch_rescore<double>(p.X, p.d, Y64, r, pool, pn, nullptr, kPoolCap, vals, 256, st));
+  HIPCHK(launch_cols64(Pi, r, p.d, p.colmap, p.dx, P64, st));
+  const double one = 1.0, zero = 0.0;
+  // column-major: W^T (r x npool, ld r) = op(P64) (r x dx) * V^T (dx x npool, ld dx)
+  BLASCHK(rocblas_dgemm(blas_on(ws, st), rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)r,
+                        (rocblas_int)npool, (rocblas_int)p.dx, &one, P64, (rocblas_int)p.dx, V, (rocblas_int)p.dx,
+                        &zero, W, (rocblas_int)r));
+  HIPCHK(launch_pair_ratio(V, p.dx, W, r, pool, npool, vals, st));
   HIPCHK(launch_best_reset(wcd, st));
-  HIPCHK(launch_top2(vals, pn, kPoolCap, parts, vp, wcd, st));
-  PairVal w;
+  HIPCHK(launch_top2(vals, pn, npool, parts, vp, wcd, st));
   HIPCHK(hipMemcpyAsync(&w, &wcd->best, sizeof(PairVal), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   return w;
@@ -1114,20 +1129,19 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     bool gready = false;
     // Witness pool: probes after the first certificate are first checked
     // against the worst pairs of the earlier certificates.
-    bool pool_live = false;
+    uint32_t npool = 0;
     if (!no_witness) pool_reset(ws, st);
     auto probe = [&](int64_t r, int scr) {
       need_axes(r);
       build_family_map(ws, family, ax.Vt, d, r, seed, Pi, st);
-      double* Y64 = map_images64(ws, p, Pi, r, st);
-      if (pool_live) {
-        const PairVal w = pool_witness(ws, p, Y64, r, st);
+      if (npool > 0) {
+        const PairVal w = pool_witness(ws, p, Pi, r, npool, st);
         if (w.i >= 0 && w.v > eps + kWitnessMargin) {
           log_refuted(tm, r, w.v);
           return false;
         }
       }
-      Images im = images_from64(ws, p, Y64, r, st);
+      Images im = images_of_map(ws, p, Pi, r, st);
       int gmode = 0;
       if (scr == screen) {
         if (!gready) gcache = gram_cache(ws, p);
@@ -1136,10 +1150,7 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
       adagio_cert_t c = certificate(ws, p, im, cap0, st, &tm, scr, gcache, gmode);
       if (gmode == 1) gready = true;
       ++ncert;
-      if (!no_witness) {
-        pool_add(ws, p, st);
-        pool_live = true;
-      }
+      if (!no_witness) npool = pool_add(ws, p, st);
       if (scr == ADAGIO_SCREEN_FP8) return c.max_distortion <= eps;
       const bool pass = c.certified ? c.max_distortion <= eps : c.bound_rest <= eps;
       if (pass) {
@@ -1415,7 +1426,8 @@ int adagio_release(void) {
                       &ws.mlp_f, &ws.mlp_hb, &ws.mlp_grad, &ws.mlp_loss, &ws.knQ, &ws.knD, &ws.knNq64,
                       &ws.knNd64, &ws.knNq32, &ws.knNd32, &ws.knMax, &ws.knKeys, &ws.knFb, &ws.knCnt, &ws.knTau,
                       &ws.lam1, &ws.Vt1, &ws.colmap, &ws.xc64, &ws.pi64c,
-                      &ws.colminmax, &ws.colkeep, &ws.pool, &ws.pooln, &ws.wvals, &ws.wparts, &ws.wcd};
+                      &ws.colminmax, &ws.colkeep, &ws.pool, &ws.pooln, &ws.wvals, &ws.wparts, &ws.wcd,
+                      &ws.wV, &ws.wW};
     for (DevBuf* b : bufs) {
       if (b->p) HIPCHK(hipFree(b->p));
       b->p = nullptr;

@@ -241,6 +241,54 @@ __global__ __launch_bounds__(256) void k_pool_gather(const TileRec* __restrict__
   }
 }
 
+// Witness pairs by direct differences (the oracle's definition of eq. (2)):
+// V (npairs x m, row-major) = x_i - x_j in FP64 over the m non-constant
+// coordinates colmap[0..m) (constant ones differ by exactly zero).
+__global__ void k_pair_diffs(const float* __restrict__ X, int64_t d, const int* __restrict__ colmap, int64_t m,
+                             const int2* __restrict__ pairs, int64_t npairs, double* __restrict__ V) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= npairs * m) return;
+  const int64_t k = e / m;
+  const int64_t col = colmap[e - k * m];
+  const int2 pr = pairs[k];
+  V[e] = (double)X[(int64_t)pr.x * d + col] - (double)X[(int64_t)pr.y * d + col];
+}
+
+// eq. (2) of each witness pair from its difference row v (length m) and its
+// image row W = Pi v (length r), one wave per pair; same encoding as
+// k_rescore.
+__global__ __launch_bounds__(256) void k_pair_ratio(const double* __restrict__ V, int64_t m,
+                                                    const double* __restrict__ W, int64_t r,
+                                                    const int2* __restrict__ pairs, int64_t npairs,
+                                                    PairVal* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= npairs) return;   // uniform per wave
+  double D2 = 0.0, E2 = 0.0;
+  for (int64_t l = lane; l < m; l += 64) {
+    const double t = V[w * m + l];
+    D2 += t * t;
+  }
+  for (int64_t l = lane; l < r; l += 64) {
+    const double t = W[w * r + l];
+    E2 += t * t;
+  }
+  D2 = wave_sum_d(D2);
+  E2 = wave_sum_d(E2);
+  if (lane == 0) {
+    const int2 pr = pairs[w];
+    PairVal pv;
+    pv.i = pr.x; pv.j = pr.y; pv.pad = 0;
+    if (D2 == 0.0) { pv.v = -1.0; pv.side = 0; }
+    else {
+      const double ratio = sqrt(E2) / sqrt(D2);
+      pv.v = fabs(ratio - 1.0);
+      pv.side = ratio > 1.0 ? 1 : (ratio < 1.0 ? -1 : 0);
+    }
+    out[w] = pv;
+  }
+}
+
 __global__ void k_best_reset(CertDev* __restrict__ cd) {
   if (threadIdx.x != 0) return;
   cd->best = pv_none();
@@ -290,6 +338,20 @@ hipError_t launch_top2(const PairVal* vals, const uint32_t* count_ptr, uint32_t 
 hipError_t launch_pool_gather(const TileRec* recs, const uint32_t* list, const uint32_t* nsel, uint32_t kmax,
                               int2* pool, uint32_t* pool_n, uint32_t cap, hipStream_t st) {
   k_pool_gather<<<(unsigned)((kmax + 255) / 256), 256, 0, st>>>(recs, list, nsel, kmax, pool, pool_n, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_diffs(const float* X, int64_t d, const int* colmap, int64_t m, const int2* pairs,
+                             int64_t npairs, double* V, hipStream_t st) {
+  if (npairs * m == 0) return hipSuccess;
+  k_pair_diffs<<<(unsigned)((npairs * m + 255) / 256), 256, 0, st>>>(X, d, colmap, m, pairs, npairs, V);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_ratio(const double* V, int64_t m, const double* W, int64_t r, const int2* pairs,
+                             int64_t npairs, PairVal* out, hipStream_t st) {
+  if (npairs == 0) return hipSuccess;
+  k_pair_ratio<<<(unsigned)((npairs + 3) / 4), 256, 0, st>>>(V, m, W, r, pairs, npairs, out);
   return hipGetLastError();
 }
 

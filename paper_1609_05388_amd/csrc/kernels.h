@@ -94,6 +94,13 @@ hipError_t launch_top2(const PairVal* vals, const uint32_t* count_ptr, uint32_t 
 // witness pool (pool_n counts, slots past cap are dropped).
 hipError_t launch_pool_gather(const TileRec* recs, const uint32_t* list, const uint32_t* nsel, uint32_t kmax,
                               int2* pool, uint32_t* pool_n, uint32_t cap, hipStream_t st);
+// Witness pairs by direct differences: V (npairs x m) = x_i - x_j over the
+// non-constant coordinates colmap[0..m) in FP64; then eq. (2) from V and its
+// images W = V Pi^T (npairs x r).
+hipError_t launch_pair_diffs(const float* X, int64_t d, const int* colmap, int64_t m, const int2* pairs,
+                             int64_t npairs, double* V, hipStream_t st);
+hipError_t launch_pair_ratio(const double* V, int64_t m, const double* W, int64_t r, const int2* pairs,
+                             int64_t npairs, PairVal* out, hipStream_t st);
 // cd->best = cd->second = no pair.
 hipError_t launch_best_reset(CertDev* cd, hipStream_t st);
 
