@@ -109,11 +109,13 @@ typedef struct adagio_stats {
     double probe_screen_ms[48]; /* its all-pairs screen kernel time (device events) */
     int32_t probe_gram[48];  /* its point Gram: 0 computed, 1 computed and stored in the
                                 fit's point-Gram cache, 2 loaded from it (image Gram only),
-                                3 none: the probe was refuted by a witness pair (no screen;
-                                probe_delta is that pair's exact distortion, a lower bound
-                                on the probe's maximum) */
-    int32_t n_refuted;       /* fit: probes refuted by a witness pair (not counted in
-                                n_certificates)                                   */
+                                3 none: the probe was refuted by a witness pair of the pool
+                                (no screen; probe_delta is that pair's exact distortion, a
+                                lower bound on the probe's maximum), 4 as 2 or 0, but the
+                                screen stopped early at a pair certain to exceed eps
+                                (probe_delta: that pair's exact distortion) */
+    int32_t n_refuted;       /* fit: probes refuted by a witness pair (kinds 3 and 4, not
+                                counted in n_certificates)                        */
 } adagio_stats_t;
 
 typedef struct adagio_opts {
@@ -228,9 +230,14 @@ int adagio_certify_map(const float* X, int64_t n, int64_t d, const float* Pi, in
  * first evaluates the pool in FP64 by direct differences Pi (x_i - x_j), before
  * it embeds the cloud, and fails when a pair exceeds eps + 1e-9 (a
  * margin far above the re-evaluation's rounding error, so that a refuted
- * probe is one its certificate would fail too).  Passing probes are certified in full as before, so r, Pi
- * and the certificate do not depend on the pool; opts->no_witness = 1 turns
- * it off.  Synchronises `stream`. */
+ * probe is one its certificate would fail too).  A probe that the pool does
+ * not refute runs its screen with an early stop: a pair whose rigorous bounds
+ * put eq. (2) above eps + 2e-9 is recorded, workgroups that start after it
+ * skip their tiles, and the pair re-evaluated above eps + 1e-9 fails the
+ * probe (not while the first certificate fills the point-Gram cache).
+ * Passing probes are certified in full as before, so r, Pi and the
+ * certificate do not depend on either; opts->no_witness = 1 turns both off.
+ * Synchronises `stream`. */
 int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed,
                const adagio_opts_t* opts, float* Pi_out, int32_t* r_out, int32_t* s_out,
                adagio_cert_t* cert_out, void* stream);

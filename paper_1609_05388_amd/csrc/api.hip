@@ -64,7 +64,7 @@ struct Workspace {
   DevBuf skpart, skG, skK, sklam, skV, skfeat, mlp_pb, mlp_X, mlp_f, mlp_hb, mlp_grad, mlp_loss;
   DevBuf knQ, knD, knNq64, knNd64, knNq32, knNd32, knMax, knKeys, knFb, knCnt, knTau;
   DevBuf lam1, Vt1, colmap, colminmax, colkeep, xc64, pi64c;
-  DevBuf pool, pooln, wvals, wparts, wcd, wV, wW;
+  DevBuf pool, pooln, wvals, wparts, wcd, wV, wW, stopn, stopp;
   rocblas_handle blas = nullptr;  // plain FP64 GEMMs (covariance, embeddings)
   bool checked = false;
 };
@@ -642,17 +642,6 @@ static void log_probe(CertTimes& tm, int64_t r, const adagio_cert_t& c, double s
   }
 }
 
-static void log_refuted(CertTimes& tm, int64_t r, double w) {
-  ++tm.refuted;
-  if (tm.nprobe < 48) {
-    tm.probe_r[tm.nprobe] = (int32_t)r;
-    tm.probe_delta[tm.nprobe] = w;
-    tm.probe_ms[tm.nprobe] = 0.0;
-    tm.probe_gram[tm.nprobe] = 3;
-    ++tm.nprobe;
-  }
-}
-
 static void fill_stats(adagio_stats_t* s, const CertTimes& tm, int ncert, double total_ms) {
   memset(s, 0, sizeof(*s));
   s->t_screen_ms = tm.screen_ms;
@@ -678,6 +667,12 @@ static void rescore(const Points& p, const Images& im, const int2* pairs, const 
   else HIPCHK(launch_rescore<float>(p.X, p.d, im.Y32, im.r, pairs, count_ptr, count_i, cap, out, grid, st));
 }
 
+// Witness pool of a fit's search (record pairs of earlier certificates) and
+// the margin above eps that a witness must clear.
+static const uint32_t kPoolCap = 16384;
+static const uint32_t kPoolTiles = 256;
+static const double kWitnessMargin = 1e-9;
+
 static const uint32_t kDefaultCap = 1u << 20;
 static const uint32_t kHardCap = 1u << 26;
 // FP8 screen: tiles re-screened with the FP32 bounds (at most 4x that many
@@ -702,9 +697,41 @@ static float* gram_cache(Workspace& ws, const Points& p) {
   return ensure<float>(ws.gcache, bytes / sizeof(float));
 }
 
+// A probe refuted by a witness pair: kind 3 from the pool (no screen), 4 from
+// a screen that stopped early (screen_ms: its partial time).
+static void log_refuted(CertTimes& tm, int64_t r, double w, int kind, double screen_ms) {
+  ++tm.refuted;
+  if (tm.nprobe < 48) {
+    tm.probe_r[tm.nprobe] = (int32_t)r;
+    tm.probe_delta[tm.nprobe] = w;
+    tm.probe_ms[tm.nprobe] = screen_ms;
+    tm.probe_gram[tm.nprobe] = kind;
+    ++tm.nprobe;
+  }
+}
+
+// Early stop of a fit's screen: the screen records pairs whose bounds prove
+// eq. (2) > eps + 2e-9 and stops; one of them re-evaluated above
+// eps + kWitnessMargin fails the probe.
+struct StopOut {
+  bool stopped = false;
+  PairVal w;
+};
+
+static float f32_up(double x) {
+  float f = (float)x;
+  if ((double)f < x) f = nextafterf(f, INFINITY);
+  return f;
+}
+static float f32_down(double x) {
+  float f = (float)x;
+  if ((double)f > x) f = nextafterf(f, -INFINITY);
+  return f;
+}
+
 static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& im, uint32_t cap0,
                                  hipStream_t st, CertTimes* times, int screen, float* gcache = nullptr,
-                                 int gmode = 0) {
+                                 int gmode = 0, double stop_eps = -1.0, StopOut* so = nullptr) {
   PairsView v;
   v.X = p.Xc; v.ldx = (int)p.ldx;
   v.Y = im.Yc; v.ldy = (int)im.ldy;
@@ -723,24 +750,77 @@ static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& i
   const int vp = 64;
   PairVal* vparts = ensure<PairVal>(ws.vparts, 2 * vp);
 
-  EvPair e_screen, e_rest;
-  e_screen.begin(st);
-  if (screen == ADAGIO_SCREEN_BF16X3) {
-    // BF16 split screen; the emit pass below keeps the FP32 Gram (tighter
-    // bounds, fewer candidates, equally rigorous).
-    PairsViewB vb;
-    vb.Xb = p.Xb; vb.ldx = (int)p.ldxb;
-    vb.Yb = im.Yb; vb.ldy = (int)im.ldyb;
-    vb.tx = p.txb; vb.ty = im.tyb;
-    vb.n = v.n; vb.NT = v.NT; vb.ntiles = v.ntiles;
-    HIPCHK(launch_pairs_screen_bf16(vb, recs, gcache, gmode, st));
-  } else if (screen == ADAGIO_SCREEN_FP8) {
-    HIPCHK(launch_pairs_screen_fp8(p.Xq, (int)p.ldxq, im.Yq, (int)im.ldyq, im.q8, v.n, v.NT, recs, gcache, gmode,
-                                   st));
-  } else {
-    HIPCHK(launch_pairs_screen(v, recs, gcache, gmode, st));
+  ScreenStop ss;
+  const ScreenStop* sp = nullptr;
+  if (stop_eps > 0.0 && so && screen != ADAGIO_SCREEN_FP8 && gmode != 1) {
+    const double e = stop_eps + 2.0 * kWitnessMargin;
+    ss.count = ensure<uint32_t>(ws.stopn, 1);
+    ss.pairs = ensure<int2>(ws.stopp, 8);
+    ss.q_hi = f32_up((1.0 + e) * (1.0 + e));
+    ss.q_lo = e < 1.0 ? f32_down((1.0 - e) * (1.0 - e)) : -1.0f;
+    HIPCHK(hipMemsetAsync(ss.count, 0, sizeof(uint32_t), st));
+    sp = &ss;
   }
-  e_screen.end(st);
+  EvPair e_screen, e_rest;
+  auto run_screen = [&](const ScreenStop* stop) {
+    e_screen.begin(st);
+    if (screen == ADAGIO_SCREEN_BF16X3) {
+      // BF16 split screen; the emit pass below keeps the FP32 Gram (tighter
+      // bounds, fewer candidates, equally rigorous).
+      PairsViewB vb;
+      vb.Xb = p.Xb; vb.ldx = (int)p.ldxb;
+      vb.Yb = im.Yb; vb.ldy = (int)im.ldyb;
+      vb.tx = p.txb; vb.ty = im.tyb;
+      vb.n = v.n; vb.NT = v.NT; vb.ntiles = v.ntiles;
+      HIPCHK(launch_pairs_screen_bf16(vb, recs, gcache, gmode, stop, st));
+    } else if (screen == ADAGIO_SCREEN_FP8) {
+      HIPCHK(launch_pairs_screen_fp8(p.Xq, (int)p.ldxq, im.Yq, (int)im.ldyq, im.q8, v.n, v.NT, recs, gcache, gmode,
+                                     st));
+    } else {
+      HIPCHK(launch_pairs_screen(v, recs, gcache, gmode, stop, st));
+    }
+    e_screen.end(st);
+  };
+  run_screen(sp);
+  if (sp) {
+    uint32_t hc = 0;
+    HIPCHK(hipMemcpyAsync(&hc, ss.count, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hc > 0) {
+      PairVal* wv = ensure<PairVal>(ws.wvals, kPoolCap);
+      PairVal* parts = ensure<PairVal>(ws.wparts, 64);
+      CertDev* wcd = ensure<CertDev>(ws.wcd, 1);
+      rescore(p, im, ss.pairs, ss.count, nullptr, 8, wv, 1, st);
+      HIPCHK(launch_best_reset(wcd, st));
+      HIPCHK(launch_top2(wv, ss.count, 8, parts, 1, wcd, st));
+      PairVal w;
+      HIPCHK(hipMemcpyAsync(&w, &wcd->best, sizeof(PairVal), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (w.i >= 0 && w.v > stop_eps + kWitnessMargin) {
+        so->stopped = true;
+        so->w = w;
+        adagio_cert_t c;
+        memset(&c, 0, sizeof(c));
+        c.n_pairs = p.n * (p.n - 1) / 2;
+        c.max_distortion = w.v;
+        c.i = w.i;
+        c.j = w.j;
+        c.side = w.side;
+        c.runner_up = -1.0;
+        c.i2 = c.j2 = -1;
+        c.bound_rest = INFINITY;
+        if (times) {
+          const double sm = e_screen.ms();
+          times->screen_ms += sm;
+          log_refuted(*times, im.r, w.v, 4, sm);
+        }
+        return c;
+      }
+      // The bounds are rigorous, so this does not happen; if it did, the
+      // records of the skipped tiles would be stale: screen again in full.
+      run_screen(nullptr);
+    }
+  }
   e_rest.begin(st);
   HIPCHK(launch_seeds(recs, v.ntiles, tparts, nparts, seeds, cd, st));
   rescore(p, im, seeds, nullptr, &cd->n_seed, 2, seedv, 1, st);
@@ -837,9 +917,6 @@ static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& i
 // fails a map).  Each certificate adds the record pairs of its kPoolTiles
 // tiles of largest bound; a probe evaluates the pool exactly, by direct
 // differences, before it embeds the cloud and screens it.
-static const uint32_t kPoolCap = 16384;
-static const uint32_t kPoolTiles = 256;
-static const double kWitnessMargin = 1e-9;
 
 static void pool_reset(Workspace& ws, hipStream_t st) {
   uint32_t* pn = ensure<uint32_t>(ws.pooln, 2);
@@ -1137,7 +1214,7 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
       if (npool > 0) {
         const PairVal w = pool_witness(ws, p, Pi, r, npool, st);
         if (w.i >= 0 && w.v > eps + kWitnessMargin) {
-          log_refuted(tm, r, w.v);
+          log_refuted(tm, r, w.v, 3, 0.0);
           return false;
         }
       }
@@ -1147,8 +1224,13 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
         if (!gready) gcache = gram_cache(ws, p);
         gmode = gcache ? (gready ? 2 : 1) : 0;
       }
-      adagio_cert_t c = certificate(ws, p, im, cap0, st, &tm, scr, gcache, gmode);
+      // Early stop on a pair certain to exceed eps (not while the point-Gram
+      // cache is being filled)
+      StopOut so;
+      const bool may_stop = !no_witness && gmode != 1;
+      adagio_cert_t c = certificate(ws, p, im, cap0, st, &tm, scr, gcache, gmode, may_stop ? eps : -1.0, &so);
       if (gmode == 1) gready = true;
+      if (so.stopped) return false;
       ++ncert;
       if (!no_witness) npool = pool_add(ws, p, st);
       if (scr == ADAGIO_SCREEN_FP8) return c.max_distortion <= eps;
@@ -1427,7 +1509,7 @@ int adagio_release(void) {
                       &ws.knNd64, &ws.knNq32, &ws.knNd32, &ws.knMax, &ws.knKeys, &ws.knFb, &ws.knCnt, &ws.knTau,
                       &ws.lam1, &ws.Vt1, &ws.colmap, &ws.xc64, &ws.pi64c,
                       &ws.colminmax, &ws.colkeep, &ws.pool, &ws.pooln, &ws.wvals, &ws.wparts, &ws.wcd,
-                      &ws.wV, &ws.wW};
+                      &ws.wV, &ws.wW, &ws.stopn, &ws.stopp};
     for (DevBuf* b : bufs) {
       if (b->p) HIPCHK(hipFree(b->p));
       b->p = nullptr;

@@ -56,6 +56,7 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_f32(PairsArgs p) 
   __shared__ float4 termA[PT], termB[PT];
   __shared__ float red_v[2][4];
   __shared__ int red_i[2][4], red_j[2][4];
+  __shared__ uint32_t s_stop;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
@@ -73,6 +74,9 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_f32(PairsArgs p) 
     if (tp.I < 0) return;
     I = (int)tp.I;
     J = (int)tp.J;
+    // early stop: the flag's load overlaps the first chunk's loads and is
+    // shared through LDS at the first barrier, so the exit is uniform
+    if (tid == 0) s_stop = p.stop ? __hip_atomic_load(p.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
   } else {
     u_end = p.cd->n_flagged;
     thr_hi = p.cd->thr_hi;
@@ -163,6 +167,7 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_f32(PairsArgs p) 
     fetch(c0);
     stash(c0 & 1);
     __syncthreads();
+    if (MODE == 0 && s_stop != 0u) return;
     if (!LOADED) {
       for (int c = 0; c < p.nchx; ++c) {
         const int buf = c & 1;
@@ -193,11 +198,16 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_f32(PairsArgs p) 
   }
 }
 
-hipError_t launch_pairs_screen(const PairsView& v, TileRec* recs, float* gcache, int gmode, hipStream_t st) {
+hipError_t launch_pairs_screen(const PairsView& v, TileRec* recs, float* gcache, int gmode, const ScreenStop* stop,
+                               hipStream_t st) {
   const int NS = (v.NT + 7) / 8;
   const int64_t nslots = (int64_t)NS * (NS + 1) / 2 * 64;
   PairsArgs a{v.X, v.ldx, v.ldx / PK, v.Y, v.ldy, v.ldy / PK, v.tx, v.ty, v.n, v.NT, v.ntiles,
-              NS, nslots, recs, nullptr, nullptr, nullptr, 0u, nullptr, gcache, gcache ? gmode : 0};
+              NS, nslots, recs, nullptr, nullptr, nullptr, 0u, nullptr, gcache, gcache ? gmode : 0,
+              nullptr, nullptr, 3.0e38f, -1.0f};
+  if (stop) {
+    a.stop = stop->count; a.stop_pairs = stop->pairs; a.stop_hi = stop->q_hi; a.stop_lo = stop->q_lo;
+  }
   const int64_t G = round_up(nslots, 8);
   if (a.gmode == 2) k_pairs_f32<0, true><<<(unsigned)G, 256, 0, st>>>(a);
   else k_pairs_f32<0, false><<<(unsigned)G, 256, 0, st>>>(a);
@@ -207,7 +217,7 @@ hipError_t launch_pairs_screen(const PairsView& v, TileRec* recs, float* gcache,
 hipError_t launch_pairs_emit(const PairsView& v, const uint32_t* list, const CertDev* cd, int2* cand,
                              uint32_t cap, uint32_t* ncand, int grid, hipStream_t st) {
   PairsArgs a{v.X, v.ldx, v.ldx / PK, v.Y, v.ldy, v.ldy / PK, v.tx, v.ty, v.n, v.NT, v.ntiles,
-              0, 0, nullptr, list, cd, cand, cap, ncand, nullptr, 0};
+              0, 0, nullptr, list, cd, cand, cap, ncand, nullptr, 0, nullptr, nullptr, 3.0e38f, -1.0f};
   k_pairs_f32<1, false><<<(unsigned)grid, 256, 0, st>>>(a);
   return hipGetLastError();
 }

@@ -63,6 +63,7 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
   const __bf16* const Xg = b.X;
   const __bf16* const Yg = b.Y;
   const int ldx = b.ldx, ldy = b.ldy, nchx = b.nchx, nchy = b.nchy;
+  __shared__ uint32_t s_stop;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
@@ -80,6 +81,8 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
     if (tp.I < 0) return;
     I = (int)tp.I;
     J = (int)tp.J;
+    // early stop, shared through LDS at the first barrier (uniform exit)
+    if (tid == 0) s_stop = p.stop ? __hip_atomic_load(p.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
   } else {
     u_end = p.cd->n_flagged;
     thr_hi = p.cd->thr_hi;
@@ -182,6 +185,7 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
     fetch(c0);
     stash(c0 & 1);
     __syncthreads();
+    if (MODE == 0 && s_stop != 0u) return;
     for (int c = c0; c < nchx; ++c) {
       const int buf = c & 1;
       if (c + 1 < total) fetch(c + 1);
@@ -218,7 +222,8 @@ hipError_t launch_split_bf16(const float* src, int64_t n_pad, int64_t m, int64_t
   return hipGetLastError();
 }
 
-hipError_t launch_pairs_screen_bf16(const PairsViewB& v, TileRec* recs, float* gcache, int gmode, hipStream_t st) {
+hipError_t launch_pairs_screen_bf16(const PairsViewB& v, TileRec* recs, float* gcache, int gmode,
+                                    const ScreenStop* stop, hipStream_t st) {
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pairs_bf16x3<0>),
@@ -232,7 +237,11 @@ hipError_t launch_pairs_screen_bf16(const PairsViewB& v, TileRec* recs, float* g
   a.X = v.Xb; a.ldx = v.ldx; a.nchx = v.ldx / BK;
   a.Y = v.Yb; a.ldy = v.ldy; a.nchy = v.ldy / BK;
   a.p = PairsArgs{nullptr, 0, 0, nullptr, 0, 0, v.tx, v.ty, v.n, v.NT, v.ntiles, NS, nslots, recs,
-                  nullptr, nullptr, nullptr, 0u, nullptr, gcache, gcache ? gmode : 0};
+                  nullptr, nullptr, nullptr, 0u, nullptr, gcache, gcache ? gmode : 0,
+                  nullptr, nullptr, 3.0e38f, -1.0f};
+  if (stop) {
+    a.p.stop = stop->count; a.p.stop_pairs = stop->pairs; a.p.stop_hi = stop->q_hi; a.p.stop_lo = stop->q_lo;
+  }
   const int64_t G = round_up(nslots, 8);
   k_pairs_bf16x3<0><<<(unsigned)G, 256, kLdsBf16, st>>>(a);
   return hipGetLastError();

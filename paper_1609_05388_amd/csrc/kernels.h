@@ -62,9 +62,19 @@ struct PairsView {
   const float2* tx; const float2* ty;
   int n; int NT; int64_t ntiles;
 };
+// Early stop of a screen (MODE 0): pairs with q_lo > q_hi or q_hi < q_lo of
+// these thresholds are certain to exceed the target distortion; the first 8
+// go to pairs, *count (zeroed by the caller) counts them, and workgroups
+// that start once *count is nonzero skip their tile (their records are left
+// as they were).
+struct ScreenStop {
+  uint32_t* count; int2* pairs; float q_hi, q_lo;
+};
 // gcache: point-Gram cache (16384 floats per tile) or null; gmode 1 stores
-// the tiles' point Grams there, 2 loads them instead of recomputing.
-hipError_t launch_pairs_screen(const PairsView& v, TileRec* recs, float* gcache, int gmode, hipStream_t st);
+// the tiles' point Grams there, 2 loads them instead of recomputing.  stop:
+// null, or the early stop.
+hipError_t launch_pairs_screen(const PairsView& v, TileRec* recs, float* gcache, int gmode, const ScreenStop* stop,
+                               hipStream_t st);
 hipError_t launch_pairs_emit(const PairsView& v, const uint32_t* list, const CertDev* cd, int2* cand, uint32_t cap,
                              uint32_t* ncand, int grid, hipStream_t st);
 
@@ -77,7 +87,8 @@ struct PairsViewB {
 };
 hipError_t launch_split_bf16(const float* src, int64_t n_pad, int64_t m, int64_t lds, int64_t ldb, __bf16* dst,
                              hipStream_t st);
-hipError_t launch_pairs_screen_bf16(const PairsViewB& v, TileRec* recs, float* gcache, int gmode, hipStream_t st);
+hipError_t launch_pairs_screen_bf16(const PairsViewB& v, TileRec* recs, float* gcache, int gmode,
+                                    const ScreenStop* stop, hipStream_t st);
 
 // k_cert.hip
 hipError_t launch_seeds(const TileRec* recs, int64_t ntiles, TileRec* part, int nparts, int2* seeds, CertDev* cd,

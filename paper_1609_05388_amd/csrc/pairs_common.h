@@ -86,6 +86,11 @@ struct PairsArgs {
   const CertDev* cd;                   //         thresholds and count
   int2* cand; uint32_t cap; uint32_t* ncand;
   float* gcache; int gmode;            // MODE 0: point Gram per tile, 0 off, 1 store, 2 load
+  // MODE 0 early stop (null: off): a pair with q_lo > stop_hi or q_hi <
+  // stop_lo is certain to exceed the search's target; the pair goes to
+  // stop_pairs[*stop] (first 8 kept), *stop counts them, and workgroups that
+  // start after *stop became nonzero skip their tile.
+  uint32_t* stop; int2* stop_pairs; float stop_hi, stop_lo;
 };
 
 // Bounds on q for one pair from its two Gram entries and row terms.  Branch
@@ -126,7 +131,8 @@ __device__ inline void tile_epilogue(const f32x16 (&accX)[2][2], const f32x16 (&
   // Edge tiles (diagonal, or past the last point) mask invalid pairs.
   const bool masked = !((I < J) && (col0 + kTile <= p.n));
   float best_hi = -1.0f, best_lo = 3.0e38f;
-  int code_hi = -1, code_lo = -1;
+  int code_hi = -1, code_lo = -1, code_c = -1;
+  const float stop_hi = p.stop_hi, stop_lo = p.stop_lo;
   const float4 tb0 = termB[wc * 64 + li], tb1 = termB[wc * 64 + 32 + li];
   // The pass over the thread's 64 pairs, compiled once with the edge mask and
   // once without (the mask is uniform per tile: no per-pair branch).
@@ -142,18 +148,20 @@ __device__ inline void tile_epilogue(const f32x16 (&accX)[2][2], const f32x16 (&
         for (int y = 0; y < 2; ++y) {
           float qhi, qlo;
           pair_bounds(accX[x][y][v], accY[x][y][v], ta, y ? tb1 : tb0, qhi, qlo);
+          bool certain = MODE == 0 && (qlo > stop_hi || qhi < stop_lo);
           if (M) {
             const int cl = wc * 64 + y * 32 + li;
             const bool valid = (I < J || rl < cl) && col0 + cl < p.n;
-            if (!valid) { qhi = -1.0f; qlo = 3.0e38f; }
+            if (!valid) { qhi = -1.0f; qlo = 3.0e38f; certain = false; }
           }
           if (MODE == 0) {
             const int code = (x * 2 + y) * 16 + v;
             if (qhi > best_hi) { best_hi = qhi; code_hi = code; }
             if (qlo < best_lo) { best_lo = qlo; code_lo = code; }
+            if (certain) code_c = code;
             // Pin the running arg-extremes here: otherwise the compiler first
             // evaluates all 64 pairs (128 live values) and spills.
-            asm volatile("" : "+v"(best_hi), "+v"(code_hi), "+v"(best_lo), "+v"(code_lo));
+            asm volatile("" : "+v"(best_hi), "+v"(code_hi), "+v"(best_lo), "+v"(code_lo), "+v"(code_c));
           } else {
             if (qhi >= thr_hi || qlo <= thr_lo) {
               const uint32_t pos = atomicAdd(p.ncand, 1u);
@@ -175,6 +183,11 @@ __device__ inline void tile_epilogue(const f32x16 (&accX)[2][2], const f32x16 (&
       gj = col0 + wc * 64 + y * 32 + li;
     };
     int ih, jh, il, jl;
+    if (p.stop && code_c >= 0) {   // rare: a pair certain to exceed the target
+      decode(code_c, ih, jh);
+      const uint32_t pos = atomicAdd(p.stop, 1u);
+      if (pos < 8) p.stop_pairs[pos] = make_int2(ih, jh);
+    }
     decode(code_hi, ih, jh);
     decode(code_lo, il, jl);
     wave_arg<true>(best_hi, ih, jh);

@@ -1,8 +1,9 @@
 """Refutation by witness pairs in the fit's search: eq. (3) is a maximum over
 pairs, so one pair whose exact eq. (2) value exceeds eps fails a probe's map
 without its all-pairs screen.  The fit keeps a pool of the worst record pairs
-of its earlier certificates; the result must be the one of the search that
-certifies every probe in full, probe for probe."""
+of its earlier certificates (kind 3) and stops a screen at a pair that its
+bounds prove above eps (kind 4); the result must be the one of the search
+that certifies every probe in full, probe for probe."""
 import numpy as np
 import pytest
 import torch
@@ -42,14 +43,14 @@ def test_witness_search_same_result(gpu_lib, name, eps, screen):
     assert torch.equal(a["Pi"], b["Pi"])
     assert a["cert"] == b["cert"]
     sa, sb = a["stats"], b["stats"]
-    assert sb["n_refuted"] == 0 and 3 not in sb["probe_gram"]
+    assert sb["n_refuted"] == 0 and 3 not in sb["probe_gram"] and 4 not in sb["probe_gram"]
     # the same probes in the same order; each refuted one replaces a certificate
     assert sa["probe_r"] == sb["probe_r"]
     assert sa["n_certificates"] + sa["n_refuted"] == sb["n_certificates"]
-    assert sa["probe_gram"].count(3) == sa["n_refuted"]
+    assert sa["probe_gram"].count(3) + sa["probe_gram"].count(4) == sa["n_refuted"]
     for k, g in enumerate(sa["probe_gram"]):
         full = sb["probe_delta"][k]
-        if g == 3:
+        if g in (3, 4):
             # an attained value above eps, at most the probe's exact maximum
             assert eps < sa["probe_delta"][k] <= full + 1e-9
             assert full > eps
@@ -69,7 +70,7 @@ def test_witness_values_against_oracle(gpu_lib):
     assert st["n_refuted"] >= 2
     _, Vt = gpu_lib.pca(dev(X))
     for r, dl, g in zip(st["probe_r"], st["probe_delta"], st["probe_gram"]):
-        if g != 3:
+        if g not in (3, 4):
             continue
         Pi = gpu_lib.project_axes(Vt, r, gen.JL_SEED).cpu().numpy()
         want = ocert.certify(X, oemb.embed(X, Pi))
