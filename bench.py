@@ -111,13 +111,14 @@ def summarize_traffic(d):
         "fetch": out["FETCH_SIZE"], "write": out["WRITE_SIZE"],
         "commands": [
             "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pmc -o copy_FETCH_SIZE -- python3 <repo>/bench.py --calib-copy-mib 1024",
-            "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pmc -o fit_FETCH_SIZE -- python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extra-eps --no-forms --no-large --no-knn",
+            "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pmc -o fit_FETCH_SIZE -- python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extra-eps --no-forms --no-large --no-knn --no-witness",
             "(the same two with WRITE_SIZE)",
             "python3 <repo>/bench.py --summarize-traffic <out>/pmc",
         ],
-        "note": "counter bytes are KiB x 1024 per dispatch; one fit: the mean of its k_pairs_f32<0, false> "
-                "launches (point Gram computed and stored) and of its k_pairs_f32<0, true> launches (point Gram "
-                "loaded); each counter is scaled by the factor that maps its reading for a plain 1 GiB copy to 1 GiB",
+        "note": "counter bytes are KiB x 1024 per dispatch; one fit certifying every probe in full (so every "
+                "launch is whole): the mean of its k_pairs_f32<0, false> launches (point Gram computed and "
+                "stored) and of its k_pairs_f32<0, true> launches (point Gram loaded); each counter is scaled by "
+                "the factor that maps its reading for a plain 1 GiB copy to 1 GiB",
     }
     print(json.dumps(rec, indent=1))
 
@@ -369,6 +370,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the precision-form fits")
     ap.add_argument("--no-large", action="store_true", help="skip the n=200000, d=4096 precision-form fit")
     ap.add_argument("--no-knn", action="store_true", help="skip the kNN retrieval application")
+    ap.add_argument("--no-witness", action="store_true",
+                    help="plain fits certify every probe in full (every screen launch whole: the counter runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this size (HBM counter calibration)")
     ap.add_argument("--summarize-traffic", metavar="PMC_DIR",
@@ -405,15 +408,16 @@ def main():
     Xd = torch.from_numpy(X).cuda()
     torch.cuda.synchronize()
 
+    wit = not args.no_witness
     for w in range(args.warmup):
-        out = adagio.fit(Xd, args.eps, gen.JL_SEED)
+        out = adagio.fit(Xd, args.eps, gen.JL_SEED, witness=wit)
         log("warmup %d: r=%d fit %.1f ms" % (w, out["r"], out["stats"]["t_total_ms"]))
     torch.cuda.synchronize()
 
     outs = []
     t0 = time.perf_counter()
     for k in range(args.steps):
-        outs.append(adagio.fit(Xd, args.eps, gen.JL_SEED))
+        outs.append(adagio.fit(Xd, args.eps, gen.JL_SEED, witness=wit))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     fit_s = (t1 - t0) / args.steps
@@ -426,14 +430,16 @@ def main():
         "screen %.1f ms" % (fit_s * 1e3, last["r"], ncert, st["n_refuted"], last["cert"]["max_distortion"],
                             st["t_pca_ms"], st["t_search_ms"], st["t_screen_ms"]))
 
-    # the same fit certifying every probe in full (no witness pool)
-    nw_s, nw_outs = timed_fits(adagio, torch, Xd, args.eps, gen.JL_SEED, args.steps, witness=False)
-    nw = nw_outs[-1]
-    without_witness = {"fit_ms": nw_s * 1e3, "certificates": nw["stats"]["n_certificates"],
-                       "same_result": bool(nw["r"] == last["r"] and torch.equal(nw["Pi"], last["Pi"])
-                                           and nw["cert"] == last["cert"]),
-                       "pair_evaluations_per_s": npairs * nw["stats"]["n_certificates"] / nw_s}
-    log("without witnesses: fit %.1f ms, %d certificates" % (nw_s * 1e3, without_witness["certificates"]))
+    # the same fit certifying every probe in full (no witness pool, no early stop)
+    without_witness = None
+    if wit:
+        nw_s, nw_outs = timed_fits(adagio, torch, Xd, args.eps, gen.JL_SEED, args.steps, witness=False)
+        nw = nw_outs[-1]
+        without_witness = {"fit_ms": nw_s * 1e3, "certificates": nw["stats"]["n_certificates"],
+                           "same_result": bool(nw["r"] == last["r"] and torch.equal(nw["Pi"], last["Pi"])
+                                               and nw["cert"] == last["cert"]),
+                           "pair_evaluations_per_s": npairs * nw["stats"]["n_certificates"] / nw_s}
+        log("without witnesses: fit %.1f ms, %d certificates" % (nw_s * 1e3, without_witness["certificates"]))
 
     # roofline of the screen kernel over the launches of the timed steps.  The
     # first certificate of a fit computes (and caches) the point Gram: 2(d' + r)
