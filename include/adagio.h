@@ -29,7 +29,9 @@
  *   work, so invalid arguments never touch the GPU.
  * - Results are deterministic: the same inputs, seed and device give bitwise
  *   identical outputs (timing fields aside; adagio_knn's n_fallback may also
- *   vary between runs, its answers do not).
+ *   vary between runs, its answers do not; so may probe_delta of a fit probe
+ *   whose screen stopped early, which is the first pair found, while the
+ *   probe's outcome is fixed).
  */
 #ifndef ADAGIO_H
 #define ADAGIO_H
