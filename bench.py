@@ -52,10 +52,10 @@ def source_hash():
 
 
 def traffic_per_launch(kind):
-    """HBM bytes per screen launch of one kind ("full": the first certificate
-    of a fit, point Gram computed and stored; "cached": the others) from the
-    committed rocprofv3 counter runs, or None when absent or taken on other
-    kernel sources."""
+    """HBM bytes per screen launch of one kind ("fill": the point-Gram fill
+    of a fit; "cached": its certificates' screens) from the committed
+    rocprofv3 counter runs, or None when absent or taken on other kernel
+    sources."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
@@ -66,7 +66,7 @@ def traffic_per_launch(kind):
 
 
 TRAFFIC_KERNEL = "adg::k_pairs_f32<0"
-FULL_KERNEL = "adg::k_pairs_f32<0, false>"     # point Gram computed (and stored)
+FULL_KERNEL = "adg::k_pairs_f32<0, false>"     # point Gram computed (the fit's cache fill)
 CACHED_KERNEL = "adg::k_pairs_f32<0, true>"    # point Gram loaded
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 COPY_BYTES = 1 << 30
@@ -95,13 +95,13 @@ def summarize_traffic(d):
     for c in ("FETCH_SIZE", "WRITE_SIZE"):
         copy = pick(per_kernel(os.path.join(d, "copy_%s_counter_collection.csv" % c)), COPY_KERNEL)
         agg = per_kernel(os.path.join(d, "fit_%s_counter_collection.csv" % c))
-        full, cached = pick(agg, FULL_KERNEL), pick(agg, CACHED_KERNEL)
+        fill, cached = pick(agg, FULL_KERNEL), pick(agg, CACHED_KERNEL)
         factor = COPY_BYTES / (sum(copy) / len(copy))
         out[c] = {"copy_counter_bytes": sum(copy) / len(copy), "factor": factor,
-                  "full_launch_bytes": sum(full) / len(full) * factor,
+                  "fill_launch_bytes": sum(fill) / len(fill) * factor,
                   "cached_launch_bytes": (sum(cached) / len(cached) * factor) if cached else None,
-                  "launches": len(full) + len(cached)}
-    hb = {"full": out["FETCH_SIZE"]["full_launch_bytes"] + out["WRITE_SIZE"]["full_launch_bytes"]}
+                  "launches": len(fill) + len(cached)}
+    hb = {"fill": out["FETCH_SIZE"]["fill_launch_bytes"] + out["WRITE_SIZE"]["fill_launch_bytes"]}
     if out["FETCH_SIZE"]["cached_launch_bytes"] is not None:
         hb["cached"] = out["FETCH_SIZE"]["cached_launch_bytes"] + out["WRITE_SIZE"]["cached_launch_bytes"]
     rec = {
@@ -116,9 +116,9 @@ def summarize_traffic(d):
             "python3 <repo>/bench.py --summarize-traffic <out>/pmc",
         ],
         "note": "counter bytes are KiB x 1024 per dispatch; one fit certifying every probe in full (so every "
-                "launch is whole): the mean of its k_pairs_f32<0, false> launches (point Gram computed and "
-                "stored) and of its k_pairs_f32<0, true> launches (point Gram loaded); each counter is scaled by "
-                "the factor that maps its reading for a plain 1 GiB copy to 1 GiB",
+                "launch is whole): its k_pairs_f32<0, false> launch (the point-Gram fill, no images) and the "
+                "mean of its k_pairs_f32<0, true> launches (point Gram loaded, image Gram computed); each counter "
+                "is scaled by the factor that maps its reading for a plain 1 GiB copy to 1 GiB",
     }
     print(json.dumps(rec, indent=1))
 
@@ -441,13 +441,18 @@ def main():
                            "pair_evaluations_per_s": npairs * nw["stats"]["n_certificates"] / nw_s}
         log("without witnesses: fit %.1f ms, %d certificates" % (nw_s * 1e3, without_witness["certificates"]))
 
-    # roofline of the screen kernel over the launches of the timed steps.  The
-    # first certificate of a fit computes (and caches) the point Gram: 2(d' + r)
-    # flops per pair (d' non-constant coordinates); the others load it and
-    # compute the image Gram: 2r.
-    kinds = {"full": [0.0, 0.0, 0], "cached": [0.0, 0.0, 0]}
+    # roofline of the screen kernel over the launches of the timed steps.  A
+    # fit fills the point-Gram cache once (2 d' flops per pair, d' non-constant
+    # coordinates; on a second stream during the PCA); its certificates load it
+    # and compute the image Gram (2r flops per pair).  Without the cache a
+    # screen computes both (2(d' + r)).
+    kinds = {"fill": [0.0, 0.0, 0], "full": [0.0, 0.0, 0], "cached": [0.0, 0.0, 0]}
     for o in outs:
         s = o["stats"]
+        if s["t_gram_ms"] > 0:  # the point-Gram fill: 2 d' flops per pair, overlapping the PCA
+            kinds["fill"][0] += npairs * 2.0 * dx
+            kinds["fill"][1] += s["t_gram_ms"]
+            kinds["fill"][2] += 1
         for r, t, g in zip(s["probe_r"], s["probe_screen_ms"], s["probe_gram"]):
             if g in (3, 4):     # refuted by a witness pair: no screen, or one stopped early
                 continue
@@ -464,7 +469,8 @@ def main():
     traffic = traffic_per_launch(dom)
     roofline = {"bound": "mfma", "achieved": launch_kinds[dom]["tflops"], "peak": PEAK_FP32_MFMA_TFLOPS,
                 "unit": "TFLOP/s", "frac": launch_kinds[dom]["frac"], "traffic": traffic,
-                "kernel": "k_pairs_f32<0, %s> (all-pairs screen), %s launches" % ("true" if dom == "cached" else "false", dom),
+                "kernel": "k_pairs_f32<0, %s> (all-pairs screen), %s launches" % ("true" if dom == "cached" else "false",
+                                                                                    dom),
                 "launches": launch_kinds[dom]["launches"], "avg_launch_ms": launch_kinds[dom]["avg_launch_ms"],
                 "flops_per_launch": launch_kinds[dom]["flops_per_launch"], "launch_kinds": launch_kinds}
 

@@ -110,7 +110,8 @@ typedef struct adagio_stats {
     double probe_delta[48];  /* its exact max distortion                          */
     double probe_screen_ms[48]; /* its all-pairs screen kernel time (device events) */
     int32_t probe_gram[48];  /* its point Gram: 0 computed, 1 computed and stored in the
-                                fit's point-Gram cache, 2 loaded from it (image Gram only),
+                                fit's point-Gram cache (no longer used by fits, which fill
+                                the cache beforehand), 2 loaded from it (image Gram only),
                                 3 none: the probe was refuted by a witness pair of the pool
                                 (no screen; probe_delta is that pair's exact distortion, a
                                 lower bound on the probe's maximum), 4 as 2 or 0, but the
@@ -118,6 +119,9 @@ typedef struct adagio_stats {
                                 (probe_delta: that pair's exact distortion) */
     int32_t n_refuted;       /* fit: probes refuted by a witness pair (kinds 3 and 4, not
                                 counted in n_certificates)                        */
+    double t_gram_ms;        /* fit: the point-Gram cache fill (device events on the
+                                library's second stream, overlapping the PCA); 0 when
+                                the cache did not fit                             */
 } adagio_stats_t;
 
 typedef struct adagio_opts {
@@ -213,11 +217,13 @@ int adagio_certify_map(const float* X, int64_t n, int64_t d, const float* Pi, in
  * BF16 split screen; if that fails, certified bisection continues above it,
  * so the returned certificate is always a certificate.  The certificates of
  * the search share a point-Gram cache: the points do not change within a
- * fit, so the first certificate keeps each 128 x 128 tile's point Gram
- * (64 KB per tile: 7.2 GB at n = 60000) in device memory and the others read
- * it back and compute only the image Gram; the cache is used when it fits in
- * half of the free device memory, and the certificate is the same either
- * way.  opts->family = ADAGIO_MAP_PCA or ADAGIO_MAP_JL runs the same search
+ * fit, so each 128 x 128 tile's point Gram (64 KB per tile: 7.2 GB at
+ * n = 60000) is kept in device memory and the screens read it back and
+ * compute only the image Gram; the cache is used when it fits in half of the
+ * free device memory, and the certificate is the same either way.  The fit
+ * fills it with one Gram-only screen launch on a second, non-blocking stream
+ * of default priority while the PCA runs on `stream`; `stream` waits for it
+ * before its first screen.  opts->family = ADAGIO_MAP_PCA or ADAGIO_MAP_JL runs the same search
  * over the PCA-only or JL-only maps of Table 2 (at r = d: V^T, resp. the
  * identity); the learned search is for Algorithm 1's maps only.
  * opts->pca = ADAGIO_PCA_RANDOMIZED takes the principal directions from

@@ -45,7 +45,8 @@ class Stats(ctypes.Structure):
                 ("n_rescored", ctypes.c_int64), ("n_probes", ctypes.c_int32),
                 ("n_screened", ctypes.c_int32), ("probe_r", ctypes.c_int32 * 48),
                 ("probe_delta", ctypes.c_double * 48), ("probe_screen_ms", ctypes.c_double * 48),
-                ("probe_gram", ctypes.c_int32 * 48), ("n_refuted", ctypes.c_int32)]
+                ("probe_gram", ctypes.c_int32 * 48), ("n_refuted", ctypes.c_int32),
+                ("t_gram_ms", ctypes.c_double)]
 
     def to_dict(self):
         out = {}

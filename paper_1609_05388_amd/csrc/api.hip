@@ -66,6 +66,11 @@ struct Workspace {
   DevBuf lam1, Vt1, colmap, colminmax, colkeep, xc64, pi64c;
   DevBuf pool, pooln, wvals, wparts, wcd, wV, wW, stopn, stopp;
   rocblas_handle blas = nullptr;  // plain FP64 GEMMs (covariance, embeddings)
+  // second stream (non-blocking, default priority) for work that overlaps
+  // the caller's stream: the fit's point-Gram fill during its PCA
+  hipStream_t aux = nullptr;
+  hipStream_t aux2 = nullptr;  // non-blocking, all CUs: the fit's exact PCA beside the fill
+  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_t0 = nullptr, ev_t1 = nullptr, ev_pca = nullptr;
   bool checked = false;
 };
 
@@ -103,6 +108,10 @@ static Workspace& workspace() {
     }
     ws.checked = true;
   }
+  // work an earlier call left on the library's streams (a fit that ended in
+  // an error) must not overlap this call's use of the workspace
+  if (ws.aux) HIPCHK(hipStreamSynchronize(ws.aux));
+  if (ws.aux2) HIPCHK(hipStreamSynchronize(ws.aux2));
   return ws;
 }
 
@@ -983,6 +992,68 @@ static PairVal pool_witness(Workspace& ws, const Points& p, const float* Pi, int
 
 static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// The library's two extra streams, both of default priority.  aux runs the
+// point-Gram fill on 7/8 of the CUs (a CU-masked stream, so that the PCA's
+// small latency-bound kernels keep CUs of their own; a plain non-blocking
+// stream if the mask is refused).  A CU-masked stream is a blocking stream:
+// it orders itself after work on the null stream, and later null-stream work
+// after it, so the PCA beside it runs on aux2, non-blocking.
+static void ensure_streams(Workspace& ws) {
+  if (!ws.aux) {
+    int dev = 0, ncu = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int keep = ncu - ncu / 8;
+    std::vector<uint32_t> mask((size_t)(ncu + 31) / 32, 0u);
+    for (int c = 0; c < keep; ++c) mask[(size_t)c / 32] |= 1u << (c % 32);
+    if (ncu < 16 || hipExtStreamCreateWithCUMask(&ws.aux, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
+      (void)hipGetLastError();
+      ws.aux = nullptr;
+      HIPCHK(hipStreamCreateWithFlags(&ws.aux, hipStreamNonBlocking));
+    }
+  }
+  if (!ws.aux2) HIPCHK(hipStreamCreateWithFlags(&ws.aux2, hipStreamNonBlocking));
+  for (hipEvent_t* e : {&ws.ev_in, &ws.ev_out, &ws.ev_pca}) {
+    if (!*e) HIPCHK(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  }
+  for (hipEvent_t* e : {&ws.ev_t0, &ws.ev_t1}) {
+    if (!*e) HIPCHK(hipEventCreate(e));
+  }
+}
+
+// Point Gram of every tile into the fit's cache, on ws.aux after the work
+// already queued on st (the centred copies); st waits for it with ws.ev_out
+// before its first screen.  The points' Gram does not depend on the map, so
+// it overlaps the PCA, which leaves most of the GPU idle.  The fill's kernel
+// time is read later from ws.ev_t0 / ev_t1.
+static void gram_fill_async(Workspace& ws, const Points& p, int screen, float* gcache, hipStream_t st) {
+  ensure_streams(ws);
+  HIPCHK(hipEventRecord(ws.ev_in, st));
+  HIPCHK(hipStreamWaitEvent(ws.aux, ws.ev_in, 0));
+  HIPCHK(hipEventRecord(ws.ev_t0, ws.aux));
+  const int NT = (int)(p.n_pad / kTile);
+  const int64_t ntiles = (int64_t)NT * (NT + 1) / 2;
+  if (screen == ADAGIO_SCREEN_BF16X3) {
+    PairsViewB vb;
+    vb.Xb = p.Xb; vb.ldx = (int)p.ldxb;
+    vb.Yb = p.Xb; vb.ldy = 0;
+    vb.tx = p.txb; vb.ty = p.txb;
+    vb.n = (int)p.n; vb.NT = NT; vb.ntiles = ntiles;
+    HIPCHK(launch_pairs_gram_fill_bf16(vb, gcache, ws.aux));
+  } else if (screen == ADAGIO_SCREEN_FP8) {
+    HIPCHK(launch_pairs_screen_fp8(p.Xq, (int)p.ldxq, p.Xq, 0, nullptr, (int)p.n, NT, nullptr, gcache, 1, ws.aux));
+  } else {
+    PairsView v;
+    v.X = p.Xc; v.ldx = (int)p.ldx;
+    v.Y = p.Xc; v.ldy = 0;
+    v.tx = p.tx; v.ty = p.tx;
+    v.n = (int)p.n; v.NT = NT; v.ntiles = ntiles;
+    HIPCHK(launch_pairs_gram_fill(v, gcache, ws.aux));
+  }
+  HIPCHK(hipEventRecord(ws.ev_t1, ws.aux));
+  HIPCHK(hipEventRecord(ws.ev_out, ws.aux));
+}
+
 template <typename F>
 static int guarded(F&& f) {
   std::lock_guard<std::mutex> lock(g_mu);
@@ -1162,6 +1233,14 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     EvPair e_pca, e_search;
     e_pca.begin(st);
     Points p = prep_points(ws, X, n, d, st, screen);
+    // The search's screens share a point-Gram cache (when it fits), filled on
+    // the second stream while the PCA runs.
+    float* gcache = gram_cache(ws, p);
+    bool gwait = false;
+    if (gcache) {
+      gram_fill_async(ws, p, screen, gcache, st);
+      gwait = true;
+    }
     Axes ax;                         // the JL-only family needs no PCA
     const bool randomized = pca == ADAGIO_PCA_RANDOMIZED && family != ADAGIO_MAP_JL;
     const int mc = (int)round_up(d, 2 * bj_block());
@@ -1171,7 +1250,16 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
       ax.lam = ensure<double>(ws.lam, (size_t)d);
       ax.Vt = ensure<double>(ws.Vt, (size_t)(d * d));
     } else if (family != ADAGIO_MAP_JL) {
-      ax = principal_axes(ws, p, st);
+      if (gwait) {
+        // beside the fill: on the non-blocking second stream, after the
+        // centred copies (ws.ev_in), and st continues after it
+        HIPCHK(hipStreamWaitEvent(ws.aux2, ws.ev_in, 0));
+        ax = principal_axes(ws, p, ws.aux2);
+        HIPCHK(hipEventRecord(ws.ev_pca, ws.aux2));
+        HIPCHK(hipStreamWaitEvent(st, ws.ev_pca, 0));
+      } else {
+        ax = principal_axes(ws, p, st);
+      }
     }
     e_pca.end(st);
     // Randomized PCA: directions for the largest s needed so far plus 10.
@@ -1201,9 +1289,7 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     // all pairs is <= eps, and becomes the current answer.  A screened probe
     // passes when its re-evaluated maximum is <= eps; it fails only on a pair
     // that exceeds eps, but may pass a map that a certificate rejects.
-    // The probes of the search's own screen share the point-Gram cache.
-    float* gcache = nullptr;
-    bool gready = false;
+    // The probes of the search's own screen load the point-Gram cache.
     // Witness pool: probes after the first certificate are first checked
     // against the worst pairs of the earlier certificates.
     uint32_t npool = 0;
@@ -1219,17 +1305,15 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
         }
       }
       Images im = images_of_map(ws, p, Pi, r, st);
-      int gmode = 0;
-      if (scr == screen) {
-        if (!gready) gcache = gram_cache(ws, p);
-        gmode = gcache ? (gready ? 2 : 1) : 0;
+      const int gmode = scr == screen && gcache ? 2 : 0;
+      if (gmode == 2 && gwait) {
+        HIPCHK(hipStreamWaitEvent(st, ws.ev_out, 0));
+        gwait = false;
       }
-      // Early stop on a pair certain to exceed eps (not while the point-Gram
-      // cache is being filled)
+      // Early stop on a pair certain to exceed eps
       StopOut so;
-      const bool may_stop = !no_witness && gmode != 1;
-      adagio_cert_t c = certificate(ws, p, im, cap0, st, &tm, scr, gcache, gmode, may_stop ? eps : -1.0, &so);
-      if (gmode == 1) gready = true;
+      adagio_cert_t c = certificate(ws, p, im, cap0, st, &tm, scr, gmode ? gcache : nullptr, gmode,
+                                    no_witness ? -1.0 : eps, &so);
       if (so.stopped) return false;
       ++ncert;
       if (!no_witness) npool = pool_add(ws, p, st);
@@ -1285,6 +1369,7 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
       cert_hi = certificate(ws, p, im, cap0, st, &tm, rig);
       ++ncert;
     }
+    if (gwait) HIPCHK(hipStreamWaitEvent(st, ws.ev_out, 0));   // no probe loaded the cache
     e_search.end(st);
     HIPCHK(hipStreamSynchronize(st));
     *r_out = (int32_t)hi;
@@ -1301,6 +1386,9 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
       s->eig_sweeps = ax.sweeps;
       s->r_predicted = r_pred;
       s->n_fallback = fallback;
+      float gms = 0.0f;
+      if (gcache) HIPCHK(hipEventElapsedTime(&gms, ws.ev_t0, ws.ev_t1));
+      s->t_gram_ms = gms;
     }
   });
 }
@@ -1518,6 +1606,17 @@ int adagio_release(void) {
     if (ws.blas) {
       (void)rocblas_destroy_handle(ws.blas);
       ws.blas = nullptr;
+    }
+    for (hipStream_t* q : {&ws.aux, &ws.aux2}) {
+      if (*q) {
+        HIPCHK(hipStreamSynchronize(*q));
+        (void)hipStreamDestroy(*q);
+        *q = nullptr;
+      }
+    }
+    for (hipEvent_t* e : {&ws.ev_in, &ws.ev_out, &ws.ev_t0, &ws.ev_t1, &ws.ev_pca}) {
+      if (*e) (void)hipEventDestroy(*e);
+      *e = nullptr;
     }
   });
 }

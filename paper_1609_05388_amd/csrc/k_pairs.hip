@@ -91,8 +91,11 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_f32(PairsArgs p) 
       J = (int)tp.J;
     }
     const int row0 = I * PT, col0 = J * PT;
+    // no tile records: the launch only fills the point-Gram cache
+    const bool store_only = MODE == 0 && p.recs == nullptr;
 
-    if (tid < PT) {
+    if (store_only) {
+    } else if (tid < PT) {
       const float2 a = p.tx[row0 + tid], b = p.ty[row0 + tid];
       termA[tid] = make_float4(a.x, a.y, b.x, b.y);
     } else {
@@ -189,6 +192,7 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_f32(PairsArgs p) 
     // chunk loads, which the vector-memory counter completes in issue order)
     if (LOADED) gcache_load(p.gcache, tix, accX);
     if (!LOADED && MODE == 0 && p.gmode == 1) gcache_store(p.gcache, tix, accX);
+    if (store_only) return;
 
     tile_epilogue<MODE>(accX, accY, termA, termB, I, J, p, thr_hi, thr_lo, red_v, red_i, red_j);
     if (MODE == 0) return;
@@ -211,6 +215,16 @@ hipError_t launch_pairs_screen(const PairsView& v, TileRec* recs, float* gcache,
   const int64_t G = round_up(nslots, 8);
   if (a.gmode == 2) k_pairs_f32<0, true><<<(unsigned)G, 256, 0, st>>>(a);
   else k_pairs_f32<0, false><<<(unsigned)G, 256, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pairs_gram_fill(const PairsView& v, float* gcache, hipStream_t st) {
+  const int NS = (v.NT + 7) / 8;
+  const int64_t nslots = (int64_t)NS * (NS + 1) / 2 * 64;
+  PairsArgs a{v.X, v.ldx, v.ldx / PK, v.X, 0, 0, v.tx, v.tx, v.n, v.NT, v.ntiles,
+              NS, nslots, nullptr, nullptr, nullptr, nullptr, 0u, nullptr, gcache, 1,
+              nullptr, nullptr, 3.0e38f, -1.0f};
+  k_pairs_f32<0, false><<<(unsigned)round_up(nslots, 8), 256, 0, st>>>(a);
   return hipGetLastError();
 }
 

@@ -97,7 +97,10 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
       J = (int)tp.J;
     }
     const int row0 = I * kTile, col0 = J * kTile;
-    if (tid < kTile) {
+    // no tile records: the launch only fills the point-Gram cache
+    const bool store_only = MODE == 0 && p.recs == nullptr;
+    if (store_only) {
+    } else if (tid < kTile) {
       const float2 a = p.tx[row0 + tid], c = p.ty[row0 + tid];
       termA[tid] = make_float4(a.x, a.y, c.x, c.y);
     } else {
@@ -205,6 +208,7 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
     }
     // stored after the image loop: earlier stores would hold up its chunk loads
     if (MODE == 0 && p.gmode == 1) gcache_store(p.gcache, tix, accX);
+    if (store_only) return;
 
     tile_epilogue<MODE>(accX, accY, termA, termB, I, J, p, thr_hi, thr_lo, red_v, red_i, red_j);
     if (MODE == 0) return;
@@ -244,6 +248,25 @@ hipError_t launch_pairs_screen_bf16(const PairsViewB& v, TileRec* recs, float* g
   }
   const int64_t G = round_up(nslots, 8);
   k_pairs_bf16x3<0><<<(unsigned)G, 256, kLdsBf16, st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pairs_gram_fill_bf16(const PairsViewB& v, float* gcache, hipStream_t st) {
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pairs_bf16x3<0>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBf16);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const int NS = (v.NT + 7) / 8;
+  const int64_t nslots = (int64_t)NS * (NS + 1) / 2 * 64;
+  PairsArgsB a;
+  a.X = v.Xb; a.ldx = v.ldx; a.nchx = v.ldx / BK;
+  a.Y = v.Xb; a.ldy = 0; a.nchy = 0;
+  a.p = PairsArgs{nullptr, 0, 0, nullptr, 0, 0, v.tx, v.tx, v.n, v.NT, v.ntiles, NS, nslots, nullptr,
+                  nullptr, nullptr, nullptr, 0u, nullptr, gcache, 1, nullptr, nullptr, 3.0e38f, -1.0f};
+  k_pairs_bf16x3<0><<<(unsigned)round_up(nslots, 8), 256, kLdsBf16, st>>>(a);
   return hipGetLastError();
 }
 

@@ -129,7 +129,10 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
   if (tp.I < 0) return;
   const int I = (int)tp.I, J = (int)tp.J;
   const int row0 = I * kTile, col0 = J * kTile;
-  if (tid < kTile) termA[tid] = b.terms[row0 + tid];
+  // no tile records: the launch only fills the point-Gram cache
+  const bool store_only = b.recs == nullptr;
+  if (store_only) {
+  } else if (tid < kTile) termA[tid] = b.terms[row0 + tid];
   else termB[tid - kTile] = b.terms[col0 + tid - kTile];
 
   f32x16 accX[2][2], accY[2][2];
@@ -221,6 +224,7 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
   }
   // stored after the image loop: earlier stores would hold up its chunk loads
   if (b.gmode == 1) gcache_store(b.gcache, tix, accX);
+  if (store_only) return;
 
   // epilogue: central estimates, largest and smallest q~ of the tile
   const bool masked = !((I < J) && (col0 + kTile <= n));

@@ -75,6 +75,9 @@ struct ScreenStop {
 // null, or the early stop.
 hipError_t launch_pairs_screen(const PairsView& v, TileRec* recs, float* gcache, int gmode, const ScreenStop* stop,
                                hipStream_t st);
+// The point Gram of every tile into gcache (gmode 1 without images or tile
+// records): the screens of a fit then load it (gmode 2).
+hipError_t launch_pairs_gram_fill(const PairsView& v, float* gcache, hipStream_t st);
 hipError_t launch_pairs_emit(const PairsView& v, const uint32_t* list, const CertDev* cd, int2* cand, uint32_t cap,
                              uint32_t* ncand, int grid, hipStream_t st);
 
@@ -89,6 +92,7 @@ hipError_t launch_split_bf16(const float* src, int64_t n_pad, int64_t m, int64_t
                              hipStream_t st);
 hipError_t launch_pairs_screen_bf16(const PairsViewB& v, TileRec* recs, float* gcache, int gmode,
                                     const ScreenStop* stop, hipStream_t st);
+hipError_t launch_pairs_gram_fill_bf16(const PairsViewB& v, float* gcache, hipStream_t st);
 
 // k_cert.hip
 hipError_t launch_seeds(const TileRec* recs, int64_t ntiles, TileRec* part, int nparts, int2* seeds, CertDev* cd,
