@@ -5,6 +5,7 @@ passes their device pointers and torch's current HIP stream to the C ABI of
 include/adagio.h.  No computation happens here: if the shared library is
 missing, ``load()`` raises instead of falling back to anything else.
 """
+import atexit
 import ctypes
 import os
 
@@ -120,7 +121,15 @@ def load(path=LIB_PATH):
             fn.restype = res
             fn.argtypes = args
         _lib = lib
+        atexit.register(_release_at_exit)
     return _lib
+
+
+def _release_at_exit():
+    """Frees the library's device memory, streams and events while the HIP
+    runtime is still up (runs before the interpreter tears modules down)."""
+    if _lib is not None and torch.cuda.is_initialized():
+        _lib.adagio_release()
 
 
 def _check(rc):
