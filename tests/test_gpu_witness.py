@@ -44,6 +44,11 @@ def test_witness_search_same_result(gpu_lib, name, eps, screen):
     assert a["cert"] == b["cert"]
     sa, sb = a["stats"], b["stats"]
     assert sb["n_refuted"] == 0 and 3 not in sb["probe_gram"] and 4 not in sb["probe_gram"]
+    # the point-Gram cache is filled beside the PCA and every screen of the
+    # search's own precision loads it
+    for st in (sa, sb):
+        assert st["t_gram_ms"] > 0
+        assert 0 not in st["probe_gram"] and 1 not in st["probe_gram"] or screen == "fp8"
     # the same probes in the same order; each refuted one replaces a certificate
     assert sa["probe_r"] == sb["probe_r"]
     assert sa["n_certificates"] + sa["n_refuted"] == sb["n_certificates"]
