@@ -37,6 +37,7 @@ PEAK_FP8_MFMA_TFLOPS = 5000.0
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 PAIRS_KERNEL_SRC = [os.path.join(ROOT, "paper_1609_05388_amd", "csrc", f) for f in ("k_pairs.hip", "pairs_common.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pairs_f32_mnist60k_traffic.txt")
+MFMA_FILE = os.path.join(ROOT, "profiles", "pairs_f32_mnist60k_mfma_util.txt")
 
 
 def log(*a):
@@ -63,6 +64,19 @@ def traffic_per_launch(kind):
     if rec.get("kernel_source_sha256") != source_hash():
         return None
     return rec.get("hbm_bytes_per_launch", {}).get(kind)
+
+
+def mfma_util(kind):
+    """Mean MFMA utilisation (percent, rocprofv3 MfmaUtil) of the screen
+    launches of one kind from the committed counter run, or None when absent
+    or taken on other kernel sources."""
+    try:
+        rec = json.load(open(MFMA_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != source_hash():
+        return None
+    return rec.get("kinds", {}).get(kind, {}).get("mean_mfma_util_pct")
 
 
 TRAFFIC_KERNEL = "adg::k_pairs_f32<0"
@@ -357,6 +371,50 @@ def knn_form(adagio, gen, torch, rs=(128, 64, 32, 24, 20, 16, 12, 8, 4)):
             "per_r": rows, "screen_roofline_r128": roof, "knn_graph": graph}
 
 
+def summarize_mfma(d):
+    """MFMA utilisation of the screen kernel from one rocprofv3 --pmc run of
+    one plain fit certifying every probe in full (derived counters MfmaUtil =
+    SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x SIMDs) and MfmaFlopsF32 =
+    512 x SQ_INSTS_VALU_MFMA_MOPS_F32), per launch kind, beside the
+    algorithmic flops of the same launches."""
+    rows = sorted(csv.DictReader(open(os.path.join(d, "fit_mfma_counter_collection.csv"))),
+                  key=lambda r: int(r["Dispatch_Id"]))
+    per = collections.defaultdict(dict)
+    for r in rows:
+        per[(int(r["Dispatch_Id"]), r["Kernel_Name"])][r["Counter_Name"]] = float(r["Counter_Value"])
+    fit = [json.loads(l) for l in open(os.path.join(d, "fit_mfma.log")) if l.startswith("{")][-1]
+    n, dx = fit["config"]["n"], fit["config"]["d_nonconstant"]
+    npairs = n * (n - 1) // 2
+    rs = [p[0] for p in fit["fit"]["probes"]]
+    out = {}
+    for kind, key in (("fill", FULL_KERNEL), ("cached", CACHED_KERNEL)):
+        ds = [v for (i, k), v in sorted(per.items()) if key in k]
+        if kind == "cached":      # the fit's screens in probe order
+            alg = [npairs * 2.0 * r for r in rs]
+        else:
+            alg = [npairs * 2.0 * dx for _ in ds]
+        util = [v["MfmaUtil"] for v in ds]
+        hw = [v["MfmaFlopsF32"] for v in ds]
+        out[kind] = {"launches": len(ds), "mfma_util_pct": util, "mean_mfma_util_pct": sum(util) / len(util),
+                     "hw_mfma_flops": hw, "algorithmic_flops": alg[:len(hw)],
+                     "algorithmic_over_hw": sum(alg[:len(hw)]) / sum(hw)}
+    rec = {
+        "kernel": TRAFFIC_KERNEL,
+        "kernel_source_sha256": source_hash(),
+        "workload": fit["config"]["workload"], "probes_r": rs,
+        "kinds": out,
+        "commands": [
+            "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc MfmaUtil MfmaFlopsF32 --output-format csv -d <out>/mfma -o fit_mfma -- python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extra-eps --no-forms --no-large --no-knn --no-witness > <out>/mfma/fit_mfma.log",
+            "python3 <repo>/bench.py --summarize-mfma <out>/mfma",
+        ],
+        "note": "MfmaUtil: percent of the dispatch's GPU-active cycles during which the SIMDs' MFMA units were busy "
+                "(SQ_VALU_MFMA_BUSY_CYCLES summed over SIMDs / (GRBM_GUI_ACTIVE x 1024)); MfmaFlopsF32: FP32 MFMA "
+                "flops executed (MOPS x 512), which include the padded rows and columns and the masked halves of "
+                "the diagonal tiles that the algorithmic count leaves out",
+    }
+    print(json.dumps(rec, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -374,10 +432,15 @@ def main():
                     help="plain fits certify every probe in full (every screen launch whole: the counter runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this size (HBM counter calibration)")
+    ap.add_argument("--summarize-mfma", metavar="PMC_DIR",
+                    help="print the MFMA-utilisation summary of a rocprofv3 MfmaUtil/MfmaFlopsF32 run")
     ap.add_argument("--summarize-traffic", metavar="PMC_DIR",
                     help="print the traffic summary of rocprofv3 --pmc runs in PMC_DIR and exit")
     args = ap.parse_args()
 
+    if args.summarize_mfma:
+        summarize_mfma(args.summarize_mfma)
+        return
     if args.summarize_traffic:
         summarize_traffic(args.summarize_traffic)
         return
@@ -469,6 +532,7 @@ def main():
     traffic = traffic_per_launch(dom)
     roofline = {"bound": "mfma", "achieved": launch_kinds[dom]["tflops"], "peak": PEAK_FP32_MFMA_TFLOPS,
                 "unit": "TFLOP/s", "frac": launch_kinds[dom]["frac"], "traffic": traffic,
+                "mfma_util_rocprof_pct": mfma_util(dom),
                 "kernel": "k_pairs_f32<0, %s> (all-pairs screen), %s launches" % ("true" if dom == "cached" else "false",
                                                                                     dom),
                 "launches": launch_kinds[dom]["launches"], "avg_launch_ms": launch_kinds[dom]["avg_launch_ms"],
