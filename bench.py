@@ -177,19 +177,21 @@ def nonconstant_columns(X):
     return int((X.max(axis=0) != X.min(axis=0)).sum())
 
 
-def screen_flops(npairs, d, r, gram):
-    """Algorithmic flops of one screen launch: both Grams (2(d + r) per pair,
-    d = non-constant coordinates), or the image Gram only (2r) when the point
-    Gram came from the cache."""
-    return npairs * 2.0 * (r if gram == 2 else d + r)
+def screen_flops(npairs, d, cols, gram):
+    """Algorithmic flops of one screen launch: both Grams (2(d + cols) per
+    pair, d = non-constant coordinates), or the image Gram only (2 cols) when
+    the point Gram came from the cache; cols = the image columns the screen
+    ran over (r, or d when a map of more rows went through the Gram factor)."""
+    return npairs * 2.0 * (cols if gram == 2 else d + cols)
 
 
 def split_probes(st):
     """A fit's logged probes as (screened, rigorous, refuted) lists of
-    (r, delta, screen_ms, gram): the first n_screened probes that ran a
-    screen were FP8 screens; gram 3 marks a probe refuted by a witness pair."""
+    (r, delta, screen_ms, gram, cols): the first n_screened probes that ran a
+    screen were FP8 screens; gram 3 and 4 mark probes refuted by a witness
+    pair."""
     fp8, rig, ref = [], [], []
-    for p in zip(st["probe_r"], st["probe_delta"], st["probe_screen_ms"], st["probe_gram"]):
+    for p in zip(st["probe_r"], st["probe_delta"], st["probe_screen_ms"], st["probe_gram"], st["probe_cols"]):
         if p[3] in (3, 4):
             ref.append(p)
         elif len(fp8) < st["n_screened"]:
@@ -215,15 +217,15 @@ def fp8_form(adagio, gen, torch, Xd, eps, steps, plain_s, plain, npairs, d):
     o = outs[-1]
     st = o["stats"]
     scr, _, ref = split_probes(st)
-    fl = sum(screen_flops(npairs, d, r, g) for r, _, _, g in scr)
-    ms = sum(t for _, _, t, _ in scr)
+    fl = sum(screen_flops(npairs, d, c, g) for _, _, _, g, c in scr)
+    ms = sum(t for _, _, t, _, _ in scr)
     return {"fit_ms": fs * 1e3, "speedup_vs_plain": plain_s / fs, "r": o["r"],
             "max_distortion": o["cert"]["max_distortion"], "certified": o["cert"]["certified"],
             "abs_err_vs_plain_fp64_certificate": abs(o["cert"]["max_distortion"] - plain["cert"]["max_distortion"]),
             "same_map_as_plain": bool(o["r"] == plain["r"] and torch.equal(o["Pi"], plain["Pi"])),
             "screens": st["n_screened"], "certificates": st["n_certificates"] - st["n_screened"],
             "refuted_probes": st["n_refuted"],
-            "screen_probes": [[r, dl] for r, dl, _, _ in scr],
+            "screen_probes": [[r, dl] for r, dl, _, _, _ in scr],
             "screen_avg_launch_ms": ms / max(1, len(scr)),
             "screen_fp8_mfma_tflops": fl / max(ms, 1e-9) / 1e9,
             "screen_fp8_mfma_frac": fl / max(ms, 1e-9) / 1e9 / PEAK_FP8_MFMA_TFLOPS}
@@ -271,11 +273,11 @@ def large_form(adagio, gen, torch, eps):
     npairs = n * (n - 1) // 2
     scr = list(zip(st["probe_r"], st["probe_delta"], st["probe_screen_ms"], st["probe_gram"]))
     fp8, rig, ref = split_probes(st)
-    fl = sum(screen_flops(npairs, dx, r, g) for r, _, _, g in fp8)
-    ms = sum(t for _, _, t, _ in fp8)
-    bfl = sum(screen_flops(npairs, dx, r, g) for r, _, _, g in rig)
-    bms = sum(t for _, _, t, _ in rig)
-    same_r = [dl for r, dl, _, _ in fp8 if r == o["r"]]
+    fl = sum(screen_flops(npairs, dx, c, g) for _, _, _, g, c in fp8)
+    ms = sum(t for _, _, t, _, _ in fp8)
+    bfl = sum(screen_flops(npairs, dx, c, g) for _, _, _, g, c in rig)
+    bms = sum(t for _, _, t, _, _ in rig)
+    same_r = [dl for r, dl, _, _, _ in fp8 if r == o["r"]]
     plain = adagio.certify_map(Xd, o["Pi"].contiguous(), screen="f32", with_stats=True)
     pst = plain.pop("stats")
     torch.cuda.synchronize()
@@ -386,11 +388,12 @@ def summarize_mfma(d):
     n, dx = fit["config"]["n"], fit["config"]["d_nonconstant"]
     npairs = n * (n - 1) // 2
     rs = [p[0] for p in fit["fit"]["probes"]]
+    cols = [p[3] if len(p) > 3 else p[0] for p in fit["fit"]["probes"]]   # the screens' image columns
     out = {}
     for kind, key in (("fill", FULL_KERNEL), ("cached", CACHED_KERNEL)):
         ds = [v for (i, k), v in sorted(per.items()) if key in k]
         if kind == "cached":      # the fit's screens in probe order
-            alg = [npairs * 2.0 * r for r in rs]
+            alg = [npairs * 2.0 * c for c in cols]
         else:
             alg = [npairs * 2.0 * dx for _ in ds]
         util = [v["MfmaUtil"] for v in ds]
@@ -401,7 +404,7 @@ def summarize_mfma(d):
     rec = {
         "kernel": TRAFFIC_KERNEL,
         "kernel_source_sha256": source_hash(),
-        "workload": fit["config"]["workload"], "probes_r": rs,
+        "workload": fit["config"]["workload"], "probes_r": rs, "probes_screen_cols": cols,
         "kinds": out,
         "commands": [
             "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc MfmaUtil MfmaFlopsF32 --output-format csv -d <out>/mfma -o fit_mfma -- python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extra-eps --no-forms --no-large --no-knn --no-witness > <out>/mfma/fit_mfma.log",
@@ -516,11 +519,11 @@ def main():
             kinds["fill"][0] += npairs * 2.0 * dx
             kinds["fill"][1] += s["t_gram_ms"]
             kinds["fill"][2] += 1
-        for r, t, g in zip(s["probe_r"], s["probe_screen_ms"], s["probe_gram"]):
+        for c, t, g in zip(s["probe_cols"], s["probe_screen_ms"], s["probe_gram"]):
             if g in (3, 4):     # refuted by a witness pair: no screen, or one stopped early
                 continue
             k = "cached" if g == 2 else "full"
-            kinds[k][0] += npairs * 2.0 * ((dx + r) if k == "full" else r)
+            kinds[k][0] += screen_flops(npairs, dx, c, g)
             kinds[k][1] += t
             kinds[k][2] += 1
     launch_kinds = {}
@@ -551,10 +554,10 @@ def main():
         bl = bouts[-1]
         bflops, bms, bn = 0.0, 0.0, 0
         for o in bouts:
-            for r, t, g in zip(o["stats"]["probe_r"], o["stats"]["probe_screen_ms"], o["stats"]["probe_gram"]):
+            for c, t, g in zip(o["stats"]["probe_cols"], o["stats"]["probe_screen_ms"], o["stats"]["probe_gram"]):
                 if g in (3, 4):
                     continue
-                bflops += screen_flops(npairs, dx, r, g)
+                bflops += screen_flops(npairs, dx, c, g)
                 bms += t
                 bn += 1
         forms["bf16x3"] = {
@@ -669,8 +672,9 @@ def main():
                 "t_rescore_ms": st["t_rescore_ms"], "eig_sweeps": st["eig_sweeps"],
                 "rescored_pairs": st["n_rescored"], "flagged_tiles": st["n_flagged_tiles"],
                 "refuted_probes": st["n_refuted"], "pair_evaluations_per_s": npairs * ncert / fit_s,
-                "probes": [[r, dl, {3: "refuted by the pool", 4: "screen stopped early"}.get(g, "certified")]
-                           for r, dl, g in zip(st["probe_r"], st["probe_delta"], st["probe_gram"])],
+                "probes": [[r, dl, {3: "refuted by the pool", 4: "screen stopped early"}.get(g, "certified"), c]
+                           for r, dl, g, c in zip(st["probe_r"], st["probe_delta"], st["probe_gram"],
+                                                  st["probe_cols"])],
                 "without_witness_pool": without_witness},
         "other_eps": extra,
         "mnist_like_67_constant_coordinates": border67,

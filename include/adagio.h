@@ -122,6 +122,9 @@ typedef struct adagio_stats {
     double t_gram_ms;        /* fit: the point-Gram cache fill (device events on the
                                 library's second stream, overlapping the PCA); 0 when
                                 the cache did not fit                             */
+    int32_t probe_cols[48];  /* image columns its screen ran over: r, or d' (the non-constant
+                                coordinates) when a map of r >= d' + 32 rows is screened
+                                through the Gram factor; 0 for kind 3            */
 } adagio_stats_t;
 
 typedef struct adagio_opts {

@@ -47,7 +47,7 @@ class Stats(ctypes.Structure):
                 ("n_screened", ctypes.c_int32), ("probe_r", ctypes.c_int32 * 48),
                 ("probe_delta", ctypes.c_double * 48), ("probe_screen_ms", ctypes.c_double * 48),
                 ("probe_gram", ctypes.c_int32 * 48), ("n_refuted", ctypes.c_int32),
-                ("t_gram_ms", ctypes.c_double)]
+                ("t_gram_ms", ctypes.c_double), ("probe_cols", ctypes.c_int32 * 48)]
 
     def to_dict(self):
         out = {}

@@ -64,7 +64,7 @@ struct Workspace {
   DevBuf skpart, skG, skK, sklam, skV, skfeat, mlp_pb, mlp_X, mlp_f, mlp_hb, mlp_grad, mlp_loss;
   DevBuf knQ, knD, knNq64, knNd64, knNq32, knNd32, knMax, knKeys, knFb, knCnt, knTau;
   DevBuf lam1, Vt1, colmap, colminmax, colkeep, xc64, pi64c;
-  DevBuf pool, pooln, wvals, wparts, wcd, wV, wW, stopn, stopp;
+  DevBuf pool, pooln, wvals, wparts, wcd, wV, wW, stopn, stopp, gfM, gfFail, gfZ;
   rocblas_handle blas = nullptr;  // plain FP64 GEMMs (covariance, embeddings)
   // second stream (non-blocking, default priority) for work that overlaps
   // the caller's stream: the fit's point-Gram fill during its PCA
@@ -558,6 +558,7 @@ static void build_family_map(Workspace& ws, int family, const double* Vt, int64_
 // ----------------------------------------------------------- certificate
 struct Images {
   int64_t r = 0, ldy = 0;
+  int64_t rs = 0;               // columns of the screen images Yc: r, or d' for images through the Gram factor
   float* Yc = nullptr;
   float2* ty = nullptr;
   int64_t ldyb = 0;             // BF16 split (screen = BF16X3)
@@ -575,38 +576,83 @@ struct Images {
 static void image_copies(Workspace& ws, const Points& p, Images& im, const double* ny, const double* nx_emb,
                          double c_emb, hipStream_t st) {
   if (p.screen == ADAGIO_SCREEN_BF16X3 || p.screen == ADAGIO_SCREEN_FP8) {
-    im.ldyb = round_up(im.r, kChunkBf16);
+    im.ldyb = round_up(im.rs, kChunkBf16);
     im.Yb = ensure<__bf16>(ws.Yb, (size_t)(p.n_pad * 2 * im.ldyb));
     im.tyb = ensure<float2>(ws.tyb, (size_t)p.n_pad);
-    HIPCHK(launch_split_bf16(im.Yc, p.n_pad, im.r, im.ldy, im.ldyb, im.Yb, st));
+    HIPCHK(launch_split_bf16(im.Yc, p.n_pad, im.rs, im.ldy, im.ldyb, im.Yb, st));
     HIPCHK(launch_row_terms(ny, screen_const_bf16(im.ldyb), nx_emb, c_emb, p.n_pad, im.tyb, st));
   }
   if (p.screen == ADAGIO_SCREEN_FP8) {
-    im.ldyq = round_up(im.r, fp8_chunk());
+    im.ldyq = round_up(im.rs, fp8_chunk());
     im.Yq = ensure<unsigned char>(ws.Yq, (size_t)(p.n_pad * im.ldyq));
     float* sy = ensure<float>(ws.sy, (size_t)p.n_pad);
     double* nyq = ensure<double>(ws.nyq, (size_t)p.n_pad);
-    HIPCHK(launch_quant_fp8(im.Yc, p.n_pad, im.r, im.ldy, im.ldyq, im.Yq, sy, nyq, st));
+    HIPCHK(launch_quant_fp8(im.Yc, p.n_pad, im.rs, im.ldy, im.ldyq, im.Yq, sy, nyq, st));
     im.q8 = ensure<float4>(ws.q8terms, (size_t)p.n_pad);
     HIPCHK(launch_fp8_terms(p.nxq, nyq, p.sx, sy, p.n_pad, im.q8, st));
   }
 }
 
-// Images of the linear map Pi in FP64, centred: Y64 = (X - mu) Pi^T.
+// Screen images through the Gram factor, for a map with r >= d' + 32 rows
+// (d' non-constant coordinates): M = Pi'^T Pi' (d' x d', FP64 library GEMM
+// over the FP64 values of Pi's columns), M = L L^T (k_cholesky), and
+// Z = (X - mu)' L (n x d', FP64 library GEMM).  ||z_i - z_j||^2 = v^T L L^T v
+// for the difference v of the non-constant coordinates, and
+// |v^T L L^T v - v^T M v| <= (gamma_r + 1.01 gamma_{d'+1}) ||Pi||_F^2 ||v||^2
+// (the dot products of M, then the factor's backward error).  Null when
+// d' is beyond the factor kernel's size or the factor fails (then the
+// screen takes the r images).
+static double* gram_factor_images(Workspace& ws, const Points& p, int64_t r, hipStream_t st) {
+  const int64_t m = p.dx;
+  if (m < 1 || m > chol_max_m() || r < m + 32) return nullptr;
+  const double* P64 = static_cast<const double*>(ws.pi64c.p);   // m x r, column-major, from embed64
+  double* M = ensure<double>(ws.gfM, (size_t)(m * m));
+  int* fail = ensure<int>(ws.gfFail, 1);
+  const double one = 1.0, zero = 0.0;
+  BLASCHK(rocblas_dgemm(blas_on(ws, st), rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)m,
+                        (rocblas_int)m, (rocblas_int)r, &one, P64, (rocblas_int)m, P64, (rocblas_int)m, &zero, M,
+                        (rocblas_int)m));
+  HIPCHK(hipMemsetAsync(fail, 0, sizeof(int), st));
+  HIPCHK(launch_cholesky(M, (int)m, fail, st));
+  int hf = 0;
+  HIPCHK(hipMemcpyAsync(&hf, fail, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (hf) return nullptr;
+  const double* xc = centred64(ws, p, st);
+  double* Z = ensure<double>(ws.gfZ, (size_t)(p.n * m));
+  // column-major: Z^T (m x n, ld m) = L^T (m x m) * Xc^T (m x n, ld m)
+  BLASCHK(rocblas_dgemm(blas_on(ws, st), rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)m,
+                        (rocblas_int)p.n, (rocblas_int)m, &one, M, (rocblas_int)m, xc, (rocblas_int)m, &zero, Z,
+                        (rocblas_int)m));
+  return Z;
+}
+
+// Images of the linear map Pi in FP64, centred: Y64 = (X - mu) Pi^T (the
+// re-evaluation source), and the screen images: Y64 itself, or Z from the
+// Gram factor when Pi has at least d' + 32 rows.
 static Images images_of_map(Workspace& ws, const Points& p, const float* Pi, int64_t r, hipStream_t st) {
   Images im;
   im.r = r;
-  im.ldy = round_up(r, kChunk);
   double* Y64 = ensure<double>(ws.Y64, (size_t)(p.n * r));
   embed64(ws, p, Pi, r, Y64, st);
+  // FP64 embedding error: |E_64^2 - E^2| <= 4.02 gamma_{d+1} ||Pi||_F^2 (N_i + N_j)
+  // with ||Pi||_F^2 <= s + d <= 2.1 d for Algorithm 1's maps (and
+  // ||L||_F^2 = trace(M) for the factor's images).
+  const double dd = (double)p.d;
+  double c_emb = 4.02 * 2.1 * dd * (dd + 1.0) * kU64 * 1.01;
+  const double* Ys = Y64;
+  im.rs = r;
+  if (const double* Z = gram_factor_images(ws, p, r, st)) {
+    Ys = Z;
+    im.rs = p.dx;
+    // ||v||^2 <= 2 (N_i + N_j)
+    c_emb += 2.0 * 2.1 * dd * ((double)r + 1.01 * ((double)p.dx + 1.0)) * kU64 * 1.01;
+  }
+  im.ldy = round_up(im.rs, kChunk);
   im.Yc = ensure<float>(ws.Yc, (size_t)(p.n_pad * im.ldy));
   double* ny = ensure<double>(ws.ny, (size_t)p.n_pad);
-  HIPCHK(launch_center<double>(Y64, p.n, r, r, nullptr, im.Yc, im.ldy, p.n_pad, ny, st));
+  HIPCHK(launch_center<double>(Ys, p.n, im.rs, im.rs, nullptr, im.Yc, im.ldy, p.n_pad, ny, st));
   im.ty = ensure<float2>(ws.ty, (size_t)p.n_pad);
-  // FP64 embedding error: |E_64^2 - E^2| <= 4.02 gamma_{d+1} ||Pi||_F^2 (N_i + N_j)
-  // with ||Pi||_F^2 <= s + d <= 2.1 d for Algorithm 1's maps.
-  const double dd = (double)p.d;
-  const double c_emb = 4.02 * 2.1 * dd * (dd + 1.0) * kU64 * 1.01;
   HIPCHK(launch_row_terms(ny, screen_const(im.ldy), p.nx, c_emb, p.n_pad, im.ty, st));
   image_copies(ws, p, im, ny, p.nx, c_emb, st);
   im.Y64 = Y64;
@@ -617,6 +663,7 @@ static Images images_of_map(Workspace& ws, const Points& p, const float* Pi, int
 static Images images_given(Workspace& ws, const Points& p, const float* Y, int64_t r, hipStream_t st) {
   Images im;
   im.r = r;
+  im.rs = r;
   im.ldy = round_up(r, kChunk);
   double* muY = ensure<double>(ws.muY, (size_t)r);
   mean_rows(ws, Y, p.n, r, r, muY, st);
@@ -636,14 +683,15 @@ struct CertTimes {
   int screened = 0;   // FP8 screens among the calls
   int nprobe = 0;
   int refuted = 0;    // probes refuted by a witness pair
-  int32_t probe_r[48];
+  int32_t probe_r[48], probe_cols[48];
   double probe_delta[48], probe_ms[48];
   int32_t probe_gram[48];
 };
 
-static void log_probe(CertTimes& tm, int64_t r, const adagio_cert_t& c, double screen_ms, int gmode) {
+static void log_probe(CertTimes& tm, int64_t r, int64_t cols, const adagio_cert_t& c, double screen_ms, int gmode) {
   if (tm.nprobe < 48) {
     tm.probe_r[tm.nprobe] = (int32_t)r;
+    tm.probe_cols[tm.nprobe] = (int32_t)cols;
     tm.probe_delta[tm.nprobe] = c.max_distortion;
     tm.probe_ms[tm.nprobe] = screen_ms;
     tm.probe_gram[tm.nprobe] = gmode;
@@ -665,6 +713,7 @@ static void fill_stats(adagio_stats_t* s, const CertTimes& tm, int ncert, double
     s->probe_delta[k] = tm.probe_delta[k];
     s->probe_screen_ms[k] = tm.probe_ms[k];
     s->probe_gram[k] = tm.probe_gram[k];
+    s->probe_cols[k] = tm.probe_cols[k];
   }
   s->n_refuted = tm.refuted;
   s->t_total_ms = total_ms;
@@ -708,10 +757,11 @@ static float* gram_cache(Workspace& ws, const Points& p) {
 
 // A probe refuted by a witness pair: kind 3 from the pool (no screen), 4 from
 // a screen that stopped early (screen_ms: its partial time).
-static void log_refuted(CertTimes& tm, int64_t r, double w, int kind, double screen_ms) {
+static void log_refuted(CertTimes& tm, int64_t r, int64_t cols, double w, int kind, double screen_ms) {
   ++tm.refuted;
   if (tm.nprobe < 48) {
     tm.probe_r[tm.nprobe] = (int32_t)r;
+    tm.probe_cols[tm.nprobe] = (int32_t)cols;
     tm.probe_delta[tm.nprobe] = w;
     tm.probe_ms[tm.nprobe] = screen_ms;
     tm.probe_gram[tm.nprobe] = kind;
@@ -821,7 +871,7 @@ static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& i
         if (times) {
           const double sm = e_screen.ms();
           times->screen_ms += sm;
-          log_refuted(*times, im.r, w.v, 4, sm);
+          log_refuted(*times, im.r, im.rs, w.v, 4, sm);
         }
         return c;
       }
@@ -917,7 +967,7 @@ static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& i
     times->flagged += h.n_flagged;
     times->rescored += c.n_rescored;
     if (screen == ADAGIO_SCREEN_FP8) ++times->screened;
-    log_probe(*times, im.r, c, sm, gcache ? gmode : 0);
+    log_probe(*times, im.r, im.rs, c, sm, gcache ? gmode : 0);
   }
   return c;
 }
@@ -1300,7 +1350,7 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
       if (npool > 0) {
         const PairVal w = pool_witness(ws, p, Pi, r, npool, st);
         if (w.i >= 0 && w.v > eps + kWitnessMargin) {
-          log_refuted(tm, r, w.v, 3, 0.0);
+          log_refuted(tm, r, 0, w.v, 3, 0.0);
           return false;
         }
       }
@@ -1597,7 +1647,7 @@ int adagio_release(void) {
                       &ws.knNd64, &ws.knNq32, &ws.knNd32, &ws.knMax, &ws.knKeys, &ws.knFb, &ws.knCnt, &ws.knTau,
                       &ws.lam1, &ws.Vt1, &ws.colmap, &ws.xc64, &ws.pi64c,
                       &ws.colminmax, &ws.colkeep, &ws.pool, &ws.pooln, &ws.wvals, &ws.wparts, &ws.wcd,
-                      &ws.wV, &ws.wW, &ws.stopn, &ws.stopp};
+                      &ws.wV, &ws.wW, &ws.stopn, &ws.stopp, &ws.gfM, &ws.gfFail, &ws.gfZ};
     for (DevBuf* b : bufs) {
       if (b->p) HIPCHK(hipFree(b->p));
       b->p = nullptr;

@@ -46,6 +46,12 @@ hipError_t launch_eig_sort(const double* A, const double* W, int m, int d, doubl
 hipError_t launch_scatter_axes(const double* lam1, const double* Vt1, const int* idx, int d1, int d, double* lam,
                                double* Vt, hipStream_t st);
 
+// k_chol.hip: in-place Cholesky factor (lower, strict upper zeroed) of an
+// SPD m x m column-major FP64 matrix, m <= chol_max_m(); *fail = 1 on a
+// non-positive pivot.
+hipError_t launch_cholesky(double* A, int m, int* fail, hipStream_t st);
+int chol_max_m();
+
 // k_eig_block.hip
 hipError_t launch_bj_round(const double* A, double* A2, double* W, double* Uall, double* Sall, int m, int t,
                            double thr, int* rot_count, hipStream_t st);
