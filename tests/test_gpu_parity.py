@@ -152,6 +152,33 @@ def test_max_distortion_parity_c1(gpu_lib):
         assert got["n_pairs"] == 2000 * 1999 // 2
 
 
+@pytest.mark.parametrize("r", [266, 267, 400, 784])
+@pytest.mark.parametrize("screen", ["f32", "bf16x3"])
+def test_certify_map_through_gram_factor(gpu_lib, r, screen):
+    """A map with r >= d' + 32 rows (d' = 235 non-constant coordinates) is
+    screened over d' columns, z = L^T x with L L^T the Cholesky factor of the
+    map's d' x d' Gram; r = d' + 31 still takes the r images.  The
+    certificate is the oracle's either way."""
+    X = gen.mnist_shaped(n=2500)
+    dx = int((X.max(axis=0) != X.min(axis=0)).sum())
+    assert dx == 235
+    _, _, _, Vt = opca.pca(X)
+    Pi32 = embedding.adagio_map(Vt, r, gen.JL_SEED).astype(np.float32)
+    got = gpu_lib.certify_map(dev(X), dev(Pi32), screen=screen, with_stats=True)
+    st = got.pop("stats")
+    assert st["probe_cols"] == [dx if r >= dx + 32 else r]
+    assert_cert_parity(got, oracle_cert_of_map(X, Pi32))
+
+
+def test_certify_gaussian_map_through_gram_factor(gpu_lib):
+    """Any linear map, not only Algorithm 1's: Gaussian entries, r = 300."""
+    X = gen.mnist_shaped(n=1500)
+    Pi32 = (np.random.default_rng(5).standard_normal((300, X.shape[1])) / np.sqrt(300)).astype(np.float32)
+    got = gpu_lib.certify_map(dev(X), dev(Pi32), with_stats=True)
+    assert got.pop("stats")["probe_cols"] == [235]
+    assert_cert_parity(got, oracle_cert_of_map(X, Pi32))
+
+
 def test_certify_map_parity_c1(gpu_lib):
     X = gen.low_rank_pixels()
     _, _, _, Vt = opca.pca(X)
