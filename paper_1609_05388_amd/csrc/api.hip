@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -70,7 +71,8 @@ struct Workspace {
   // the caller's stream: the fit's point-Gram fill during its PCA
   hipStream_t aux = nullptr;
   hipStream_t aux2 = nullptr;  // non-blocking, all CUs: the fit's exact PCA beside the fill
-  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_t0 = nullptr, ev_t1 = nullptr, ev_pca = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_t0 = nullptr, ev_t1 = nullptr, ev_pca = nullptr,
+             ev_cov = nullptr;
   bool checked = false;
 };
 
@@ -429,8 +431,10 @@ static void randomized_axes(Workspace& ws, const double* C, int m, int64_t d, in
   HIPCHK(launch_gemm_nn(V, ell, ell, ell, Qt, d, d, Vt_out, d, st));
 }
 
+// after_cov (optional) runs once the covariance is queued on st, before the
+// eigensolver.
 static Axes principal_axes(Workspace& ws, const Points& p, hipStream_t st, double* lam_out = nullptr,
-                           double* Vt_out = nullptr) {
+                           double* Vt_out = nullptr, const std::function<void()>& after_cov = {}) {
   const int64_t d = p.d;
   // block Jacobi works on m = d rounded up to a multiple of two index blocks
   Axes ax;
@@ -439,6 +443,7 @@ static Axes principal_axes(Workspace& ws, const Points& p, hipStream_t st, doubl
   if (p.dx == d) {
     const int m = (int)round_up(d, 2 * bj_block());
     double* A = covariance64(ws, p, m, st);
+    if (after_cov) after_cov();
     ax.sweeps = jacobi_eig(ws, A, m, d, ax.lam, ax.Vt, st);
     return ax;
   }
@@ -452,7 +457,10 @@ static Axes principal_axes(Workspace& ws, const Points& p, hipStream_t st, doubl
   if (d1 > 0) {
     const int m1 = (int)round_up(d1, 2 * bj_block());
     double* A1 = covariance64(ws, p, m1, st);
+    if (after_cov) after_cov();
     ax.sweeps = jacobi_eig(ws, A1, m1, d1, lam1, Vt1, st);
+  } else if (after_cov) {
+    after_cov();
   }
   const int* idx = p.colmap;
   HIPCHK(launch_scatter_axes(lam1, Vt1, idx, (int)d1, (int)d, ax.lam, ax.Vt, st));
@@ -1063,7 +1071,7 @@ static void ensure_streams(Workspace& ws) {
     }
   }
   if (!ws.aux2) HIPCHK(hipStreamCreateWithFlags(&ws.aux2, hipStreamNonBlocking));
-  for (hipEvent_t* e : {&ws.ev_in, &ws.ev_out, &ws.ev_pca}) {
+  for (hipEvent_t* e : {&ws.ev_in, &ws.ev_out, &ws.ev_pca, &ws.ev_cov}) {
     if (!*e) HIPCHK(hipEventCreateWithFlags(e, hipEventDisableTiming));
   }
   for (hipEvent_t* e : {&ws.ev_t0, &ws.ev_t1}) {
@@ -1072,14 +1080,15 @@ static void ensure_streams(Workspace& ws) {
 }
 
 // Point Gram of every tile into the fit's cache, on ws.aux after the work
-// already queued on st (the centred copies); st waits for it with ws.ev_out
-// before its first screen.  The points' Gram does not depend on the map, so
-// it overlaps the PCA, which leaves most of the GPU idle.  The fill's kernel
-// time is read later from ws.ev_t0 / ev_t1.
-static void gram_fill_async(Workspace& ws, const Points& p, int screen, float* gcache, hipStream_t st) {
+// already queued on `after` (at least the centred copies; in a fit with the
+// exact PCA also its covariance); the caller's stream waits for it with
+// ws.ev_out before its first screen.  The points' Gram does not depend on the
+// map, so it overlaps the PCA's eigensolver, which leaves most of the GPU
+// idle.  The fill's kernel time is read later from ws.ev_t0 / ev_t1.
+static void gram_fill_async(Workspace& ws, const Points& p, int screen, float* gcache, hipStream_t after) {
   ensure_streams(ws);
-  HIPCHK(hipEventRecord(ws.ev_in, st));
-  HIPCHK(hipStreamWaitEvent(ws.aux, ws.ev_in, 0));
+  HIPCHK(hipEventRecord(ws.ev_cov, after));
+  HIPCHK(hipStreamWaitEvent(ws.aux, ws.ev_cov, 0));
   HIPCHK(hipEventRecord(ws.ev_t0, ws.aux));
   const int NT = (int)(p.n_pad / kTile);
   const int64_t ntiles = (int64_t)NT * (NT + 1) / 2;
@@ -1286,11 +1295,10 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     // The search's screens share a point-Gram cache (when it fits), filled on
     // the second stream while the PCA runs.
     float* gcache = gram_cache(ws, p);
-    bool gwait = false;
-    if (gcache) {
-      gram_fill_async(ws, p, screen, gcache, st);
-      gwait = true;
-    }
+    const bool gwait_pca = gcache && family != ADAGIO_MAP_JL && pca == ADAGIO_PCA_EXACT;
+    bool gwait = gcache != nullptr;
+    // without the exact PCA to run beside, the fill starts at once
+    if (gcache && !gwait_pca) gram_fill_async(ws, p, screen, gcache, st);
     Axes ax;                         // the JL-only family needs no PCA
     const bool randomized = pca == ADAGIO_PCA_RANDOMIZED && family != ADAGIO_MAP_JL;
     const int mc = (int)round_up(d, 2 * bj_block());
@@ -1300,11 +1308,16 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
       ax.lam = ensure<double>(ws.lam, (size_t)d);
       ax.Vt = ensure<double>(ws.Vt, (size_t)(d * d));
     } else if (family != ADAGIO_MAP_JL) {
-      if (gwait) {
-        // beside the fill: on the non-blocking second stream, after the
-        // centred copies (ws.ev_in), and st continues after it
+      if (gwait_pca) {
+        // beside the fill: on the non-blocking third stream after the
+        // centred copies, the fill starting once the covariance (a large
+        // library GEMM) is done, so that it runs beside the eigensolver's
+        // small kernels only; st continues after the PCA
+        ensure_streams(ws);
+        HIPCHK(hipEventRecord(ws.ev_in, st));
         HIPCHK(hipStreamWaitEvent(ws.aux2, ws.ev_in, 0));
-        ax = principal_axes(ws, p, ws.aux2);
+        ax = principal_axes(ws, p, ws.aux2, nullptr, nullptr,
+                            [&] { gram_fill_async(ws, p, screen, gcache, ws.aux2); });
         HIPCHK(hipEventRecord(ws.ev_pca, ws.aux2));
         HIPCHK(hipStreamWaitEvent(st, ws.ev_pca, 0));
       } else {
@@ -1664,7 +1677,7 @@ int adagio_release(void) {
         *q = nullptr;
       }
     }
-    for (hipEvent_t* e : {&ws.ev_in, &ws.ev_out, &ws.ev_t0, &ws.ev_t1, &ws.ev_pca}) {
+    for (hipEvent_t* e : {&ws.ev_in, &ws.ev_out, &ws.ev_t0, &ws.ev_t1, &ws.ev_pca, &ws.ev_cov}) {
       if (*e) (void)hipEventDestroy(*e);
       *e = nullptr;
     }
