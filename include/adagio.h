@@ -203,7 +203,12 @@ int adagio_max_distortion(const float* X, int64_t n, int64_t d, const float* Y, 
 
 /* a6-a8.  Certificate of eq. (3) for the linear map Pi (r x d FP32, device)
  * applied exactly: images are formed in FP64 from the FP32 entries of X and
- * Pi, so the result is the distortion of Pi itself.  Synchronises `stream`. */
+ * Pi, so the result is the distortion of Pi itself.  When Pi has at least
+ * d' + 32 rows (d' = coordinates of X that are not constant), the screen runs
+ * over d' columns z = L^T x, L L^T = Pi'^T Pi' (the Cholesky factor of the
+ * map's Gram over those coordinates), with the factor's rounding in its
+ * bounds; the exact values are still taken from Pi x.  The bounds assume
+ * ||Pi||_F^2 <= 2.1 d, as for Algorithm 1's maps.  Synchronises `stream`. */
 int adagio_certify_map(const float* X, int64_t n, int64_t d, const float* Pi, int32_t r,
                        const adagio_opts_t* opts, adagio_cert_t* cert_out, void* stream);
 
