@@ -207,8 +207,8 @@ int adagio_max_distortion(const float* X, int64_t n, int64_t d, const float* Y, 
  * d' + 32 rows (d' = coordinates of X that are not constant), the screen runs
  * over d' columns z = L^T x, L L^T = Pi'^T Pi' (the Cholesky factor of the
  * map's Gram over those coordinates), with the factor's rounding in its
- * bounds; the exact values are still taken from Pi x.  The bounds assume
- * ||Pi||_F^2 <= 2.1 d, as for Algorithm 1's maps.  Synchronises `stream`. */
+ * bounds; the exact values are still taken from Pi x.  Synchronises
+ * `stream`. */
 int adagio_certify_map(const float* X, int64_t n, int64_t d, const float* Pi, int32_t r,
                        const adagio_opts_t* opts, adagio_cert_t* cert_out, void* stream);
 

@@ -643,18 +643,26 @@ static Images images_of_map(Workspace& ws, const Points& p, const float* Pi, int
   im.r = r;
   double* Y64 = ensure<double>(ws.Y64, (size_t)(p.n * r));
   embed64(ws, p, Pi, r, Y64, st);
-  // FP64 embedding error: |E_64^2 - E^2| <= 4.02 gamma_{d+1} ||Pi||_F^2 (N_i + N_j)
-  // with ||Pi||_F^2 <= s + d <= 2.1 d for Algorithm 1's maps (and
-  // ||L||_F^2 = trace(M) for the factor's images).
-  const double dd = (double)p.d;
-  double c_emb = 4.02 * 2.1 * dd * (dd + 1.0) * kU64 * 1.01;
+  // FP64 embedding error: |E_64^2 - E^2| <= 4.02 gamma_{d'+1} ||Pi'||_F^2 (N_i + N_j)
+  // over the d' non-constant coordinates (and ||L||_F^2 = trace(M) <=
+  // ||Pi'||_F^2 for the factor's images); ||Pi'||_F from the FP64 values of
+  // Pi's columns (library nrm2, inflated far beyond its rounding).
+  double pf2 = 0.0;
+  if (p.dx > 0) {
+    double nrm = 0.0;
+    BLASCHK(rocblas_dnrm2(blas_on(ws, st), (rocblas_int)(p.dx * r), static_cast<const double*>(ws.pi64c.p), 1,
+                          &nrm));
+    pf2 = nrm * nrm * (1.0 + 1e-8);
+  }
+  const double dx1 = (double)p.dx + 1.0;
+  double c_emb = 4.02 * pf2 * dx1 * kU64 * 1.01;
   const double* Ys = Y64;
   im.rs = r;
   if (const double* Z = gram_factor_images(ws, p, r, st)) {
     Ys = Z;
     im.rs = p.dx;
     // ||v||^2 <= 2 (N_i + N_j)
-    c_emb += 2.0 * 2.1 * dd * ((double)r + 1.01 * ((double)p.dx + 1.0)) * kU64 * 1.01;
+    c_emb += 2.0 * pf2 * ((double)r + 1.01 * dx1) * kU64 * 1.01;
   }
   im.ldy = round_up(im.rs, kChunk);
   im.Yc = ensure<float>(ws.Yc, (size_t)(p.n_pad * im.ldy));
