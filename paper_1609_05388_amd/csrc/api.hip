@@ -817,7 +817,7 @@ static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& i
 
   TileRec* recs = ensure<TileRec>(ws.recs, (size_t)v.ntiles);
   const int nparts = 256;
-  TileRec* tparts = ensure<TileRec>(ws.tparts, nparts);
+  TileRec* tparts = ensure<TileRec>(ws.tparts, nparts + 1);
   int2* seeds = ensure<int2>(ws.seeds, 2);
   PairVal* seedv = ensure<PairVal>(ws.seedv, 2);
   uint32_t* list = ensure<uint32_t>(ws.list, (size_t)v.ntiles);

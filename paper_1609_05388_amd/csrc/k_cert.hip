@@ -298,8 +298,10 @@ __global__ void k_best_reset(CertDev* __restrict__ cd) {
 // ---------------------------------------------------------------- launchers
 hipError_t launch_seeds(const TileRec* recs, int64_t ntiles, TileRec* part, int nparts, int2* seeds, CertDev* cd,
                         hipStream_t st) {
+  // nparts block records, reduced again by one block into part[nparts]
   k_tiles_reduce<<<(unsigned)nparts, 256, 0, st>>>(recs, ntiles, part);
-  k_seeds<<<1, 64, 0, st>>>(part, nparts, seeds, cd);
+  k_tiles_reduce<<<1, 256, 0, st>>>(part, nparts, part + nparts);
+  k_seeds<<<1, 64, 0, st>>>(part + nparts, 1, seeds, cd);
   return hipGetLastError();
 }
 

@@ -25,41 +25,37 @@ constexpr int kCholMaxM = 600;   // LDS panel: kCholMaxM x CB doubles
 // A: m x m FP64, column-major (ld m), symmetric positive definite; on return
 // its lower triangle holds L (A = L L^T) and its strict upper triangle zero.
 // *fail = 1 (set, never cleared) on a pivot that is not positive and finite.
+// Per panel column: every thread takes the pivot from the diagonal (the same
+// value for all, so the exit on a bad pivot is uniform), the scaled column
+// goes to lc, then the panel's later columns are updated from lc (two
+// barriers per column).  The trailing update gives each thread four rows of
+// one column, so a panel value of that column serves four products.
 __global__ __launch_bounds__(1024) void k_cholesky(double* __restrict__ A, int m, int* __restrict__ fail) {
   __shared__ double P[kCholMaxM * CB];   // panel, P[(i - j0) + c * rows]
-  __shared__ double piv;
-  __shared__ int bad;
+  __shared__ double lc[kCholMaxM];       // the current panel column, scaled
   const int t = threadIdx.x;
-  if (t == 0) bad = 0;
-  __syncthreads();
-  for (int j0 = 0; j0 < m; j0 += CB) {
+  bool bad = false;
+  for (int j0 = 0; j0 < m && !bad; j0 += CB) {
     const int nb = min(CB, m - j0), rows = m - j0;
     for (int e = t; e < rows * nb; e += 1024) {
       const int c = e / rows, i = e - c * rows;
       P[e] = A[(int64_t)(j0 + c) * m + j0 + i];
     }
     __syncthreads();
-    // factor the panel in LDS
     for (int c = 0; c < nb; ++c) {
-      if (t == 0) {
-        const double a = P[c + c * rows];
-        if (!(a > 0.0) || !isfinite(a)) {
-          bad = 1;
-          piv = 1.0;
-        } else {
-          piv = sqrt(a);
-        }
-        P[c + c * rows] = piv;
+      const double a = P[c + c * rows];
+      if (!(a > 0.0) || !isfinite(a)) {   // the same value in every thread
+        bad = true;
+        break;
       }
+      const double piv = sqrt(a);
+      for (int i = c + t; i < rows; i += 1024) lc[i] = i == c ? piv : P[i + c * rows] / piv;
       __syncthreads();
-      if (bad) break;   // uniform: every thread reads it after the barrier
-      for (int i = c + 1 + t; i < rows; i += 1024) P[i + c * rows] /= piv;
-      __syncthreads();
-      // panel columns c + 1 .. nb - 1, rows at or below the diagonal
+      for (int i = c + t; i < rows; i += 1024) P[i + c * rows] = lc[i];
       const int w = nb - c - 1;
       for (int e = t; e < w * rows; e += 1024) {
         const int cc = c + 1 + e / rows, i = e - (e / rows) * rows;
-        if (i >= cc) P[i + cc * rows] -= P[i + c * rows] * P[cc + c * rows];
+        if (i >= cc) P[i + cc * rows] -= lc[i] * lc[cc];
       }
       __syncthreads();
     }
@@ -68,15 +64,27 @@ __global__ __launch_bounds__(1024) void k_cholesky(double* __restrict__ A, int m
       const int c = e / rows, i = e - c * rows;
       A[(int64_t)(j0 + c) * m + j0 + i] = P[e];
     }
-    // trailing lower triangle: columns k and rows i >= k past the panel
-    const int w = rows - nb;
-    for (int64_t e = t; e < (int64_t)w * w; e += 1024) {
-      const int kc = (int)(e / w), ir = (int)(e - (int64_t)kc * w);
-      if (ir < kc) continue;
-      const int pi = nb + ir, pk = nb + kc;   // panel rows of i and k
-      double s = 0.0;
-      for (int c = 0; c < nb; ++c) s = fma(P[pi + c * rows], P[pk + c * rows], s);
-      A[(int64_t)(j0 + nb + kc) * m + j0 + nb + ir] -= s;
+    // trailing lower triangle: column kc, rows 4 q .. 4 q + 3 (those >= kc)
+    const int w = rows - nb, wq = (w + 3) / 4;
+    for (int64_t e = t; e < (int64_t)w * wq; e += 1024) {
+      const int kc = (int)(e / wq), i0 = 4 * (int)(e - (int64_t)kc * wq);
+      if (i0 + 3 < kc) continue;
+      const int pk = nb + kc;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      const bool v1 = i0 + 1 < w, v2 = i0 + 2 < w, v3 = i0 + 3 < w;
+      for (int c = 0; c < nb; ++c) {
+        const double* col = P + c * rows + nb + i0;
+        const double bk = P[pk + c * rows];
+        s0 = fma(col[0], bk, s0);
+        if (v1) s1 = fma(col[1], bk, s1);
+        if (v2) s2 = fma(col[2], bk, s2);
+        if (v3) s3 = fma(col[3], bk, s3);
+      }
+      double* out = A + (int64_t)(j0 + nb + kc) * m + j0 + nb + i0;
+      if (i0 >= kc) out[0] -= s0;
+      if (v1 && i0 + 1 >= kc) out[1] -= s1;
+      if (v2 && i0 + 2 >= kc) out[2] -= s2;
+      if (v3 && i0 + 3 >= kc) out[3] -= s3;
     }
     __syncthreads();
   }

@@ -304,31 +304,57 @@ __device__ inline uint32_t tile_key(const TileRec& r) {
   return __float_as_uint(fmaxf(u, 0.0f));   // non-negative floats order like their bits
 }
 
-// Histogram of the keys' top 16 bits.
+// Histogram of the keys' top 16 bits.  Neighbouring tiles' keys fall in few
+// buckets, so the lanes of a wave that share a bucket add their count with
+// one atomic: the first pending lane's bucket is broadcast, the lanes holding
+// it are counted by a ballot, and they leave the loop.
 __global__ void k_key_hist(const TileRec* __restrict__ recs, int64_t ntiles, uint32_t* __restrict__ hist) {
-  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * 256)
-    atomicAdd(&hist[tile_key(recs[t]) >> 16], 1u);
+  const int lane = threadIdx.x & 63;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * 256) {
+    const uint32_t b = tile_key(recs[t]) >> 16;
+    bool pending = true;
+    for (;;) {
+      const uint64_t pend = __ballot(pending);
+      if (pend == 0) break;
+      const int leader = __ffsll((unsigned long long)pend) - 1;
+      const uint32_t lb = (uint32_t)__shfl((int)b, leader, 64);
+      const uint64_t same = __ballot(pending && b == lb);
+      if (lane == leader) atomicAdd(&hist[lb], (uint32_t)__popcll(same));
+      if (b == lb) pending = false;
+    }
+  }
 }
 
 // Largest bucket b such that the tiles in buckets >= b number at least K
 // (bucket 0, all tiles, if fewer); when a tied boundary bucket would take the
 // count above kmax, b + 1 (fewer than K tiles, none of that bucket).
-// out[0] = b.  1024 threads, 64 buckets each.
+// out[0] = b.  1024 threads, 64 buckets each: segment sums, their suffix sums
+// (a parallel scan), the boundary segment, then its 64 buckets.
 __global__ __launch_bounds__(1024) void k_key_select(const uint32_t* __restrict__ hist, uint32_t K, uint32_t kmax,
                                                      uint32_t* __restrict__ out) {
-  __shared__ uint32_t seg[1024];
+  __shared__ uint32_t suf[1025];   // suf[g] = tiles in segments >= g; suf[1024] = 0
+  __shared__ int gstar;
   const int t = threadIdx.x;
   uint32_t s = 0;
   for (int k = 0; k < 64; ++k) s += hist[t * 64 + k];
-  seg[t] = s;
+  suf[t] = s;
+  if (t == 0) {
+    suf[1024] = 0;
+    gstar = 0;
+  }
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const uint32_t v = suf[t] + (t + o < 1024 ? suf[t + o] : 0u);
+    __syncthreads();
+    suf[t] = v;
+    __syncthreads();
+  }
+  // the largest segment g >= 1 whose suffix reaches K (suffixes do not grow with g)
+  if (t >= 1 && suf[t] >= K && suf[t + 1] < K) gstar = t;
   __syncthreads();
   if (t != 0) return;
-  uint64_t acc = 0;
-  int g = 1023;
-  for (; g > 0; --g) {
-    if (acc + seg[g] >= K) break;
-    acc += seg[g];
-  }
+  const int g = gstar;
+  uint64_t acc = suf[g + 1];
   int b = g * 64 + 63;
   for (; b > g * 64; --b) {
     if (acc + hist[b] >= K) break;

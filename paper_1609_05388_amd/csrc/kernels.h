@@ -101,6 +101,7 @@ hipError_t launch_pairs_screen_bf16(const PairsViewB& v, TileRec* recs, float* g
 hipError_t launch_pairs_gram_fill_bf16(const PairsViewB& v, float* gcache, hipStream_t st);
 
 // k_cert.hip
+// part: nparts + 1 records of scratch.
 hipError_t launch_seeds(const TileRec* recs, int64_t ntiles, TileRec* part, int nparts, int2* seeds, CertDev* cd,
                         hipStream_t st);
 template <typename TY>
