@@ -170,6 +170,20 @@ def test_certify_map_through_gram_factor(gpu_lib, r, screen):
     assert_cert_parity(got, oracle_cert_of_map(X, Pi32))
 
 
+def test_certify_map_singular_gram_falls_back(gpu_lib):
+    """r >= d' + 32 rows, but the map is zero on one non-constant
+    coordinate: that row and column of its Gram are exact zeros, so the
+    factor meets an exactly zero pivot and fails, and the screen takes the r
+    images; the certificate is still the oracle's."""
+    X = gen.mnist_shaped(n=1200)
+    rng = np.random.default_rng(9)
+    Pi32 = (rng.standard_normal((300, X.shape[1])) / np.sqrt(300)).astype(np.float32)
+    Pi32[:, np.flatnonzero(X.std(axis=0) > 0)[17]] = 0.0
+    got = gpu_lib.certify_map(dev(X), dev(Pi32), with_stats=True)
+    assert got.pop("stats")["probe_cols"] == [300]
+    assert_cert_parity(got, oracle_cert_of_map(X, Pi32))
+
+
 def test_certify_gaussian_map_through_gram_factor(gpu_lib):
     """Any linear map, not only Algorithm 1's: Gaussian entries, r = 300."""
     X = gen.mnist_shaped(n=1500)
