@@ -231,7 +231,9 @@ int adagio_certify_map(const float* X, int64_t n, int64_t d, const float* Pi, in
  * free device memory, and the certificate is the same either way.  The fit
  * fills it with one Gram-only screen launch on a second, non-blocking stream
  * of default priority while the PCA runs on `stream`; `stream` waits for it
- * before its first screen.  opts->family = ADAGIO_MAP_PCA or ADAGIO_MAP_JL runs the same search
+ * before its first screen.  An FP8 fit fills the BF16 split Gram, which its
+ * FP8 screens (with unit point scales) and its BF16 split certificates both
+ * load.  opts->family = ADAGIO_MAP_PCA or ADAGIO_MAP_JL runs the same search
  * over the PCA-only or JL-only maps of Table 2 (at r = d: V^T, resp. the
  * identity); the learned search is for Algorithm 1's maps only.
  * opts->pca = ADAGIO_PCA_RANDOMIZED takes the principal directions from

@@ -183,6 +183,10 @@ struct Points {
   unsigned char* Xq = nullptr;
   float* sx = nullptr;
   double* nxq = nullptr;
+  // FP8 screens of a fit load the BF16 split point Gram from the fit's cache
+  // (unscaled, of the centred rows): their row terms take N = ||a||^2 and unit
+  // point scales
+  bool xgram_split = false;
 };
 
 // Column means (FP64) of the n x m rows of A.  With colmap, also the columns
@@ -597,7 +601,8 @@ static void image_copies(Workspace& ws, const Points& p, Images& im, const doubl
     double* nyq = ensure<double>(ws.nyq, (size_t)p.n_pad);
     HIPCHK(launch_quant_fp8(im.Yc, p.n_pad, im.rs, im.ldy, im.ldyq, im.Yq, sy, nyq, st));
     im.q8 = ensure<float4>(ws.q8terms, (size_t)p.n_pad);
-    HIPCHK(launch_fp8_terms(p.nxq, nyq, p.sx, sy, p.n_pad, im.q8, st));
+    HIPCHK(launch_fp8_terms(p.xgram_split ? p.nx : p.nxq, nyq, p.xgram_split ? nullptr : p.sx, sy, p.n_pad, im.q8,
+                            st));
   }
 }
 
@@ -1100,15 +1105,14 @@ static void gram_fill_async(Workspace& ws, const Points& p, int screen, float* g
   HIPCHK(hipEventRecord(ws.ev_t0, ws.aux));
   const int NT = (int)(p.n_pad / kTile);
   const int64_t ntiles = (int64_t)NT * (NT + 1) / 2;
-  if (screen == ADAGIO_SCREEN_BF16X3) {
+  if (screen == ADAGIO_SCREEN_BF16X3 || screen == ADAGIO_SCREEN_FP8) {
+    // an FP8 fit's screens and its BF16 split certificates share this one
     PairsViewB vb;
     vb.Xb = p.Xb; vb.ldx = (int)p.ldxb;
     vb.Yb = p.Xb; vb.ldy = 0;
     vb.tx = p.txb; vb.ty = p.txb;
     vb.n = (int)p.n; vb.NT = NT; vb.ntiles = ntiles;
     HIPCHK(launch_pairs_gram_fill_bf16(vb, gcache, ws.aux));
-  } else if (screen == ADAGIO_SCREEN_FP8) {
-    HIPCHK(launch_pairs_screen_fp8(p.Xq, (int)p.ldxq, p.Xq, 0, nullptr, (int)p.n, NT, nullptr, gcache, 1, ws.aux));
   } else {
     PairsView v;
     v.X = p.Xc; v.ldx = (int)p.ldx;
@@ -1303,6 +1307,7 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     // The search's screens share a point-Gram cache (when it fits), filled on
     // the second stream while the PCA runs.
     float* gcache = gram_cache(ws, p);
+    p.xgram_split = gcache && screen == ADAGIO_SCREEN_FP8;
     const bool gwait_pca = gcache && family != ADAGIO_MAP_JL && pca == ADAGIO_PCA_EXACT;
     bool gwait = gcache != nullptr;
     // without the exact PCA to run beside, the fill starts at once
@@ -1376,7 +1381,9 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
         }
       }
       Images im = images_of_map(ws, p, Pi, r, st);
-      const int gmode = scr == screen && gcache ? 2 : 0;
+      // the search's own screens, and in an FP8 fit its BF16 split
+      // certificates, load the fit's point-Gram cache
+      const int gmode = gcache && (scr == screen || (screen == ADAGIO_SCREEN_FP8 && scr == ADAGIO_SCREEN_BF16X3)) ? 2 : 0;
       if (gmode == 2 && gwait) {
         HIPCHK(hipStreamWaitEvent(st, ws.ev_out, 0));
         gwait = false;

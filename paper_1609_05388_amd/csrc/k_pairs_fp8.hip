@@ -88,12 +88,13 @@ __global__ void k_quant_fp8(const float* __restrict__ src, int64_t n_pad, int64_
   }
 }
 
-// Per-row epilogue terms (N_x, N_y, -2 s_x, -2 s_y).
+// Per-row epilogue terms (N_x, N_y, -2 s_x, -2 s_y); sx null: unit point
+// scales (the point Gram then comes unscaled from a BF16 split cache).
 __global__ void k_fp8_terms(const double* __restrict__ nx, const double* __restrict__ ny,
                             const float* __restrict__ sx, const float* __restrict__ sy, int64_t n_pad,
                             float4* __restrict__ t) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n_pad) t[i] = make_float4((float)nx[i], (float)ny[i], -2.0f * sx[i], -2.0f * sy[i]);
+  if (i < n_pad) t[i] = make_float4((float)nx[i], (float)ny[i], sx ? -2.0f * sx[i] : -2.0f, -2.0f * sy[i]);
 }
 
 struct PairsArgsF {

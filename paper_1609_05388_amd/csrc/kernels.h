@@ -157,6 +157,7 @@ hipError_t launch_sym_eigvals(const double* A, int m, int lda, double* lam, hipS
 // lds): q (ldq bytes per row, zero padded), scale s_i, N_i = s_i^2 |q_i|^2.
 hipError_t launch_quant_fp8(const float* src, int64_t n_pad, int64_t m, int64_t lds, int64_t ldq, unsigned char* q,
                             float* scale, double* norm2, hipStream_t st);
+// sx null: unit point scales (point Gram loaded unscaled from a BF16 split cache).
 hipError_t launch_fp8_terms(const double* nx, const double* ny, const float* sx, const float* sy, int64_t n_pad,
                             float4* t, hipStream_t st);
 // Estimated q extremes per tile (ldx, ldy multiples of fp8_chunk()); gcache /
