@@ -3,7 +3,7 @@
  * ADAGIO (Blasiok & Tsourakakis, arXiv 1609.05388) maps each point w of a
  * cloud T in R^d to (P w, S (w - P^T P w)), where P holds the top principal
  * directions of the centred cloud and S is a +-1/sqrt(k) Johnson-Lindenstrauss
- * matrix (Algorithm 1), and judges the map by its distortion: the largest,
+ * matrix (Algorithm 1), and rates the map by its distortion: the largest,
  * over all pairs, of | ||f(x) - f(y)|| / ||x - y|| - 1 | (eqs. 2 and 3).
  *
  * Conventions shared by every entry point
