@@ -104,10 +104,12 @@ typedef struct adagio_stats {
     int32_t r_predicted;     /* learned search: the network's r (0 otherwise)     */
     int64_t n_flagged_tiles; /* summed over certificates                          */
     int64_t n_rescored;      /* summed over certificates                          */
-    int32_t n_probes;        /* certificates logged below, in call order (<= 48)  */
+    int32_t n_probes;        /* probes logged below, in call order (<= 48): the
+                                certificates and, in a fit, the refuted probes    */
     int32_t n_screened;      /* how many of the certificates were FP8 screens     */
-    int32_t probe_r[48];     /* target dimension of each certificate              */
-    double probe_delta[48];  /* its exact max distortion                          */
+    int32_t probe_r[48];     /* target dimension of each probe                    */
+    double probe_delta[48];  /* its exact max distortion (kinds 3 and 4 below: the
+                                witness pair's exact distortion)                  */
     double probe_screen_ms[48]; /* its all-pairs screen kernel time (device events) */
     int32_t probe_gram[48];  /* its point Gram: 0 computed, 1 computed and stored in the
                                 fit's point-Gram cache (no longer used by fits, which fill
@@ -137,7 +139,7 @@ typedef struct adagio_opts {
     int32_t pca;             /* ADAGIO_PCA_*; default EXACT (fit only)            */
     int32_t pca_iters;       /* randomized PCA: power iterations q (>= 0)         */
     int32_t no_witness;      /* fit: 1 = certify every probe in full (no refutation by
-                                witness pairs); default 0                         */
+                                witness pairs, no early stop); default 0          */
 } adagio_opts_t;
 
 /* a1-a3.  Principal axes of the centred cloud (Sec. 2 PCA paragraph, eq. 4;
