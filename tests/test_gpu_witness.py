@@ -10,6 +10,7 @@ import torch
 
 from oracle import certificate as ocert
 from oracle import embedding as oemb
+from oracle import search
 from paper_1609_05388_amd import gen
 
 pytestmark = pytest.mark.gpu
@@ -80,3 +81,24 @@ def test_witness_values_against_oracle(gpu_lib):
         Pi = gpu_lib.project_axes(Vt, r, gen.JL_SEED).cpu().numpy()
         want = ocert.certify(X, oemb.embed(X, Pi))
         assert eps < dl <= want["max"] + 1e-9, r
+
+
+@pytest.mark.parametrize("n,d", [(2, 1), (2, 5), (3, 2), (7, 4), (130, 3)])
+@pytest.mark.parametrize("screen", ["f32", "bf16x3", "fp8"])
+def test_witness_search_tiny_clouds(gpu_lib, n, d, screen):
+    """Clouds of one tile (or a single pair): a pool of at most a few pairs,
+    early stops on tiny screens, the cache filled with one or two tiles.  The
+    search visits the oracle's probes and ends at its r and maximum."""
+    rng = np.random.default_rng(100 * n + d)
+    X = (rng.standard_normal((n, d)) * np.linspace(1.0, 0.2, d)).astype(np.float32)
+    got = gpu_lib.fit(dev(X), 0.1, gen.JL_SEED, screen=screen)
+    ref = gpu_lib.fit(dev(X), 0.1, gen.JL_SEED, screen=screen, witness=False)
+    assert got["r"] == ref["r"] and torch.equal(got["Pi"], ref["Pi"]) and got["cert"] == ref["cert"]
+    want = search.fit(X, 0.1, gen.JL_SEED)
+    near = [abs(v - 0.1) for _, v in want["probes"]]
+    if not near or min(near) > 1e-5:
+        assert got["r"] == want["r"]
+        assert abs(got["cert"]["max_distortion"] - want["cert"]["max"]) <= 1e-5
+        # the same probes (an FP8 fit then certifies its result once more)
+        wr = [r for r, _ in want["probes"]]
+        assert got["stats"]["probe_r"][:len(wr)] == wr
