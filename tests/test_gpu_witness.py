@@ -35,11 +35,14 @@ def cloud(name):
     return gen.mnist_shaped(n=3000)
 
 
-@pytest.mark.parametrize("name,eps,screen", CASES)
-def test_witness_search_same_result(gpu_lib, name, eps, screen):
+@pytest.mark.parametrize("name,eps,screen,family", [c + ("adagio",) for c in CASES] + [
+    ("mnist", 0.1, "f32", "pca"),      # Table 2's PCA-only maps
+    ("c1", 0.2, "f32", "jl"),          # JL-only maps: no PCA, the cache fill starts at once
+])
+def test_witness_search_same_result(gpu_lib, name, eps, screen, family):
     X = cloud(name)
-    a = gpu_lib.fit(dev(X), eps, gen.JL_SEED, screen=screen)
-    b = gpu_lib.fit(dev(X), eps, gen.JL_SEED, screen=screen, witness=False)
+    a = gpu_lib.fit(dev(X), eps, gen.JL_SEED, screen=screen, family=family)
+    b = gpu_lib.fit(dev(X), eps, gen.JL_SEED, screen=screen, family=family, witness=False)
     assert a["r"] == b["r"]
     assert torch.equal(a["Pi"], b["Pi"])
     assert a["cert"] == b["cert"]
