@@ -18,6 +18,12 @@
  *   returning; embed, project_axes, project_family and the MLP calls return
  *   without synchronising (later calls that share the workspace must use the
  *   same stream).
+ * - Sizes: 2 <= n <= 700000 points, 1 <= d <= 32768 coordinates, and n and d
+ *   padded (to multiples of 128) with a product below 2^32; larger clouds
+ *   return ADAGIO_E_UNSUPPORTED before any device work (a dispatch holds
+ *   fewer than 2^32 work-items: the all-pairs screens launch one 256-thread
+ *   workgroup per 128 x 128 tile slot, elementwise kernels one work-item per
+ *   element of an n x d copy or a d x d matrix).
  * - Host structs (adagio_cert_t, adagio_opts_t, adagio_stats_t) are owned by
  *   the caller; opts may be NULL (defaults).
  * - The library keeps a per-device workspace that grows on demand and is
@@ -63,7 +69,7 @@ extern "C" {
                                     (certified = 0, bound_rest = +inf); fits
                                     certify their result with BF16X3 */
 
-/* Map family of a fit (Sec. 4.3 / Table 2 compare the three). */
+/* Map family of a fit (Table 3 of Sec. 4.4 compares the three). */
 #define ADAGIO_MAP_ADAGIO 0      /* Algorithm 1: [P ; S Q], floor(r/2) + ceil(r/2) rows */
 #define ADAGIO_MAP_PCA 1         /* the top r principal directions alone          */
 #define ADAGIO_MAP_JL 2          /* Lemma 1's r x d +-1/sqrt(r) matrix alone (no PCA) */
@@ -174,7 +180,7 @@ int adagio_pca_randomized(const float* X, int64_t n, int64_t d, int32_t ell, int
 int adagio_project_axes(const double* Vt, int64_t d, int32_t r, uint64_t seed, float* Pi_out, void* stream);
 
 /* f3.  The map of one family at a fixed r from the same sorted axes (the
- * rows compared in Table 2): ADAGIO_MAP_ADAGIO is adagio_project_axes's map,
+ * rows compared in Table 3, Sec. 4.4): ADAGIO_MAP_ADAGIO is adagio_project_axes's map,
  * ADAGIO_MAP_PCA the top r rows of Vt, ADAGIO_MAP_JL the r x d +-1/sqrt(r)
  * sign matrix of Lemma 1 (the identity at r = d).  Vt: device d x d FP64;
  * Pi_out: device r x d FP32.  Asynchronous. */
@@ -216,7 +222,7 @@ int adagio_certify_map(const float* X, int64_t n, int64_t d, const float* Pi, in
 
 /* a1-a9.  Fit: PCA once, then the smallest target dimension r whose map
  * (adagio_project_axes at r) has certified distortion <= eps, found by
- * bisection over r with lo = 0 and hi = d (Sec. 4.3 / Table 2 ask how many
+ * bisection over r with lo = 0 and hi = d (Sec. 4.3's Fig. 6 and Sec. 4.4's Table 3 ask how many
  * dimensions a distortion level needs; the search procedure is this
  * library's).  eps is the absolute distortion target, in (0, 1).
  * Pi_out: device buffer of capacity d x d FP32; receives Pi (r x d).
@@ -236,7 +242,7 @@ int adagio_certify_map(const float* X, int64_t n, int64_t d, const float* Pi, in
  * before its first screen.  An FP8 fit fills the BF16 split Gram, which its
  * FP8 screens (with unit point scales) and its BF16 split certificates both
  * load.  opts->family = ADAGIO_MAP_PCA or ADAGIO_MAP_JL runs the same search
- * over the PCA-only or JL-only maps of Table 2 (at r = d: V^T, resp. the
+ * over the PCA-only or JL-only maps of Table 3 (at r = d: V^T, resp. the
  * identity); the learned search is for Algorithm 1's maps only.
  * opts->pca = ADAGIO_PCA_RANDOMIZED takes the principal directions from
  * adagio_pca_randomized with ell = s + 10 for the largest s the search has
@@ -318,8 +324,8 @@ typedef struct adagio_knn_stats {
     int64_t reserved[4];
 } adagio_knn_stats_t;
 
-/* f4.  Exact k-nearest-neighbour queries, the operation of Sec. 5's
- * applications: the 10-NN query of each descriptor of a query photo in the
+/* f4.  Exact k-nearest-neighbour queries, the operation of the
+ * applications of Secs. 4.6 and 4.7: the 10-NN query of each descriptor of a query photo in the
  * image-retrieval experiment (Q = query descriptors, D = the database) and the
  * k = 30 nearest-neighbour graph of the classification experiment (Q = D,
  * exclude_self = 1), on original or embedded points.
@@ -338,7 +344,7 @@ typedef struct adagio_knn_stats {
 int adagio_knn(const float* Q, int64_t nq, const float* D, int64_t nd, int64_t m, int32_t k, int32_t exclude_self,
                int32_t* idx_out, double* dist_out, adagio_knn_stats_t* stats_out, void* stream);
 
-/* f4.  Majority vote of the image-retrieval experiment (Sec. 5): queries come
+/* f4.  Majority vote of the image-retrieval experiment (Sec. 4.6): queries come
  * in groups of `group` consecutive rows (one query photo; the last group may
  * be shorter); every neighbour in nn_idx (device nq x k int32, database row
  * indices) adds a vote to its label d_label[row] (device nd int32, in

@@ -14,6 +14,7 @@
  * No Gram identity, blocking or reordering is used.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 
 typedef struct {
@@ -90,6 +91,46 @@ void oracle_certificate(const double *X, const double *Y, int64_t n, int64_t d, 
     out->nzero = nzero; out->npairs = npairs;
 }
 
+/* Pairs (IA[a], IB[b]) of two lists of row indices, counted when
+ * IA[a] < IB[b] (a sample of the unordered pairs of eq. (3): row blocks
+ * against row blocks, or one row against every other).  X and Y hold every
+ * row of the cloud, as in oracle_certificate. */
+void oracle_cross_certificate(const double *X, const double *Y, int64_t d, int64_t r,
+                              const int64_t *IA, int64_t na, const int64_t *IB, int64_t nb,
+                              oracle_cert *out) {
+    rec top[2] = {{-1.0, -1, -1, 0}, {-1.0, -1, -1, 0}};
+    int64_t nzero = 0, npairs = 0;
+#pragma omp parallel
+    {
+        rec loc[2] = {{-1.0, -1, -1, 0}, {-1.0, -1, -1, 0}};
+        int64_t lz = 0, lp = 0;
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t a = 0; a < na; ++a) {
+            for (int64_t b = 0; b < nb; ++b) {
+                int64_t i = IA[a], j = IB[b];
+                if (i >= j) continue;
+                int32_t side; int zero;
+                double v = pair_distortion(X, Y, d, r, i, j, &side, &zero);
+                ++lp;
+                if (zero) { ++lz; continue; }
+                rec c = {v, i, j, side};
+                push(loc, &c);
+            }
+        }
+#pragma omp critical
+        {
+            push(top, &loc[0]);
+            if (loc[1].i >= 0) push(top, &loc[1]);
+            nzero += lz; npairs += lp;
+        }
+    }
+    out->best = top[0].i >= 0 ? top[0].v : 0.0;
+    out->bi = top[0].i; out->bj = top[0].j; out->bside = top[0].side;
+    out->second = top[1].i >= 0 ? top[1].v : 0.0;
+    out->si = top[1].i; out->sj = top[1].j; out->sside = top[1].side;
+    out->nzero = nzero; out->npairs = npairs;
+}
+
 /* Distortion of an explicit list of pairs (sampled checks at full size).
  * out[t] = -1 marks a skipped pair with x_i == x_j. */
 void oracle_pair_list(const double *X, const double *Y, int64_t d, int64_t r,
@@ -102,3 +143,8 @@ void oracle_pair_list(const double *X, const double *Y, int64_t d, int64_t r,
         out[t] = zero ? -1.0 : v;
     }
 }
+
+/* Threads the OpenMP loops above use (for reporting the CPU baseline), and
+ * a way to change it (a 1-thread reference run). */
+int oracle_threads(void) { return omp_get_max_threads(); }
+void oracle_set_threads(int t) { omp_set_num_threads(t > 0 ? t : 1); }

@@ -43,8 +43,14 @@ def _load():
             i64, dp = ctypes.c_int64, ctypes.c_void_p
             lib.oracle_certificate.argtypes = [dp, dp, i64, i64, i64, i64, i64, ctypes.POINTER(OracleCert)]
             lib.oracle_certificate.restype = None
+            lib.oracle_cross_certificate.argtypes = [dp, dp, i64, i64, dp, i64, dp, i64, ctypes.POINTER(OracleCert)]
+            lib.oracle_cross_certificate.restype = None
             lib.oracle_pair_list.argtypes = [dp, dp, i64, i64, dp, dp, i64, dp, dp]
             lib.oracle_pair_list.restype = None
+            lib.oracle_threads.argtypes = []
+            lib.oracle_threads.restype = ctypes.c_int
+            lib.oracle_set_threads.argtypes = [ctypes.c_int]
+            lib.oracle_set_threads.restype = None
             _lib = lib
     return _lib
 
@@ -69,6 +75,27 @@ def certify(X, Y, rows=None):
             "n_zero": out.nzero, "n_pairs": out.npairs}
 
 
+def certify_cross(X, Y, IA, IB):
+    """Max distortion over the pairs (IA[a], IB[b]) with IA[a] < IB[b]: a
+    sample of eq. (3)'s pairs given by two lists of row indices (row blocks
+    against row blocks, or one row against all others).  Same result dict as
+    ``certify``."""
+    X, Y = _f64(X), _f64(Y)
+    n, d = X.shape
+    if Y.ndim != 2 or Y.shape[0] != n:
+        raise ValueError("Y must have one row per point")
+    IA = np.ascontiguousarray(IA, dtype=np.int64)
+    IB = np.ascontiguousarray(IB, dtype=np.int64)
+    if IA.size and (IA.min() < 0 or IA.max() >= n) or IB.size and (IB.min() < 0 or IB.max() >= n):
+        raise ValueError("row index out of range")
+    out = OracleCert()
+    _load().oracle_cross_certificate(X.ctypes.data, Y.ctypes.data, d, Y.shape[1], IA.ctypes.data, IA.shape[0],
+                                     IB.ctypes.data, IB.shape[0], ctypes.byref(out))
+    return {"max": out.best, "i": out.bi, "j": out.bj, "side": out.bside,
+            "runner_up": out.second, "i2": out.si, "j2": out.sj, "side2": out.sside,
+            "n_zero": out.nzero, "n_pairs": out.npairs}
+
+
 def pair_distortions(X, Y, I, J):
     """eq. (2) for explicit pairs; -1 marks a pair of identical points."""
     X, Y = _f64(X), _f64(Y)
@@ -80,3 +107,13 @@ def pair_distortions(X, Y, I, J):
     _load().oracle_pair_list(X.ctypes.data, Y.ctypes.data, X.shape[1], Y.shape[1],
                              I.ctypes.data, J.ctypes.data, m, out.ctypes.data, side.ctypes.data)
     return out, side
+
+
+def threads():
+    """OpenMP threads the certificate loops use."""
+    return int(_load().oracle_threads())
+
+
+def set_threads(t):
+    """Run the certificate loops on t threads from now on (t >= 1)."""
+    _load().oracle_set_threads(int(t))

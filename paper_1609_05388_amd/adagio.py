@@ -265,7 +265,7 @@ def certify_map(X, Pi, screen="f32", max_candidates=0, with_stats=False):
 def fit(X, eps, seed, screen="f32", search="bisect", predictor=None, max_candidates=0, family="adagio",
         pca="exact", pca_iters=2, witness=True):
     """Returns dict(Pi=(r x d tensor), r, s, k, cert, stats).  family: "adagio"
-    (Algorithm 1), "pca" or "jl" (Table 2's single-component maps); pca:
+    (Algorithm 1), "pca" or "jl" (Table 3's single-component maps); pca:
     "exact" or "randomized" (Sec. 4.5's variant, pca_iters power iterations);
     witness=False certifies every probe in full."""
     lib = load()

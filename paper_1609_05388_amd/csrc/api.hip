@@ -1140,12 +1140,24 @@ static int guarded(F&& f) {
   }
 }
 
+// Launch geometry bounds the sizes: a dispatch holds fewer than 2^32
+// work-items, the all-pairs screens run one 256-thread workgroup per tile
+// slot (n = 700000 gives 1.5e7 slots, 3.8e9 work-items; 740352 points would
+// reach 2^32), and the elementwise kernels one work-item per element of an
+// n x d copy or a d x d matrix.
+static const int64_t kMaxPoints = 700000;
+static const int64_t kMaxDim = 32768;
+
 static void check_points(const float* X, int64_t n, int64_t d) {
   ARGCHK(X != nullptr, "X is NULL");
   ARGCHK(n >= 2, "need n >= 2 points");
   ARGCHK(d >= 1, "need d >= 1");
-  if (n > (int64_t)0x7fffff00 || d > (int64_t)0x100000) {
-    set_err("n or d beyond the supported range%s%lld", "", 0);
+  if (n > kMaxPoints || d > kMaxDim) {
+    set_err("n <= 700000 and d <= 32768 are supported%s (n or d is %lld)", "", (long long)(n > kMaxPoints ? n : d));
+    throw Fail{ADAGIO_E_UNSUPPORTED};
+  }
+  if (round_up(n, kTile) * round_up(d, 128) >= ((int64_t)1 << 32)) {
+    set_err("n x d beyond the supported range%s (n x d = %lld)", "", (long long)(n * d));
     throw Fail{ADAGIO_E_UNSUPPORTED};
   }
 }

@@ -123,3 +123,12 @@ def test_invalid_arguments_rejected_without_gpu(lib):
     assert lib.adagio_knn(fake, 10, fake, 10, 4, 3, 0, None, fake, ctypes.byref(ks), None) == -1
     assert lib.adagio_knn_vote(fake, 10, 3, fake, 10, 0, 5, fake, None) == -1
     assert lib.adagio_knn_vote(fake, 10, 3, fake, 10, 4, 0, fake, None) == -1
+    # sizes beyond the launch geometry (one 256-thread workgroup per tile slot
+    # of the screens, one work-item per element of n x d and d x d arrays, at
+    # most 2^32 work-items per dispatch) are refused before any device work
+    assert lib.adagio_fit(fake, 700001, 8, 0.1, 1, None, fake, ctypes.byref(r), ctypes.byref(s), ctypes.byref(c),
+                          None) == -5
+    assert b"700000" in lib.adagio_last_error()
+    assert lib.adagio_max_distortion(fake, 10, 32769, fake, 3, None, ctypes.byref(c), None) == -5
+    assert lib.adagio_certify_map(fake, 600000, 8192, fake, 3, None, ctypes.byref(c), None) == -5
+    assert b"n x d" in lib.adagio_last_error()

@@ -338,6 +338,36 @@ def test_certificate_row_blocks_and_pair_list():
     assert v[0] == full["max"] and side[0] == full["side"]
 
 
+def test_cross_certificate_is_a_sample_of_the_pairs():
+    """Pairs between two index lists (i < j): all rows against all rows is
+    the full certificate, bit for bit; a row block against all rows is the
+    row-block certificate; two disjoint blocks are brute force over their
+    cross pairs; one row against every row (both directions) holds every
+    pair of that row."""
+    X = gen.gaussian(50, 9, seed=23).astype(np.float64)
+    X[31] = X[7]
+    Y = X @ np.random.default_rng(6).standard_normal((9, 4))
+    allr = np.arange(50)
+    full = certificate.certify(X, Y)
+    cross = certificate.certify_cross(X, Y, allr, allr)
+    assert cross == full
+    blk = certificate.certify(X, Y, rows=(10, 20))
+    assert certificate.certify_cross(X, Y, np.arange(10, 20), allr) == blk
+    A, B = np.arange(5, 15), np.arange(30, 42)
+    c = certificate.certify_cross(X, Y, A, B)
+    best = max((abs(np.linalg.norm(Y[i] - Y[j]) / np.linalg.norm(X[i] - X[j]) - 1), i, j)
+               for i in A for j in B if np.any(X[i] != X[j]))
+    assert abs(c["max"] - best[0]) < 1e-14 and (c["i"], c["j"]) == best[1:]
+    assert c["n_pairs"] == len(A) * len(B)
+    assert certificate.certify_cross(X, Y, B, A)["n_pairs"] == 0
+    row = 7
+    lo = certificate.certify_cross(X, Y, allr, [row])
+    hi = certificate.certify_cross(X, Y, [row], allr)
+    assert lo["n_pairs"] + hi["n_pairs"] == 49 and lo["n_zero"] + hi["n_zero"] == 1
+    v, _ = certificate.pair_distortions(X, Y, np.minimum(row, allr[allr != row]), np.maximum(row, allr[allr != row]))
+    assert max(lo["max"], hi["max"]) == v.max()
+
+
 # ---------------------------------------------------------------- search
 def test_pca_search_equals_linear_scan():
     """For PCA alone ||P_s v|| grows with s, so the distortion is monotone in r
