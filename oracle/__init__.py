@@ -18,15 +18,15 @@ What it computes, each step following the paper (Blasiok & Tsourakakis,
                      floor(r/2) / ceil(r/2) split of Sec. 4.1 "Implementation".
 * ``certificate`` -- eq. (3): the maximum over all unordered pairs of the
                      eq. (2) distortion, by direct differences in FP64 (C).
-* ``search``      -- smallest-r search for a target distortion (Sec. 4.3 /
-                     Table 2), by bisection over r.
+* ``search``      -- smallest-r search for a target distortion (Sec. 4.3,
+                     Fig. 6; Table 3 of Sec. 4.4), by bisection over r.
 * ``mlp``         -- FP64 forward/backward of the learned dimension predictor
                      (a method extension; not in the paper).
 * ``sketch``      -- the predictor's input features (a method extension).
 * ``fp8``         -- the e4m3 operand encoding of the FP8 screen (OCP FP8).
 * ``rpca``        -- the randomized PCA of Sec. 4.5's Adagio-Randomized-PCA.
 * ``knn``         -- exact k-nearest-neighbour queries and the majority vote
-                     of Sec. 5's applications.
+                     of Secs. 4.6 and 4.7's applications.
 
 Readings of the paper where it is silent or garbled are listed in each
 module header.

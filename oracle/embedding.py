@@ -7,7 +7,7 @@ Pi = [P ; S Q].  Sec. 4.1 "Implementation": for a target dimension r the paper
 uses floor(r/2) principal components and ceil(r/2) JL rows.
 
 Readings:
-* r = d means "no reduction" (Sec. 4.3, Table 2's JL rows): Pi = V^T, the full
+* r = d means "no reduction" (Table 3's JL rows, Sec. 4.4): Pi = V^T, the full
   orthonormal eigenbasis, which is an isometry.  The printed floor/ceil split
   at r = d would not be one.
 * The map is linear and is not shifted by the mean (f(w) = Pi w as printed);
@@ -43,12 +43,12 @@ def adagio_map(Vt, r, seed):
 
 
 def pca_map(Vt, r):
-    """PCA alone: the top-r principal directions (Table 2's PCA rows)."""
+    """PCA alone: the top-r principal directions (Table 3's PCA rows)."""
     return Vt[:r].copy()
 
 
 def jl_map(d, r, seed):
-    """JL alone: Lemma 1's r x d +-1/sqrt(r) matrix (Table 2's JL rows);
+    """JL alone: Lemma 1's r x d +-1/sqrt(r) matrix (Table 3's JL rows);
     r = d means no reduction (identity)."""
     if r == d:
         return np.eye(d)
@@ -56,7 +56,7 @@ def jl_map(d, r, seed):
 
 
 def family_map(family, Vt, r, seed):
-    """Pi_r of one of the three map families compared in Table 2."""
+    """Pi_r of one of the three map families compared in Table 3 (Sec. 4.4)."""
     if family == "adagio":
         return adagio_map(Vt, r, seed)
     if family == "pca":

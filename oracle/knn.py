@@ -3,10 +3,10 @@ of the image-retrieval application (oracle, FP64).
 
 Test infrastructure only: the library never imports this module.
 
-Sec. 5 ("Approximate Nearest Neighbor Queries") runs a 10-nearest-neighbour
+Sec. 4.6 ("Approximate Nearest Neighbor Queries") runs a 10-nearest-neighbour
 query in the database for each descriptor of a query photo and labels the
 photo with the object that appears most often among the answers; accuracy
-is the fraction of objects labelled correctly.  Sec. 5 ("Classification")
+is the fraction of objects labelled correctly.  Sec. 4.7 ("Classification")
 builds the k-nearest-neighbour graph (k = 30) of a point set.  Both are the
 same operation: for every query q, the k database rows x with the smallest
 ||q - x||^2.

@@ -1,12 +1,12 @@
 """Target-dimension search and the full fit (oracle, FP64).  Test
 infrastructure only.
 
-Paper: Sec. 4.3 and Table 2 ask, for a distortion level delta, how many
+Paper: Sec. 4.3 (Fig. 6) and Sec. 4.4 (Table 3) ask, for a distortion level delta, how many
 dimensions each method needs; Sec. 4.1 "Implementation" fixes the
 floor(r/2)/ceil(r/2) split; Algorithm 1 gives the map.
 
 Readings:
-* The API's ``eps`` is the absolute target max distortion (Table 2's delta),
+* The API's ``eps`` is the absolute target max distortion (Table 3's delta),
   not Algorithm 1's multiplicative reduction factor.
 * The search procedure is not stated.  Bisection over r: lo = 0 (the empty map
   collapses every distance, distortion 1 by convention), hi = d (the full

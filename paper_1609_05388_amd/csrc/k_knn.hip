@@ -1,5 +1,5 @@
-// Exact k-nearest-neighbour queries, the operation behind Sec. 5's
-// applications: the 10-NN query of every descriptor of a query photo in the
+// Exact k-nearest-neighbour queries, the operation behind the
+// applications of Secs. 4.6 and 4.7: the 10-NN query of every descriptor of a query photo in the
 // image-retrieval experiment and the 30-NN graph of the classification
 // experiment.  For every query q the answer is the k database rows x with the
 // smallest FP64 squared distance ||q - x||^2, summed coordinate by

@@ -111,7 +111,7 @@ def instance_params(index, held_out=False):
 def sift_shaped(buildings=201, photos=4, per_photo=500, per_query=100, proto=500, clutter=3000,
                 latent=48, own=0.22, noise=0.065, seed=DATA_SEED):
     """SIFT-shaped descriptors of a building-retrieval workload (the image
-    retrieval experiment of Sec. 5's nearest-neighbour queries): ``buildings``
+    retrieval experiment of Sec. 4.6's nearest-neighbour queries): ``buildings``
     objects, ``photos`` database photos of ``per_photo`` descriptors each and
     one query photo of ``per_query`` descriptors per object, all in R^128.
 

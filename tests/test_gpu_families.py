@@ -1,4 +1,4 @@
-"""Map families of Sec. 4.3 / Table 2 on the GPU: the same certified search
+"""Map families of Table 3 (Sec. 4.4) on the GPU: the same certified search
 over the PCA-only and JL-only maps, against the oracle's search over its own
 family maps (same r, same certified maximum)."""
 import numpy as np

@@ -1,4 +1,4 @@
-"""Exact kNN queries and the majority vote (Sec. 5's applications) on the GPU
+"""Exact kNN queries and the majority vote (the applications of Secs. 4.6 and 4.7) on the GPU
 against the oracle: indices and FP64 distances bit for bit (both sides sum the
 same squares in the same order and order ties by index)."""
 import numpy as np

@@ -36,7 +36,7 @@ def cloud(name):
 
 
 @pytest.mark.parametrize("name,eps,screen,family", [c + ("adagio",) for c in CASES] + [
-    ("mnist", 0.1, "f32", "pca"),      # Table 2's PCA-only maps
+    ("mnist", 0.1, "f32", "pca"),      # Table 3's PCA-only maps
     ("c1", 0.2, "f32", "jl"),          # JL-only maps: no PCA, the cache fill starts at once
 ])
 def test_witness_search_same_result(gpu_lib, name, eps, screen, family):

@@ -1,4 +1,4 @@
-"""Pins of the oracle's exact kNN and majority vote (Sec. 5's applications)
+"""Pins of the oracle's exact kNN and majority vote (the applications of Secs. 4.6 and 4.7)
 against what the definitions fix: exact rational brute force on tiny integer
 inputs (ties included), scikit-learn's brute-force search, exact invariances,
 self-matches, and hand-worked votes."""
