@@ -125,7 +125,7 @@ def summarize_traffic(d):
         "fetch": out["FETCH_SIZE"], "write": out["WRITE_SIZE"],
         "commands": [
             "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pmc -o copy_FETCH_SIZE -- python3 <repo>/bench.py --calib-copy-mib 1024",
-            "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pmc -o fit_FETCH_SIZE -- python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extra-eps --no-forms --no-large --no-knn --no-witness",
+            "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pmc -o fit_FETCH_SIZE -- python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-oracle-parity --no-extra-eps --no-forms --no-large --no-knn --no-witness",
             "(the same two with WRITE_SIZE)",
             "python3 <repo>/bench.py --summarize-traffic <out>/pmc",
         ],
@@ -137,37 +137,168 @@ def summarize_traffic(d):
     print(json.dumps(rec, indent=1))
 
 
+def host_cpu():
+    """The host's CPU model and core counts (lscpu) and the CPUs this
+    process may run on."""
+    import subprocess
+    info = {"model": None, "physical_cores": None, "logical_cpus": None}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        kv = {}
+        for line in out.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        info["model"] = kv.get("Model name")
+        sockets, cps = int(kv.get("Socket(s)", "0") or 0), int(kv.get("Core(s) per socket", "0") or 0)
+        info["physical_cores"] = sockets * cps or None
+        info["logical_cpus"] = int(kv.get("CPU(s)", "0") or 0) or None
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    try:
+        info["cpus_available"] = len(os.sched_getaffinity(0))
+    except OSError:
+        info["cpus_available"] = os.cpu_count()
+    return info
+
+
+def rows_for_pairs(n, goal):
+    """Smallest m such that rows [0, m) x all j > i hold at least goal pairs."""
+    m, acc = 0, 0
+    while m < n and acc < goal:
+        acc += n - 1 - m
+        m += 1
+    return max(m, 1)
+
+
 def cpu_baseline(X, Pi, target_s, n_probes):
-    """Oracle certificate (C, FP64, OpenMP) on rows [0, m) x all j > i, in
-    the metric's unit: the oracle's fit certifies all n(n-1)/2 pairs once per
-    probe of its bisection (n_probes of them), so its pairs certified per
-    second of fit are its pair rate / n_probes (its PCA not counted)."""
+    """The oracle, as it stands, on this host: its certificate (C, FP64,
+    OpenMP over the host's threads) on rows [0, m) x all j > i of the same
+    cloud at the fitted map, m chosen for ~target_s of work, the same on one
+    thread for a shorter row block, and its PCA (centre, covariance, eigh).
+    In the metric's unit: an oracle fit runs its PCA once and certifies all
+    n(n-1)/2 pairs once per probe of its bisection (n_probes of them), so its
+    pairs certified per second of fit are n(n-1)/2 / (t_pca + n_probes *
+    n(n-1)/2 / pair rate)."""
     import numpy as np
-    from oracle import certificate, embedding
+    from oracle import certificate, embedding, pca as opca
     X64 = X.astype(np.float64)
     Y = embedding.embed(X64, Pi)
     n = X.shape[0]
-    m = 64
+    npairs = n * (n - 1) // 2
+    threads = certificate.threads()
+    c = certificate.certify(X64, Y, rows=(0, 64))                  # warm-up and rate estimate
+    t0 = time.perf_counter()
+    c = certificate.certify(X64, Y, rows=(0, 64))
+    rate0 = c["n_pairs"] / max(time.perf_counter() - t0, 1e-9)
+    m = rows_for_pairs(n, rate0 * target_s)
     t0 = time.perf_counter()
     c = certificate.certify(X64, Y, rows=(0, m))
     dt = time.perf_counter() - t0
-    rate = c["n_pairs"] / max(dt, 1e-9)
-    pairs_goal = rate * target_s
-    m2, acc = 0, 0
-    while m2 < n and acc < pairs_goal:
-        acc += n - 1 - m2
-        m2 += 1
-    t0 = time.perf_counter()
-    c = certificate.certify(X64, Y, rows=(0, m2))
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
     rate = c["n_pairs"] / dt
-    return {"value": rate / n_probes, "unit": "pairs/s", "cores": cores, "kind": "oracle",
-            "pair_evaluations_per_s": rate,
-            "sample": "eq.(3) certificate by FP64 direct differences (oracle/certificate.c, OpenMP) over "
-                      "rows [0,%d) x all j>i of the same cloud at the fitted r (%d pairs, %.1f s); value = "
-                      "that pair rate / the %d certificates of the oracle's bisection (PCA not counted)"
-                      % (m2, c["n_pairs"], dt, n_probes)}
+    # one thread, on a block of ~target_s / 4 of work
+    m1 = rows_for_pairs(n, rate / max(threads, 1) * target_s / 4)
+    certificate.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        c1 = certificate.certify(X64, Y, rows=(0, m1))
+        dt1 = time.perf_counter() - t0
+    finally:
+        certificate.set_threads(threads)
+    rate1 = c1["n_pairs"] / dt1
+    t0 = time.perf_counter()
+    opca.pca(X)
+    t_pca = time.perf_counter() - t0
+    est_fit = t_pca + n_probes * npairs / rate
+    return {"value": npairs / est_fit, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "host": host_cpu(), "threads": threads,
+            "pair_evaluations_per_s": rate, "pair_evaluations_per_s_1thread": rate1,
+            "t_pca_s": t_pca, "certificates_per_fit": n_probes, "est_oracle_fit_s": est_fit,
+            "sample": "eq.(3) certificate by FP64 direct differences (oracle/certificate.c, OpenMP, %d threads) "
+                      "over rows [0,%d) x all j>i of the same cloud at the fitted r (%d pairs, %.1f s); one thread "
+                      "over rows [0,%d) (%d pairs, %.1f s); the oracle's PCA (numpy centre, covariance, eigh) "
+                      "%.2f s; value = n(n-1)/2 / (PCA + %d full certificates at the sampled rate)"
+                      % (threads, m, c["n_pairs"], dt, m1, c1["n_pairs"], dt1, t_pca, n_probes)}
+
+
+def oracle_parity(X, plain, forms, torch):
+    """The oracle's full eq. (3) certificate of the plain fit's final map
+    (every pair, FP64 direct differences) and the error against it of the
+    maximum each form certified; a form whose map differs from the plain
+    fit's is certified by the oracle separately."""
+    import numpy as np
+    from oracle import certificate, embedding
+    X64 = X.astype(np.float64)
+    cache = {}
+
+    def oracle_of(Pi):
+        key = Pi.cpu().numpy().tobytes()
+        if key not in cache:
+            t0 = time.perf_counter()
+            w = certificate.certify(X64, embedding.embed(X64, Pi.cpu().numpy().astype(np.float64)))
+            cache[key] = (w, time.perf_counter() - t0)
+        return cache[key]
+
+    def entry(o):
+        w, sec = oracle_of(o["Pi"])
+        c = o["cert"]
+        gap = w["max"] - w["runner_up"]
+        return {"r": o["r"], "max_distortion": c["max_distortion"], "oracle_max": w["max"],
+                "abs_err": abs(c["max_distortion"] - w["max"]),
+                "argmax": [c["i"], c["j"]], "oracle_argmax": [w["i"], w["j"]],
+                "oracle_runner_up_gap": gap,
+                "same_argmax": bool((c["i"], c["j"]) == (w["i"], w["j"])), "oracle_s": sec,
+                "oracle_pairs": w["n_pairs"]}
+
+    out = {"threads": certificate.threads(), "plain_f32": entry(plain)}
+    for name, o in forms.items():
+        out[name] = entry(o)
+    return out
+
+
+def c4_oracle_sample(X, Pi, cert, n_blocks, block=1024, seed=4096):
+    """The oracle on the large cloud's fitted map, where a full certificate
+    (2e10 pairs) is out of reach: every pair of the argmax's and runner-up's
+    rows (both directions), the 2048 x 2048 row block holding the argmax
+    pair, and n_blocks random block x block row-block pairs."""
+    import numpy as np
+    from oracle import certificate
+    n = X.shape[0]
+    t0 = time.perf_counter()
+    X64 = X.astype(np.float64)
+    Y = X64 @ Pi.astype(np.float64).T
+    t_embed = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    allr = np.arange(n)
+    rows = sorted({cert["i"], cert["j"], cert["i2"], cert["j2"]} - {-1})
+    pairs, row_best = 0, -1.0
+    for row in rows:
+        for a, b in ((allr, [row]), ([row], allr)):
+            o = certificate.certify_cross(X64, Y, a, b)
+            pairs += o["n_pairs"]
+            row_best = max(row_best, o["max"])
+    a0 = min(max(cert["i"] - 1024, 0), n - 2048)
+    b0 = min(max(cert["j"] - 1024, 0), n - 2048)
+    blk = certificate.certify_cross(X64, Y, np.arange(a0, a0 + 2048), np.arange(b0, b0 + 2048))
+    pairs += blk["n_pairs"]
+    rng = np.random.default_rng(seed)
+    top = max(row_best, blk["max"])
+    for _ in range(n_blocks):
+        a, b = np.sort(rng.integers(0, n - block, 2))
+        o = certificate.certify_cross(X64, Y, np.arange(a, a + block), np.arange(b, b + block))
+        pairs += o["n_pairs"]
+        top = max(top, o["max"])
+    dt = time.perf_counter() - t0
+    return {"pairs": pairs, "seconds": dt, "embed_s": t_embed, "threads": certificate.threads(),
+            "rows": rows, "random_blocks": n_blocks, "block_rows": block,
+            "largest_sampled": top, "argmax_rows_largest": row_best,
+            "argmax_block_max": blk["max"], "argmax_block_argmax": [blk["i"], blk["j"]],
+            "reproduces_certified_max": bool(abs(row_best - cert["max_distortion"]) <= 1e-12
+                                             and (blk["i"], blk["j"]) == (cert["i"], cert["j"])),
+            "none_above_certified": bool(top <= cert["max_distortion"] + 1e-12),
+            "sample": "oracle/certificate.c on the fitted map: every pair of rows %s against all rows, the 2048 x "
+                      "2048 row block holding the argmax pair, %d random %d x %d row-block pairs"
+                      % (rows, n_blocks, block, block)}
 
 
 def nonconstant_columns(X):
@@ -219,9 +350,9 @@ def fp8_form(adagio, gen, torch, Xd, eps, steps, plain_s, plain, npairs, d):
     scr, _, ref = split_probes(st)
     fl = sum(screen_flops(npairs, d, c, g) for _, _, _, g, c in scr)
     ms = sum(t for _, _, t, _, _ in scr)
-    return {"fit_ms": fs * 1e3, "speedup_vs_plain": plain_s / fs, "r": o["r"],
+    return o, {"fit_ms": fs * 1e3, "speedup_vs_plain": plain_s / fs, "r": o["r"],
             "max_distortion": o["cert"]["max_distortion"], "certified": o["cert"]["certified"],
-            "abs_err_vs_plain_fp64_certificate": abs(o["cert"]["max_distortion"] - plain["cert"]["max_distortion"]),
+            "abs_err_vs_plain_f32_fit": abs(o["cert"]["max_distortion"] - plain["cert"]["max_distortion"]),
             "same_map_as_plain": bool(o["r"] == plain["r"] and torch.equal(o["Pi"], plain["Pi"])),
             "screens": st["n_screened"], "certificates": st["n_certificates"] - st["n_screened"],
             "refuted_probes": st["n_refuted"],
@@ -252,7 +383,7 @@ def learned_form(adagio, gen, torch, Xd, eps, steps, plain_s, plain):
                                     "certified": ro["cert"]["certified"]}}
 
 
-def large_form(adagio, gen, torch, eps):
+def large_form(adagio, gen, torch, eps, oracle_blocks):
     """Precision form at scale: the power-law cloud n=200000, d=4096 (rank 512,
     sigma_i = 1/i, noise 0.01), fit with FP8-screened bisection and a BF16
     split certificate of the result; the plain FP32 certificate of the same
@@ -262,7 +393,6 @@ def large_form(adagio, gen, torch, eps):
     gen_s = time.perf_counter() - t0
     dx = nonconstant_columns(X)
     Xd = torch.from_numpy(X).cuda()
-    del X
     torch.cuda.synchronize()
     ta = time.perf_counter()
     o = adagio.fit(Xd, eps, gen.JL_SEED, screen="fp8")
@@ -288,8 +418,16 @@ def large_form(adagio, gen, torch, eps):
             "certified": ro["cert"]["certified"], "power_iterations": 2, "oversampling": 10}
     del Xd
     torch.cuda.empty_cache()
+    sample = None
+    if oracle_blocks >= 0:
+        log("large: oracle sample of the fitted map")
+        sample = c4_oracle_sample(X, o["Pi"].cpu().numpy(), o["cert"], oracle_blocks)
+        log("large: oracle checked %d pairs in %.1f s, largest %.9f, reproduces the max: %s"
+            % (sample["pairs"], sample["seconds"], sample["largest_sampled"], sample["reproduces_certified_max"]))
+    del X
     return {
         "workload": "power-law cloud n=200000, d=4096, rank 512, sigma_i=1/i, noise 0.01, eps=%g" % eps,
+        "oracle_sample": sample,
         "generate_s": gen_s, "fit_ms": fit_ms, "t_pca_ms": st["t_pca_ms"], "eig_sweeps": st["eig_sweeps"],
         "r": o["r"], "max_distortion": o["cert"]["max_distortion"], "certified": o["cert"]["certified"],
         "argmax": [o["cert"]["i"], o["cert"]["j"]],
@@ -310,7 +448,7 @@ def large_form(adagio, gen, torch, eps):
 
 
 def knn_form(adagio, gen, torch, rs=(128, 64, 32, 24, 20, 16, 12, 8, 4)):
-    """Sec. 5's image retrieval on the SIFT-shaped workload (201 objects, a
+    """Sec. 4.6's image retrieval on the SIFT-shaped workload (201 objects, a
     402,000 x 128 database of 4 photos x 500 descriptors each, 20,100 query
     descriptors of one photo per object): at each target dimension r the
     ADAGIO map of the database and, beside it, the PCA-only map (both from
@@ -407,7 +545,7 @@ def summarize_mfma(d):
         "workload": fit["config"]["workload"], "probes_r": rs, "probes_screen_cols": cols,
         "kinds": out,
         "commands": [
-            "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc MfmaUtil MfmaFlopsF32 --output-format csv -d <out>/mfma -o fit_mfma -- python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extra-eps --no-forms --no-large --no-knn --no-witness > <out>/mfma/fit_mfma.log",
+            "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc MfmaUtil MfmaFlopsF32 --output-format csv -d <out>/mfma -o fit_mfma -- python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-oracle-parity --no-extra-eps --no-forms --no-large --no-knn --no-witness > <out>/mfma/fit_mfma.log",
             "python3 <repo>/bench.py --summarize-mfma <out>/mfma",
         ],
         "note": "MfmaUtil: percent of the dispatch's GPU-active cycles during which the SIMDs' MFMA units were busy "
@@ -427,6 +565,10 @@ def main():
     ap.add_argument("--n", type=int, default=60000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-parity", action="store_true",
+                    help="skip the oracle's full certificate of the fitted map (about 45 s on 16 threads)")
+    ap.add_argument("--c4-oracle-blocks", type=int, default=16,
+                    help="random 1024 x 1024 row-block pairs the oracle checks on the large cloud (-1: none)")
     ap.add_argument("--no-extra-eps", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision-form fits")
     ap.add_argument("--no-large", action="store_true", help="skip the n=200000, d=4096 precision-form fit")
@@ -543,6 +685,7 @@ def main():
 
     # precision form: BF16 split screen, same exact certificate
     forms = {}
+    form_outs = {}
     if not args.no_forms:
         torch.cuda.synchronize()
         bf = adagio.fit(Xd, args.eps, gen.JL_SEED, screen="bf16x3")  # warm-up of its buffers
@@ -563,7 +706,7 @@ def main():
         forms["bf16x3"] = {
             "fit_ms": bf_s * 1e3, "speedup_vs_plain": fit_s / bf_s, "r": bl["r"],
             "max_distortion": bl["cert"]["max_distortion"], "certified": bl["cert"]["certified"],
-            "abs_err_vs_plain_fp64_certificate": abs(bl["cert"]["max_distortion"] - last["cert"]["max_distortion"]),
+            "abs_err_vs_plain_f32_fit": abs(bl["cert"]["max_distortion"] - last["cert"]["max_distortion"]),
             "same_map_as_plain": bool(bl["r"] == last["r"] and torch.equal(bl["Pi"], last["Pi"])),
             "screen_avg_launch_ms": bms / bn,
             "screen_useful_tflops": bflops / bms / 1e9,
@@ -571,7 +714,8 @@ def main():
             "screen_bf16_mfma_frac": 3.0 * bflops / bms / 1e9 / PEAK_BF16_MFMA_TFLOPS,
             "rescored_pairs": bl["stats"]["n_rescored"], "flagged_tiles": bl["stats"]["n_flagged_tiles"]}
         log("bf16x3 fit %.1f ms (%.2fx), screen %.2f ms/launch" % (bf_s * 1e3, fit_s / bf_s, bms / bn))
-        forms["fp8"] = fp8_form(adagio, gen, torch, Xd, args.eps, args.steps, fit_s, last, npairs, dx)
+        fp8_last, forms["fp8"] = fp8_form(adagio, gen, torch, Xd, args.eps, args.steps, fit_s, last, npairs, dx)
+        form_outs = {"bf16x3": bl, "fp8": fp8_last}
         log("fp8 fit %.1f ms (%.2fx)" % (forms["fp8"]["fit_ms"], forms["fp8"]["speedup_vs_plain"]))
         rs, routs = timed_fits(adagio, torch, Xd, args.eps, gen.JL_SEED, args.steps, pca="randomized", pca_iters=2)
         ro = routs[-1]
@@ -584,6 +728,16 @@ def main():
         if lf:
             forms["learned"] = lf
             log("learned fit %.1f ms (%.2fx)" % (lf["fit_ms"], lf["speedup_vs_plain"]))
+
+    parity = None
+    if not args.no_oracle_parity:
+        log("oracle: full eq. (3) certificate of the fit's map (%d pairs)" % npairs)
+        parity = oracle_parity(X, last, form_outs, torch)
+        for k in form_outs:
+            forms[k]["abs_err_vs_oracle"] = parity[k]["abs_err"]
+        log("oracle max %.9f in %.1f s; |err| plain %.2e%s" % (
+            parity["plain_f32"]["oracle_max"], parity["plain_f32"]["oracle_s"], parity["plain_f32"]["abs_err"],
+            "".join(", %s %.2e" % (k, parity[k]["abs_err"]) for k in form_outs)))
 
     extra = {}
     if not args.no_extra_eps:
@@ -616,7 +770,7 @@ def main():
         log("67 constant coordinates: fit %.1f ms, r=%d" % (border67["fit_ms"], o["r"]))
         del X67d
 
-    # Table 2 analogue: the smallest certified r of each map family per eps
+    # Table 3 (Sec. 4.4) / Fig. 6 (Sec. 4.3) analogue: the smallest certified r of each map family per eps
     tradeoff = {}
     if not args.no_extra_eps:
         for fam in ("adagio", "pca", "jl"):
@@ -634,7 +788,7 @@ def main():
     large = None
     if not args.no_large:
         log("precision form at n=200000, d=4096")
-        large = large_form(adagio, gen, torch, args.eps)
+        large = large_form(adagio, gen, torch, args.eps, args.c4_oracle_blocks)
         log("large: fp8 fit %.0f ms, r=%d, delta=%.6f" % (large["fit_ms"], large["r"], large["max_distortion"]))
 
     knn = None
@@ -684,6 +838,7 @@ def main():
         "knn_application": knn,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "oracle_parity": parity,
         "paper_context": "paper: <10 s for 60,000 x 784 MNIST on an i5-3317U laptop (abstract); not this workload",
     }
     print(json.dumps(rec), flush=True)
