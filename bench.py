@@ -609,6 +609,10 @@ def main():
         return
 
     adagio.load()
+    # a loop of fits keeps the library's workspace across calls (the opt-in
+    # adagio_keep_workspace; the library default allocates per call: timed
+    # below beside it)
+    adagio.keep_workspace(True)
     log("generating MNIST-shaped cloud n=%d" % args.n)
     X = gen.mnist_shaped(n=args.n)
     n, d = X.shape
@@ -637,6 +641,16 @@ def main():
     log("fit %.1f ms/step: r=%d, %d certificates, %d probes refuted, delta=%.6f, pca %.1f ms, search %.1f ms, "
         "screen %.1f ms" % (fit_s * 1e3, last["r"], ncert, st["n_refuted"], last["cert"]["max_distortion"],
                             st["t_pca_ms"], st["t_search_ms"], st["t_screen_ms"]))
+
+    # the same fits with the library default: every call allocates its
+    # workspace (the 7.2 GB point-Gram cache among it) and frees it
+    adagio.keep_workspace(False)
+    pc_s, pc_outs = timed_fits(adagio, torch, Xd, args.eps, gen.JL_SEED, args.steps, witness=wit)
+    adagio.keep_workspace(True)
+    per_call = {"fit_ms": pc_s * 1e3, "slowdown_vs_kept_workspace": pc_s / fit_s,
+                "same_result": bool(pc_outs[-1]["r"] == last["r"] and torch.equal(pc_outs[-1]["Pi"], last["Pi"])
+                                    and pc_outs[-1]["cert"] == last["cert"])}
+    log("per-call workspace: fit %.1f ms" % (pc_s * 1e3))
 
     # the same fit certifying every probe in full (no witness pool, no early stop)
     without_witness = None
@@ -818,7 +832,7 @@ def main():
                                "zero mask), n=%d, d=%d, eps=%g, plain FP32 screen, bisection search"
                                % (n, d, args.eps),
                    "n": n, "d": d, "d_nonconstant": dx, "eps": args.eps, "seed": gen.JL_SEED, "data_seed": gen.DATA_SEED,
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU", "workspace": "kept across calls"},
         "fit": {"r": last["r"], "s": last["s"], "k": last["k"], "certificates": ncert,
                 "max_distortion": last["cert"]["max_distortion"], "certified": last["cert"]["certified"],
                 "argmax": [last["cert"]["i"], last["cert"]["j"]], "t_pca_ms": st["t_pca_ms"],
@@ -829,7 +843,9 @@ def main():
                 "probes": [[r, dl, {3: "refuted by the pool", 4: "screen stopped early"}.get(g, "certified"), c]
                            for r, dl, g, c in zip(st["probe_r"], st["probe_delta"], st["probe_gram"],
                                                   st["probe_cols"])],
-                "without_witness_pool": without_witness},
+                "without_witness_pool": without_witness,
+                "workspace": "kept across calls (adagio_keep_workspace(1), opted in for the loop of fits)",
+                "with_per_call_workspace": per_call},
         "other_eps": extra,
         "mnist_like_67_constant_coordinates": border67,
         "tradeoff_min_r": tradeoff,

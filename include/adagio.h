@@ -15,9 +15,10 @@
  *   All device work is ordered on it.  Entry points that return host scalars
  *   or check device results (fit, max_distortion, certify_map, pca,
  *   pca_randomized, project, knn, knn_vote) synchronise that stream before
- *   returning; embed, project_axes, project_family and the MLP calls return
- *   without synchronising (later calls that share the workspace must use the
- *   same stream).
+ *   returning; embed and quantize_fp8 (no scratch) return without
+ *   synchronising, and so do project_axes, project_family and the MLP calls
+ *   when the workspace is kept (see below; later calls that share the kept
+ *   workspace must then use the same stream).
  * - Sizes: 2 <= n <= 700000 points, 1 <= d <= 32768 coordinates, and n and d
  *   padded (to multiples of 128) with a product below 2^32; larger clouds
  *   return ADAGIO_E_UNSUPPORTED before any device work (a dispatch holds
@@ -26,9 +27,16 @@
  *   element of an n x d copy or a d x d matrix).
  * - Host structs (adagio_cert_t, adagio_opts_t, adagio_stats_t) are owned by
  *   the caller; opts may be NULL (defaults).
- * - The library keeps a per-device workspace that grows on demand and is
- *   reused across calls; adagio_release() frees it.  Calls are serialised by
- *   an internal lock.
+ * - Scratch memory: by default each call allocates the device workspace it
+ *   needs (hipMalloc) and frees it before returning, after draining
+ *   `stream` and the library's own streams; an entry point that uses
+ *   scratch therefore returns with `stream` synchronised.  A caller that
+ *   repeats calls can opt in to keeping one workspace per device across
+ *   calls with adagio_keep_workspace(1); adagio_release() frees the current
+ *   device's, and the library frees what is kept at process exit by itself
+ *   (an exit handler registered after the HIP runtime has started, so it
+ *   runs before the runtime's teardown).  Calls are serialised by an
+ *   internal lock.
  * - Return value: ADAGIO_OK (0) or a negative ADAGIO_E_* code.  On error the
  *   output buffers are unspecified and adagio_last_error() describes the
  *   failure (thread-local text).  Arguments are validated before any device
@@ -355,7 +363,14 @@ int adagio_knn(const float* Q, int64_t nq, const float* D, int64_t nd, int64_t m
 int adagio_knn_vote(const int32_t* nn_idx, int64_t nq, int32_t k, const int32_t* d_label, int64_t nd,
                     int32_t n_labels, int32_t group, int32_t* label_out, void* stream);
 
-/* Frees the cached device workspace of the current device. */
+/* Workspace ownership: keep = 1 keeps each device's workspace (buffers,
+ * the fit's point-Gram cache, two streams and their events) across calls,
+ * so that repeated calls skip allocation; keep = 0 (the default) frees every
+ * call's workspace before it returns and frees what is kept now.  Any other
+ * value returns ADAGIO_E_INVALID_ARG. */
+int adagio_keep_workspace(int keep);
+
+/* Frees the kept workspace of the current device (nothing when none is kept). */
 int adagio_release(void);
 
 /* Static text of a status code. */

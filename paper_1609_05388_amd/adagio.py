@@ -5,7 +5,6 @@ passes their device pointers and torch's current HIP stream to the C ABI of
 include/adagio.h.  No computation happens here: if the shared library is
 missing, ``load()`` raises instead of falling back to anything else.
 """
-import atexit
 import ctypes
 import os
 
@@ -104,6 +103,7 @@ SIGNATURES = {
     "adagio_knn": (ctypes.c_int, [_P, _I64, _P, _I64, _I64, _I32, _I32, _P, _P, ctypes.POINTER(KnnStats), _P]),
     "adagio_knn_vote": (ctypes.c_int, [_P, _I64, _I32, _P, _I64, _I32, _I32, _P, _P]),
     "adagio_release": (ctypes.c_int, []),
+    "adagio_keep_workspace": (ctypes.c_int, [ctypes.c_int]),
     "adagio_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "adagio_last_error": (ctypes.c_char_p, []),
 }
@@ -121,15 +121,7 @@ def load(path=LIB_PATH):
             fn.restype = res
             fn.argtypes = args
         _lib = lib
-        atexit.register(_release_at_exit)
     return _lib
-
-
-def _release_at_exit():
-    """Frees the library's device memory, streams and events while the HIP
-    runtime is still up (runs before the interpreter tears modules down)."""
-    if _lib is not None and torch.cuda.is_initialized():
-        _lib.adagio_release()
 
 
 def _check(rc):
@@ -377,4 +369,11 @@ def knn_vote(nn_idx, d_label, n_labels, group):
 
 
 def release():
+    """Frees the current device's kept workspace."""
     _check(load().adagio_release())
+
+
+def keep_workspace(keep=True):
+    """Keep one workspace per device across calls (True), or free each call's
+    workspace before it returns (False, the library's default)."""
+    _check(load().adagio_keep_workspace(1 if keep else 0))

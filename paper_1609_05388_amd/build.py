@@ -1,9 +1,9 @@
 """Build the gfx950 shared library ``libadagio.so`` in-tree with hipcc.
 
 Every .hip source under csrc/ is compiled to an object for gfx950 only and
-linked into one shared library next to this file (with rocBLAS, which runs
-the two plain FP64 GEMMs: covariance and the probes' embeddings).  Objects are rebuilt when
-their source or any header changed.
+linked into one shared library next to this file (HIP runtime only: every
+product, the FP64 GEMMs included, runs in the library's own kernels).
+Objects are rebuilt when their source or any header changed.
 """
 import concurrent.futures
 import glob
@@ -54,7 +54,7 @@ def build(force=False, jobs=8):
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, force), srcs))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lrocblas"]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("link failed:\n" + res.stderr)

@@ -11,8 +11,6 @@
 #include <string>
 #include <vector>
 
-#include <rocblas/rocblas.h>
-
 #include "../../include/adagio.h"
 #include "common.h"
 #include "kernels.h"
@@ -50,9 +48,16 @@ static void set_err(const char* fmt, const char* a = "", long long b = 0) {
   } while (0)
 
 // --------------------------------------------------------------- workspace
+// A device buffer that grows on demand and is freed with its owner.
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
 };
 
 struct Workspace {
@@ -65,19 +70,62 @@ struct Workspace {
   DevBuf skpart, skG, skK, sklam, skV, skfeat, mlp_pb, mlp_X, mlp_f, mlp_hb, mlp_grad, mlp_loss;
   DevBuf knQ, knD, knNq64, knNd64, knNq32, knNd32, knMax, knKeys, knFb, knCnt, knTau;
   DevBuf lam1, Vt1, colmap, colminmax, colkeep, xc64, pi64c;
-  DevBuf pool, pooln, wvals, wparts, wcd, wV, wW, stopn, stopp, gfM, gfFail, gfZ;
-  rocblas_handle blas = nullptr;  // plain FP64 GEMMs (covariance, embeddings)
+  DevBuf pool, pooln, wvals, wparts, wcd, wV, wW, stopn, stopp, gfM, gfFail, gfZ, nrm;
   // second stream (non-blocking, default priority) for work that overlaps
   // the caller's stream: the fit's point-Gram fill during its PCA
   hipStream_t aux = nullptr;
   hipStream_t aux2 = nullptr;  // non-blocking, all CUs: the fit's exact PCA beside the fill
   hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_t0 = nullptr, ev_t1 = nullptr, ev_pca = nullptr,
              ev_cov = nullptr;
-  bool checked = false;
+  Workspace() = default;
+  Workspace(const Workspace&) = delete;
+  Workspace& operator=(const Workspace&) = delete;
+  // Drains the library's streams, then frees streams, events and (member
+  // destructors) every buffer.  Errors are ignored: this also runs while an
+  // error unwinds a call.
+  ~Workspace() {
+    for (hipStream_t q : {aux, aux2}) {
+      if (q) {
+        (void)hipStreamSynchronize(q);
+        (void)hipStreamDestroy(q);
+      }
+    }
+    for (hipEvent_t e : {ev_in, ev_out, ev_t0, ev_t1, ev_pca, ev_cov}) {
+      if (e) (void)hipEventDestroy(e);
+    }
+  }
 };
 
+// Calls are serialised by g_mu.  By default each call owns a workspace that
+// it frees before returning.  With adagio_keep_workspace(1) every device
+// keeps one workspace across calls (g_kept, heap objects that no static
+// destructor touches); the library then registers, once, an exit handler
+// that frees them: it is registered after the HIP runtime has initialised,
+// so it runs before the runtime's own teardown.
 static std::mutex g_mu;
-static Workspace g_ws[64];
+static bool g_keep = false;
+static Workspace* g_kept[64];
+static bool g_checked[64];
+static bool g_exit_hook = false;
+
+static void release_kept_all() {
+  int cur = -1;
+  const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+  for (int dev = 0; dev < 64; ++dev) {
+    if (!g_kept[dev]) continue;
+    if (hipSetDevice(dev) == hipSuccess) delete g_kept[dev];
+    g_kept[dev] = nullptr;
+  }
+  if (have_cur) (void)hipSetDevice(cur);
+}
+
+static void release_at_exit() {
+  // another thread may still be inside a call at exit: leave its memory to
+  // the process teardown rather than free it under the call
+  if (!g_mu.try_lock()) return;
+  release_kept_all();
+  g_mu.unlock();
+}
 
 template <typename T>
 static T* ensure(DevBuf& b, size_t count) {
@@ -93,55 +141,59 @@ static T* ensure(DevBuf& b, size_t count) {
   return static_cast<T*>(b.p);
 }
 
-static Workspace& workspace() {
+// The current device, checked to be gfx950 (once per device).
+static int checked_device() {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   if (dev < 0 || dev >= 64) {
     set_err("device index %s%lld out of range", "", dev);
     throw Fail{ADAGIO_E_UNSUPPORTED};
   }
-  Workspace& ws = g_ws[dev];
-  if (!ws.checked) {
+  if (!g_checked[dev]) {
     hipDeviceProp_t prop;
     HIPCHK(hipGetDeviceProperties(&prop, dev));
     if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
       set_err("device architecture %s is not gfx950%lld", prop.gcnArchName, 0);
       throw Fail{ADAGIO_E_UNSUPPORTED};
     }
-    ws.checked = true;
+    g_checked[dev] = true;
   }
-  // work an earlier call left on the library's streams (a fit that ended in
-  // an error) must not overlap this call's use of the workspace
-  if (ws.aux) HIPCHK(hipStreamSynchronize(ws.aux));
-  if (ws.aux2) HIPCHK(hipStreamSynchronize(ws.aux2));
-  return ws;
+  return dev;
 }
 
-// rocBLAS handle of the workspace's device on stream st: deterministic
-// (no atomics), host scalars.
-static rocblas_handle blas_on(Workspace& ws, hipStream_t st) {
-  auto chk = [](rocblas_status e, const char* what) {
-    if (e != rocblas_status_success) {
-      set_err("rocBLAS %s failed (status %lld)", what, (long long)e);
-      throw Fail{ADAGIO_E_HIP};
+// The workspace of one call on `st`: the device's kept workspace, or a fresh
+// one that the call frees when it ends (after its stream has drained), on
+// success and on error alike.
+struct CallWs {
+  hipStream_t st;
+  Workspace* ws = nullptr;
+  Workspace* own = nullptr;
+  explicit CallWs(hipStream_t s) : st(s) {
+    const int dev = checked_device();
+    if (g_keep) {
+      if (!g_kept[dev]) {
+        g_kept[dev] = new Workspace();
+        if (!g_exit_hook) g_exit_hook = atexit(release_at_exit) == 0;
+      }
+      ws = g_kept[dev];
+      // work an earlier call left on the library's streams (a fit that ended
+      // in an error) must not overlap this call's use of the workspace
+      if (ws->aux) HIPCHK(hipStreamSynchronize(ws->aux));
+      if (ws->aux2) HIPCHK(hipStreamSynchronize(ws->aux2));
+    } else {
+      own = new Workspace();
+      ws = own;
     }
-  };
-  if (!ws.blas) {
-    chk(rocblas_create_handle(&ws.blas), "create_handle");
-    chk(rocblas_set_atomics_mode(ws.blas, rocblas_atomics_not_allowed), "set_atomics_mode");
-    chk(rocblas_set_pointer_mode(ws.blas, rocblas_pointer_mode_host), "set_pointer_mode");
   }
-  chk(rocblas_set_stream(ws.blas, st), "set_stream");
-  return ws.blas;
-}
-#define BLASCHK(expr)                                                            \
-  do {                                                                           \
-    rocblas_status b_ = (expr);                                                  \
-    if (b_ != rocblas_status_success) {                                          \
-      set_err("rocBLAS call failed (" #expr ", status %lld)", "", (long long)b_); \
-      throw Fail{ADAGIO_E_HIP};                                                  \
-    }                                                                            \
-  } while (0)
+  CallWs(const CallWs&) = delete;
+  CallWs& operator=(const CallWs&) = delete;
+  ~CallWs() {
+    if (own) {
+      (void)hipStreamSynchronize(st);
+      delete own;
+    }
+  }
+};
 
 // --------------------------------------------------------------- timing
 struct EvPair {
@@ -352,34 +404,28 @@ static const double* centred64(Workspace& ws, const Points& p, hipStream_t st) {
 }
 
 // The covariance of the non-constant coordinates, C = Xc^T Xc over the FP64
-// centred rows (plain products: rocBLAS), in full into ws.A0 (m_pad x m_pad,
-// zero padding).
+// centred rows (k_dgemm), in full into ws.A0 (m_pad x m_pad, zero padding).
 static double* covariance64(Workspace& ws, const Points& p, int m_pad, hipStream_t st) {
   const int64_t D = p.dx;
   double* A = ensure<double>(ws.A0, (size_t)m_pad * m_pad);
   const double* xc = centred64(ws, p, st);
-  // Split-K over row blocks so that a small D still fills the GPU: each block
-  // of kc rows gives a partial A_b A_b^T (one batched library GEMM; row-major
-  // rows x D is column-major D x rows), and k_cov_reduce adds the partials in
+  // Split-K over row blocks so that a small D still fills the GPU (about
+  // 2048 workgroups, at least 256 rows each): each block gives the upper
+  // tiles of a partial A_b^T A_b, and k_cov_reduce adds the partials in
   // block order and mirrors one triangle, so C is exactly symmetric.
   const int64_t np = rows64(p);
-  const int64_t tiles = ((D + 127) / 128) * ((D + 127) / 128);
-  int64_t nsplit = std::max<int64_t>(1, std::min<int64_t>(np / 4096 * 8, (512 + tiles - 1) / tiles));
-  while (np % nsplit) --nsplit;
-  const int64_t kc = np / nsplit;
+  const int64_t T = (D + dgemm_tile() - 1) / dgemm_tile();
+  const int64_t tiles = T * (T + 1) / 2;
+  const int64_t nsplit = std::max<int64_t>(1, std::min<int64_t>(np / 256, (2048 + tiles - 1) / tiles));
   double* part = ensure<double>(ws.covpart, (size_t)(nsplit * D * D));
-  const double one = 1.0, zero = 0.0;
-  BLASCHK(rocblas_dgemm_strided_batched(blas_on(ws, st), rocblas_operation_none, rocblas_operation_transpose,
-                                        (rocblas_int)D, (rocblas_int)D, (rocblas_int)kc, &one, xc, (rocblas_int)D,
-                                        (rocblas_stride)(kc * D), xc, (rocblas_int)D, (rocblas_stride)(kc * D), &zero,
-                                        part, (rocblas_int)D, (rocblas_stride)(D * D), (rocblas_int)nsplit));
+  HIPCHK(launch_dgemm_syrk_upper(xc, D, D, np, (int)nsplit, part, st));
   HIPCHK(launch_cov_reduce(part, (int)nsplit, D, m_pad, A, st));
   return A;
 }
 
 // Y64 = (X - mu) Pi^T in FP64 over the non-constant columns (constant ones
-// centre to exact zeros), a plain GEMM (rocBLAS) of the FP64 centred rows and
-// the FP64 values of the FP32 map.  Y64: n x r row-major.
+// centre to exact zeros), a k_dgemm product of the FP64 centred rows and the
+// FP64 values of the FP32 map.  Y64: n x r row-major.
 static void embed64(Workspace& ws, const Points& p, const float* Pi, int64_t r, double* Y64, hipStream_t st) {
   if (p.dx == 0) {
     HIPCHK(hipMemsetAsync(Y64, 0, sizeof(double) * (size_t)(p.n * r), st));
@@ -388,12 +434,8 @@ static void embed64(Workspace& ws, const Points& p, const float* Pi, int64_t r, 
   const double* xc = centred64(ws, p, st);
   double* P64 = ensure<double>(ws.pi64c, (size_t)(r * p.dx));
   HIPCHK(launch_cols64(Pi, r, p.d, p.colmap, p.dx, P64, st));
-  const double one = 1.0, zero = 0.0;
-  // column-major: Y^T (r x n, ld r) = op(P64) (r x dx) * Xc^T (dx x n, ld dx),
-  // P64 stored as column-major dx x r (ld dx), transposed
-  BLASCHK(rocblas_dgemm(blas_on(ws, st), rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)r,
-                        (rocblas_int)p.n, (rocblas_int)p.dx, &one, P64, (rocblas_int)p.dx, xc, (rocblas_int)p.dx,
-                        &zero, Y64, (rocblas_int)r));
+  // Y64[i][a] = sum_c xc[i][c] P64[a][c]  (P64: r x dx row-major)
+  HIPCHK(launch_dgemm_nt(xc, p.dx, P64, p.dx, p.n, r, p.dx, Y64, r, st));
 }
 
 // Randomized PCA (the paper's Sec. 4.5 variant, after Halko, Martinsson &
@@ -607,9 +649,9 @@ static void image_copies(Workspace& ws, const Points& p, Images& im, const doubl
 }
 
 // Screen images through the Gram factor, for a map with r >= d' + 32 rows
-// (d' non-constant coordinates): M = Pi'^T Pi' (d' x d', FP64 library GEMM
-// over the FP64 values of Pi's columns), M = L L^T (k_cholesky), and
-// Z = (X - mu)' L (n x d', FP64 library GEMM).  ||z_i - z_j||^2 = v^T L L^T v
+// (d' non-constant coordinates): M = Pi'^T Pi' (d' x d', FP64 k_dgemm over
+// the FP64 values of Pi's columns), M = L L^T (k_cholesky), and
+// Z = (X - mu)' L (n x d', FP64 k_dgemm).  ||z_i - z_j||^2 = v^T L L^T v
 // for the difference v of the non-constant coordinates, and
 // |v^T L L^T v - v^T M v| <= (gamma_r + 1.01 gamma_{d'+1}) ||Pi||_F^2 ||v||^2
 // (the dot products of M, then the factor's backward error).  Null when
@@ -618,13 +660,11 @@ static void image_copies(Workspace& ws, const Points& p, Images& im, const doubl
 static double* gram_factor_images(Workspace& ws, const Points& p, int64_t r, hipStream_t st) {
   const int64_t m = p.dx;
   if (m < 1 || m > chol_max_m() || r < m + 32) return nullptr;
-  const double* P64 = static_cast<const double*>(ws.pi64c.p);   // m x r, column-major, from embed64
+  const double* P64 = static_cast<const double*>(ws.pi64c.p);   // r x m, row-major, from embed64
   double* M = ensure<double>(ws.gfM, (size_t)(m * m));
   int* fail = ensure<int>(ws.gfFail, 1);
-  const double one = 1.0, zero = 0.0;
-  BLASCHK(rocblas_dgemm(blas_on(ws, st), rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)m,
-                        (rocblas_int)m, (rocblas_int)r, &one, P64, (rocblas_int)m, P64, (rocblas_int)m, &zero, M,
-                        (rocblas_int)m));
+  // M[c][c'] = sum_a P64[a][c] P64[a][c'] (symmetric: row- and column-major alike)
+  HIPCHK(launch_dgemm_tn(P64, m, P64, m, m, m, r, 1, M, m, st));
   HIPCHK(hipMemsetAsync(fail, 0, sizeof(int), st));
   HIPCHK(launch_cholesky(M, (int)m, fail, st));
   int hf = 0;
@@ -633,10 +673,8 @@ static double* gram_factor_images(Workspace& ws, const Points& p, int64_t r, hip
   if (hf) return nullptr;
   const double* xc = centred64(ws, p, st);
   double* Z = ensure<double>(ws.gfZ, (size_t)(p.n * m));
-  // column-major: Z^T (m x n, ld m) = L^T (m x m) * Xc^T (m x n, ld m)
-  BLASCHK(rocblas_dgemm(blas_on(ws, st), rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)m,
-                        (rocblas_int)p.n, (rocblas_int)m, &one, M, (rocblas_int)m, xc, (rocblas_int)m, &zero, Z,
-                        (rocblas_int)m));
+  // Z[i][j] = sum_c xc[i][c] L[c][j], L column-major in M: L[c][j] = M[j * m + c]
+  HIPCHK(launch_dgemm_nt(xc, m, M, m, p.n, m, m, Z, m, st));
   return Z;
 }
 
@@ -650,14 +688,16 @@ static Images images_of_map(Workspace& ws, const Points& p, const float* Pi, int
   embed64(ws, p, Pi, r, Y64, st);
   // FP64 embedding error: |E_64^2 - E^2| <= 4.02 gamma_{d'+1} ||Pi'||_F^2 (N_i + N_j)
   // over the d' non-constant coordinates (and ||L||_F^2 = trace(M) <=
-  // ||Pi'||_F^2 for the factor's images); ||Pi'||_F from the FP64 values of
-  // Pi's columns (library nrm2, inflated far beyond its rounding).
+  // ||Pi'||_F^2 for the factor's images); ||Pi'||_F^2 from the FP64 values of
+  // Pi's columns (a sum of squares, inflated far beyond its rounding).
   double pf2 = 0.0;
   if (p.dx > 0) {
-    double nrm = 0.0;
-    BLASCHK(rocblas_dnrm2(blas_on(ws, st), (rocblas_int)(p.dx * r), static_cast<const double*>(ws.pi64c.p), 1,
-                          &nrm));
-    pf2 = nrm * nrm * (1.0 + 1e-8);
+    const int nparts = 256;
+    double* part = ensure<double>(ws.nrm, nparts + 1);
+    HIPCHK(launch_sumsq(static_cast<const double*>(ws.pi64c.p), p.dx * r, part, nparts, part + nparts, st));
+    HIPCHK(hipMemcpyAsync(&pf2, part + nparts, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    pf2 *= 1.0 + 1e-8;
   }
   const double dx1 = (double)p.dx + 1.0;
   double c_emb = 4.02 * pf2 * dx1 * kU64 * 1.01;
@@ -1031,8 +1071,8 @@ static uint32_t pool_add(Workspace& ws, const Points& p, hipStream_t st) {
 }
 
 // The largest eq. (2) value over the pool's npool pairs under the map Pi
-// (r x d FP32), by direct differences: W = V Pi^T in FP64 (a plain library
-// GEMM over the non-constant coordinates).  i < 0: no pair with x_i != x_j.
+// (r x d FP32), by direct differences: W = V Pi^T in FP64 (k_dgemm over the
+// non-constant coordinates).  i < 0: no pair with x_i != x_j.
 static PairVal pool_witness(Workspace& ws, const Points& p, const float* Pi, int64_t r, uint32_t npool,
                             hipStream_t st) {
   PairVal w;
@@ -1048,11 +1088,8 @@ static PairVal pool_witness(Workspace& ws, const Points& p, const float* Pi, int
   PairVal* parts = ensure<PairVal>(ws.wparts, 2 * vp);
   CertDev* wcd = ensure<CertDev>(ws.wcd, 1);
   HIPCHK(launch_cols64(Pi, r, p.d, p.colmap, p.dx, P64, st));
-  const double one = 1.0, zero = 0.0;
-  // column-major: W^T (r x npool, ld r) = op(P64) (r x dx) * V^T (dx x npool, ld dx)
-  BLASCHK(rocblas_dgemm(blas_on(ws, st), rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)r,
-                        (rocblas_int)npool, (rocblas_int)p.dx, &one, P64, (rocblas_int)p.dx, V, (rocblas_int)p.dx,
-                        &zero, W, (rocblas_int)r));
+  // W[q][a] = sum_c V[q][c] P64[a][c]  (npool x r)
+  HIPCHK(launch_dgemm_nt(V, p.dx, P64, p.dx, npool, r, p.dx, W, r, st));
   HIPCHK(launch_pair_ratio(V, p.dx, W, r, pool, npool, vals, st));
   HIPCHK(launch_best_reset(wcd, st));
   HIPCHK(launch_top2(vals, pn, npool, parts, vp, wcd, st));
@@ -1173,7 +1210,8 @@ int adagio_pca(const float* X, int64_t n, int64_t d, double* lambda, double* Vt,
     check_points(X, n, d);
     ARGCHK(lambda && Vt, "lambda or Vt is NULL");
     hipStream_t st = as_stream(stream);
-    Workspace& ws = workspace();
+    CallWs cw(as_stream(stream));
+    Workspace& ws = *cw.ws;
     Points p = prep_points(ws, X, n, d, st);
     principal_axes(ws, p, st, lambda, Vt);
     HIPCHK(hipStreamSynchronize(st));
@@ -1188,7 +1226,8 @@ int adagio_pca_randomized(const float* X, int64_t n, int64_t d, int32_t ell, int
     ARGCHK(ell >= 1 && ell <= d, "ell must be in [1, d]");
     ARGCHK(power_iters >= 0 && power_iters <= 64, "power_iters must be in [0, 64]");
     hipStream_t st = as_stream(stream);
-    Workspace& ws = workspace();
+    CallWs cw(as_stream(stream));
+    Workspace& ws = *cw.ws;
     Points p = prep_points(ws, X, n, d, st);
     const int m = (int)round_up(d, 2 * bj_block());
     const double* C = covariance(ws, p, m, st);
@@ -1202,7 +1241,8 @@ int adagio_project_axes(const double* Vt, int64_t d, int32_t r, uint64_t seed, f
     ARGCHK(Vt && Pi_out, "Vt or Pi_out is NULL");
     ARGCHK(d >= 1, "need d >= 1");
     ARGCHK(r >= 1 && r <= d, "r must be in [1, d]");
-    Workspace& ws = workspace();
+    CallWs cw(as_stream(stream));
+    Workspace& ws = *cw.ws;
     build_map(ws, Vt, d, r, seed, Pi_out, as_stream(stream));
   });
 }
@@ -1214,7 +1254,8 @@ int adagio_project_family(const double* Vt, int64_t d, int32_t r, int32_t family
     ARGCHK(d >= 1, "need d >= 1");
     ARGCHK(r >= 1 && r <= d, "r must be in [1, d]");
     ARGCHK(family == ADAGIO_MAP_ADAGIO || family == ADAGIO_MAP_PCA || family == ADAGIO_MAP_JL, "unknown map family");
-    Workspace& ws = workspace();
+    CallWs cw(as_stream(stream));
+    Workspace& ws = *cw.ws;
     build_family_map(ws, family, Vt, d, r, seed, Pi_out, as_stream(stream));
   });
 }
@@ -1225,7 +1266,8 @@ int adagio_project(const float* X, int64_t n, int64_t d, int32_t r, uint64_t see
     ARGCHK(Pi_out, "Pi_out is NULL");
     ARGCHK(r >= 1 && r <= d, "r must be in [1, d]");
     hipStream_t st = as_stream(stream);
-    Workspace& ws = workspace();
+    CallWs cw(as_stream(stream));
+    Workspace& ws = *cw.ws;
     Points p = prep_points(ws, X, n, d, st);
     Axes ax = principal_axes(ws, p, st);
     build_map(ws, ax.Vt, d, r, seed, Pi_out, st);
@@ -1238,7 +1280,7 @@ int adagio_embed(const float* X, int64_t n, int64_t d, const float* Pi, int32_t 
     ARGCHK(X && Pi && Y_out, "NULL pointer");
     ARGCHK(n >= 1 && d >= 1, "need n >= 1 and d >= 1");
     ARGCHK(r >= 1, "need r >= 1");
-    (void)workspace();
+    (void)checked_device();
     HIPCHK(launch_embed_f32(X, n, d, Pi, r, Y_out, as_stream(stream)));
   });
 }
@@ -1254,7 +1296,8 @@ int adagio_max_distortion(const float* X, int64_t n, int64_t d, const float* Y, 
            "unknown screen precision");
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = as_stream(stream);
-    Workspace& ws = workspace();
+    CallWs cw(as_stream(stream));
+    Workspace& ws = *cw.ws;
     Points p = prep_points(ws, X, n, d, st, screen);
     Images im = images_given(ws, p, Y, r, st);
     CertTimes tm;
@@ -1276,7 +1319,8 @@ int adagio_certify_map(const float* X, int64_t n, int64_t d, const float* Pi, in
            "unknown screen precision");
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = as_stream(stream);
-    Workspace& ws = workspace();
+    CallWs cw(as_stream(stream));
+    Workspace& ws = *cw.ws;
     Points p = prep_points(ws, X, n, d, st, screen);
     Images im = images_of_map(ws, p, Pi, r, st);
     CertTimes tm;
@@ -1311,7 +1355,8 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     ARGCHK(no_witness == 0 || no_witness == 1, "no_witness must be 0 or 1");
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = as_stream(stream);
-    Workspace& ws = workspace();
+    CallWs cw(as_stream(stream));
+    Workspace& ws = *cw.ws;
     const uint32_t cap0 = opts ? (uint32_t)std::max(0, opts->max_candidates) : 0u;
     EvPair e_pca, e_search;
     e_pca.begin(st);
@@ -1488,7 +1533,7 @@ int adagio_quantize_fp8(const float* A, int64_t n, int64_t m, uint8_t* Q_out, fl
   return guarded([&] {
     ARGCHK(A && Q_out && scale_out && norm2_out, "NULL pointer");
     ARGCHK(n >= 1 && m >= 1, "need n >= 1 and m >= 1");
-    (void)workspace();
+    (void)checked_device();
     HIPCHK(launch_quant_fp8(A, n, m, m, m, Q_out, scale_out, norm2_out, as_stream(stream)));
   });
 }
@@ -1500,7 +1545,8 @@ int adagio_sketch_features(const float* X, int64_t n, int64_t d, double eps, uin
     ARGCHK(feat_out, "feat_out is NULL");
     ARGCHK(eps > 0.0 && eps < 1.0, "eps must be in (0, 1)");
     hipStream_t st = as_stream(stream);
-    Workspace& ws = workspace();
+    CallWs cw(as_stream(stream));
+    Workspace& ws = *cw.ws;
     Points p = prep_points(ws, X, n, d, st);
     sketch_features(ws, p, eps, seed, feat_out, st);
     HIPCHK(hipStreamSynchronize(st));
@@ -1514,7 +1560,8 @@ int adagio_mlp_forward(const float* params, const float* feats, int32_t B, float
     ARGCHK(params && feats && out, "NULL pointer");
     ARGCHK(B >= 1 && B <= (1 << 20), "batch must be in [1, 2^20]");
     hipStream_t st = as_stream(stream);
-    Workspace& ws = workspace();
+    CallWs cw(as_stream(stream));
+    Workspace& ws = *cw.ws;
     const MlpLayout L = mlp_layout();
     MlpBufs b = mlp_bufs(ws, L, B);
     HIPCHK(mlp_to_bf16(params, b.pb, L.total, st));
@@ -1530,7 +1577,8 @@ int adagio_mlp_grad(const float* params, const float* feats, const float* target
     ARGCHK(B >= 1 && B <= (1 << 20), "batch must be in [1, 2^20]");
     ARGCHK(tau > 0.0f && tau < 1.0f, "tau must be in (0, 1)");
     hipStream_t st = as_stream(stream);
-    Workspace& ws = workspace();
+    CallWs cw(as_stream(stream));
+    Workspace& ws = *cw.ws;
     const MlpLayout L = mlp_layout();
     MlpBufs b = mlp_bufs(ws, L, B);
     HIPCHK(mlp_to_bf16(params, b.pb, L.total, st));
@@ -1549,7 +1597,8 @@ int adagio_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t s
     ARGCHK(step >= 1, "step is 1-based");
     ARGCHK(tau > 0.0f && tau < 1.0f, "tau must be in (0, 1)");
     hipStream_t st = as_stream(stream);
-    Workspace& ws = workspace();
+    CallWs cw(as_stream(stream));
+    Workspace& ws = *cw.ws;
     const MlpLayout L = mlp_layout();
     MlpBufs b = mlp_bufs(ws, L, B);
     float* grad = ensure<float>(ws.mlp_grad, (size_t)L.total);
@@ -1575,7 +1624,8 @@ int adagio_knn(const float* Q, int64_t nq, const float* D, int64_t nd, int64_t m
     ARGCHK(!exclude_self || nq <= nd, "exclude_self needs nq <= nd (query i is database row i)");
     ARGCHK(k <= nd - exclude_self, "k exceeds the number of database rows");
     hipStream_t st = as_stream(stream);
-    Workspace& ws = workspace();
+    CallWs cw(as_stream(stream));
+    Workspace& ws = *cw.ws;
     const int64_t K = round_up(m, kChunk);
     const int64_t nq_pad = round_up(nq, kTile), nd_pad = round_up(nd, kTile);
     KnnView v;
@@ -1659,7 +1709,8 @@ int adagio_knn_vote(const int32_t* nn_idx, int64_t nq, int32_t k, const int32_t*
     ARGCHK(n_labels >= 1 && n_labels <= 8192, "n_labels must be in [1, 8192]");
     ARGCHK(group >= 1, "group must be >= 1");
     hipStream_t st = as_stream(stream);
-    Workspace& ws = workspace();
+    CallWs cw(as_stream(stream));
+    Workspace& ws = *cw.ws;
     int* bad = ensure<int>(ws.knCnt, 2);
     HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), st));
     HIPCHK(launch_knn_vote(nn_idx, nq, k, d_label, nd, n_labels, group, label_out, bad, st));
@@ -1674,40 +1725,17 @@ int adagio_release(void) {
   return guarded([&] {
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
-    if (dev < 0 || dev >= 64) return;
-    Workspace& ws = g_ws[dev];
-    DevBuf* bufs[] = {&ws.mu, &ws.colpart, &ws.nonfinite, &ws.Xc, &ws.nx, &ws.tx, &ws.covpart, &ws.A0, &ws.A1,
-                      &ws.W, &ws.trace, &ws.rot, &ws.lam, &ws.Vt, &ws.S, &ws.T, &ws.Pi, &ws.Pi64, &ws.Y64,
-                      &ws.Yc, &ws.ny, &ws.ty, &ws.muY, &ws.recs, &ws.tparts, &ws.seeds, &ws.seedv, &ws.list,
-                      &ws.cand, &ws.vals, &ws.vparts, &ws.cd, &ws.Xb, &ws.txb, &ws.Yb, &ws.tyb, &ws.bjU, &ws.bjS,
-                      &ws.Xq, &ws.sx, &ws.nxq, &ws.Yq, &ws.sy, &ws.nyq, &ws.q8terms, &ws.hist, &ws.kthr, &ws.gcache, &ws.rpQ, &ws.rpY,
-                      &ws.rpG, &ws.rpV, &ws.rpLam,
-                      &ws.skpart, &ws.skG, &ws.skK, &ws.sklam, &ws.skV, &ws.skfeat, &ws.mlp_pb, &ws.mlp_X,
-                      &ws.mlp_f, &ws.mlp_hb, &ws.mlp_grad, &ws.mlp_loss, &ws.knQ, &ws.knD, &ws.knNq64,
-                      &ws.knNd64, &ws.knNq32, &ws.knNd32, &ws.knMax, &ws.knKeys, &ws.knFb, &ws.knCnt, &ws.knTau,
-                      &ws.lam1, &ws.Vt1, &ws.colmap, &ws.xc64, &ws.pi64c,
-                      &ws.colminmax, &ws.colkeep, &ws.pool, &ws.pooln, &ws.wvals, &ws.wparts, &ws.wcd,
-                      &ws.wV, &ws.wW, &ws.stopn, &ws.stopp, &ws.gfM, &ws.gfFail, &ws.gfZ};
-    for (DevBuf* b : bufs) {
-      if (b->p) HIPCHK(hipFree(b->p));
-      b->p = nullptr;
-      b->cap = 0;
-    }
-    if (ws.blas) {
-      (void)rocblas_destroy_handle(ws.blas);
-      ws.blas = nullptr;
-    }
-    for (hipStream_t* q : {&ws.aux, &ws.aux2}) {
-      if (*q) {
-        HIPCHK(hipStreamSynchronize(*q));
-        (void)hipStreamDestroy(*q);
-        *q = nullptr;
-      }
-    }
-    for (hipEvent_t* e : {&ws.ev_in, &ws.ev_out, &ws.ev_t0, &ws.ev_t1, &ws.ev_pca, &ws.ev_cov}) {
-      if (*e) (void)hipEventDestroy(*e);
-      *e = nullptr;
-    }
+    if (dev < 0 || dev >= 64 || !g_kept[dev]) return;
+    delete g_kept[dev];
+    g_kept[dev] = nullptr;
+  });
+}
+
+int adagio_keep_workspace(int keep) {
+  return guarded([&] {
+    ARGCHK(keep == 0 || keep == 1, "keep must be 0 or 1");
+    g_keep = keep == 1;
+    if (!g_keep) release_kept_all();
   });
 }
 

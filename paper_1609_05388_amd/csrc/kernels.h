@@ -46,6 +46,23 @@ hipError_t launch_eig_sort(const double* A, const double* W, int m, int d, doubl
 hipError_t launch_scatter_axes(const double* lam1, const double* Vt1, const int* idx, int d1, int d, double* lam,
                                double* Vt, hipStream_t st);
 
+// k_dgemm.hip: FP64 MFMA products on 128 x 128 tiles (row-major operands).
+// nt: C[m][n] = sum_k A[m][k] B[n][k];  nn: C[m][n] = sum_k A[m][k] B[k][n];
+// tn: C[m][n] = sum_k A[k][m] B[k][n], split over k into nsplit partials
+// C + s M ldc; syrk_upper: the upper 128 x 128 tiles of A^T A (A: K x M),
+// split over k into nsplit partials part + s M M (row stride M).
+hipError_t launch_dgemm_nt(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M, int64_t N,
+                           int64_t K, double* C, int64_t ldc, hipStream_t st);
+hipError_t launch_dgemm_nn(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M, int64_t N,
+                           int64_t K, double* C, int64_t ldc, hipStream_t st);
+hipError_t launch_dgemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M, int64_t N,
+                           int64_t K, int nsplit, double* C, int64_t ldc, hipStream_t st);
+hipError_t launch_dgemm_syrk_upper(const double* A, int64_t lda, int64_t M, int64_t K, int nsplit, double* part,
+                                   hipStream_t st);
+int dgemm_tile();
+// *out = sum of a[e]^2 (FP64), through nparts block partials in part.
+hipError_t launch_sumsq(const double* a, int64_t count, double* part, int nparts, double* out, hipStream_t st);
+
 // k_chol.hip: in-place Cholesky factor (lower, strict upper zeroed) of an
 // SPD m x m column-major FP64 matrix, m <= chol_max_m(); *fail = 1 on a
 // non-positive pivot.

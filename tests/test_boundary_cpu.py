@@ -132,3 +132,13 @@ def test_invalid_arguments_rejected_without_gpu(lib):
     assert lib.adagio_max_distortion(fake, 10, 32769, fake, 3, None, ctypes.byref(c), None) == -5
     assert lib.adagio_certify_map(fake, 600000, 8192, fake, 3, None, ctypes.byref(c), None) == -5
     assert b"n x d" in lib.adagio_last_error()
+
+
+def test_workspace_mode_argument(lib):
+    """adagio_keep_workspace takes 0 or 1; other values are refused before any
+    device work (keep = 0 with nothing kept touches no device)."""
+    assert lib.adagio_keep_workspace(2) == -1
+    assert b"keep must be 0 or 1" in lib.adagio_last_error()
+    assert lib.adagio_keep_workspace(-1) == -1
+    assert lib.adagio_keep_workspace(0) == 0
+
