@@ -217,6 +217,27 @@ int adagio_embed(const float* X, int64_t n, int64_t d, const float* Pi, int32_t 
 int adagio_max_distortion(const float* X, int64_t n, int64_t d, const float* Y, int32_t r,
                           const adagio_opts_t* opts, adagio_cert_t* cert_out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * certificate of adagio_max_distortion with the FP32 screen, every buffer
+ * carved from one fixed 64 MiB device array that the library holds on each
+ * GPU it runs on until the process ends; no hipMalloc, hipFree or allocating
+ * library call.  The array holds the FP32 copies of the centred points and
+ * images (about 4 n (d + r) bytes, n and d, r padded to 128 and 16), the
+ * tile records and room for at least 65536 candidate pairs (32 bytes each);
+ * inputs that need more return ADAGIO_E_UNSUPPORTED before any device work,
+ * and so does opts->screen other than ADAGIO_SCREEN_F32.  The candidate
+ * buffer does not grow: when the pairs to re-evaluate exceed the room left
+ * (or opts->max_candidates), the result is an incomplete certificate
+ * (certified = 0 with the proven bound_rest) where adagio_max_distortion
+ * would grow its buffer and finish.  Every call on a GPU reuses that GPU's
+ * array and leaves its contents behind (what must start at zero is cleared
+ * by each call); calls are serialised by the library's lock and synchronise
+ * `stream`, so two calls overlap only when made from separate processes,
+ * which hold separate arrays.  cert_out: host.  Synchronises `stream`. */
+int adagio_max_distortion_noalloc(const float* X, int64_t n, int64_t d, const float* Y, int32_t r,
+                                  const adagio_opts_t* opts, adagio_cert_t* cert_out, void* stream);
+
 /* a6-a8.  Certificate of eq. (3) for the linear map Pi (r x d FP32, device)
  * applied exactly: images are formed in FP64 from the FP32 entries of X and
  * Pi, so the result is the distortion of Pi itself.  When Pi has at least

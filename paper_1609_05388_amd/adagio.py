@@ -88,6 +88,8 @@ SIGNATURES = {
     "adagio_embed": (ctypes.c_int, [_P, _I64, _I64, _P, _I32, _P, _P]),
     "adagio_max_distortion": (ctypes.c_int, [_P, _I64, _I64, _P, _I32, ctypes.POINTER(Opts),
                                              ctypes.POINTER(Cert), _P]),
+    "adagio_max_distortion_noalloc": (ctypes.c_int, [_P, _I64, _I64, _P, _I32, ctypes.POINTER(Opts),
+                                                     ctypes.POINTER(Cert), _P]),
     "adagio_certify_map": (ctypes.c_int, [_P, _I64, _I64, _P, _I32, ctypes.POINTER(Opts),
                                           ctypes.POINTER(Cert), _P]),
     "adagio_fit": (ctypes.c_int, [_P, _I64, _I64, _D, _U64, ctypes.POINTER(Opts), _P,
@@ -232,6 +234,24 @@ def max_distortion(X, Y, screen="f32", max_candidates=0, with_stats=False):
     c = Cert()
     _check(lib.adagio_max_distortion(_dev(X, torch.float32, "X"), n, d, _dev(Y, torch.float32, "Y"),
                                      Y.shape[1], ctypes.byref(o), ctypes.byref(c), _stream()))
+    out = c.to_dict()
+    if st is not None:
+        out["stats"] = st.to_dict()
+    return out
+
+
+def max_distortion_noalloc(X, Y, max_candidates=0, with_stats=False):
+    """adagio_max_distortion_noalloc: the FP32-screen certificate with every
+    buffer in the library's fixed device array (no allocation)."""
+    lib = load()
+    n, d = X.shape
+    if Y.shape[0] != n:
+        raise ValueError("Y must have one row per point")
+    st = Stats() if with_stats else None
+    o = _opts("f32", max_candidates=max_candidates, stats=st)
+    c = Cert()
+    _check(lib.adagio_max_distortion_noalloc(_dev(X, torch.float32, "X"), n, d, _dev(Y, torch.float32, "Y"),
+                                             Y.shape[1], ctypes.byref(o), ctypes.byref(c), _stream()))
     out = c.to_dict()
     if st is not None:
         out["stats"] = st.to_dict()

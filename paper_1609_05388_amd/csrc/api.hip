@@ -48,15 +48,17 @@ static void set_err(const char* fmt, const char* a = "", long long b = 0) {
   } while (0)
 
 // --------------------------------------------------------------- workspace
-// A device buffer that grows on demand and is freed with its owner.
+// A device buffer that grows on demand and is freed with its owner (unless
+// it was carved from a call's fixed arena).
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
+  bool owned = true;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() {
-    if (p) (void)hipFree(p);
+    if (p && owned) (void)hipFree(p);
   }
 };
 
@@ -127,14 +129,37 @@ static void release_at_exit() {
   g_mu.unlock();
 }
 
+// A fixed device region that a call carves its buffers from instead of
+// allocating (adagio_max_distortion_noalloc); set while such a call runs.
+struct Arena {
+  unsigned char* base = nullptr;
+  size_t size = 0, used = 0;
+};
+static Arena* g_arena = nullptr;
+
 template <typename T>
 static T* ensure(DevBuf& b, size_t count) {
   size_t bytes = count * sizeof(T);
   if (bytes == 0) bytes = 256;
   if (b.cap < bytes) {
-    if (b.p) HIPCHK(hipFree(b.p));
+    if (g_arena) {
+      // grows by carving a new piece (the old one stays unused)
+      const size_t off = (size_t)round_up((int64_t)g_arena->used, 256);
+      if (off > g_arena->size || bytes > g_arena->size - off) {
+        set_err("scratch array exhausted%s (needs %lld more bytes)", "", (long long)(off + bytes - g_arena->size));
+        throw Fail{ADAGIO_E_UNSUPPORTED};
+      }
+      if (b.p && b.owned) HIPCHK(hipFree(b.p));
+      b.p = g_arena->base + off;
+      b.cap = bytes;
+      b.owned = false;
+      g_arena->used = off + bytes;
+      return static_cast<T*>(b.p);
+    }
+    if (b.p && b.owned) HIPCHK(hipFree(b.p));
     b.p = nullptr;
     b.cap = 0;
+    b.owned = true;
     HIPCHK(hipMalloc(&b.p, bytes));
     b.cap = bytes;
   }
@@ -198,12 +223,17 @@ struct CallWs {
 // --------------------------------------------------------------- timing
 struct EvPair {
   hipEvent_t a = nullptr, b = nullptr;
+  bool on = true;    // off: no events are created or recorded, ms() is 0
   void begin(hipStream_t st) {
+    if (!on) return;
     if (!a) { HIPCHK(hipEventCreate(&a)); HIPCHK(hipEventCreate(&b)); }
     HIPCHK(hipEventRecord(a, st));
   }
-  void end(hipStream_t st) { HIPCHK(hipEventRecord(b, st)); }
+  void end(hipStream_t st) {
+    if (on) HIPCHK(hipEventRecord(b, st));
+  }
   double ms() {
+    if (!on) return 0.0;
     float t = 0.f;
     HIPCHK(hipEventElapsedTime(&t, a, b));
     return (double)t;
@@ -849,9 +879,12 @@ static float f32_down(double x) {
   return f;
 }
 
+// grow = false: the candidate buffer keeps capacity cap0 (a fixed arena);
+// more candidates than that leave the certificate incomplete.
 static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& im, uint32_t cap0,
                                  hipStream_t st, CertTimes* times, int screen, float* gcache = nullptr,
-                                 int gmode = 0, double stop_eps = -1.0, StopOut* so = nullptr) {
+                                 int gmode = 0, double stop_eps = -1.0, StopOut* so = nullptr,
+                                 bool grow = true) {
   PairsView v;
   v.X = p.Xc; v.ldx = (int)p.ldx;
   v.Y = im.Yc; v.ldy = (int)im.ldy;
@@ -882,6 +915,7 @@ static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& i
     sp = &ss;
   }
   EvPair e_screen, e_rest;
+  e_screen.on = e_rest.on = times != nullptr;
   auto run_screen = [&](const ScreenStop* stop) {
     e_screen.begin(st);
     if (screen == ADAGIO_SCREEN_BF16X3) {
@@ -974,7 +1008,7 @@ static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& i
     HIPCHK(launch_top2(vals, &cd->n_cand, cap, vparts, vp, cd, st));
     HIPCHK(hipMemcpyAsync(&h, cd, sizeof(CertDev), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    if (h.n_cand <= cap || cap >= kHardCap) break;
+    if (h.n_cand <= cap || cap >= kHardCap || !grow) break;
     // More candidates than room: grow and redo the exact pass (the thresholds
     // and flagged tiles are unchanged).
     cap = h.n_cand > kHardCap ? kHardCap : h.n_cand;
@@ -1185,6 +1219,45 @@ static int guarded(F&& f) {
 static const int64_t kMaxPoints = 700000;
 static const int64_t kMaxDim = 32768;
 
+// Scratch of adagio_max_distortion_noalloc: a fixed device array (one copy
+// on each GPU the library runs on, held until the process ends).  Host code
+// uses its device address from hipGetSymbolAddress, taken once per device
+// with that device current; the array's name is only a host-side stand-in.
+static const size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static void* g_scratch[64];
+// candidate pairs the scratch must leave room for beyond the fixed buffers
+static const uint32_t kScratchMinCand = 1u << 16;
+
+static void* scratch_ptr(int dev) {
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch[dev] = ptr;
+  }
+  return g_scratch[dev];
+}
+
+// Bytes the FP32-screen certificate of n points (d coordinates) and r image
+// coordinates carves from an arena before its candidate buffers: every
+// buffer of prep_points, images_given and certificate, each rounded up to
+// 256 bytes (an upper bound: the screens' copies may have fewer columns).
+static size_t noalloc_fixed_bytes(int64_t n, int64_t d, int64_t r) {
+  const int64_t n_pad = round_up(n, kTile), nch = (n + 511) / 512;
+  const int64_t ldx = round_up(d, kChunk), ldy = round_up(r, kChunk);
+  const int64_t NT = n_pad / kTile, ntiles = NT * (NT + 1) / 2;
+  const int64_t sizes[] = {
+      d * 8, d * 4, nch * d * 8, 2 * 4, 2 * nch * d * 8, d * 4,              // mu, colmap, mean_rows(X)
+      n_pad * ldx * 4, n_pad * 8, n_pad * 8,                                  // Xc, nx, tx
+      r * 8, nch * r * 8, n_pad * ldy * 4, n_pad * 8, n_pad * 8,              // muY, mean_rows(Y), Yc, ny, ty
+      ntiles * (int64_t)sizeof(TileRec), 257 * (int64_t)sizeof(TileRec), 2 * 8,  // recs, tparts, seeds
+      2 * (int64_t)sizeof(PairVal), ntiles * 4, (int64_t)sizeof(CertDev),     // seedv, list, cd
+      128 * (int64_t)sizeof(PairVal)};                                        // vparts
+  size_t tot = 0;
+  for (int64_t b : sizes) tot += (size_t)round_up(std::max<int64_t>(b, 1), 256) + 256;
+  return tot;
+}
+
 static void check_points(const float* X, int64_t n, int64_t d) {
   ARGCHK(X != nullptr, "X is NULL");
   ARGCHK(n >= 2, "need n >= 2 points");
@@ -1303,6 +1376,50 @@ int adagio_max_distortion(const float* X, int64_t n, int64_t d, const float* Y, 
     CertTimes tm;
     *cert_out = certificate(ws, p, im, opts ? (uint32_t)std::max(0, opts->max_candidates) : 0u, st, &tm, screen);
     if (opts && opts->stats)
+      fill_stats(opts->stats, tm, 1,
+                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+  });
+}
+
+int adagio_max_distortion_noalloc(const float* X, int64_t n, int64_t d, const float* Y, int32_t r,
+                                  const adagio_opts_t* opts, adagio_cert_t* cert_out, void* stream) {
+  return guarded([&] {
+    check_points(X, n, d);
+    ARGCHK(Y && cert_out, "Y or cert_out is NULL");
+    ARGCHK(r >= 1, "need r >= 1");
+    const int screen = opts ? opts->screen : ADAGIO_SCREEN_F32;
+    ARGCHK(screen == ADAGIO_SCREEN_F32 || screen == ADAGIO_SCREEN_BF16X3 || screen == ADAGIO_SCREEN_FP8,
+           "unknown screen precision");
+    if (screen != ADAGIO_SCREEN_F32) {
+      set_err("the no-allocation certificate runs the FP32 screen only%s%lld", "", 0);
+      throw Fail{ADAGIO_E_UNSUPPORTED};
+    }
+    const size_t fixed = noalloc_fixed_bytes(n, d, r);
+    const size_t cand_bytes = sizeof(int2) + sizeof(PairVal);
+    if (fixed + 512 + (size_t)kScratchMinCand * cand_bytes > kScratchBytes) {
+      set_err("n, d and r need %s%lld bytes of scratch; the no-allocation entry point has 64 MiB", "",
+              (long long)(fixed + 512 + (size_t)kScratchMinCand * cand_bytes));
+      throw Fail{ADAGIO_E_UNSUPPORTED};
+    }
+    uint32_t cap = (uint32_t)std::min<size_t>(kDefaultCap, (kScratchBytes - fixed - 512) / cand_bytes);
+    if (opts && opts->max_candidates > 0) cap = std::min<uint32_t>(cap, (uint32_t)opts->max_candidates);
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = as_stream(stream);
+    const int dev = checked_device();
+    Arena arena;
+    arena.base = static_cast<unsigned char*>(scratch_ptr(dev));
+    arena.size = kScratchBytes;
+    struct ArenaScope {
+      explicit ArenaScope(Arena* a) { g_arena = a; }
+      ~ArenaScope() { g_arena = nullptr; }
+    } arena_scope(&arena);
+    Workspace ws;   // every buffer carved from the arena; no streams or events
+    Points p = prep_points(ws, X, n, d, st, screen);
+    Images im = images_given(ws, p, Y, r, st);
+    CertTimes tm;
+    const bool timed = opts && opts->stats;
+    *cert_out = certificate(ws, p, im, cap, st, timed ? &tm : nullptr, screen, nullptr, 0, -1.0, nullptr, false);
+    if (timed)
       fill_stats(opts->stats, tm, 1,
                  std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
   });

@@ -142,3 +142,17 @@ def test_workspace_mode_argument(lib):
     assert lib.adagio_keep_workspace(-1) == -1
     assert lib.adagio_keep_workspace(0) == 0
 
+
+def test_noalloc_certificate_refuses_before_device_work(lib):
+    """The no-allocation certificate refuses inputs beyond its fixed scratch
+    array, and screens other than FP32, on the host."""
+    from paper_1609_05388_amd import adagio
+    fake = ctypes.c_void_p(0x1000)
+    c = adagio.Cert()
+    assert lib.adagio_max_distortion_noalloc(fake, 20000, 784, fake, 256, None, ctypes.byref(c), None) == -5
+    assert b"64 MiB" in lib.adagio_last_error()
+    o = adagio.Opts()
+    o.screen = 1
+    assert lib.adagio_max_distortion_noalloc(fake, 100, 8, fake, 3, ctypes.byref(o), ctypes.byref(c), None) == -5
+    assert b"FP32 screen only" in lib.adagio_last_error()
+    assert lib.adagio_max_distortion_noalloc(fake, 100, 8, None, 3, None, ctypes.byref(c), None) == -1
