@@ -364,7 +364,9 @@ def fp8_form(adagio, gen, torch, Xd, eps, steps, plain_s, plain, npairs, d):
 
 def learned_form(adagio, gen, torch, Xd, eps, steps, plain_s, plain):
     """Fit from the trained predictor's r (certified, bisection fallback),
-    with exact PCA and with the randomized PCA for the predicted s."""
+    with exact PCA and with the randomized PCA for the predicted s, on the
+    MNIST-shaped cloud: outside the predictor's training range (n <= 20000),
+    so r there says nothing about the learned form's accuracy."""
     from paper_1609_05388_amd import learned
     if not os.path.exists(learned.PREDICTOR):
         return None
@@ -381,6 +383,67 @@ def learned_form(adagio, gen, torch, Xd, eps, steps, plain_s, plain):
             "with_randomized_pca": {"fit_ms": rs * 1e3, "speedup_vs_plain": plain_s / rs, "r": ro["r"],
                                     "max_distortion": ro["cert"]["max_distortion"],
                                     "certified": ro["cert"]["certified"]}}
+
+
+def learned_heldout(adagio, gen, torch, count):
+    """The learned form where it is defined: the first `count` held-out
+    instances of the learned-form workload (n in [1000, 20000], d in
+    {128, 256, 784, 2048}, power-law spectra, eps in [0.05, 0.3]; never seen
+    in training).  Per instance one warm-up fit, then plain bisection, the
+    learned search (certified prediction, bisection fallback) and the learned
+    search with downward refinement, each timed once (FP32 screen)."""
+    import numpy as np
+    from paper_1609_05388_amd import learned
+    if not os.path.exists(learned.PREDICTOR):
+        return None
+    P = learned.load_predictor(learned.PREDICTOR)
+    modes = (("plain", {}), ("learned", {"search": "learned", "predictor": P}),
+             ("learned_refine", {"search": "learned", "predictor": P, "refine": True}))
+    rows = []
+    t0 = time.perf_counter()
+    for index, pr, X in learned.instances(list(range(count)), held_out=True):
+        Xd = torch.from_numpy(X).cuda()
+        adagio.fit(Xd, pr["eps"], gen.JL_SEED)
+        row = {"index": index, "n": pr["n"], "d": pr["d"], "eps": pr["eps"]}
+        for name, kw in modes:
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            o = adagio.fit(Xd, pr["eps"], gen.JL_SEED, **kw)
+            torch.cuda.synchronize()
+            c = o["cert"]
+            row[name] = {"ms": (time.perf_counter() - ta) * 1e3, "r": o["r"],
+                         "certificates": o["stats"]["n_certificates"], "fallback": o["stats"]["n_fallback"],
+                         "r_predicted": o["stats"]["r_predicted"],
+                         "proven": bool(c["max_distortion"] <= pr["eps"] if c["certified"] == 1
+                                        else c["bound_rest"] <= pr["eps"]),
+                         "t_pca_ms": o["stats"]["t_pca_ms"]}
+        rows.append(row)
+        del Xd
+    out = {"instances": len(rows), "seconds": time.perf_counter() - t0, "screen": "f32",
+           "d_counts": {str(d): sum(1 for r in rows if r["d"] == d) for d in (128, 256, 784, 2048)},
+           "workload": "held-out learned-form instances 0..%d (n U{1000..20000}, d in {128, 256, 784, 2048}, "
+                       "power-law spectrum exponent U[0.5, 2] at rank U{10..200}, noise 0.01, eps U[0.05, 0.3])"
+                       % (count - 1)}
+    plain_ms = sum(r["plain"]["ms"] for r in rows)
+    for name, _ in modes:
+        ms = sum(r[name]["ms"] for r in rows)
+        out[name] = {"fit_ms_total": ms, "speedup_vs_plain": plain_ms / ms,
+                     "mean_certificates": float(np.mean([r[name]["certificates"] for r in rows])),
+                     "mean_pca_ms": float(np.mean([r[name]["t_pca_ms"] for r in rows])),
+                     "fallback_rate": float(np.mean([r[name]["fallback"] for r in rows])),
+                     "mean_r_over_plain": float(np.mean([r[name]["r"] / r["plain"]["r"] for r in rows])),
+                     "max_r_over_plain": float(max(r[name]["r"] / r["plain"]["r"] for r in rows)),
+                     "same_r_as_plain": float(np.mean([r[name]["r"] == r["plain"]["r"] for r in rows])),
+                     "all_proven_within_eps": bool(all(r[name]["proven"] for r in rows))}
+    log("learned held-out (%d instances): learned %.2fx (r %.3f), refined %.2fx (r %.3f)" % (
+        len(rows), out["learned"]["speedup_vs_plain"], out["learned"]["mean_r_over_plain"],
+        out["learned_refine"]["speedup_vs_plain"], out["learned_refine"]["mean_r_over_plain"]))
+    out["per_instance"] = [[r["index"], r["n"], r["d"], round(r["eps"], 4), r["plain"]["r"], r["learned"]["r"],
+                            r["learned_refine"]["r"], round(r["plain"]["ms"], 2), round(r["learned"]["ms"], 2),
+                            round(r["learned_refine"]["ms"], 2)] for r in rows]
+    out["per_instance_columns"] = ["index", "n", "d", "eps", "r_plain", "r_learned", "r_refined", "ms_plain",
+                                   "ms_learned", "ms_refined"]
+    return out
 
 
 def large_form(adagio, gen, torch, eps, oracle_blocks):
@@ -573,6 +636,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the precision-form fits")
     ap.add_argument("--no-large", action="store_true", help="skip the n=200000, d=4096 precision-form fit")
     ap.add_argument("--no-knn", action="store_true", help="skip the kNN retrieval application")
+    ap.add_argument("--learned-instances", type=int, default=64,
+                    help="held-out learned-form instances for the learned search's gain (0: none)")
     ap.add_argument("--no-witness", action="store_true",
                     help="plain fits certify every probe in full (every screen launch whole: the counter runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -740,8 +805,12 @@ def main():
         log("randomized-PCA fit %.1f ms (%.2fx), r=%d" % (rs * 1e3, fit_s / rs, ro["r"]))
         lf = learned_form(adagio, gen, torch, Xd, args.eps, args.steps, fit_s, last)
         if lf:
-            forms["learned"] = lf
-            log("learned fit %.1f ms (%.2fx)" % (lf["fit_ms"], lf["speedup_vs_plain"]))
+            forms["learned_out_of_distribution"] = lf
+            log("learned fit (out of distribution) %.1f ms (%.2fx)" % (lf["fit_ms"], lf["speedup_vs_plain"]))
+        if args.learned_instances > 0:
+            lh = learned_heldout(adagio, gen, torch, args.learned_instances)
+            if lh:
+                forms["learned_heldout"] = lh
 
     parity = None
     if not args.no_oracle_parity:

@@ -154,6 +154,13 @@ typedef struct adagio_opts {
     int32_t pca_iters;       /* randomized PCA: power iterations q (>= 0)         */
     int32_t no_witness;      /* fit: 1 = certify every probe in full (no refutation by
                                 witness pairs, no early stop); default 0          */
+    int32_t refine;          /* learned search: 1 = once the predicted r certifies,
+                                probe downward (r / 1.25 each step while probes
+                                pass), then bisect between the last failing and
+                                the last passing r, so the result is
+                                bisection-minimal like the plain search's (r - 1
+                                fails); default 0 returns the certified
+                                prediction                                        */
 } adagio_opts_t;
 
 /* a1-a3.  Principal axes of the centred cloud (Sec. 2 PCA paragraph, eq. 4;

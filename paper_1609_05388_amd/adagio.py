@@ -72,7 +72,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("screen", ctypes.c_int32), ("search", ctypes.c_int32),
                 ("max_candidates", ctypes.c_int32), ("family", ctypes.c_int32),
                 ("predictor", ctypes.c_void_p), ("stats", ctypes.POINTER(Stats)),
-                ("pca", ctypes.c_int32), ("pca_iters", ctypes.c_int32), ("no_witness", ctypes.c_int32)]
+                ("pca", ctypes.c_int32), ("pca_iters", ctypes.c_int32), ("no_witness", ctypes.c_int32),
+                ("refine", ctypes.c_int32)]
 
 
 _lib = None
@@ -148,9 +149,10 @@ def _dev(t, dtype, name):
 
 
 def _opts(screen="f32", search="bisect", max_candidates=0, predictor=None, stats=None, family="adagio",
-          pca="exact", pca_iters=2, witness=True):
+          pca="exact", pca_iters=2, witness=True, refine=False):
     o = Opts()
     o.no_witness = 0 if witness else 1
+    o.refine = 1 if refine else 0
     o.screen = SCREEN[screen]
     o.search = SEARCH[search]
     o.family = FAMILY[family]
@@ -275,16 +277,17 @@ def certify_map(X, Pi, screen="f32", max_candidates=0, with_stats=False):
 
 
 def fit(X, eps, seed, screen="f32", search="bisect", predictor=None, max_candidates=0, family="adagio",
-        pca="exact", pca_iters=2, witness=True):
+        pca="exact", pca_iters=2, witness=True, refine=False):
     """Returns dict(Pi=(r x d tensor), r, s, k, cert, stats).  family: "adagio"
     (Algorithm 1), "pca" or "jl" (Table 3's single-component maps); pca:
     "exact" or "randomized" (Sec. 4.5's variant, pca_iters power iterations);
-    witness=False certifies every probe in full."""
+    witness=False certifies every probe in full; refine=True makes the
+    learned search probe downward from a certified prediction."""
     lib = load()
     n, d = X.shape
     Pi_buf = torch.empty((d, d), dtype=torch.float32, device=X.device)
     st = Stats()
-    o = _opts(screen, search, max_candidates, predictor, st, family, pca, pca_iters, witness)
+    o = _opts(screen, search, max_candidates, predictor, st, family, pca, pca_iters, witness, refine)
     r = ctypes.c_int32()
     s = ctypes.c_int32()
     c = Cert()

@@ -66,7 +66,7 @@ struct Workspace {
   DevBuf mu, colpart, nonfinite, Xc, nx, tx, covpart, A0, A1, W, trace, rot, lam, Vt;
   DevBuf S, T, Pi, Pi64, Y64, Yc, ny, ty, muY;
   DevBuf recs, tparts, seeds, seedv, list, cand, vals, vparts, cd;
-  DevBuf Xb, txb, Yb, tyb, bjU, bjS;
+  DevBuf Xb, txb, Yb, tyb, bjU, bjS, bjRot;
   DevBuf Xq, sx, nxq, Yq, sy, nyq, q8terms, hist, kthr, gcache;
   DevBuf rpQ, rpY, rpG, rpV, rpLam;
   DevBuf skpart, skG, skK, sklam, skV, skfeat, mlp_pb, mlp_X, mlp_f, mlp_hb, mlp_grad, mlp_loss;
@@ -362,10 +362,10 @@ struct Axes {
 static int jacobi_eig(Workspace& ws, double* A, int m, int64_t d, double* lam, double* Vt, hipStream_t st) {
   const int JB = bj_block();
   const int nb = m / JB;
-  double* B = ensure<double>(ws.A1, (size_t)m * m);
   double* W = ensure<double>(ws.W, (size_t)m * m);
   double* Ub = ensure<double>(ws.bjU, (size_t)(nb / 2) * 4 * JB * JB);
   double* Sb = ensure<double>(ws.bjS, (size_t)(nb / 2) * 4 * JB * JB);
+  int* rotated = ensure<int>(ws.bjRot, (size_t)(nb / 2));
   HIPCHK(launch_eye(W, m, st));
   double* tr = ensure<double>(ws.trace, 1);
   HIPCHK(launch_trace(A, m, tr, st));
@@ -383,10 +383,7 @@ static int jacobi_eig(Workspace& ws, double* A, int m, int64_t d, double* lam, d
   bool converged = false;
   for (; sweep < max_sweeps && !converged; ++sweep) {
     HIPCHK(hipMemsetAsync(rot, 0, sizeof(int), st));
-    for (int t = 0; t < nb - 1; ++t) {
-      HIPCHK(launch_bj_round(A, B, W, Ub, Sb, m, t, thr, rot, st));
-      std::swap(A, B);
-    }
+    for (int t = 0; t < nb - 1; ++t) HIPCHK(launch_bj_round(A, W, Ub, Sb, rotated, m, t, thr, rot, st));
     int h = 0;
     HIPCHK(hipMemcpyAsync(&h, rot, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1470,6 +1467,8 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
            "the learned search is for Algorithm 1's maps only");
     const int no_witness = opts ? opts->no_witness : 0;
     ARGCHK(no_witness == 0 || no_witness == 1, "no_witness must be 0 or 1");
+    const int refine = opts ? opts->refine : 0;
+    ARGCHK(refine == 0 || refine == 1, "refine must be 0 or 1");
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = as_stream(stream);
     CallWs cw(as_stream(stream));
@@ -1600,7 +1599,19 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
         if (probe(rp, rig)) hi = rp;
         else { lo = rp; fallback = 1; }
       }
-      if (fallback) bisect(rig);
+      if (!fallback && refine) {
+        // downward from the certified prediction: r / 1.25 while probes pass
+        // (a failing probe is usually refuted by the witness pool the first
+        // certificate filled), then bisection between the last failure and
+        // the last pass
+        for (;;) {
+          const int64_t g = (int64_t)std::floor((double)hi / 1.25);
+          if (g <= lo) break;
+          if (probe(g, rig)) hi = g;
+          else { lo = g; break; }
+        }
+      }
+      if (fallback || refine) bisect(rig);
     } else if (screen == ADAGIO_SCREEN_FP8) {
       // Bisection over r on screened probes, then the certificate of the
       // result; if it fails, certified bisection continues on (r, d].

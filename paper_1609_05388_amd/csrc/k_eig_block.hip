@@ -13,7 +13,12 @@
 // The round then applies the block-diagonal orthogonal J (the U's on their
 // index sets): A <- J^T A J tile by tile (tile (PQ, RS) becomes
 // U_PQ^T A_tile U_RS) and W <- J^T W, with W = V^T accumulating eigenvectors
-// as rows.  The method has converged when a whole sweep skips every rotation.
+// as rows.  Every tile and every W row block is read and written by one
+// workgroup of the round, so both are updated in place; a subproblem that
+// rotated nothing has U = I, and the products with it are skipped (a tile
+// between two such pairs is left as it is), which makes the late sweeps,
+// where most subproblems are already below the threshold, cheap.  The method
+// has converged when a whole sweep skips every rotation.
 #include "common.h"
 #include "kernels.h"
 
@@ -64,7 +69,7 @@ __device__ inline void sub_rotation(const double* S, int p, int q, double thr, d
 template <bool FULL>
 __global__ __launch_bounds__(256) void k_bj_solve(const double* __restrict__ A, int m, int nb, int t, double thr,
                                                   double* __restrict__ Uout, double* __restrict__ Sout,
-                                                  int* __restrict__ rot_count) {
+                                                  int* __restrict__ rot_count, int* __restrict__ rotated) {
   extern __shared__ double lds_d[];
   double* const S0 = lds_d;
   double* const S1 = lds_d + JS * JLD;
@@ -132,6 +137,13 @@ __global__ __launch_bounds__(256) void k_bj_solve(const double* __restrict__ A, 
       cur ^= 1;
     }
   }
+  __syncthreads();
+  const int applied = applied_sh;
+  if (tid == 0) {
+    rotated[pair] = applied ? 1 : 0;
+    if (applied) atomicAdd(rot_count, applied);
+  }
+  if (!applied) return;   // U = I and S unchanged: nothing to write or apply
   const double* S = cur ? S1 : S0;
   double* Ug = Uout + (int64_t)pair * JS * JS;
   double* Sg = Sout + (int64_t)pair * JS * JS;
@@ -140,7 +152,6 @@ __global__ __launch_bounds__(256) void k_bj_solve(const double* __restrict__ A, 
     Ug[e] = U[i * JLD + j];
     Sg[e] = S[i * JLD + j];
   }
-  if (tid == 0 && applied_sh) atomicAdd(rot_count, applied_sh);
 }
 
 // One 32 x 32 quadrant (wave w: rows 32 (w / 2), columns 32 (w % 2)) of
@@ -167,13 +178,14 @@ __device__ inline void quad_xty(const double* X, const double* Y, f64x4 (&acc)[2
   }
 }
 
-// Apply round t: A2 = J^T A J (grid: (nb/2)^2 tiles of JS x JS) and
+// Apply round t in place: A <- J^T A J (grid: (nb/2)^2 tiles of JS x JS) and
 // W <- J^T W (grid: (nb/2) * (m / JS) tiles), one workgroup per tile:
 // tile (PQ, RS) of A becomes U_PQ^T A_tile U_RS (two FP64 MFMA products with
-// the intermediate kept transposed in LDS), a diagonal tile is the solved S.
-__global__ __launch_bounds__(256) void k_bj_apply(const double* __restrict__ A, double* __restrict__ A2,
-                                                  double* __restrict__ W, const double* __restrict__ Uall,
-                                                  const double* __restrict__ Sall, int m, int nb, int t) {
+// the intermediate kept transposed in LDS; one when either U is the
+// identity, none when both are), a diagonal tile the solved S.
+__global__ __launch_bounds__(256) void k_bj_apply(double* __restrict__ A, double* __restrict__ W,
+                                                  const double* __restrict__ Uall, const double* __restrict__ Sall,
+                                                  const int* __restrict__ rotated, int m, int nb, int t) {
   extern __shared__ double lds_d[];
   double* X = lds_d;
   double* Y = lds_d + JS * JLD;
@@ -187,25 +199,52 @@ __global__ __launch_bounds__(256) void k_bj_apply(const double* __restrict__ A, 
     int P, Q, R, S;
     rr_pair_b(t, ka, nb, P, Q);
     rr_pair_b(t, kb, nb, R, S);
+    const bool rot_a = rotated[ka] != 0, rot_b = rotated[kb] != 0;
     if (ka == kb) {  // diagonal tile: the solved subproblem itself
+      if (!rot_a) return;
       const double* Sg = Sall + (int64_t)ka * JS * JS;
       for (int e = tid; e < JS * JS; e += 256) {
         const int i = e / JS, j = e % JS;
-        A2[(int64_t)sub_index(P, Q, i) * m + sub_index(P, Q, j)] = Sg[e];
+        A[(int64_t)sub_index(P, Q, i) * m + sub_index(P, Q, j)] = Sg[e];
       }
       return;
     }
+    if (!rot_a && !rot_b) return;
     const double* ua = Uall + (int64_t)ka * JS * JS;
     const double* ub = Uall + (int64_t)kb * JS * JS;
-    for (int e = tid; e < JS * JS; e += 256) {
-      const int i = e / JS, j = e % JS;
-      X[i * JLD + j] = A[(int64_t)sub_index(P, Q, i) * m + sub_index(R, S, j)];
-      Y[i * JLD + j] = ua[e];
+    if (rot_a) {
+      for (int e = tid; e < JS * JS; e += 256) {
+        const int i = e / JS, j = e % JS;
+        X[i * JLD + j] = A[(int64_t)sub_index(P, Q, i) * m + sub_index(R, S, j)];
+        Y[i * JLD + j] = ua[e];
+      }
+      __syncthreads();
+      quad_xty(Y, X, acc);          // T1 = Ua^T A_tile
+      __syncthreads();
+      if (rot_b) {
+        // X <- T1^T (X[j][i] = T1[i][j])
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int i = r0 + a * 16 + 4 * v + (lane >> 4), j = c0w + b * 16 + (lane & 15);
+              X[j * JLD + i] = acc[a][b][v];
+            }
+      }
+    } else {
+      // T1 = A_tile, held transposed: X[j][i] = A_tile[i][j]
+      for (int e = tid; e < JS * JS; e += 256) {
+        const int i = e / JS, j = e % JS;
+        X[j * JLD + i] = A[(int64_t)sub_index(P, Q, i) * m + sub_index(R, S, j)];
+      }
     }
-    __syncthreads();
-    quad_xty(Y, X, acc);          // T1 = Ua^T A_tile
-    __syncthreads();
-    // X <- T1^T (X[j][i] = T1[i][j]), Y <- Ub
+    if (rot_b) {
+      for (int e = tid; e < JS * JS; e += 256) Y[(e / JS) * JLD + (e % JS)] = ub[e];
+      __syncthreads();
+      quad_xty(X, Y, acc);          // T1 Ub = (T1^T)^T Ub
+    }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -213,25 +252,14 @@ __global__ __launch_bounds__(256) void k_bj_apply(const double* __restrict__ A, 
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i = r0 + a * 16 + 4 * v + (lane >> 4), j = c0w + b * 16 + (lane & 15);
-          X[j * JLD + i] = acc[a][b][v];
-        }
-    for (int e = tid; e < JS * JS; e += 256) Y[(e / JS) * JLD + (e % JS)] = ub[e];
-    __syncthreads();
-    quad_xty(X, Y, acc);          // T1 Ub = (T1^T)^T Ub
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = r0 + a * 16 + 4 * v + (lane >> 4), j = c0w + b * 16 + (lane & 15);
-          A2[(int64_t)sub_index(P, Q, i) * m + sub_index(R, S, j)] = acc[a][b][v];
+          A[(int64_t)sub_index(P, Q, i) * m + sub_index(R, S, j)] = acc[a][b][v];
         }
   } else {
     // W rows of pair ka, columns [c0, c0 + JS): W' = Ua^T W
     const int wb = blockIdx.x - nA;
     const int ncol = m / JS;
     const int ka = wb / ncol, c0 = (wb % ncol) * JS;
+    if (rotated[ka] == 0) return;
     int P, Q;
     rr_pair_b(t, ka, nb, P, Q);
     const double* ua = Uall + (int64_t)ka * JS * JS;
@@ -257,7 +285,7 @@ __global__ __launch_bounds__(256) void k_bj_apply(const double* __restrict__ A, 
 constexpr size_t kLdsSolve = 3 * JS * JLD * sizeof(double);
 constexpr size_t kLdsApply = 2 * JS * JLD * sizeof(double);
 
-hipError_t launch_bj_round(const double* A, double* A2, double* W, double* Uall, double* Sall, int m, int t,
+hipError_t launch_bj_round(double* A, double* W, double* Uall, double* Sall, int* rotated, int m, int t,
                            double thr, int* rot_count, hipStream_t st) {
   static bool attr = false;
   if (!attr) {
@@ -274,11 +302,14 @@ hipError_t launch_bj_round(const double* A, double* A2, double* W, double* Uall,
   }
   const int nb = m / JB;
   const int half = nb / 2;
-  if (t == 0) k_bj_solve<true><<<(unsigned)half, 256, kLdsSolve, st>>>(A, m, nb, t, thr, Uall, Sall, rot_count);
-  else k_bj_solve<false><<<(unsigned)half, 256, kLdsSolve, st>>>(A, m, nb, t, thr, Uall, Sall, rot_count);
+  if (t == 0)
+    k_bj_solve<true><<<(unsigned)half, 256, kLdsSolve, st>>>(A, m, nb, t, thr, Uall, Sall, rot_count, rotated);
+  else
+    k_bj_solve<false><<<(unsigned)half, 256, kLdsSolve, st>>>(A, m, nb, t, thr, Uall, Sall, rot_count, rotated);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_bj_apply<<<(unsigned)(half * half + half * (m / JS)), 256, kLdsApply, st>>>(A, A2, W, Uall, Sall, m, nb, t);
+  k_bj_apply<<<(unsigned)(half * half + half * (m / JS)), 256, kLdsApply, st>>>(A, W, Uall, Sall, rotated, m, nb,
+                                                                                 t);
   return hipGetLastError();
 }
 

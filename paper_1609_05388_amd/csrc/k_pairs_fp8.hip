@@ -213,9 +213,6 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
     if (c + 1 < total) stash(buf ^ 1);
     __syncthreads();
   }
-  // the cached point Gram (loaded before the image loop: placing the loads
-  // inside it costs this kernel register spills)
-  if (gload) gcache_load(b.gcache, tix, accX);
   for (int c = nchx; c < total; ++c) {
     const int buf = c & 1;
     if (c + 1 < total) fetch(c + 1);
@@ -223,14 +220,19 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
     if (c + 1 < total) stash(buf ^ 1);
     __syncthreads();
   }
-  // stored after the image loop: earlier stores would hold up its chunk loads
+  // the cached point Gram after the image loop, where its accumulators become
+  // live (the loop then holds the image accumulators only); stores after it
+  // too (earlier they would hold up its chunk loads)
+  if (gload) gcache_load(b.gcache, tix, accX);
   if (b.gmode == 1) gcache_store(b.gcache, tix, accX);
   if (store_only) return;
 
   // epilogue: central estimates, largest and smallest q~ of the tile
   const bool masked = !((I < J) && (col0 + kTile <= n));
-  float best_hi = -1.0f, best_lo = 3.0e38f;
-  int code_hi = -1, code_lo = -1;
+  // the tile's largest and smallest estimate as sortable keys (value bits
+  // with the low 6 mantissa bits replaced by the pair's code); pairs whose
+  // estimated distance is not positive are not ranked
+  uint32_t khi = 0u, klo = 0xFFFFFFFFu;
   // column terms with s in place of -2 s (the row term carries the -2)
   float4 tb0 = termB[wc * 64 + li], tb1 = termB[wc * 64 + 32 + li];
   tb0.z *= -0.5f; tb0.w *= -0.5f;
@@ -246,17 +248,16 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
         const float4 tb = y ? tb1 : tb0;
         const float d2 = fmaf(ta.z * tb.z, accX[x][y][v], ta.x + tb.x);   // -2 s_i s_j g + N_i + N_j
         const float e2 = fmaf(ta.w * tb.w, accY[x][y][v], ta.y + tb.y);
-        // a pair whose estimated distance vanishes is not ranked
-        const float q = fmaxf(e2, 0.0f) * __builtin_amdgcn_rcpf(d2);
-        float qh = d2 > 0.0f ? q : -1.0f, ql = d2 > 0.0f ? q : 3.0e38f;
+        const float q = e2 * __builtin_amdgcn_rcpf(d2);
+        const uint32_t k = pair_key(fmaxf(q, 0.0f), (x * 2 + y) * 16 + v);
+        bool ok = d2 > 0.0f;
         if (masked) {
           const int cl = wc * 64 + y * 32 + li;
-          if (!((I < J || rl < cl) && col0 + cl < n)) { qh = -1.0f; ql = 3.0e38f; }
+          ok = ok && (I < J || rl < cl) && col0 + cl < n;
         }
-        const int code = (x * 2 + y) * 16 + v;
-        if (qh > best_hi) { best_hi = qh; code_hi = code; }
-        if (ql < best_lo) { best_lo = ql; code_lo = code; }
-        asm volatile("" : "+v"(best_hi), "+v"(code_hi), "+v"(best_lo), "+v"(code_lo));
+        khi = ok && k > khi ? k : khi;
+        klo = ok && k < klo ? k : klo;
+        asm volatile("" : "+v"(khi), "+v"(klo));
       }
     }
   auto decode = [&](int code, int& gi, int& gj) {
@@ -265,14 +266,18 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
     gi = row0 + wr * 64 + x * 32 + (v >> 2) * 8 + lh * 4 + (v & 3);
     gj = col0 + wc * 64 + y * 32 + li;
   };
+  // the wave's extreme keys and the lowest lanes holding them
+  const uint32_t whi = wave_max_u32(khi), wlo = wave_min_u32(klo);
+  const uint64_t bh = __ballot(khi == whi), bl = __ballot(klo == wlo);
+  const int lhi = __ffsll((unsigned long long)bh) - 1, llo = __ffsll((unsigned long long)bl) - 1;
   int ih, jh, il, jl;
-  decode(code_hi, ih, jh);
-  decode(code_lo, il, jl);
-  wave_arg<true>(best_hi, ih, jh);
-  wave_arg<false>(best_lo, il, jl);
+  decode(khi == 0u ? -1 : (int)(khi & 63u), ih, jh);
+  decode(klo == 0xFFFFFFFFu ? -1 : (int)(klo & 63u), il, jl);
+  ih = __shfl(ih, lhi, 64); jh = __shfl(jh, lhi, 64);
+  il = __shfl(il, llo, 64); jl = __shfl(jl, llo, 64);
   if (lane == 0) {
-    red_v[wave] = best_hi; red_i[wave] = ih; red_j[wave] = jh;
-    red_v[4 + wave] = best_lo; red_i[4 + wave] = il; red_j[4 + wave] = jl;
+    red_v[wave] = whi == 0u ? -1.0f : key_lo_value(whi); red_i[wave] = ih; red_j[wave] = jh;
+    red_v[4 + wave] = wlo == 0xFFFFFFFFu ? 3.0e38f : key_lo_value(wlo); red_i[4 + wave] = il; red_j[4 + wave] = jl;
   }
   __syncthreads();
   if (tid == 0) {

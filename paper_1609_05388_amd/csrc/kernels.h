@@ -70,7 +70,10 @@ hipError_t launch_cholesky(double* A, int m, int* fail, hipStream_t st);
 int chol_max_m();
 
 // k_eig_block.hip
-hipError_t launch_bj_round(const double* A, double* A2, double* W, double* Uall, double* Sall, int m, int t,
+// One round t of the block Jacobi method on the m x m matrix A (in place), W
+// (= V^T, in place); Uall, Sall: per block pair JS x JS scratch; rotated: per
+// block pair flag (nb / 2 ints); rot_count accumulates applied rotations.
+hipError_t launch_bj_round(double* A, double* W, double* Uall, double* Sall, int* rotated, int m, int t,
                            double thr, int* rot_count, hipStream_t st);
 int bj_block();
 

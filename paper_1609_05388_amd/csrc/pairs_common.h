@@ -111,6 +111,44 @@ __device__ inline void pair_bounds(float gx, float gy, const float4& ta, const f
   if (!(d2hi > 0.0f)) { qhi = 1.0f; qlo = 1.0f; }
 }
 
+// Wave-wide reductions (all lanes receive the result).
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const uint32_t w = (uint32_t)__shfl_xor((int)v, o, 64);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+__device__ inline uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const uint32_t w = (uint32_t)__shfl_xor((int)v, o, 64);
+    v = w < v ? w : v;
+  }
+  return v;
+}
+__device__ inline float wave_min_f32(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline float wave_max_f32(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Sortable key of a non-negative FP32 value and a 6-bit pair code: the
+// value's bits with the low 6 mantissa bits replaced by the code (the sign
+// bit dropped, so -0 sorts as 0).  For keys k of values q:
+// q <= key_hi_value(max k) and q >= key_lo_value(min k).
+__device__ inline uint32_t pair_key(float q, int code) {
+  return (__float_as_uint(q) & 0x7FFFFFC0u) | (uint32_t)code;
+}
+__device__ inline float key_hi_value(uint32_t k) { return __uint_as_float((k & 0xFFFFFFC0u) | 63u); }
+__device__ inline float key_lo_value(uint32_t k) { return __uint_as_float(k & 0xFFFFFFC0u); }
+
 // Epilogue of one 128 x 128 tile, shared by the screen kernels.  accX/accY
 // hold the point and image Gram blocks of this wave in the D layout of the
 // 32 x 32 MFMAs (lane l, register v -> row (v / 4) * 8 + (l / 32) * 4 + v % 4,
@@ -118,7 +156,7 @@ __device__ inline void pair_bounds(float gx, float gy, const float4& ta, const f
 // v_mfma_f32_32x32x16_bf16.  MODE 0 writes the tile record (after a
 // block-wide barrier); MODE 1 appends the pairs reaching the thresholds.
 template <int MODE>
-__device__ inline void tile_epilogue(const f32x16 (&accX)[2][2], const f32x16 (&accY)[2][2],
+__device__ __attribute__((always_inline)) inline void tile_epilogue(const f32x16 (&accX)[2][2], const f32x16 (&accY)[2][2],
                                      const float4* termA, const float4* termB, int I, int J,
                                      const PairsArgs& p, float thr_hi, float thr_lo, float (*red_v)[4],
                                      int (*red_i)[4], int (*red_j)[4]) {
@@ -172,16 +210,118 @@ __device__ inline void tile_epilogue(const f32x16 (&accX)[2][2], const f32x16 (&
         }
       }
   };
-  if (masked) scan(std::integral_constant<bool, true>{});
-  else scan(std::integral_constant<bool, false>{});
+  auto decode = [&](int code, int& gi, int& gj) {
+    if (code < 0) { gi = 0x7fffffff; gj = 0x7fffffff; return; }
+    const int x = code >> 5, y = (code >> 4) & 1, v = code & 15;
+    gi = row0 + wr * 64 + x * 32 + (v >> 2) * 8 + lh * 4 + (v & 3);
+    gj = col0 + wc * 64 + y * 32 + li;
+  };
+
+  // MODE 0 fast pass: per pair only the rigorous upper bound
+  // q+ = E2hi / D2lo (E2hi = (hi_i + hi_j) - 2 g_y, D2lo = (lo_i + lo_j) - 2 g_x),
+  // kept as sortable keys (largest and smallest per lane), and the smallest
+  // D2lo and E2hi.  The wave's record then takes
+  //   q_hi = the largest q+ (rounded up),
+  //   q_lo = the smallest q+ x (1 - W_E / E2hi_min) / (1 + W_D / D2lo_min) (rounded down),
+  // where W_D, W_E >= 1.25 (width_i + width_j) bound D2hi - D2lo and
+  // E2hi - E2lo over the wave's rows i and columns j (width = hi - lo of a
+  // row term, which also covers the rounding of the epilogue's add and fma):
+  // for every pair E2 >= E2hi - W_E and D2 <= D2lo + W_D, so
+  // E2 / D2 >= q+ (1 - W_E / E2hi) / (1 + W_D / D2lo), and the factor grows
+  // with E2hi and D2lo.  A wave whose smallest D2lo or E2hi is within 64
+  // widths (so q_lo would lose more than about 3%), holds a pair with
+  // D2lo <= 1e-30 (identical or nearly identical points) or a q+ near FP32
+  // overflow takes the per-pair pass above instead.
+  bool fast = false;
+  if (MODE == 0) {
+    uint32_t khi = 0u, klo = 0xFFFFFFFFu;
+    float dmin = 3.0e38f, emin = 3.0e38f;
+    auto fscan = [&](auto maskc) __attribute__((always_inline)) {
+      constexpr bool M = decltype(maskc)::value;
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int rl = wr * 64 + x * 32 + (v >> 2) * 8 + lh * 4 + (v & 3);
+          const float4 ta = termA[rl];
+#pragma unroll
+          for (int y = 0; y < 2; ++y) {
+            const float4 tb = y ? tb1 : tb0;
+            const float d2lo = fmaf(-2.0f, accX[x][y][v], ta.x + tb.x);
+            const float e2hi = fmaf(-2.0f, accY[x][y][v], ta.w + tb.w);
+            const float q = e2hi * __builtin_amdgcn_rcpf(d2lo);
+            const uint32_t k = pair_key(q, (x * 2 + y) * 16 + v);
+            if (M) {
+              const int cl = wc * 64 + y * 32 + li;
+              const bool valid = (I < J || rl < cl) && col0 + cl < p.n;
+              khi = valid && k > khi ? k : khi;
+              klo = valid && k < klo ? k : klo;
+              dmin = valid ? fminf(dmin, d2lo) : dmin;
+              emin = valid ? fminf(emin, e2hi) : emin;
+            } else {
+              khi = k > khi ? k : khi;
+              klo = k < klo ? k : klo;
+              dmin = fminf(dmin, d2lo);
+              emin = fminf(emin, e2hi);
+            }
+            // pinned per pair, as in the per-pair pass (else the compiler
+            // evaluates many pairs first and runs out of registers)
+            asm volatile("" : "+v"(khi), "+v"(klo), "+v"(dmin), "+v"(emin));
+          }
+        }
+    };
+    if (masked) fscan(std::integral_constant<bool, true>{});
+    else fscan(std::integral_constant<bool, false>{});
+    // widths of the wave's 64 rows and 64 columns, one of each per lane
+    const float4 ra = termA[wr * 64 + lane], cb = termB[wc * 64 + lane];
+    const float wDr = wave_max_f32(ra.y - ra.x), wEr = wave_max_f32(ra.w - ra.z);
+    const float wDc = wave_max_f32(cb.y - cb.x), wEc = wave_max_f32(cb.w - cb.z);
+    const uint32_t whi = wave_max_u32(khi), wlo = wave_min_u32(klo);
+    const float wd = wave_min_f32(dmin), we = wave_min_f32(emin);
+    const double WD = 1.25 * ((double)wDr + (double)wDc), WE = 1.25 * ((double)wEr + (double)wEc);
+    // a wave without valid pairs (whi = 0, wlo = ~0) has no record to make
+    const bool any = wlo != 0xFFFFFFFFu;
+    fast = any && wd > 1e-30f && (double)wd > 64.0 * WD && (double)we > 64.0 * WE && whi < 0x7F000000u;
+    if (fast) {
+      const float vhi = key_hi_value(whi);
+      const double f = (1.0 - WE / (double)we) / (1.0 + WD / (double)wd);
+      const float vlo = (float)((double)key_lo_value(wlo) * (1.0 - 0x1.0p-20) * f * (1.0 - 1e-7));
+      // the lanes holding the wave's extreme keys (lowest lane among equal keys)
+      const uint64_t bh = __ballot(khi == whi), bl = __ballot(klo == wlo);
+      const int lhi = __ffsll((unsigned long long)bh) - 1, llo = __ffsll((unsigned long long)bl) - 1;
+      int ih, jh, il, jl;
+      decode((int)(khi & 63u), ih, jh);
+      decode((int)(klo & 63u), il, jl);
+      ih = __shfl(ih, lhi, 64); jh = __shfl(jh, lhi, 64);
+      il = __shfl(il, llo, 64); jl = __shfl(jl, llo, 64);
+      // early stop: the expansion winner's q >= its q+ x factor, the
+      // contraction winner's q <= its q+
+      if (p.stop && lane == 0) {
+        const bool c_hi = (double)key_lo_value(whi) * (1.0 - 0x1.0p-20) * f > (double)stop_hi;
+        const bool c_lo = key_hi_value(wlo) < stop_lo;
+        if (c_hi || c_lo) {
+          const uint32_t pos = atomicAdd(p.stop, 1u);
+          if (pos < 8) p.stop_pairs[pos] = c_hi ? make_int2(ih, jh) : make_int2(il, jl);
+        }
+      }
+      if (lane == 0) {
+        red_v[0][wave] = vhi; red_i[0][wave] = ih; red_j[0][wave] = jh;
+        red_v[1][wave] = vlo; red_i[1][wave] = il; red_j[1][wave] = jl;
+      }
+    } else if (!any && lane == 0) {
+      red_v[0][wave] = -1.0f; red_i[0][wave] = 0x7fffffff; red_j[0][wave] = 0x7fffffff;
+      red_v[1][wave] = 3.0e38f; red_i[1][wave] = 0x7fffffff; red_j[1][wave] = 0x7fffffff;
+    }
+    fast = fast || !any;
+  }
+
+  if (MODE == 1 || !fast) {
+    if (masked) scan(std::integral_constant<bool, true>{});
+    else scan(std::integral_constant<bool, false>{});
+  }
 
   if (MODE == 0) {
-    auto decode = [&](int code, int& gi, int& gj) {
-      if (code < 0) { gi = 0x7fffffff; gj = 0x7fffffff; return; }
-      const int x = code >> 5, y = (code >> 4) & 1, v = code & 15;
-      gi = row0 + wr * 64 + x * 32 + (v >> 2) * 8 + lh * 4 + (v & 3);
-      gj = col0 + wc * 64 + y * 32 + li;
-    };
+    if (!fast) {
     int ih, jh, il, jl;
     if (p.stop && code_c >= 0) {   // rare: a pair certain to exceed the target
       decode(code_c, ih, jh);
@@ -195,6 +335,7 @@ __device__ inline void tile_epilogue(const f32x16 (&accX)[2][2], const f32x16 (&
     if (lane == 0) {
       red_v[0][wave] = best_hi; red_i[0][wave] = ih; red_j[0][wave] = jh;
       red_v[1][wave] = best_lo; red_i[1][wave] = il; red_j[1][wave] = jl;
+    }
     }
     __syncthreads();
     if (tid == 0) {

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 import torch
 
+from oracle import certificate, embedding
 from oracle import mlp as omlp
 from oracle import sketch as osketch
 from paper_1609_05388_amd import gen, learned
@@ -140,3 +141,26 @@ def test_trained_predictor_gains_over_bisection(gpu_lib):
     assert s["all_proven_within_eps"]
     assert s["mean_certificates_learned"] < s["mean_certificates_plain"]
     assert s["speedup"] > 1.0
+
+
+def test_learned_search_refined_downward(gpu_lib):
+    """refine=True: a prediction far above the needed r certifies, then the
+    search probes downward and bisects, so the result is bisection-minimal:
+    certified within eps, and the map at r - 1 fails (an FP64 oracle
+    certificate of the library's own map at r - 1 exceeds eps)."""
+    X = gen.low_rank_pixels(n=600, d=120, rank=10, seed=5)
+    Xd = torch.from_numpy(X).cuda()
+    count = gpu_lib.mlp_param_count()
+    P = torch.zeros(count, dtype=torch.float32, device="cuda")
+    off, _ = omlp.layout()
+    P[off["b4"][0]] = float(np.log(100.0 / 120.0))   # r = 100, far above r*
+    plain = gpu_lib.fit(Xd, 0.1, 7)
+    coarse = gpu_lib.fit(Xd, 0.1, 7, search="learned", predictor=P)
+    f = gpu_lib.fit(Xd, 0.1, 7, search="learned", predictor=P, refine=True)
+    assert coarse["r"] == 100 and f["stats"]["r_predicted"] == 100 and f["stats"]["n_fallback"] == 0
+    assert f["cert"]["certified"] == 1 and f["cert"]["max_distortion"] <= 0.1
+    assert f["r"] < 100
+    below = gpu_lib.project(Xd, f["r"] - 1, 7).cpu().numpy().astype(np.float64)
+    want = certificate.certify(X, embedding.embed(X, below))
+    assert want["max"] > 0.1
+    print("refined r %d, plain r %d" % (f["r"], plain["r"]))
