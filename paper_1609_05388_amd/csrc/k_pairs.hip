@@ -119,28 +119,35 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_f32(PairsArgs p) 
     const float* ya = p.Y + (size_t)(row0 + lr) * p.ldy + lc;
     const float* yb = p.Y + (size_t)(col0 + lr) * p.ldy + lc;
     const size_t x64 = (size_t)64 * p.ldx, y64 = (size_t)64 * p.ldy;
-    float4 ga0, ga1, gb0, gb1;
-    auto fetch = [&](int c) __attribute__((always_inline)) {
+    // two register sets of staging loads (the second for the pipelined image
+    // loop of the LOADED kernel)
+    float4 ga0, ga1, gb0, gb1, ha0, ha1, hb0, hb1;
+    auto fetch_into = [&](float4& a0, float4& a1, float4& b0, float4& b1, int c) __attribute__((always_inline)) {
       if (c < p.nchx) {
         const int cb = c * PK;
-        ga0 = *reinterpret_cast<const float4*>(xa + cb);
-        ga1 = *reinterpret_cast<const float4*>(xa + x64 + cb);
-        gb0 = *reinterpret_cast<const float4*>(xb + cb);
-        gb1 = *reinterpret_cast<const float4*>(xb + x64 + cb);
+        a0 = *reinterpret_cast<const float4*>(xa + cb);
+        a1 = *reinterpret_cast<const float4*>(xa + x64 + cb);
+        b0 = *reinterpret_cast<const float4*>(xb + cb);
+        b1 = *reinterpret_cast<const float4*>(xb + x64 + cb);
       } else {
         const int cb = (c - p.nchx) * PK;
-        ga0 = *reinterpret_cast<const float4*>(ya + cb);
-        ga1 = *reinterpret_cast<const float4*>(ya + y64 + cb);
-        gb0 = *reinterpret_cast<const float4*>(yb + cb);
-        gb1 = *reinterpret_cast<const float4*>(yb + y64 + cb);
+        a0 = *reinterpret_cast<const float4*>(ya + cb);
+        a1 = *reinterpret_cast<const float4*>(ya + y64 + cb);
+        b0 = *reinterpret_cast<const float4*>(yb + cb);
+        b1 = *reinterpret_cast<const float4*>(yb + y64 + cb);
       }
     };
-    auto stash = [&](int buf) __attribute__((always_inline)) {
-      *reinterpret_cast<float4*>(&As[buf][lds_at(lr, lc >> 2)]) = ga0;
-      *reinterpret_cast<float4*>(&As[buf][lds_at(lr + 64, lc >> 2)]) = ga1;
-      *reinterpret_cast<float4*>(&Bs[buf][lds_at(lr, lc >> 2)]) = gb0;
-      *reinterpret_cast<float4*>(&Bs[buf][lds_at(lr + 64, lc >> 2)]) = gb1;
+    auto stash_from = [&](const float4& a0, const float4& a1, const float4& b0, const float4& b1, int buf)
+        __attribute__((always_inline)) {
+      *reinterpret_cast<float4*>(&As[buf][lds_at(lr, lc >> 2)]) = a0;
+      *reinterpret_cast<float4*>(&As[buf][lds_at(lr + 64, lc >> 2)]) = a1;
+      *reinterpret_cast<float4*>(&Bs[buf][lds_at(lr, lc >> 2)]) = b0;
+      *reinterpret_cast<float4*>(&Bs[buf][lds_at(lr + 64, lc >> 2)]) = b1;
     };
+    auto fetch = [&](int c) __attribute__((always_inline)) { fetch_into(ga0, ga1, gb0, gb1, c); };
+    auto stash = [&](int buf) __attribute__((always_inline)) { stash_from(ga0, ga1, gb0, gb1, buf); };
+    auto fetch2 = [&](int c) __attribute__((always_inline)) { fetch_into(ha0, ha1, hb0, hb1, c); };
+    auto stash2 = [&](int buf) __attribute__((always_inline)) { stash_from(ha0, ha1, hb0, hb1, buf); };
     // MFMA step kk sums columns kk (lanes 0-31) and 8 + kk (lanes 32-63) of
     // the chunk; the same permutation is used for both operands.
     auto mma = [&](f32x16 (&acc)[2][2], int buf) __attribute__((always_inline)) {
@@ -166,12 +173,43 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_f32(PairsArgs p) 
     // the compiler copy the other set); the prefetch runs across the seam.
     // With a loaded point Gram the pipeline starts at the first image chunk.
     const int64_t tix = (int64_t)I * p.NT - (int64_t)I * (I - 1) / 2 + (J - I);
-    const int c0 = LOADED ? p.nchx : 0;
-    fetch(c0);
-    stash(c0 & 1);
-    __syncthreads();
-    if (MODE == 0 && s_stop != 0u) return;
-    if (!LOADED) {
+    if (LOADED) {
+      // image chunk k (0 <= k < nk) sits in LDS buffer k & 1 and, while in
+      // flight, in register set k & 1: the next two chunks load while one
+      // is multiplied
+      const int nk = p.nchy, cy = p.nchx;
+      fetch(cy);
+      if (nk > 1) fetch2(cy + 1);
+      stash(0);
+      __syncthreads();
+      if (MODE == 0 && s_stop != 0u) return;
+      int k = 0;
+      for (; k + 2 < nk; k += 2) {
+        fetch(cy + k + 2);
+        mma(accY, 0);
+        stash2(1);
+        __syncthreads();
+        if (k + 3 < nk) fetch2(cy + k + 3);
+        mma(accY, 1);
+        stash(0);
+        __syncthreads();
+      }
+      // the last one or two chunks; then the cached point Gram, where its
+      // accumulators become live (issued before these MFMAs it would wait
+      // behind the staging loads, which the vector-memory counter completes
+      // in issue order, and hold registers through the loop)
+      mma(accY, 0);
+      if (k + 1 < nk) {
+        stash2(1);
+        __syncthreads();
+        mma(accY, 1);
+      }
+      gcache_load(p.gcache, tix, accX);
+    } else {
+      fetch(0);
+      stash(0);
+      __syncthreads();
+      if (MODE == 0 && s_stop != 0u) return;
       for (int c = 0; c < p.nchx; ++c) {
         const int buf = c & 1;
         if (c + 1 < total) fetch(c + 1);
@@ -179,18 +217,16 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_f32(PairsArgs p) 
         if (c + 1 < total) stash(buf ^ 1);
         __syncthreads();
       }
+      for (int c = p.nchx; c < total; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < total) fetch(c + 1);
+        mma(accY, buf);
+        if (c + 1 < total) stash(buf ^ 1);
+        __syncthreads();
+      }
     }
-    for (int c = p.nchx; c < total; ++c) {
-      const int buf = c & 1;
-      if (c + 1 < total) fetch(c + 1);
-      mma(accY, buf);
-      if (c + 1 < total) stash(buf ^ 1);
-      __syncthreads();
-    }
-    // the cached point Gram after the loop, where its accumulators become
-    // live; stores after the image loop too (earlier they would hold up its
-    // chunk loads, which the vector-memory counter completes in issue order)
-    if (LOADED) gcache_load(p.gcache, tix, accX);
+    // stores after the image loop (earlier they would hold up its chunk
+    // loads, which the vector-memory counter completes in issue order)
     if (!LOADED && MODE == 0 && p.gmode == 1) gcache_store(p.gcache, tix, accX);
     if (store_only) return;
 

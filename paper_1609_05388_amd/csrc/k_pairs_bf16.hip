@@ -47,7 +47,13 @@ struct PairsArgsB {
   PairsArgs p;                         // row terms, sizes, outputs (X/Y fields unused)
 };
 
-template <int MODE>
+// LOADED: the point Gram comes from the cache and the kernel runs the image
+// chunks only, with the next two chunks in flight (two register sets of
+// staging loads; the LDS double buffer holds the chunk being multiplied and
+// the next one), since a 32-column chunk is only 24 MFMAs per wave, far less
+// than a global load's latency; the cached point Gram loads during the last
+// chunks, once no staging loads remain.
+template <int MODE, bool LOADED>
 __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   unsigned char* As = lds_raw;                          // [2][128][BROW]
@@ -124,31 +130,36 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
     const __bf16* xb = Xg + (size_t)(col0 + lr) * xstride + seg * 8;
     const __bf16* ya = Yg + (size_t)(row0 + lr) * ystride + seg * 8;
     const __bf16* yb = Yg + (size_t)(col0 + lr) * ystride + seg * 8;
-    u32x4 ga[4], gb[4];
-    auto fetch = [&](int c) __attribute__((always_inline)) {
+    struct Stage {
+      u32x4 a[4], b[4];
+    };
+    auto fetch_into = [&](Stage& g, int c) __attribute__((always_inline)) {
       if (c < nchx) {
         const size_t off = (size_t)c * 2 * BK;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-          ga[m] = *reinterpret_cast<const u32x4*>(xa + off + (size_t)32 * m * xstride);
-          gb[m] = *reinterpret_cast<const u32x4*>(xb + off + (size_t)32 * m * xstride);
+          g.a[m] = *reinterpret_cast<const u32x4*>(xa + off + (size_t)32 * m * xstride);
+          g.b[m] = *reinterpret_cast<const u32x4*>(xb + off + (size_t)32 * m * xstride);
         }
       } else {
         const size_t off = (size_t)(c - nchx) * 2 * BK;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-          ga[m] = *reinterpret_cast<const u32x4*>(ya + off + (size_t)32 * m * ystride);
-          gb[m] = *reinterpret_cast<const u32x4*>(yb + off + (size_t)32 * m * ystride);
+          g.a[m] = *reinterpret_cast<const u32x4*>(ya + off + (size_t)32 * m * ystride);
+          g.b[m] = *reinterpret_cast<const u32x4*>(yb + off + (size_t)32 * m * ystride);
         }
       }
     };
-    auto stash = [&](int buf) __attribute__((always_inline)) {
+    auto stash_from = [&](const Stage& g, int buf) __attribute__((always_inline)) {
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        *reinterpret_cast<u32x4*>(As + (size_t)buf * kTile * BROW + (lr + 32 * m) * BROW + seg * 16) = ga[m];
-        *reinterpret_cast<u32x4*>(Bs + (size_t)buf * kTile * BROW + (lr + 32 * m) * BROW + seg * 16) = gb[m];
+        *reinterpret_cast<u32x4*>(As + (size_t)buf * kTile * BROW + (lr + 32 * m) * BROW + seg * 16) = g.a[m];
+        *reinterpret_cast<u32x4*>(Bs + (size_t)buf * kTile * BROW + (lr + 32 * m) * BROW + seg * 16) = g.b[m];
       }
     };
+    Stage g0;
+    auto fetch = [&](int c) __attribute__((always_inline)) { fetch_into(g0, c); };
+    auto stash = [&](int buf) __attribute__((always_inline)) { stash_from(g0, buf); };
     // k-step s of a chunk: lanes 0-31 take columns 16 s .. 16 s + 7, lanes
     // 32-63 columns 16 s + 8 .. 16 s + 15 (8 bf16 = 16 bytes per lane).
     auto mma = [&](f32x16 (&acc)[2][2], int buf) __attribute__((always_inline)) {
@@ -181,33 +192,60 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
       }
     };
 
-    // with a loaded point Gram the pipeline starts at the first image chunk
-    const bool gload = MODE == 0 && p.gmode == 2;
     const int64_t tix = (int64_t)I * p.NT - (int64_t)I * (I - 1) / 2 + (J - I);
-    const int c0 = gload ? nchx : 0;
-    fetch(c0);
-    stash(c0 & 1);
-    __syncthreads();
-    if (MODE == 0 && s_stop != 0u) return;
-    for (int c = c0; c < nchx; ++c) {
-      const int buf = c & 1;
-      if (c + 1 < total) fetch(c + 1);
-      mma(accX, buf);
-      if (c + 1 < total) stash(buf ^ 1);
+    if (LOADED) {
+      // image chunk k (0 <= k < nk) sits in LDS buffer k & 1 and, while in
+      // flight, in register set k & 1
+      const int nk = nchy;
+      Stage g1;
+      fetch_into(g0, nchx);
+      if (nk > 1) fetch_into(g1, nchx + 1);
+      stash_from(g0, 0);
       __syncthreads();
-    }
-    for (int c = nchx; c < total; ++c) {
-      const int buf = c & 1;
-      if (c + 1 < total) fetch(c + 1);
-      // the cached point Gram, issued after the last prefetch so that the
-      // chunk loads before it complete first; it lands during the last MFMAs
-      if (gload && c == (total - 2 > nchx ? total - 2 : nchx)) gcache_load(p.gcache, tix, accX);
-      mma(accY, buf);
-      if (c + 1 < total) stash(buf ^ 1);
+      if (s_stop != 0u) return;
+      int k = 0;
+      for (; k + 2 < nk; k += 2) {
+        fetch_into(g0, nchx + k + 2);
+        mma(accY, 0);
+        stash_from(g1, 1);
+        __syncthreads();
+        if (k + 3 < nk) fetch_into(g1, nchx + k + 3);
+        mma(accY, 1);
+        stash_from(g0, 0);
+        __syncthreads();
+      }
+      // the last one or two chunks: no staging loads left, so the cached
+      // point Gram loads here and lands during their MFMAs
+      gcache_load(p.gcache, tix, accX);
+      mma(accY, 0);
+      if (k + 1 < nk) {
+        stash_from(g1, 1);
+        __syncthreads();
+        mma(accY, 1);
+      }
+    } else {
+      // both Grams (or the point Gram alone, filling the cache)
+      fetch(0);
+      stash(0);
       __syncthreads();
+      if (MODE == 0 && s_stop != 0u) return;
+      for (int c = 0; c < nchx; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < total) fetch(c + 1);
+        mma(accX, buf);
+        if (c + 1 < total) stash(buf ^ 1);
+        __syncthreads();
+      }
+      for (int c = nchx; c < total; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < total) fetch(c + 1);
+        mma(accY, buf);
+        if (c + 1 < total) stash(buf ^ 1);
+        __syncthreads();
+      }
     }
     // stored after the image loop: earlier stores would hold up its chunk loads
-    if (MODE == 0 && p.gmode == 1) gcache_store(p.gcache, tix, accX);
+    if (!LOADED && MODE == 0 && p.gmode == 1) gcache_store(p.gcache, tix, accX);
     if (store_only) return;
 
     tile_epilogue<MODE>(accX, accY, termA, termB, I, J, p, thr_hi, thr_lo, red_v, red_i, red_j);
@@ -226,15 +264,24 @@ hipError_t launch_split_bf16(const float* src, int64_t n_pad, int64_t m, int64_t
   return hipGetLastError();
 }
 
-hipError_t launch_pairs_screen_bf16(const PairsViewB& v, TileRec* recs, float* gcache, int gmode,
-                                    const ScreenStop* stop, hipStream_t st) {
+static hipError_t bf16_attrs() {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pairs_bf16x3<0>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pairs_bf16x3<0, false>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBf16);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pairs_bf16x3<0, true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBf16);
     if (e != hipSuccess) return e;
     attr = true;
   }
+  return hipSuccess;
+}
+
+hipError_t launch_pairs_screen_bf16(const PairsViewB& v, TileRec* recs, float* gcache, int gmode,
+                                    const ScreenStop* stop, hipStream_t st) {
+  hipError_t e0 = bf16_attrs();
+  if (e0 != hipSuccess) return e0;
   const int NS = (v.NT + 7) / 8;
   const int64_t nslots = (int64_t)NS * (NS + 1) / 2 * 64;
   PairsArgsB a;
@@ -247,18 +294,15 @@ hipError_t launch_pairs_screen_bf16(const PairsViewB& v, TileRec* recs, float* g
     a.p.stop = stop->count; a.p.stop_pairs = stop->pairs; a.p.stop_hi = stop->q_hi; a.p.stop_lo = stop->q_lo;
   }
   const int64_t G = round_up(nslots, 8);
-  k_pairs_bf16x3<0><<<(unsigned)G, 256, kLdsBf16, st>>>(a);
+  // the pipelined image loop needs at least one image chunk
+  if (a.p.gmode == 2 && a.nchy >= 1) k_pairs_bf16x3<0, true><<<(unsigned)G, 256, kLdsBf16, st>>>(a);
+  else k_pairs_bf16x3<0, false><<<(unsigned)G, 256, kLdsBf16, st>>>(a);
   return hipGetLastError();
 }
 
 hipError_t launch_pairs_gram_fill_bf16(const PairsViewB& v, float* gcache, hipStream_t st) {
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pairs_bf16x3<0>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBf16);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  hipError_t e0 = bf16_attrs();
+  if (e0 != hipSuccess) return e0;
   const int NS = (v.NT + 7) / 8;
   const int64_t nslots = (int64_t)NS * (NS + 1) / 2 * 64;
   PairsArgsB a;
@@ -266,7 +310,7 @@ hipError_t launch_pairs_gram_fill_bf16(const PairsViewB& v, float* gcache, hipSt
   a.Y = v.Xb; a.ldy = 0; a.nchy = 0;
   a.p = PairsArgs{nullptr, 0, 0, nullptr, 0, 0, v.tx, v.tx, v.n, v.NT, v.ntiles, NS, nslots, nullptr,
                   nullptr, nullptr, nullptr, 0u, nullptr, gcache, 1, nullptr, nullptr, 3.0e38f, -1.0f};
-  k_pairs_bf16x3<0><<<(unsigned)round_up(nslots, 8), 256, kLdsBf16, st>>>(a);
+  k_pairs_bf16x3<0, false><<<(unsigned)round_up(nslots, 8), 256, kLdsBf16, st>>>(a);
   return hipGetLastError();
 }
 

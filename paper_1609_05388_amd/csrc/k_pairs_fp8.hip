@@ -106,6 +106,11 @@ struct PairsArgsF {
   float* gcache; int gmode;                    // point-Gram cache: 0 off, 1 store, 2 load
 };
 
+// LOADED: the point Gram comes from the cache; the kernel runs the image
+// chunks only, with the next two chunks in flight (two register sets of
+// staging loads; a 128-column chunk is only 8 MFMAs per wave, far less than
+// a global load's latency), and loads the cached Gram after them.
+template <bool LOADED>
 __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   unsigned char* As = lds_raw;
@@ -149,31 +154,37 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
   const unsigned char* xb = Xg + (size_t)(col0 + lr) * ldx + seg * 16;
   const unsigned char* ya = Yg + (size_t)(row0 + lr) * ldy + seg * 16;
   const unsigned char* yb = Yg + (size_t)(col0 + lr) * ldy + seg * 16;
-  u32x4 ga[4], gb[4];
-  auto fetch = [&](int c) __attribute__((always_inline)) {
+  // two register sets of staging loads (the second for the pipelined image
+  // loop of the LOADED kernel)
+  u32x4 ga[4], gb[4], ha[4], hb[4];
+  auto fetch_into = [&](u32x4 (&ra)[4], u32x4 (&rb)[4], int c) __attribute__((always_inline)) {
     if (c < nchx) {
       const size_t off = (size_t)c * FK;
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        ga[m] = *reinterpret_cast<const u32x4*>(xa + off + (size_t)32 * m * ldx);
-        gb[m] = *reinterpret_cast<const u32x4*>(xb + off + (size_t)32 * m * ldx);
+        ra[m] = *reinterpret_cast<const u32x4*>(xa + off + (size_t)32 * m * ldx);
+        rb[m] = *reinterpret_cast<const u32x4*>(xb + off + (size_t)32 * m * ldx);
       }
     } else {
       const size_t off = (size_t)(c - nchx) * FK;
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        ga[m] = *reinterpret_cast<const u32x4*>(ya + off + (size_t)32 * m * ldy);
-        gb[m] = *reinterpret_cast<const u32x4*>(yb + off + (size_t)32 * m * ldy);
+        ra[m] = *reinterpret_cast<const u32x4*>(ya + off + (size_t)32 * m * ldy);
+        rb[m] = *reinterpret_cast<const u32x4*>(yb + off + (size_t)32 * m * ldy);
       }
     }
   };
-  auto stash = [&](int buf) __attribute__((always_inline)) {
+  auto stash_from = [&](const u32x4 (&ra)[4], const u32x4 (&rb)[4], int buf) __attribute__((always_inline)) {
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      *reinterpret_cast<u32x4*>(As + (size_t)buf * kTile * FROW + (lr + 32 * m) * FROW + seg * 16) = ga[m];
-      *reinterpret_cast<u32x4*>(Bs + (size_t)buf * kTile * FROW + (lr + 32 * m) * FROW + seg * 16) = gb[m];
+      *reinterpret_cast<u32x4*>(As + (size_t)buf * kTile * FROW + (lr + 32 * m) * FROW + seg * 16) = ra[m];
+      *reinterpret_cast<u32x4*>(Bs + (size_t)buf * kTile * FROW + (lr + 32 * m) * FROW + seg * 16) = rb[m];
     }
   };
+  auto fetch = [&](int c) __attribute__((always_inline)) { fetch_into(ga, gb, c); };
+  auto stash = [&](int buf) __attribute__((always_inline)) { stash_from(ga, gb, buf); };
+  auto fetch2 = [&](int c) __attribute__((always_inline)) { fetch_into(ha, hb, c); };
+  auto stash2 = [&](int buf) __attribute__((always_inline)) { stash_from(ha, hb, buf); };
   // k-step s: lanes 0-31 take bytes 64 s .. 64 s + 31 of their row, lanes
   // 32-63 bytes 64 s + 32 .. 64 s + 63 (the same split for both operands).
   auto mma = [&](f32x16 (&acc)[2][2], int buf) __attribute__((always_inline)) {
@@ -199,32 +210,56 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
     }
   };
 
-  // with a loaded point Gram the pipeline starts at the first image chunk
-  const bool gload = b.gmode == 2;
   const int64_t tix = (int64_t)I * NT - (int64_t)I * (I - 1) / 2 + (J - I);
-  const int c0 = gload ? nchx : 0;
-  fetch(c0);
-  stash(c0 & 1);
-  __syncthreads();
-  for (int c = c0; c < nchx; ++c) {
-    const int buf = c & 1;
-    if (c + 1 < total) fetch(c + 1);
-    mma(accX, buf);
-    if (c + 1 < total) stash(buf ^ 1);
+  if (LOADED) {
+    // image chunk k (0 <= k < nk) sits in LDS buffer k & 1 and, while in
+    // flight, in register set k & 1
+    const int nk = nchy;
+    fetch(nchx);
+    if (nk > 1) fetch2(nchx + 1);
+    stash(0);
     __syncthreads();
-  }
-  for (int c = nchx; c < total; ++c) {
-    const int buf = c & 1;
-    if (c + 1 < total) fetch(c + 1);
-    mma(accY, buf);
-    if (c + 1 < total) stash(buf ^ 1);
+    int k = 0;
+    for (; k + 2 < nk; k += 2) {
+      fetch(nchx + k + 2);
+      mma(accY, 0);
+      stash2(1);
+      __syncthreads();
+      if (k + 3 < nk) fetch2(nchx + k + 3);
+      mma(accY, 1);
+      stash(0);
+      __syncthreads();
+    }
+    mma(accY, 0);
+    if (k + 1 < nk) {
+      stash2(1);
+      __syncthreads();
+      mma(accY, 1);
+    }
+    // the cached point Gram after the image loop, where its accumulators
+    // become live
+    gcache_load(b.gcache, tix, accX);
+  } else {
+    fetch(0);
+    stash(0);
     __syncthreads();
+    for (int c = 0; c < nchx; ++c) {
+      const int buf = c & 1;
+      if (c + 1 < total) fetch(c + 1);
+      mma(accX, buf);
+      if (c + 1 < total) stash(buf ^ 1);
+      __syncthreads();
+    }
+    for (int c = nchx; c < total; ++c) {
+      const int buf = c & 1;
+      if (c + 1 < total) fetch(c + 1);
+      mma(accY, buf);
+      if (c + 1 < total) stash(buf ^ 1);
+      __syncthreads();
+    }
+    // stored after the image loop: earlier stores would hold up its chunk loads
+    if (b.gmode == 1) gcache_store(b.gcache, tix, accX);
   }
-  // the cached point Gram after the image loop, where its accumulators become
-  // live (the loop then holds the image accumulators only); stores after it
-  // too (earlier they would hold up its chunk loads)
-  if (gload) gcache_load(b.gcache, tix, accX);
-  if (b.gmode == 1) gcache_store(b.gcache, tix, accX);
   if (store_only) return;
 
   // epilogue: central estimates, largest and smallest q~ of the tile
@@ -401,8 +436,11 @@ hipError_t launch_pairs_screen_fp8(const unsigned char* Xq, int ldx, const unsig
                                    hipStream_t st) {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pairs_fp8),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pairs_fp8<false>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsFp8);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pairs_fp8<true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsFp8);
     if (e != hipSuccess) return e;
     attr = true;
   }
@@ -416,7 +454,9 @@ hipError_t launch_pairs_screen_fp8(const unsigned char* Xq, int ldx, const unsig
   a.recs = recs;
   a.gcache = gcache;
   a.gmode = gcache ? gmode : 0;
-  k_pairs_fp8<<<(unsigned)round_up(a.nslots, 8), 256, kLdsFp8, st>>>(a);
+  const unsigned G = (unsigned)round_up(a.nslots, 8);
+  if (a.gmode == 2 && a.nchy >= 1) k_pairs_fp8<true><<<G, 256, kLdsFp8, st>>>(a);
+  else k_pairs_fp8<false><<<G, 256, kLdsFp8, st>>>(a);
   return hipGetLastError();
 }
 
