@@ -155,22 +155,40 @@ __global__ __launch_bounds__(256) void k_bj_solve(const double* __restrict__ A, 
 }
 
 // One 32 x 32 quadrant (wave w: rows 32 (w / 2), columns 32 (w % 2)) of
-// C = X^T Y for 64 x 64 LDS matrices X, Y (row stride JLD): C[i][j] =
+// C = X^T Y for 64 x 64 matrices X (row stride LDX) and Y (row stride LDY),
+// one in global memory (XG: X, else Y) and one in LDS: C[i][j] =
 // sum_k X[k][i] Y[k][j], on v_mfma_f64_16x16x4f64 (A operand lane l: row
 // l % 16, k = 4 ks + l / 16; B operand: column l % 16, same k; D register v:
-// row 4 v + l / 16, column l % 16).
-__device__ inline void quad_xty(const double* X, const double* Y, f64x4 (&acc)[2][2]) {
+// row 4 v + l / 16, column l % 16).  The global operand's values are all
+// loaded before the products; the LDS operand's as they are needed.
+template <int LDX, int LDY, bool XG>
+__device__ inline void quad_xty(const double* __restrict__ X, const double* __restrict__ Y, f64x4 (&acc)[2][2]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r0 = (wave >> 1) * 32, c0 = (wave & 1) * 32;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = (f64x4){0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
+  const double* G = XG ? X : Y;
+  const int ldg = XG ? LDX : LDY, g0 = XG ? r0 : c0;
+  double ga[JS / 4], gb[JS / 4];
+#pragma unroll
   for (int ks = 0; ks < JS / 4; ++ks) {
     const int k = 4 * ks + (lane >> 4);
-    const double x0 = X[k * JLD + r0 + (lane & 15)], x1 = X[k * JLD + r0 + 16 + (lane & 15)];
-    const double y0 = Y[k * JLD + c0 + (lane & 15)], y1 = Y[k * JLD + c0 + 16 + (lane & 15)];
+    ga[ks] = G[k * ldg + g0 + (lane & 15)];
+    gb[ks] = G[k * ldg + g0 + 16 + (lane & 15)];
+  }
+#pragma unroll
+  for (int ks = 0; ks < JS / 4; ++ks) {
+    const int k = 4 * ks + (lane >> 4);
+    double x0, x1, y0, y1;
+    if (XG) {
+      x0 = ga[ks]; x1 = gb[ks];
+      y0 = Y[k * LDY + c0 + (lane & 15)]; y1 = Y[k * LDY + c0 + 16 + (lane & 15)];
+    } else {
+      x0 = X[k * LDX + r0 + (lane & 15)]; x1 = X[k * LDX + r0 + 16 + (lane & 15)];
+      y0 = ga[ks]; y1 = gb[ks];
+    }
     acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, acc[0][0], 0, 0, 0);
     acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y1, acc[0][1], 0, 0, 0);
     acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y0, acc[1][0], 0, 0, 0);
@@ -186,9 +204,11 @@ __device__ inline void quad_xty(const double* X, const double* Y, f64x4 (&acc)[2
 __global__ __launch_bounds__(256) void k_bj_apply(double* __restrict__ A, double* __restrict__ W,
                                                   const double* __restrict__ Uall, const double* __restrict__ Sall,
                                                   const int* __restrict__ rotated, int m, int nb, int t) {
+  // one 64 x 64 LDS buffer (the tile, then the intermediate); the rotations
+  // U are read from global memory (L2 resident), so several workgroups share
+  // a CU
   extern __shared__ double lds_d[];
   double* X = lds_d;
-  double* Y = lds_d + JS * JLD;
   const int half = nb / 2;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r0 = (wave >> 1) * 32, c0w = (wave & 1) * 32;
@@ -216,10 +236,9 @@ __global__ __launch_bounds__(256) void k_bj_apply(double* __restrict__ A, double
       for (int e = tid; e < JS * JS; e += 256) {
         const int i = e / JS, j = e % JS;
         X[i * JLD + j] = A[(int64_t)sub_index(P, Q, i) * m + sub_index(R, S, j)];
-        Y[i * JLD + j] = ua[e];
       }
       __syncthreads();
-      quad_xty(Y, X, acc);          // T1 = Ua^T A_tile
+      quad_xty<JS, JLD, true>(ua, X, acc);    // T1 = Ua^T A_tile
       __syncthreads();
       if (rot_b) {
         // X <- T1^T (X[j][i] = T1[i][j])
@@ -241,9 +260,8 @@ __global__ __launch_bounds__(256) void k_bj_apply(double* __restrict__ A, double
       }
     }
     if (rot_b) {
-      for (int e = tid; e < JS * JS; e += 256) Y[(e / JS) * JLD + (e % JS)] = ub[e];
       __syncthreads();
-      quad_xty(X, Y, acc);          // T1 Ub = (T1^T)^T Ub
+      quad_xty<JLD, JS, false>(X, ub, acc);   // T1 Ub = (T1^T)^T Ub
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -266,10 +284,9 @@ __global__ __launch_bounds__(256) void k_bj_apply(double* __restrict__ A, double
     for (int e = tid; e < JS * JS; e += 256) {
       const int i = e / JS, j = e % JS;
       X[i * JLD + j] = W[(int64_t)sub_index(P, Q, i) * m + c0 + j];
-      Y[i * JLD + j] = ua[e];
     }
     __syncthreads();
-    quad_xty(Y, X, acc);
+    quad_xty<JS, JLD, true>(ua, X, acc);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -283,7 +300,7 @@ __global__ __launch_bounds__(256) void k_bj_apply(double* __restrict__ A, double
 }
 
 constexpr size_t kLdsSolve = 3 * JS * JLD * sizeof(double);
-constexpr size_t kLdsApply = 2 * JS * JLD * sizeof(double);
+constexpr size_t kLdsApply = JS * JLD * sizeof(double);
 
 hipError_t launch_bj_round(double* A, double* W, double* Uall, double* Sall, int* rotated, int m, int t,
                            double thr, int* rot_count, hipStream_t st) {
