@@ -593,8 +593,8 @@ def summarize_mfma(d):
     out = {}
     for kind, key in (("fill", FULL_KERNEL), ("cached", CACHED_KERNEL)):
         ds = [v for (i, k), v in sorted(per.items()) if key in k]
-        if kind == "cached":      # the fit's screens in probe order
-            alg = [npairs * 2.0 * c for c in cols]
+        if kind == "cached":      # each fit's screens in probe order (the run may hold several fits)
+            alg = [npairs * 2.0 * cols[i % len(cols)] for i in range(len(ds))]
         else:
             alg = [npairs * 2.0 * dx for _ in ds]
         util = [v["MfmaUtil"] for v in ds]

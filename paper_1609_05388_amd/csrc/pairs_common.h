@@ -56,23 +56,27 @@ __device__ inline void wave_arg(float& v, int& i, int& j) {
 // tile's 64 KB block, so every store and load of a wave is one contiguous
 // 1 KB segment.  The points do not change across the certificates of one
 // fit, so the first certificate stores the Grams and the others load them.
+// Every tile is written once and read once per screen: non-temporal stores
+// and loads, so that the stream of cache blocks does not evict the row and
+// column panels that neighbouring tiles share in L2.
 __device__ inline void gcache_store(float* cache, int64_t tile, const f32x16 (&acc)[2][2]) {
-  float4* g = reinterpret_cast<float4*>(cache) + tile * 4096 + threadIdx.x;
+  f32x4* g = reinterpret_cast<f32x4*>(cache) + tile * 4096 + threadIdx.x;
 #pragma unroll
   for (int k4 = 0; k4 < 16; ++k4) {
     const f32x16& a = acc[k4 >> 3][(k4 >> 2) & 1];
     const int v = (k4 & 3) * 4;
-    g[k4 * 256] = make_float4(a[v], a[v + 1], a[v + 2], a[v + 3]);
+    const f32x4 t = {a[v], a[v + 1], a[v + 2], a[v + 3]};
+    __builtin_nontemporal_store(t, g + k4 * 256);
   }
 }
 __device__ inline void gcache_load(const float* cache, int64_t tile, f32x16 (&acc)[2][2]) {
-  const float4* g = reinterpret_cast<const float4*>(cache) + tile * 4096 + threadIdx.x;
+  const f32x4* g = reinterpret_cast<const f32x4*>(cache) + tile * 4096 + threadIdx.x;
 #pragma unroll
   for (int k4 = 0; k4 < 16; ++k4) {
-    const float4 t = g[k4 * 256];
+    const f32x4 t = __builtin_nontemporal_load(g + k4 * 256);
     f32x16& a = acc[k4 >> 3][(k4 >> 2) & 1];
     const int v = (k4 & 3) * 4;
-    a[v] = t.x; a[v + 1] = t.y; a[v + 2] = t.z; a[v + 3] = t.w;
+    a[v] = t[0]; a[v + 1] = t[1]; a[v + 2] = t[2]; a[v + 3] = t[3];
   }
 }
 struct PairsArgs {
