@@ -67,7 +67,7 @@ struct Workspace {
   DevBuf S, T, Pi, Pi64, Y64, Yc, ny, ty, muY;
   DevBuf recs, tparts, seeds, seedv, list, cand, vals, vparts, cd;
   DevBuf Xb, txb, Yb, tyb, bjU, bjS, bjRot;
-  DevBuf Xq, sx, nxq, Yq, sy, nyq, q8terms, hist, kthr, gcache;
+  DevBuf Xq, sx, nxq, Yq, sy, nyq, q8terms, hist, kthr, gcache, dscale;
   DevBuf rpQ, rpY, rpG, rpV, rpLam;
   DevBuf skpart, skG, skK, sklam, skV, skfeat, mlp_pb, mlp_X, mlp_f, mlp_hb, mlp_grad, mlp_loss;
   DevBuf knQ, knD, knNq64, knNd64, knNq32, knNd32, knMax, knKeys, knFb, knCnt, knTau;
@@ -269,6 +269,8 @@ struct Points {
   // (unscaled, of the centred rows): their row terms take N = ||a||^2 and unit
   // point scales
   bool xgram_split = false;
+  // scale of the fit's compact D^2 cache (precision-form fits with a cache)
+  float* dscale = nullptr;
 };
 
 // Column means (FP64) of the n x m rows of A.  With colmap, also the columns
@@ -828,14 +830,17 @@ static const uint32_t kFp8Tiles = 1024;
 // The certificate of eq. (3) for points p and images im.  With the FP8 screen
 // the same steps run on the FP8 estimates' top tiles only, and the result is
 // the exact maximum over those tiles (certified = 0, no bound on the rest).
-// Point-Gram cache for the certificates of one fit (64 KB per tile of pairs):
-// the points do not change across a fit's certificates, so the first one
-// stores every tile's point Gram and the others read it back instead of
-// recomputing it.  Null (no caching) when it would take more than half of the
-// free device memory.
+// Point-Gram cache for the certificates of one fit: the points do not change
+// across a fit's certificates, so a fill stores every tile's point side once
+// and the screens read it back instead of recomputing it.  FP32 screens keep
+// the FP32 point Gram (64 KB per tile of pairs), the precision forms the
+// compact D^2 cache (32 KB per tile).  Null (no caching) when it would take
+// more than half of the free device memory.
 static float* gram_cache(Workspace& ws, const Points& p) {
   const int64_t NT = p.n_pad / kTile;
-  const size_t bytes = (size_t)(NT * (NT + 1) / 2) * (size_t)kGcacheFloatsPerTile * sizeof(float);
+  const bool compact = p.screen == ADAGIO_SCREEN_BF16X3 || p.screen == ADAGIO_SCREEN_FP8;
+  const size_t per_tile = compact ? (size_t)kDcacheBytesPerTile : (size_t)kGcacheFloatsPerTile * sizeof(float);
+  const size_t bytes = (size_t)(NT * (NT + 1) / 2) * per_tile;
   if (ws.gcache.cap >= bytes) return static_cast<float*>(ws.gcache.p);
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) return nullptr;
@@ -923,10 +928,11 @@ static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& i
       vb.Yb = im.Yb; vb.ldy = (int)im.ldyb;
       vb.tx = p.txb; vb.ty = im.tyb;
       vb.n = v.n; vb.NT = v.NT; vb.ntiles = v.ntiles;
+      vb.dscale = p.dscale;
       HIPCHK(launch_pairs_screen_bf16(vb, recs, gcache, gmode, stop, st));
     } else if (screen == ADAGIO_SCREEN_FP8) {
       HIPCHK(launch_pairs_screen_fp8(p.Xq, (int)p.ldxq, im.Yq, (int)im.ldyq, im.q8, v.n, v.NT, recs, gcache, gmode,
-                                     st));
+                                     p.dscale, st));
     } else {
       HIPCHK(launch_pairs_screen(v, recs, gcache, gmode, stop, st));
     }
@@ -1174,12 +1180,15 @@ static void gram_fill_async(Workspace& ws, const Points& p, int screen, float* g
   const int NT = (int)(p.n_pad / kTile);
   const int64_t ntiles = (int64_t)NT * (NT + 1) / 2;
   if (screen == ADAGIO_SCREEN_BF16X3 || screen == ADAGIO_SCREEN_FP8) {
-    // an FP8 fit's screens and its BF16 split certificates share this one
+    // the compact D^2 cache, from the BF16 split point Gram: an FP8 fit's
+    // screens and its BF16 split certificates share this one
+    HIPCHK(launch_dcache_scale(p.nx, p.n_pad, p.dscale, ws.aux));
     PairsViewB vb;
     vb.Xb = p.Xb; vb.ldx = (int)p.ldxb;
     vb.Yb = p.Xb; vb.ldy = 0;
     vb.tx = p.txb; vb.ty = p.txb;
     vb.n = (int)p.n; vb.NT = NT; vb.ntiles = ntiles;
+    vb.dscale = p.dscale;
     HIPCHK(launch_pairs_gram_fill_bf16(vb, gcache, ws.aux));
   } else {
     PairsView v;
@@ -1481,6 +1490,8 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     // the second stream while the PCA runs.
     float* gcache = gram_cache(ws, p);
     p.xgram_split = gcache && screen == ADAGIO_SCREEN_FP8;
+    if (gcache && (screen == ADAGIO_SCREEN_BF16X3 || screen == ADAGIO_SCREEN_FP8))
+      p.dscale = ensure<float>(ws.dscale, 1);
     const bool gwait_pca = gcache && family != ADAGIO_MAP_JL && pca == ADAGIO_PCA_EXACT;
     bool gwait = gcache != nullptr;
     // without the exact PCA to run beside, the fill starts at once
@@ -1497,7 +1508,7 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
       if (gwait_pca) {
         // beside the fill: on the non-blocking third stream after the
         // centred copies, the fill starting once the covariance (a large
-        // library GEMM) is done, so that it runs beside the eigensolver's
+        // GEMM) is done, so that it runs beside the eigensolver's
         // small kernels only; st continues after the PCA
         ensure_streams(ws);
         HIPCHK(hipEventRecord(ws.ev_in, st));

@@ -25,6 +25,9 @@ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 // FP32 values of a tile's point Gram in the screens' point-Gram cache.
 constexpr int64_t kGcacheFloatsPerTile = (int64_t)kTile * kTile;
+// Bytes of a tile's block in the precision-form screens' compact D^2 cache
+// (one FP16 value per pair).
+constexpr int64_t kDcacheBytesPerTile = (int64_t)kTile * kTile * 2;
 
 // kNN screen: candidates kept per query and database split, and the most
 // splits one query's keys may span.

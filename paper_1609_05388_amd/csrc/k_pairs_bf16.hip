@@ -47,6 +47,10 @@ struct PairsArgsB {
   PairsArgs p;                         // row terms, sizes, outputs (X/Y fields unused)
 };
 
+// The cache of these screens is the compact D^2 cache (32 KB per tile): the
+// fill (store_only) turns each tile's point Gram into the pairs' D2lo with
+// the row terms and stores it rounded down to FP16 at the fit's scale.
+//
 // LOADED: the point Gram comes from the cache and the kernel runs the image
 // chunks only, with the next two chunks in flight (two register sets of
 // staging loads; the LDS double buffer holds the chunk being multiplied and
@@ -104,9 +108,9 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
     }
     const int row0 = I * kTile, col0 = J * kTile;
     // no tile records: the launch only fills the point-Gram cache
+    // (it still reads the point row terms: the cache holds D2lo)
     const bool store_only = MODE == 0 && p.recs == nullptr;
-    if (store_only) {
-    } else if (tid < kTile) {
+    if (tid < kTile) {
       const float2 a = p.tx[row0 + tid], c = p.ty[row0 + tid];
       termA[tid] = make_float4(a.x, a.y, c.x, c.y);
     } else {
@@ -216,7 +220,7 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
       }
       // the last one or two chunks: no staging loads left, so the cached
       // point Gram loads here and lands during their MFMAs
-      gcache_load(p.gcache, tix, accX);
+      dcache_load(p.gcache, tix, accX, *p.dscale);
       mma(accY, 0);
       if (k + 1 < nk) {
         stash_from(g1, 1);
@@ -244,15 +248,43 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
         __syncthreads();
       }
     }
-    // stored after the image loop: earlier stores would hold up its chunk loads
-    if (!LOADED && MODE == 0 && p.gmode == 1) gcache_store(p.gcache, tix, accX);
-    if (store_only) return;
+    if (store_only) {
+      gram_to_d2lo(accX, termA, termB);
+      dcache_store(p.gcache, tix, accX, 1.0f / *p.dscale);
+      return;
+    }
 
-    tile_epilogue<MODE>(accX, accY, termA, termB, I, J, p, thr_hi, thr_lo, red_v, red_i, red_j);
+    tile_epilogue<MODE, LOADED>(accX, accY, termA, termB, I, J, p, thr_hi, thr_lo, red_v, red_i, red_j);
     if (MODE == 0) return;
     u += gridDim.x;
     if (u >= u_end) return;
     __syncthreads();
+  }
+}
+
+// Scale of a compact D^2 cache: the power of two 2^e >= max_i N_i / 8192,
+// clamped to [2^-120, 2^120] (row norms whose squares pass FP32's range make
+// the FP32 row terms infinite, and those pairs are re-examined anyway).
+// Every D2lo is at most D^2 <= 4 max N, so D2lo / scale <= 32768 stays within
+// FP16's range, and with a power of two the division and the multiplication
+// back are exact.
+__global__ __launch_bounds__(1024) void k_dcache_scale(const double* __restrict__ nx, int64_t n,
+                                                       float* __restrict__ scale) {
+  __shared__ double red[16];
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) m = fmax(m, nx[i]);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 16; ++w) m = fmax(m, red[w]);
+    int e = -120;
+    if (m > 0.0) {
+      frexp(m / 8192.0, &e);   // m / 8192 = f 2^e, f in [0.5, 1)
+      e = e < -120 ? -120 : (e > 120 ? 120 : e);
+    }
+    scale[0] = ldexpf(1.0f, e);
   }
 }
 
@@ -261,6 +293,11 @@ constexpr size_t kLdsBf16 = 4 * kTile * BROW + 2 * kTile * sizeof(float4) + 3 * 
 hipError_t launch_split_bf16(const float* src, int64_t n_pad, int64_t m, int64_t lds, int64_t ldb, __bf16* dst,
                              hipStream_t st) {
   k_split_bf16<<<(unsigned)((n_pad * ldb + 255) / 256), 256, 0, st>>>(src, n_pad, m, lds, ldb, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_dcache_scale(const double* nx, int64_t n, float* scale, hipStream_t st) {
+  k_dcache_scale<<<1, 1024, 0, st>>>(nx, n, scale);
   return hipGetLastError();
 }
 
@@ -280,6 +317,8 @@ static hipError_t bf16_attrs() {
 
 hipError_t launch_pairs_screen_bf16(const PairsViewB& v, TileRec* recs, float* gcache, int gmode,
                                     const ScreenStop* stop, hipStream_t st) {
+  // the compact cache is filled by launch_pairs_gram_fill_bf16 only
+  if (gcache && (gmode == 1 || v.dscale == nullptr)) return hipErrorInvalidValue;
   hipError_t e0 = bf16_attrs();
   if (e0 != hipSuccess) return e0;
   const int NS = (v.NT + 7) / 8;
@@ -289,7 +328,7 @@ hipError_t launch_pairs_screen_bf16(const PairsViewB& v, TileRec* recs, float* g
   a.Y = v.Yb; a.ldy = v.ldy; a.nchy = v.ldy / BK;
   a.p = PairsArgs{nullptr, 0, 0, nullptr, 0, 0, v.tx, v.ty, v.n, v.NT, v.ntiles, NS, nslots, recs,
                   nullptr, nullptr, nullptr, 0u, nullptr, gcache, gcache ? gmode : 0,
-                  nullptr, nullptr, 3.0e38f, -1.0f};
+                  nullptr, nullptr, 3.0e38f, -1.0f, v.dscale};
   if (stop) {
     a.p.stop = stop->count; a.p.stop_pairs = stop->pairs; a.p.stop_hi = stop->q_hi; a.p.stop_lo = stop->q_lo;
   }
@@ -301,6 +340,7 @@ hipError_t launch_pairs_screen_bf16(const PairsViewB& v, TileRec* recs, float* g
 }
 
 hipError_t launch_pairs_gram_fill_bf16(const PairsViewB& v, float* gcache, hipStream_t st) {
+  if (!gcache || !v.dscale) return hipErrorInvalidValue;
   hipError_t e0 = bf16_attrs();
   if (e0 != hipSuccess) return e0;
   const int NS = (v.NT + 7) / 8;
@@ -309,7 +349,7 @@ hipError_t launch_pairs_gram_fill_bf16(const PairsViewB& v, float* gcache, hipSt
   a.X = v.Xb; a.ldx = v.ldx; a.nchx = v.ldx / BK;
   a.Y = v.Xb; a.ldy = 0; a.nchy = 0;
   a.p = PairsArgs{nullptr, 0, 0, nullptr, 0, 0, v.tx, v.tx, v.n, v.NT, v.ntiles, NS, nslots, nullptr,
-                  nullptr, nullptr, nullptr, 0u, nullptr, gcache, 1, nullptr, nullptr, 3.0e38f, -1.0f};
+                  nullptr, nullptr, nullptr, 0u, nullptr, gcache, 1, nullptr, nullptr, 3.0e38f, -1.0f, v.dscale};
   k_pairs_bf16x3<0, false><<<(unsigned)round_up(nslots, 8), 256, kLdsBf16, st>>>(a);
   return hipGetLastError();
 }

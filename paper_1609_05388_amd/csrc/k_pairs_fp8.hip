@@ -103,13 +103,16 @@ struct PairsArgsF {
   const float4* terms;                         // (N_x, N_y, -2 s_x, -2 s_y) per row
   int n; int NT; int NS; int64_t nslots;
   TileRec* recs;
-  float* gcache; int gmode;                    // point-Gram cache: 0 off, 1 store, 2 load
+  float* gcache; int gmode;                    // compact D^2 cache of the fit: 0 off, 2 load
+  const float* dscale;                         // its scale (device)
 };
 
-// LOADED: the point Gram comes from the cache; the kernel runs the image
-// chunks only, with the next two chunks in flight (two register sets of
-// staging loads; a 128-column chunk is only 8 MFMAs per wave, far less than
-// a global load's latency), and loads the cached Gram after them.
+// LOADED: the pairs' D2lo come from the fit's compact D^2 cache (filled from
+// the BF16 split point Gram, a far better D^2 estimate than the FP8 Gram);
+// the kernel runs the image chunks only, with the next two chunks in flight
+// (two register sets of staging loads; a 128-column chunk is only 8 MFMAs per
+// wave, far less than a global load's latency), and loads the cached block
+// after them.
 template <bool LOADED>
 __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
@@ -135,10 +138,7 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
   if (tp.I < 0) return;
   const int I = (int)tp.I, J = (int)tp.J;
   const int row0 = I * kTile, col0 = J * kTile;
-  // no tile records: the launch only fills the point-Gram cache
-  const bool store_only = b.recs == nullptr;
-  if (store_only) {
-  } else if (tid < kTile) termA[tid] = b.terms[row0 + tid];
+  if (tid < kTile) termA[tid] = b.terms[row0 + tid];
   else termB[tid - kTile] = b.terms[col0 + tid - kTile];
 
   f32x16 accX[2][2], accY[2][2];
@@ -236,9 +236,9 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
       __syncthreads();
       mma(accY, 1);
     }
-    // the cached point Gram after the image loop, where its accumulators
-    // become live
-    gcache_load(b.gcache, tix, accX);
+    // the cached block after the image loop, where its accumulators become
+    // live
+    dcache_load(b.gcache, tix, accX, *b.dscale);
   } else {
     fetch(0);
     stash(0);
@@ -257,10 +257,7 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
       if (c + 1 < total) stash(buf ^ 1);
       __syncthreads();
     }
-    // stored after the image loop: earlier stores would hold up its chunk loads
-    if (b.gmode == 1) gcache_store(b.gcache, tix, accX);
   }
-  if (store_only) return;
 
   // epilogue: central estimates, largest and smallest q~ of the tile
   const bool masked = !((I < J) && (col0 + kTile <= n));
@@ -281,7 +278,8 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
 #pragma unroll
       for (int y = 0; y < 2; ++y) {
         const float4 tb = y ? tb1 : tb0;
-        const float d2 = fmaf(ta.z * tb.z, accX[x][y][v], ta.x + tb.x);   // -2 s_i s_j g + N_i + N_j
+        // -2 s_i s_j g + N_i + N_j, or the cached D2lo
+        const float d2 = LOADED ? accX[x][y][v] : fmaf(ta.z * tb.z, accX[x][y][v], ta.x + tb.x);
         const float e2 = fmaf(ta.w * tb.w, accY[x][y][v], ta.y + tb.y);
         const float q = e2 * __builtin_amdgcn_rcpf(d2);
         const uint32_t k = pair_key(fmaxf(q, 0.0f), (x * 2 + y) * 16 + v);
@@ -433,7 +431,8 @@ hipError_t launch_fp8_terms(const double* nx, const double* ny, const float* sx,
 
 hipError_t launch_pairs_screen_fp8(const unsigned char* Xq, int ldx, const unsigned char* Yq, int ldy,
                                    const float4* terms, int n, int NT, TileRec* recs, float* gcache, int gmode,
-                                   hipStream_t st) {
+                                   const float* dscale, hipStream_t st) {
+  if (!recs || (gcache && (gmode != 2 || dscale == nullptr))) return hipErrorInvalidValue;
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pairs_fp8<false>),
@@ -454,6 +453,7 @@ hipError_t launch_pairs_screen_fp8(const unsigned char* Xq, int ldx, const unsig
   a.recs = recs;
   a.gcache = gcache;
   a.gmode = gcache ? gmode : 0;
+  a.dscale = dscale;
   const unsigned G = (unsigned)round_up(a.nslots, 8);
   if (a.gmode == 2 && a.nchy >= 1) k_pairs_fp8<true><<<G, 256, kLdsFp8, st>>>(a);
   else k_pairs_fp8<false><<<G, 256, kLdsFp8, st>>>(a);

@@ -113,9 +113,17 @@ struct PairsViewB {
   const __bf16* Yb; int ldy;    // hi/lo split images
   const float2* tx; const float2* ty;
   int n; int NT; int64_t ntiles;
+  const float* dscale = nullptr;   // scale of the compact D^2 cache (device), with gcache
 };
 hipError_t launch_split_bf16(const float* src, int64_t n_pad, int64_t m, int64_t lds, int64_t ldb, __bf16* dst,
                              hipStream_t st);
+// The precision-form screens' cache is the compact D^2 cache: per tile the
+// 16384 pairs' D2lo, rounded down to FP16 at a power-of-two scale (32 KB per
+// tile; kDcacheBytesPerTile).  scale: one float on the device, from
+// launch_dcache_scale over the points' row norms N_i (FP64, n_pad of them).
+hipError_t launch_dcache_scale(const double* nx, int64_t n, float* scale, hipStream_t st);
+// gcache: null, or the compact cache with gmode 2 (and v.dscale); gmode 1 is
+// refused (the fill below writes the cache).
 hipError_t launch_pairs_screen_bf16(const PairsViewB& v, TileRec* recs, float* gcache, int gmode,
                                     const ScreenStop* stop, hipStream_t st);
 hipError_t launch_pairs_gram_fill_bf16(const PairsViewB& v, float* gcache, hipStream_t st);
@@ -177,14 +185,16 @@ hipError_t launch_sym_eigvals(const double* A, int m, int lda, double* lam, hipS
 // lds): q (ldq bytes per row, zero padded), scale s_i, N_i = s_i^2 |q_i|^2.
 hipError_t launch_quant_fp8(const float* src, int64_t n_pad, int64_t m, int64_t lds, int64_t ldq, unsigned char* q,
                             float* scale, double* norm2, hipStream_t st);
-// sx null: unit point scales (point Gram loaded unscaled from a BF16 split cache).
+// sx null: unit point scales (the point side then comes from the fit's
+// compact D^2 cache and these terms' point entries go unused).
 hipError_t launch_fp8_terms(const double* nx, const double* ny, const float* sx, const float* sy, int64_t n_pad,
                             float4* t, hipStream_t st);
-// Estimated q extremes per tile (ldx, ldy multiples of fp8_chunk()); gcache /
-// gmode as for launch_pairs_screen.
+// Estimated q extremes per tile (ldx, ldy multiples of fp8_chunk()).  gcache:
+// null, or the fit's compact D^2 cache (launch_pairs_gram_fill_bf16) with
+// gmode 2 and its scale dscale; recs non-null.
 hipError_t launch_pairs_screen_fp8(const unsigned char* Xq, int ldx, const unsigned char* Yq, int ldy,
                                    const float4* terms, int n, int NT, TileRec* recs, float* gcache, int gmode,
-                                   hipStream_t st);
+                                   const float* dscale, hipStream_t st);
 // Indices of the >= K tiles with the largest estimated distortion appended to
 // list (at most kmax unless a single tied bucket exceeds it; hist: 65536
 // zeroed counters; nsel zeroed, receives the count).

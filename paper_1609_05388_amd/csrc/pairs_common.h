@@ -79,6 +79,54 @@ __device__ inline void gcache_load(const float* cache, int64_t tile, f32x16 (&ac
     a[v] = t[0]; a[v + 1] = t[1]; a[v + 2] = t[2]; a[v + 3] = t[3];
   }
 }
+// Compact cache block of a precision-form fit: per tile the 16384 lower
+// bounds D2lo of the pairs' squared distances (from the fill's Gram and its
+// row terms), divided by the fit's power-of-two scale and rounded down to
+// FP16 (32 KB per tile instead of 64), so the screens that load it stream
+// half the bytes.  Thread tid's 64 values sit in 16-byte slots k8 * 256 + tid
+// (k8 = 0..7, 8 halves each), in the order of its accumulators.  A stored
+// value h gives h * scale <= D2lo <= h * scale * (1 + 2^-10) + 2^-24 scale
+// (FP16 keeps 11 significant bits; 2^-24 is its smallest spacing), and
+// D2lo <= D2 <= D2hi.
+__device__ inline uint16_t f16_down_bits(float x) {
+  const _Float16 h = (_Float16)x;   // round to nearest even (infinity beyond 65504)
+  uint16_t b = __builtin_bit_cast(uint16_t, h);
+  if ((float)h > x) {               // step one FP16 value towards -infinity
+    if (b == 0x0000u) b = 0x8001u;
+    else if (b & 0x8000u) b = (uint16_t)(b + 1u);
+    else b = (uint16_t)(b - 1u);
+  }
+  return b;
+}
+__device__ inline void dcache_store(void* cache, int64_t tile, const f32x16 (&d2)[2][2], float inv_scale) {
+  u32x4* g = reinterpret_cast<u32x4*>(cache) + tile * 2048 + threadIdx.x;
+#pragma unroll
+  for (int k8 = 0; k8 < 8; ++k8) {
+    const f32x16& a = d2[k8 >> 2][(k8 >> 1) & 1];
+    const int v = (k8 & 1) * 8;
+    u32x4 t;
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+      t[w] = (uint32_t)f16_down_bits(a[v + 2 * w] * inv_scale) |
+             ((uint32_t)f16_down_bits(a[v + 2 * w + 1] * inv_scale) << 16);
+    __builtin_nontemporal_store(t, g + k8 * 256);
+  }
+}
+__device__ inline void dcache_load(const void* cache, int64_t tile, f32x16 (&d2)[2][2], float scale) {
+  const u32x4* g = reinterpret_cast<const u32x4*>(cache) + tile * 2048 + threadIdx.x;
+#pragma unroll
+  for (int k8 = 0; k8 < 8; ++k8) {
+    const u32x4 t = __builtin_nontemporal_load(g + k8 * 256);
+    f32x16& a = d2[k8 >> 2][(k8 >> 1) & 1];
+    const int v = (k8 & 1) * 8;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      a[v + 2 * w] = (float)__builtin_bit_cast(_Float16, (uint16_t)(t[w] & 0xFFFFu)) * scale;
+      a[v + 2 * w + 1] = (float)__builtin_bit_cast(_Float16, (uint16_t)(t[w] >> 16)) * scale;
+    }
+  }
+}
+
 struct PairsArgs {
   const float* X; int ldx; int nchx;   // centred points, n_pad x ldx, ldx = 16 * nchx
   const float* Y; int ldy; int nchy;   // centred images, n_pad x ldy
@@ -95,6 +143,9 @@ struct PairsArgs {
   // stop_pairs[*stop] (first 8 kept), *stop counts them, and workgroups that
   // start after *stop became nonzero skip their tile.
   uint32_t* stop; int2* stop_pairs; float stop_hi, stop_lo;
+  // compact D^2 cache (precision-form screens): device pointer to its scale
+  // (null: gcache, if any, holds FP32 point Grams)
+  const float* dscale;
 };
 
 // Bounds on q for one pair from its two Gram entries and row terms.  Branch
@@ -113,6 +164,45 @@ __device__ inline void pair_bounds(float gx, float gy, const float4& ta, const f
   qhi = d2lo > 1e-30f ? h : 3.0e38f;
   qlo = d2hi > 1e-30f ? l : 0.0f;
   if (!(d2hi > 0.0f)) { qhi = 1.0f; qlo = 1.0f; }
+}
+
+// Bounds on q for one pair of a compact-cache screen, from L = the cached
+// D2lo rounded down (h * scale), the image Gram entry and the row terms.
+// D^2 <= D2lo + 1.25 (width_i + width_j) (the bound the FP32 epilogue's
+// d2hi also satisfies) and D2lo <= L (1 + 2^-10) + 2^-24 scale, so
+//   D2hi' = max(L, 0) (1 + 2^-9) + 1.25 (1 + 2^-20) w + 2^-23 scale
+// (w = the two widths' sum), formed with two FMAs, is an upper bound on D^2:
+// the doubled constants absorb the roundings of w and of both FMAs.
+// tail = 2^-23 scale.  q_hi = E2hi / L while L > 1e-30; a pair with a
+// smaller L (identical or nearly identical points) gets the widest bounds
+// and is always re-examined.
+__device__ inline void pair_bounds_compact(float L, float gy, const float4& ta, const float4& tb, float tail,
+                                           float& qhi, float& qlo) {
+  const float e2lo = fmaf(-2.0f, gy, ta.z + tb.z);
+  const float e2hi = fmaf(-2.0f, gy, ta.w + tb.w);
+  const float w = (ta.y - ta.x) + (tb.y - tb.x);
+  const float d2hi = fmaf(fmaxf(L, 0.0f), 0x1.008p+0f, fmaf(w, 0x1.400014p+0f, tail));
+  const float h = fmaxf(e2hi, 0.0f) * __builtin_amdgcn_rcpf(L);
+  const float l = fmaxf(e2lo, 0.0f) * __builtin_amdgcn_rcpf(d2hi);
+  qhi = L > 1e-30f ? h : 3.0e38f;
+  qlo = d2hi > 1e-30f ? l : 0.0f;
+}
+
+// A tile's point Gram (accumulators in the D layout) turned in place into the
+// pairs' D2lo = (lo_i + lo_j) - 2 g, the value the FP32 epilogue bounds D^2
+// from below with; what a compact cache block stores.
+__device__ inline void gram_to_d2lo(f32x16 (&acc)[2][2], const float4* termA, const float4* termB) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1, li = lane & 31, lh = lane >> 5;
+  const float b0 = termB[wc * 64 + li].x, b1 = termB[wc * 64 + 32 + li].x;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const float a = termA[wr * 64 + x * 32 + (v >> 2) * 8 + lh * 4 + (v & 3)].x;
+      acc[x][0][v] = fmaf(-2.0f, acc[x][0][v], a + b0);
+      acc[x][1][v] = fmaf(-2.0f, acc[x][1][v], a + b1);
+    }
 }
 
 // Wave-wide reductions (all lanes receive the result).
@@ -159,7 +249,9 @@ __device__ inline float key_lo_value(uint32_t k) { return __uint_as_float(k & 0x
 // column l % 32), which is the same for v_mfma_f32_32x32x2f32 and
 // v_mfma_f32_32x32x16_bf16.  MODE 0 writes the tile record (after a
 // block-wide barrier); MODE 1 appends the pairs reaching the thresholds.
-template <int MODE>
+// COMPACT: accX holds the compact cache's L (the point Gram's D2lo rounded
+// down) in place of the point Gram.
+template <int MODE, bool COMPACT = false>
 __device__ __attribute__((always_inline)) inline void tile_epilogue(const f32x16 (&accX)[2][2], const f32x16 (&accY)[2][2],
                                      const float4* termA, const float4* termB, int I, int J,
                                      const PairsArgs& p, float thr_hi, float thr_lo, float (*red_v)[4],
@@ -176,6 +268,7 @@ __device__ __attribute__((always_inline)) inline void tile_epilogue(const f32x16
   int code_hi = -1, code_lo = -1, code_c = -1;
   const float stop_hi = p.stop_hi, stop_lo = p.stop_lo;
   const float4 tb0 = termB[wc * 64 + li], tb1 = termB[wc * 64 + 32 + li];
+  const float dsc = COMPACT ? *p.dscale : 0.0f;
   // The pass over the thread's 64 pairs, compiled once with the edge mask and
   // once without (the mask is uniform per tile: no per-pair branch).
   auto scan = [&](auto maskc) __attribute__((always_inline)) {
@@ -189,7 +282,8 @@ __device__ __attribute__((always_inline)) inline void tile_epilogue(const f32x16
 #pragma unroll
         for (int y = 0; y < 2; ++y) {
           float qhi, qlo;
-          pair_bounds(accX[x][y][v], accY[x][y][v], ta, y ? tb1 : tb0, qhi, qlo);
+          if (COMPACT) pair_bounds_compact(accX[x][y][v], accY[x][y][v], ta, y ? tb1 : tb0, 0x1p-23f * dsc, qhi, qlo);
+          else pair_bounds(accX[x][y][v], accY[x][y][v], ta, y ? tb1 : tb0, qhi, qlo);
           bool certain = MODE == 0 && (qlo > stop_hi || qhi < stop_lo);
           if (M) {
             const int cl = wc * 64 + y * 32 + li;
@@ -235,7 +329,10 @@ __device__ __attribute__((always_inline)) inline void tile_epilogue(const f32x16
   // with E2hi and D2lo.  A wave whose smallest D2lo or E2hi is within 64
   // widths (so q_lo would lose more than about 3%), holds a pair with
   // D2lo <= 1e-30 (identical or nearly identical points) or a q+ near FP32
-  // overflow takes the per-pair pass above instead.
+  // overflow takes the per-pair pass above instead.  COMPACT: D2lo <=
+  // L (1 + 2^-10) + 2^-24 scale for the cached L, so the same steps hold with
+  // L in place of D2lo, 1 + 2^-10 + (W_D + 2^-24 scale) / L_min in the
+  // denominator and W_D + 2^-24 scale in the width test.
   bool fast = false;
   if (MODE == 0) {
     uint32_t khi = 0u, klo = 0xFFFFFFFFu;
@@ -251,7 +348,7 @@ __device__ __attribute__((always_inline)) inline void tile_epilogue(const f32x16
 #pragma unroll
           for (int y = 0; y < 2; ++y) {
             const float4 tb = y ? tb1 : tb0;
-            const float d2lo = fmaf(-2.0f, accX[x][y][v], ta.x + tb.x);
+            const float d2lo = COMPACT ? accX[x][y][v] : fmaf(-2.0f, accX[x][y][v], ta.x + tb.x);
             const float e2hi = fmaf(-2.0f, accY[x][y][v], ta.w + tb.w);
             const float q = e2hi * __builtin_amdgcn_rcpf(d2lo);
             const uint32_t k = pair_key(q, (x * 2 + y) * 16 + v);
@@ -282,13 +379,15 @@ __device__ __attribute__((always_inline)) inline void tile_epilogue(const f32x16
     const float wDc = wave_max_f32(cb.y - cb.x), wEc = wave_max_f32(cb.w - cb.z);
     const uint32_t whi = wave_max_u32(khi), wlo = wave_min_u32(klo);
     const float wd = wave_min_f32(dmin), we = wave_min_f32(emin);
-    const double WD = 1.25 * ((double)wDr + (double)wDc), WE = 1.25 * ((double)wEr + (double)wEc);
+    const double WD = 1.25 * ((double)wDr + (double)wDc) + (COMPACT ? 0x1p-24 * (double)dsc : 0.0);
+    const double WE = 1.25 * ((double)wEr + (double)wEc);
+    const double rel = COMPACT ? 0x1p-10 : 0.0;
     // a wave without valid pairs (whi = 0, wlo = ~0) has no record to make
     const bool any = wlo != 0xFFFFFFFFu;
     fast = any && wd > 1e-30f && (double)wd > 64.0 * WD && (double)we > 64.0 * WE && whi < 0x7F000000u;
     if (fast) {
       const float vhi = key_hi_value(whi);
-      const double f = (1.0 - WE / (double)we) / (1.0 + WD / (double)wd);
+      const double f = (1.0 - WE / (double)we) / (1.0 + rel + WD / (double)wd);
       const float vlo = (float)((double)key_lo_value(wlo) * (1.0 - 0x1.0p-20) * f * (1.0 - 1e-7));
       // the lanes holding the wave's extreme keys (lowest lane among equal keys)
       const uint64_t bh = __ballot(khi == whi), bl = __ballot(klo == wlo);
