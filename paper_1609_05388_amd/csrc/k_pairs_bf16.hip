@@ -47,9 +47,9 @@ struct PairsArgsB {
   PairsArgs p;                         // row terms, sizes, outputs (X/Y fields unused)
 };
 
-// The cache of these screens is the compact D^2 cache (32 KB per tile): the
-// fill (store_only) turns each tile's point Gram into the pairs' D2lo with
-// the row terms and stores it rounded down to FP16 at the fit's scale.
+// The cache of these screens is the compact cache (32 KB per tile): the fill
+// (store_only) turns each tile's point Gram into the pairs' D2lo with the row
+// terms and stores c / D2lo rounded up to FP16 (dcache_code).
 //
 // LOADED: the point Gram comes from the cache and the kernel runs the image
 // chunks only, with the next two chunks in flight (two register sets of
@@ -197,6 +197,7 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
     };
 
     const int64_t tix = (int64_t)I * p.NT - (int64_t)I * (I - 1) / 2 + (J - I);
+    u32x4 pk[8];   // LOADED: the tile's compact cache block
     if (LOADED) {
       // image chunk k (0 <= k < nk) sits in LDS buffer k & 1 and, while in
       // flight, in register set k & 1
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
       }
       // the last one or two chunks: no staging loads left, so the cached
       // point Gram loads here and lands during their MFMAs
-      dcache_load(p.gcache, tix, accX, *p.dscale);
+      dcache_load(p.gcache, tix, pk);
       mma(accY, 0);
       if (k + 1 < nk) {
         stash_from(g1, 1);
@@ -250,11 +251,12 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
     }
     if (store_only) {
       gram_to_d2lo(accX, termA, termB);
-      dcache_store(p.gcache, tix, accX, 1.0f / *p.dscale);
+      dcache_store(p.gcache, tix, accX, *p.dscale);
       return;
     }
 
-    tile_epilogue<MODE, LOADED>(accX, accY, termA, termB, I, J, p, thr_hi, thr_lo, red_v, red_i, red_j);
+    if constexpr (LOADED) tile_epilogue<MODE, true>(pk, accY, termA, termB, I, J, p, thr_hi, thr_lo, red_v, red_i, red_j);
+    else tile_epilogue<MODE, false>(accX, accY, termA, termB, I, J, p, thr_hi, thr_lo, red_v, red_i, red_j);
     if (MODE == 0) return;
     u += gridDim.x;
     if (u >= u_end) return;
@@ -262,12 +264,12 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
   }
 }
 
-// Scale of a compact D^2 cache: the power of two 2^e >= max_i N_i / 8192,
-// clamped to [2^-120, 2^120] (row norms whose squares pass FP32's range make
-// the FP32 row terms infinite, and those pairs are re-examined anyway).
-// Every D2lo is at most D^2 <= 4 max N, so D2lo / scale <= 32768 stays within
-// FP16's range, and with a power of two the division and the multiplication
-// back are exact.
+// Constant c of a compact cache: the power of two with
+// 2^-12 max_i N_i < c <= 2^-11 max_i N_i, clamped to [2^-120, 2^120] (row
+// norms whose squares pass FP32's range make the FP32 row terms infinite, and
+// those pairs are re-examined anyway).  Every D2lo <= D^2 <= 4 max N then
+// gives c / D2lo > 2^-14, an FP16 normal, and the scalings by c and 1/c are
+// exact.
 __global__ __launch_bounds__(1024) void k_dcache_scale(const double* __restrict__ nx, int64_t n,
                                                        float* __restrict__ scale) {
   __shared__ double red[16];
@@ -281,7 +283,7 @@ __global__ __launch_bounds__(1024) void k_dcache_scale(const double* __restrict_
     for (int w = 1; w < 16; ++w) m = fmax(m, red[w]);
     int e = -120;
     if (m > 0.0) {
-      frexp(m / 8192.0, &e);   // m / 8192 = f 2^e, f in [0.5, 1)
+      frexp(m * 0x1p-12, &e);   // 2^-12 m = f 2^e, f in [0.5, 1): 2^-12 m < 2^e <= 2^-11 m
       e = e < -120 ? -120 : (e > 120 ? 120 : e);
     }
     scale[0] = ldexpf(1.0f, e);

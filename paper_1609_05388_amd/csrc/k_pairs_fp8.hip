@@ -157,6 +157,7 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
   // two register sets of staging loads (the second for the pipelined image
   // loop of the LOADED kernel)
   u32x4 ga[4], gb[4], ha[4], hb[4];
+  u32x4 pk[8];   // LOADED: the tile's compact cache block
   auto fetch_into = [&](u32x4 (&ra)[4], u32x4 (&rb)[4], int c) __attribute__((always_inline)) {
     if (c < nchx) {
       const size_t off = (size_t)c * FK;
@@ -236,9 +237,8 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
       __syncthreads();
       mma(accY, 1);
     }
-    // the cached block after the image loop, where its accumulators become
-    // live
-    dcache_load(b.gcache, tix, accX, *b.dscale);
+    // the cached block after the image loop
+    dcache_load(b.gcache, tix, pk);
   } else {
     fetch(0);
     stash(0);
@@ -278,12 +278,23 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
 #pragma unroll
       for (int y = 0; y < 2; ++y) {
         const float4 tb = y ? tb1 : tb0;
-        // -2 s_i s_j g + N_i + N_j, or the cached D2lo
-        const float d2 = LOADED ? accX[x][y][v] : fmaf(ta.z * tb.z, accX[x][y][v], ta.x + tb.x);
         const float e2 = fmaf(ta.w * tb.w, accY[x][y][v], ta.y + tb.y);
-        const float q = e2 * __builtin_amdgcn_rcpf(d2);
-        const uint32_t k = pair_key(fmaxf(q, 0.0f), (x * 2 + y) * 16 + v);
-        bool ok = d2 > 0.0f;
+        // q~ = E~^2 / D~^2 with D~^2 = -2 s_i s_j g + N_i + N_j, or c q~ =
+        // E~^2 g from the cached g = c / D2lo (finite: D2lo > 0)
+        float q;
+        bool ok;
+        if constexpr (LOADED) {
+          const float g = dcache_g(pk, x, y, v);
+          q = e2 * g;
+          ok = __float_as_uint(g) < 0x7F800000u;
+        } else {
+          const float d2 = fmaf(ta.z * tb.z, accX[x][y][v], ta.x + tb.x);
+          q = e2 * __builtin_amdgcn_rcpf(d2);
+          ok = d2 > 0.0f;
+        }
+        // negative estimates rank as 0 (integer max on the bits)
+        const int32_t qi = __float_as_int(q);
+        const uint32_t k = pair_key(__int_as_float(qi > 0 ? qi : 0), (x * 2 + y) * 16 + v);
         if (masked) {
           const int cl = wc * 64 + y * 32 + li;
           ok = ok && (I < J || rl < cl) && col0 + cl < n;
@@ -309,8 +320,10 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
   ih = __shfl(ih, lhi, 64); jh = __shfl(jh, lhi, 64);
   il = __shfl(il, llo, 64); jl = __shfl(jl, llo, 64);
   if (lane == 0) {
-    red_v[wave] = whi == 0u ? -1.0f : key_lo_value(whi); red_i[wave] = ih; red_j[wave] = jh;
-    red_v[4 + wave] = wlo == 0xFFFFFFFFu ? 3.0e38f : key_lo_value(wlo); red_i[4 + wave] = il; red_j[4 + wave] = jl;
+    const float sc = LOADED ? 1.0f / *b.dscale : 1.0f;   // exact: a power of two
+    red_v[wave] = whi == 0u ? -1.0f : key_lo_value(whi) * sc; red_i[wave] = ih; red_j[wave] = jh;
+    red_v[4 + wave] = wlo == 0xFFFFFFFFu ? 3.0e38f : key_lo_value(wlo) * sc; red_i[4 + wave] = il;
+    red_j[4 + wave] = jl;
   }
   __syncthreads();
   if (tid == 0) {

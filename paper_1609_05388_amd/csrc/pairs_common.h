@@ -79,52 +79,54 @@ __device__ inline void gcache_load(const float* cache, int64_t tile, f32x16 (&ac
     a[v] = t[0]; a[v + 1] = t[1]; a[v + 2] = t[2]; a[v + 3] = t[3];
   }
 }
-// Compact cache block of a precision-form fit: per tile the 16384 lower
-// bounds D2lo of the pairs' squared distances (from the fill's Gram and its
-// row terms), divided by the fit's power-of-two scale and rounded down to
-// FP16 (32 KB per tile instead of 64), so the screens that load it stream
-// half the bytes.  Thread tid's 64 values sit in 16-byte slots k8 * 256 + tid
-// (k8 = 0..7, 8 halves each), in the order of its accumulators.  A stored
-// value h gives h * scale <= D2lo <= h * scale * (1 + 2^-10) + 2^-24 scale
-// (FP16 keeps 11 significant bits; 2^-24 is its smallest spacing), and
-// D2lo <= D2 <= D2hi.
-__device__ inline uint16_t f16_down_bits(float x) {
-  const _Float16 h = (_Float16)x;   // round to nearest even (infinity beyond 65504)
-  uint16_t b = __builtin_bit_cast(uint16_t, h);
-  if ((float)h > x) {               // step one FP16 value towards -infinity
-    if (b == 0x0000u) b = 0x8001u;
-    else if (b & 0x8000u) b = (uint16_t)(b + 1u);
-    else b = (uint16_t)(b - 1u);
-  }
+// Compact cache block of a precision-form fit.  Per tile and pair, from the
+// fill's D2lo (the FP32 lower bound on D^2 that the epilogue forms from the
+// point Gram and its row terms), the FP16 value
+//   g = c / D2lo rounded up
+// (+infinity when D2lo <= c 2^-16 or the quotient passes 65504, so only for
+// D2lo < c 2^-15), with c the fit's power of two, 2^-12 max N < c <=
+// 2^-11 max N: every D2lo <= D^2 <= 4 max N then gives g > 2^-14, an FP16
+// normal.  A finite g satisfies g >= c / D2lo (so
+// q <= E2hi g / c) and D2lo <= (1 + 2^-10 + 2^-20) c / g (FP16 keeps 11
+// significant bits; the 2^-20 covers the division's rounding and the
+// inflation before the FP16 rounding).  32 KB per tile instead of 64, and the
+// screens' fast pass needs no reciprocal.  Thread tid's 64 values sit in
+// 16-byte slots k8 * 256 + tid (k8 = 0..7): slot k8 holds registers
+// (k8 & 1) * 8 .. + 7 of accumulator block [k8 >> 2][(k8 >> 1) & 1], two per
+// 32-bit word, the lower-numbered register in the low half.
+__device__ inline uint32_t f16_up_bits(float x) {   // x > 0
+  const _Float16 h = (_Float16)x;                    // nearest even (infinity past 65520)
+  uint32_t b = __builtin_bit_cast(uint16_t, h);
+  if ((float)h < x) ++b;                             // the next FP16 value up (0x7BFF + 1 = infinity)
   return b;
 }
-__device__ inline void dcache_store(void* cache, int64_t tile, const f32x16 (&d2)[2][2], float inv_scale) {
+__device__ inline uint32_t dcache_code(float d2lo, float c) {
+  if (!(d2lo > c * 0x1p-16f)) return 0x7C00u;        // +infinity: D2lo small, zero or negative
+  return f16_up_bits((c / d2lo) * (1.0f + 0x1p-22f));
+}
+__device__ inline void dcache_store(void* cache, int64_t tile, const f32x16 (&d2lo)[2][2], float c) {
   u32x4* g = reinterpret_cast<u32x4*>(cache) + tile * 2048 + threadIdx.x;
 #pragma unroll
   for (int k8 = 0; k8 < 8; ++k8) {
-    const f32x16& a = d2[k8 >> 2][(k8 >> 1) & 1];
+    const f32x16& a = d2lo[k8 >> 2][(k8 >> 1) & 1];
     const int v = (k8 & 1) * 8;
     u32x4 t;
 #pragma unroll
-    for (int w = 0; w < 4; ++w)
-      t[w] = (uint32_t)f16_down_bits(a[v + 2 * w] * inv_scale) |
-             ((uint32_t)f16_down_bits(a[v + 2 * w + 1] * inv_scale) << 16);
+    for (int w = 0; w < 4; ++w) t[w] = dcache_code(a[v + 2 * w], c) | (dcache_code(a[v + 2 * w + 1], c) << 16);
     __builtin_nontemporal_store(t, g + k8 * 256);
   }
 }
-__device__ inline void dcache_load(const void* cache, int64_t tile, f32x16 (&d2)[2][2], float scale) {
+// The block's 8 slots into registers, still packed (32 registers).
+__device__ inline void dcache_load(const void* cache, int64_t tile, u32x4 (&pk)[8]) {
   const u32x4* g = reinterpret_cast<const u32x4*>(cache) + tile * 2048 + threadIdx.x;
 #pragma unroll
-  for (int k8 = 0; k8 < 8; ++k8) {
-    const u32x4 t = __builtin_nontemporal_load(g + k8 * 256);
-    f32x16& a = d2[k8 >> 2][(k8 >> 1) & 1];
-    const int v = (k8 & 1) * 8;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      a[v + 2 * w] = (float)__builtin_bit_cast(_Float16, (uint16_t)(t[w] & 0xFFFFu)) * scale;
-      a[v + 2 * w + 1] = (float)__builtin_bit_cast(_Float16, (uint16_t)(t[w] >> 16)) * scale;
-    }
-  }
+  for (int k8 = 0; k8 < 8; ++k8) pk[k8] = __builtin_nontemporal_load(g + k8 * 256);
+}
+// g of accumulator register v of block [x][y], as FP32 (exact).
+__device__ inline float dcache_g(const u32x4 (&pk)[8], int x, int y, int v) {
+  const uint32_t word = pk[x * 4 + y * 2 + (v >> 3)][(v & 7) >> 1];
+  const uint16_t hb = (uint16_t)((v & 1) ? (word >> 16) : (word & 0xFFFFu));
+  return (float)__builtin_bit_cast(_Float16, hb);
 }
 
 struct PairsArgs {
@@ -166,26 +168,36 @@ __device__ inline void pair_bounds(float gx, float gy, const float4& ta, const f
   if (!(d2hi > 0.0f)) { qhi = 1.0f; qlo = 1.0f; }
 }
 
-// Bounds on q for one pair of a compact-cache screen, from L = the cached
-// D2lo rounded down (h * scale), the image Gram entry and the row terms.
-// D^2 <= D2lo + 1.25 (width_i + width_j) (the bound the FP32 epilogue's
-// d2hi also satisfies) and D2lo <= L (1 + 2^-10) + 2^-24 scale, so
-//   D2hi' = max(L, 0) (1 + 2^-9) + 1.25 (1 + 2^-20) w + 2^-23 scale
+// Bounds on q for one pair of a compact-cache screen, from its cached g,
+// the image Gram entry and the row terms (c: the cache's constant, ic = 1/c).
+// D^2 <= D2lo + 1.25 (width_i + width_j) (the bound the FP32 epilogue's d2hi
+// also satisfies) and D2lo <= (1 + 2^-10 + 2^-20) c / g, or D2lo < c 2^-15
+// when g is infinite, so
+//   D2hi' = (1 + 2^-10 + 2^-18) fl(c / g) + 1.25 (1 + 2^-20) w + c 2^-15
 // (w = the two widths' sum), formed with two FMAs, is an upper bound on D^2:
-// the doubled constants absorb the roundings of w and of both FMAs.
-// tail = 2^-23 scale.  q_hi = E2hi / L while L > 1e-30; a pair with a
-// smaller L (identical or nearly identical points) gets the widest bounds
-// and is always re-examined.
-__device__ inline void pair_bounds_compact(float L, float gy, const float4& ta, const float4& tb, float tail,
-                                           float& qhi, float& qlo) {
+// the margins absorb the roundings of the division, of w and of both FMAs.
+// q_hi = (E2hi / c) g while g is finite; an infinite g (identical or nearly
+// identical points) gets the widest upper bound and the pair is re-examined.
+__device__ inline void pair_bounds_compact(float g, float gy, const float4& ta, const float4& tb, float c,
+                                           float ic, float& qhi, float& qlo) {
   const float e2lo = fmaf(-2.0f, gy, ta.z + tb.z);
   const float e2hi = fmaf(-2.0f, gy, ta.w + tb.w);
   const float w = (ta.y - ta.x) + (tb.y - tb.x);
-  const float d2hi = fmaf(fmaxf(L, 0.0f), 0x1.008p+0f, fmaf(w, 0x1.400014p+0f, tail));
-  const float h = fmaxf(e2hi, 0.0f) * __builtin_amdgcn_rcpf(L);
-  const float l = fmaxf(e2lo, 0.0f) * __builtin_amdgcn_rcpf(d2hi);
-  qhi = L > 1e-30f ? h : 3.0e38f;
-  qlo = d2hi > 1e-30f ? l : 0.0f;
+  const float d2hi = fmaf(c / g, 0x1.00404p+0f, fmaf(w, 0x1.400014p+0f, c * 0x1p-15f));
+  qhi = g < INFINITY ? (fmaxf(e2hi, 0.0f) * ic) * g : 3.0e38f;
+  qlo = fmaxf(e2lo, 0.0f) * __builtin_amdgcn_rcpf(d2hi);
+}
+
+// Wave-wide integer minimum (all lanes receive it).  On the bits of FP32
+// values it is the smallest value while all are positive, and a negative
+// value's bits (or -0's) whenever one is present.
+__device__ inline int32_t wave_min_i32(int32_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const int32_t w = __shfl_xor(v, o, 64);
+    v = w < v ? w : v;
+  }
+  return v;
 }
 
 // A tile's point Gram (accumulators in the D layout) turned in place into the
@@ -249,10 +261,15 @@ __device__ inline float key_lo_value(uint32_t k) { return __uint_as_float(k & 0x
 // column l % 32), which is the same for v_mfma_f32_32x32x2f32 and
 // v_mfma_f32_32x32x16_bf16.  MODE 0 writes the tile record (after a
 // block-wide barrier); MODE 1 appends the pairs reaching the thresholds.
-// COMPACT: accX holds the compact cache's L (the point Gram's D2lo rounded
-// down) in place of the point Gram.
-template <int MODE, bool COMPACT = false>
-__device__ __attribute__((always_inline)) inline void tile_epilogue(const f32x16 (&accX)[2][2], const f32x16 (&accY)[2][2],
+// COMPACT: px is the tile's compact cache block (packed FP16 g values, see
+// dcache_load) in place of the point Gram accX.
+template <bool COMPACT, typename PX>
+__device__ __attribute__((always_inline)) inline float point_side(const PX& px, int x, int y, int v) {
+  if constexpr (COMPACT) return dcache_g(px, x, y, v);
+  else return px[x][y][v];
+}
+template <int MODE, bool COMPACT = false, typename PX>
+__device__ __attribute__((always_inline)) inline void tile_epilogue(const PX& accX, const f32x16 (&accY)[2][2],
                                      const float4* termA, const float4* termB, int I, int J,
                                      const PairsArgs& p, float thr_hi, float thr_lo, float (*red_v)[4],
                                      int (*red_i)[4], int (*red_j)[4]) {
@@ -268,7 +285,7 @@ __device__ __attribute__((always_inline)) inline void tile_epilogue(const f32x16
   int code_hi = -1, code_lo = -1, code_c = -1;
   const float stop_hi = p.stop_hi, stop_lo = p.stop_lo;
   const float4 tb0 = termB[wc * 64 + li], tb1 = termB[wc * 64 + 32 + li];
-  const float dsc = COMPACT ? *p.dscale : 0.0f;
+  const float dc = COMPACT ? *p.dscale : 1.0f, idc = 1.0f / dc;   // exact: a power of two
   // The pass over the thread's 64 pairs, compiled once with the edge mask and
   // once without (the mask is uniform per tile: no per-pair branch).
   auto scan = [&](auto maskc) __attribute__((always_inline)) {
@@ -282,8 +299,9 @@ __device__ __attribute__((always_inline)) inline void tile_epilogue(const f32x16
 #pragma unroll
         for (int y = 0; y < 2; ++y) {
           float qhi, qlo;
-          if (COMPACT) pair_bounds_compact(accX[x][y][v], accY[x][y][v], ta, y ? tb1 : tb0, 0x1p-23f * dsc, qhi, qlo);
-          else pair_bounds(accX[x][y][v], accY[x][y][v], ta, y ? tb1 : tb0, qhi, qlo);
+          const float pv = point_side<COMPACT>(accX, x, y, v);
+          if (COMPACT) pair_bounds_compact(pv, accY[x][y][v], ta, y ? tb1 : tb0, dc, idc, qhi, qlo);
+          else pair_bounds(pv, accY[x][y][v], ta, y ? tb1 : tb0, qhi, qlo);
           bool certain = MODE == 0 && (qlo > stop_hi || qhi < stop_lo);
           if (M) {
             const int cl = wc * 64 + y * 32 + li;
@@ -329,14 +347,20 @@ __device__ __attribute__((always_inline)) inline void tile_epilogue(const f32x16
   // with E2hi and D2lo.  A wave whose smallest D2lo or E2hi is within 64
   // widths (so q_lo would lose more than about 3%), holds a pair with
   // D2lo <= 1e-30 (identical or nearly identical points) or a q+ near FP32
-  // overflow takes the per-pair pass above instead.  COMPACT: D2lo <=
-  // L (1 + 2^-10) + 2^-24 scale for the cached L, so the same steps hold with
-  // L in place of D2lo, 1 + 2^-10 + (W_D + 2^-24 scale) / L_min in the
-  // denominator and W_D + 2^-24 scale in the width test.
+  // overflow takes the per-pair pass above instead.
+  // COMPACT: per pair q+ = E2hi g / c (g >= c / D2lo), and since
+  // D2lo <= (1 + 2^-10 + 2^-20) c / g, the same steps give the factor
+  // (1 - W_E / E2hi_min) / (1 + 2^-10 + 2^-19 + W_D g_max / c); the wave
+  // takes the per-pair pass when g_max is infinite or W_D g_max / c >= 1/64.
+  // The keys hold E2hi g (c q+), scaled by 1/c (exactly) once per wave.
+  // The running minima are kept as integers on the values' bits (positive
+  // FP32 values order like their bits, and a negative value's bits, or -0's,
+  // are below every positive one's), which spares the NaN handling of fminf.
   bool fast = false;
   if (MODE == 0) {
     uint32_t khi = 0u, klo = 0xFFFFFFFFu;
-    float dmin = 3.0e38f, emin = 3.0e38f;
+    int32_t dmin = 0x7F7FFFFF, emin = 0x7F7FFFFF;   // FP32 path: smallest D2lo; smallest E2hi
+    uint32_t gmax = 0u;                              // COMPACT: largest g
     auto fscan = [&](auto maskc) __attribute__((always_inline)) {
       constexpr bool M = decltype(maskc)::value;
 #pragma unroll
@@ -348,26 +372,26 @@ __device__ __attribute__((always_inline)) inline void tile_epilogue(const f32x16
 #pragma unroll
           for (int y = 0; y < 2; ++y) {
             const float4 tb = y ? tb1 : tb0;
-            const float d2lo = COMPACT ? accX[x][y][v] : fmaf(-2.0f, accX[x][y][v], ta.x + tb.x);
             const float e2hi = fmaf(-2.0f, accY[x][y][v], ta.w + tb.w);
-            const float q = e2hi * __builtin_amdgcn_rcpf(d2lo);
+            // dv: g (COMPACT) or D2lo
+            const float pv = point_side<COMPACT>(accX, x, y, v);
+            const float dv = COMPACT ? pv : fmaf(-2.0f, pv, ta.x + tb.x);
+            const float q = COMPACT ? e2hi * dv : e2hi * __builtin_amdgcn_rcpf(dv);
             const uint32_t k = pair_key(q, (x * 2 + y) * 16 + v);
+            const int32_t di = __float_as_int(dv), ei = __float_as_int(e2hi);
+            bool valid = true;
             if (M) {
               const int cl = wc * 64 + y * 32 + li;
-              const bool valid = (I < J || rl < cl) && col0 + cl < p.n;
-              khi = valid && k > khi ? k : khi;
-              klo = valid && k < klo ? k : klo;
-              dmin = valid ? fminf(dmin, d2lo) : dmin;
-              emin = valid ? fminf(emin, e2hi) : emin;
-            } else {
-              khi = k > khi ? k : khi;
-              klo = k < klo ? k : klo;
-              dmin = fminf(dmin, d2lo);
-              emin = fminf(emin, e2hi);
+              valid = (I < J || rl < cl) && col0 + cl < p.n;
             }
+            khi = valid && k > khi ? k : khi;
+            klo = valid && k < klo ? k : klo;
+            if (COMPACT) gmax = valid && (uint32_t)di > gmax ? (uint32_t)di : gmax;
+            else dmin = valid && di < dmin ? di : dmin;
+            emin = valid && ei < emin ? ei : emin;
             // pinned per pair, as in the per-pair pass (else the compiler
             // evaluates many pairs first and runs out of registers)
-            asm volatile("" : "+v"(khi), "+v"(klo), "+v"(dmin), "+v"(emin));
+            asm volatile("" : "+v"(khi), "+v"(klo), "+v"(dmin), "+v"(emin), "+v"(gmax));
           }
         }
     };
@@ -378,17 +402,33 @@ __device__ __attribute__((always_inline)) inline void tile_epilogue(const f32x16
     const float wDr = wave_max_f32(ra.y - ra.x), wEr = wave_max_f32(ra.w - ra.z);
     const float wDc = wave_max_f32(cb.y - cb.x), wEc = wave_max_f32(cb.w - cb.z);
     const uint32_t whi = wave_max_u32(khi), wlo = wave_min_u32(klo);
-    const float wd = wave_min_f32(dmin), we = wave_min_f32(emin);
-    const double WD = 1.25 * ((double)wDr + (double)wDc) + (COMPACT ? 0x1p-24 * (double)dsc : 0.0);
-    const double WE = 1.25 * ((double)wEr + (double)wEc);
-    const double rel = COMPACT ? 0x1p-10 : 0.0;
+    const float we = __int_as_float(wave_min_i32(emin));
+    const double WD = 1.25 * ((double)wDr + (double)wDc), WE = 1.25 * ((double)wEr + (double)wEc);
+    // dterm = W_D / D2lo_min, or W_D g_max / c
+    double dterm;
+    bool dok;
+    if constexpr (COMPACT) {
+      const uint32_t gm = wave_max_u32(gmax);
+      dok = gm < 0x7F800000u;
+      dterm = WD * (double)__uint_as_float(gm) * (double)idc;
+    } else {
+      const float wd = __int_as_float(wave_min_i32(dmin));
+      dok = wd > 1e-30f;
+      dterm = WD / (double)wd;
+    }
+    const double rel = COMPACT ? 0x1p-10 + 0x1p-19 : 0.0, sc = (double)idc;
     // a wave without valid pairs (whi = 0, wlo = ~0) has no record to make
     const bool any = wlo != 0xFFFFFFFFu;
-    fast = any && wd > 1e-30f && (double)wd > 64.0 * WD && (double)we > 64.0 * WE && whi < 0x7F000000u;
+    fast = any && dok && dterm * 64.0 < 1.0 && (double)we > 64.0 * WE && whi < 0x7F000000u;
     if (fast) {
-      const float vhi = key_hi_value(whi);
-      const double f = (1.0 - WE / (double)we) / (1.0 + rel + WD / (double)wd);
-      const float vlo = (float)((double)key_lo_value(wlo) * (1.0 - 0x1.0p-20) * f * (1.0 - 1e-7));
+      float vhi = key_hi_value(whi);
+      if (COMPACT) {   // the scaling by 1/c, rounded up
+        const double h = (double)vhi * sc;
+        vhi = (float)h;
+        if ((double)vhi < h) vhi = __uint_as_float(__float_as_uint(vhi) + 1u);
+      }
+      const double f = (1.0 - WE / (double)we) / (1.0 + rel + dterm);
+      const float vlo = (float)((double)key_lo_value(wlo) * sc * (1.0 - 0x1.0p-20) * f * (1.0 - 1e-7));
       // the lanes holding the wave's extreme keys (lowest lane among equal keys)
       const uint64_t bh = __ballot(khi == whi), bl = __ballot(klo == wlo);
       const int lhi = __ffsll((unsigned long long)bh) - 1, llo = __ffsll((unsigned long long)bl) - 1;
@@ -400,8 +440,8 @@ __device__ __attribute__((always_inline)) inline void tile_epilogue(const f32x16
       // early stop: the expansion winner's q >= its q+ x factor, the
       // contraction winner's q <= its q+
       if (p.stop && lane == 0) {
-        const bool c_hi = (double)key_lo_value(whi) * (1.0 - 0x1.0p-20) * f > (double)stop_hi;
-        const bool c_lo = key_hi_value(wlo) < stop_lo;
+        const bool c_hi = (double)key_lo_value(whi) * sc * (1.0 - 0x1.0p-20) * f > (double)stop_hi;
+        const bool c_lo = (double)key_hi_value(wlo) * sc < (double)stop_lo;
         if (c_hi || c_lo) {
           const uint32_t pos = atomicAdd(p.stop, 1u);
           if (pos < 8) p.stop_pairs[pos] = c_hi ? make_int2(ih, jh) : make_int2(il, jl);
