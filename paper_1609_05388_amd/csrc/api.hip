@@ -827,9 +827,12 @@ static const uint32_t kHardCap = 1u << 26;
 // when key buckets tie).
 static const uint32_t kFp8Tiles = 1024;
 
-// The certificate of eq. (3) for points p and images im.  With the FP8 screen
-// the same steps run on the FP8 estimates' top tiles only, and the result is
-// the exact maximum over those tiles (certified = 0, no bound on the rest).
+// Largest eigensolver size (m, the padded covariance order) that a fit's
+// cache fill runs beside: at m = 832 the fill (8 ms) hides beside the PCA
+// (7 -> 10 ms); at m = 4096 the sweeps it overlapped took 76 ms each and the
+// overlap gained nothing.
+static const int64_t kFillBesideMaxM = 1024;
+
 // Point-Gram cache for the certificates of one fit: the points do not change
 // across a fit's certificates, so a fill stores every tile's point side once
 // and the screens read it back instead of recomputing it.  FP32 screens keep
@@ -881,6 +884,9 @@ static float f32_down(double x) {
   return f;
 }
 
+// The certificate of eq. (3) for points p and images im.  With the FP8 screen
+// the same steps run on the FP8 estimates' top tiles only, and the result is
+// the exact maximum over those tiles (certified = 0, no bound on the rest).
 // grow = false: the candidate buffer keeps capacity cap0 (a fixed arena);
 // more candidates than that leave the certificate incomplete.
 static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& im, uint32_t cap0,
@@ -1166,40 +1172,44 @@ static void ensure_streams(Workspace& ws) {
   }
 }
 
-// Point Gram of every tile into the fit's cache, on ws.aux after the work
-// already queued on `after` (at least the centred copies; in a fit with the
-// exact PCA also its covariance); the caller's stream waits for it with
-// ws.ev_out before its first screen.  The points' Gram does not depend on the
-// map, so it overlaps the PCA's eigensolver, which leaves most of the GPU
-// idle.  The fill's kernel time is read later from ws.ev_t0 / ev_t1.
-static void gram_fill_async(Workspace& ws, const Points& p, int screen, float* gcache, hipStream_t after) {
+// Point Gram of every tile into the fit's cache, on ws.aux (CU-masked, to
+// run beside other work) or, with `alone`, on ws.aux2 (all CUs,
+// non-blocking), after the work already queued on `after` (at least the
+// centred copies; in a fit with the exact PCA also its covariance, or the
+// whole PCA); the caller's stream waits for it with ws.ev_out before its
+// first screen.  The points' Gram does not depend on the map, so it can
+// overlap the PCA's eigensolver where that leaves most of the GPU idle.  The
+// fill's kernel time is read later from ws.ev_t0 / ev_t1.
+static void gram_fill_async(Workspace& ws, const Points& p, int screen, float* gcache, hipStream_t after,
+                            bool alone = false) {
   ensure_streams(ws);
+  const hipStream_t q = alone ? ws.aux2 : ws.aux;
   HIPCHK(hipEventRecord(ws.ev_cov, after));
-  HIPCHK(hipStreamWaitEvent(ws.aux, ws.ev_cov, 0));
-  HIPCHK(hipEventRecord(ws.ev_t0, ws.aux));
+  HIPCHK(hipStreamWaitEvent(q, ws.ev_cov, 0));
+  HIPCHK(hipEventRecord(ws.ev_t0, q));
   const int NT = (int)(p.n_pad / kTile);
   const int64_t ntiles = (int64_t)NT * (NT + 1) / 2;
   if (screen == ADAGIO_SCREEN_BF16X3 || screen == ADAGIO_SCREEN_FP8) {
     // the compact D^2 cache, from the BF16 split point Gram: an FP8 fit's
     // screens and its BF16 split certificates share this one
-    HIPCHK(launch_dcache_scale(p.nx, p.n_pad, p.dscale, ws.aux));
+    HIPCHK(launch_dcache_scale(p.nx, p.n_pad, p.dscale, q));
     PairsViewB vb;
     vb.Xb = p.Xb; vb.ldx = (int)p.ldxb;
     vb.Yb = p.Xb; vb.ldy = 0;
     vb.tx = p.txb; vb.ty = p.txb;
     vb.n = (int)p.n; vb.NT = NT; vb.ntiles = ntiles;
     vb.dscale = p.dscale;
-    HIPCHK(launch_pairs_gram_fill_bf16(vb, gcache, ws.aux));
+    HIPCHK(launch_pairs_gram_fill_bf16(vb, gcache, q));
   } else {
     PairsView v;
     v.X = p.Xc; v.ldx = (int)p.ldx;
     v.Y = p.Xc; v.ldy = 0;
     v.tx = p.tx; v.ty = p.tx;
     v.n = (int)p.n; v.NT = NT; v.ntiles = ntiles;
-    HIPCHK(launch_pairs_gram_fill(v, gcache, ws.aux));
+    HIPCHK(launch_pairs_gram_fill(v, gcache, q));
   }
-  HIPCHK(hipEventRecord(ws.ev_t1, ws.aux));
-  HIPCHK(hipEventRecord(ws.ev_out, ws.aux));
+  HIPCHK(hipEventRecord(ws.ev_t1, q));
+  HIPCHK(hipEventRecord(ws.ev_out, q));
 }
 
 template <typename F>
@@ -1492,10 +1502,15 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     p.xgram_split = gcache && screen == ADAGIO_SCREEN_FP8;
     if (gcache && (screen == ADAGIO_SCREEN_BF16X3 || screen == ADAGIO_SCREEN_FP8))
       p.dscale = ensure<float>(ws.dscale, 1);
-    const bool gwait_pca = gcache && family != ADAGIO_MAP_JL && pca == ADAGIO_PCA_EXACT;
+    // The fill runs beside the exact PCA while the eigensolver leaves most of
+    // the GPU idle.  Past kFillBesideMaxM its per-round update (m^2 / 2048
+    // workgroups, bound by HBM) fills the GPU by itself and the fill beside it
+    // only time-slices with it, so the fill follows the PCA there.
+    const bool exact_pca = gcache && family != ADAGIO_MAP_JL && pca == ADAGIO_PCA_EXACT;
+    const bool gwait_pca = exact_pca && round_up(p.dx, 2 * bj_block()) <= kFillBesideMaxM;
     bool gwait = gcache != nullptr;
     // without the exact PCA to run beside, the fill starts at once
-    if (gcache && !gwait_pca) gram_fill_async(ws, p, screen, gcache, st);
+    if (gcache && !exact_pca) gram_fill_async(ws, p, screen, gcache, st);
     Axes ax;                         // the JL-only family needs no PCA
     const bool randomized = pca == ADAGIO_PCA_RANDOMIZED && family != ADAGIO_MAP_JL;
     const int mc = (int)round_up(d, 2 * bj_block());
@@ -1519,6 +1534,8 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
         HIPCHK(hipStreamWaitEvent(st, ws.ev_pca, 0));
       } else {
         ax = principal_axes(ws, p, st);
+        // after the PCA, on all CUs; the first probes' embeddings run beside it
+        if (exact_pca) gram_fill_async(ws, p, screen, gcache, st, true);
       }
     }
     e_pca.end(st);

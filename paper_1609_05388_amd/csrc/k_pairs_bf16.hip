@@ -47,9 +47,8 @@ struct PairsArgsB {
   PairsArgs p;                         // row terms, sizes, outputs (X/Y fields unused)
 };
 
-// The cache of these screens is the compact cache (32 KB per tile): the fill
-// (store_only) turns each tile's point Gram into the pairs' D2lo with the row
-// terms and stores c / D2lo rounded up to FP16 (dcache_code).
+// The cache of these screens is the compact cache (32 KB per tile), written
+// by k_pairs_bf16x3_fill below.
 //
 // LOADED: the point Gram comes from the cache and the kernel runs the image
 // chunks only, with the next two chunks in flight (two register sets of
@@ -107,9 +106,6 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
       J = (int)tp.J;
     }
     const int row0 = I * kTile, col0 = J * kTile;
-    // no tile records: the launch only fills the point-Gram cache
-    // (it still reads the point row terms: the cache holds D2lo)
-    const bool store_only = MODE == 0 && p.recs == nullptr;
     if (tid < kTile) {
       const float2 a = p.tx[row0 + tid], c = p.ty[row0 + tid];
       termA[tid] = make_float4(a.x, a.y, c.x, c.y);
@@ -249,12 +245,6 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
         __syncthreads();
       }
     }
-    if (store_only) {
-      gram_to_d2lo(accX, termA, termB);
-      dcache_store(p.gcache, tix, accX, *p.dscale);
-      return;
-    }
-
     if constexpr (LOADED) tile_epilogue<MODE, true>(pk, accY, termA, termB, I, J, p, thr_hi, thr_lo, red_v, red_i, red_j);
     else tile_epilogue<MODE, false>(accX, accY, termA, termB, I, J, p, thr_hi, thr_lo, red_v, red_i, red_j);
     if (MODE == 0) return;
@@ -262,6 +252,119 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
     if (u >= u_end) return;
     __syncthreads();
   }
+}
+
+// The fill of a fit's compact cache: each tile's BF16 split point Gram,
+// turned into the pairs' D2lo with the point row terms and stored as
+// c / D2lo rounded up to FP16 (dcache_code).  The Gram runs over all the
+// points' chunks (128 at 4096 columns), with the next two chunks in flight
+// (two register sets of staging loads; chunk k sits in LDS buffer k & 1 and
+// register set k & 1).
+__global__ __launch_bounds__(256, 2) void k_pairs_bf16x3_fill(PairsArgsB b) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  unsigned char* As = lds_raw;                          // [2][128][BROW]
+  unsigned char* Bs = lds_raw + 2 * kTile * BROW;       // [2][128][BROW]
+  float4* termA = reinterpret_cast<float4*>(lds_raw + 4 * kTile * BROW);
+  float4* termB = termA + kTile;
+  const PairsArgs p = b.p;
+  const __bf16* const Xg = b.X;
+  const int ldx = b.ldx, nk = b.nchx;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1, li = lane & 31, lh = lane >> 5;
+
+  const uint32_t G = gridDim.x;
+  const int64_t slot = (int64_t)(blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  if (slot >= p.nslots) return;
+  const TilePos tp = slot_tile(slot, p.NT, p.NS);
+  if (tp.I < 0) return;
+  const int I = (int)tp.I, J = (int)tp.J;
+  const int row0 = I * kTile, col0 = J * kTile;
+  if (tid < kTile) termA[tid] = make_float4(p.tx[row0 + tid].x, 0.0f, 0.0f, 0.0f);
+  else termB[tid - kTile] = make_float4(p.tx[col0 + tid - kTile].x, 0.0f, 0.0f, 0.0f);
+
+  f32x16 accX[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) accX[x][y] = (f32x16){0};
+
+  // staging: thread t loads 16-byte segment (t % 8) of rows t / 8 + 32 m
+  const int seg = tid & 7, lr = tid >> 3;
+  const size_t xstride = (size_t)2 * ldx;
+  const __bf16* xa = Xg + (size_t)(row0 + lr) * xstride + seg * 8;
+  const __bf16* xb = Xg + (size_t)(col0 + lr) * xstride + seg * 8;
+  auto fetch_into = [&](u32x4 (&ra)[4], u32x4 (&rb)[4], int c) __attribute__((always_inline)) {
+    const size_t off = (size_t)c * 2 * BK;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      ra[m] = *reinterpret_cast<const u32x4*>(xa + off + (size_t)32 * m * xstride);
+      rb[m] = *reinterpret_cast<const u32x4*>(xb + off + (size_t)32 * m * xstride);
+    }
+  };
+  auto stash_from = [&](const u32x4 (&ra)[4], const u32x4 (&rb)[4], int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      *reinterpret_cast<u32x4*>(As + (size_t)buf * kTile * BROW + (lr + 32 * m) * BROW + seg * 16) = ra[m];
+      *reinterpret_cast<u32x4*>(Bs + (size_t)buf * kTile * BROW + (lr + 32 * m) * BROW + seg * 16) = rb[m];
+    }
+  };
+  // k-step s of a chunk: lanes 0-31 take columns 16 s .. 16 s + 7, lanes
+  // 32-63 columns 16 s + 8 .. 16 s + 15 (8 bf16 = 16 bytes per lane).
+  auto mma = [&](int buf) __attribute__((always_inline)) {
+    const unsigned char* A0 = As + (size_t)buf * kTile * BROW;
+    const unsigned char* B0 = Bs + (size_t)buf * kTile * BROW;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const unsigned char* pa = A0 + (wr * 64 + x * 32 + li) * BROW + s * 32 + lh * 16;
+        const unsigned char* pb = B0 + (wc * 64 + x * 32 + li) * BROW + s * 32 + lh * 16;
+        ah[x] = *reinterpret_cast<const bf16x8*>(pa);
+        al[x] = *reinterpret_cast<const bf16x8*>(pa + 64);
+        bh[x] = *reinterpret_cast<const bf16x8*>(pb);
+        bl[x] = *reinterpret_cast<const bf16x8*>(pb + 64);
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) accX[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[x], bh[y], accX[x][y], 0, 0, 0);
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) accX[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[x], bl[y], accX[x][y], 0, 0, 0);
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) accX[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[x], bh[y], accX[x][y], 0, 0, 0);
+    }
+  };
+
+  u32x4 g0a[4], g0b[4], g1a[4], g1b[4];
+  fetch_into(g0a, g0b, 0);
+  if (nk > 1) fetch_into(g1a, g1b, 1);
+  stash_from(g0a, g0b, 0);
+  __syncthreads();
+  int k = 0;
+  for (; k + 2 < nk; k += 2) {
+    fetch_into(g0a, g0b, k + 2);
+    mma(0);
+    stash_from(g1a, g1b, 1);
+    __syncthreads();
+    if (k + 3 < nk) fetch_into(g1a, g1b, k + 3);
+    mma(1);
+    stash_from(g0a, g0b, 0);
+    __syncthreads();
+  }
+  mma(0);
+  if (k + 1 < nk) {
+    stash_from(g1a, g1b, 1);
+    __syncthreads();
+    mma(1);
+  }
+  gram_to_d2lo(accX, termA, termB);
+  const int64_t tix = (int64_t)I * p.NT - (int64_t)I * (I - 1) / 2 + (J - I);
+  dcache_store(p.gcache, tix, accX, *p.dscale);
 }
 
 // Constant c of a compact cache: the power of two with
@@ -312,6 +415,9 @@ static hipError_t bf16_attrs() {
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pairs_bf16x3<0, true>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBf16);
     if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pairs_bf16x3_fill),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBf16);
+    if (e != hipSuccess) return e;
     attr = true;
   }
   return hipSuccess;
@@ -352,7 +458,7 @@ hipError_t launch_pairs_gram_fill_bf16(const PairsViewB& v, float* gcache, hipSt
   a.Y = v.Xb; a.ldy = 0; a.nchy = 0;
   a.p = PairsArgs{nullptr, 0, 0, nullptr, 0, 0, v.tx, v.tx, v.n, v.NT, v.ntiles, NS, nslots, nullptr,
                   nullptr, nullptr, nullptr, 0u, nullptr, gcache, 1, nullptr, nullptr, 3.0e38f, -1.0f, v.dscale};
-  k_pairs_bf16x3<0, false><<<(unsigned)round_up(nslots, 8), 256, kLdsBf16, st>>>(a);
+  k_pairs_bf16x3_fill<<<(unsigned)round_up(nslots, 8), 256, kLdsBf16, st>>>(a);
   return hipGetLastError();
 }
 
