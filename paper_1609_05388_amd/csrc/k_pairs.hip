@@ -74,9 +74,6 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_f32(PairsArgs p) 
     if (tp.I < 0) return;
     I = (int)tp.I;
     J = (int)tp.J;
-    // early stop: the flag's load overlaps the first chunk's loads and is
-    // shared through LDS at the first barrier, so the exit is uniform
-    if (tid == 0) s_stop = p.stop ? __hip_atomic_load(p.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
   } else {
     u_end = p.cd->n_flagged;
     thr_hi = p.cd->thr_hi;
@@ -93,15 +90,30 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_f32(PairsArgs p) 
     const int row0 = I * PT, col0 = J * PT;
     // no tile records: the launch only fills the point-Gram cache
     const bool store_only = MODE == 0 && p.recs == nullptr;
-
-    if (store_only) {
-    } else if (tid < PT) {
-      const float2 a = p.tx[row0 + tid], b = p.ty[row0 + tid];
-      termA[tid] = make_float4(a.x, a.y, b.x, b.y);
-    } else {
-      const float2 a = p.tx[col0 + tid - PT], b = p.ty[col0 + tid - PT];
-      termB[tid - PT] = make_float4(a.x, a.y, b.x, b.y);
-    }
+    // The tile's first chunk, its row terms and (MODE 0) the early-stop flag
+    // are all requested before any of them is waited for: the first chunk's
+    // loads, then these two, whose LDS stores follow the first stash.
+    // Thread t < 128 holds the terms of row t of the tile's rows, t >= 128
+    // of its columns; the flag is shared through LDS at the first barrier
+    // (a uniform exit).
+    float4 side_t = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    uint32_t side_s = 0u;
+    auto load_side = [&]() __attribute__((always_inline)) {
+      if (!store_only) {
+        const int row = tid < PT ? row0 + tid : col0 + tid - PT;
+        const float2 a = p.tx[row], b = p.ty[row];
+        side_t = make_float4(a.x, a.y, b.x, b.y);
+      }
+      if (MODE == 0 && tid == 0 && p.stop)
+        side_s = __hip_atomic_load(p.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    auto store_side = [&]() __attribute__((always_inline)) {
+      if (!store_only) {
+        if (tid < PT) termA[tid] = side_t;
+        else termB[tid - PT] = side_t;
+      }
+      if (MODE == 0 && tid == 0) s_stop = side_s;
+    };
 
     // ---------------------------------------------------------- Gram phase
     f32x16 accX[2][2], accY[2][2];
@@ -179,8 +191,10 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_f32(PairsArgs p) 
       // is multiplied
       const int nk = p.nchy, cy = p.nchx;
       fetch(cy);
+      load_side();   // before the second chunk: the first barrier waits for these
       if (nk > 1) fetch2(cy + 1);
       stash(0);
+      store_side();
       __syncthreads();
       if (MODE == 0 && s_stop != 0u) return;
       int k = 0;
@@ -207,7 +221,9 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_f32(PairsArgs p) 
       gcache_load(p.gcache, tix, accX);
     } else {
       fetch(0);
+      load_side();
       stash(0);
+      store_side();
       __syncthreads();
       if (MODE == 0 && s_stop != 0u) return;
       for (int c = 0; c < p.nchx; ++c) {

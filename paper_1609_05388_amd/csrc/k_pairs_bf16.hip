@@ -90,8 +90,6 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
     if (tp.I < 0) return;
     I = (int)tp.I;
     J = (int)tp.J;
-    // early stop, shared through LDS at the first barrier (uniform exit)
-    if (tid == 0) s_stop = p.stop ? __hip_atomic_load(p.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
   } else {
     u_end = p.cd->n_flagged;
     thr_hi = p.cd->thr_hi;
@@ -106,13 +104,26 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
       J = (int)tp.J;
     }
     const int row0 = I * kTile, col0 = J * kTile;
-    if (tid < kTile) {
-      const float2 a = p.tx[row0 + tid], c = p.ty[row0 + tid];
-      termA[tid] = make_float4(a.x, a.y, c.x, c.y);
-    } else {
-      const float2 a = p.tx[col0 + tid - kTile], c = p.ty[col0 + tid - kTile];
-      termB[tid - kTile] = make_float4(a.x, a.y, c.x, c.y);
-    }
+    // The tile's first chunks, its row terms and (MODE 0) the early-stop
+    // flag are all requested before any of them is waited for: the first
+    // chunk's loads, then these two, whose LDS stores follow the first stash.
+    // Thread t < 128 holds the terms of row t of the tile's rows, t >= 128
+    // of its columns; the flag is shared through LDS at the first barrier
+    // (a uniform exit).
+    auto load_side = [&](float4& tr, uint32_t& sv) __attribute__((always_inline)) {
+      const int row = tid < kTile ? row0 + tid : col0 + tid - kTile;
+      const float2 a = p.tx[row], c = p.ty[row];
+      tr = make_float4(a.x, a.y, c.x, c.y);
+      sv = MODE == 0 && tid == 0 && p.stop ? __hip_atomic_load(p.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                           : 0u;
+    };
+    auto store_side = [&](const float4& tr, uint32_t sv) __attribute__((always_inline)) {
+      if (tid < kTile) termA[tid] = tr;
+      else termB[tid - kTile] = tr;
+      if (MODE == 0 && tid == 0) s_stop = sv;
+    };
+    float4 side_t;
+    uint32_t side_s;
 
     f32x16 accX[2][2], accY[2][2];
 #pragma unroll
@@ -200,8 +211,10 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
       const int nk = nchy;
       Stage g1;
       fetch_into(g0, nchx);
+      load_side(side_t, side_s);   // before the second chunk: the first barrier waits for these
       if (nk > 1) fetch_into(g1, nchx + 1);
       stash_from(g0, 0);
+      store_side(side_t, side_s);
       __syncthreads();
       if (s_stop != 0u) return;
       int k = 0;
@@ -225,9 +238,11 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
         mma(accY, 1);
       }
     } else {
-      // both Grams (or the point Gram alone, filling the cache)
+      // both Grams
       fetch(0);
+      load_side(side_t, side_s);
       stash(0);
+      store_side(side_t, side_s);
       __syncthreads();
       if (MODE == 0 && s_stop != 0u) return;
       for (int c = 0; c < nchx; ++c) {
@@ -279,8 +294,6 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3_fill(PairsArgsB b) {
   if (tp.I < 0) return;
   const int I = (int)tp.I, J = (int)tp.J;
   const int row0 = I * kTile, col0 = J * kTile;
-  if (tid < kTile) termA[tid] = make_float4(p.tx[row0 + tid].x, 0.0f, 0.0f, 0.0f);
-  else termB[tid - kTile] = make_float4(p.tx[col0 + tid - kTile].x, 0.0f, 0.0f, 0.0f);
 
   f32x16 accX[2][2];
 #pragma unroll
@@ -343,7 +356,13 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3_fill(PairsArgsB b) {
   u32x4 g0a[4], g0b[4], g1a[4], g1b[4];
   fetch_into(g0a, g0b, 0);
   if (nk > 1) fetch_into(g1a, g1b, 1);
+  // the row terms (lo of D^2) after the first chunks' loads, stored after
+  // the first stash: thread t < 128 row t of the tile's rows, t >= 128 of
+  // its columns
+  const float lo = p.tx[tid < kTile ? row0 + tid : col0 + tid - kTile].x;
   stash_from(g0a, g0b, 0);
+  if (tid < kTile) termA[tid] = make_float4(lo, 0.0f, 0.0f, 0.0f);
+  else termB[tid - kTile] = make_float4(lo, 0.0f, 0.0f, 0.0f);
   __syncthreads();
   int k = 0;
   for (; k + 2 < nk; k += 2) {

@@ -138,8 +138,16 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
   if (tp.I < 0) return;
   const int I = (int)tp.I, J = (int)tp.J;
   const int row0 = I * kTile, col0 = J * kTile;
-  if (tid < kTile) termA[tid] = b.terms[row0 + tid];
-  else termB[tid - kTile] = b.terms[col0 + tid - kTile];
+  // the row terms load after the first chunk's loads (both in flight at
+  // once); their LDS stores follow the first stash
+  float4 side_t;
+  auto load_side = [&]() __attribute__((always_inline)) {
+    side_t = b.terms[tid < kTile ? row0 + tid : col0 + tid - kTile];
+  };
+  auto store_side = [&]() __attribute__((always_inline)) {
+    if (tid < kTile) termA[tid] = side_t;
+    else termB[tid - kTile] = side_t;
+  };
 
   f32x16 accX[2][2], accY[2][2];
 #pragma unroll
@@ -217,8 +225,10 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
     // flight, in register set k & 1
     const int nk = nchy;
     fetch(nchx);
+    load_side();
     if (nk > 1) fetch2(nchx + 1);
     stash(0);
+    store_side();
     __syncthreads();
     int k = 0;
     for (; k + 2 < nk; k += 2) {
@@ -241,7 +251,9 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
     dcache_load(b.gcache, tix, pk);
   } else {
     fetch(0);
+    load_side();
     stash(0);
+    store_side();
     __syncthreads();
     for (int c = 0; c < nchx; ++c) {
       const int buf = c & 1;
