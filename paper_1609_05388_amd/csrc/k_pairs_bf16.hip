@@ -11,20 +11,26 @@
 // in place of the FP32 Gram's gamma_K, so the epilogue's bounds stay rigorous
 // and the FP64 rescoring keeps the certificate exact.
 //
-// Operand layout in HBM: per row, per 32-column chunk, 32 hi values then 32
-// lo values (128 bytes), so one chunk of one row is one contiguous 128-byte
-// segment.  LDS rows are 144 bytes (128 + 16 padding: conflict-free
-// ds_read_b128 for 32 and 64 banks).  A 128 x 128 pair tile per workgroup of
-// four waves (64 x 64 each, 2 x 2 MFMA blocks), 32-column chunks double
-// buffered in LDS with the next chunk prefetched into registers.
+// Operand layout in HBM: per row, per 16-column chunk, 16 hi values then 16
+// lo values (64 bytes), so one chunk of one row is one contiguous 64-byte
+// segment.  LDS rows are 80 bytes (64 + 16 padding: rows 20 banks apart,
+// conflict-free ds_read_b128 for 16 lanes of consecutive rows).  A 128 x 128
+// pair tile per workgroup of four waves (64 x 64 each, 2 x 2 MFMA blocks),
+// 16-column chunks (one MFMA k-step) double buffered in LDS with the next
+// chunks prefetched into registers; a workgroup needs 45 KB of LDS, so three
+// fit on a CU.
 #include "common.h"
 #include "kernels.h"
 #include "pairs_common.h"
 
 namespace adg {
 
-constexpr int BK = 32;        // columns per chunk
-constexpr int BROW = 144;     // LDS bytes per row (64 hi + 64 lo bytes + 16 pad)
+constexpr int BK = 16;               // columns per chunk (one MFMA k-step)
+constexpr int KS = BK / 16;          // MFMA k-steps per chunk
+constexpr int BROW = 4 * BK + 16;    // LDS bytes per row: BK hi, BK lo values, 16 bytes of padding
+constexpr int SEGS = BK / 4;         // 16-byte segments per row and chunk
+constexpr int SROWS = 256 / SEGS;    // rows one staging pass covers
+constexpr int SPASS = kTile / SROWS; // staging passes per 128 rows
 
 // Split centred FP32 rows (n_pad x lds) into the chunk-interleaved BF16 hi/lo
 // layout (n_pad rows of ldb * 2 bf16, ldb = columns rounded up to 32).
@@ -53,11 +59,12 @@ struct PairsArgsB {
 // LOADED: the point Gram comes from the cache and the kernel runs the image
 // chunks only, with the next two chunks in flight (two register sets of
 // staging loads; the LDS double buffer holds the chunk being multiplied and
-// the next one), since a 32-column chunk is only 24 MFMAs per wave, far less
-// than a global load's latency; the cached point Gram loads during the last
-// chunks, once no staging loads remain.
+// the next one), since a 16-column chunk is only 12 MFMAs per wave, far less
+// than a global load's latency; the cached block loads during the last
+// chunks, once no staging loads remain.  Three workgroups per CU (154
+// VGPRs).
 template <int MODE, bool LOADED>
-__global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
+__global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_bf16x3(PairsArgsB b) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   unsigned char* As = lds_raw;                          // [2][128][BROW]
   unsigned char* Bs = lds_raw + 2 * kTile * BROW;       // [2][128][BROW]
@@ -135,37 +142,37 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
       }
 
     // staging: thread t loads 16-byte segment (t % 8) of rows t / 8 + 32 m
-    const int seg = tid & 7, lr = tid >> 3;
+    const int seg = tid % SEGS, lr = tid / SEGS;
     const size_t xstride = (size_t)2 * ldx, ystride = (size_t)2 * ldy;  // bf16 per row
     const __bf16* xa = Xg + (size_t)(row0 + lr) * xstride + seg * 8;
     const __bf16* xb = Xg + (size_t)(col0 + lr) * xstride + seg * 8;
     const __bf16* ya = Yg + (size_t)(row0 + lr) * ystride + seg * 8;
     const __bf16* yb = Yg + (size_t)(col0 + lr) * ystride + seg * 8;
     struct Stage {
-      u32x4 a[4], b[4];
+      u32x4 a[SPASS], b[SPASS];
     };
     auto fetch_into = [&](Stage& g, int c) __attribute__((always_inline)) {
       if (c < nchx) {
         const size_t off = (size_t)c * 2 * BK;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          g.a[m] = *reinterpret_cast<const u32x4*>(xa + off + (size_t)32 * m * xstride);
-          g.b[m] = *reinterpret_cast<const u32x4*>(xb + off + (size_t)32 * m * xstride);
+        for (int m = 0; m < SPASS; ++m) {
+          g.a[m] = *reinterpret_cast<const u32x4*>(xa + off + (size_t)SROWS * m * xstride);
+          g.b[m] = *reinterpret_cast<const u32x4*>(xb + off + (size_t)SROWS * m * xstride);
         }
       } else {
         const size_t off = (size_t)(c - nchx) * 2 * BK;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          g.a[m] = *reinterpret_cast<const u32x4*>(ya + off + (size_t)32 * m * ystride);
-          g.b[m] = *reinterpret_cast<const u32x4*>(yb + off + (size_t)32 * m * ystride);
+        for (int m = 0; m < SPASS; ++m) {
+          g.a[m] = *reinterpret_cast<const u32x4*>(ya + off + (size_t)SROWS * m * ystride);
+          g.b[m] = *reinterpret_cast<const u32x4*>(yb + off + (size_t)SROWS * m * ystride);
         }
       }
     };
     auto stash_from = [&](const Stage& g, int buf) __attribute__((always_inline)) {
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        *reinterpret_cast<u32x4*>(As + (size_t)buf * kTile * BROW + (lr + 32 * m) * BROW + seg * 16) = g.a[m];
-        *reinterpret_cast<u32x4*>(Bs + (size_t)buf * kTile * BROW + (lr + 32 * m) * BROW + seg * 16) = g.b[m];
+      for (int m = 0; m < SPASS; ++m) {
+        *reinterpret_cast<u32x4*>(As + (size_t)buf * kTile * BROW + (lr + SROWS * m) * BROW + seg * 16) = g.a[m];
+        *reinterpret_cast<u32x4*>(Bs + (size_t)buf * kTile * BROW + (lr + SROWS * m) * BROW + seg * 16) = g.b[m];
       }
     };
     Stage g0;
@@ -177,16 +184,16 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
       const unsigned char* A0 = As + (size_t)buf * kTile * BROW;
       const unsigned char* B0 = Bs + (size_t)buf * kTile * BROW;
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
+      for (int s = 0; s < KS; ++s) {
         bf16x8 ah[2], al[2], bh[2], bl[2];
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
           const unsigned char* pa = A0 + (wr * 64 + x * 32 + li) * BROW + s * 32 + lh * 16;
           const unsigned char* pb = B0 + (wc * 64 + x * 32 + li) * BROW + s * 32 + lh * 16;
           ah[x] = *reinterpret_cast<const bf16x8*>(pa);
-          al[x] = *reinterpret_cast<const bf16x8*>(pa + 64);
+          al[x] = *reinterpret_cast<const bf16x8*>(pa + 2 * BK);
           bh[x] = *reinterpret_cast<const bf16x8*>(pb);
-          bl[x] = *reinterpret_cast<const bf16x8*>(pb + 64);
+          bl[x] = *reinterpret_cast<const bf16x8*>(pb + 2 * BK);
         }
 #pragma unroll
         for (int x = 0; x < 2; ++x)
@@ -275,7 +282,7 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
 // points' chunks (128 at 4096 columns), with the next two chunks in flight
 // (two register sets of staging loads; chunk k sits in LDS buffer k & 1 and
 // register set k & 1).
-__global__ __launch_bounds__(256, 2) void k_pairs_bf16x3_fill(PairsArgsB b) {
+__global__ __launch_bounds__(256, 3) void k_pairs_bf16x3_fill(PairsArgsB b) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   unsigned char* As = lds_raw;                          // [2][128][BROW]
   unsigned char* Bs = lds_raw + 2 * kTile * BROW;       // [2][128][BROW]
@@ -302,23 +309,23 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3_fill(PairsArgsB b) {
     for (int y = 0; y < 2; ++y) accX[x][y] = (f32x16){0};
 
   // staging: thread t loads 16-byte segment (t % 8) of rows t / 8 + 32 m
-  const int seg = tid & 7, lr = tid >> 3;
+  const int seg = tid % SEGS, lr = tid / SEGS;
   const size_t xstride = (size_t)2 * ldx;
   const __bf16* xa = Xg + (size_t)(row0 + lr) * xstride + seg * 8;
   const __bf16* xb = Xg + (size_t)(col0 + lr) * xstride + seg * 8;
-  auto fetch_into = [&](u32x4 (&ra)[4], u32x4 (&rb)[4], int c) __attribute__((always_inline)) {
+  auto fetch_into = [&](u32x4 (&ra)[SPASS], u32x4 (&rb)[SPASS], int c) __attribute__((always_inline)) {
     const size_t off = (size_t)c * 2 * BK;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      ra[m] = *reinterpret_cast<const u32x4*>(xa + off + (size_t)32 * m * xstride);
-      rb[m] = *reinterpret_cast<const u32x4*>(xb + off + (size_t)32 * m * xstride);
+    for (int m = 0; m < SPASS; ++m) {
+      ra[m] = *reinterpret_cast<const u32x4*>(xa + off + (size_t)SROWS * m * xstride);
+      rb[m] = *reinterpret_cast<const u32x4*>(xb + off + (size_t)SROWS * m * xstride);
     }
   };
-  auto stash_from = [&](const u32x4 (&ra)[4], const u32x4 (&rb)[4], int buf) __attribute__((always_inline)) {
+  auto stash_from = [&](const u32x4 (&ra)[SPASS], const u32x4 (&rb)[SPASS], int buf) __attribute__((always_inline)) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      *reinterpret_cast<u32x4*>(As + (size_t)buf * kTile * BROW + (lr + 32 * m) * BROW + seg * 16) = ra[m];
-      *reinterpret_cast<u32x4*>(Bs + (size_t)buf * kTile * BROW + (lr + 32 * m) * BROW + seg * 16) = rb[m];
+    for (int m = 0; m < SPASS; ++m) {
+      *reinterpret_cast<u32x4*>(As + (size_t)buf * kTile * BROW + (lr + SROWS * m) * BROW + seg * 16) = ra[m];
+      *reinterpret_cast<u32x4*>(Bs + (size_t)buf * kTile * BROW + (lr + SROWS * m) * BROW + seg * 16) = rb[m];
     }
   };
   // k-step s of a chunk: lanes 0-31 take columns 16 s .. 16 s + 7, lanes
@@ -327,16 +334,16 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3_fill(PairsArgsB b) {
     const unsigned char* A0 = As + (size_t)buf * kTile * BROW;
     const unsigned char* B0 = Bs + (size_t)buf * kTile * BROW;
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < KS; ++s) {
       bf16x8 ah[2], al[2], bh[2], bl[2];
 #pragma unroll
       for (int x = 0; x < 2; ++x) {
         const unsigned char* pa = A0 + (wr * 64 + x * 32 + li) * BROW + s * 32 + lh * 16;
         const unsigned char* pb = B0 + (wc * 64 + x * 32 + li) * BROW + s * 32 + lh * 16;
         ah[x] = *reinterpret_cast<const bf16x8*>(pa);
-        al[x] = *reinterpret_cast<const bf16x8*>(pa + 64);
+        al[x] = *reinterpret_cast<const bf16x8*>(pa + 2 * BK);
         bh[x] = *reinterpret_cast<const bf16x8*>(pb);
-        bl[x] = *reinterpret_cast<const bf16x8*>(pb + 64);
+        bl[x] = *reinterpret_cast<const bf16x8*>(pb + 2 * BK);
       }
 #pragma unroll
       for (int x = 0; x < 2; ++x)
@@ -353,7 +360,7 @@ __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3_fill(PairsArgsB b) {
     }
   };
 
-  u32x4 g0a[4], g0b[4], g1a[4], g1b[4];
+  u32x4 g0a[SPASS], g0b[SPASS], g1a[SPASS], g1b[SPASS];
   fetch_into(g0a, g0b, 0);
   if (nk > 1) fetch_into(g1a, g1b, 1);
   // the row terms (lo of D^2) after the first chunks' loads, stored after

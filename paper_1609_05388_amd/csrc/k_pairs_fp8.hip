@@ -16,15 +16,21 @@
 // the result is the exact maximum over the selected tiles, a screened value.
 //
 // Operand layout in HBM: per row, chunks of 64 e4m3 bytes (one MFMA k-step);
-// LDS rows of 144 bytes hold two k-steps (128 bytes) plus 16 bytes padding.
+// LDS rows of 80 bytes hold one chunk plus 16 bytes of padding (rows 20
+// banks apart: conflict-free 16-byte reads for 16 lanes of consecutive
+// rows), so that a workgroup needs 45 KB of LDS and three fit on a CU.
 #include "common.h"
 #include "kernels.h"
 #include "pairs_common.h"
 
 namespace adg {
 
-constexpr int FK = 128;     // columns per chunk (two k-steps of 64)
-constexpr int FROW = 144;   // LDS bytes per row
+constexpr int FK = 64;               // columns per chunk (one MFMA k-step)
+constexpr int FKS = FK / 64;         // MFMA k-steps per chunk
+constexpr int FROW = FK + 16;        // LDS bytes per row (16 bytes of padding)
+constexpr int FSEGS = FK / 16;       // 16-byte segments per row and chunk
+constexpr int FSROWS = 256 / FSEGS;  // rows one staging pass covers
+constexpr int FSPASS = kTile / FSROWS;
 
 // OCP FP8 e4m3 (bias 7, no infinities, 448 the largest finite): round to
 // nearest even of |x| <= 448, returned as its bit pattern.
@@ -107,14 +113,14 @@ struct PairsArgsF {
   const float* dscale;                         // its scale (device)
 };
 
-// LOADED: the pairs' D2lo come from the fit's compact D^2 cache (filled from
+// LOADED: the pairs' c / D2lo come from the fit's compact cache (filled from
 // the BF16 split point Gram, a far better D^2 estimate than the FP8 Gram);
 // the kernel runs the image chunks only, with the next two chunks in flight
-// (two register sets of staging loads; a 128-column chunk is only 8 MFMAs per
-// wave, far less than a global load's latency), and loads the cached block
-// after them.
+// (two register sets of staging loads; a 64-column chunk is only 4 MFMAs per
+// wave, far less than a global load's latency), loads the cached block after
+// them, and runs three workgroups per CU (151 VGPRs).
 template <bool LOADED>
-__global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
+__global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_fp8(PairsArgsF b) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   unsigned char* As = lds_raw;
   unsigned char* Bs = lds_raw + 2 * kTile * FROW;
@@ -157,37 +163,37 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
       accX[x][y] = (f32x16){0};
       accY[x][y] = (f32x16){0};
     }
-  const int seg = tid & 7, lr = tid >> 3;
+  const int seg = tid % FSEGS, lr = tid / FSEGS;
   const unsigned char* xa = Xg + (size_t)(row0 + lr) * ldx + seg * 16;
   const unsigned char* xb = Xg + (size_t)(col0 + lr) * ldx + seg * 16;
   const unsigned char* ya = Yg + (size_t)(row0 + lr) * ldy + seg * 16;
   const unsigned char* yb = Yg + (size_t)(col0 + lr) * ldy + seg * 16;
   // two register sets of staging loads (the second for the pipelined image
   // loop of the LOADED kernel)
-  u32x4 ga[4], gb[4], ha[4], hb[4];
+  u32x4 ga[FSPASS], gb[FSPASS], ha[FSPASS], hb[FSPASS];
   u32x4 pk[8];   // LOADED: the tile's compact cache block
-  auto fetch_into = [&](u32x4 (&ra)[4], u32x4 (&rb)[4], int c) __attribute__((always_inline)) {
+  auto fetch_into = [&](u32x4 (&ra)[FSPASS], u32x4 (&rb)[FSPASS], int c) __attribute__((always_inline)) {
     if (c < nchx) {
       const size_t off = (size_t)c * FK;
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        ra[m] = *reinterpret_cast<const u32x4*>(xa + off + (size_t)32 * m * ldx);
-        rb[m] = *reinterpret_cast<const u32x4*>(xb + off + (size_t)32 * m * ldx);
+      for (int m = 0; m < FSPASS; ++m) {
+        ra[m] = *reinterpret_cast<const u32x4*>(xa + off + (size_t)FSROWS * m * ldx);
+        rb[m] = *reinterpret_cast<const u32x4*>(xb + off + (size_t)FSROWS * m * ldx);
       }
     } else {
       const size_t off = (size_t)(c - nchx) * FK;
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        ra[m] = *reinterpret_cast<const u32x4*>(ya + off + (size_t)32 * m * ldy);
-        rb[m] = *reinterpret_cast<const u32x4*>(yb + off + (size_t)32 * m * ldy);
+      for (int m = 0; m < FSPASS; ++m) {
+        ra[m] = *reinterpret_cast<const u32x4*>(ya + off + (size_t)FSROWS * m * ldy);
+        rb[m] = *reinterpret_cast<const u32x4*>(yb + off + (size_t)FSROWS * m * ldy);
       }
     }
   };
-  auto stash_from = [&](const u32x4 (&ra)[4], const u32x4 (&rb)[4], int buf) __attribute__((always_inline)) {
+  auto stash_from = [&](const u32x4 (&ra)[FSPASS], const u32x4 (&rb)[FSPASS], int buf) __attribute__((always_inline)) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      *reinterpret_cast<u32x4*>(As + (size_t)buf * kTile * FROW + (lr + 32 * m) * FROW + seg * 16) = ra[m];
-      *reinterpret_cast<u32x4*>(Bs + (size_t)buf * kTile * FROW + (lr + 32 * m) * FROW + seg * 16) = rb[m];
+    for (int m = 0; m < FSPASS; ++m) {
+      *reinterpret_cast<u32x4*>(As + (size_t)buf * kTile * FROW + (lr + FSROWS * m) * FROW + seg * 16) = ra[m];
+      *reinterpret_cast<u32x4*>(Bs + (size_t)buf * kTile * FROW + (lr + FSROWS * m) * FROW + seg * 16) = rb[m];
     }
   };
   auto fetch = [&](int c) __attribute__((always_inline)) { fetch_into(ga, gb, c); };
@@ -200,7 +206,7 @@ __global__ __launch_bounds__(256, 2) void k_pairs_fp8(PairsArgsF b) {
     const unsigned char* A0 = As + (size_t)buf * kTile * FROW;
     const unsigned char* B0 = Bs + (size_t)buf * kTile * FROW;
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < FKS; ++s) {
       i32x8 av[2], bv[2];
 #pragma unroll
       for (int x = 0; x < 2; ++x) {
