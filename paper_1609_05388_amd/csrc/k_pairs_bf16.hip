@@ -13,12 +13,12 @@
 //
 // Operand layout in HBM: per row, per 16-column chunk, 16 hi values then 16
 // lo values (64 bytes), so one chunk of one row is one contiguous 64-byte
-// segment.  LDS rows are 80 bytes (64 + 16 padding: rows 20 banks apart,
-// conflict-free ds_read_b128 for 16 lanes of consecutive rows).  A 128 x 128
-// pair tile per workgroup of four waves (64 x 64 each, 2 x 2 MFMA blocks),
-// 16-column chunks (one MFMA k-step) double buffered in LDS with the next
-// chunks prefetched into registers; a workgroup needs 45 KB of LDS, so three
-// fit on a CU.
+// segment.  LDS rows are those 64 bytes, unpadded and XOR-swizzled by
+// 16-byte segment (wide_at), free of bank conflicts for both the staging
+// stores and the operand reads.  A 128 x 128 pair tile per workgroup of four
+// waves (64 x 64 each, 2 x 2 MFMA blocks), 16-column chunks (one MFMA k-step)
+// double buffered in LDS with the next chunks prefetched into registers; a
+// workgroup needs 36 KB of LDS.
 #include "common.h"
 #include "kernels.h"
 #include "pairs_common.h"
@@ -26,11 +26,15 @@
 namespace adg {
 
 constexpr int BK = 16;               // columns per chunk (one MFMA k-step)
-constexpr int KS = BK / 16;          // MFMA k-steps per chunk
-constexpr int BROW = 4 * BK + 16;    // LDS bytes per row: BK hi, BK lo values, 16 bytes of padding
-constexpr int SEGS = BK / 4;         // 16-byte segments per row and chunk
-constexpr int SROWS = 256 / SEGS;    // rows one staging pass covers
+constexpr int SEGS = BK / 4;         // 16-byte segments per row and chunk (hi 0-1, lo 2-3)
+constexpr int SROWS = 256 / SEGS;    // rows one staging pass of 256 threads covers
 constexpr int SPASS = kTile / SROWS; // staging passes per 128 rows
+// LDS rows of one chunk are 64 bytes, unpadded: segment s of row r sits in
+// slot s ^ ((r >> 2) & 3).  Sixteen consecutive rows (the 16-byte operand
+// reads of 16 lanes) then cover all 64 banks, and so do four consecutive rows'
+// four segments (the staging stores of 16 lanes).
+constexpr int WROW = 4 * BK;
+__device__ inline int wide_at(int row, int seg) { return row * WROW + ((seg ^ ((row >> 2) & 3)) << 4); }
 
 // Split centred FP32 rows (n_pad x lds) into the chunk-interleaved BF16 hi/lo
 // layout (n_pad rows of ldb * 2 bf16, ldb = columns rounded up to 32).
@@ -53,22 +57,15 @@ struct PairsArgsB {
   PairsArgs p;                         // row terms, sizes, outputs (X/Y fields unused)
 };
 
-// The cache of these screens is the compact cache (32 KB per tile), written
-// by k_pairs_bf16x3_fill below.
-//
-// LOADED: the point Gram comes from the cache and the kernel runs the image
-// chunks only, with the next two chunks in flight (two register sets of
-// staging loads; the LDS double buffer holds the chunk being multiplied and
-// the next one), since a 16-column chunk is only 12 MFMAs per wave, far less
-// than a global load's latency; the cached block loads during the last
-// chunks, once no staging loads remain.  Three workgroups per CU (154
-// VGPRs).
-template <int MODE, bool LOADED>
-__global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_bf16x3(PairsArgsB b) {
+// The screen with both Grams (no cache).  The screens of a fit with the
+// compact cache are k_pairs_bf16x3_wide below, the cache's fill
+// k_pairs_bf16x3_fill.
+template <int MODE>
+__global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
-  unsigned char* As = lds_raw;                          // [2][128][BROW]
-  unsigned char* Bs = lds_raw + 2 * kTile * BROW;       // [2][128][BROW]
-  float4* termA = reinterpret_cast<float4*>(lds_raw + 4 * kTile * BROW);
+  unsigned char* As = lds_raw;                          // [2][128][WROW]
+  unsigned char* Bs = lds_raw + 2 * kTile * WROW;       // [2][128][WROW]
+  float4* termA = reinterpret_cast<float4*>(lds_raw + 4 * kTile * WROW);
   float4* termB = termA + kTile;
   float (*red_v)[4] = reinterpret_cast<float (*)[4]>(termB + kTile);
   int (*red_i)[4] = reinterpret_cast<int (*)[4]>(reinterpret_cast<float*>(red_v) + 8);
@@ -171,29 +168,27 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_bf16x3(PairsArgsB
     auto stash_from = [&](const Stage& g, int buf) __attribute__((always_inline)) {
 #pragma unroll
       for (int m = 0; m < SPASS; ++m) {
-        *reinterpret_cast<u32x4*>(As + (size_t)buf * kTile * BROW + (lr + SROWS * m) * BROW + seg * 16) = g.a[m];
-        *reinterpret_cast<u32x4*>(Bs + (size_t)buf * kTile * BROW + (lr + SROWS * m) * BROW + seg * 16) = g.b[m];
+        *reinterpret_cast<u32x4*>(As + (size_t)buf * kTile * WROW + wide_at(lr + SROWS * m, seg)) = g.a[m];
+        *reinterpret_cast<u32x4*>(Bs + (size_t)buf * kTile * WROW + wide_at(lr + SROWS * m, seg)) = g.b[m];
       }
     };
     Stage g0;
     auto fetch = [&](int c) __attribute__((always_inline)) { fetch_into(g0, c); };
     auto stash = [&](int buf) __attribute__((always_inline)) { stash_from(g0, buf); };
-    // k-step s of a chunk: lanes 0-31 take columns 16 s .. 16 s + 7, lanes
-    // 32-63 columns 16 s + 8 .. 16 s + 15 (8 bf16 = 16 bytes per lane).
+    // one k-step: lanes 0-31 take columns 0-7 (segment 0: hi, 2: lo), lanes
+    // 32-63 columns 8-15 (segments 1 and 3).
     auto mma = [&](f32x16 (&acc)[2][2], int buf) __attribute__((always_inline)) {
-      const unsigned char* A0 = As + (size_t)buf * kTile * BROW;
-      const unsigned char* B0 = Bs + (size_t)buf * kTile * BROW;
-#pragma unroll
-      for (int s = 0; s < KS; ++s) {
+      const unsigned char* A0 = As + (size_t)buf * kTile * WROW;
+      const unsigned char* B0 = Bs + (size_t)buf * kTile * WROW;
+      {
         bf16x8 ah[2], al[2], bh[2], bl[2];
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
-          const unsigned char* pa = A0 + (wr * 64 + x * 32 + li) * BROW + s * 32 + lh * 16;
-          const unsigned char* pb = B0 + (wc * 64 + x * 32 + li) * BROW + s * 32 + lh * 16;
-          ah[x] = *reinterpret_cast<const bf16x8*>(pa);
-          al[x] = *reinterpret_cast<const bf16x8*>(pa + 2 * BK);
-          bh[x] = *reinterpret_cast<const bf16x8*>(pb);
-          bl[x] = *reinterpret_cast<const bf16x8*>(pb + 2 * BK);
+          const int ra = wr * 64 + x * 32 + li, rb = wc * 64 + x * 32 + li;
+          ah[x] = *reinterpret_cast<const bf16x8*>(A0 + wide_at(ra, lh));
+          al[x] = *reinterpret_cast<const bf16x8*>(A0 + wide_at(ra, 2 + lh));
+          bh[x] = *reinterpret_cast<const bf16x8*>(B0 + wide_at(rb, lh));
+          bl[x] = *reinterpret_cast<const bf16x8*>(B0 + wide_at(rb, 2 + lh));
         }
 #pragma unroll
         for (int x = 0; x < 2; ++x)
@@ -210,42 +205,7 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_bf16x3(PairsArgsB
       }
     };
 
-    const int64_t tix = (int64_t)I * p.NT - (int64_t)I * (I - 1) / 2 + (J - I);
-    u32x4 pk[8];   // LOADED: the tile's compact cache block
-    if (LOADED) {
-      // image chunk k (0 <= k < nk) sits in LDS buffer k & 1 and, while in
-      // flight, in register set k & 1
-      const int nk = nchy;
-      Stage g1;
-      fetch_into(g0, nchx);
-      load_side(side_t, side_s);   // before the second chunk: the first barrier waits for these
-      if (nk > 1) fetch_into(g1, nchx + 1);
-      stash_from(g0, 0);
-      store_side(side_t, side_s);
-      __syncthreads();
-      if (s_stop != 0u) return;
-      int k = 0;
-      for (; k + 2 < nk; k += 2) {
-        fetch_into(g0, nchx + k + 2);
-        mma(accY, 0);
-        stash_from(g1, 1);
-        __syncthreads();
-        if (k + 3 < nk) fetch_into(g1, nchx + k + 3);
-        mma(accY, 1);
-        stash_from(g0, 0);
-        __syncthreads();
-      }
-      // the last one or two chunks: no staging loads left, so the cached
-      // point Gram loads here and lands during their MFMAs
-      dcache_load(p.gcache, tix, pk);
-      mma(accY, 0);
-      if (k + 1 < nk) {
-        stash_from(g1, 1);
-        __syncthreads();
-        mma(accY, 1);
-      }
-    } else {
-      // both Grams
+    {
       fetch(0);
       load_side(side_t, side_s);
       stash(0);
@@ -267,13 +227,152 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_bf16x3(PairsArgsB
         __syncthreads();
       }
     }
-    if constexpr (LOADED) tile_epilogue<MODE, true>(pk, accY, termA, termB, I, J, p, thr_hi, thr_lo, red_v, red_i, red_j);
-    else tile_epilogue<MODE, false>(accX, accY, termA, termB, I, J, p, thr_hi, thr_lo, red_v, red_i, red_j);
+    tile_epilogue<MODE>(accX, accY, termA, termB, I, J, p, thr_hi, thr_lo, red_v, red_i, red_j);
     if (MODE == 0) return;
     u += gridDim.x;
     if (u >= u_end) return;
     __syncthreads();
   }
+}
+
+// The screen of a fit with the compact cache, with wider waves: two waves
+// per 128 x 128 tile, wave w holding columns 64 w .. 64 w + 63 of all 128
+// rows as 4 x 2 blocks of 32 x 32 (the blocks of two 64 x 64 waves of the
+// other kernels, whose epilogue and cache layout it keeps).  Per chunk a
+// wave runs 24 MFMAs between barriers (the four-wave kernel 12) and reads
+// 12 KB of operands from LDS for them (16 KB for two waves' worth); 36 KB of
+// LDS per workgroup.
+
+__global__ __launch_bounds__(128, 2) void k_pairs_bf16x3_wide(PairsArgsB b) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  unsigned char* As = lds_raw;                          // [2][128][WROW]
+  unsigned char* Bs = lds_raw + 2 * kTile * WROW;       // [2][128][WROW]
+  float4* termA = reinterpret_cast<float4*>(lds_raw + 4 * kTile * WROW);
+  float4* termB = termA + kTile;
+  float (*red_v)[4] = reinterpret_cast<float (*)[4]>(termB + kTile);
+  int (*red_i)[4] = reinterpret_cast<int (*)[4]>(reinterpret_cast<float*>(red_v) + 8);
+  int (*red_j)[4] = reinterpret_cast<int (*)[4]>(reinterpret_cast<int*>(red_i) + 8);
+  const PairsArgs p = b.p;
+  const __bf16* const Yg = b.Y;
+  const int ldy = b.ldy, nk = b.nchy;
+  __shared__ uint32_t s_stop;
+  const int tid = threadIdx.x, lane = tid & 63, wc = tid >> 6;
+  const int li = lane & 31, lh = lane >> 5;
+
+  const uint32_t G = gridDim.x;
+  const int64_t slot = (int64_t)(blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  if (slot >= p.nslots) return;
+  const TilePos tp = slot_tile(slot, p.NT, p.NS);
+  if (tp.I < 0) return;
+  const int I = (int)tp.I, J = (int)tp.J;
+  const int row0 = I * kTile, col0 = J * kTile;
+
+  // staging: thread t loads segment t % 4 of rows t / 4 + 32 m (m = 0..3)
+  const int seg = tid & 3, lr = tid >> 2;
+  const size_t ystride = (size_t)2 * ldy;
+  const __bf16* ya = Yg + (size_t)(row0 + lr) * ystride + seg * 8;
+  const __bf16* yb = Yg + (size_t)(col0 + lr) * ystride + seg * 8;
+  auto fetch_into = [&](u32x4 (&ra)[4], u32x4 (&rb)[4], int c) __attribute__((always_inline)) {
+    const size_t off = (size_t)c * 2 * BK;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      ra[m] = *reinterpret_cast<const u32x4*>(ya + off + (size_t)32 * m * ystride);
+      rb[m] = *reinterpret_cast<const u32x4*>(yb + off + (size_t)32 * m * ystride);
+    }
+  };
+  auto stash_from = [&](const u32x4 (&ra)[4], const u32x4 (&rb)[4], int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      *reinterpret_cast<u32x4*>(As + (size_t)buf * kTile * WROW + wide_at(lr + 32 * m, seg)) = ra[m];
+      *reinterpret_cast<u32x4*>(Bs + (size_t)buf * kTile * WROW + wide_at(lr + 32 * m, seg)) = rb[m];
+    }
+  };
+  // one k-step: lanes 0-31 take columns 0-7 (segment 0: hi, 2: lo), lanes
+  // 32-63 columns 8-15 (segments 1 and 3)
+  f32x16 acc[2][2][2];   // [sub][x][y]: rows 64 sub + 32 x, columns 64 wc + 32 y
+  auto mma = [&](int buf) __attribute__((always_inline)) {
+    const unsigned char* A0 = As + (size_t)buf * kTile * WROW;
+    const unsigned char* B0 = Bs + (size_t)buf * kTile * WROW;
+    bf16x8 bh[2], bl[2];
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      const int r = wc * 64 + y * 32 + li;
+      bh[y] = *reinterpret_cast<const bf16x8*>(B0 + wide_at(r, lh));
+      bl[y] = *reinterpret_cast<const bf16x8*>(B0 + wide_at(r, 2 + lh));
+    }
+    // the two 64-row halves one after the other (half the A operands live)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      bf16x8 ah[2], al[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const int r = a * 64 + x * 32 + li;
+        ah[x] = *reinterpret_cast<const bf16x8*>(A0 + wide_at(r, lh));
+        al[x] = *reinterpret_cast<const bf16x8*>(A0 + wide_at(r, 2 + lh));
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[a][x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[x], bh[y], acc[a][x][y], 0, 0, 0);
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[a][x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[x], bl[y], acc[a][x][y], 0, 0, 0);
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[a][x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[x], bh[y], acc[a][x][y], 0, 0, 0);
+    }
+  };
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) acc[a][x][y] = (f32x16){0};
+
+  // the first chunk, then the row terms (thread t: row t of the tile's rows
+  // and of its columns) and the early-stop flag, then the second chunk;
+  // the first barrier waits for all but the second chunk
+  u32x4 g0a[4], g0b[4], g1a[4], g1b[4];
+  fetch_into(g0a, g0b, 0);
+  const float2 ax = p.tx[row0 + tid], ay = p.ty[row0 + tid];
+  const float2 bx = p.tx[col0 + tid], by = p.ty[col0 + tid];
+  const uint32_t sv = tid == 0 && p.stop ? __hip_atomic_load(p.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                         : 0u;
+  if (nk > 1) fetch_into(g1a, g1b, 1);
+  stash_from(g0a, g0b, 0);
+  termA[tid] = make_float4(ax.x, ax.y, ay.x, ay.y);
+  termB[tid] = make_float4(bx.x, bx.y, by.x, by.y);
+  if (tid == 0) s_stop = sv;
+  __syncthreads();
+  if (s_stop != 0u) return;
+  int k = 0;
+  for (; k + 2 < nk; k += 2) {
+    fetch_into(g0a, g0b, k + 2);
+    mma(0);
+    stash_from(g1a, g1b, 1);
+    __syncthreads();
+    if (k + 3 < nk) fetch_into(g1a, g1b, k + 3);
+    mma(1);
+    stash_from(g0a, g0b, 0);
+    __syncthreads();
+  }
+  mma(0);
+  if (k + 1 < nk) {
+    stash_from(g1a, g1b, 1);
+    __syncthreads();
+    mma(1);
+  }
+  // the cache blocks of this wave's two 64 x 64 blocks (the slots of the
+  // four-wave kernels' waves 2 sub + wc), after the loop
+  const int64_t tix = (int64_t)I * p.NT - (int64_t)I * (I - 1) / 2 + (J - I);
+  u32x4 pk0[8], pk1[8];
+  dcache_load(p.gcache, tix, pk0, wc * 64 + lane);
+  dcache_load(p.gcache, tix, pk1, (2 + wc) * 64 + lane);
+  wave_epilogue<0, true>(pk0, acc[0], termA, termB, I, J, p, 0.0f, 0.0f, red_v, red_i, red_j, wc);
+  wave_epilogue<0, true>(pk1, acc[1], termA, termB, I, J, p, 0.0f, 0.0f, red_v, red_i, red_j, 2 + wc);
+  tile_record(I, J, p, red_v, red_i, red_j);
 }
 
 // The fill of a fit's compact cache: each tile's BF16 split point Gram,
@@ -284,9 +383,9 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_bf16x3(PairsArgsB
 // register set k & 1).
 __global__ __launch_bounds__(256, 3) void k_pairs_bf16x3_fill(PairsArgsB b) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
-  unsigned char* As = lds_raw;                          // [2][128][BROW]
-  unsigned char* Bs = lds_raw + 2 * kTile * BROW;       // [2][128][BROW]
-  float4* termA = reinterpret_cast<float4*>(lds_raw + 4 * kTile * BROW);
+  unsigned char* As = lds_raw;                          // [2][128][WROW]
+  unsigned char* Bs = lds_raw + 2 * kTile * WROW;       // [2][128][WROW]
+  float4* termA = reinterpret_cast<float4*>(lds_raw + 4 * kTile * WROW);
   float4* termB = termA + kTile;
   const PairsArgs p = b.p;
   const __bf16* const Xg = b.X;
@@ -324,26 +423,24 @@ __global__ __launch_bounds__(256, 3) void k_pairs_bf16x3_fill(PairsArgsB b) {
   auto stash_from = [&](const u32x4 (&ra)[SPASS], const u32x4 (&rb)[SPASS], int buf) __attribute__((always_inline)) {
 #pragma unroll
     for (int m = 0; m < SPASS; ++m) {
-      *reinterpret_cast<u32x4*>(As + (size_t)buf * kTile * BROW + (lr + SROWS * m) * BROW + seg * 16) = ra[m];
-      *reinterpret_cast<u32x4*>(Bs + (size_t)buf * kTile * BROW + (lr + SROWS * m) * BROW + seg * 16) = rb[m];
+      *reinterpret_cast<u32x4*>(As + (size_t)buf * kTile * WROW + wide_at(lr + SROWS * m, seg)) = ra[m];
+      *reinterpret_cast<u32x4*>(Bs + (size_t)buf * kTile * WROW + wide_at(lr + SROWS * m, seg)) = rb[m];
     }
   };
-  // k-step s of a chunk: lanes 0-31 take columns 16 s .. 16 s + 7, lanes
-  // 32-63 columns 16 s + 8 .. 16 s + 15 (8 bf16 = 16 bytes per lane).
+  // one k-step: lanes 0-31 take columns 0-7 (segment 0: hi, 2: lo), lanes
+  // 32-63 columns 8-15 (segments 1 and 3).
   auto mma = [&](int buf) __attribute__((always_inline)) {
-    const unsigned char* A0 = As + (size_t)buf * kTile * BROW;
-    const unsigned char* B0 = Bs + (size_t)buf * kTile * BROW;
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
+    const unsigned char* A0 = As + (size_t)buf * kTile * WROW;
+    const unsigned char* B0 = Bs + (size_t)buf * kTile * WROW;
+    {
       bf16x8 ah[2], al[2], bh[2], bl[2];
 #pragma unroll
       for (int x = 0; x < 2; ++x) {
-        const unsigned char* pa = A0 + (wr * 64 + x * 32 + li) * BROW + s * 32 + lh * 16;
-        const unsigned char* pb = B0 + (wc * 64 + x * 32 + li) * BROW + s * 32 + lh * 16;
-        ah[x] = *reinterpret_cast<const bf16x8*>(pa);
-        al[x] = *reinterpret_cast<const bf16x8*>(pa + 2 * BK);
-        bh[x] = *reinterpret_cast<const bf16x8*>(pb);
-        bl[x] = *reinterpret_cast<const bf16x8*>(pb + 2 * BK);
+        const int ra = wr * 64 + x * 32 + li, rb = wc * 64 + x * 32 + li;
+        ah[x] = *reinterpret_cast<const bf16x8*>(A0 + wide_at(ra, lh));
+        al[x] = *reinterpret_cast<const bf16x8*>(A0 + wide_at(ra, 2 + lh));
+        bh[x] = *reinterpret_cast<const bf16x8*>(B0 + wide_at(rb, lh));
+        bl[x] = *reinterpret_cast<const bf16x8*>(B0 + wide_at(rb, 2 + lh));
       }
 #pragma unroll
       for (int x = 0; x < 2; ++x)
@@ -419,7 +516,8 @@ __global__ __launch_bounds__(1024) void k_dcache_scale(const double* __restrict_
   }
 }
 
-constexpr size_t kLdsBf16 = 4 * kTile * BROW + 2 * kTile * sizeof(float4) + 3 * 8 * sizeof(float);
+constexpr size_t kLdsBf16 = 4 * kTile * WROW + 2 * kTile * sizeof(float4) + 3 * 8 * sizeof(float);
+constexpr size_t kLdsWide = 4 * kTile * WROW + 2 * kTile * sizeof(float4) + 3 * 8 * sizeof(float);
 
 hipError_t launch_split_bf16(const float* src, int64_t n_pad, int64_t m, int64_t lds, int64_t ldb, __bf16* dst,
                              hipStream_t st) {
@@ -435,11 +533,8 @@ hipError_t launch_dcache_scale(const double* nx, int64_t n, float* scale, hipStr
 static hipError_t bf16_attrs() {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pairs_bf16x3<0, false>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pairs_bf16x3<0>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBf16);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pairs_bf16x3<0, true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBf16);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pairs_bf16x3_fill),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBf16);
@@ -468,8 +563,8 @@ hipError_t launch_pairs_screen_bf16(const PairsViewB& v, TileRec* recs, float* g
   }
   const int64_t G = round_up(nslots, 8);
   // the pipelined image loop needs at least one image chunk
-  if (a.p.gmode == 2 && a.nchy >= 1) k_pairs_bf16x3<0, true><<<(unsigned)G, 256, kLdsBf16, st>>>(a);
-  else k_pairs_bf16x3<0, false><<<(unsigned)G, 256, kLdsBf16, st>>>(a);
+  if (a.p.gmode == 2 && a.nchy >= 1) k_pairs_bf16x3_wide<<<(unsigned)G, 128, kLdsWide, st>>>(a);
+  else k_pairs_bf16x3<0><<<(unsigned)G, 256, kLdsBf16, st>>>(a);
   return hipGetLastError();
 }
 

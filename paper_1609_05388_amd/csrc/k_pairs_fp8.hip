@@ -16,9 +16,9 @@
 // the result is the exact maximum over the selected tiles, a screened value.
 //
 // Operand layout in HBM: per row, chunks of 64 e4m3 bytes (one MFMA k-step);
-// LDS rows of 80 bytes hold one chunk plus 16 bytes of padding (rows 20
-// banks apart: conflict-free 16-byte reads for 16 lanes of consecutive
-// rows), so that a workgroup needs 45 KB of LDS and three fit on a CU.
+// LDS rows hold one chunk (64 bytes, unpadded, XOR-swizzled by 16-byte
+// segment: fp8_at), free of bank conflicts for the staging stores and the
+// operand reads; a workgroup needs 36 KB of LDS.
 #include "common.h"
 #include "kernels.h"
 #include "pairs_common.h"
@@ -26,11 +26,15 @@
 namespace adg {
 
 constexpr int FK = 64;               // columns per chunk (one MFMA k-step)
-constexpr int FKS = FK / 64;         // MFMA k-steps per chunk
-constexpr int FROW = FK + 16;        // LDS bytes per row (16 bytes of padding)
 constexpr int FSEGS = FK / 16;       // 16-byte segments per row and chunk
 constexpr int FSROWS = 256 / FSEGS;  // rows one staging pass covers
 constexpr int FSPASS = kTile / FSROWS;
+// LDS rows of one chunk are 64 bytes, unpadded: segment s of row r sits in
+// slot s ^ ((r >> 2) & 3), so that 16 consecutive rows (16 lanes' operand
+// reads) and four consecutive rows' four segments (16 lanes' staging
+// stores) each cover all 64 banks.
+constexpr int FROW = FK;
+__device__ inline int fp8_at(int row, int seg) { return row * FROW + ((seg ^ ((row >> 2) & 3)) << 4); }
 
 // OCP FP8 e4m3 (bias 7, no infinities, 448 the largest finite): round to
 // nearest even of |x| <= 448, returned as its bit pattern.
@@ -192,28 +196,28 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_fp8(PairsArgsF b)
   auto stash_from = [&](const u32x4 (&ra)[FSPASS], const u32x4 (&rb)[FSPASS], int buf) __attribute__((always_inline)) {
 #pragma unroll
     for (int m = 0; m < FSPASS; ++m) {
-      *reinterpret_cast<u32x4*>(As + (size_t)buf * kTile * FROW + (lr + FSROWS * m) * FROW + seg * 16) = ra[m];
-      *reinterpret_cast<u32x4*>(Bs + (size_t)buf * kTile * FROW + (lr + FSROWS * m) * FROW + seg * 16) = rb[m];
+      *reinterpret_cast<u32x4*>(As + (size_t)buf * kTile * FROW + fp8_at(lr + FSROWS * m, seg)) = ra[m];
+      *reinterpret_cast<u32x4*>(Bs + (size_t)buf * kTile * FROW + fp8_at(lr + FSROWS * m, seg)) = rb[m];
     }
   };
   auto fetch = [&](int c) __attribute__((always_inline)) { fetch_into(ga, gb, c); };
   auto stash = [&](int buf) __attribute__((always_inline)) { stash_from(ga, gb, buf); };
   auto fetch2 = [&](int c) __attribute__((always_inline)) { fetch_into(ha, hb, c); };
   auto stash2 = [&](int buf) __attribute__((always_inline)) { stash_from(ha, hb, buf); };
-  // k-step s: lanes 0-31 take bytes 64 s .. 64 s + 31 of their row, lanes
-  // 32-63 bytes 64 s + 32 .. 64 s + 63 (the same split for both operands).
+  // one k-step: lanes 0-31 take bytes 0-31 of their row (segments 0, 1),
+  // lanes 32-63 bytes 32-63 (segments 2, 3), the same split for both operands.
   auto mma = [&](f32x16 (&acc)[2][2], int buf) __attribute__((always_inline)) {
     const unsigned char* A0 = As + (size_t)buf * kTile * FROW;
     const unsigned char* B0 = Bs + (size_t)buf * kTile * FROW;
-#pragma unroll
-    for (int s = 0; s < FKS; ++s) {
+    {
       i32x8 av[2], bv[2];
 #pragma unroll
       for (int x = 0; x < 2; ++x) {
-        const unsigned char* pa = A0 + (wr * 64 + x * 32 + li) * FROW + s * 64 + lh * 32;
-        const unsigned char* pb = B0 + (wc * 64 + x * 32 + li) * FROW + s * 64 + lh * 32;
-        const u32x4 a0 = *reinterpret_cast<const u32x4*>(pa), a1 = *reinterpret_cast<const u32x4*>(pa + 16);
-        const u32x4 b0 = *reinterpret_cast<const u32x4*>(pb), b1 = *reinterpret_cast<const u32x4*>(pb + 16);
+        const int ra = wr * 64 + x * 32 + li, rb = wc * 64 + x * 32 + li;
+        const u32x4 a0 = *reinterpret_cast<const u32x4*>(A0 + fp8_at(ra, 2 * lh));
+        const u32x4 a1 = *reinterpret_cast<const u32x4*>(A0 + fp8_at(ra, 2 * lh + 1));
+        const u32x4 b0 = *reinterpret_cast<const u32x4*>(B0 + fp8_at(rb, 2 * lh));
+        const u32x4 b1 = *reinterpret_cast<const u32x4*>(B0 + fp8_at(rb, 2 * lh + 1));
         av[x] = (i32x8){(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w, (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
         bv[x] = (i32x8){(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w, (int)b1.x, (int)b1.y, (int)b1.z, (int)b1.w};
       }
@@ -254,7 +258,7 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_fp8(PairsArgsF b)
       mma(accY, 1);
     }
     // the cached block after the image loop
-    dcache_load(b.gcache, tix, pk);
+    dcache_load(b.gcache, tix, pk, threadIdx.x);
   } else {
     fetch(0);
     load_side();

@@ -116,9 +116,10 @@ __device__ inline void dcache_store(void* cache, int64_t tile, const f32x16 (&d2
     __builtin_nontemporal_store(t, g + k8 * 256);
   }
 }
-// The block's 8 slots into registers, still packed (32 registers).
-__device__ inline void dcache_load(const void* cache, int64_t tile, u32x4 (&pk)[8]) {
-  const u32x4* g = reinterpret_cast<const u32x4*>(cache) + tile * 2048 + threadIdx.x;
+// The 8 slots of thread slot_tid of a tile's block into registers, still
+// packed (32 registers).
+__device__ inline void dcache_load(const void* cache, int64_t tile, u32x4 (&pk)[8], int slot_tid) {
+  const u32x4* g = reinterpret_cast<const u32x4*>(cache) + tile * 2048 + slot_tid;
 #pragma unroll
   for (int k8 = 0; k8 < 8; ++k8) pk[k8] = __builtin_nontemporal_load(g + k8 * 256);
 }
@@ -268,12 +269,16 @@ __device__ __attribute__((always_inline)) inline float point_side(const PX& px, 
   if constexpr (COMPACT) return dcache_g(px, x, y, v);
   else return px[x][y][v];
 }
+// The part of one wave's 64 x 64 block: `wave` (0..3) is the block's place
+// in the tile (rows (wave / 2) * 64, columns (wave % 2) * 64); MODE 0 leaves
+// the block's record in red_*[.][wave], MODE 1 appends its pairs.  A kernel
+// whose waves hold two such blocks calls it once per block.
 template <int MODE, bool COMPACT = false, typename PX>
-__device__ __attribute__((always_inline)) inline void tile_epilogue(const PX& accX, const f32x16 (&accY)[2][2],
+__device__ __attribute__((always_inline)) inline void wave_epilogue(const PX& accX, const f32x16 (&accY)[2][2],
                                      const float4* termA, const float4* termB, int I, int J,
                                      const PairsArgs& p, float thr_hi, float thr_lo, float (*red_v)[4],
-                                     int (*red_i)[4], int (*red_j)[4]) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+                                     int (*red_i)[4], int (*red_j)[4], int wave) {
+  const int lane = threadIdx.x & 63;
   const int wr = wave >> 1, wc = wave & 1;
   const int li = lane & 31, lh = lane >> 5;
   const int row0 = I * kTile, col0 = J * kTile;
@@ -480,8 +485,17 @@ __device__ __attribute__((always_inline)) inline void tile_epilogue(const PX& ac
       red_v[1][wave] = best_lo; red_i[1][wave] = il; red_j[1][wave] = jl;
     }
     }
+  }
+}
+
+// MODE 0: the tile record from the four blocks' records, after a block-wide
+// barrier.
+__device__ __attribute__((always_inline)) inline void tile_record(int I, int J, const PairsArgs& p,
+                                                                  float (*red_v)[4], int (*red_i)[4],
+                                                                  int (*red_j)[4]) {
+  {
     __syncthreads();
-    if (tid == 0) {
+    if (threadIdx.x == 0) {
       float vh = red_v[0][0], vl = red_v[1][0];
       int ih0 = red_i[0][0], jh0 = red_j[0][0], il0 = red_i[1][0], jl0 = red_j[1][0];
       for (int w = 1; w < 4; ++w) {
@@ -504,8 +518,17 @@ __device__ __attribute__((always_inline)) inline void tile_epilogue(const PX& ac
       const int64_t t = (int64_t)I * p.NT - (int64_t)I * (I - 1) / 2 + (J - I);
       p.recs[t] = rec;
     }
-    return;
   }
+}
+
+template <int MODE, bool COMPACT = false, typename PX>
+__device__ __attribute__((always_inline)) inline void tile_epilogue(const PX& accX, const f32x16 (&accY)[2][2],
+                                     const float4* termA, const float4* termB, int I, int J,
+                                     const PairsArgs& p, float thr_hi, float thr_lo, float (*red_v)[4],
+                                     int (*red_i)[4], int (*red_j)[4]) {
+  wave_epilogue<MODE, COMPACT>(accX, accY, termA, termB, I, J, p, thr_hi, thr_lo, red_v, red_i, red_j,
+                               (int)(threadIdx.x >> 6));
+  if (MODE == 0) tile_record(I, J, p, red_v, red_i, red_j);
 }
 
 }  // namespace adg
