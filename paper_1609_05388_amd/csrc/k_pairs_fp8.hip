@@ -291,41 +291,48 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_fp8(PairsArgsF b)
   float4 tb0 = termB[wc * 64 + li], tb1 = termB[wc * 64 + 32 + li];
   tb0.z *= -0.5f; tb0.w *= -0.5f;
   tb1.z *= -0.5f; tb1.w *= -0.5f;
+  // the pass over the thread's 64 pairs, compiled once with the edge mask
+  // and once without (the mask is uniform per tile: no per-pair branch)
+  auto scan = [&](auto maskc) __attribute__((always_inline)) {
+    constexpr bool M = decltype(maskc)::value;
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int rl = wr * 64 + x * 32 + (v >> 2) * 8 + lh * 4 + (v & 3);
-      const float4 ta = termA[rl];
+      for (int v = 0; v < 16; ++v) {
+        const int rl = wr * 64 + x * 32 + (v >> 2) * 8 + lh * 4 + (v & 3);
+        const float4 ta = termA[rl];
 #pragma unroll
-      for (int y = 0; y < 2; ++y) {
-        const float4 tb = y ? tb1 : tb0;
-        const float e2 = fmaf(ta.w * tb.w, accY[x][y][v], ta.y + tb.y);
-        // q~ = E~^2 / D~^2 with D~^2 = -2 s_i s_j g + N_i + N_j, or c q~ =
-        // E~^2 g from the cached g = c / D2lo (finite: D2lo > 0)
-        float q;
-        bool ok;
-        if constexpr (LOADED) {
-          const float g = dcache_g(pk, x, y, v);
-          q = e2 * g;
-          ok = __float_as_uint(g) < 0x7F800000u;
-        } else {
-          const float d2 = fmaf(ta.z * tb.z, accX[x][y][v], ta.x + tb.x);
-          q = e2 * __builtin_amdgcn_rcpf(d2);
-          ok = d2 > 0.0f;
+        for (int y = 0; y < 2; ++y) {
+          const float4 tb = y ? tb1 : tb0;
+          const float e2 = fmaf(ta.w * tb.w, accY[x][y][v], ta.y + tb.y);
+          // q~ = E~^2 / D~^2 with D~^2 = -2 s_i s_j g + N_i + N_j, or c q~ =
+          // E~^2 g from the cached g = c / D2lo (finite: D2lo > 0)
+          float q;
+          bool ok;
+          if constexpr (LOADED) {
+            const float g = dcache_g(pk, x, y, v);
+            q = e2 * g;
+            ok = __float_as_uint(g) < 0x7F800000u;
+          } else {
+            const float d2 = fmaf(ta.z * tb.z, accX[x][y][v], ta.x + tb.x);
+            q = e2 * __builtin_amdgcn_rcpf(d2);
+            ok = d2 > 0.0f;
+          }
+          // negative estimates rank as 0 (integer max on the bits)
+          const int32_t qi = __float_as_int(q);
+          const uint32_t k = pair_key(__int_as_float(qi > 0 ? qi : 0), (x * 2 + y) * 16 + v);
+          if (M) {
+            const int cl = wc * 64 + y * 32 + li;
+            ok = ok && (I < J || rl < cl) && col0 + cl < n;
+          }
+          khi = ok && k > khi ? k : khi;
+          klo = ok && k < klo ? k : klo;
+          asm volatile("" : "+v"(khi), "+v"(klo));
         }
-        // negative estimates rank as 0 (integer max on the bits)
-        const int32_t qi = __float_as_int(q);
-        const uint32_t k = pair_key(__int_as_float(qi > 0 ? qi : 0), (x * 2 + y) * 16 + v);
-        if (masked) {
-          const int cl = wc * 64 + y * 32 + li;
-          ok = ok && (I < J || rl < cl) && col0 + cl < n;
-        }
-        khi = ok && k > khi ? k : khi;
-        klo = ok && k < klo ? k : klo;
-        asm volatile("" : "+v"(khi), "+v"(klo));
       }
-    }
+  };
+  if (masked) scan(std::integral_constant<bool, true>{});
+  else scan(std::integral_constant<bool, false>{});
   auto decode = [&](int code, int& gi, int& gj) {
     if (code < 0) { gi = 0x7fffffff; gj = 0x7fffffff; return; }
     const int x = code >> 5, y = (code >> 4) & 1, v = code & 15;
