@@ -269,15 +269,19 @@ int adagio_certify_map(const float* X, int64_t n, int64_t d, const float* Pi, in
  * BF16 split screen; if that fails, certified bisection continues above it,
  * so the returned certificate is always a certificate.  The certificates of
  * the search share a point-Gram cache: the points do not change within a
- * fit, so each 128 x 128 tile's point Gram (64 KB per tile: 7.2 GB at
- * n = 60000) is kept in device memory and the screens read it back and
- * compute only the image Gram; the cache is used when it fits in half of the
- * free device memory, and the certificate is the same either way.  The fit
- * fills it with one Gram-only screen launch on a second, non-blocking stream
- * of default priority while the PCA runs on `stream`; `stream` waits for it
- * before its first screen.  An FP8 fit fills the BF16 split Gram, which its
- * FP8 screens (with unit point scales) and its BF16 split certificates both
- * load.  opts->family = ADAGIO_MAP_PCA or ADAGIO_MAP_JL runs the same search
+ * fit, so each 128 x 128 tile's point side is kept in device memory and the
+ * screens read it back and compute only the image Gram.  FP32 screens keep
+ * the point Gram (64 KB per tile: 7.2 GB at n = 60000); the precision forms
+ * keep, per pair, c / D2lo rounded up to FP16 (D2lo: the rigorous lower bound
+ * on the squared distance that the screens' epilogue forms from the Gram;
+ * c: a power of two from the largest row norm), 32 KB per tile.  The cache
+ * is used when it fits in half of the free device memory, and the
+ * certificate is the same either way.  The fit fills it with one launch on a
+ * second stream of default priority: beside the PCA while the eigensolver
+ * leaves the GPU mostly idle (padded covariance order up to 1024), after it
+ * otherwise; `stream` waits for the fill before its first screen.  An FP8
+ * fit fills the BF16 split cache, which its FP8 screens and its BF16 split
+ * certificates both load.  opts->family = ADAGIO_MAP_PCA or ADAGIO_MAP_JL runs the same search
  * over the PCA-only or JL-only maps of Table 3 (at r = d: V^T, resp. the
  * identity); the learned search is for Algorithm 1's maps only.
  * opts->pca = ADAGIO_PCA_RANDOMIZED takes the principal directions from
