@@ -59,7 +59,7 @@ struct PairsArgsB {
 
 // The screen with both Grams (no cache).  The screens of a fit with the
 // compact cache are k_pairs_bf16x3_wide below, the cache's fill
-// k_pairs_bf16x3_fill.
+// k_pairs_bf16x3_fill_quad.
 template <int MODE>
 __global__ __launch_bounds__(256, 2) void k_pairs_bf16x3(PairsArgsB b) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
@@ -378,116 +378,154 @@ __global__ __launch_bounds__(128, 2) void k_pairs_bf16x3_wide(PairsArgsB b) {
 // The fill of a fit's compact cache: each tile's BF16 split point Gram,
 // turned into the pairs' D2lo with the point row terms and stored as
 // c / D2lo rounded up to FP16 (dcache_code).  The Gram runs over all the
-// points' chunks (128 at 4096 columns), with the next two chunks in flight
-// (two register sets of staging loads; chunk k sits in LDS buffer k & 1 and
-// register set k & 1).
-__global__ __launch_bounds__(256, 3) void k_pairs_bf16x3_fill(PairsArgsB b) {
+// points' chunks with the next two in flight, on 256 x 256 quads of four
+// tiles, one workgroup of eight waves per quad: the four tiles share their
+// two row panels and two column panels, so every chunk staged through LDS
+// feeds twice the MFMA work of a one-tile workgroup, halving the panel
+// traffic from L2 and, for wide rows (a BF16 split row of 4096 coordinates
+// is 16 KB, a panel 2 MB), from HBM.  Wave w holds rows 64 (w & 1) .. + 63 of tile w >> 2 (row) / (w >> 1)
+// & 1 (column) of the quad, all 128 columns, as 2 x 4 blocks: the blocks of
+// two 64 x 64 waves of the one-tile kernels, stored to the same slots.  Rows
+// past the last tile (odd tile counts) are read from the last row and their
+// tiles, like the quad's tile below the diagonal, are not stored.  The
+// launch passes the quad triangle's super-tile rows and slots in p.NS and
+// p.nslots.
+constexpr int QT = 2 * kTile;   // rows of a quad
+__global__ __launch_bounds__(512) void k_pairs_bf16x3_fill_quad(PairsArgsB b) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
-  unsigned char* As = lds_raw;                          // [2][128][WROW]
-  unsigned char* Bs = lds_raw + 2 * kTile * WROW;       // [2][128][WROW]
-  float4* termA = reinterpret_cast<float4*>(lds_raw + 4 * kTile * WROW);
-  float4* termB = termA + kTile;
+  unsigned char* As = lds_raw;                          // [2][256][WROW]
+  unsigned char* Bs = lds_raw + 2 * QT * WROW;          // [2][256][WROW]
+  float* loA = reinterpret_cast<float*>(lds_raw + 4 * QT * WROW);   // lo of D^2 row terms, quad rows
+  float* loB = loA + QT;                                            // and quad columns
   const PairsArgs p = b.p;
   const __bf16* const Xg = b.X;
   const int ldx = b.ldx, nk = b.nchx;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1, li = lane & 31, lh = lane >> 5;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int dI = w >> 2, dJ = (w >> 1) & 1, h = w & 1, li = lane & 31, lh = lane >> 5;
+  const int NQ = (p.NT + 1) / 2, n_pad = p.NT * kTile;
 
   const uint32_t G = gridDim.x;
   const int64_t slot = (int64_t)(blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
   if (slot >= p.nslots) return;
-  const TilePos tp = slot_tile(slot, p.NT, p.NS);
-  if (tp.I < 0) return;
-  const int I = (int)tp.I, J = (int)tp.J;
-  const int row0 = I * kTile, col0 = J * kTile;
+  const TilePos qp = slot_tile(slot, NQ, p.NS);
+  if (qp.I < 0) return;
+  const int row0 = (int)qp.I * QT, col0 = (int)qp.J * QT;
 
-  f32x16 accX[2][2];
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y) accX[x][y] = (f32x16){0};
-
-  // staging: thread t loads 16-byte segment (t % 8) of rows t / 8 + 32 m
-  const int seg = tid % SEGS, lr = tid / SEGS;
+  // staging: thread t loads segment t % 4 of quad rows t / 4 and t / 4 + 128
+  // of the row panels and of the column panels
+  const int seg = tid & 3, lr = tid >> 2;
   const size_t xstride = (size_t)2 * ldx;
-  const __bf16* xa = Xg + (size_t)(row0 + lr) * xstride + seg * 8;
-  const __bf16* xb = Xg + (size_t)(col0 + lr) * xstride + seg * 8;
-  auto fetch_into = [&](u32x4 (&ra)[SPASS], u32x4 (&rb)[SPASS], int c) __attribute__((always_inline)) {
+  auto row_ptr = [&](int r) { return Xg + (size_t)(r < n_pad ? r : n_pad - 1) * xstride + seg * 8; };
+  const __bf16* xa0 = row_ptr(row0 + lr);
+  const __bf16* xa1 = row_ptr(row0 + lr + kTile);
+  const __bf16* xb0 = row_ptr(col0 + lr);
+  const __bf16* xb1 = row_ptr(col0 + lr + kTile);
+  auto fetch_into = [&](u32x4 (&g)[4], int c) __attribute__((always_inline)) {
     const size_t off = (size_t)c * 2 * BK;
-#pragma unroll
-    for (int m = 0; m < SPASS; ++m) {
-      ra[m] = *reinterpret_cast<const u32x4*>(xa + off + (size_t)SROWS * m * xstride);
-      rb[m] = *reinterpret_cast<const u32x4*>(xb + off + (size_t)SROWS * m * xstride);
-    }
+    g[0] = *reinterpret_cast<const u32x4*>(xa0 + off);
+    g[1] = *reinterpret_cast<const u32x4*>(xa1 + off);
+    g[2] = *reinterpret_cast<const u32x4*>(xb0 + off);
+    g[3] = *reinterpret_cast<const u32x4*>(xb1 + off);
   };
-  auto stash_from = [&](const u32x4 (&ra)[SPASS], const u32x4 (&rb)[SPASS], int buf) __attribute__((always_inline)) {
-#pragma unroll
-    for (int m = 0; m < SPASS; ++m) {
-      *reinterpret_cast<u32x4*>(As + (size_t)buf * kTile * WROW + wide_at(lr + SROWS * m, seg)) = ra[m];
-      *reinterpret_cast<u32x4*>(Bs + (size_t)buf * kTile * WROW + wide_at(lr + SROWS * m, seg)) = rb[m];
-    }
+  auto stash_from = [&](const u32x4 (&g)[4], int buf) __attribute__((always_inline)) {
+    unsigned char* A0 = As + (size_t)buf * QT * WROW;
+    unsigned char* B0 = Bs + (size_t)buf * QT * WROW;
+    *reinterpret_cast<u32x4*>(A0 + wide_at(lr, seg)) = g[0];
+    *reinterpret_cast<u32x4*>(A0 + wide_at(lr + kTile, seg)) = g[1];
+    *reinterpret_cast<u32x4*>(B0 + wide_at(lr, seg)) = g[2];
+    *reinterpret_cast<u32x4*>(B0 + wide_at(lr + kTile, seg)) = g[3];
   };
+  // acc[wc][x][y]: rows 128 dI + 64 h + 32 x, columns 128 dJ + 64 wc + 32 y
+  f32x16 acc[2][2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) acc[a][x][y] = (f32x16){0};
   // one k-step: lanes 0-31 take columns 0-7 (segment 0: hi, 2: lo), lanes
-  // 32-63 columns 8-15 (segments 1 and 3).
+  // 32-63 columns 8-15 (segments 1 and 3)
   auto mma = [&](int buf) __attribute__((always_inline)) {
-    const unsigned char* A0 = As + (size_t)buf * kTile * WROW;
-    const unsigned char* B0 = Bs + (size_t)buf * kTile * WROW;
-    {
-      bf16x8 ah[2], al[2], bh[2], bl[2];
+    const unsigned char* A0 = As + (size_t)buf * QT * WROW;
+    const unsigned char* B0 = Bs + (size_t)buf * QT * WROW;
+    bf16x8 ah[2], al[2];
 #pragma unroll
-      for (int x = 0; x < 2; ++x) {
-        const int ra = wr * 64 + x * 32 + li, rb = wc * 64 + x * 32 + li;
-        ah[x] = *reinterpret_cast<const bf16x8*>(A0 + wide_at(ra, lh));
-        al[x] = *reinterpret_cast<const bf16x8*>(A0 + wide_at(ra, 2 + lh));
-        bh[x] = *reinterpret_cast<const bf16x8*>(B0 + wide_at(rb, lh));
-        bl[x] = *reinterpret_cast<const bf16x8*>(B0 + wide_at(rb, 2 + lh));
+    for (int x = 0; x < 2; ++x) {
+      const int r = dI * kTile + h * 64 + x * 32 + li;
+      ah[x] = *reinterpret_cast<const bf16x8*>(A0 + wide_at(r, lh));
+      al[x] = *reinterpret_cast<const bf16x8*>(A0 + wide_at(r, 2 + lh));
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      bf16x8 bh[2], bl[2];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const int r = dJ * kTile + a * 64 + y * 32 + li;
+        bh[y] = *reinterpret_cast<const bf16x8*>(B0 + wide_at(r, lh));
+        bl[y] = *reinterpret_cast<const bf16x8*>(B0 + wide_at(r, 2 + lh));
       }
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) accX[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[x], bh[y], accX[x][y], 0, 0, 0);
+        for (int y = 0; y < 2; ++y) acc[a][x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[x], bh[y], acc[a][x][y], 0, 0, 0);
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) accX[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[x], bl[y], accX[x][y], 0, 0, 0);
+        for (int y = 0; y < 2; ++y) acc[a][x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[x], bl[y], acc[a][x][y], 0, 0, 0);
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) accX[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[x], bh[y], accX[x][y], 0, 0, 0);
+        for (int y = 0; y < 2; ++y) acc[a][x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[x], bh[y], acc[a][x][y], 0, 0, 0);
     }
   };
 
-  u32x4 g0a[SPASS], g0b[SPASS], g1a[SPASS], g1b[SPASS];
-  fetch_into(g0a, g0b, 0);
-  if (nk > 1) fetch_into(g1a, g1b, 1);
-  // the row terms (lo of D^2) after the first chunks' loads, stored after
-  // the first stash: thread t < 128 row t of the tile's rows, t >= 128 of
-  // its columns
-  const float lo = p.tx[tid < kTile ? row0 + tid : col0 + tid - kTile].x;
-  stash_from(g0a, g0b, 0);
-  if (tid < kTile) termA[tid] = make_float4(lo, 0.0f, 0.0f, 0.0f);
-  else termB[tid - kTile] = make_float4(lo, 0.0f, 0.0f, 0.0f);
+  u32x4 g0[4], g1[4];
+  fetch_into(g0, 0);
+  // the lo terms of the quad's 256 rows (threads 0-255) and columns (256-511)
+  const int tr = tid < QT ? row0 + tid : col0 + tid - QT;
+  const float lo = p.tx[tr < n_pad ? tr : n_pad - 1].x;
+  if (nk > 1) fetch_into(g1, 1);
+  stash_from(g0, 0);
+  if (tid < QT) loA[tid] = lo;
+  else loB[tid - QT] = lo;
   __syncthreads();
   int k = 0;
   for (; k + 2 < nk; k += 2) {
-    fetch_into(g0a, g0b, k + 2);
+    fetch_into(g0, k + 2);
     mma(0);
-    stash_from(g1a, g1b, 1);
+    stash_from(g1, 1);
     __syncthreads();
-    if (k + 3 < nk) fetch_into(g1a, g1b, k + 3);
+    if (k + 3 < nk) fetch_into(g1, k + 3);
     mma(1);
-    stash_from(g0a, g0b, 0);
+    stash_from(g0, 0);
     __syncthreads();
   }
   mma(0);
   if (k + 1 < nk) {
-    stash_from(g1a, g1b, 1);
+    stash_from(g1, 1);
     __syncthreads();
     mma(1);
   }
-  gram_to_d2lo(accX, termA, termB);
+
+  const int I = (int)qp.I * 2 + dI, J = (int)qp.J * 2 + dJ;
+  if (I >= p.NT || J >= p.NT || I > J) return;   // uniform per wave
+  const float c = *p.dscale;
   const int64_t tix = (int64_t)I * p.NT - (int64_t)I * (I - 1) / 2 + (J - I);
-  dcache_store(p.gcache, tix, accX, *p.dscale);
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    // D2lo = (lo_i + lo_j) - 2 g for the block of the one-tile kernels' wave
+    // (h, a), then its slots
+    const float b0 = loB[dJ * kTile + a * 64 + li], b1 = loB[dJ * kTile + a * 64 + 32 + li];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const float av = loA[dI * kTile + h * 64 + x * 32 + (v >> 2) * 8 + lh * 4 + (v & 3)];
+        acc[a][x][0][v] = fmaf(-2.0f, acc[a][x][0][v], av + b0);
+        acc[a][x][1][v] = fmaf(-2.0f, acc[a][x][1][v], av + b1);
+      }
+    dcache_store(p.gcache, tix, acc[a], c, (h * 2 + a) * 64 + lane);
+  }
 }
 
 // Constant c of a compact cache: the power of two with
@@ -518,6 +556,7 @@ __global__ __launch_bounds__(1024) void k_dcache_scale(const double* __restrict_
 
 constexpr size_t kLdsBf16 = 4 * kTile * WROW + 2 * kTile * sizeof(float4) + 3 * 8 * sizeof(float);
 constexpr size_t kLdsWide = 4 * kTile * WROW + 2 * kTile * sizeof(float4) + 3 * 8 * sizeof(float);
+constexpr size_t kLdsQuad = 4 * QT * WROW + 2 * QT * sizeof(float);
 
 hipError_t launch_split_bf16(const float* src, int64_t n_pad, int64_t m, int64_t lds, int64_t ldb, __bf16* dst,
                              hipStream_t st) {
@@ -536,8 +575,8 @@ static hipError_t bf16_attrs() {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pairs_bf16x3<0>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBf16);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pairs_bf16x3_fill),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBf16);
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pairs_bf16x3_fill_quad),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsQuad);
     if (e != hipSuccess) return e;
     attr = true;
   }
@@ -579,7 +618,11 @@ hipError_t launch_pairs_gram_fill_bf16(const PairsViewB& v, float* gcache, hipSt
   a.Y = v.Xb; a.ldy = 0; a.nchy = 0;
   a.p = PairsArgs{nullptr, 0, 0, nullptr, 0, 0, v.tx, v.tx, v.n, v.NT, v.ntiles, NS, nslots, nullptr,
                   nullptr, nullptr, nullptr, 0u, nullptr, gcache, 1, nullptr, nullptr, 3.0e38f, -1.0f, v.dscale};
-  k_pairs_bf16x3_fill<<<(unsigned)round_up(nslots, 8), 256, kLdsBf16, st>>>(a);
+  // quads: super-tile rows and slots of the quad triangle
+  const int NQ = (v.NT + 1) / 2, NSq = (NQ + 7) / 8;
+  a.p.NS = NSq;
+  a.p.nslots = (int64_t)NSq * (NSq + 1) / 2 * 64;
+  k_pairs_bf16x3_fill_quad<<<(unsigned)round_up(a.p.nslots, 8), 512, kLdsQuad, st>>>(a);
   return hipGetLastError();
 }
 

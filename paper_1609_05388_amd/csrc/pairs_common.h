@@ -104,8 +104,10 @@ __device__ inline uint32_t dcache_code(float d2lo, float c) {
   if (!(d2lo > c * 0x1p-16f)) return 0x7C00u;        // +infinity: D2lo small, zero or negative
   return f16_up_bits((c / d2lo) * (1.0f + 0x1p-22f));
 }
-__device__ inline void dcache_store(void* cache, int64_t tile, const f32x16 (&d2lo)[2][2], float c) {
-  u32x4* g = reinterpret_cast<u32x4*>(cache) + tile * 2048 + threadIdx.x;
+// The 8 slots of thread slot_tid of a tile's block, from that thread's 64
+// D2lo values (in the order of its accumulators).
+__device__ inline void dcache_store(void* cache, int64_t tile, const f32x16 (&d2lo)[2][2], float c, int slot_tid) {
+  u32x4* g = reinterpret_cast<u32x4*>(cache) + tile * 2048 + slot_tid;
 #pragma unroll
   for (int k8 = 0; k8 < 8; ++k8) {
     const f32x16& a = d2lo[k8 >> 2][(k8 >> 1) & 1];
