@@ -989,9 +989,8 @@ static adagio_cert_t certificate(Workspace& ws, const Points& p, const Images& i
   rescore(p, im, seeds, nullptr, &cd->n_seed, 2, seedv, 1, st);
   HIPCHK(launch_thresholds(seedv, cd, st));
   if (screen == ADAGIO_SCREEN_FP8) {
-    uint32_t* hist = ensure<uint32_t>(ws.hist, 65536);
+    uint32_t* hist = ensure<uint32_t>(ws.hist, kTopkHistWords);
     uint32_t* kthr = ensure<uint32_t>(ws.kthr, 1);
-    HIPCHK(hipMemsetAsync(hist, 0, 65536 * sizeof(uint32_t), st));
     HIPCHK(launch_topk_tiles(recs, v.ntiles, kFp8Tiles, 4 * kFp8Tiles, hist, kthr, list, &cd->n_flagged, st));
   } else {
     HIPCHK(launch_flag_tiles(recs, v.ntiles, cd, list, st));
@@ -1094,11 +1093,10 @@ static uint32_t pool_add(Workspace& ws, const Points& p, hipStream_t st) {
   const int64_t ntiles = NT * (NT + 1) / 2;
   int2* pool = ensure<int2>(ws.pool, kPoolCap);
   uint32_t* pn = static_cast<uint32_t*>(ws.pooln.p);          // [0] pool size, [1] selected tiles
-  uint32_t* hist = ensure<uint32_t>(ws.hist, 65536);
+  uint32_t* hist = ensure<uint32_t>(ws.hist, kTopkHistWords);
   uint32_t* kthr = ensure<uint32_t>(ws.kthr, 1);
   uint32_t* list = ensure<uint32_t>(ws.list, (size_t)ntiles);
   const TileRec* recs = static_cast<const TileRec*>(ws.recs.p);
-  HIPCHK(hipMemsetAsync(hist, 0, 65536 * sizeof(uint32_t), st));
   HIPCHK(hipMemsetAsync(pn + 1, 0, sizeof(uint32_t), st));
   HIPCHK(launch_topk_tiles(recs, ntiles, kPoolTiles, 4 * kPoolTiles, hist, kthr, list, pn + 1, st));
   HIPCHK(launch_pool_gather(recs, list, pn + 1, 4 * kPoolTiles, pool, pn, kPoolCap, st));

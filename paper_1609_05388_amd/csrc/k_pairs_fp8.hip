@@ -385,64 +385,89 @@ __device__ inline uint32_t tile_key(const TileRec& r) {
   return __float_as_uint(fmaxf(u, 0.0f));   // non-negative floats order like their bits
 }
 
-// Histogram of the keys' top 16 bits.  Neighbouring tiles' keys fall in few
-// buckets, so the lanes of a wave that share a bucket add their count with
-// one atomic: the first pending lane's bucket is broadcast, the lanes holding
-// it are counted by a ballot, and they leave the loop.
-__global__ void k_key_hist(const TileRec* __restrict__ recs, int64_t ntiles, uint32_t* __restrict__ hist) {
-  const int lane = threadIdx.x & 63;
-  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * 256) {
-    const uint32_t b = tile_key(recs[t]) >> 16;
-    bool pending = true;
+// The K tiles of largest key are found on the keys' top 16 bits (bucket
+// b = key >> 16) in two histogram passes of 256 buckets each: first over the
+// top byte of b, then, among the tiles whose top byte is the selected one,
+// over its low byte.  Each workgroup counts into LDS and adds its nonzero
+// counters to the global ones.  Neighbouring tiles' keys fall in few buckets,
+// so the lanes of a wave that share a bucket add their count with one LDS
+// atomic: the first pending lane's bucket is broadcast, the lanes holding it
+// are counted by a ballot, and they leave the loop.
+// sel < 0: pass 1 (bucket b >> 8); else pass 2 (tiles with b >> 8 == *sel,
+// bucket b & 255).
+__global__ __launch_bounds__(256) void k_key_hist256(const TileRec* __restrict__ recs, int64_t ntiles,
+                                                     const uint32_t* __restrict__ sel, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[256];
+  const int tid = threadIdx.x, lane = tid & 63;
+  h[tid] = 0;
+  __syncthreads();
+  const int s = sel ? (int)sel[0] : -1;
+  for (int64_t t0 = (int64_t)blockIdx.x * 256; t0 < ntiles; t0 += (int64_t)gridDim.x * 256) {
+    const int64_t t = t0 + tid;
+    int bk = -1;
+    if (t < ntiles) {
+      const uint32_t b = tile_key(recs[t]) >> 16;
+      if (s < 0) bk = (int)(b >> 8);
+      else if ((int)(b >> 8) == s) bk = (int)(b & 255u);
+    }
+    bool pending = bk >= 0;
     for (;;) {
       const uint64_t pend = __ballot(pending);
       if (pend == 0) break;
       const int leader = __ffsll((unsigned long long)pend) - 1;
-      const uint32_t lb = (uint32_t)__shfl((int)b, leader, 64);
-      const uint64_t same = __ballot(pending && b == lb);
-      if (lane == leader) atomicAdd(&hist[lb], (uint32_t)__popcll(same));
-      if (b == lb) pending = false;
+      const int lb = __shfl(bk, leader, 64);
+      const uint64_t same = __ballot(pending && bk == lb);
+      if (lane == leader) atomicAdd(&h[lb], (uint32_t)__popcll(same));
+      if (bk == lb) pending = false;
     }
   }
+  __syncthreads();
+  if (h[tid]) atomicAdd(&hist[tid], h[tid]);
 }
 
-// Largest bucket b such that the tiles in buckets >= b number at least K
-// (bucket 0, all tiles, if fewer); when a tied boundary bucket would take the
-// count above kmax, b + 1 (fewer than K tiles, none of that bucket).
-// out[0] = b.  1024 threads, 64 buckets each: segment sums, their suffix sums
-// (a parallel scan), the boundary segment, then its 64 buckets.
-__global__ __launch_bounds__(1024) void k_key_select(const uint32_t* __restrict__ hist, uint32_t K, uint32_t kmax,
-                                                     uint32_t* __restrict__ out) {
-  __shared__ uint32_t suf[1025];   // suf[g] = tiles in segments >= g; suf[1024] = 0
-  __shared__ int gstar;
+// Pass-1 selection (one workgroup of 256): the largest top byte t whose
+// tiles with top byte >= t number at least K (0 if there are fewer), into
+// out[0], and the count of tiles above it, into out[1].
+__global__ __launch_bounds__(256) void k_key_select_top(const uint32_t* __restrict__ hist, uint32_t K,
+                                                        uint32_t* __restrict__ out) {
+  __shared__ uint32_t suf[257];   // suf[t] = tiles with top byte >= t
   const int t = threadIdx.x;
-  uint32_t s = 0;
-  for (int k = 0; k < 64; ++k) s += hist[t * 64 + k];
-  suf[t] = s;
-  if (t == 0) {
-    suf[1024] = 0;
-    gstar = 0;
-  }
+  suf[t] = hist[t];
+  if (t == 0) suf[256] = 0;
   __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const uint32_t v = suf[t] + (t + o < 1024 ? suf[t + o] : 0u);
+  for (int o = 1; o < 256; o <<= 1) {
+    const uint32_t v = suf[t] + (t + o < 256 ? suf[t + o] : 0u);
     __syncthreads();
     suf[t] = v;
     __syncthreads();
   }
-  // the largest segment g >= 1 whose suffix reaches K (suffixes do not grow with g)
-  if (t >= 1 && suf[t] >= K && suf[t + 1] < K) gstar = t;
-  __syncthreads();
-  if (t != 0) return;
-  const int g = gstar;
-  uint64_t acc = suf[g + 1];
-  int b = g * 64 + 63;
-  for (; b > g * 64; --b) {
-    if (acc + hist[b] >= K) break;
-    acc += hist[b];
+  if (suf[t] >= K && suf[t + 1] < K) {   // exactly one such t, when any
+    out[0] = (uint32_t)t;
+    out[1] = suf[t + 1];
   }
-  if (acc + hist[b] > kmax && b < 65535) ++b;
-  out[0] = (uint32_t)b;
+  if (t == 0 && suf[0] < K) {
+    out[0] = 0;
+    out[1] = suf[1];
+  }
+}
+
+// Pass-2 selection: within the selected top byte, the largest bucket b such
+// that the tiles in buckets >= b number at least K (bucket 0, all tiles, if
+// fewer); when the boundary bucket would take the count above kmax, b + 1
+// (fewer than K tiles, none of that bucket).  thr[0] = b.
+__global__ void k_key_select_low(const uint32_t* __restrict__ hist2, const uint32_t* __restrict__ top,
+                                 uint32_t K, uint32_t kmax, uint32_t* __restrict__ thr) {
+  if (threadIdx.x != 0) return;
+  const uint32_t hb = top[0];
+  uint64_t acc = top[1];
+  int lo = 255;
+  for (; lo > 0; --lo) {
+    if (acc + hist2[lo] >= K) break;
+    acc += hist2[lo];
+  }
+  uint32_t b = (hb << 8) | (uint32_t)lo;
+  if (acc + hist2[lo] > kmax && b < 65535u) ++b;
+  thr[0] = b;
 }
 
 // Tiles whose key bucket is >= the threshold and that hold a pair: their
@@ -505,10 +530,16 @@ hipError_t launch_pairs_screen_fp8(const unsigned char* Xq, int ldx, const unsig
 hipError_t launch_topk_tiles(const TileRec* recs, int64_t ntiles, uint32_t K, uint32_t kmax, uint32_t* hist,
                              uint32_t* thr, uint32_t* list, uint32_t* nsel, hipStream_t st) {
   int64_t g = (ntiles + 255) / 256;
-  if (g > 2048) g = 2048;
+  if (g > 1024) g = 1024;
   if (g < 1) g = 1;
-  k_key_hist<<<(unsigned)g, 256, 0, st>>>(recs, ntiles, hist);
-  k_key_select<<<1, 1024, 0, st>>>(hist, K, kmax, thr);
+  // hist: [0, 256) pass-1 counters, [256, 512) pass-2 counters, [512, 514)
+  // the pass-1 selection
+  hipError_t e = hipMemsetAsync(hist, 0, 512 * sizeof(uint32_t), st);
+  if (e != hipSuccess) return e;
+  k_key_hist256<<<(unsigned)g, 256, 0, st>>>(recs, ntiles, nullptr, hist);
+  k_key_select_top<<<1, 256, 0, st>>>(hist, K, hist + 512);
+  k_key_hist256<<<(unsigned)g, 256, 0, st>>>(recs, ntiles, hist + 512, hist + 256);
+  k_key_select_low<<<1, 64, 0, st>>>(hist + 256, hist + 512, K, kmax, thr);
   k_key_compact<<<(unsigned)g, 256, 0, st>>>(recs, ntiles, thr, list, nsel);
   return hipGetLastError();
 }

@@ -196,8 +196,9 @@ hipError_t launch_pairs_screen_fp8(const unsigned char* Xq, int ldx, const unsig
                                    const float4* terms, int n, int NT, TileRec* recs, float* gcache, int gmode,
                                    const float* dscale, hipStream_t st);
 // Indices of the >= K tiles with the largest estimated distortion appended to
-// list (at most kmax unless a single tied bucket exceeds it; hist: 65536
-// zeroed counters; nsel zeroed, receives the count).
+// list (at most kmax unless a single tied bucket exceeds it; hist: scratch of
+// kTopkHistWords words, cleared here; nsel zeroed, receives the count).
+constexpr size_t kTopkHistWords = 514;
 hipError_t launch_topk_tiles(const TileRec* recs, int64_t ntiles, uint32_t K, uint32_t kmax, uint32_t* hist,
                              uint32_t* thr, uint32_t* list, uint32_t* nsel, hipStream_t st);
 int fp8_chunk();
