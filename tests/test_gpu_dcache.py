@@ -72,3 +72,20 @@ def test_bf16x3_fit_all_points_identical_but_two(gpu_lib):
     a = gpu_lib.fit(Xd, 0.1, gen.JL_SEED)
     b = gpu_lib.fit(Xd, 0.1, gen.JL_SEED, screen="bf16x3")
     same_fit(a, b)
+
+
+@pytest.mark.parametrize("n", [1100, 1300])
+def test_precision_fits_odd_tile_count(gpu_lib, n):
+    """An odd number of 128-row tiles (9 and 11): the cache fill works on
+    quads of 2 x 2 tiles, so its last quad row and column hold one tile and
+    read rows past the cloud (from its last row), which must not reach any
+    stored block."""
+    X = wide_norms(n=n, seed=n)
+    print("precision fits, n = %d" % n, flush=True)
+    Xd = dev(X)
+    a = gpu_lib.fit(Xd, 0.1, gen.JL_SEED)
+    b = gpu_lib.fit(Xd, 0.1, gen.JL_SEED, screen="bf16x3")
+    same_fit(a, b)
+    f = gpu_lib.fit(Xd, 0.1, gen.JL_SEED, screen="fp8")
+    assert f["cert"]["certified"] == 1
+    assert f["r"] == a["r"] and torch.equal(f["Pi"], a["Pi"])
