@@ -71,7 +71,7 @@ struct Workspace {
   DevBuf rpQ, rpY, rpG, rpV, rpLam;
   DevBuf skpart, skG, skK, sklam, skV, skfeat, mlp_pb, mlp_X, mlp_f, mlp_hb, mlp_grad, mlp_loss;
   DevBuf knQ, knD, knNq64, knNd64, knNq32, knNd32, knMax, knKeys, knFb, knCnt, knTau;
-  DevBuf lam1, Vt1, colmap, colminmax, colkeep, xc64, pi64c;
+  DevBuf lam1, Vt1, colmap, colminmax, colkeep, xc64, pi64c, axy;
   DevBuf pool, pooln, wvals, wparts, wcd, wV, wW, stopn, stopp, gfM, gfFail, gfZ, nrm;
   // second stream (non-blocking, default priority) for work that overlaps
   // the caller's stream: the fit's point-Gram fill during its PCA
@@ -460,10 +460,27 @@ static const double* full_covariance(Workspace& ws, const Points& p, int m, hipS
   return p.dx == p.d ? covariance64(ws, p, m, st) : covariance(ws, p, m, st);
 }
 
+// FP64 images of the principal axes that lead a fit's maps: the first s rows
+// of every map the search builds (s = r/2 for Algorithm 1's maps, r for the
+// PCA family) are the same FP32 copies of the rows of Vt, so their images
+// (X - mu) Vt_s^T are computed once, for the largest s asked so far, and each
+// probe's FP64 product covers only its other rows.  The k_dgemm result of an
+// entry depends only on its row of X and its row of the map (the same k
+// order at any tile position), so the images are the ones a whole product
+// would give, bit for bit.  Valid while the axes stay; reset when they change
+// (the randomized PCA's larger blocks).
+struct AxisImages {
+  double* Y = nullptr;   // n x cap, row-major; columns [0, s) hold images
+  int64_t cap = 0, s = 0;
+};
+constexpr size_t kAxisImagesMaxBytes = (size_t)16 << 30;
+
 // Y64 = (X - mu) Pi^T in FP64 over the non-constant columns (constant ones
 // centre to exact zeros), a k_dgemm product of the FP64 centred rows and the
-// FP64 values of the FP32 map.  Y64: n x r row-major.
-static void embed64(Workspace& ws, const Points& p, const float* Pi, int64_t r, double* Y64, hipStream_t st) {
+// FP64 values of the FP32 map.  Y64: n x r row-major.  With ai, the first
+// `lead` rows of Pi are the axes behind ai and their images come from it.
+static void embed64(Workspace& ws, const Points& p, const float* Pi, int64_t r, double* Y64, hipStream_t st,
+                    AxisImages* ai = nullptr, int64_t lead = 0) {
   if (p.dx == 0) {
     HIPCHK(hipMemsetAsync(Y64, 0, sizeof(double) * (size_t)(p.n * r), st));
     return;
@@ -472,7 +489,16 @@ static void embed64(Workspace& ws, const Points& p, const float* Pi, int64_t r, 
   double* P64 = ensure<double>(ws.pi64c, (size_t)(r * p.dx));
   HIPCHK(launch_cols64(Pi, r, p.d, p.colmap, p.dx, P64, st));
   // Y64[i][a] = sum_c xc[i][c] P64[a][c]  (P64: r x dx row-major)
-  HIPCHK(launch_dgemm_nt(xc, p.dx, P64, p.dx, p.n, r, p.dx, Y64, r, st));
+  int64_t s = 0;
+  if (ai && ai->Y) {
+    s = std::min(std::min(lead, r), ai->cap);
+    if (s > ai->s) {   // the axes' images [ai->s, s) join the kept ones
+      HIPCHK(launch_dgemm_nt(xc, p.dx, P64 + ai->s * p.dx, p.dx, p.n, s - ai->s, p.dx, ai->Y + ai->s, ai->cap, st));
+      ai->s = s;
+    }
+    HIPCHK(launch_copy_block64(ai->Y, ai->cap, Y64, r, p.n, s, st));
+  }
+  if (r > s) HIPCHK(launch_dgemm_nt(xc, p.dx, P64 + s * p.dx, p.dx, p.n, r - s, p.dx, Y64 + s, r, st));
 }
 
 // Randomized PCA (the paper's Sec. 4.5 variant, after Halko, Martinsson &
@@ -718,11 +744,12 @@ static double* gram_factor_images(Workspace& ws, const Points& p, int64_t r, hip
 // Images of the linear map Pi in FP64, centred: Y64 = (X - mu) Pi^T (the
 // re-evaluation source), and the screen images: Y64 itself, or Z from the
 // Gram factor when Pi has at least d' + 32 rows.
-static Images images_of_map(Workspace& ws, const Points& p, const float* Pi, int64_t r, hipStream_t st) {
+static Images images_of_map(Workspace& ws, const Points& p, const float* Pi, int64_t r, hipStream_t st,
+                            AxisImages* ai = nullptr, int64_t lead = 0) {
   Images im;
   im.r = r;
   double* Y64 = ensure<double>(ws.Y64, (size_t)(p.n * r));
-  embed64(ws, p, Pi, r, Y64, st);
+  embed64(ws, p, Pi, r, Y64, st, ai, lead);
   // FP64 embedding error: |E_64^2 - E^2| <= 4.02 gamma_{d'+1} ||Pi'||_F^2 (N_i + N_j)
   // over the d' non-constant coordinates (and ||L||_F^2 = trace(M) <=
   // ||Pi'||_F^2 for the factor's images); ||Pi'||_F^2 from the FP64 values of
@@ -1545,6 +1572,16 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
       }
     }
     e_pca.end(st);
+    // The images of the leading axes, kept across the probes (none for the
+    // JL-only family, or past the memory budget).
+    AxisImages axim;
+    axim.cap = family == ADAGIO_MAP_PCA ? d : family == ADAGIO_MAP_ADAGIO ? d / 2 : 0;
+    if (axim.cap > 0 && p.dx > 0 && (size_t)(p.n * axim.cap) * sizeof(double) <= kAxisImagesMaxBytes)
+      axim.Y = ensure<double>(ws.axy, (size_t)(p.n * axim.cap));
+    // rows of the map at r that are axes
+    auto lead_axes = [&](int64_t r) -> int64_t {
+      return family == ADAGIO_MAP_PCA ? r : family == ADAGIO_MAP_JL ? 0 : (r == d ? d : r / 2);
+    };
     // Randomized PCA: directions for the largest s needed so far plus 10.
     const int64_t kOversample = 10;
     int64_t ell_cur = 0;
@@ -1554,6 +1591,7 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
       if (sn == 0 || ell_cur == d || sn + kOversample <= ell_cur) return;
       ell_cur = std::min<int64_t>(d, sn + kOversample);
       randomized_axes(ws, Cov, mc, d, ell_cur, pca_iters, seed, ax.lam, ax.Vt, st);
+      axim.s = 0;   // new axes: their images are not the kept ones
     };
     e_search.begin(st);
     float* Pi = ensure<float>(ws.Pi, (size_t)(d * d));
@@ -1587,7 +1625,7 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
           return false;
         }
       }
-      Images im = images_of_map(ws, p, Pi, r, st);
+      Images im = images_of_map(ws, p, Pi, r, st, &axim, lead_axes(r));
       // the search's own screens, and in an FP8 fit its BF16 split
       // certificates, load the fit's point-Gram cache
       const int gmode = gcache && (scr == screen || (screen == ADAGIO_SCREEN_FP8 && scr == ADAGIO_SCREEN_BF16X3)) ? 2 : 0;
@@ -1662,7 +1700,7 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     if (!have_hi) {  // hi == d: no reduction (the full eigenbasis, or the identity)
       need_axes(d);
       build_family_map(ws, family, ax.Vt, d, d, seed, Pi_out, st);
-      Images im = images_of_map(ws, p, Pi_out, d, st);
+      Images im = images_of_map(ws, p, Pi_out, d, st, &axim, lead_axes(d));
       cert_hi = certificate(ws, p, im, cap0, st, &tm, rig);
       ++ncert;
     }

@@ -205,6 +205,14 @@ __global__ void k_sumsq_part(const double* __restrict__ a, int64_t count, double
   }
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
+// dst[i * ldd + c] = src[i * lds + c] for rows i, columns c < cols.
+__global__ __launch_bounds__(256) void k_copy_block64(const double* __restrict__ src, int64_t lds,
+                                                      double* __restrict__ dst, int64_t ldd, int64_t rows,
+                                                      int64_t cols) {
+  for (int64_t i = blockIdx.x; i < rows; i += gridDim.x)
+    for (int64_t c = threadIdx.x; c < cols; c += 256) dst[i * ldd + c] = src[i * lds + c];
+}
+
 __global__ void k_sum_parts(const double* __restrict__ part, int nparts, double* __restrict__ out) {
   if (threadIdx.x != 0) return;
   double s = 0.0;
@@ -241,6 +249,14 @@ hipError_t launch_sumsq(const double* a, int64_t count, double* part, int nparts
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_sum_parts<<<1, 64, 0, st>>>(part, nparts, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_block64(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
+                               int64_t cols, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const int64_t g = rows < 8192 ? rows : 8192;
+  k_copy_block64<<<(unsigned)g, 256, 0, st>>>(src, lds, dst, ldd, rows, cols);
   return hipGetLastError();
 }
 

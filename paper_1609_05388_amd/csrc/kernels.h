@@ -60,6 +60,9 @@ hipError_t launch_dgemm_tn(const double* A, int64_t lda, const double* B, int64_
 hipError_t launch_dgemm_syrk_upper(const double* A, int64_t lda, int64_t M, int64_t K, int nsplit, double* part,
                                    hipStream_t st);
 int dgemm_tile();
+// dst[i * ldd + c] = src[i * lds + c] for i < rows, c < cols (FP64).
+hipError_t launch_copy_block64(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
+                               int64_t cols, hipStream_t st);
 // *out = sum of a[e]^2 (FP64), through nparts block partials in part.
 hipError_t launch_sumsq(const double* a, int64_t count, double* part, int nparts, double* out, hipStream_t st);
 
