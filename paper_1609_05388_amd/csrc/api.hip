@@ -1578,6 +1578,8 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     axim.cap = family == ADAGIO_MAP_PCA ? d : family == ADAGIO_MAP_ADAGIO ? d / 2 : 0;
     if (axim.cap > 0 && p.dx > 0 && (size_t)(p.n * axim.cap) * sizeof(double) <= kAxisImagesMaxBytes)
       axim.Y = ensure<double>(ws.axy, (size_t)(p.n * axim.cap));
+    Images im_last;      // the images of the map at im_r, the last one embedded
+    int64_t im_r = -1;
     // rows of the map at r that are axes
     auto lead_axes = [&](int64_t r) -> int64_t {
       return family == ADAGIO_MAP_PCA ? r : family == ADAGIO_MAP_JL ? 0 : (r == d ? d : r / 2);
@@ -1592,6 +1594,7 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
       ell_cur = std::min<int64_t>(d, sn + kOversample);
       randomized_axes(ws, Cov, mc, d, ell_cur, pca_iters, seed, ax.lam, ax.Vt, st);
       axim.s = 0;   // new axes: their images are not the kept ones
+      im_r = -1;
     };
     e_search.begin(st);
     float* Pi = ensure<float>(ws.Pi, (size_t)(d * d));
@@ -1625,7 +1628,13 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
           return false;
         }
       }
-      Images im = images_of_map(ws, p, Pi, r, st, &axim, lead_axes(r));
+      // An FP8 fit certifies the r of its last screened probe, usually the
+      // map embedded last: its images (and their screen copies) are reused.
+      if (r != im_r) {
+        im_last = images_of_map(ws, p, Pi, r, st, &axim, lead_axes(r));
+        im_r = r;
+      }
+      const Images& im = im_last;
       // the search's own screens, and in an FP8 fit its BF16 split
       // certificates, load the fit's point-Gram cache
       const int gmode = gcache && (scr == screen || (screen == ADAGIO_SCREEN_FP8 && scr == ADAGIO_SCREEN_BF16X3)) ? 2 : 0;

@@ -2,8 +2,10 @@
 //
 // Every centred row a_i is scaled by s_i = max_l |a_il| / 448 and quantised
 // to OCP FP8 e4m3 (round to nearest even; 448 is the largest finite value):
-// q_i = e4m3(a_i / s_i).  The Gram q_i . q_j runs on
-// v_mfma_scale_f32_32x32x64_f8f6f4 (scale bytes 127 = 2^0) with FP32
+// q_i = e4m3(a_i / s_i).  The Gram q_i . q_j runs on the unscaled
+// v_mfma_f32_32x32x64_f8f6f4 (the scaled builtin with zero scale operands,
+// which the compiler emits as the unscaled instruction; the same products as
+// the scaled one with unit scales, about 3% faster) with FP32
 // accumulation, and the epilogue forms the central estimates
 //   D~^2 = N_i + N_j - 2 s_i s_j q_i.q_j,   N_i = s_i^2 |q_i|^2 (FP64, rounded),
 // and the same for the images, q~ = E~^2 / D~^2.  With a 2^-4 unit roundoff
@@ -117,6 +119,113 @@ struct PairsArgsF {
   const float* dscale;                         // its scale (device)
 };
 
+// Epilogue of one wave's 64 x 64 block of a tile (rows 64 wr, columns 64 wc
+// of tile (I, J)): the central estimates q~ of its pairs, the largest and
+// smallest as sortable keys (value bits with the low 6 mantissa bits replaced
+// by the pair's code), reduced over the wave into red_*[blk] (largest) and
+// red_*[4 + blk] (smallest), the values scaled by sc.  Pairs whose estimated
+// distance is not positive are not ranked.  LOADED: c / D2lo from the cache
+// block pk, accX unused.
+template <bool LOADED>
+__device__ __attribute__((always_inline)) inline void fp8_block(const f32x16 (&accX)[2][2],
+                                                                const f32x16 (&accY)[2][2], const u32x4 (&pk)[8],
+                                                                const float4* termA, const float4* termB, int wr,
+                                                                int wc, int I, int J, int n, float sc, float* red_v,
+                                                                int* red_i, int* red_j, int blk) {
+  const int lane = threadIdx.x & 63, li = lane & 31, lh = lane >> 5;
+  const int row0 = I * kTile, col0 = J * kTile;
+  const bool masked = !((I < J) && (col0 + kTile <= n));
+  uint32_t khi = 0u, klo = 0xFFFFFFFFu;
+  // column terms with s in place of -2 s (the row term carries the -2)
+  float4 tb0 = termB[wc * 64 + li], tb1 = termB[wc * 64 + 32 + li];
+  tb0.z *= -0.5f; tb0.w *= -0.5f;
+  tb1.z *= -0.5f; tb1.w *= -0.5f;
+  // the pass over the thread's 64 pairs, compiled once with the edge mask
+  // and once without (the mask is uniform per tile: no per-pair branch)
+  auto scan = [&](auto maskc) __attribute__((always_inline)) {
+    constexpr bool M = decltype(maskc)::value;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int rl = wr * 64 + x * 32 + (v >> 2) * 8 + lh * 4 + (v & 3);
+        const float4 ta = termA[rl];
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          const float4 tb = y ? tb1 : tb0;
+          const float e2 = fmaf(ta.w * tb.w, accY[x][y][v], ta.y + tb.y);
+          // q~ = E~^2 / D~^2 with D~^2 = -2 s_i s_j g + N_i + N_j, or c q~ =
+          // E~^2 g from the cached g = c / D2lo (finite: D2lo > 0)
+          float q;
+          bool ok;
+          if constexpr (LOADED) {
+            const float g = dcache_g(pk, x, y, v);
+            q = e2 * g;
+            ok = __float_as_uint(g) < 0x7F800000u;
+          } else {
+            const float d2 = fmaf(ta.z * tb.z, accX[x][y][v], ta.x + tb.x);
+            q = e2 * __builtin_amdgcn_rcpf(d2);
+            ok = d2 > 0.0f;
+          }
+          // negative estimates rank as 0 (integer max on the bits)
+          const int32_t qi = __float_as_int(q);
+          const uint32_t k = pair_key(__int_as_float(qi > 0 ? qi : 0), (x * 2 + y) * 16 + v);
+          if (M) {
+            const int cl = wc * 64 + y * 32 + li;
+            ok = ok && (I < J || rl < cl) && col0 + cl < n;
+          }
+          khi = ok && k > khi ? k : khi;
+          klo = ok && k < klo ? k : klo;
+          asm volatile("" : "+v"(khi), "+v"(klo));
+        }
+      }
+  };
+  if (masked) scan(std::integral_constant<bool, true>{});
+  else scan(std::integral_constant<bool, false>{});
+  auto decode = [&](int code, int& gi, int& gj) {
+    if (code < 0) { gi = 0x7fffffff; gj = 0x7fffffff; return; }
+    const int x = code >> 5, y = (code >> 4) & 1, v = code & 15;
+    gi = row0 + wr * 64 + x * 32 + (v >> 2) * 8 + lh * 4 + (v & 3);
+    gj = col0 + wc * 64 + y * 32 + li;
+  };
+  // the wave's extreme keys and the lowest lanes holding them
+  const uint32_t whi = wave_max_u32(khi), wlo = wave_min_u32(klo);
+  const uint64_t bh = __ballot(khi == whi), bl = __ballot(klo == wlo);
+  const int lhi = __ffsll((unsigned long long)bh) - 1, llo = __ffsll((unsigned long long)bl) - 1;
+  int ih, jh, il, jl;
+  decode(khi == 0u ? -1 : (int)(khi & 63u), ih, jh);
+  decode(klo == 0xFFFFFFFFu ? -1 : (int)(klo & 63u), il, jl);
+  ih = __shfl(ih, lhi, 64); jh = __shfl(jh, lhi, 64);
+  il = __shfl(il, llo, 64); jl = __shfl(jl, llo, 64);
+  if (lane == 0) {
+    red_v[blk] = whi == 0u ? -1.0f : key_lo_value(whi) * sc; red_i[blk] = ih; red_j[blk] = jh;
+    red_v[4 + blk] = wlo == 0xFFFFFFFFu ? 3.0e38f : key_lo_value(wlo) * sc; red_i[4 + blk] = il;
+    red_j[4 + blk] = jl;
+  }
+}
+
+// The tile record from its four blocks' extremes (one thread).
+__device__ inline void fp8_tile_record(const float* red_v, const int* red_i, const int* red_j, TileRec* rec_out) {
+  float vh = red_v[0], vl = red_v[4];
+  int ih0 = red_i[0], jh0 = red_j[0], il0 = red_i[4], jl0 = red_j[4];
+  for (int w = 1; w < 4; ++w) {
+    if (red_v[w] > vh || (red_v[w] == vh && idx_better(red_i[w], red_j[w], ih0, jh0))) {
+      vh = red_v[w]; ih0 = red_i[w]; jh0 = red_j[w];
+    }
+    if (red_v[4 + w] < vl || (red_v[4 + w] == vl && idx_better(red_i[4 + w], red_j[4 + w], il0, jl0))) {
+      vl = red_v[4 + w]; il0 = red_i[4 + w]; jl0 = red_j[4 + w];
+    }
+  }
+  const bool none_hi = ih0 == 0x7fffffff || vh < 0.0f;
+  const bool none_lo = il0 == 0x7fffffff || vl >= 3.0e38f;
+  TileRec rec;
+  rec.qhi = vh; rec.qlo = vl;
+  rec.ihi = none_hi ? -1 : ih0; rec.jhi = none_hi ? -1 : jh0;
+  rec.ilo = none_lo ? -1 : il0; rec.jlo = none_lo ? -1 : jl0;
+  rec.pad0 = 0; rec.pad1 = 0;
+  *rec_out = rec;
+}
+
 // LOADED: the pairs' c / D2lo come from the fit's compact cache (filled from
 // the BF16 split point Gram, a far better D^2 estimate than the FP8 Gram);
 // the kernel runs the image chunks only, with the next two chunks in flight
@@ -225,7 +334,7 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_fp8(PairsArgsF b)
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y)
-          acc[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av[x], bv[y], acc[x][y], 0, 0, 0, 127, 0, 127);
+          acc[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av[x], bv[y], acc[x][y], 0, 0, 0, 0, 0, 0);
     }
   };
 
@@ -282,99 +391,10 @@ __global__ __launch_bounds__(256, LOADED ? 3 : 2) void k_pairs_fp8(PairsArgsF b)
   }
 
   // epilogue: central estimates, largest and smallest q~ of the tile
-  const bool masked = !((I < J) && (col0 + kTile <= n));
-  // the tile's largest and smallest estimate as sortable keys (value bits
-  // with the low 6 mantissa bits replaced by the pair's code); pairs whose
-  // estimated distance is not positive are not ranked
-  uint32_t khi = 0u, klo = 0xFFFFFFFFu;
-  // column terms with s in place of -2 s (the row term carries the -2)
-  float4 tb0 = termB[wc * 64 + li], tb1 = termB[wc * 64 + 32 + li];
-  tb0.z *= -0.5f; tb0.w *= -0.5f;
-  tb1.z *= -0.5f; tb1.w *= -0.5f;
-  // the pass over the thread's 64 pairs, compiled once with the edge mask
-  // and once without (the mask is uniform per tile: no per-pair branch)
-  auto scan = [&](auto maskc) __attribute__((always_inline)) {
-    constexpr bool M = decltype(maskc)::value;
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int rl = wr * 64 + x * 32 + (v >> 2) * 8 + lh * 4 + (v & 3);
-        const float4 ta = termA[rl];
-#pragma unroll
-        for (int y = 0; y < 2; ++y) {
-          const float4 tb = y ? tb1 : tb0;
-          const float e2 = fmaf(ta.w * tb.w, accY[x][y][v], ta.y + tb.y);
-          // q~ = E~^2 / D~^2 with D~^2 = -2 s_i s_j g + N_i + N_j, or c q~ =
-          // E~^2 g from the cached g = c / D2lo (finite: D2lo > 0)
-          float q;
-          bool ok;
-          if constexpr (LOADED) {
-            const float g = dcache_g(pk, x, y, v);
-            q = e2 * g;
-            ok = __float_as_uint(g) < 0x7F800000u;
-          } else {
-            const float d2 = fmaf(ta.z * tb.z, accX[x][y][v], ta.x + tb.x);
-            q = e2 * __builtin_amdgcn_rcpf(d2);
-            ok = d2 > 0.0f;
-          }
-          // negative estimates rank as 0 (integer max on the bits)
-          const int32_t qi = __float_as_int(q);
-          const uint32_t k = pair_key(__int_as_float(qi > 0 ? qi : 0), (x * 2 + y) * 16 + v);
-          if (M) {
-            const int cl = wc * 64 + y * 32 + li;
-            ok = ok && (I < J || rl < cl) && col0 + cl < n;
-          }
-          khi = ok && k > khi ? k : khi;
-          klo = ok && k < klo ? k : klo;
-          asm volatile("" : "+v"(khi), "+v"(klo));
-        }
-      }
-  };
-  if (masked) scan(std::integral_constant<bool, true>{});
-  else scan(std::integral_constant<bool, false>{});
-  auto decode = [&](int code, int& gi, int& gj) {
-    if (code < 0) { gi = 0x7fffffff; gj = 0x7fffffff; return; }
-    const int x = code >> 5, y = (code >> 4) & 1, v = code & 15;
-    gi = row0 + wr * 64 + x * 32 + (v >> 2) * 8 + lh * 4 + (v & 3);
-    gj = col0 + wc * 64 + y * 32 + li;
-  };
-  // the wave's extreme keys and the lowest lanes holding them
-  const uint32_t whi = wave_max_u32(khi), wlo = wave_min_u32(klo);
-  const uint64_t bh = __ballot(khi == whi), bl = __ballot(klo == wlo);
-  const int lhi = __ffsll((unsigned long long)bh) - 1, llo = __ffsll((unsigned long long)bl) - 1;
-  int ih, jh, il, jl;
-  decode(khi == 0u ? -1 : (int)(khi & 63u), ih, jh);
-  decode(klo == 0xFFFFFFFFu ? -1 : (int)(klo & 63u), il, jl);
-  ih = __shfl(ih, lhi, 64); jh = __shfl(jh, lhi, 64);
-  il = __shfl(il, llo, 64); jl = __shfl(jl, llo, 64);
-  if (lane == 0) {
-    const float sc = LOADED ? 1.0f / *b.dscale : 1.0f;   // exact: a power of two
-    red_v[wave] = whi == 0u ? -1.0f : key_lo_value(whi) * sc; red_i[wave] = ih; red_j[wave] = jh;
-    red_v[4 + wave] = wlo == 0xFFFFFFFFu ? 3.0e38f : key_lo_value(wlo) * sc; red_i[4 + wave] = il;
-    red_j[4 + wave] = jl;
-  }
+  const float sc = LOADED ? 1.0f / *b.dscale : 1.0f;   // exact: a power of two
+  fp8_block<LOADED>(accX, accY, pk, termA, termB, wr, wc, I, J, n, sc, red_v, red_i, red_j, wave);
   __syncthreads();
-  if (tid == 0) {
-    float vh = red_v[0], vl = red_v[4];
-    int ih0 = red_i[0], jh0 = red_j[0], il0 = red_i[4], jl0 = red_j[4];
-    for (int w = 1; w < 4; ++w) {
-      if (red_v[w] > vh || (red_v[w] == vh && idx_better(red_i[w], red_j[w], ih0, jh0))) {
-        vh = red_v[w]; ih0 = red_i[w]; jh0 = red_j[w];
-      }
-      if (red_v[4 + w] < vl || (red_v[4 + w] == vl && idx_better(red_i[4 + w], red_j[4 + w], il0, jl0))) {
-        vl = red_v[4 + w]; il0 = red_i[4 + w]; jl0 = red_j[4 + w];
-      }
-    }
-    const bool none_hi = ih0 == 0x7fffffff || vh < 0.0f;
-    const bool none_lo = il0 == 0x7fffffff || vl >= 3.0e38f;
-    TileRec rec;
-    rec.qhi = vh; rec.qlo = vl;
-    rec.ihi = none_hi ? -1 : ih0; rec.jhi = none_hi ? -1 : jh0;
-    rec.ilo = none_lo ? -1 : il0; rec.jlo = none_lo ? -1 : jl0;
-    rec.pad0 = 0; rec.pad1 = 0;
-    b.recs[(int64_t)I * NT - (int64_t)I * (I - 1) / 2 + (J - I)] = rec;
-  }
+  if (tid == 0) fp8_tile_record(red_v, red_i, red_j, b.recs + tix);
 }
 
 // Estimated distortion of a tile record, as a monotone 32-bit key.
