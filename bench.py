@@ -636,6 +636,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the precision-form fits")
     ap.add_argument("--no-large", action="store_true", help="skip the n=200000, d=4096 precision-form fit")
     ap.add_argument("--no-knn", action="store_true", help="skip the kNN retrieval application")
+    ap.add_argument("--no-ceiling", action="store_true",
+                    help="skip the MFMA-only kernels that measure the matrix cores' attainable rate")
     ap.add_argument("--learned-instances", type=int, default=64,
                     help="held-out learned-form instances for the learned search's gain (0: none)")
     ap.add_argument("--no-witness", action="store_true",
@@ -879,6 +881,31 @@ def main():
         log("kNN retrieval on the SIFT-shaped workload")
         knn = knn_form(adagio, gen, torch)
 
+    # The matrix cores' attainable rate: kernels of independent MFMAs only,
+    # under which the shader clock settles below the 2.4 GHz that the
+    # published peaks assume; context for the fractions of peak above.
+    ceil = None
+    if not args.no_ceiling:
+        ceil = {k: adagio.mfma_ceiling(k) for k in ("fp32", "bf16", "fp8")}
+        for k, v in ceil.items():
+            v["frac_of_peak"] = v["tflops"] / {"fp32": PEAK_FP32_MFMA_TFLOPS, "bf16": PEAK_BF16_MFMA_TFLOPS,
+                                               "fp8": PEAK_FP8_MFMA_TFLOPS}[k]
+        roofline["attainable"] = ceil["fp32"]["tflops"]
+        roofline["frac_of_attainable"] = roofline["achieved"] / ceil["fp32"]["tflops"]
+        if "bf16x3" in forms:
+            f = forms["bf16x3"]
+            f["screen_bf16_mfma_frac_of_attainable"] = f["screen_bf16_mfma_tflops"] / ceil["bf16"]["tflops"]
+        if "fp8" in forms:
+            f = forms["fp8"]
+            f["screen_fp8_mfma_frac_of_attainable"] = f["screen_fp8_mfma_tflops"] / ceil["fp8"]["tflops"]
+        if large:
+            large["fp8_screen_frac_of_attainable"] = large["fp8_screen_tflops"] / ceil["fp8"]["tflops"]
+            large["bf16x3_screen_mfma_frac_of_attainable"] = (3.0 * large["bf16x3_screen_useful_tflops"]
+                                                              / ceil["bf16"]["tflops"])
+        log("MFMA-only ceilings: " + ", ".join("%s %.0f TFLOP/s (%.2f of peak, %.2f GHz)"
+                                               % (k, v["tflops"], v["frac_of_peak"], v["clock_ghz"])
+                                               for k, v in ceil.items()))
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample (~%.0f s)" % args.cpu_seconds)
@@ -922,6 +949,7 @@ def main():
         "large_precision_form": large,
         "knn_application": knn,
         "roofline": roofline,
+        "mfma_ceilings": ceil,
         "cpu_baseline": cpu,
         "oracle_parity": parity,
         "paper_context": "paper: <10 s for 60,000 x 784 MNIST on an i5-3317U laptop (abstract); not this workload",

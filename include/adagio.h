@@ -395,6 +395,18 @@ int adagio_knn(const float* Q, int64_t nq, const float* D, int64_t nd, int64_t m
 int adagio_knn_vote(const int32_t* nn_idx, int64_t nq, int32_t k, const int32_t* d_label, int64_t nd,
                     int32_t n_labels, int32_t group, int32_t* label_out, void* stream);
 
+/* Measurement aid for roofline figures (not a step of the method): the
+ * matrix-core throughput of a kernel that issues nothing but independent
+ * MFMAs of one kind on register operands (kind 0: FP8 e4m3 32x32x64, 1: BF16
+ * 32x32x16, 2: FP32 32x32x2; four accumulators per wave, 1024 workgroups of
+ * 256 threads), in TFLOP/s, and the shader clock in GHz that one workgroup
+ * measured during it (s_memtime against the 100 MHz s_memrealtime).  The
+ * published dense peaks assume the 2.4 GHz peak clock; under a sustained
+ * MFMA load the clock settles lower.  tflops_out and ghz_out are host
+ * doubles.  Allocates about 1 MB, runs four launches of ~2.5 ms (the last is
+ * timed) and synchronises `stream`.  ADAGIO_E_INVALID_ARG for another kind. */
+int adagio_mfma_ceiling(int32_t kind, double* tflops_out, double* ghz_out, void* stream);
+
 /* Workspace ownership: keep = 1 keeps each device's workspace (buffers,
  * the fit's point-Gram cache, two streams and their events) across calls,
  * so that repeated calls skip allocation; keep = 0 (the default) frees every

@@ -106,6 +106,7 @@ SIGNATURES = {
     "adagio_knn": (ctypes.c_int, [_P, _I64, _P, _I64, _I64, _I32, _I32, _P, _P, ctypes.POINTER(KnnStats), _P]),
     "adagio_knn_vote": (ctypes.c_int, [_P, _I64, _I32, _P, _I64, _I32, _I32, _P, _P]),
     "adagio_release": (ctypes.c_int, []),
+    "adagio_mfma_ceiling": (ctypes.c_int, [_I32, ctypes.POINTER(_D), ctypes.POINTER(_D), _P]),
     "adagio_keep_workspace": (ctypes.c_int, [ctypes.c_int]),
     "adagio_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "adagio_last_error": (ctypes.c_char_p, []),
@@ -394,6 +395,20 @@ def knn_vote(nn_idx, d_label, n_labels, group):
 def release():
     """Frees the current device's kept workspace."""
     _check(load().adagio_release())
+
+
+MFMA_KINDS = {"fp8": 0, "bf16": 1, "fp32": 2}
+
+
+def mfma_ceiling(kind):
+    """Throughput (TFLOP/s) of a kernel of independent MFMAs of `kind`
+    ("fp8", "bf16" or "fp32") on this device, and the shader clock (GHz) it
+    ran at: the attainable matrix-core rate under a sustained load."""
+    lib = load()
+    t = ctypes.c_double()
+    g = ctypes.c_double()
+    _check(lib.adagio_mfma_ceiling(MFMA_KINDS[kind], ctypes.byref(t), ctypes.byref(g), _stream()))
+    return {"tflops": t.value, "clock_ghz": g.value}
 
 
 def keep_workspace(keep=True):

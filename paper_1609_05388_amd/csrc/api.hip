@@ -1930,6 +1930,55 @@ int adagio_knn_vote(const int32_t* nn_idx, int64_t nq, int32_t k, const int32_t*
   });
 }
 
+int adagio_mfma_ceiling(int32_t kind, double* tflops_out, double* ghz_out, void* stream) {
+  return guarded([&] {
+    ARGCHK(kind >= 0 && kind <= 2, "kind must be 0 (FP8), 1 (BF16) or 2 (FP32)");
+    ARGCHK(tflops_out && ghz_out, "NULL output pointer");
+    hipStream_t st = as_stream(stream);
+    // operands: 1024 words of e4m3 byte patterns without NaN codes (FP8);
+    // the BF16 and FP32 loops read values from the same words
+    std::vector<int> h(1024);
+    uint32_t z = 0x9E3779B9u;
+    for (int& x : h) {
+      uint32_t w = 0;
+      for (int k = 0; k < 4; ++k) {
+        z = z * 1664525u + 1013904223u;
+        uint32_t b = (z >> 24) & 0xFFu;
+        if ((b & 0x7Fu) == 0x7Fu) b = 0x38u;
+        w |= b << (8 * k);
+      }
+      x = (int)w;
+    }
+    DevBuf bin, bout, bclk;
+    int* din = ensure<int>(bin, 1024);
+    float* dout = ensure<float>(bout, (size_t)mfma_ceiling_grid() * 256);
+    unsigned long long* dclk = ensure<unsigned long long>(bclk, 2);
+    HIPCHK(hipMemcpyAsync(din, h.data(), 4096, hipMemcpyHostToDevice, st));
+    // about 2.5 ms per launch; the last of four is timed, after the clock
+    // has settled under the load
+    const int iters = kind == 0 ? 4096 : kind == 1 ? 8192 : 2048;
+    const double flop = (kind == 0 ? 32.0 * 32 * 64 : kind == 1 ? 32.0 * 32 * 16 : 32.0 * 32 * 2) * 2.0 * 4.0 *
+                        iters * mfma_ceiling_grid() * 4.0;
+    struct Ev {
+      hipEvent_t e = nullptr;
+      ~Ev() { if (e) (void)hipEventDestroy(e); }
+    } e0, e1;
+    HIPCHK(hipEventCreate(&e0.e));
+    HIPCHK(hipEventCreate(&e1.e));
+    for (int rep = 0; rep < 3; ++rep) HIPCHK(launch_mfma_ceiling(kind, din, dout, dclk, iters, st));
+    HIPCHK(hipEventRecord(e0.e, st));
+    HIPCHK(launch_mfma_ceiling(kind, din, dout, dclk, iters, st));
+    HIPCHK(hipEventRecord(e1.e, st));
+    unsigned long long c[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(c, dclk, sizeof(c), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, e0.e, e1.e));
+    *tflops_out = ms > 0.0f ? flop / ((double)ms * 1e9) : 0.0;
+    *ghz_out = c[1] ? (double)c[0] / ((double)c[1] / 100e6) / 1e9 : 0.0;
+  });
+}
+
 int adagio_release(void) {
   return guarded([&] {
     int dev = 0;

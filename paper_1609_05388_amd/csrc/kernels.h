@@ -66,6 +66,14 @@ hipError_t launch_copy_block64(const double* src, int64_t lds, double* dst, int6
 // *out = sum of a[e]^2 (FP64), through nparts block partials in part.
 hipError_t launch_sumsq(const double* a, int64_t count, double* part, int nparts, double* out, hipStream_t st);
 
+// k_ceiling.hip: a kernel of independent MFMAs only (kind 0 FP8 32x32x64,
+// 1 BF16 32x32x16, 2 FP32 32x32x2) over mfma_ceiling_grid() workgroups of
+// 256 threads; in: 1024 words, out: one float per thread, clk: the shader
+// clock and 100 MHz counter deltas of workgroup 0.
+int mfma_ceiling_grid();
+hipError_t launch_mfma_ceiling(int kind, const int* in, float* out, unsigned long long* clk, int iters,
+                               hipStream_t st);
+
 // k_chol.hip: in-place Cholesky factor (lower, strict upper zeroed) of an
 // SPD m x m column-major FP64 matrix, m <= chol_max_m(); *fail = 1 on a
 // non-positive pivot.

@@ -143,6 +143,16 @@ def test_workspace_mode_argument(lib):
     assert lib.adagio_keep_workspace(0) == 0
 
 
+def test_mfma_ceiling_arguments(lib):
+    """The MFMA ceiling measurement takes kinds 0-2 and host outputs; others
+    are refused before any device work."""
+    t, g = ctypes.c_double(), ctypes.c_double()
+    assert lib.adagio_mfma_ceiling(3, ctypes.byref(t), ctypes.byref(g), None) == -1
+    assert b"kind must be" in lib.adagio_last_error()
+    assert lib.adagio_mfma_ceiling(-1, ctypes.byref(t), ctypes.byref(g), None) == -1
+    assert lib.adagio_mfma_ceiling(0, None, ctypes.byref(g), None) == -1
+
+
 def test_noalloc_certificate_refuses_before_device_work(lib):
     """The no-allocation certificate refuses inputs beyond its fixed scratch
     array, and screens other than FP32, on the host."""
