@@ -89,3 +89,26 @@ def test_precision_fits_odd_tile_count(gpu_lib, n):
     f = gpu_lib.fit(Xd, 0.1, gen.JL_SEED, screen="fp8")
     assert f["cert"]["certified"] == 1
     assert f["r"] == a["r"] and torch.equal(f["Pi"], a["Pi"])
+
+
+@pytest.mark.parametrize("n", [1100, 1300, 1500])
+def test_fp8_fit_long_image_rows(gpu_lib, n):
+    """Maps with at least eight 64-column image chunks (r > 448) screen on
+    256 x 256 quads of tiles; odd tile counts (9, 11 tiles) leave quads
+    with rows past the cloud.  The FP8-screened fit's certificate must be the
+    oracle's for its map."""
+    rng = np.random.default_rng(n)
+    X = gen.low_rank_pixels(n=n, d=1100, rank=300, seed=n).astype(np.float64)
+    X *= 10.0 ** rng.uniform(-1.0, 1.0, (n, 1))
+    X = X.astype(np.float32)
+    print("fp8 fit, %d x 1100, long image rows" % n, flush=True)
+    Xd = dev(X)
+    f = gpu_lib.fit(Xd, 0.1, gen.JL_SEED, screen="fp8")
+    assert max(f["stats"]["probe_cols"]) > 448
+    c = f["cert"]
+    assert c["certified"] == 1 and c["max_distortion"] <= 0.1
+    Pi = f["Pi"][: f["r"]].cpu().numpy().astype(np.float64)
+    want = certificate.certify(X, embedding.embed(X, Pi))
+    assert abs(c["max_distortion"] - want["max"]) <= 1e-12
+    if want["max"] - want["runner_up"] > 1e-12:
+        assert (c["i"], c["j"]) == (want["i"], want["j"])
