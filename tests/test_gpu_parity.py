@@ -36,8 +36,9 @@ def assert_cert_parity(got, want, tol=TOL):
 
 
 # ---------------------------------------------------------------- a1 - a3
-@pytest.mark.parametrize("n,d", [(300, 48), (129, 7), (2000, 784), (65, 1)])
+@pytest.mark.parametrize("n,d", [(300, 48), (129, 7), (2000, 784), (65, 1), (2500, 2100)])
 def test_pca_matches_oracle(gpu_lib, n, d):
+    """(2500, 2100): an eigensolve of order 2112 (66 index blocks)."""
     X = gen.low_rank_pixels(n=n, d=d, rank=min(6, d), seed=n + d)
     lam, Vt = gpu_lib.pca(dev(X))
     lam, Vt = lam.cpu().numpy(), Vt.cpu().numpy()
