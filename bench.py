@@ -125,7 +125,7 @@ def summarize_traffic(d):
         "fetch": out["FETCH_SIZE"], "write": out["WRITE_SIZE"],
         "commands": [
             "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pmc -o copy_FETCH_SIZE -- python3 <repo>/bench.py --calib-copy-mib 1024",
-            "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pmc -o fit_FETCH_SIZE -- python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-oracle-parity --no-extra-eps --no-forms --no-large --no-knn --no-witness",
+            "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pmc -o fit_FETCH_SIZE -- python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-oracle-parity --no-extra-eps --no-forms --no-large --no-knn --no-witness --no-ceiling --learned-instances 0",
             "(the same two with WRITE_SIZE)",
             "python3 <repo>/bench.py --summarize-traffic <out>/pmc",
         ],
@@ -608,7 +608,7 @@ def summarize_mfma(d):
         "workload": fit["config"]["workload"], "probes_r": rs, "probes_screen_cols": cols,
         "kinds": out,
         "commands": [
-            "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc MfmaUtil MfmaFlopsF32 --output-format csv -d <out>/mfma -o fit_mfma -- python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-oracle-parity --no-extra-eps --no-forms --no-large --no-knn --no-witness > <out>/mfma/fit_mfma.log",
+            "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc MfmaUtil MfmaFlopsF32 --output-format csv -d <out>/mfma -o fit_mfma -- python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-oracle-parity --no-extra-eps --no-forms --no-large --no-knn --no-witness --no-ceiling --learned-instances 0 > <out>/mfma/fit_mfma.log",
             "python3 <repo>/bench.py --summarize-mfma <out>/mfma",
         ],
         "note": "MfmaUtil: percent of the dispatch's GPU-active cycles during which the SIMDs' MFMA units were busy "
