@@ -52,7 +52,7 @@ __global__ void k_split_bf16(const float* __restrict__ src, int64_t n_pad, int64
 }
 
 struct PairsArgsB {
-  const __bf16* X; int ldx; int nchx;  // hi/lo points, row stride 2 * ldx bf16, ldx = 32 * nchx
+  const __bf16* X; int ldx; int nchx;  // hi/lo points, row stride 2 * ldx bf16, ldx = 16 * nchx
   const __bf16* Y; int ldy; int nchy;  // hi/lo images
   PairsArgs p;                         // row terms, sizes, outputs (X/Y fields unused)
 };
