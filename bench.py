@@ -391,16 +391,19 @@ def learned_heldout(adagio, gen, torch, count):
     {128, 256, 784, 2048}, power-law spectra, eps in [0.05, 0.3]; never seen
     in training).  Per instance plain bisection, the learned search
     (certified prediction, bisection fallback) and the learned search with
-    downward refinement, each timed once after a warm-up fit of the same
-    search (FP32 screen; the warm-up sizes the kept workspace's buffers for
-    that search, as the 512-instance evaluation does)."""
+    downward refinement, each run once as a warm-up (which sizes the kept
+    workspace's buffers for that search, as the 512-instance evaluation does)
+    and then timed twice, the faster time counting (a single timing of a fit
+    of a few ms picks up host-side stalls of tens of ms now and then; FP32
+    screen)."""
     import numpy as np
     from paper_1609_05388_amd import learned
     if not os.path.exists(learned.PREDICTOR):
         return None
     P = learned.load_predictor(learned.PREDICTOR)
     modes = (("plain", {}), ("learned", {"search": "learned", "predictor": P}),
-             ("learned_refine", {"search": "learned", "predictor": P, "refine": True}))
+             ("learned_refine", {"search": "learned", "predictor": P, "refine": True}),
+             ("learned_refine_within4", {"search": "learned", "predictor": P, "refine": "within4"}))
     rows = []
     t0 = time.perf_counter()
     for index, pr, X in learned.instances(list(range(count)), held_out=True):
@@ -408,12 +411,16 @@ def learned_heldout(adagio, gen, torch, count):
         row = {"index": index, "n": pr["n"], "d": pr["d"], "eps": pr["eps"]}
         for name, kw in modes:
             adagio.fit(Xd, pr["eps"], gen.JL_SEED, **kw)
-            torch.cuda.synchronize()
-            ta = time.perf_counter()
-            o = adagio.fit(Xd, pr["eps"], gen.JL_SEED, **kw)
-            torch.cuda.synchronize()
+            best = None
+            for _ in range(2):
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                o = adagio.fit(Xd, pr["eps"], gen.JL_SEED, **kw)
+                torch.cuda.synchronize()
+                t = (time.perf_counter() - ta) * 1e3
+                best = t if best is None else min(best, t)
             c = o["cert"]
-            row[name] = {"ms": (time.perf_counter() - ta) * 1e3, "r": o["r"],
+            row[name] = {"ms": best, "r": o["r"],
                          "certificates": o["stats"]["n_certificates"], "fallback": o["stats"]["n_fallback"],
                          "r_predicted": o["stats"]["r_predicted"],
                          "proven": bool(c["max_distortion"] <= pr["eps"] if c["certified"] == 1
@@ -437,14 +444,18 @@ def learned_heldout(adagio, gen, torch, count):
                      "max_r_over_plain": float(max(r[name]["r"] / r["plain"]["r"] for r in rows)),
                      "same_r_as_plain": float(np.mean([r[name]["r"] == r["plain"]["r"] for r in rows])),
                      "all_proven_within_eps": bool(all(r[name]["proven"] for r in rows))}
-    log("learned held-out (%d instances): learned %.2fx (r %.3f), refined %.2fx (r %.3f)" % (
-        len(rows), out["learned"]["speedup_vs_plain"], out["learned"]["mean_r_over_plain"],
-        out["learned_refine"]["speedup_vs_plain"], out["learned_refine"]["mean_r_over_plain"]))
+    log("learned held-out (%d instances): learned %.2fx (r %.3f), refined %.2fx (r %.3f), "
+        "refined within 4%% %.2fx (r %.3f)" % (
+            len(rows), out["learned"]["speedup_vs_plain"], out["learned"]["mean_r_over_plain"],
+            out["learned_refine"]["speedup_vs_plain"], out["learned_refine"]["mean_r_over_plain"],
+            out["learned_refine_within4"]["speedup_vs_plain"], out["learned_refine_within4"]["mean_r_over_plain"]))
     out["per_instance"] = [[r["index"], r["n"], r["d"], round(r["eps"], 4), r["plain"]["r"], r["learned"]["r"],
-                            r["learned_refine"]["r"], round(r["plain"]["ms"], 2), round(r["learned"]["ms"], 2),
-                            round(r["learned_refine"]["ms"], 2)] for r in rows]
-    out["per_instance_columns"] = ["index", "n", "d", "eps", "r_plain", "r_learned", "r_refined", "ms_plain",
-                                   "ms_learned", "ms_refined"]
+                            r["learned_refine"]["r"], r["learned_refine_within4"]["r"], round(r["plain"]["ms"], 2),
+                            round(r["learned"]["ms"], 2), round(r["learned_refine"]["ms"], 2),
+                            round(r["learned_refine_within4"]["ms"], 2)] for r in rows]
+    out["per_instance_columns"] = ["index", "n", "d", "eps", "r_plain", "r_learned", "r_refined",
+                                   "r_refined_within4", "ms_plain", "ms_learned", "ms_refined",
+                                   "ms_refined_within4"]
     return out
 
 

@@ -159,8 +159,12 @@ typedef struct adagio_opts {
                                 pass), then bisect between the last failing and
                                 the last passing r, so the result is
                                 bisection-minimal like the plain search's (r - 1
-                                fails); default 0 returns the certified
-                                prediction                                        */
+                                fails); 2 = the same, but the bisection stops
+                                once the last failing r is within 4% of the
+                                last passing one (r - r_fail <= r / 25, so r is
+                                within 1/0.96 of the smallest passing r when the
+                                distortion falls with r); default 0 returns the
+                                certified prediction                              */
 } adagio_opts_t;
 
 /* a1-a3.  Principal axes of the centred cloud (Sec. 2 PCA paragraph, eq. 4;

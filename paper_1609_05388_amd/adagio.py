@@ -153,7 +153,7 @@ def _opts(screen="f32", search="bisect", max_candidates=0, predictor=None, stats
           pca="exact", pca_iters=2, witness=True, refine=False):
     o = Opts()
     o.no_witness = 0 if witness else 1
-    o.refine = 1 if refine else 0
+    o.refine = 2 if refine == "within4" else int(refine)
     o.screen = SCREEN[screen]
     o.search = SEARCH[search]
     o.family = FAMILY[family]
@@ -283,7 +283,9 @@ def fit(X, eps, seed, screen="f32", search="bisect", predictor=None, max_candida
     (Algorithm 1), "pca" or "jl" (Table 3's single-component maps); pca:
     "exact" or "randomized" (Sec. 4.5's variant, pca_iters power iterations);
     witness=False certifies every probe in full; refine=True makes the
-    learned search probe downward from a certified prediction."""
+    learned search probe downward from a certified prediction to the
+    bisection-minimal r, refine="within4" stops that downward bisection once
+    its last failing r is within 4% of the returned one."""
     lib = load()
     n, d = X.shape
     Pi_buf = torch.empty((d, d), dtype=torch.float32, device=X.device)

@@ -1520,7 +1520,7 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
     const int no_witness = opts ? opts->no_witness : 0;
     ARGCHK(no_witness == 0 || no_witness == 1, "no_witness must be 0 or 1");
     const int refine = opts ? opts->refine : 0;
-    ARGCHK(refine == 0 || refine == 1, "refine must be 0 or 1");
+    ARGCHK(refine == 0 || refine == 1 || refine == 2, "refine must be 0, 1 or 2");
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = as_stream(stream);
     CallWs cw(as_stream(stream));
@@ -1658,8 +1658,9 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
       }
       return pass;
     };
-    auto bisect = [&](int scr) {
-      while (hi - lo > 1) {
+    // rel > 0: stop once the bracket (lo fails, hi passes) is within hi / rel
+    auto bisect = [&](int scr, int64_t rel = 0) {
+      while (hi - lo > 1 && (rel == 0 || (hi - lo) * rel > hi)) {
         const int64_t mid = (lo + hi) / 2;
         if (probe(mid, scr)) hi = mid;
         else lo = mid;
@@ -1684,7 +1685,8 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
         // downward from the certified prediction: r / 1.25 while probes pass
         // (a failing probe is usually refuted by the witness pool the first
         // certificate filled), then bisection between the last failure and
-        // the last pass
+        // the last pass: to the end (refine 1), or until the bracket is
+        // within 4% of the last pass (refine 2)
         for (;;) {
           const int64_t g = (int64_t)std::floor((double)hi / 1.25);
           if (g <= lo) break;
@@ -1692,7 +1694,8 @@ int adagio_fit(const float* X, int64_t n, int64_t d, double eps, uint64_t seed, 
           else { lo = g; break; }
         }
       }
-      if (fallback || refine) bisect(rig);
+      if (fallback) bisect(rig);
+      else if (refine) bisect(rig, refine == 2 ? 25 : 0);
     } else if (screen == ADAGIO_SCREEN_FP8) {
       // Bisection over r on screened probes, then the certificate of the
       // result; if it fails, certified bisection continues on (r, d].

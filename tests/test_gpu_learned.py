@@ -164,3 +164,27 @@ def test_learned_search_refined_downward(gpu_lib):
     want = certificate.certify(X, embedding.embed(X, below))
     assert want["max"] > 0.1
     print("refined r %d, plain r %d" % (f["r"], plain["r"]))
+
+
+def test_learned_search_refined_within_4_percent(gpu_lib):
+    """refine="within4": the same downward search, but its bisection stops
+    once the largest failing probe below the returned r is within r / 25 of
+    it (or next to it); the result is certified within eps, lies between the
+    bisection-minimal r and the prediction, and takes no more certificates
+    than refine=True."""
+    X = gen.low_rank_pixels(n=600, d=120, rank=10, seed=5)
+    Xd = torch.from_numpy(X).cuda()
+    count = gpu_lib.mlp_param_count()
+    P = torch.zeros(count, dtype=torch.float32, device="cuda")
+    off, _ = omlp.layout()
+    P[off["b4"][0]] = float(np.log(100.0 / 120.0))   # r = 100, far above r*
+    print("learned search, refine within 4%", flush=True)
+    f = gpu_lib.fit(Xd, 0.1, 7, search="learned", predictor=P, refine="within4")
+    full = gpu_lib.fit(Xd, 0.1, 7, search="learned", predictor=P, refine=True)
+    assert f["cert"]["certified"] == 1 and f["cert"]["max_distortion"] <= 0.1
+    assert f["stats"]["n_fallback"] == 0 and full["r"] <= f["r"] < 100
+    st = f["stats"]
+    failed = [r for r, dl in zip(st["probe_r"], st["probe_delta"]) if dl > 0.1 and r < f["r"]]
+    gap = f["r"] - max(failed)
+    assert failed and (gap <= 1 or gap * 25 <= f["r"])
+    assert st["n_certificates"] <= full["stats"]["n_certificates"]
