@@ -13,12 +13,14 @@
 // The round then applies the block-diagonal orthogonal J (the U's on their
 // index sets): A <- J^T A J tile by tile (tile (PQ, RS) becomes
 // U_PQ^T A_tile U_RS) and W <- J^T W, with W = V^T accumulating eigenvectors
-// as rows.  Every tile and every W row block is read and written by one
-// workgroup of the round, so both are updated in place; a subproblem that
-// rotated nothing has U = I, and the products with it are skipped (a tile
-// between two such pairs is left as it is), which makes the late sweeps,
-// where most subproblems are already below the threshold, cheap.  The method
-// has converged when a whole sweep skips every rotation.
+// as rows.  A stays symmetric: one workgroup forms tile (PQ, RS) for pair
+// indices ka <= kb and writes it and its transpose, tile (RS, PQ).  Every tile
+// and every W row block is read and written by one workgroup of the round, so
+// both are updated in place; a subproblem that rotated nothing has U = I, and
+// the products with it are skipped (a tile between two such pairs is left as
+// it is), which makes the late sweeps, where most subproblems are already
+// below the threshold, cheap.  The method has converged when a whole sweep
+// skips every rotation.
 #include "common.h"
 #include "kernels.h"
 
@@ -196,11 +198,25 @@ __device__ inline void quad_xty(const double* __restrict__ X, const double* __re
   }
 }
 
-// Apply round t in place: A <- J^T A J (grid: (nb/2)^2 tiles of JS x JS) and
-// W <- J^T W (grid: (nb/2) * (m / JS) tiles), one workgroup per tile:
-// tile (PQ, RS) of A becomes U_PQ^T A_tile U_RS (two FP64 MFMA products with
-// the intermediate kept transposed in LDS; one when either U is the
-// identity, none when both are), a diagonal tile the solved S.
+// Row ka and column kb (ka <= kb) of entry e of the upper triangle (with its
+// diagonal) of an h x h array, stored row by row.
+__device__ inline void tri_index(int e, int h, int& ka, int& kb) {
+  const double b = 2.0 * h + 1.0;
+  int a = (int)((b - sqrt(b * b - 8.0 * e)) * 0.5);
+  // row a starts at a h - a (a - 1) / 2; correct the rounding of the root
+  while (a > 0 && a * h - a * (a - 1) / 2 > e) --a;
+  while ((a + 1) * h - (a + 1) * a / 2 <= e) ++a;
+  ka = a;
+  kb = a + (e - (a * h - a * (a - 1) / 2));
+}
+
+// Apply round t in place: A <- J^T A J (grid: (nb/2)(nb/2 + 1)/2 tiles of
+// JS x JS, the block pairs ka <= kb) and W <- J^T W (grid: (nb/2) * (m / JS)
+// tiles), one workgroup per tile: tile (PQ, RS) of A becomes
+// U_PQ^T A_tile U_RS (two FP64 MFMA products with the intermediate kept
+// transposed in LDS; one when either U is the identity, none when both are),
+// a diagonal tile the solved S.  A stays symmetric, so tile (RS, PQ) is the
+// transpose of tile (PQ, RS): the workgroup writes both from the one product.
 __global__ __launch_bounds__(256) void k_bj_apply(double* __restrict__ A, double* __restrict__ W,
                                                   const double* __restrict__ Uall, const double* __restrict__ Sall,
                                                   const int* __restrict__ rotated, int m, int nb, int t) {
@@ -212,10 +228,11 @@ __global__ __launch_bounds__(256) void k_bj_apply(double* __restrict__ A, double
   const int half = nb / 2;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r0 = (wave >> 1) * 32, c0w = (wave & 1) * 32;
-  const int nA = half * half;
+  const int nA = half * (half + 1) / 2;
   f64x4 acc[2][2];
   if ((int)blockIdx.x < nA) {
-    const int ka = blockIdx.x / half, kb = blockIdx.x % half;
+    int ka, kb;
+    tri_index((int)blockIdx.x, half, ka, kb);
     int P, Q, R, S;
     rr_pair_b(t, ka, nb, P, Q);
     rr_pair_b(t, kb, nb, R, S);
@@ -263,6 +280,7 @@ __global__ __launch_bounds__(256) void k_bj_apply(double* __restrict__ A, double
       __syncthreads();
       quad_xty<JLD, JS, false>(X, ub, acc);   // T1 Ub = (T1^T)^T Ub
     }
+    __syncthreads();   // every wave is done reading X
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -271,7 +289,14 @@ __global__ __launch_bounds__(256) void k_bj_apply(double* __restrict__ A, double
         for (int v = 0; v < 4; ++v) {
           const int i = r0 + a * 16 + 4 * v + (lane >> 4), j = c0w + b * 16 + (lane & 15);
           A[(int64_t)sub_index(P, Q, i) * m + sub_index(R, S, j)] = acc[a][b][v];
+          X[i * JLD + j] = acc[a][b][v];
         }
+    __syncthreads();
+    // tile (RS, PQ): row j is column j of the new tile
+    for (int e = tid; e < JS * JS; e += 256) {
+      const int j = e / JS, i = e % JS;
+      A[(int64_t)sub_index(R, S, j) * m + sub_index(P, Q, i)] = X[i * JLD + j];
+    }
   } else {
     // W rows of pair ka, columns [c0, c0 + JS): W' = Ua^T W
     const int wb = blockIdx.x - nA;
@@ -325,8 +350,8 @@ hipError_t launch_bj_round(double* A, double* W, double* Uall, double* Sall, int
     k_bj_solve<false><<<(unsigned)half, 256, kLdsSolve, st>>>(A, m, nb, t, thr, Uall, Sall, rot_count, rotated);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_bj_apply<<<(unsigned)(half * half + half * (m / JS)), 256, kLdsApply, st>>>(A, W, Uall, Sall, rotated, m, nb,
-                                                                                 t);
+  k_bj_apply<<<(unsigned)(half * (half + 1) / 2 + half * (m / JS)), 256, kLdsApply, st>>>(A, W, Uall, Sall, rotated,
+                                                                                           m, nb, t);
   return hipGetLastError();
 }
 
