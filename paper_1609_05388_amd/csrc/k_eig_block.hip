@@ -43,18 +43,29 @@ __device__ inline void rr_pair_b(int t, int k, int players, int& p, int& q) {
 // Global index of local index i (0 <= i < JS) of block pair (P, Q).
 __device__ inline int sub_index(int P, int Q, int i) { return i < JB ? P * JB + i : Q * JB + (i - JB); }
 
-// Rotation (c, s) annihilating S[p][q] (Golub & Van Loan, sym.schur2);
-// (1, 0) when |S_pq| <= thr.
+// Rotation (c, s) annihilating S[p][q] (Golub & Van Loan, sym.schur2: t = s / c
+// is the root of t^2 + 2 tau t - 1 = 0 of smaller magnitude, tau = delta / a2,
+// delta = S_qq - S_pp, a2 = 2 S_pq); (1, 0) when |S_pq| <= thr.  Without the
+// divisions: with h = (delta^2 + a2^2)^(1/2) and w = |delta| + h,
+// t = sgn(delta) a2 / w and 1 + t^2 = 2 h / w, so c = w / (2 h w)^(1/2) and
+// s = t c = sgn(delta) a2 / (2 h w)^(1/2).  delta and a2 are first scaled by
+// one power of two (exactly), which leaves c and s unchanged and keeps the
+// squares in range.
 __device__ inline void sub_rotation(const double* S, int p, int q, double thr, double& c, double& s) {
   const double apq = S[p * JLD + q];
   c = 1.0;
   s = 0.0;
   if (fabs(apq) > thr) {
-    const double app = S[p * JLD + p], aqq = S[q * JLD + q];
-    const double tau = (aqq - app) / (2.0 * apq);
-    const double tt = fabs(tau) > 1e150 ? 0.5 / tau : (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-    c = 1.0 / sqrt(1.0 + tt * tt);
-    s = tt * c;
+    double dl = S[q * JLD + q] - S[p * JLD + p], a2 = 2.0 * apq;
+    int e;
+    (void)frexp(fmax(fabs(dl), fabs(a2)), &e);
+    dl = ldexp(dl, -e);
+    a2 = ldexp(a2, -e);
+    const double h = sqrt(fma(dl, dl, a2 * a2));
+    const double w = fabs(dl) + h;
+    const double r = rsqrt(2.0 * h * w);
+    c = w * r;
+    s = (dl < 0.0 ? -a2 : a2) * r;
   }
 }
 
