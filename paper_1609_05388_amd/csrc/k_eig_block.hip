@@ -74,9 +74,10 @@ __device__ inline void sub_rotation(const double* S, int p, int q, double thr, d
 // cross pairs only, inner round r pairing p = i with q = JB + (i + r) mod JB
 // (JB inner rounds).  Each inner round is one phase: a thread recomputes the
 // rotations of the pairs it touches from the current S (every wave computes
-// the JB rotations once: lanes l and l + 32 hold rotation l % 32, fetched by
-// shuffles), writes its 2 x 2 blocks of J^T S J into the other LDS buffer and
-// rotates its pair's columns of U; one barrier per inner round.  Writes U
+// the JB rotations once: lanes l and l + 32 hold rotation l % 32, whose (c, s)
+// the other lanes fetch by shuffles and whose index pair they recompute),
+// writes its 2 x 2 blocks of J^T S J into the other LDS buffer and rotates its
+// pair's columns of U; one barrier per inner round.  Writes U
 // (JS x JS, U[i][j] = component i of vector j) and the final S; a subproblem
 // with nothing above the threshold returns U = I without rotating.
 template <bool FULL>
@@ -113,6 +114,7 @@ __global__ __launch_bounds__(256) void k_bj_solve(const double* __restrict__ A, 
     // (u < 4); the U update: pair kb, rows tid / 32 + 8 v (v < 8)
     const int kb = tid & (JB - 1), ka0 = tid >> 5;
     constexpr int rounds = FULL ? JS - 1 : JB;
+    int nrot = 0;   // rotations applied by this lane's pair (lanes of wave 0 below JB)
     for (int r = 0; r < rounds; ++r) {
       const double* S = cur ? S1 : S0;
       double* S2 = cur ? S0 : S1;
@@ -121,34 +123,54 @@ __global__ __launch_bounds__(256) void k_bj_solve(const double* __restrict__ A, 
       else { pb = kb; qb = JB + ((kb + r) & (JB - 1)); }
       double cb, sbv;
       sub_rotation(S, pb, qb, thr, cb, sbv);
-      if (tid < JB && sbv != 0.0) atomicAdd(&applied_sh, 1);
+      nrot += (sbv != 0.0);
+      // all LDS reads of the inner round first, then the arithmetic and the
+      // writes, so that the reads' latencies overlap
+      double ca[4], sa[4], mm[4][4];
+      int pa[4], qa[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int ka = ka0 + 8 * u;
-        const double ca = __shfl(cb, ka, 64), sa = __shfl(sbv, ka, 64);
-        const int pa = __shfl(pb, ka, 64), qa = __shfl(qb, ka, 64);
-        const double m00 = S[pa * JLD + pb], m01 = S[pa * JLD + qb];
-        const double m10 = S[qa * JLD + pb], m11 = S[qa * JLD + qb];
-        const double r00 = ca * m00 - sa * m10, r01 = ca * m01 - sa * m11;
-        const double r10 = sa * m00 + ca * m10, r11 = sa * m01 + ca * m11;
+        ca[u] = __shfl(cb, ka, 64);
+        sa[u] = __shfl(sbv, ka, 64);
+        if (FULL) rr_pair_b(r, ka, JS, pa[u], qa[u]);
+        else { pa[u] = ka; qa[u] = JB + ((ka + r) & (JB - 1)); }
+        mm[u][0] = S[pa[u] * JLD + pb]; mm[u][1] = S[pa[u] * JLD + qb];
+        mm[u][2] = S[qa[u] * JLD + pb]; mm[u][3] = S[qa[u] * JLD + qb];
+      }
+      double up[8], uq[8];
+      if (sbv != 0.0) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          const int row = ka0 + 8 * v;
+          up[v] = U[row * JLD + pb];
+          uq[v] = U[row * JLD + qb];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int ka = ka0 + 8 * u;
+        const double m00 = mm[u][0], m01 = mm[u][1], m10 = mm[u][2], m11 = mm[u][3];
+        const double r00 = ca[u] * m00 - sa[u] * m10, r01 = ca[u] * m01 - sa[u] * m11;
+        const double r10 = sa[u] * m00 + ca[u] * m10, r11 = sa[u] * m01 + ca[u] * m11;
         double n00 = cb * r00 - sbv * r01, n01 = sbv * r00 + cb * r01;
         double n10 = cb * r10 - sbv * r11, n11 = sbv * r10 + cb * r11;
         if (ka == kb && sbv != 0.0) { n01 = 0.0; n10 = 0.0; }  // the annihilated pair
-        S2[pa * JLD + pb] = n00; S2[pa * JLD + qb] = n01;
-        S2[qa * JLD + pb] = n10; S2[qa * JLD + qb] = n11;
+        S2[pa[u] * JLD + pb] = n00; S2[pa[u] * JLD + qb] = n01;
+        S2[qa[u] * JLD + pb] = n10; S2[qa[u] * JLD + qb] = n11;
       }
       if (sbv != 0.0) {
 #pragma unroll
         for (int v = 0; v < 8; ++v) {
           const int row = ka0 + 8 * v;
-          const double up = U[row * JLD + pb], uq = U[row * JLD + qb];
-          U[row * JLD + pb] = cb * up - sbv * uq;
-          U[row * JLD + qb] = sbv * up + cb * uq;
+          U[row * JLD + pb] = cb * up[v] - sbv * uq[v];
+          U[row * JLD + qb] = sbv * up[v] + cb * uq[v];
         }
       }
       __syncthreads();
       cur ^= 1;
     }
+    if (tid < JB && nrot) atomicAdd(&applied_sh, nrot);
   }
   __syncthreads();
   const int applied = applied_sh;
