@@ -359,8 +359,10 @@ struct Axes {
 };
 
 // Eigenpairs of the symmetric m x m FP64 matrix in A (m a multiple of two
-// Jacobi blocks, zero outside the leading d x d); A is overwritten.  Writes
-// lam (d, decreasing) and Vt (d x d, rows = eigenvectors); returns sweeps.
+// Jacobi blocks, zero outside the leading d x d); only its Jacobi blocks on
+// and above the block diagonal are read, and they are overwritten (the
+// others are left stale).  Writes lam (d, decreasing) and Vt (d x d, rows =
+// eigenvectors); returns sweeps.
 static int jacobi_eig(Workspace& ws, double* A, int m, int64_t d, double* lam, double* Vt, hipStream_t st) {
   const int JB = bj_block();
   const int nb = m / JB;

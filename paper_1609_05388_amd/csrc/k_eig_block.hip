@@ -13,14 +13,17 @@
 // The round then applies the block-diagonal orthogonal J (the U's on their
 // index sets): A <- J^T A J tile by tile (tile (PQ, RS) becomes
 // U_PQ^T A_tile U_RS) and W <- J^T W, with W = V^T accumulating eigenvectors
-// as rows.  A stays symmetric: one workgroup forms tile (PQ, RS) for pair
-// indices ka <= kb and writes it and its transpose, tile (RS, PQ).  Every tile
-// and every W row block is read and written by one workgroup of the round, so
-// both are updated in place; a subproblem that rotated nothing has U = I, and
-// the products with it are skipped (a tile between two such pairs is left as
-// it is), which makes the late sweeps, where most subproblems are already
-// below the threshold, cheap.  The method has converged when a whole sweep
-// skips every rotation.
+// as rows.  A stays symmetric, so only its JB x JB blocks on and above the
+// block diagonal are kept: a block (X, Y) with X > Y is read as the transpose
+// of block (Y, X) and never written (the blocks below the diagonal of the
+// input are left as they are), and one workgroup forms tile (PQ, RS) for pair
+// indices ka <= kb only (half the A traffic and products of the full
+// matrix).  Every tile and every W row block is read and written by one
+// workgroup of the round, so both are updated in place; a subproblem that
+// rotated nothing has U = I, and the products with it are skipped (a tile
+// between two such pairs is left as it is), which makes the late sweeps,
+// where most subproblems are already below the threshold, cheap.  The method
+// has converged when a whole sweep skips every rotation.
 #include "common.h"
 #include "kernels.h"
 
@@ -97,9 +100,11 @@ __global__ __launch_bounds__(256) void k_bj_solve(const double* __restrict__ A, 
   double off = 0.0;
   for (int e = tid; e < JS * JS; e += 256) {
     const int i = e / JS, j = e % JS;
+    U[i * JLD + j] = (i == j) ? 1.0 : 0.0;
+    if (i >= JB && j < JB) continue;   // block (Q, P), P < Q: the transpose of block (P, Q)
     const double x = A[(int64_t)sub_index(P, Q, i) * m + sub_index(P, Q, j)];
     S0[i * JLD + j] = x;
-    U[i * JLD + j] = (i == j) ? 1.0 : 0.0;
+    if (i < JB && j >= JB) S0[j * JLD + i] = x;
     if (FULL ? i != j : (i < JB && j >= JB)) off = fmax(off, fabs(x));
   }
 #pragma unroll
@@ -231,6 +236,53 @@ __device__ inline void quad_xty(const double* __restrict__ X, const double* __re
   }
 }
 
+// Tile (PQ, RS) of A (blocks P, Q of rows, R, S of columns, {P, Q} and {R, S}
+// disjoint) into LDS, X[i][j] = A_tile[i][j] (X[j][i] when TR), from the blocks
+// at or above the block diagonal: a block below it is read from its mirror,
+// along the mirror's rows so that the reads stay coalesced.
+template <bool TR>
+__device__ inline void load_tile_upper(const double* __restrict__ A, int m, int P, int Q, int R, int S,
+                                       double* X) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int bi = b >> 1, bj = b & 1;
+    const int xb = bi ? Q : P, yb = bj ? S : R;
+    const bool above = xb < yb;   // uniform over the workgroup
+#pragma unroll
+    for (int k = 0; k < JB * JB / 256; ++k) {
+      const int e = tid + 256 * k, hi = e / JB, lo = e % JB;
+      const int i = above ? hi : lo, j = above ? lo : hi;
+      const double v = above ? A[(int64_t)(xb * JB + i) * m + yb * JB + j]
+                             : A[(int64_t)(yb * JB + j) * m + xb * JB + i];
+      const int li = bi * JB + i, lj = bj * JB + j;
+      if (TR) X[lj * JLD + li] = v;
+      else X[li * JLD + lj] = v;
+    }
+  }
+}
+
+// The new tile X[i][j] (LDS) into the blocks of A at or above the block
+// diagonal: a block below it is written, transposed, into its mirror.
+__device__ inline void store_tile_upper(double* __restrict__ A, int m, int P, int Q, int R, int S,
+                                        const double* X) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int bi = b >> 1, bj = b & 1;
+    const int xb = bi ? Q : P, yb = bj ? S : R;
+    const bool above = xb < yb;
+#pragma unroll
+    for (int k = 0; k < JB * JB / 256; ++k) {
+      const int e = tid + 256 * k, hi = e / JB, lo = e % JB;
+      const int i = above ? hi : lo, j = above ? lo : hi;
+      const double v = X[(bi * JB + i) * JLD + bj * JB + j];
+      if (above) A[(int64_t)(xb * JB + i) * m + yb * JB + j] = v;
+      else A[(int64_t)(yb * JB + j) * m + xb * JB + i] = v;
+    }
+  }
+}
+
 // Row ka and column kb (ka <= kb) of entry e of the upper triangle (with its
 // diagonal) of an h x h array, stored row by row.
 __device__ inline void tri_index(int e, int h, int& ka, int& kb) {
@@ -248,8 +300,8 @@ __device__ inline void tri_index(int e, int h, int& ka, int& kb) {
 // tiles), one workgroup per tile: tile (PQ, RS) of A becomes
 // U_PQ^T A_tile U_RS (two FP64 MFMA products with the intermediate kept
 // transposed in LDS; one when either U is the identity, none when both are),
-// a diagonal tile the solved S.  A stays symmetric, so tile (RS, PQ) is the
-// transpose of tile (PQ, RS): the workgroup writes both from the one product.
+// a diagonal tile the solved S; only the blocks at or above the block diagonal
+// are read and written.
 __global__ __launch_bounds__(256) void k_bj_apply(double* __restrict__ A, double* __restrict__ W,
                                                   const double* __restrict__ Uall, const double* __restrict__ Sall,
                                                   const int* __restrict__ rotated, int m, int nb, int t) {
@@ -275,6 +327,7 @@ __global__ __launch_bounds__(256) void k_bj_apply(double* __restrict__ A, double
       const double* Sg = Sall + (int64_t)ka * JS * JS;
       for (int e = tid; e < JS * JS; e += 256) {
         const int i = e / JS, j = e % JS;
+        if (i >= JB && j < JB) continue;   // block (Q, P), P < Q: not kept
         A[(int64_t)sub_index(P, Q, i) * m + sub_index(P, Q, j)] = Sg[e];
       }
       return;
@@ -283,10 +336,7 @@ __global__ __launch_bounds__(256) void k_bj_apply(double* __restrict__ A, double
     const double* ua = Uall + (int64_t)ka * JS * JS;
     const double* ub = Uall + (int64_t)kb * JS * JS;
     if (rot_a) {
-      for (int e = tid; e < JS * JS; e += 256) {
-        const int i = e / JS, j = e % JS;
-        X[i * JLD + j] = A[(int64_t)sub_index(P, Q, i) * m + sub_index(R, S, j)];
-      }
+      load_tile_upper<false>(A, m, P, Q, R, S, X);
       __syncthreads();
       quad_xty<JS, JLD, true>(ua, X, acc);    // T1 = Ua^T A_tile
       __syncthreads();
@@ -304,10 +354,7 @@ __global__ __launch_bounds__(256) void k_bj_apply(double* __restrict__ A, double
       }
     } else {
       // T1 = A_tile, held transposed: X[j][i] = A_tile[i][j]
-      for (int e = tid; e < JS * JS; e += 256) {
-        const int i = e / JS, j = e % JS;
-        X[j * JLD + i] = A[(int64_t)sub_index(P, Q, i) * m + sub_index(R, S, j)];
-      }
+      load_tile_upper<true>(A, m, P, Q, R, S, X);
     }
     if (rot_b) {
       __syncthreads();
@@ -321,15 +368,10 @@ __global__ __launch_bounds__(256) void k_bj_apply(double* __restrict__ A, double
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i = r0 + a * 16 + 4 * v + (lane >> 4), j = c0w + b * 16 + (lane & 15);
-          A[(int64_t)sub_index(P, Q, i) * m + sub_index(R, S, j)] = acc[a][b][v];
           X[i * JLD + j] = acc[a][b][v];
         }
     __syncthreads();
-    // tile (RS, PQ): row j is column j of the new tile
-    for (int e = tid; e < JS * JS; e += 256) {
-      const int j = e / JS, i = e % JS;
-      A[(int64_t)sub_index(R, S, j) * m + sub_index(P, Q, i)] = X[i * JLD + j];
-    }
+    store_tile_upper(A, m, P, Q, R, S, X);
   } else {
     // W rows of pair ka, columns [c0, c0 + JS): W' = Ua^T W
     const int wb = blockIdx.x - nA;
