@@ -98,11 +98,20 @@ __global__ __launch_bounds__(256) void k_bj_solve(const double* __restrict__ A, 
   rr_pair_b(t, pair, nb, P, Q);
   const int tid = threadIdx.x;
   double off = 0.0;
-  for (int e = tid; e < JS * JS; e += 256) {
-    const int i = e / JS, j = e % JS;
+  // all global reads first (in flight together), then the LDS writes; block
+  // (Q, P), P < Q, is not read: it is the transpose of block (P, Q)
+  double xv[JS * JS / 256];
+#pragma unroll
+  for (int k = 0; k < JS * JS / 256; ++k) {
+    const int e = tid + 256 * k, i = e / JS, j = e % JS;
+    xv[k] = (i >= JB && j < JB) ? 0.0 : A[(int64_t)sub_index(P, Q, i) * m + sub_index(P, Q, j)];
+  }
+#pragma unroll
+  for (int k = 0; k < JS * JS / 256; ++k) {
+    const int e = tid + 256 * k, i = e / JS, j = e % JS;
     U[i * JLD + j] = (i == j) ? 1.0 : 0.0;
-    if (i >= JB && j < JB) continue;   // block (Q, P), P < Q: the transpose of block (P, Q)
-    const double x = A[(int64_t)sub_index(P, Q, i) * m + sub_index(P, Q, j)];
+    if (i >= JB && j < JB) continue;
+    const double x = xv[k];
     S0[i * JLD + j] = x;
     if (i < JB && j >= JB) S0[j * JLD + i] = x;
     if (FULL ? i != j : (i < JB && j >= JB)) off = fmax(off, fabs(x));
@@ -325,10 +334,14 @@ __global__ __launch_bounds__(256) void k_bj_apply(double* __restrict__ A, double
     if (ka == kb) {  // diagonal tile: the solved subproblem itself
       if (!rot_a) return;
       const double* Sg = Sall + (int64_t)ka * JS * JS;
-      for (int e = tid; e < JS * JS; e += 256) {
-        const int i = e / JS, j = e % JS;
+      double sv[JS * JS / 256];   // all reads in flight before the writes
+#pragma unroll
+      for (int k = 0; k < JS * JS / 256; ++k) sv[k] = Sg[tid + 256 * k];
+#pragma unroll
+      for (int k = 0; k < JS * JS / 256; ++k) {
+        const int e = tid + 256 * k, i = e / JS, j = e % JS;
         if (i >= JB && j < JB) continue;   // block (Q, P), P < Q: not kept
-        A[(int64_t)sub_index(P, Q, i) * m + sub_index(P, Q, j)] = Sg[e];
+        A[(int64_t)sub_index(P, Q, i) * m + sub_index(P, Q, j)] = sv[k];
       }
       return;
     }
@@ -381,9 +394,16 @@ __global__ __launch_bounds__(256) void k_bj_apply(double* __restrict__ A, double
     int P, Q;
     rr_pair_b(t, ka, nb, P, Q);
     const double* ua = Uall + (int64_t)ka * JS * JS;
-    for (int e = tid; e < JS * JS; e += 256) {
-      const int i = e / JS, j = e % JS;
-      X[i * JLD + j] = W[(int64_t)sub_index(P, Q, i) * m + c0 + j];
+    double wv[JS * JS / 256];   // all global reads in flight before the LDS writes
+#pragma unroll
+    for (int k = 0; k < JS * JS / 256; ++k) {
+      const int e = tid + 256 * k, i = e / JS, j = e % JS;
+      wv[k] = W[(int64_t)sub_index(P, Q, i) * m + c0 + j];
+    }
+#pragma unroll
+    for (int k = 0; k < JS * JS / 256; ++k) {
+      const int e = tid + 256 * k, i = e / JS, j = e % JS;
+      X[i * JLD + j] = wv[k];
     }
     __syncthreads();
     quad_xty<JS, JLD, true>(ua, X, acc);
