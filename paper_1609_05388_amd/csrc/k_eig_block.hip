@@ -247,47 +247,59 @@ __device__ inline void quad_xty(const double* __restrict__ X, const double* __re
 
 // Tile (PQ, RS) of A (blocks P, Q of rows, R, S of columns, {P, Q} and {R, S}
 // disjoint) into LDS, X[i][j] = A_tile[i][j] (X[j][i] when TR), from the blocks
-// at or above the block diagonal: a block below it is read from its mirror,
-// along the mirror's rows so that the reads stay coalesced.
+// at or above the block diagonal: sub-block (xb, yb) is read from stored block
+// (min, max) along its rows, so that the reads stay coalesced, and lands
+// transposed when xb > yb.  All sixteen reads of a thread are in flight
+// before the LDS writes.
 template <bool TR>
 __device__ inline void load_tile_upper(const double* __restrict__ A, int m, int P, int Q, int R, int S,
                                        double* X) {
   const int tid = threadIdx.x;
+  constexpr int per = JB * JB / 256;
+  double v[4 * per];
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
-    const int bi = b >> 1, bj = b & 1;
-    const int xb = bi ? Q : P, yb = bj ? S : R;
-    const bool above = xb < yb;   // uniform over the workgroup
+    const int xb = (b >> 1) ? Q : P, yb = (b & 1) ? S : R;
+    const int rb = xb < yb ? xb : yb, cb = xb < yb ? yb : xb;
 #pragma unroll
-    for (int k = 0; k < JB * JB / 256; ++k) {
+    for (int k = 0; k < per; ++k) {
       const int e = tid + 256 * k, hi = e / JB, lo = e % JB;
-      const int i = above ? hi : lo, j = above ? lo : hi;
-      const double v = above ? A[(int64_t)(xb * JB + i) * m + yb * JB + j]
-                             : A[(int64_t)(yb * JB + j) * m + xb * JB + i];
-      const int li = bi * JB + i, lj = bj * JB + j;
-      if (TR) X[lj * JLD + li] = v;
-      else X[li * JLD + lj] = v;
+      v[b * per + k] = A[(int64_t)(rb * JB + hi) * m + cb * JB + lo];
     }
   }
-}
-
-// The new tile X[i][j] (LDS) into the blocks of A at or above the block
-// diagonal: a block below it is written, transposed, into its mirror.
-__device__ inline void store_tile_upper(double* __restrict__ A, int m, int P, int Q, int R, int S,
-                                        const double* X) {
-  const int tid = threadIdx.x;
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
     const int bi = b >> 1, bj = b & 1;
     const int xb = bi ? Q : P, yb = bj ? S : R;
     const bool above = xb < yb;
 #pragma unroll
-    for (int k = 0; k < JB * JB / 256; ++k) {
+    for (int k = 0; k < per; ++k) {
       const int e = tid + 256 * k, hi = e / JB, lo = e % JB;
-      const int i = above ? hi : lo, j = above ? lo : hi;
-      const double v = X[(bi * JB + i) * JLD + bj * JB + j];
-      if (above) A[(int64_t)(xb * JB + i) * m + yb * JB + j] = v;
-      else A[(int64_t)(yb * JB + j) * m + xb * JB + i] = v;
+      const int li = bi * JB + (above ? hi : lo), lj = bj * JB + (above ? lo : hi);
+      if (TR) X[lj * JLD + li] = v[b * per + k];
+      else X[li * JLD + lj] = v[b * per + k];
+    }
+  }
+}
+
+// The new tile X[i][j] (LDS) into the blocks of A at or above the block
+// diagonal: sub-block (xb, yb) goes to stored block (min, max), transposed
+// when xb > yb.
+__device__ inline void store_tile_upper(double* __restrict__ A, int m, int P, int Q, int R, int S,
+                                        const double* X) {
+  const int tid = threadIdx.x;
+  constexpr int per = JB * JB / 256;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int bi = b >> 1, bj = b & 1;
+    const int xb = bi ? Q : P, yb = bj ? S : R;
+    const bool above = xb < yb;
+    const int rb = above ? xb : yb, cb = above ? yb : xb;
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+      const int e = tid + 256 * k, hi = e / JB, lo = e % JB;
+      const int li = bi * JB + (above ? hi : lo), lj = bj * JB + (above ? lo : hi);
+      A[(int64_t)(rb * JB + hi) * m + cb * JB + lo] = X[li * JLD + lj];
     }
   }
 }
