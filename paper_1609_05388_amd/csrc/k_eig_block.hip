@@ -32,6 +32,7 @@ namespace adg {
 constexpr int JB = 32;        // index block
 constexpr int JS = 2 * JB;    // subproblem size
 constexpr int JLD = JS + 1;   // LDS row stride (doubles) of the subproblem
+constexpr int SNT = 512;      // threads of a subproblem's workgroup: two waves per SIMD
 
 // Pair k of round t of the round-robin ordering of `players` (even) players.
 __device__ inline void rr_pair_b(int t, int k, int players, int& p, int& q) {
@@ -84,14 +85,14 @@ __device__ inline void sub_rotation(const double* S, int p, int q, double thr, d
 // (JS x JS, U[i][j] = component i of vector j) and the final S; a subproblem
 // with nothing above the threshold returns U = I without rotating.
 template <bool FULL>
-__global__ __launch_bounds__(256) void k_bj_solve(const double* __restrict__ A, int m, int nb, int t, double thr,
+__global__ __launch_bounds__(SNT) void k_bj_solve(const double* __restrict__ A, int m, int nb, int t, double thr,
                                                   double* __restrict__ Uout, double* __restrict__ Sout,
                                                   int* __restrict__ rot_count, int* __restrict__ rotated) {
   extern __shared__ double lds_d[];
   double* const S0 = lds_d;
   double* const S1 = lds_d + JS * JLD;
   double* const U = lds_d + 2 * JS * JLD;
-  __shared__ double off_sh[4];
+  __shared__ double off_sh[SNT / 64];
   __shared__ int applied_sh;
   const int pair = blockIdx.x;
   int P, Q;
@@ -100,15 +101,15 @@ __global__ __launch_bounds__(256) void k_bj_solve(const double* __restrict__ A, 
   double off = 0.0;
   // all global reads first (in flight together), then the LDS writes; block
   // (Q, P), P < Q, is not read: it is the transpose of block (P, Q)
-  double xv[JS * JS / 256];
+  double xv[JS * JS / SNT];
 #pragma unroll
-  for (int k = 0; k < JS * JS / 256; ++k) {
-    const int e = tid + 256 * k, i = e / JS, j = e % JS;
+  for (int k = 0; k < JS * JS / SNT; ++k) {
+    const int e = tid + SNT * k, i = e / JS, j = e % JS;
     xv[k] = (i >= JB && j < JB) ? 0.0 : A[(int64_t)sub_index(P, Q, i) * m + sub_index(P, Q, j)];
   }
 #pragma unroll
-  for (int k = 0; k < JS * JS / 256; ++k) {
-    const int e = tid + 256 * k, i = e / JS, j = e % JS;
+  for (int k = 0; k < JS * JS / SNT; ++k) {
+    const int e = tid + SNT * k, i = e / JS, j = e % JS;
     U[i * JLD + j] = (i == j) ? 1.0 : 0.0;
     if (i >= JB && j < JB) continue;
     const double x = xv[k];
@@ -121,12 +122,15 @@ __global__ __launch_bounds__(256) void k_bj_solve(const double* __restrict__ A, 
   if ((tid & 63) == 0) off_sh[tid >> 6] = off;
   if (tid == 0) applied_sh = 0;
   __syncthreads();
-  off = fmax(fmax(off_sh[0], off_sh[1]), fmax(off_sh[2], off_sh[3]));
+  off = off_sh[0];
+#pragma unroll
+  for (int w = 1; w < SNT / 64; ++w) off = fmax(off, off_sh[w]);
   int cur = 0;
   if (off > thr) {
-    // thread -> column pair kb = tid % 32 and row pairs ka = tid / 32 + 8 u
-    // (u < 4); the U update: pair kb, rows tid / 32 + 8 v (v < 8)
-    const int kb = tid & (JB - 1), ka0 = tid >> 5;
+    // thread -> column pair kb = tid % 32 and row pairs ka = tid / 32 + RS u
+    // (u < JB / RS); the U update: pair kb, rows tid / 32 + RS v (v < JS / RS)
+    constexpr int RS = SNT / JB;
+    const int kb = tid & (JB - 1), ka0 = tid / JB;
     constexpr int rounds = FULL ? JS - 1 : JB;
     int nrot = 0;   // rotations applied by this lane's pair (lanes of wave 0 below JB)
     for (int r = 0; r < rounds; ++r) {
@@ -140,11 +144,11 @@ __global__ __launch_bounds__(256) void k_bj_solve(const double* __restrict__ A, 
       nrot += (sbv != 0.0);
       // all LDS reads of the inner round first, then the arithmetic and the
       // writes, so that the reads' latencies overlap
-      double ca[4], sa[4], mm[4][4];
-      int pa[4], qa[4];
+      double ca[JB / RS], sa[JB / RS], mm[JB / RS][4];
+      int pa[JB / RS], qa[JB / RS];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int ka = ka0 + 8 * u;
+      for (int u = 0; u < JB / RS; ++u) {
+        const int ka = ka0 + RS * u;
         ca[u] = __shfl(cb, ka, 64);
         sa[u] = __shfl(sbv, ka, 64);
         if (FULL) rr_pair_b(r, ka, JS, pa[u], qa[u]);
@@ -152,18 +156,18 @@ __global__ __launch_bounds__(256) void k_bj_solve(const double* __restrict__ A, 
         mm[u][0] = S[pa[u] * JLD + pb]; mm[u][1] = S[pa[u] * JLD + qb];
         mm[u][2] = S[qa[u] * JLD + pb]; mm[u][3] = S[qa[u] * JLD + qb];
       }
-      double up[8], uq[8];
+      double up[JS / RS], uq[JS / RS];
       if (sbv != 0.0) {
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
-          const int row = ka0 + 8 * v;
+        for (int v = 0; v < JS / RS; ++v) {
+          const int row = ka0 + RS * v;
           up[v] = U[row * JLD + pb];
           uq[v] = U[row * JLD + qb];
         }
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int ka = ka0 + 8 * u;
+      for (int u = 0; u < JB / RS; ++u) {
+        const int ka = ka0 + RS * u;
         const double m00 = mm[u][0], m01 = mm[u][1], m10 = mm[u][2], m11 = mm[u][3];
         const double r00 = ca[u] * m00 - sa[u] * m10, r01 = ca[u] * m01 - sa[u] * m11;
         const double r10 = sa[u] * m00 + ca[u] * m10, r11 = sa[u] * m01 + ca[u] * m11;
@@ -175,8 +179,8 @@ __global__ __launch_bounds__(256) void k_bj_solve(const double* __restrict__ A, 
       }
       if (sbv != 0.0) {
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
-          const int row = ka0 + 8 * v;
+        for (int v = 0; v < JS / RS; ++v) {
+          const int row = ka0 + RS * v;
           U[row * JLD + pb] = cb * up[v] - sbv * uq[v];
           U[row * JLD + qb] = sbv * up[v] + cb * uq[v];
         }
@@ -196,7 +200,7 @@ __global__ __launch_bounds__(256) void k_bj_solve(const double* __restrict__ A, 
   const double* S = cur ? S1 : S0;
   double* Ug = Uout + (int64_t)pair * JS * JS;
   double* Sg = Sout + (int64_t)pair * JS * JS;
-  for (int e = tid; e < JS * JS; e += 256) {
+  for (int e = tid; e < JS * JS; e += SNT) {
     const int i = e / JS, j = e % JS;
     Ug[e] = U[i * JLD + j];
     Sg[e] = S[i * JLD + j];
@@ -452,9 +456,9 @@ hipError_t launch_bj_round(double* A, double* W, double* Uall, double* Sall, int
   const int nb = m / JB;
   const int half = nb / 2;
   if (t == 0)
-    k_bj_solve<true><<<(unsigned)half, 256, kLdsSolve, st>>>(A, m, nb, t, thr, Uall, Sall, rot_count, rotated);
+    k_bj_solve<true><<<(unsigned)half, SNT, kLdsSolve, st>>>(A, m, nb, t, thr, Uall, Sall, rot_count, rotated);
   else
-    k_bj_solve<false><<<(unsigned)half, 256, kLdsSolve, st>>>(A, m, nb, t, thr, Uall, Sall, rot_count, rotated);
+    k_bj_solve<false><<<(unsigned)half, SNT, kLdsSolve, st>>>(A, m, nb, t, thr, Uall, Sall, rot_count, rotated);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_bj_apply<<<(unsigned)(half * (half + 1) / 2 + half * (m / JS)), 256, kLdsApply, st>>>(A, W, Uall, Sall, rotated,
