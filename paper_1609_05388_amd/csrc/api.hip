@@ -63,7 +63,7 @@ struct DevBuf {
 };
 
 struct Workspace {
-  DevBuf mu, colpart, nonfinite, Xc, nx, tx, covpart, A0, A1, W, trace, rot, lam, Vt;
+  DevBuf mu, colpart, nonfinite, Xc, nx, tx, covpart, A0, W, trace, rot, lam, Vt;
   DevBuf S, T, Pi, Pi64, Y64, Yc, ny, ty, muY;
   DevBuf recs, tparts, seeds, seedv, list, cand, vals, vparts, cd;
   DevBuf Xb, txb, Yb, tyb, bjU, bjS, bjRot;
