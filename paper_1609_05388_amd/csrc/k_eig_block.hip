@@ -44,6 +44,25 @@ __device__ inline void rr_pair_b(int t, int k, int players, int& p, int& q) {
   q = a < b ? b : a;
 }
 
+// Pair k of the round-robin ordering of JS players (the pairs rr_pair_b(r, k,
+// JS) of inner rounds r = 0, 1, ...), advanced one round at a time: x and y
+// hold (r + k) mod (JS - 1) and (r - k) mod (JS - 1), so a round costs two
+// increments instead of two divisions.
+struct RrStep {
+  int x, y;
+  bool first;   // k == 0: the pair (0, r mod (JS - 1) + 1)
+  __device__ explicit RrStep(int k) : x(k % (JS - 1)), y((JS - 1 - k % (JS - 1)) % (JS - 1)), first(k == 0) {}
+  __device__ void pair(int& p, int& q) const {
+    const int a = first ? 0 : x + 1, b = first ? x + 1 : y + 1;
+    p = a < b ? a : b;
+    q = a < b ? b : a;
+  }
+  __device__ void next() {
+    x = x + 1 == JS - 1 ? 0 : x + 1;
+    y = y + 1 == JS - 1 ? 0 : y + 1;
+  }
+};
+
 // Global index of local index i (0 <= i < JS) of block pair (P, Q).
 __device__ inline int sub_index(int P, int Q, int i) { return i < JB ? P * JB + i : Q * JB + (i - JB); }
 
@@ -133,11 +152,13 @@ __global__ __launch_bounds__(SNT) void k_bj_solve(const double* __restrict__ A, 
     const int kb = tid & (JB - 1), ka0 = tid / JB;
     constexpr int rounds = FULL ? JS - 1 : JB;
     int nrot = 0;   // rotations applied by this lane's pair (lanes of wave 0 below JB)
+    RrStep rb(kb), ra[JB / RS] = {RrStep(ka0), RrStep(ka0 + RS)};
+    static_assert(JB / RS == 2, "two row pairs per thread");
     for (int r = 0; r < rounds; ++r) {
       const double* S = cur ? S1 : S0;
       double* S2 = cur ? S0 : S1;
       int pb, qb;
-      if (FULL) rr_pair_b(r, kb, JS, pb, qb);
+      if (FULL) { rb.pair(pb, qb); rb.next(); }
       else { pb = kb; qb = JB + ((kb + r) & (JB - 1)); }
       double cb, sbv;
       sub_rotation(S, pb, qb, thr, cb, sbv);
@@ -151,7 +172,7 @@ __global__ __launch_bounds__(SNT) void k_bj_solve(const double* __restrict__ A, 
         const int ka = ka0 + RS * u;
         ca[u] = __shfl(cb, ka, 64);
         sa[u] = __shfl(sbv, ka, 64);
-        if (FULL) rr_pair_b(r, ka, JS, pa[u], qa[u]);
+        if (FULL) { ra[u].pair(pa[u], qa[u]); ra[u].next(); }
         else { pa[u] = ka; qa[u] = JB + ((ka + r) & (JB - 1)); }
         mm[u][0] = S[pa[u] * JLD + pb]; mm[u][1] = S[pa[u] * JLD + qb];
         mm[u][2] = S[qa[u] * JLD + pb]; mm[u][3] = S[qa[u] * JLD + qb];
