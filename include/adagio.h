@@ -35,8 +35,10 @@
  *   calls with adagio_keep_workspace(1); adagio_release() frees the current
  *   device's, and the library frees what is kept at process exit by itself
  *   (an exit handler registered after the HIP runtime has started, so it
- *   runs before the runtime's teardown).  Calls are serialised by an
- *   internal lock.
+ *   runs before the runtime's teardown).  A fit also makes two streams of
+ *   its own on its device (one CU-masked), which every later call on that
+ *   device reuses, kept or not, and which the same exit handler destroys.
+ *   Calls are serialised by an internal lock.
  * - Return value: ADAGIO_OK (0) or a negative ADAGIO_E_* code.  On error the
  *   output buffers are unspecified and adagio_last_error() describes the
  *   failure (thread-local text).  Arguments are validated before any device

@@ -73,8 +73,8 @@ struct Workspace {
   DevBuf knQ, knD, knNq64, knNd64, knNq32, knNd32, knMax, knKeys, knFb, knCnt, knTau;
   DevBuf lam1, Vt1, colmap, colminmax, colkeep, xc64, pi64c, axy;
   DevBuf pool, pooln, wvals, wparts, wcd, wV, wW, stopn, stopp, gfM, gfFail, gfZ, nrm;
-  // second stream (non-blocking, default priority) for work that overlaps
-  // the caller's stream: the fit's point-Gram fill during its PCA
+  // the device's library streams (borrowed from g_aux / g_aux2, never
+  // destroyed here): aux runs the fit's point-Gram fill during its PCA
   hipStream_t aux = nullptr;
   hipStream_t aux2 = nullptr;  // non-blocking, all CUs: the fit's exact PCA beside the fill
   hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_t0 = nullptr, ev_t1 = nullptr, ev_pca = nullptr,
@@ -82,15 +82,12 @@ struct Workspace {
   Workspace() = default;
   Workspace(const Workspace&) = delete;
   Workspace& operator=(const Workspace&) = delete;
-  // Drains the library's streams, then frees streams, events and (member
-  // destructors) every buffer.  Errors are ignored: this also runs while an
-  // error unwinds a call.
+  // Drains the library's streams (the device's, which it borrows: see
+  // device_streams), then frees events and (member destructors) every
+  // buffer.  Errors are ignored: this also runs while an error unwinds a call.
   ~Workspace() {
     for (hipStream_t q : {aux, aux2}) {
-      if (q) {
-        (void)hipStreamSynchronize(q);
-        (void)hipStreamDestroy(q);
-      }
+      if (q) (void)hipStreamSynchronize(q);
     }
     for (hipEvent_t e : {ev_in, ev_out, ev_t0, ev_t1, ev_pca, ev_cov}) {
       if (e) (void)hipEventDestroy(e);
@@ -109,6 +106,11 @@ static bool g_keep = false;
 static Workspace* g_kept[64];
 static bool g_checked[64];
 static bool g_exit_hook = false;
+// The library's two streams of each device (aux: CU-masked, aux2), made on a
+// device's first fit and kept until the process ends, by workspaces kept
+// across calls and by per-call ones alike: making and destroying a CU-masked
+// stream costs ~20 ms (measured on MI355X), more than a small fit.
+static hipStream_t g_aux[64], g_aux2[64];
 
 static void release_kept_all() {
   int cur = -1;
@@ -121,11 +123,30 @@ static void release_kept_all() {
   if (have_cur) (void)hipSetDevice(cur);
 }
 
+static void release_streams_all() {
+  int cur = -1;
+  const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+  for (int dev = 0; dev < 64; ++dev) {
+    if (!g_aux[dev] && !g_aux2[dev]) continue;
+    if (hipSetDevice(dev) == hipSuccess) {
+      for (hipStream_t q : {g_aux[dev], g_aux2[dev]}) {
+        if (q) {
+          (void)hipStreamSynchronize(q);
+          (void)hipStreamDestroy(q);
+        }
+      }
+    }
+    g_aux[dev] = g_aux2[dev] = nullptr;
+  }
+  if (have_cur) (void)hipSetDevice(cur);
+}
+
 static void release_at_exit() {
   // another thread may still be inside a call at exit: leave its memory to
   // the process teardown rather than free it under the call
   if (!g_mu.try_lock()) return;
   release_kept_all();
+  release_streams_all();
   g_mu.unlock();
 }
 
@@ -1183,22 +1204,36 @@ static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 // small latency-bound kernels keep CUs of their own; a plain non-blocking
 // stream if the mask is refused).  A CU-masked stream is a blocking stream:
 // it orders itself after work on the null stream, and later null-stream work
-// after it, so the PCA beside it runs on aux2, non-blocking.
+// after it, so the PCA beside it runs on aux2, non-blocking.  Both are the
+// device's (g_aux, g_aux2), made once and kept until the process ends.
 static void ensure_streams(Workspace& ws) {
-  if (!ws.aux) {
-    int dev = 0, ncu = 0;
-    HIPCHK(hipGetDevice(&dev));
-    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    const int keep = ncu - ncu / 8;
-    std::vector<uint32_t> mask((size_t)(ncu + 31) / 32, 0u);
-    for (int c = 0; c < keep; ++c) mask[(size_t)c / 32] |= 1u << (c % 32);
-    if (ncu < 16 || hipExtStreamCreateWithCUMask(&ws.aux, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
-      (void)hipGetLastError();
-      ws.aux = nullptr;
-      HIPCHK(hipStreamCreateWithFlags(&ws.aux, hipStreamNonBlocking));
+  if (!ws.aux || !ws.aux2) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));   // 0 <= dev < 64: checked when the call began
+    if (!g_aux[dev]) {
+      int ncu = 0;
+      HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+      const int keep = ncu - ncu / 8;
+      std::vector<uint32_t> mask((size_t)(ncu + 31) / 32, 0u);
+      for (int c = 0; c < keep; ++c) mask[(size_t)c / 32] |= 1u << (c % 32);
+      hipStream_t q = nullptr;
+      if (ncu < 16 || hipExtStreamCreateWithCUMask(&q, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
+        (void)hipGetLastError();
+        q = nullptr;
+        HIPCHK(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+      }
+      g_aux[dev] = q;
+      if (!g_exit_hook) g_exit_hook = atexit(release_at_exit) == 0;
     }
+    if (!g_aux2[dev]) {
+      hipStream_t q = nullptr;
+      HIPCHK(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+      g_aux2[dev] = q;
+      if (!g_exit_hook) g_exit_hook = atexit(release_at_exit) == 0;
+    }
+    ws.aux = g_aux[dev];
+    ws.aux2 = g_aux2[dev];
   }
-  if (!ws.aux2) HIPCHK(hipStreamCreateWithFlags(&ws.aux2, hipStreamNonBlocking));
   for (hipEvent_t* e : {&ws.ev_in, &ws.ev_out, &ws.ev_pca, &ws.ev_cov}) {
     if (!*e) HIPCHK(hipEventCreateWithFlags(e, hipEventDisableTiming));
   }

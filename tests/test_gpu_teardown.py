@@ -12,7 +12,10 @@ driver stack at start-up, not from the library).
   loaded: a process must not hold two HIP runtimes);
 * kept workspace (adagio_keep_workspace(1)) left allocated at exit, device
   memory from the HIP runtime through ctypes, no torch in the process: the
-  library's own exit handler frees the workspace, its streams and events.
+  library's own exit handler frees the workspace, its streams and events;
+* two fits with per-call workspaces, no torch: the device's library streams
+  that both fits used are still held at exit, and the exit handler destroys
+  them.
 """
 import os
 import subprocess
@@ -73,6 +76,9 @@ sys.exit(0 if rc == 0 and rc2 == 0 else 3)
 '''
 
 
+_HIP_PER_CALL = _HIP_KEEP.replace("assert lib.adagio_keep_workspace(1) == 0\n", "")
+
+
 def _run_child(body, use_torch):
     code = "ROOT = %r\nLIB = %r\nUSE_TORCH = %r\n" % (ROOT, LIB, use_torch) + body
     print("child interpreter: adagio_fit through ctypes, then exit", flush=True)
@@ -90,6 +96,14 @@ def test_exit_after_fit_with_per_call_workspace():
 
 def test_exit_with_kept_workspace_and_no_torch():
     res, err = _run_child(_HIP_KEEP, False)
+    assert res.returncode == 0, (res.returncode, res.stdout, res.stderr)
+    assert err == "", res.stderr
+    assert "rc 0 0" in res.stdout
+
+
+def test_exit_after_per_call_fits_and_no_torch():
+    assert "adagio_keep_workspace(1)" not in _HIP_PER_CALL
+    res, err = _run_child(_HIP_PER_CALL, False)
     assert res.returncode == 0, (res.returncode, res.stdout, res.stderr)
     assert err == "", res.stderr
     assert "rc 0 0" in res.stdout
